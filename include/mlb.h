@@ -1,0 +1,213 @@
+/*
+ * mlb.h - C ABI of the MI355X multilevel linearized-buckling engine.
+ *
+ * The calls follow the analysis the paper performs for every design
+ * (Ferrari & Sigmund, "Towards solving large-scale topology optimization
+ * problems with buckling constraints at the cost of linear analyses"):
+ *   Alg. 1       set a reference load, solve K[x] u = f, set up G[x, u],
+ *                compute the lowest buckling pairs (K + lambda G) phi = 0;
+ *   Sec. 2.1     multilevel approximation of those pairs: Galerkin coarse
+ *                eigenproblem, interpolation of the coarse modes to the fine
+ *                grid, one fine block solve K Phi~ = G Psi, Rayleigh-Ritz;
+ *   Sec. 2       SIMP interpolations E_kappa = E0 + x^p (E1 - E0),
+ *                E_sigma = x^p E1 (eq. interpolationSIMP2-SIMP), modes
+ *                normalised phi_i^T K phi_j = delta_ij;
+ *   eqs. SensitivityLambda, AdjointSystem
+ *                buckling-factor sensitivities with one adjoint solve per
+ *                mode; compliance J = f^T u (Sec. 3) and its gradient.
+ *
+ * Discretisation: regular grid of unit Q4 (dim 2, plane stress, unit
+ * thickness) or H8 (dim 3) elements, nel = (nx, ny[, nz]).
+ *   node index  node = i + (nx+1)*(j + (ny+1)*k)        (x fastest)
+ *   DOF index   dof  = dim*node + c                     (interleaved)
+ *   element     e    = i + nx*(j + ny*k)
+ *   blocks      column-major, leading dimension n (DOFs) or m (elements).
+ * Vectors are full length, Dirichlet DOFs included (they hold zero in every
+ * solution and mode).  Level 1 is the fine grid; level j has nel / 2^(j-1)
+ * elements per axis, so every nel[i] must be divisible by 2^(levels-1).
+ *
+ * Ownership: the caller owns every pointer it passes.  The library copies
+ * inputs before returning (host calls) or before the enqueued work completes
+ * (device calls) and never keeps a caller pointer.  Device work memory is
+ * owned by the context and freed by mlb_destroy.
+ *
+ * Errors: every call returns an int status, MLB_OK (0) or a negative code;
+ * mlb_last_error() gives a message for the last failure on that context.
+ * A context is used by one host thread at a time.
+ *
+ * Streams: *_dev calls take device pointers and a hipStream_t passed as
+ * void* (NULL = the context's own stream).  Kernel-level *_dev calls only
+ * enqueue work.  Solver calls (static, buckling, sensitivities) synchronise
+ * the stream they run on, because convergence is decided on the host.
+ */
+#ifndef MLB_H
+#define MLB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MLB_OK          0
+#define MLB_EINVAL     -1   /* bad argument: sizes, NaN/Inf, density outside [0,1] */
+#define MLB_ESTATE     -2   /* call order: e.g. buckling before a static solve */
+#define MLB_ENOMEM     -3   /* device allocation failed */
+#define MLB_EDEVICE    -4   /* HIP runtime error */
+#define MLB_ENOTCONV   -5   /* iteration limit reached; outputs hold the last iterate */
+#define MLB_ENOPOS     -6   /* fewer than k positive buckling factors */
+#define MLB_EBREAKDOWN -7   /* CG breakdown (p^T K p <= 0) or singular Gram matrix */
+
+/* precision of the preconditioner (the outer Krylov solvers are FP64) */
+#define MLB_FP64   0
+#define MLB_MIXED  1        /* FP32 V-cycle; FP64 outer CG, coarsest solve, Rayleigh-Ritz */
+
+/* warm-start kinds for mlb_set_warm_start */
+#define MLB_WARM_NONE    0
+#define MLB_WARM_COARSE  1  /* start block for the coarse eigensolve */
+#define MLB_WARM_STATIC  2  /* initial guess for the static solve */
+
+typedef struct mlb_ctx mlb_ctx;
+
+/* Problem description (copied by mlb_create). */
+typedef struct {
+    int dim;            /* 2 (Q4) or 3 (H8) */
+    int nel[3];         /* elements per axis; nel[2] ignored when dim == 2 */
+    double E1;          /* solid Young modulus (Sec. 2) */
+    double E0;          /* void modulus in E_kappa only; E_sigma has no floor */
+    double nu;          /* Poisson ratio */
+    double penal;       /* SIMP exponent p */
+    int mg_levels;      /* geometric multigrid levels, >= 1 (1: Jacobi-PCG) */
+    int eig_level;      /* level l of the coarse eigenproblem, 1..mg_levels */
+    int precision;      /* MLB_FP64 or MLB_MIXED */
+    int device;         /* HIP device ordinal */
+} mlb_desc;
+
+/* Solver options (mlb_set_opts); zero fields keep their defaults. */
+typedef struct {
+    int smooth_steps;     /* Jacobi sweeps before and after the coarse correction (default 2) */
+    double jacobi_omega;  /* damping factor times rho(D^-1 A); default 4/3 (omega = 4/(3 rho)) */
+    int eig_guard;        /* extra vectors in the coarse eigensolver block (default max(4, k/2)) */
+    int eig_max_it;       /* coarse eigensolver iteration limit (default 400) */
+    int check_every;      /* CG iterations between host convergence checks (default 1) */
+    uint64_t seed;        /* seed of the coarse eigensolver start block (default 1) */
+} mlb_opts;
+
+/* Per-call solver report; for blocks, the worst column is reported. */
+typedef struct {
+    int iterations;             /* CG iterations of the last solve */
+    int converged;              /* 1 if every column met the tolerance */
+    double rel_residual;        /* recursive ||r|| / ||b|| at exit */
+    double true_rel_residual;   /* ||b - K x|| / ||b|| recomputed at exit */
+    double seconds;             /* wall time of the call */
+} mlb_solve_info;
+
+typedef struct {
+    int coarse_iterations;      /* coarse eigensolver iterations */
+    double coarse_residual;     /* max relative residual of the coarse pairs */
+    double coarse_gap;          /* (mu_k - mu_{k+1}) / mu_k at the coarse level */
+    int fine_iterations;        /* CG iterations of the fine block solve K Phi~ = G Psi */
+    double fine_true_residual;  /* worst true relative residual of that solve */
+    double seconds_coarse;      /* Galerkin operators + coarse eigensolve */
+    double seconds_fine;        /* interpolation + fine block solve */
+    double seconds_ritz;        /* Rayleigh-Ritz + residuals */
+} mlb_eig_info;
+
+/* ---- lifetime --------------------------------------------------------- */
+
+/* Creates a context on desc->device: element tables, grid hierarchy and
+ * device work buffers.  EINVAL for bad sizes or levels; ENOMEM/EDEVICE. */
+int mlb_create(const mlb_desc* desc, mlb_ctx** out);
+void mlb_destroy(mlb_ctx* ctx);
+const char* mlb_last_error(const mlb_ctx* ctx);
+int mlb_set_opts(mlb_ctx* ctx, const mlb_opts* opts);
+/* Sizes: DOFs and elements of level `level` (1 = fine). */
+int mlb_level_size(const mlb_ctx* ctx, int level, int64_t* n_dofs, int64_t* n_elems);
+
+/* ---- problem data (Alg. 1 line 1; Sec. 2) ------------------------------ */
+
+/* Dirichlet mask, one byte per DOF (nonzero = fixed).  The fixed set must be
+ * nested: every fixed fine DOF may interpolate only from fixed coarse DOFs
+ * (true for clamped faces/edges); otherwise EINVAL. */
+int mlb_set_bc(mlb_ctx* ctx, const uint8_t* fixed);
+int mlb_set_bc_dev(mlb_ctx* ctx, const uint8_t* fixed, void* stream);
+/* Load cases F (n x ncases, column-major).  Entries at fixed DOFs are ignored. */
+int mlb_set_loads(mlb_ctx* ctx, int ncases, const double* F);
+int mlb_set_loads_dev(mlb_ctx* ctx, int ncases, const double* F, void* stream);
+/* Physical densities x (m), each in [0, 1] (EINVAL otherwise, or NaN).
+ * Builds the multigrid hierarchy for K[x]; invalidates previous solutions. */
+int mlb_set_density(mlb_ctx* ctx, const double* x);
+int mlb_set_density_dev(mlb_ctx* ctx, const double* x, void* stream);
+
+/* ---- analysis -------------------------------------------------------- */
+
+/* LA (Alg. 1 line 2): U = K^-1 F for every load case by multigrid-
+ * preconditioned CG to ||F - K U|| <= tol ||F|| per column; J = f^T u.
+ * U (n x ncases) and J (ncases) may be NULL.  ENOTCONV after max_it. */
+int mlb_solve_static(mlb_ctx* ctx, double tol, int max_it, double* U, double* J,
+                     mlb_solve_info* info);
+int mlb_solve_static_dev(mlb_ctx* ctx, double tol, int max_it, double* U, double* J_host,
+                         mlb_solve_info* info, void* stream);
+
+/* EA by the multilevel procedure (Sec. 2.1 steps 1-4) for load case
+ * ref_case: G[x, u] from that case, Galerkin K^l, G^l, lowest k positive
+ * coarse pairs to relative residual tol_eig, interpolation to the fine
+ * grid, K Phi~ = G Psi to relative residual `tol_solve` (set by
+ * mlb_solve_static's tol), Rayleigh-Ritz.  lambda (k, ascending) and Phi
+ * (n x k, K-normalised, largest-magnitude entry positive) may be NULL.
+ * With eig_level == 1 the eigensolve runs on the fine grid (exact pairs).
+ * ESTATE without a converged static solve; ENOPOS if fewer than k
+ * positive factors exist; ENOTCONV if the coarse eigensolver stalls. */
+int mlb_buckling(mlb_ctx* ctx, int ref_case, int k, double tol_eig, double* lambda,
+                 double* Phi, mlb_eig_info* info);
+int mlb_buckling_dev(mlb_ctx* ctx, int ref_case, int k, double tol_eig, double* lambda_host,
+                     double* Phi, mlb_eig_info* info, void* stream);
+
+/* Residual norms ||(K + lambda_i G) phi_i||_inf of the last buckling call
+ * (eq. eigResidual); res_inf has k entries (host). */
+int mlb_eig_residuals(mlb_ctx* ctx, double* res_inf);
+
+/* Sensitivities w.r.t. the physical densities (no filter/projection):
+ * dJ (m x ncases) = -p x^(p-1) (E1-E0) u_e^T K_e0 u_e; dlam (m x k) for the
+ * pairs of the last buckling call:
+ *   dlam_i/dx_e = lam_i [phi_i^T K'_e phi_i + lam_i (phi_i^T G'_e phi_i - z_i^T K'_e u)]
+ * with K z_i = grad_u(phi_i^T G phi_i) solved as one block (eq. AdjointSystem).
+ * (eq. SensitivityLambda times lam_i, the factor the normalisation
+ * phi^T K phi = 1 implies.)  Either output may be NULL; ESTATE if dlam is
+ * requested before mlb_buckling. */
+int mlb_sensitivities(mlb_ctx* ctx, double* dJ, double* dlam, mlb_solve_info* info);
+int mlb_sensitivities_dev(mlb_ctx* ctx, double* dJ, double* dlam, mlb_solve_info* info,
+                          void* stream);
+
+/* Warm starts.  kind MLB_WARM_COARSE: `data` holds ncols start vectors of
+ * the eigen level (n_l x ncols, column-major, host); MLB_WARM_STATIC: one
+ * fine initial guess per load case (n x ncases, host).  MLB_WARM_NONE
+ * clears both.  A warm start only changes iteration counts, never the
+ * tolerance the solvers reach. */
+int mlb_set_warm_start(mlb_ctx* ctx, int kind, int ncols, const double* data);
+
+/* ---- kernel-level entry points (device pointers, enqueue only) -------- */
+
+/* y = A x on level `level` for ncols columns (leading dimension n_level),
+ * A = K (identity rows/columns at fixed DOFs).  Level 1 is matrix-free;
+ * levels > 1 use the Galerkin element matrices built by mlb_set_density. */
+int mlb_apply_K_dev(mlb_ctx* ctx, int level, int ncols, const double* x, double* y, void* stream);
+/* y = G x (zero rows/columns at fixed DOFs) for the stress state of the
+ * last mlb_set_state_dev / static solve; levels > 1 after mlb_buckling. */
+int mlb_apply_G_dev(mlb_ctx* ctx, int level, int ncols, const double* x, double* y, void* stream);
+/* Sets the reference displacement u (n, device) used for G[x, u]; computes
+ * element stresses E_sigma(x_e) D0 B_c u_e (centroid), stored SoA (m x nv)
+ * into `stress_out` when non-NULL. */
+int mlb_set_state_dev(mlb_ctx* ctx, const double* u, double* stress_out, void* stream);
+/* Interpolation from level+1 to level (y = P x) and restriction (y = P^T x)
+ * of ncols columns, masked at fixed DOFs of both levels. */
+int mlb_prolong_dev(mlb_ctx* ctx, int level, int ncols, const double* xc, double* yf, void* stream);
+int mlb_restrict_dev(mlb_ctx* ctx, int level, int ncols, const double* xf, double* yc, void* stream);
+/* One multigrid V-cycle z = M^-1 r starting at `level` (ncols columns). */
+int mlb_vcycle_dev(mlb_ctx* ctx, int level, int ncols, const double* r, double* z, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLB_H */

@@ -1,0 +1,211 @@
+"""MI355X multilevel linearized-buckling engine (Python binding).
+
+Thin wrapper around the C ABI of ``include/mlb.h``: every call marshals
+arguments and forwards to ``libmlb.so`` (hand-written HIP kernels for gfx950).
+Host arrays are numpy float64 / uint8; device arrays are torch tensors on the
+GPU (torch supplies device memory and the current stream only).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _binding as B
+from ._binding import (MLB_FP64, MLB_MIXED, MLB_WARM_COARSE, MLB_WARM_NONE, MLB_WARM_STATIC, MlbError,
+                       MlbEigInfo, MlbSolveInfo)
+
+__all__ = ["Context", "MlbError", "MLB_FP64", "MLB_MIXED", "MLB_WARM_NONE", "MLB_WARM_COARSE",
+           "MLB_WARM_STATIC", "load_library"]
+
+
+def load_library():
+    return B.load()
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _info_dict(info):
+    return {f: getattr(info, f) for f, _ in info._fields_}
+
+
+class Context:
+    """One analysis context (``mlb_ctx``) for a fixed grid and material."""
+
+    def __init__(self, nel, E1=1.0, E0=1e-6, nu=0.3, penal=3.0, mg_levels=3, eig_level=2,
+                 precision=MLB_FP64, device=0):
+        self.lib = B.load()
+        d = B.MlbDesc()
+        d.dim = len(nel)
+        for i, v in enumerate(nel):
+            d.nel[i] = int(v)
+        d.E1, d.E0, d.nu, d.penal = E1, E0, nu, penal
+        d.mg_levels, d.eig_level, d.precision, d.device = mg_levels, eig_level, precision, device
+        self.nel = tuple(int(v) for v in nel)
+        self.dim = d.dim
+        self.mg_levels, self.eig_level = mg_levels, eig_level
+        h = C.c_void_p()
+        st = self.lib.mlb_create(C.byref(d), C.byref(h))
+        self.h = h
+        if st != B.MLB_OK:
+            msg = self.last_error()
+            self.close()
+            raise MlbError(st, msg)
+        self.n, self.m = self.level_size(1)
+        self.k = 0
+        self.ncases = 0
+
+    # -- plumbing
+    def last_error(self):
+        if not self.h:
+            return ""
+        return self.lib.mlb_last_error(self.h).decode()
+
+    def _check(self, st):
+        if st != B.MLB_OK:
+            raise MlbError(st, self.last_error())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mlb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def level_size(self, level):
+        n = C.c_int64()
+        m = C.c_int64()
+        self._check(self.lib.mlb_level_size(self.h, level, C.byref(n), C.byref(m)))
+        return n.value, m.value
+
+    def set_opts(self, smooth_steps=0, jacobi_omega=0.0, eig_guard=0, eig_max_it=0, check_every=0, seed=0):
+        o = B.MlbOpts(smooth_steps, jacobi_omega, eig_guard, eig_max_it, check_every, seed)
+        self._check(self.lib.mlb_set_opts(self.h, C.byref(o)))
+
+    # -- problem data (host)
+    def set_bc(self, fixed):
+        f = np.ascontiguousarray(fixed, dtype=np.uint8)
+        assert f.shape == (self.n,)
+        self._check(self.lib.mlb_set_bc(self.h, _ptr(f)))
+
+    def set_loads(self, F):
+        F = np.asarray(F, dtype=np.float64)
+        if F.ndim == 1:
+            F = F[:, None]
+        Fc = np.asfortranarray(F)
+        assert Fc.shape[0] == self.n
+        self.ncases = Fc.shape[1]
+        self._check(self.lib.mlb_set_loads(self.h, self.ncases, C.c_void_p(Fc.ctypes.data)))
+
+    def set_density(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        assert x.shape == (self.m,)
+        self._check(self.lib.mlb_set_density(self.h, _ptr(x)))
+
+    def set_warm_start(self, kind, data=None):
+        if kind == MLB_WARM_NONE:
+            self._check(self.lib.mlb_set_warm_start(self.h, kind, 0, None))
+            return
+        D = np.asfortranarray(np.asarray(data, dtype=np.float64))
+        if D.ndim == 1:
+            D = D[:, None]
+        self._check(self.lib.mlb_set_warm_start(self.h, kind, D.shape[1], C.c_void_p(D.ctypes.data)))
+
+    # -- analysis (host outputs)
+    def solve_static(self, tol=1e-8, max_it=1000):
+        U = np.zeros((self.n, self.ncases), order="F")
+        J = np.zeros(self.ncases)
+        info = MlbSolveInfo()
+        self._check(self.lib.mlb_solve_static(self.h, tol, max_it, C.c_void_p(U.ctypes.data), _ptr(J),
+                                              C.byref(info)))
+        return U, J, _info_dict(info)
+
+    def buckling(self, k, ref_case=0, tol_eig=1e-10, want_modes=True):
+        lam = np.zeros(k)
+        Phi = np.zeros((self.n, k), order="F") if want_modes else None
+        info = MlbEigInfo()
+        self._check(self.lib.mlb_buckling(self.h, ref_case, k, tol_eig, _ptr(lam),
+                                          C.c_void_p(Phi.ctypes.data) if want_modes else None, C.byref(info)))
+        self.k = k
+        return lam, Phi, _info_dict(info)
+
+    def eig_residuals(self):
+        r = np.zeros(self.k)
+        self._check(self.lib.mlb_eig_residuals(self.h, _ptr(r)))
+        return r
+
+    def sensitivities(self, compliance=True, buckling=True):
+        dJ = np.zeros((self.m, self.ncases), order="F") if compliance else None
+        dl = np.zeros((self.m, self.k), order="F") if buckling else None
+        info = MlbSolveInfo()
+        self._check(self.lib.mlb_sensitivities(self.h, C.c_void_p(dJ.ctypes.data) if compliance else None,
+                                               C.c_void_p(dl.ctypes.data) if buckling else None, C.byref(info)))
+        return dJ, dl, _info_dict(info)
+
+    # -- device variants (torch tensors on the GPU, current stream)
+    def set_density_dev(self, x):
+        self._check(self.lib.mlb_set_density_dev(self.h, _dptr(x), _stream()))
+
+    def solve_static_dev(self, U, tol=1e-8, max_it=1000):
+        J = np.zeros(self.ncases)
+        info = MlbSolveInfo()
+        self._check(self.lib.mlb_solve_static_dev(self.h, tol, max_it, _dptr(U), _ptr(J), C.byref(info),
+                                                  _stream()))
+        return J, _info_dict(info)
+
+    def buckling_dev(self, k, Phi=None, ref_case=0, tol_eig=1e-10):
+        lam = np.zeros(k)
+        info = MlbEigInfo()
+        self._check(self.lib.mlb_buckling_dev(self.h, ref_case, k, tol_eig, _ptr(lam), _dptr(Phi), C.byref(info),
+                                              _stream()))
+        self.k = k
+        return lam, _info_dict(info)
+
+    def sensitivities_dev(self, dJ=None, dlam=None):
+        info = MlbSolveInfo()
+        self._check(self.lib.mlb_sensitivities_dev(self.h, _dptr(dJ), _dptr(dlam), C.byref(info), _stream()))
+        return _info_dict(info)
+
+    def apply_K_dev(self, level, x, y):
+        self._check(self.lib.mlb_apply_K_dev(self.h, level, x.shape[0] if x.dim() > 1 else 1,
+                                             _dptr(x), _dptr(y), _stream()))
+
+    def apply_G_dev(self, level, x, y):
+        self._check(self.lib.mlb_apply_G_dev(self.h, level, x.shape[0] if x.dim() > 1 else 1,
+                                             _dptr(x), _dptr(y), _stream()))
+
+    def set_state_dev(self, u, stress_out=None):
+        self._check(self.lib.mlb_set_state_dev(self.h, _dptr(u), _dptr(stress_out), _stream()))
+
+    def prolong_dev(self, level, xc, yf):
+        self._check(self.lib.mlb_prolong_dev(self.h, level, xc.shape[0] if xc.dim() > 1 else 1,
+                                             _dptr(xc), _dptr(yf), _stream()))
+
+    def restrict_dev(self, level, xf, yc):
+        self._check(self.lib.mlb_restrict_dev(self.h, level, xf.shape[0] if xf.dim() > 1 else 1,
+                                              _dptr(xf), _dptr(yc), _stream()))
+
+    def vcycle_dev(self, level, r, z):
+        self._check(self.lib.mlb_vcycle_dev(self.h, level, r.shape[0] if r.dim() > 1 else 1,
+                                            _dptr(r), _dptr(z), _stream()))

@@ -1,0 +1,118 @@
+"""ctypes binding of the C ABI in ``include/mlb.h`` (argument marshalling only).
+
+Every function here forwards to the HIP library ``libmlb.so``; no step of the
+analysis runs in Python.  Loading fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlb.so")
+
+MLB_OK = 0
+MLB_EINVAL = -1
+MLB_ESTATE = -2
+MLB_ENOMEM = -3
+MLB_EDEVICE = -4
+MLB_ENOTCONV = -5
+MLB_ENOPOS = -6
+MLB_EBREAKDOWN = -7
+MLB_FP64 = 0
+MLB_MIXED = 1
+MLB_WARM_NONE = 0
+MLB_WARM_COARSE = 1
+MLB_WARM_STATIC = 2
+
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EDEVICE", -5: "ENOTCONV",
+                -6: "ENOPOS", -7: "EBREAKDOWN"}
+
+
+class MlbDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nel", C.c_int * 3), ("E1", C.c_double), ("E0", C.c_double),
+                ("nu", C.c_double), ("penal", C.c_double), ("mg_levels", C.c_int), ("eig_level", C.c_int),
+                ("precision", C.c_int), ("device", C.c_int)]
+
+
+class MlbOpts(C.Structure):
+    _fields_ = [("smooth_steps", C.c_int), ("jacobi_omega", C.c_double), ("eig_guard", C.c_int),
+                ("eig_max_it", C.c_int), ("check_every", C.c_int), ("seed", C.c_uint64)]
+
+
+class MlbSolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("rel_residual", C.c_double),
+                ("true_rel_residual", C.c_double), ("seconds", C.c_double)]
+
+
+class MlbEigInfo(C.Structure):
+    _fields_ = [("coarse_iterations", C.c_int), ("coarse_residual", C.c_double), ("coarse_gap", C.c_double),
+                ("fine_iterations", C.c_int), ("fine_true_residual", C.c_double), ("seconds_coarse", C.c_double),
+                ("seconds_fine", C.c_double), ("seconds_ritz", C.c_double)]
+
+
+_P = C.c_void_p
+_I = C.c_int
+_D = C.c_double
+_SIGS = {
+    "mlb_create": (_I, [C.POINTER(MlbDesc), C.POINTER(_P)]),
+    "mlb_destroy": (None, [_P]),
+    "mlb_last_error": (C.c_char_p, [_P]),
+    "mlb_set_opts": (_I, [_P, C.POINTER(MlbOpts)]),
+    "mlb_level_size": (_I, [_P, _I, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "mlb_set_bc": (_I, [_P, _P]),
+    "mlb_set_bc_dev": (_I, [_P, _P, _P]),
+    "mlb_set_loads": (_I, [_P, _I, _P]),
+    "mlb_set_loads_dev": (_I, [_P, _I, _P, _P]),
+    "mlb_set_density": (_I, [_P, _P]),
+    "mlb_set_density_dev": (_I, [_P, _P, _P]),
+    "mlb_solve_static": (_I, [_P, _D, _I, _P, _P, C.POINTER(MlbSolveInfo)]),
+    "mlb_solve_static_dev": (_I, [_P, _D, _I, _P, _P, C.POINTER(MlbSolveInfo), _P]),
+    "mlb_buckling": (_I, [_P, _I, _I, _D, _P, _P, C.POINTER(MlbEigInfo)]),
+    "mlb_buckling_dev": (_I, [_P, _I, _I, _D, _P, _P, C.POINTER(MlbEigInfo), _P]),
+    "mlb_eig_residuals": (_I, [_P, _P]),
+    "mlb_sensitivities": (_I, [_P, _P, _P, C.POINTER(MlbSolveInfo)]),
+    "mlb_sensitivities_dev": (_I, [_P, _P, _P, C.POINTER(MlbSolveInfo), _P]),
+    "mlb_set_warm_start": (_I, [_P, _I, _I, _P]),
+    "mlb_apply_K_dev": (_I, [_P, _I, _I, _P, _P, _P]),
+    "mlb_apply_G_dev": (_I, [_P, _I, _I, _P, _P, _P]),
+    "mlb_set_state_dev": (_I, [_P, _P, _P, _P]),
+    "mlb_prolong_dev": (_I, [_P, _I, _I, _P, _P, _P]),
+    "mlb_restrict_dev": (_I, [_P, _I, _I, _P, _P, _P]),
+    "mlb_vcycle_dev": (_I, [_P, _I, _I, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Loads libmlb.so and declares every signature; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is not built; run __graft_entry__.build()")
+    # torch supplies device memory and streams, so the process must use ONE
+    # HIP runtime: load torch (and its libamdhip64) before libmlb so that the
+    # library's libamdhip64.so.7 dependency resolves to the same copy.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+class MlbError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status

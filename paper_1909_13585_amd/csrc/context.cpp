@@ -1,0 +1,1397 @@
+// Host runtime behind the C ABI: context, multigrid hierarchy, V-cycle,
+// block PCG, coarse eigensolver, Rayleigh-Ritz and sensitivities.
+//
+// The analysis follows the paper (Alg. 1 and Sec. 2.1):
+//   LA       K u = f by CG preconditioned with a geometric-multigrid V-cycle
+//            on the nested grids (Alg. 2 line 3, "mgPCG");
+//   step 1   Galerkin K^l = P^T K P, G^l = P^T G P (Alg. 2 line 5) and the
+//            lowest k positive pairs of (K^l + lambda G^l) psi = 0;
+//   step 2   Psi = P_{1<-l} Psi^l;
+//   step 3   K Phi~ = G Psi as one multi-column PCG (Alg. 2 line 16);
+//   step 4   Rayleigh-Ritz on span(Phi~) (Alg. 2 line 17).
+// The coarse eigensolver is LOBPCG for the largest mu = 1/lambda of
+// (-G^l) psi = mu K^l psi, preconditioned by the V-cycle of the levels below
+// l.  (The paper uses Krylov-Schur; that choice is prior art here.)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mlb.h"
+#include "dense.h"
+#include "kernels.h"
+#include "tables.h"
+
+using namespace mlb;
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Level {
+    Geo g{};
+    int64_t n = 0;
+    uint8_t* nmask = nullptr;
+    double* Ke = nullptr;     // dense element matrices (levels >= 2), SoA entry-major
+    float* Kef = nullptr;
+    double* dinv = nullptr;
+    float* dinvf = nullptr;
+    double omega = 0.6;
+    // V-cycle work, wcols columns each
+    double *vr = nullptr, *vz = nullptr, *vz2 = nullptr, *vt = nullptr;
+    float *fr = nullptr, *fz = nullptr, *fz2 = nullptr, *ft = nullptr;
+};
+
+}  // namespace
+
+struct mlb_ctx {
+    mlb_desc d{};
+    mlb_opts o{};
+    int dim = 0, nn = 0, nde = 0, nv = 0, L = 1, ell = 1;
+    hipStream_t own = nullptr, st = nullptr;
+    Tables tab{};
+    double *dK0 = nullptr, *dHk = nullptr, *dBc = nullptr, *dD0Bc = nullptr, *dD0 = nullptr, *dT = nullptr,
+           *dMc = nullptr, *dGHc = nullptr;
+    float* fK0 = nullptr;
+    std::vector<Level> lv;
+    int64_t n = 0, m = 0;
+    // fine-level problem data
+    double *x = nullptr, *Ek = nullptr, *Es = nullptr;
+    float* Ekf = nullptr;
+    uint8_t* fixed = nullptr;
+    std::vector<uint8_t> fixed_host;
+    bool has_bc = false, has_density = false, has_static = false, has_stress = false, has_buck = false;
+    int ncases = 0;
+    int ref_case_used = 0;
+    double* F = nullptr;
+    double* U = nullptr;
+    std::vector<double> J;
+    double tol_solve = 1e-8;
+    int max_it = 1000;
+    double* S = nullptr;   // element stresses of the reference case (SoA nv x m)
+    double* Gl = nullptr;  // scalar G element matrices at the eigen level (> 1)
+    // coarsest level dense inverse
+    double* Ainv = nullptr;
+    double *gj_r0 = nullptr, *gj_c0 = nullptr, *gj_r1 = nullptr, *gj_c1 = nullptr;
+    // block work (fine level, cg_cap columns)
+    int cg_cap = 0;
+    double *R = nullptr, *Zb = nullptr, *Pb = nullptr, *Qb = nullptr, *Zo = nullptr, *X1 = nullptr, *X2 = nullptr;
+    int wcols = 0;   // columns of the level buffers
+    // eigen
+    int k = 0;
+    double *Phi = nullptr, *Zadj = nullptr, *dlam_l = nullptr;
+    std::vector<double> lam, eigres;
+    // coarse eigensolver work
+    int eig_cap = 0;
+    double *eS = nullptr, *eK = nullptr, *eA = nullptr, *eT = nullptr, *eTK = nullptr, *eTA = nullptr, *eR = nullptr;
+    double *eP = nullptr, *ePK = nullptr, *ePA = nullptr;
+    // reductions and scalars
+    double* part = nullptr;
+    int64_t part_cap = 0;
+    int64_t* pidx = nullptr;
+    double* scal = nullptr;   // 16 blocks of kScal doubles
+    double* gbuf = nullptr;   // summed Gram matrices (up to 96 x 96)
+    double *cbuf = nullptr, *cbuf2 = nullptr;   // small coefficient matrices
+    int* iscal = nullptr;     // active / flags
+    double* hpin = nullptr;   // pinned host scalars (>= 96 x 96)
+    // warm starts
+    std::vector<double> warm_coarse;
+    int warm_coarse_cols = 0;
+    std::vector<double> warm_static;
+    std::string err;
+};
+
+namespace {
+
+constexpr int kScal = 256;
+
+int fail(mlb_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPC(call)                                                                            \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(c, MLB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+#define CHK(expr)               \
+    do {                                \
+        int r_ = (expr);        \
+        if (r_ != MLB_OK) return r_;    \
+    } while (0)
+
+template <typename T>
+int dalloc(mlb_ctx* c, T** p, size_t count) {
+    if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+    }
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, MLB_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    return MLB_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+double* sc(mlb_ctx* c, int slot) { return c->scal + slot * kScal; }
+
+int ensure_part(mlb_ctx* c, int64_t count) {
+    if (count <= c->part_cap) return MLB_OK;
+    CHK(dalloc(c, &c->part, count));
+    CHK(dalloc(c, &c->pidx, count));
+    c->part_cap = count;
+    return MLB_OK;
+}
+
+int sync(mlb_ctx* c) {
+    HIPC(hipStreamSynchronize(c->st));
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+// ---- level buffers
+
+int ensure_level_cols(mlb_ctx* c, int cols) {
+    if (cols <= c->wcols) return MLB_OK;
+    for (auto& l : c->lv) {
+        const size_t s = (size_t)l.n * cols;
+        CHK(dalloc(c, &l.vr, s));
+        CHK(dalloc(c, &l.vz, s));
+        CHK(dalloc(c, &l.vz2, s));
+        CHK(dalloc(c, &l.vt, s));
+        CHK(dalloc(c, &l.fr, s));
+        CHK(dalloc(c, &l.fz, s));
+        CHK(dalloc(c, &l.fz2, s));
+        CHK(dalloc(c, &l.ft, s));
+    }
+    c->wcols = cols;
+    return MLB_OK;
+}
+
+int ensure_cg(mlb_ctx* c, int cols) {
+    CHK(ensure_level_cols(c, cols));
+    if (cols <= c->cg_cap) return MLB_OK;
+    const size_t s = (size_t)c->n * cols;
+    CHK(dalloc(c, &c->R, s));
+    CHK(dalloc(c, &c->Zb, s));
+    CHK(dalloc(c, &c->Pb, s));
+    CHK(dalloc(c, &c->Qb, s));
+    CHK(dalloc(c, &c->Zo, s));
+    CHK(dalloc(c, &c->X1, s));
+    CHK(dalloc(c, &c->X2, s));
+    c->cg_cap = cols;
+    return MLB_OK;
+}
+
+// ---- operators
+
+template <typename T>
+const T* E_of(mlb_ctx* c);
+template <>
+const double* E_of<double>(mlb_ctx* c) { return c->Ek; }
+template <>
+const float* E_of<float>(mlb_ctx* c) { return c->Ekf; }
+template <typename T>
+const T* K0_of(mlb_ctx* c);
+template <>
+const double* K0_of<double>(mlb_ctx* c) { return c->dK0; }
+template <>
+const float* K0_of<float>(mlb_ctx* c) { return c->fK0; }
+template <typename T>
+const T* Ke_of(Level& l);
+template <>
+const double* Ke_of<double>(Level& l) { return l.Ke; }
+template <>
+const float* Ke_of<float>(Level& l) { return l.Kef; }
+template <typename T>
+const T* dinv_of(Level& l);
+template <>
+const double* dinv_of<double>(Level& l) { return l.dinv; }
+template <>
+const float* dinv_of<float>(Level& l) { return l.dinvf; }
+
+// y = A_j x (mode Y), y = r - A_j x (residual), y = x + omega D^-1 (r - A_j x) (Jacobi)
+template <typename T>
+void apply_K(mlb_ctx* c, int j, int nc, const T* x, T* y, int mode, const T* r, double* dot_part) {
+    Level& l = c->lv[j - 1];
+    if (j == 1)
+        launch_apply_fine<T>(c->dim, l.g, E_of<T>(c), l.nmask, K0_of<T>(c), nc, l.n, x, y, mode, r,
+                             dinv_of<T>(l), (T)l.omega, dot_part, c->st);
+    else
+        launch_apply_dense<T>(c->dim, l.g, Ke_of<T>(l), false, l.nmask, nc, l.n, x, y, mode, r, dinv_of<T>(l),
+                              (T)l.omega, c->st);
+}
+
+void apply_G(mlb_ctx* c, int j, int nc, const double* x, double* y) {
+    Level& l = c->lv[j - 1];
+    if (j == 1) launch_apply_G_fine(c->dim, l.g, c->S, l.nmask, c->dHk, nc, l.n, x, y, c->st);
+    else launch_apply_dense<double>(c->dim, l.g, c->Gl, true, l.nmask, nc, l.n, x, y, kModeY, nullptr, nullptr, 0.0, c->st);
+}
+
+template <typename T>
+T* lbuf(Level& l, int which);
+template <>
+double* lbuf<double>(Level& l, int w) { return w == 0 ? l.vr : w == 1 ? l.vz : w == 2 ? l.vz2 : l.vt; }
+template <>
+float* lbuf<float>(Level& l, int w) { return w == 0 ? l.fr : w == 1 ? l.fz : w == 2 ? l.fz2 : l.ft; }
+
+// One V(nu,nu)-cycle with damped Jacobi, symmetric (same sweeps before and
+// after, restriction = interpolation^T), so it is an SPD preconditioner.
+// r, z: level-j blocks with leading dimension n_j; z is overwritten.
+template <typename T>
+void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z) {
+    Level& l = c->lv[j - 1];
+    if (j == c->L) {
+        if (c->L == 1) launch_jacobi0<T>(l.n, nc, l.n, l.dinv ? dinv_of<T>(l) : nullptr, (T)1.0, r, z, c->st);
+        else launch_dense_matvec<T>(l.n, nc, l.n, c->Ainv, r, z, c->st);
+        return;
+    }
+    const int nu = std::max(1, c->o.smooth_steps);
+    T* a = lbuf<T>(l, 2);   // current iterate alternates between a and b
+    T* b = z;
+    T* t = lbuf<T>(l, 3);
+    // 2*nu - 1 Jacobi sweeps after the first: start in z2 so the result ends in z
+    launch_jacobi0<T>(l.n, nc, l.n, dinv_of<T>(l), (T)l.omega, r, a, c->st);
+    for (int s = 1; s < nu; ++s) {
+        apply_K<T>(c, j, nc, a, b, kModeJacobi, r, nullptr);
+        std::swap(a, b);
+    }
+    apply_K<T>(c, j, nc, a, t, kModeResidual, r, nullptr);
+    Level& lc = c->lv[j];
+    T* rc = lbuf<T>(lc, 0);
+    T* zc = lbuf<T>(lc, 1);
+    launch_restrict<T>(c->dim, l.g, lc.g, l.nmask, lc.nmask, nc, l.n, lc.n, t, rc, c->st);
+    vcycle<T>(c, j + 1, nc, rc, zc);
+    launch_prolong<T>(c->dim, l.g, lc.g, l.nmask, lc.nmask, nc, l.n, lc.n, zc, a, true, c->st);
+    for (int s = 0; s < nu; ++s) {
+        apply_K<T>(c, j, nc, a, b, kModeJacobi, r, nullptr);
+        std::swap(a, b);
+    }
+    // a now holds the result; by construction a == z
+}
+
+// z = M^-1 r at level j in FP64 or mixed precision (FP32 inside).
+void precondition(mlb_ctx* c, int j, int nc, const double* r, double* z) {
+    Level& l = c->lv[j - 1];
+    if (c->d.precision == MLB_MIXED) {
+        launch_d2f(l.n, nc, l.n, r, l.fr, c->st);
+        vcycle<float>(c, j, nc, l.fr, l.fz);
+        launch_f2d(l.n, nc, l.n, l.fz, z, c->st);
+    } else {
+        vcycle<double>(c, j, nc, r, z);
+    }
+}
+
+// ---- reductions
+
+// out (device, slot) = column dots of a and b (n x nc)
+void dots(mlb_ctx* c, int64_t n, int nc, const double* a, const double* b, double* out) {
+    const int np = reduction_parts(n);
+    launch_dot_part(n, nc, n, a, n, b, np, c->part, c->st);
+    launch_sum_parts(nc, np, c->part, out, c->st);
+}
+
+int read_scal(mlb_ctx* c, const double* dev, int count, double* host) {
+    HIPC(hipMemcpyAsync(c->hpin, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->st));
+    CHK(sync(c));
+    std::memcpy(host, c->hpin, sizeof(double) * count);
+    return MLB_OK;
+}
+
+// Gram A^T B (n x k1, n x k2) -> host column-major k1 x k2 (G[i + k1*j]).
+int gram(mlb_ctx* c, int64_t n, int k1, const double* A, int64_t lda, int k2, const double* B, int64_t ldb,
+         std::vector<double>& G) {
+    const int np = std::min<int>(reduction_parts(n), 256);
+    CHK(ensure_part(c, (int64_t)np * k1 * k2));
+    launch_gram_part(n, k1, lda, A, k2, ldb, B, np, c->part, c->st);
+    launch_gram_sum(k1, k2, np, c->part, c->gbuf, c->st);
+    G.resize((size_t)k1 * k2);
+    HIPC(hipMemcpyAsync(c->hpin, c->gbuf, sizeof(double) * k1 * k2, hipMemcpyDeviceToHost, c->st));
+    CHK(sync(c));
+    std::memcpy(G.data(), c->hpin, sizeof(double) * k1 * k2);
+    return MLB_OK;
+}
+
+// ---- PCG on the fine level for nc columns: K X = B.
+// X holds the initial guess when use_x0, else it is zeroed.
+int pcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, bool use_x0, mlb_solve_info* info) {
+    const double t0 = now_s();
+    const int64_t n = c->n;
+    CHK(ensure_cg(c, nc));
+    const int npa = (int)apply_fine_blocks(c->lv[0].g);
+    const int np = reduction_parts(n);
+    CHK(ensure_part(c, (int64_t)std::max(npa, np) * nc));
+    double* bb = sc(c, 0);
+    double* rr = sc(c, 1);
+    double* rz = sc(c, 2);
+    double* pq = sc(c, 3);
+    double* alpha = sc(c, 4);
+    double* beta = sc(c, 5);
+    double* rzn = sc(c, 6);
+    int* active = c->iscal;
+    int* flags = c->iscal + kScal;
+    const bool flex = c->d.precision == MLB_MIXED;
+
+    dots(c, n, nc, B, B, bb);
+    if (use_x0) {
+        apply_K<double>(c, 1, nc, X, c->R, kModeResidual, B, nullptr);
+    } else {
+        HIPC(hipMemsetAsync(X, 0, sizeof(double) * n * nc, c->st));
+        launch_copy_cols(n, nc, n, B, n, c->R, c->st);
+    }
+    dots(c, n, nc, c->R, c->R, rr);
+    std::vector<double> hb(nc), hr(nc);
+    CHK(read_scal(c, bb, nc, hb.data()));
+    CHK(read_scal(c, rr, nc, hr.data()));
+    std::vector<int> act(nc);
+    int nact = 0;
+    for (int i = 0; i < nc; ++i) {
+        if (!std::isfinite(hb[i]) || !std::isfinite(hr[i]))
+            return fail(c, MLB_EINVAL, "non-finite right-hand side or initial guess");
+        act[i] = hr[i] > tol * tol * hb[i] ? 1 : 0;
+        nact += act[i];
+    }
+    HIPC(hipMemcpyAsync(active, act.data(), sizeof(int) * nc, hipMemcpyHostToDevice, c->st));
+    HIPC(hipMemsetAsync(flags, 0, sizeof(int) * nc, c->st));
+    int it = 0;
+    int status = MLB_OK;
+    if (nact > 0) {
+        precondition(c, 1, nc, c->R, c->Zb);
+        dots(c, n, nc, c->R, c->Zb, rz);
+        launch_copy_cols(n, nc, n, c->Zb, n, c->Pb, c->st);
+        const int every = std::max(1, c->o.check_every);
+        for (it = 1; it <= max_it; ++it) {
+            apply_K<double>(c, 1, nc, c->Pb, c->Qb, kModeY, nullptr, c->part);
+            launch_sum_parts(nc, npa, c->part, pq, c->st);
+            launch_cg_alpha(nc, rz, pq, active, alpha, flags, c->st);
+            launch_cg_update_xr(n, nc, n, alpha, c->Pb, c->Qb, X, c->R, np, c->part, c->st);
+            launch_sum_parts(nc, np, c->part, rr, c->st);
+            if (it % every == 0 || it == max_it) {
+                CHK(read_scal(c, rr, nc, hr.data()));
+                int fl[kScal];
+                HIPC(hipMemcpyAsync(fl, flags, sizeof(int) * nc, hipMemcpyDeviceToHost, c->st));
+                CHK(sync(c));
+                nact = 0;
+                for (int i = 0; i < nc; ++i) {
+                    if (fl[i]) return fail(c, MLB_EBREAKDOWN, "CG breakdown: p^T K p <= 0 or non-finite");
+                    if (!std::isfinite(hr[i])) return fail(c, MLB_EBREAKDOWN, "CG residual not finite");
+                    act[i] = act[i] && hr[i] > tol * tol * hb[i] ? 1 : 0;
+                    nact += act[i];
+                }
+                HIPC(hipMemcpyAsync(active, act.data(), sizeof(int) * nc, hipMemcpyHostToDevice, c->st));
+                if (nact == 0) break;
+            }
+            if (flex) dots(c, n, nc, c->R, c->Zb, sc(c, 8));   // r_{k+1} . z_k for the flexible beta
+            precondition(c, 1, nc, c->R, c->Zb);
+            dots(c, n, nc, c->R, c->Zb, rzn);
+            if (flex) launch_cg_beta_flex(nc, rzn, sc(c, 8), rz, active, beta, c->st);
+            else launch_cg_beta(nc, rzn, rz, active, beta, c->st);
+            launch_cg_update_p(n, nc, n, beta, c->Zb, c->Pb, c->st);
+        }
+        if (it > max_it) {
+            it = max_it;
+            status = MLB_ENOTCONV;
+        }
+    }
+    // true residual
+    apply_K<double>(c, 1, nc, X, c->R, kModeResidual, B, nullptr);
+    dots(c, n, nc, c->R, c->R, rr);
+    CHK(read_scal(c, rr, nc, hr.data()));
+    double worst = 0.0;
+    for (int i = 0; i < nc; ++i) {
+        const double rel = hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0;
+        worst = std::max(worst, rel);
+    }
+    if (info) {
+        info->iterations = it;
+        info->converged = status == MLB_OK;
+        info->rel_residual = worst;
+        info->true_rel_residual = worst;
+        info->seconds = now_s() - t0;
+    }
+    if (status != MLB_OK) return fail(c, status, "CG did not reach the tolerance in " + std::to_string(max_it) + " iterations");
+    return MLB_OK;
+}
+
+}  // namespace
+
+
+namespace {
+
+// ---- hierarchy setup (per density)
+
+// rho(D^-1 A_j) by 12 power iterations kept on the device (one host read),
+// then omega_j = jacobi_omega / (1.05 rho).
+int estimate_omega(mlb_ctx* c, int j) {
+    Level& l = c->lv[j - 1];
+    double* v = l.vz;
+    double* w = l.vz2;
+    double* nrm = sc(c, 9);
+    double* inv = sc(c, 10);
+    launch_random_fill(l.n, 1, l.n, 0x5eedull + (uint64_t)j, l.nmask, c->dim, v, c->st);
+    dots(c, l.n, 1, v, v, nrm);
+    launch_rsqrt(1, nrm, inv, c->st);
+    launch_scale_cols(l.n, 1, l.n, inv, v, c->st);
+    for (int it = 0; it < 12; ++it) {
+        apply_K<double>(c, j, 1, v, w, kModeY, nullptr, nullptr);
+        launch_jacobi0<double>(l.n, 1, l.n, l.dinv, 1.0, w, w, c->st);   // w = D^-1 A v
+        dots(c, l.n, 1, w, w, nrm);
+        launch_rsqrt(1, nrm, inv, c->st);
+        launch_scale_cols(l.n, 1, l.n, inv, w, c->st);
+        std::swap(v, w);
+    }
+    double h;
+    CHK(read_scal(c, nrm, 1, &h));
+    const double rho = std::sqrt(std::max(h, 0.0));
+    if (!(rho > 0.0) || !std::isfinite(rho)) return fail(c, MLB_EINVAL, "Jacobi spectral radius estimate failed");
+    l.omega = c->o.jacobi_omega / (1.05 * rho);
+    return MLB_OK;
+}
+
+int build_hierarchy(mlb_ctx* c) {
+    const int dim = c->dim;
+    Level& l1 = c->lv[0];
+    launch_dinv_fine(dim, l1.g, c->Ek, l1.nmask, c->dK0, l1.dinv, l1.dinvf, c->st);
+    for (int j = 2; j <= c->L; ++j) {
+        Level& lf = c->lv[j - 2];
+        Level& lc = c->lv[j - 1];
+        if (j == 2) launch_galerkin_from_E(dim, lf.g, lc.g, c->Ek, c->dMc, lc.Ke, c->st);
+        else launch_galerkin_dense(dim, false, lf.g, lc.g, lf.Ke, c->dT, lc.Ke, c->st);
+        launch_to_float(lc.g.m * c->nde * c->nde, lc.Ke, lc.Kef, c->st);
+        launch_dinv_dense(dim, lc.g, lc.Ke, lc.nmask, lc.dinv, lc.dinvf, c->st);
+    }
+    for (int j = 1; j < c->L; ++j) CHK(estimate_omega(c, j));
+    if (c->L == 1) {
+        c->lv[0].omega = 1.0;
+    } else {
+        Level& lL = c->lv[c->L - 1];
+        const int64_t nL = lL.n;
+        HIPC(hipMemsetAsync(c->Ainv, 0, sizeof(double) * nL * nL, c->st));
+        launch_assemble_dense(dim, lL.g, lL.Ke, lL.nmask, nL, c->Ainv, c->st);
+        double *r0 = c->gj_r0, *c0 = c->gj_c0, *r1 = c->gj_r1, *c1 = c->gj_c1;
+        launch_gj_init(nL, c->Ainv, r0, c0, c->st);
+        for (int64_t k = 0; k < nL; ++k) {
+            launch_gj_step(nL, k, c->Ainv, r0, c0, r1, c1, c->st);
+            std::swap(r0, r1);
+            std::swap(c0, c1);
+        }
+    }
+    CHK(sync(c));
+    return MLB_OK;
+}
+
+// ---- coarse eigensolver: LOBPCG for the largest mu of (-G) psi = mu K psi
+// at level ell; X K-orthonormal on exit (columns eS[0..nb)).
+
+int upload_cm(mlb_ctx* c, double* dev, const std::vector<double>& cm) {
+    std::memcpy(c->hpin, cm.data(), sizeof(double) * cm.size());
+    HIPC(hipMemcpyAsync(dev, c->hpin, sizeof(double) * cm.size(), hipMemcpyHostToDevice, c->st));
+    CHK(sync(c));
+    return MLB_OK;
+}
+
+// Rayleigh-Ritz on span(S) from its Gram matrices GK = S^T K S and
+// GA = S^T A S (column-major, leading dimension ld, leading ncol x ncol
+// block used): scale to unit diagonal, K-orthonormalise through the
+// eigendecomposition of GK (directions with eigenvalue below 1e-12 of the
+// largest are dropped as linearly dependent), solve the projected symmetric
+// problem and return the top nb Ritz values and coefficients C (column-major
+// ncol x nb) so that S C is K-orthonormal.
+bool rayleigh_ritz_gram(int ncol, int ld, const std::vector<double>& GK, const std::vector<double>& GA, int nb,
+                        std::vector<double>& ev, std::vector<double>& C) {
+    std::vector<double> d(ncol);
+    for (int i = 0; i < ncol; ++i) {
+        const double g = GK[i + (size_t)ld * i];
+        d[i] = g > 0 ? 1.0 / std::sqrt(g) : 0.0;
+    }
+    std::vector<double> Ks((size_t)ncol * ncol), As((size_t)ncol * ncol);
+    for (int a = 0; a < ncol; ++a)
+        for (int q = 0; q < ncol; ++q) {
+            Ks[(size_t)a * ncol + q] = d[a] * d[q] * 0.5 * (GK[a + (size_t)ld * q] + GK[q + (size_t)ld * a]);
+            As[(size_t)a * ncol + q] = d[a] * d[q] * 0.5 * (GA[a + (size_t)ld * q] + GA[q + (size_t)ld * a]);
+        }
+    std::vector<double> w(ncol), V((size_t)ncol * ncol);
+    if (!sym_eig(ncol, Ks.data(), w.data(), V.data())) return false;
+    if (!(w[0] > 0)) return false;
+    int r = 0;
+    while (r < ncol && w[r] > 1e-12 * w[0]) ++r;
+    if (r < nb) return false;
+    // Bm = V_r diag(w_r^-1/2) (ncol x r); Ar = Bm^T As Bm
+    std::vector<double> Bm((size_t)ncol * r), T((size_t)ncol * r), Ar((size_t)r * r);
+    for (int a = 0; a < ncol; ++a)
+        for (int j = 0; j < r; ++j) Bm[(size_t)a * r + j] = V[(size_t)a * ncol + j] / std::sqrt(w[j]);
+    for (int a = 0; a < ncol; ++a)
+        for (int j = 0; j < r; ++j) {
+            double sacc = 0.0;
+            for (int b = 0; b < ncol; ++b) sacc += As[(size_t)a * ncol + b] * Bm[(size_t)b * r + j];
+            T[(size_t)a * r + j] = sacc;
+        }
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) {
+            double sacc = 0.0;
+            for (int a = 0; a < ncol; ++a) sacc += Bm[(size_t)a * r + i] * T[(size_t)a * r + j];
+            Ar[(size_t)i * r + j] = sacc;
+        }
+    std::vector<double> ew(r), Y((size_t)r * r);
+    if (!sym_eig(r, Ar.data(), ew.data(), Y.data())) return false;
+    ev.assign(ew.begin(), ew.begin() + nb);
+    C.assign((size_t)ncol * nb, 0.0);
+    for (int a = 0; a < ncol; ++a)
+        for (int q = 0; q < nb; ++q) {
+            double sacc = 0.0;
+            for (int j = 0; j < r; ++j) sacc += Bm[(size_t)a * r + j] * Y[(size_t)j * r + q];
+            C[a + (size_t)ncol * q] = d[a] * sacc;
+        }
+    return true;
+}
+
+// SVQB: given the Gram matrix G (r0 x r0, column-major) of a block V,
+// returns T (column-major r0 x r) with V T orthonormal in that inner product,
+// dropping directions whose Gram eigenvalue is below drop * largest.
+static int svqb(int r0, const std::vector<double>& G, double drop, std::vector<double>& T) {
+    std::vector<double> d(r0), Gs((size_t)r0 * r0), w(r0), V((size_t)r0 * r0);
+    for (int i = 0; i < r0; ++i) {
+        const double g = G[i + (size_t)r0 * i];
+        d[i] = g > 0 ? 1.0 / std::sqrt(g) : 0.0;
+    }
+    for (int a = 0; a < r0; ++a)
+        for (int q = 0; q < r0; ++q)
+            Gs[(size_t)a * r0 + q] = d[a] * d[q] * 0.5 * (G[a + (size_t)r0 * q] + G[q + (size_t)r0 * a]);
+    if (!sym_eig(r0, Gs.data(), w.data(), V.data()) || !(w[0] > 0)) return 0;
+    int r = 0;
+    while (r < r0 && w[r] > drop * w[0]) ++r;
+    T.assign((size_t)r0 * r, 0.0);
+    for (int a = 0; a < r0; ++a)
+        for (int j = 0; j < r; ++j) T[a + (size_t)r0 * j] = d[a] * V[(size_t)a * r0 + j] / std::sqrt(w[j]);
+    return r;
+}
+
+// LOBPCG for the largest mu of (-G) psi = mu K psi at level ell, in the
+// robust form: X K-orthonormal; W = T R orthogonalised twice against X (and
+// P) and orthonormalised by SVQB; P kept K-orthonormal; K X and -G X
+// recomputed explicitly every iteration.  On exit X = eS[0..nb) holds the
+// K-orthonormal Ritz vectors, mu the Ritz values (descending).
+int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double* gap, std::vector<double>& mu) {
+    const bool verbose = std::getenv("MLB_VERBOSE") != nullptr;
+    const int j = c->ell;
+    Level& l = c->lv[j - 1];
+    const int64_t n = l.n;
+    int guard = c->o.eig_guard > 0 ? c->o.eig_guard : std::max(4, k / 2);
+    int nb = std::min(k + guard, 24);
+    if (nb <= k) return fail(c, MLB_EINVAL, "k must be at most 23");
+    if (nb > n / 2) return fail(c, MLB_EINVAL, "eigen level too small for the requested modes");
+    CHK(ensure_level_cols(c, nb));
+    if (nb > c->eig_cap) {
+        const size_t s3 = (size_t)n * 3 * nb, s2 = (size_t)n * 2 * nb, s1 = (size_t)n * nb;
+        CHK(dalloc(c, &c->eS, s3));
+        CHK(dalloc(c, &c->eK, s3));
+        CHK(dalloc(c, &c->eA, s3));
+        CHK(dalloc(c, &c->eT, s2));
+        CHK(dalloc(c, &c->eTK, s2));
+        CHK(dalloc(c, &c->eTA, s2));
+        CHK(dalloc(c, &c->eR, s1));
+        CHK(dalloc(c, &c->eP, s1));
+        CHK(dalloc(c, &c->ePK, s1));
+        CHK(dalloc(c, &c->ePA, s1));
+        c->eig_cap = nb;
+    }
+    double *X = c->eS, *W = c->eS + n * nb;
+    double *KX = c->eK, *KW = c->eK + n * nb;
+    double *AX = c->eA, *AW = c->eA + n * nb;
+    auto applyKA = [&](int cols, const double* V, double* KV, double* AV) {
+        apply_K<double>(c, j, cols, V, KV, kModeY, nullptr, nullptr);
+        apply_G(c, j, cols, V, AV);
+        launch_axpby(n * cols, -1.0, AV, 0.0, AV, c->st);
+    };
+    // V -= B (KB^T V): K-orthogonalise V (cols cv) against a K-orthonormal B (cols cb)
+    auto orth_against = [&](double* V, int cv, const double* B, const double* KB, int cb) -> int {
+        std::vector<double> Cm;
+        CHK(gram(c, n, cb, KB, n, cv, V, n, Cm));
+        CHK(upload_cm(c, c->cbuf, Cm));
+        launch_gemm_small(n, cb, n, B, cv, c->cbuf, n, c->eT, c->st);
+        launch_axpby(n * cv, -1.0, c->eT, 1.0, V, c->st);
+        return MLB_OK;
+    };
+    // V <- V T with T from SVQB of V^T K V (directions below 1e-10 of the
+    // largest Gram eigenvalue dropped); K V and -G V are then recomputed
+    // explicitly so that they stay consistent with V to working precision.
+    auto orthonormalize = [&](double* V, double* KV, double* AV, int cv, int* rout) -> int {
+        std::vector<double> Gm, T;
+        CHK(gram(c, n, cv, V, n, cv, KV, n, Gm));
+        const int r = svqb(cv, Gm, 1e-10, T);
+        *rout = r;
+        if (r == 0) return MLB_OK;
+        CHK(upload_cm(c, c->cbuf, T));
+        launch_gemm_small(n, cv, n, V, r, c->cbuf, n, c->eT, c->st);
+        launch_copy_cols(n, r, n, c->eT, n, V, c->st);
+        applyKA(r, V, KV, AV);
+        return MLB_OK;
+    };
+
+    // start block: warm-start columns first, seeded random for the rest
+    launch_random_fill(n, nb, n, c->o.seed, l.nmask, c->dim, X, c->st);
+    if (c->warm_coarse_cols > 0 && (int64_t)c->warm_coarse.size() == n * c->warm_coarse_cols) {
+        const int wc = std::min(c->warm_coarse_cols, nb);
+        HIPC(hipMemcpyAsync(X, c->warm_coarse.data(), sizeof(double) * n * wc, hipMemcpyHostToDevice, c->st));
+        CHK(sync(c));
+    }
+    applyKA(nb, X, KX, AX);
+    std::vector<double> GK, GA, ev, C;
+    {
+        CHK(gram(c, n, nb, X, n, nb, KX, n, GK));
+        CHK(gram(c, n, nb, X, n, nb, AX, n, GA));
+        if (!rayleigh_ritz_gram(nb, nb, GK, GA, nb, ev, C))
+            return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: start block is rank deficient");
+        CHK(upload_cm(c, c->cbuf, C));
+        launch_gemm_small(n, nb, n, X, nb, c->cbuf, n, c->eT, c->st);
+        launch_copy_cols(n, nb, n, c->eT, n, X, c->st);
+        applyKA(nb, X, KX, AX);
+        mu.assign(ev.begin(), ev.begin() + nb);
+    }
+    int rp = 0;   // columns of P (K-orthonormal)
+    int it = 0;
+    bool stalled = false;
+    std::vector<double> hist;
+    double wres = 1e300;
+    std::vector<double> rn(nb), kn(nb);
+    const int max_it = c->o.eig_max_it > 0 ? c->o.eig_max_it : 400;
+    for (it = 0; it <= max_it; ++it) {
+        std::memcpy(c->hpin, mu.data(), sizeof(double) * nb);
+        HIPC(hipMemcpyAsync(sc(c, 11), c->hpin, sizeof(double) * nb, hipMemcpyHostToDevice, c->st));
+        launch_residual_block(n, nb, n, AX, KX, sc(c, 11), c->eR, c->st);
+        dots(c, n, nb, c->eR, c->eR, sc(c, 12));
+        dots(c, n, nb, KX, KX, sc(c, 13));
+        CHK(read_scal(c, sc(c, 12), nb, rn.data()));
+        CHK(read_scal(c, sc(c, 13), nb, kn.data()));
+        wres = 0.0;
+        for (int i = 0; i < k; ++i) {
+            const double den = std::fabs(mu[i]) * std::sqrt(kn[i]);
+            wres = std::max(wres, den > 0 ? std::sqrt(rn[i]) / den : 1e300);
+        }
+        if (!std::isfinite(wres)) return fail(c, MLB_EBREAKDOWN, "coarse eigensolver residual not finite");
+        if (verbose) std::fprintf(stderr, "[mlb] lobpcg it %d worst %.3e rp %d mu0 %.12g muk %.12g\n", it, wres, rp,
+                                  mu[0], mu[k - 1]);
+        if (wres <= tol || it == max_it) break;
+        // Precision floor: the residual of the k-th pair cannot fall below
+        // about eps * ||K^-1 G|| / mu_k, and ||K^-1 G|| includes the (possibly
+        // huge) negative part of the spectrum.  Accept a residual that has
+        // stopped improving for 15 iterations once it is below sqrt(tol).
+        hist.push_back(wres);
+        if ((int)hist.size() > 15) {
+            const double best_old = *std::min_element(hist.begin(), hist.end() - 15);
+            const double best_new = *std::min_element(hist.end() - 15, hist.end());
+            if (best_new > 0.5 * best_old && best_new <= std::sqrt(tol)) {
+                stalled = true;
+                break;
+            }
+        }
+        if (it >= 30 && !(mu[k - 1] > 0.0))
+            return fail(c, MLB_ENOPOS, "fewer than k positive buckling factors at the coarse level");
+        // W = T R, orthogonalised against X and P (twice), then K-orthonormalised
+        precondition(c, j, nb, c->eR, W);
+        for (int pass = 0; pass < 2; ++pass) {
+            CHK(orth_against(W, nb, X, KX, nb));
+            if (rp > 0) CHK(orth_against(W, nb, c->eP, c->ePK, rp));
+        }
+        apply_K<double>(c, j, nb, W, KW, kModeY, nullptr, nullptr);
+        int rw = 0;
+        CHK(orthonormalize(W, KW, AW, nb, &rw));
+        if (rw == 0) {   // nothing new to add: converged to working precision
+            stalled = true;
+            break;
+        }
+        // S = [X | W (rw) | P (rp)]
+        const int off = nb + rw;
+        if (rp > 0) {
+            launch_copy_cols(n, rp, n, c->eP, n, c->eS + n * off, c->st);
+            launch_copy_cols(n, rp, n, c->ePK, n, c->eK + n * off, c->st);
+            launch_copy_cols(n, rp, n, c->ePA, n, c->eA + n * off, c->st);
+        }
+        int ncol = off + rp;
+        CHK(gram(c, n, ncol, c->eS, n, ncol, c->eK, n, GK));
+        CHK(gram(c, n, ncol, c->eS, n, ncol, c->eA, n, GA));
+        if (!rayleigh_ritz_gram(ncol, ncol, GK, GA, nb, ev, C)) {
+            if (rp > 0 && rayleigh_ritz_gram(off, ncol, GK, GA, nb, ev, C)) {
+                if (verbose) std::fprintf(stderr, "[mlb] lobpcg it %d: dropped P\n", it);
+                ncol = off;
+            } else {
+                return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: search space collapsed");
+            }
+        }
+        // P_new = [W P] C[nb:ncol, :], then X_new = S C
+        std::vector<double> Cp((size_t)(ncol - nb) * nb);
+        for (int a = nb; a < ncol; ++a)
+            for (int q = 0; q < nb; ++q) Cp[(a - nb) + (size_t)(ncol - nb) * q] = C[a + (size_t)ncol * q];
+        CHK(upload_cm(c, c->cbuf2, Cp));
+        launch_gemm_small(n, ncol - nb, n, W, nb, c->cbuf2, n, c->eP, c->st);
+        launch_gemm_small(n, ncol - nb, n, KW, nb, c->cbuf2, n, c->ePK, c->st);
+        launch_gemm_small(n, ncol - nb, n, AW, nb, c->cbuf2, n, c->ePA, c->st);
+        CHK(upload_cm(c, c->cbuf, C));
+        launch_gemm_small(n, ncol, n, c->eS, nb, c->cbuf, n, c->eT, c->st);
+        launch_copy_cols(n, nb, n, c->eT, n, X, c->st);
+        applyKA(nb, X, KX, AX);
+        // keep P K-orthonormal (and K-orthogonal to the new X)
+        CHK(orth_against(c->eP, nb, X, KX, nb));
+        apply_K<double>(c, j, nb, c->eP, c->ePK, kModeY, nullptr, nullptr);
+        CHK(orthonormalize(c->eP, c->ePK, c->ePA, nb, &rp));
+        mu.assign(ev.begin(), ev.begin() + nb);
+    }
+    *iters = it;
+    *worst = wres;
+    *gap = mu[k - 1] > 0 ? (mu[k - 1] - mu[k]) / mu[k - 1] : 0.0;
+    if (wres > tol && !stalled)
+        return fail(c, MLB_ENOTCONV, "coarse eigensolver stalled at relative residual " + std::to_string(wres) +
+                                         " after " + std::to_string(it) + " iterations");
+    if (!(mu[k - 1] > 0.0)) return fail(c, MLB_ENOPOS, "fewer than k positive buckling factors at the coarse level");
+    return MLB_OK;
+}
+
+// G element matrices at the eigen level from the reference stresses.
+int build_G_levels(mlb_ctx* c) {
+    if (c->ell == 1) return MLB_OK;
+    const int dim = c->dim, nn2 = c->nn * c->nn;
+    double* prev = nullptr;
+    double* cur = nullptr;
+    for (int j = 2; j <= c->ell; ++j) {
+        Level& lf = c->lv[j - 2];
+        Level& lc = c->lv[j - 1];
+        double* out = (j == c->ell) ? c->Gl : nullptr;
+        if (!out) {
+            out = nullptr;
+            CHK(dalloc(c, &out, (size_t)lc.g.m * nn2));
+        }
+        if (j == 2) launch_galerkin_G_from_S(dim, lf.g, lc.g, c->S, c->dGHc, out, c->st);
+        else launch_galerkin_dense(dim, true, lf.g, lc.g, prev, c->dT, out, c->st);
+        if (prev) {
+            CHK(sync(c));
+            dfree(prev);
+        }
+        prev = (j == c->ell) ? nullptr : out;
+        cur = out;
+    }
+    (void)cur;
+    CHK(sync(c));
+    return MLB_OK;
+}
+
+int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* info) {
+    if (!c->has_static) return fail(c, MLB_ESTATE, "mlb_buckling needs a converged static solve first");
+    if (ref_case < 0 || ref_case >= c->ncases) return fail(c, MLB_EINVAL, "ref_case out of range");
+    if (k < 1) return fail(c, MLB_EINVAL, "k must be positive");
+    if (!(tol_eig > 0)) tol_eig = 1e-10;
+    const double t0 = now_s();
+    const int64_t n = c->n;
+    c->has_buck = false;
+    launch_stress(c->dim, c->lv[0].g, c->Es, c->U + (int64_t)ref_case * n, c->dD0Bc, c->S, c->st);
+    c->has_stress = true;
+    c->ref_case_used = ref_case;
+    CHK(build_G_levels(c));
+    int cit = 0;
+    double cres = 0, gap = 0;
+    std::vector<double> mu;
+    CHK(coarse_eigs(c, k, tol_eig, &cit, &cres, &gap, mu));
+    const double t1 = now_s();
+    // step 2: interpolate the coarse modes to the fine grid
+    CHK(ensure_cg(c, std::max(k, c->ncases)));
+    if ((int)c->k != k) {
+        CHK(dalloc(c, &c->Phi, (size_t)n * k));
+        CHK(dalloc(c, &c->Zadj, (size_t)n * k));
+        CHK(dalloc(c, &c->dlam_l, (size_t)k));
+        c->k = k;
+    }
+    const double* cur = c->eS;
+    int64_t ldc = c->lv[c->ell - 1].n;
+    for (int j = c->ell - 1; j >= 1; --j) {
+        Level& lf = c->lv[j - 1];
+        Level& lc = c->lv[j];
+        double* dst = j == 1 ? c->X1 : lf.vt;
+        launch_prolong<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, k, lf.n, ldc, cur, dst, false, c->st);
+        cur = dst;
+        ldc = lf.n;
+    }
+    if (c->ell == 1) launch_copy_cols(n, k, n, c->eS, n, c->X1, c->st);
+    // step 3: K Phi~ = G Psi
+    apply_G(c, 1, k, c->X1, c->X2);
+    mlb_solve_info si{};
+    CHK(pcg(c, c->X2, c->Phi, k, c->tol_solve, c->max_it, false, &si));
+    const double t2 = now_s();
+    // step 4: Rayleigh-Ritz on span(Phi~)
+    apply_K<double>(c, 1, k, c->Phi, c->X1, kModeY, nullptr, nullptr);
+    apply_G(c, 1, k, c->Phi, c->X2);
+    std::vector<double> A, B;
+    CHK(gram(c, n, k, c->Phi, n, k, c->X1, n, A));
+    CHK(gram(c, n, k, c->Phi, n, k, c->X2, n, B));
+    std::vector<double> A2(k * k), B2(k * k), ev(k), Y(k * k);
+    for (int a = 0; a < k; ++a)
+        for (int q = 0; q < k; ++q) {
+            A2[a * k + q] = 0.5 * (A[a + k * q] + A[q + k * a]);
+            B2[a * k + q] = -0.5 * (B[a + k * q] + B[q + k * a]);
+        }
+    if (!gen_eig(k, A2.data(), B2.data(), ev.data(), Y.data()))
+        return fail(c, MLB_EBREAKDOWN, "Rayleigh-Ritz: Phi~^T K Phi~ not positive definite");
+    if (!(ev[k - 1] > 0.0)) return fail(c, MLB_ENOPOS, "fewer than k positive Ritz values");
+    c->lam.assign(k, 0.0);
+    for (int i = 0; i < k; ++i) c->lam[i] = 1.0 / ev[i];
+    std::vector<double> C(k * k);
+    for (int a = 0; a < k; ++a)
+        for (int q = 0; q < k; ++q) C[a + k * q] = Y[a * k + q];
+    CHK(upload_cm(c, c->cbuf, C));
+    launch_gemm_small(n, k, n, c->Phi, k, c->cbuf, n, c->Zo, c->st);
+    launch_gemm_small(n, k, n, c->X1, k, c->cbuf, n, c->R, c->st);
+    launch_gemm_small(n, k, n, c->X2, k, c->cbuf, n, c->Qb, c->st);
+    std::memcpy(c->hpin, c->lam.data(), sizeof(double) * k);
+    HIPC(hipMemcpyAsync(c->dlam_l, c->hpin, sizeof(double) * k, hipMemcpyHostToDevice, c->st));
+    launch_axpy_cols(n, k, n, c->dlam_l, 1.0, c->Qb, c->R, c->st);   // (K + lam G) phi
+    const int np = reduction_parts(n);
+    CHK(ensure_part(c, (int64_t)np * k));
+    launch_infnorm_part(n, k, n, c->R, np, c->part, c->st);
+    launch_max_parts(k, np, c->part, sc(c, 14), c->st);
+    c->eigres.assign(k, 0.0);
+    CHK(read_scal(c, sc(c, 14), k, c->eigres.data()));
+    // sign convention: largest-magnitude entry positive (ties: lowest index)
+    launch_copy_cols(n, k, n, c->Zo, n, c->Phi, c->st);
+    launch_absmax_part(n, k, n, c->Phi, np, c->part, c->pidx, c->st);
+    launch_absmax_sum(k, np, c->part, c->pidx, sc(c, 15), c->st);
+    std::vector<double> sv(k);
+    CHK(read_scal(c, sc(c, 15), k, sv.data()));
+    for (int i = 0; i < k; ++i) sv[i] = sv[i] < 0 ? -1.0 : 1.0;
+    std::memcpy(c->hpin, sv.data(), sizeof(double) * k);
+    HIPC(hipMemcpyAsync(sc(c, 15), c->hpin, sizeof(double) * k, hipMemcpyHostToDevice, c->st));
+    launch_scale_cols(n, k, n, sc(c, 15), c->Phi, c->st);
+    CHK(sync(c));
+    const double t3 = now_s();
+    c->has_buck = true;
+    if (info) {
+        info->coarse_iterations = cit;
+        info->coarse_residual = cres;
+        info->coarse_gap = gap;
+        info->fine_iterations = si.iterations;
+        info->fine_true_residual = si.true_rel_residual;
+        info->seconds_coarse = t1 - t0;
+        info->seconds_fine = t2 - t1;
+        info->seconds_ritz = t3 - t2;
+    }
+    return MLB_OK;
+}
+
+int do_sens(mlb_ctx* c, double* dJ_dev, double* dlam_dev, mlb_solve_info* info) {
+    const double t0 = now_s();
+    const Geo& g = c->lv[0].g;
+    if (dJ_dev) {
+        if (!c->has_static) return fail(c, MLB_ESTATE, "compliance sensitivities need a static solve");
+        launch_dJ(c->dim, g, c->x, c->d.penal, c->d.E1 - c->d.E0, c->ncases, c->n, c->U, c->dK0, dJ_dev, c->st);
+    }
+    if (info) *info = mlb_solve_info{};
+    if (dlam_dev) {
+        if (!c->has_buck) return fail(c, MLB_ESTATE, "buckling sensitivities need mlb_buckling first");
+        const int k = c->k;
+        double* V = nullptr;
+        CHK(dalloc(c, &V, (size_t)g.m * c->nv * k));
+        launch_adj_elem(c->dim, g, c->Es, k, c->n, c->Phi, c->dHk, c->dD0, V, c->st);
+        launch_adj_gather(c->dim, g, k, V, c->dBc, c->lv[0].nmask, c->n, c->X2, c->st);
+        CHK(sync(c));
+        dfree(V);
+        CHK(pcg(c, c->X2, c->Zadj, k, c->tol_solve, c->max_it, false, info));
+        launch_dlam(c->dim, g, c->x, c->d.penal, c->d.E1, c->d.E0, c->U + (int64_t)c->ref_case_used * c->n, k,
+                    c->n, c->Phi, c->Zadj, c->dlam_l, c->dK0, c->dHk, c->dD0Bc, dlam_dev, c->st);
+    }
+    CHK(sync(c));
+    if (info) info->seconds = now_s() - t0;
+    return MLB_OK;
+}
+
+hipStream_t pick(mlb_ctx* c, void* stream) { return stream ? (hipStream_t)stream : c->own; }
+
+}  // namespace
+
+// ============================ C ABI ======================================
+
+extern "C" {
+
+int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
+    if (!desc || !out) return MLB_EINVAL;
+    *out = nullptr;
+    mlb_ctx* c = new mlb_ctx();
+    c->d = *desc;
+    c->o.smooth_steps = 2;
+    c->o.jacobi_omega = 4.0 / 3.0;
+    c->o.eig_guard = 0;
+    c->o.eig_max_it = 400;
+    c->o.check_every = 1;
+    c->o.seed = 1;
+    const int dim = desc->dim;
+    auto bad = [&](const std::string& m) {
+        c->err = m;
+        *out = c;   // returned so mlb_last_error works; caller must destroy
+        return MLB_EINVAL;
+    };
+    if (dim != 2 && dim != 3) return bad("dim must be 2 or 3");
+    if (desc->mg_levels < 1 || desc->mg_levels > 12) return bad("mg_levels must be in 1..12");
+    if (desc->eig_level < 1 || desc->eig_level > desc->mg_levels) return bad("eig_level must be in 1..mg_levels");
+    if (desc->precision != MLB_FP64 && desc->precision != MLB_MIXED) return bad("unknown precision");
+    if (!(desc->E1 > 0) || !(desc->E0 >= 0) || !(desc->E0 < desc->E1)) return bad("need 0 <= E0 < E1");
+    if (!(desc->nu > -1.0 && desc->nu < 0.5)) return bad("Poisson ratio must lie in (-1, 0.5)");
+    if (!(desc->penal >= 1.0)) return bad("penalty p must be >= 1");
+    const int div = 1 << (desc->mg_levels - 1);
+    for (int a = 0; a < dim; ++a)
+        if (desc->nel[a] < div || desc->nel[a] % div)
+            return bad("every nel must be a positive multiple of 2^(mg_levels-1)");
+    c->dim = dim;
+    c->nn = 1 << dim;
+    c->nde = dim << dim;
+    c->nv = dim == 2 ? 3 : 6;
+    c->L = desc->mg_levels;
+    c->ell = desc->eig_level;
+    if (hipSetDevice(desc->device) != hipSuccess) {
+        c->err = "hipSetDevice failed";
+        *out = c;
+        return MLB_EDEVICE;
+    }
+    *out = c;
+    HIPC(hipStreamCreate(&c->own));
+    c->st = c->own;
+    build_tables(dim, desc->nu, &c->tab);
+    // device tables
+    CHK(dalloc(c, &c->dK0, 576));
+    CHK(dalloc(c, &c->fK0, 576));
+    CHK(dalloc(c, &c->dHk, 6 * 64));
+    CHK(dalloc(c, &c->dBc, 6 * 24));
+    CHK(dalloc(c, &c->dD0Bc, 6 * 24));
+    CHK(dalloc(c, &c->dD0, 36));
+    CHK(dalloc(c, &c->dT, 512));
+    CHK(dalloc(c, &c->dMc, 8 * 576));
+    CHK(dalloc(c, &c->dGHc, 8 * 6 * 64));
+    float k0f[576];
+    for (int i = 0; i < 576; ++i) k0f[i] = (float)c->tab.K0[i];
+    HIPC(hipMemcpy(c->dK0, c->tab.K0, sizeof(double) * 576, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(c->fK0, k0f, sizeof(float) * 576, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(c->dHk, c->tab.Hk, sizeof(double) * 6 * 64, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(c->dBc, c->tab.Bc, sizeof(double) * 6 * 24, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(c->dD0Bc, c->tab.D0Bc, sizeof(double) * 6 * 24, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(c->dD0, c->tab.D0, sizeof(double) * 36, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(c->dT, c->tab.T, sizeof(double) * 512, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(c->dMc, c->tab.Mc, sizeof(double) * 8 * 576, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(c->dGHc, c->tab.GHc, sizeof(double) * 8 * 6 * 64, hipMemcpyHostToDevice));
+    // levels
+    c->lv.resize(c->L);
+    int nel[3] = {desc->nel[0], desc->nel[1], dim == 3 ? desc->nel[2] : 1};
+    for (int j = 0; j < c->L; ++j) {
+        Level& l = c->lv[j];
+        int ne[3] = {nel[0] >> j, nel[1] >> j, dim == 3 ? nel[2] >> j : 1};
+        l.g = make_geo(dim, ne);
+        l.n = (int64_t)dim * l.g.nodes;
+        CHK(dalloc(c, &l.nmask, (size_t)l.g.nodes));
+        HIPC(hipMemset(l.nmask, 0, (size_t)l.g.nodes));
+        CHK(dalloc(c, &l.dinv, (size_t)l.n));
+        CHK(dalloc(c, &l.dinvf, (size_t)l.n));
+        if (j > 0) {
+            CHK(dalloc(c, &l.Ke, (size_t)l.g.m * c->nde * c->nde));
+            CHK(dalloc(c, &l.Kef, (size_t)l.g.m * c->nde * c->nde));
+        }
+    }
+    c->n = c->lv[0].n;
+    c->m = c->lv[0].g.m;
+    if (c->L > 1) {
+        const int64_t nL = c->lv[c->L - 1].n;
+        if (nL > 8192) {
+            c->err = "coarsest level has " + std::to_string(nL) + " DOFs (> 8192): use more multigrid levels";
+            return MLB_EINVAL;
+        }
+        CHK(dalloc(c, &c->Ainv, (size_t)nL * nL));
+        CHK(dalloc(c, &c->gj_r0, (size_t)nL));
+        CHK(dalloc(c, &c->gj_c0, (size_t)nL));
+        CHK(dalloc(c, &c->gj_r1, (size_t)nL));
+        CHK(dalloc(c, &c->gj_c1, (size_t)nL));
+    }
+    if (c->ell > 1) CHK(dalloc(c, &c->Gl, (size_t)c->lv[c->ell - 1].g.m * c->nn * c->nn));
+    CHK(dalloc(c, &c->x, (size_t)c->m));
+    CHK(dalloc(c, &c->Ek, (size_t)c->m));
+    CHK(dalloc(c, &c->Ekf, (size_t)c->m));
+    CHK(dalloc(c, &c->Es, (size_t)c->m));
+    CHK(dalloc(c, &c->S, (size_t)c->m * c->nv));
+    CHK(dalloc(c, &c->fixed, (size_t)c->n));
+    CHK(dalloc(c, &c->scal, (size_t)16 * kScal));
+    CHK(dalloc(c, &c->iscal, (size_t)2 * kScal));
+    CHK(dalloc(c, &c->gbuf, (size_t)96 * 96));
+    CHK(dalloc(c, &c->cbuf, (size_t)96 * 96));
+    CHK(dalloc(c, &c->cbuf2, (size_t)96 * 96));
+    HIPC(hipHostMalloc((void**)&c->hpin, sizeof(double) * 96 * 96, hipHostMallocDefault));
+    CHK(ensure_part(c, 4096));
+    CHK(ensure_level_cols(c, 1));
+    return MLB_OK;
+}
+
+void mlb_destroy(mlb_ctx* c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    for (auto& l : c->lv) {
+        dfree(l.nmask); dfree(l.Ke); dfree(l.Kef); dfree(l.dinv); dfree(l.dinvf);
+        dfree(l.vr); dfree(l.vz); dfree(l.vz2); dfree(l.vt); dfree(l.fr); dfree(l.fz); dfree(l.fz2); dfree(l.ft);
+    }
+    dfree(c->dK0); dfree(c->fK0); dfree(c->dHk); dfree(c->dBc); dfree(c->dD0Bc); dfree(c->dD0); dfree(c->dT);
+    dfree(c->dMc); dfree(c->dGHc); dfree(c->x); dfree(c->Ek); dfree(c->Ekf); dfree(c->Es); dfree(c->fixed);
+    dfree(c->F); dfree(c->U); dfree(c->S); dfree(c->Gl); dfree(c->Ainv); dfree(c->gj_r0); dfree(c->gj_c0);
+    dfree(c->gj_r1); dfree(c->gj_c1); dfree(c->R); dfree(c->Zb); dfree(c->Pb); dfree(c->Qb); dfree(c->Zo);
+    dfree(c->X1); dfree(c->X2); dfree(c->Phi); dfree(c->Zadj); dfree(c->dlam_l); dfree(c->eS); dfree(c->eK);
+    dfree(c->eA); dfree(c->eT); dfree(c->eTK); dfree(c->eTA); dfree(c->eR); dfree(c->eP); dfree(c->ePK); dfree(c->ePA); dfree(c->part); dfree(c->pidx);
+    dfree(c->scal); dfree(c->iscal); dfree(c->gbuf); dfree(c->cbuf); dfree(c->cbuf2);
+    if (c->hpin) (void)hipHostFree(c->hpin);
+    if (c->own) (void)hipStreamDestroy(c->own);
+    delete c;
+}
+
+const char* mlb_last_error(const mlb_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int mlb_set_opts(mlb_ctx* c, const mlb_opts* o) {
+    if (!c || !o) return MLB_EINVAL;
+    if (o->smooth_steps > 0) c->o.smooth_steps = o->smooth_steps;
+    if (o->jacobi_omega > 0) c->o.jacobi_omega = o->jacobi_omega;
+    if (o->eig_guard > 0) c->o.eig_guard = o->eig_guard;
+    if (o->eig_max_it > 0) c->o.eig_max_it = o->eig_max_it;
+    if (o->check_every > 0) c->o.check_every = o->check_every;
+    if (o->seed > 0) c->o.seed = o->seed;
+    if (o->jacobi_omega > 0 && c->has_density) {
+        c->st = c->own;
+        for (int j = 1; j < c->L; ++j) CHK(estimate_omega(c, j));
+    }
+    return MLB_OK;
+}
+
+int mlb_level_size(const mlb_ctx* c, int level, int64_t* n_dofs, int64_t* n_elems) {
+    if (!c || level < 1 || level > c->L) return MLB_EINVAL;
+    if (n_dofs) *n_dofs = c->lv[level - 1].n;
+    if (n_elems) *n_elems = c->lv[level - 1].g.m;
+    return MLB_OK;
+}
+
+static int set_bc_common(mlb_ctx* c) {
+    // host check of nestedness + coarse masks, then node masks on device
+    const int dim = c->dim;
+    std::vector<uint8_t> mf(c->lv[0].g.nodes, 0);
+    for (int64_t nd = 0; nd < c->lv[0].g.nodes; ++nd)
+        for (int cc = 0; cc < dim; ++cc)
+            if (c->fixed_host[nd * dim + cc]) mf[nd] |= (uint8_t)(1u << cc);
+    HIPC(hipMemcpyAsync(c->lv[0].nmask, mf.data(), mf.size(), hipMemcpyHostToDevice, c->st));
+    CHK(sync(c));
+    for (int j = 1; j < c->L; ++j) {
+        const Geo& gf = c->lv[j - 1].g;
+        const Geo& gc = c->lv[j].g;
+        std::vector<uint8_t> mc(gc.nodes, 0);
+        for (int64_t N = 0; N < gc.nodes; ++N) {
+            const int I = (int)(N % gc.nnx), J = (int)((N / gc.nnx) % gc.nny), K = (int)(N / ((int64_t)gc.nnx * gc.nny));
+            mc[N] = mf[2 * I + (int64_t)gf.nnx * (2 * J + (int64_t)gf.nny * 2 * K)];
+        }
+        // every fixed fine DOF must interpolate only from fixed coarse DOFs
+        for (int64_t nd = 0; nd < gf.nodes; ++nd) {
+            if (!mf[nd]) continue;
+            const int i = (int)(nd % gf.nnx), jj = (int)((nd / gf.nnx) % gf.nny), k = (int)(nd / ((int64_t)gf.nnx * gf.nny));
+            const int ni = (i & 1) ? 2 : 1, nj = (jj & 1) ? 2 : 1, nk = (dim == 3 && (k & 1)) ? 2 : 1;
+            for (int dk = 0; dk < nk; ++dk)
+                for (int dj = 0; dj < nj; ++dj)
+                    for (int di = 0; di < ni; ++di) {
+                        const int64_t cn = (i / 2 + di) + (int64_t)gc.nnx * ((jj / 2 + dj) + (int64_t)gc.nny * (k / 2 + dk));
+                        if ((mf[nd] & ~mc[cn]) != 0)
+                            return fail(c, MLB_EINVAL, "fixed DOF set is not nested across multigrid levels");
+                    }
+        }
+        HIPC(hipMemcpyAsync(c->lv[j].nmask, mc.data(), mc.size(), hipMemcpyHostToDevice, c->st));
+        CHK(sync(c));
+        mf.swap(mc);
+    }
+    HIPC(hipMemcpyAsync(c->fixed, c->fixed_host.data(), (size_t)c->n, hipMemcpyHostToDevice, c->st));
+    CHK(sync(c));
+    c->has_bc = true;
+    c->has_static = c->has_buck = c->has_stress = false;
+    if (c->has_density) CHK(build_hierarchy(c));
+    return MLB_OK;
+}
+
+int mlb_set_bc(mlb_ctx* c, const uint8_t* fixed) {
+    if (!c || !fixed) return MLB_EINVAL;
+    c->st = c->own;
+    c->fixed_host.assign(fixed, fixed + c->n);
+    for (auto& v : c->fixed_host) v = v ? 1 : 0;
+    return set_bc_common(c);
+}
+
+int mlb_set_bc_dev(mlb_ctx* c, const uint8_t* fixed, void* stream) {
+    if (!c || !fixed) return MLB_EINVAL;
+    c->st = pick(c, stream);
+    c->fixed_host.assign(c->n, 0);
+    HIPC(hipMemcpyAsync(c->fixed_host.data(), fixed, (size_t)c->n, hipMemcpyDeviceToHost, c->st));
+    CHK(sync(c));
+    for (auto& v : c->fixed_host) v = v ? 1 : 0;
+    return set_bc_common(c);
+}
+
+static int set_loads_common(mlb_ctx* c, int ncases) {
+    c->ncases = ncases;
+    c->J.assign(ncases, 0.0);
+    c->has_static = c->has_buck = false;
+    CHK(ensure_cg(c, std::max(ncases, c->k)));
+    return MLB_OK;
+}
+
+int mlb_set_loads(mlb_ctx* c, int ncases, const double* F) {
+    if (!c || !F || ncases < 1 || ncases > 64) return fail(c, MLB_EINVAL, "need 1..64 load cases");
+    if (!c->has_bc) return fail(c, MLB_ESTATE, "set the Dirichlet mask before the loads");
+    c->st = c->own;
+    std::vector<double> h(F, F + (size_t)c->n * ncases);
+    for (int cc = 0; cc < ncases; ++cc)
+        for (int64_t i = 0; i < c->n; ++i) {
+            double& v = h[(size_t)cc * c->n + i];
+            if (!std::isfinite(v)) return fail(c, MLB_EINVAL, "non-finite load entry");
+            if (c->fixed_host[i]) v = 0.0;
+        }
+    CHK(dalloc(c, &c->F, h.size()));
+    CHK(dalloc(c, &c->U, h.size()));
+    HIPC(hipMemcpy(c->F, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+    return set_loads_common(c, ncases);
+}
+
+int mlb_set_loads_dev(mlb_ctx* c, int ncases, const double* F, void* stream) {
+    if (!c || !F || ncases < 1 || ncases > 64) return fail(c, MLB_EINVAL, "need 1..64 load cases");
+    if (!c->has_bc) return fail(c, MLB_ESTATE, "set the Dirichlet mask before the loads");
+    c->st = pick(c, stream);
+    std::vector<double> h((size_t)c->n * ncases);
+    HIPC(hipMemcpyAsync(h.data(), F, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->st));
+    CHK(sync(c));
+    c->st = c->own;
+    return mlb_set_loads(c, ncases, h.data());
+}
+
+static int set_density_common(mlb_ctx* c) {
+    const int np = reduction_parts(c->m);
+    CHK(ensure_part(c, np));
+    launch_material(c->m, c->x, c->d.E1, c->d.E0, c->d.penal, c->Ek, c->Ekf, c->Es, np, c->part, c->st);
+    launch_sum_parts(1, np, c->part, sc(c, 0), c->st);
+    double nbad = 0;
+    CHK(read_scal(c, sc(c, 0), 1, &nbad));
+    if (nbad > 0) {
+        c->has_density = false;
+        return fail(c, MLB_EINVAL, "densities must be finite and lie in [0, 1]");
+    }
+    c->has_static = c->has_buck = c->has_stress = false;
+    c->has_density = true;
+    if (!c->has_bc) return MLB_OK;   // the hierarchy is built when the mask arrives
+    return build_hierarchy(c);
+}
+
+int mlb_set_density(mlb_ctx* c, const double* x) {
+    if (!c || !x) return MLB_EINVAL;
+    c->st = c->own;
+    if (c->d.E0 == 0.0)
+        for (int64_t e = 0; e < c->m; ++e)
+            if (!(x[e] > 0.0)) return fail(c, MLB_EINVAL, "with E0 = 0 every density must be positive");
+    HIPC(hipMemcpy(c->x, x, sizeof(double) * c->m, hipMemcpyHostToDevice));
+    return set_density_common(c);
+}
+
+int mlb_set_density_dev(mlb_ctx* c, const double* x, void* stream) {
+    if (!c || !x) return MLB_EINVAL;
+    c->st = pick(c, stream);
+    HIPC(hipMemcpyAsync(c->x, x, sizeof(double) * c->m, hipMemcpyDeviceToDevice, c->st));
+    return set_density_common(c);
+}
+
+static int solve_static_common(mlb_ctx* c, double tol, int max_it, mlb_solve_info* info) {
+    if (!c->has_bc || !c->has_density) return fail(c, MLB_ESTATE, "set the mask and the densities first");
+    if (c->ncases < 1 || !c->F) return fail(c, MLB_ESTATE, "set the loads first");
+    if (!(tol > 0) || max_it < 1) return fail(c, MLB_EINVAL, "need tol > 0 and max_it >= 1");
+    c->tol_solve = tol;
+    c->max_it = max_it;
+    c->has_static = c->has_buck = false;
+    bool x0 = false;
+    if ((int64_t)c->warm_static.size() == c->n * c->ncases) {
+        HIPC(hipMemcpyAsync(c->U, c->warm_static.data(), sizeof(double) * c->n * c->ncases, hipMemcpyHostToDevice, c->st));
+        x0 = true;
+    }
+    CHK(pcg(c, c->F, c->U, c->ncases, tol, max_it, x0, info));
+    dots(c, c->n, c->ncases, c->F, c->U, sc(c, 0));
+    CHK(read_scal(c, sc(c, 0), c->ncases, c->J.data()));
+    c->has_static = true;
+    return MLB_OK;
+}
+
+int mlb_solve_static(mlb_ctx* c, double tol, int max_it, double* U, double* J, mlb_solve_info* info) {
+    if (!c) return MLB_EINVAL;
+    c->st = c->own;
+    CHK(solve_static_common(c, tol, max_it, info));
+    if (U) HIPC(hipMemcpy(U, c->U, sizeof(double) * c->n * c->ncases, hipMemcpyDeviceToHost));
+    if (J) std::memcpy(J, c->J.data(), sizeof(double) * c->ncases);
+    return MLB_OK;
+}
+
+int mlb_solve_static_dev(mlb_ctx* c, double tol, int max_it, double* U, double* J_host, mlb_solve_info* info,
+                         void* stream) {
+    if (!c) return MLB_EINVAL;
+    c->st = pick(c, stream);
+    CHK(solve_static_common(c, tol, max_it, info));
+    if (U) HIPC(hipMemcpyAsync(U, c->U, sizeof(double) * c->n * c->ncases, hipMemcpyDeviceToDevice, c->st));
+    if (J_host) std::memcpy(J_host, c->J.data(), sizeof(double) * c->ncases);
+    CHK(sync(c));
+    return MLB_OK;
+}
+
+int mlb_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, double* lambda, double* Phi, mlb_eig_info* info) {
+    if (!c) return MLB_EINVAL;
+    c->st = c->own;
+    CHK(do_buckling(c, ref_case, k, tol_eig, info));
+    if (lambda) std::memcpy(lambda, c->lam.data(), sizeof(double) * k);
+    if (Phi) HIPC(hipMemcpy(Phi, c->Phi, sizeof(double) * c->n * k, hipMemcpyDeviceToHost));
+    return MLB_OK;
+}
+
+int mlb_buckling_dev(mlb_ctx* c, int ref_case, int k, double tol_eig, double* lambda_host, double* Phi,
+                     mlb_eig_info* info, void* stream) {
+    if (!c) return MLB_EINVAL;
+    c->st = pick(c, stream);
+    CHK(do_buckling(c, ref_case, k, tol_eig, info));
+    if (lambda_host) std::memcpy(lambda_host, c->lam.data(), sizeof(double) * k);
+    if (Phi) HIPC(hipMemcpyAsync(Phi, c->Phi, sizeof(double) * c->n * k, hipMemcpyDeviceToDevice, c->st));
+    CHK(sync(c));
+    return MLB_OK;
+}
+
+int mlb_eig_residuals(mlb_ctx* c, double* res) {
+    if (!c || !res) return MLB_EINVAL;
+    if (!c->has_buck) return fail(c, MLB_ESTATE, "no buckling result");
+    std::memcpy(res, c->eigres.data(), sizeof(double) * c->eigres.size());
+    return MLB_OK;
+}
+
+int mlb_sensitivities(mlb_ctx* c, double* dJ, double* dlam, mlb_solve_info* info) {
+    if (!c) return MLB_EINVAL;
+    c->st = c->own;
+    double *dJd = nullptr, *dld = nullptr;
+    if (dJ) CHK(dalloc(c, &dJd, (size_t)c->m * std::max(1, c->ncases)));
+    if (dlam) CHK(dalloc(c, &dld, (size_t)c->m * std::max(1, c->k)));
+    int r = do_sens(c, dJd, dld, info);
+    if (r == MLB_OK && dJ) HIPC(hipMemcpy(dJ, dJd, sizeof(double) * c->m * c->ncases, hipMemcpyDeviceToHost));
+    if (r == MLB_OK && dlam) HIPC(hipMemcpy(dlam, dld, sizeof(double) * c->m * c->k, hipMemcpyDeviceToHost));
+    dfree(dJd);
+    dfree(dld);
+    return r;
+}
+
+int mlb_sensitivities_dev(mlb_ctx* c, double* dJ, double* dlam, mlb_solve_info* info, void* stream) {
+    if (!c) return MLB_EINVAL;
+    c->st = pick(c, stream);
+    return do_sens(c, dJ, dlam, info);
+}
+
+int mlb_set_warm_start(mlb_ctx* c, int kind, int ncols, const double* data) {
+    if (!c) return MLB_EINVAL;
+    if (kind == MLB_WARM_NONE) {
+        c->warm_coarse.clear();
+        c->warm_coarse_cols = 0;
+        c->warm_static.clear();
+        return MLB_OK;
+    }
+    if (!data || ncols < 1) return fail(c, MLB_EINVAL, "warm start needs data and ncols >= 1");
+    if (kind == MLB_WARM_COARSE) {
+        const int64_t nl = c->lv[c->ell - 1].n;
+        c->warm_coarse.assign(data, data + (size_t)nl * ncols);
+        c->warm_coarse_cols = ncols;
+        return MLB_OK;
+    }
+    if (kind == MLB_WARM_STATIC) {
+        c->warm_static.assign(data, data + (size_t)c->n * ncols);
+        return MLB_OK;
+    }
+    return fail(c, MLB_EINVAL, "unknown warm-start kind");
+}
+
+// ---- kernel-level entry points
+
+int mlb_apply_K_dev(mlb_ctx* c, int level, int ncols, const double* x, double* y, void* stream) {
+    if (!c || !x || !y || ncols < 1) return MLB_EINVAL;
+    if (level < 1 || level > c->L) return fail(c, MLB_EINVAL, "level out of range");
+    if (!c->has_density || !c->has_bc) return fail(c, MLB_ESTATE, "set the mask and the densities first");
+    c->st = pick(c, stream);
+    apply_K<double>(c, level, ncols, x, y, kModeY, nullptr, nullptr);
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+int mlb_apply_G_dev(mlb_ctx* c, int level, int ncols, const double* x, double* y, void* stream) {
+    if (!c || !x || !y || ncols < 1) return MLB_EINVAL;
+    if (level == 1) {
+        if (!c->has_stress) return fail(c, MLB_ESTATE, "no stress state: call mlb_set_state_dev or mlb_buckling");
+    } else if (level != c->ell || !c->has_buck) {
+        return fail(c, MLB_ESTATE, "coarse G exists only at the eigen level after mlb_buckling");
+    }
+    c->st = pick(c, stream);
+    apply_G(c, level, ncols, x, y);
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+int mlb_set_state_dev(mlb_ctx* c, const double* u, double* stress_out, void* stream) {
+    if (!c || !u) return MLB_EINVAL;
+    if (!c->has_density) return fail(c, MLB_ESTATE, "set the densities first");
+    c->st = pick(c, stream);
+    launch_stress(c->dim, c->lv[0].g, c->Es, u, c->dD0Bc, c->S, c->st);
+    if (stress_out)
+        HIPC(hipMemcpyAsync(stress_out, c->S, sizeof(double) * c->m * c->nv, hipMemcpyDeviceToDevice, c->st));
+    c->has_stress = true;
+    c->has_buck = false;
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+int mlb_prolong_dev(mlb_ctx* c, int level, int ncols, const double* xc, double* yf, void* stream) {
+    if (!c || !xc || !yf || ncols < 1) return MLB_EINVAL;
+    if (level < 1 || level >= c->L) return fail(c, MLB_EINVAL, "level out of range");
+    if (!c->has_bc) return fail(c, MLB_ESTATE, "set the mask first");
+    c->st = pick(c, stream);
+    Level& lf = c->lv[level - 1];
+    Level& lc = c->lv[level];
+    launch_prolong<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, ncols, lf.n, lc.n, xc, yf, false, c->st);
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+int mlb_restrict_dev(mlb_ctx* c, int level, int ncols, const double* xf, double* yc, void* stream) {
+    if (!c || !xf || !yc || ncols < 1) return MLB_EINVAL;
+    if (level < 1 || level >= c->L) return fail(c, MLB_EINVAL, "level out of range");
+    if (!c->has_bc) return fail(c, MLB_ESTATE, "set the mask first");
+    c->st = pick(c, stream);
+    Level& lf = c->lv[level - 1];
+    Level& lc = c->lv[level];
+    launch_restrict<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, ncols, lf.n, lc.n, xf, yc, c->st);
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+int mlb_vcycle_dev(mlb_ctx* c, int level, int ncols, const double* r, double* z, void* stream) {
+    if (!c || !r || !z || ncols < 1) return MLB_EINVAL;
+    if (level < 1 || level > c->L) return fail(c, MLB_EINVAL, "level out of range");
+    if (!c->has_density || !c->has_bc) return fail(c, MLB_ESTATE, "set the mask and the densities first");
+    c->st = pick(c, stream);
+    CHK(ensure_level_cols(c, ncols));
+    precondition(c, level, ncols, r, z);
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+}  // extern "C"

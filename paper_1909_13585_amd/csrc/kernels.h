@@ -1,0 +1,107 @@
+// Host launchers of the HIP kernels (all enqueue on the given stream).
+#pragma once
+
+#include "common.h"
+
+namespace mlb {
+
+// ---- operators and transfers (kernels_apply.hip)
+int64_t apply_fine_blocks(const Geo& g);
+template <typename T>
+void launch_apply_fine(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* K0, int ncols,
+                       int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega,
+                       double* dot_part, hipStream_t st);
+template <typename T>
+void launch_apply_dense(int dim, const Geo& g, const T* Ke, bool kron, const uint8_t* nmask, int ncols,
+                        int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega,
+                        hipStream_t st);
+void launch_apply_G_fine(int dim, const Geo& g, const double* S, const uint8_t* nmask, const double* Hk,
+                         int ncols, int64_t ld, const double* x, double* y, hipStream_t st);
+void launch_dinv_fine(int dim, const Geo& g, const double* E, const uint8_t* nmask, const double* K0,
+                      double* dinv, float* dinvf, hipStream_t st);
+void launch_dinv_dense(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, double* dinv,
+                       float* dinvf, hipStream_t st);
+template <typename T>
+void launch_prolong(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
+                    int64_t ldf, int64_t ldc, const T* xc, T* yf, bool add, hipStream_t st);
+template <typename T>
+void launch_restrict(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
+                     int64_t ldf, int64_t ldc, const T* xf, T* yc, hipStream_t st);
+
+// ---- setup (kernels_setup.hip)
+void launch_material(int64_t m, const double* x, double E1, double E0, double p, double* Ek, float* Ekf,
+                     double* Es, int nparts, double* bad_part, hipStream_t st);
+void launch_node_mask(int64_t nodes, int dim, const uint8_t* fixed_dof, uint8_t* nmask, hipStream_t st);
+void launch_coarse_mask(const Geo& gf, const Geo& gc, const uint8_t* mf, uint8_t* mc, hipStream_t st);
+void launch_galerkin_from_E(int dim, const Geo& gf, const Geo& gc, const double* E, const double* Mc,
+                            double* Kc, hipStream_t st);
+void launch_galerkin_G_from_S(int dim, const Geo& gf, const Geo& gc, const double* S, const double* GHc,
+                              double* gc_out, hipStream_t st);
+void launch_galerkin_dense(int dim, bool kron, const Geo& gf, const Geo& gc, const double* Kf,
+                           const double* T, double* Kc, hipStream_t st);
+void launch_to_float(int64_t n, const double* a, float* b, hipStream_t st);
+void launch_assemble_dense(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, int64_t n,
+                           double* A, hipStream_t st);
+void launch_gj_init(int64_t n, const double* A, double* rowk, double* colk, hipStream_t st);
+void launch_gj_step(int64_t n, int64_t k, double* A, const double* rowk, const double* colk,
+                    double* rowk1, double* colk1, hipStream_t st);
+template <typename T>
+void launch_dense_matvec(int64_t n, int ncols, int64_t ld, const double* A, const T* x, T* y, hipStream_t st);
+
+// ---- vector kernels (kernels_blas.hip)
+template <typename T>
+void launch_jacobi0(int64_t n, int ncols, int64_t ld, const T* dinv, T omega, const T* r, T* z, hipStream_t st);
+void launch_d2f(int64_t n, int ncols, int64_t ld, const double* a, float* b, hipStream_t st);
+void launch_f2d(int64_t n, int ncols, int64_t ld, const float* a, double* b, hipStream_t st);
+int reduction_parts(int64_t n);
+void launch_dot_part(int64_t n, int ncols, int64_t lda, const double* a, int64_t ldb, const double* b,
+                     int nparts, double* part, hipStream_t st);
+void launch_sum_parts(int ncols, int64_t nparts, const double* part, double* out, hipStream_t st);
+void launch_cg_alpha(int ncols, const double* rz, const double* pq, const int* active, double* alpha,
+                     int* flags, hipStream_t st);
+void launch_cg_beta(int ncols, const double* rz_new, double* rz, const int* active, double* beta,
+                    hipStream_t st);
+void launch_cg_beta_flex(int ncols, const double* rz_new, const double* rz_cross, double* rz, const int* active,
+                         double* beta, hipStream_t st);
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
+void launch_rsqrt(int ncols, const double* in, double* out, hipStream_t st);
+void launch_cg_update_xr(int64_t n, int ncols, int64_t ld, const double* alpha, const double* p,
+                         const double* q, double* x, double* r, int nparts, double* rr_part, hipStream_t st);
+void launch_cg_update_p(int64_t n, int ncols, int64_t ld, const double* beta, const double* z, double* p,
+                        hipStream_t st);
+void launch_copy_cols(int64_t n, int ncols, int64_t lds, const double* s, int64_t ldd, double* d,
+                      hipStream_t st);
+void launch_axpy_cols(int64_t n, int ncols, int64_t ld, const double* coef, double sign, const double* x,
+                      double* y, hipStream_t st);
+void launch_gram_part(int64_t n, int k1, int64_t lda, const double* A, int k2, int64_t ldb, const double* B,
+                      int nparts, double* part, hipStream_t st);
+void launch_gram_sum(int k1, int k2, int nparts, const double* part, double* out, hipStream_t st);
+void launch_gemm_small(int64_t n, int k1, int64_t lds, const double* S, int k2, const double* C, int64_t ldy,
+                       double* Y, hipStream_t st);
+void launch_residual_block(int64_t n, int ncols, int64_t ld, const double* AX, const double* KX,
+                           const double* mu, double* R, hipStream_t st);
+void launch_random_fill(int64_t n, int ncols, int64_t ld, uint64_t seed, const uint8_t* nmask, int dim,
+                        double* X, hipStream_t st);
+void launch_absmax_part(int64_t n, int ncols, int64_t ld, const double* X, int nparts, double* pval,
+                        int64_t* pidx, hipStream_t st);
+void launch_absmax_sum(int ncols, int nparts, const double* pval, const int64_t* pidx, double* out_val,
+                       hipStream_t st);
+void launch_infnorm_part(int64_t n, int ncols, int64_t ld, const double* X, int nparts, double* part,
+                         hipStream_t st);
+void launch_max_parts(int ncols, int nparts, const double* part, double* out, hipStream_t st);
+void launch_scale_cols(int64_t n, int ncols, int64_t ld, const double* s, double* X, hipStream_t st);
+
+// ---- physics (kernels_sens.hip)
+void launch_stress(int dim, const Geo& g, const double* Es, const double* u, const double* D0Bc, double* S,
+                   hipStream_t st);
+void launch_dJ(int dim, const Geo& g, const double* x, double p, double dE, int ncases, int64_t ld,
+               const double* U, const double* K0, double* dJ, hipStream_t st);
+void launch_adj_elem(int dim, const Geo& g, const double* Es, int q, int64_t ld, const double* Phi,
+                     const double* Hk, const double* D0, double* V, hipStream_t st);
+void launch_adj_gather(int dim, const Geo& g, int q, const double* V, const double* Bc, const uint8_t* nmask,
+                       int64_t ld, double* B, hipStream_t st);
+void launch_dlam(int dim, const Geo& g, const double* x, double p, double E1, double E0, const double* u, int q,
+                 int64_t ld, const double* Phi, const double* Z, const double* lam, const double* K0,
+                 const double* Hk, const double* D0Bc, double* out, hipStream_t st);
+
+}  // namespace mlb

@@ -1,0 +1,566 @@
+// Operator applies, smoother epilogues, diagonals and grid transfers.
+//
+// All applies are node-centric gathers: one thread owns one grid node and
+// sums the contributions of the (up to) 2^dim elements around it, so no
+// atomics are needed and results are bitwise repeatable.  Vectors are
+// interleaved (dof = dim*node + c) and blocks are column-major with leading
+// dimension `ld`.  Dirichlet DOFs: K has identity rows/columns, G zero ones
+// (the masked operators of the fine problem and of every Galerkin level).
+#include "kernels.h"
+
+namespace mlb {
+
+// ---------------------------------------------------------------------------
+// small helpers
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over the block; valid in linear thread 0.  Uses fixed-order trees.
+__device__ inline double block_sum(double v, double* sh) {
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthreads = blockDim.x * blockDim.y * blockDim.z;
+    const int lane = tid & 63, wid = tid >> 6, nw = (nthreads + 63) >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (wid == 0) {
+        r = lane < nw ? sh[lane] : 0.0;
+        r = wave_sum(r);
+    }
+    return r;
+}
+
+template <int DIM>
+struct Nb {
+    static constexpr int NN = 1 << DIM;
+    static constexpr int ND = DIM;
+    static constexpr int NDE = DIM << DIM;
+    static constexpr int NB = DIM == 2 ? 9 : 27;
+    // neighbour slot of offset (dx,dy,dz) in {-1,0,1}
+    static __device__ __host__ constexpr int slot(int dx, int dy, int dz) {
+        return (dx + 1) + 3 * (dy + 1) + (DIM == 3 ? 9 * (dz + 1) : 0);
+    }
+};
+
+// Loads the 3^dim neighbourhood of node (i,j,k): validity, node masks, indices.
+template <int DIM>
+__device__ inline void neighbourhood(const Geo& g, int i, int j, int k, const uint8_t* __restrict__ nmask,
+                                     int64_t* idx, uint8_t* msk) {
+    using N = Nb<DIM>;
+#pragma unroll
+    for (int t = 0; t < N::NB; ++t) {
+        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+        const int ii = i + dx, jj = j + dy, kk = k + dz;
+        const bool ok = ii >= 0 && ii < g.nnx && jj >= 0 && jj < g.nny && kk >= 0 && kk < g.nnz;
+        const int64_t n = ok ? ii + (int64_t)g.nnx * (jj + (int64_t)g.nny * kk) : 0;
+        idx[t] = n;
+        msk[t] = ok ? nmask[n] : (uint8_t)0xff;   // outside: treat as fixed (value 0)
+    }
+}
+
+template <int DIM>
+__device__ inline int64_t elem_of_slot(const Geo& g, int i, int j, int k, int s, bool& ok) {
+    const int ox = s & 1, oy = (s >> 1) & 1, oz = (s >> 2) & 1;
+    const int ei = i - 1 + ox, ej = j - 1 + oy, ek = DIM == 3 ? k - 1 + oz : 0;
+    ok = ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && (DIM == 2 || (ek >= 0 && ek < g.nz));
+    return ok ? ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek) : 0;
+}
+
+template <typename T, int MODE>
+__device__ inline T epilogue(T ax, T xown, T rr, T di, T omega) {
+    if (MODE == kModeY) return ax;
+    if (MODE == kModeResidual) return rr - ax;
+    return xown + omega * di * (rr - ax);
+}
+
+// ---------------------------------------------------------------------------
+// Level-1 stiffness apply, matrix free: y = sum_e E_e P_e^T K0 P_e x.
+
+template <int DIM, typename T, int MODE, bool DOT>
+__global__ __launch_bounds__(256) void k_apply_fine(Geo g, const T* __restrict__ E,
+                                                    const uint8_t* __restrict__ nmask,
+                                                    const T* __restrict__ K0, int ncols, int64_t ld,
+                                                    const T* __restrict__ x, T* __restrict__ y,
+                                                    const T* __restrict__ r, const T* __restrict__ dinv,
+                                                    T omega, double* __restrict__ part) {
+    using N = Nb<DIM>;
+    __shared__ double sh[16];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = DIM == 3 ? blockIdx.z : 0;
+    const bool active = i < g.nnx && j < g.nny;
+    const int ic = active ? i : 0, jc = active ? j : 0;
+    const int64_t node = ic + (int64_t)g.nnx * (jc + (int64_t)g.nny * k);
+    int64_t idx[N::NB];
+    uint8_t msk[N::NB];
+    neighbourhood<DIM>(g, ic, jc, k, nmask, idx, msk);
+    T Ee[N::NN];
+#pragma unroll
+    for (int s = 0; s < N::NN; ++s) {
+        bool ok;
+        const int64_t e = elem_of_slot<DIM>(g, ic, jc, k, s, ok);
+        Ee[s] = ok ? E[e] : T(0);
+    }
+    const uint8_t own = msk[N::slot(0, 0, 0)];
+    const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+    const int64_t nblk = (int64_t)gridDim.x * gridDim.y * gridDim.z;
+    for (int col = 0; col < ncols; ++col) {
+        const T* xc = x + col * ld;
+        T xv[N::NB][N::ND];
+#pragma unroll
+        for (int t = 0; t < N::NB; ++t)
+#pragma unroll
+            for (int c = 0; c < N::ND; ++c)
+                xv[t][c] = (msk[t] >> c) & 1 ? T(0) : xc[idx[t] * N::ND + c];
+        T acc[N::ND];
+#pragma unroll
+        for (int c = 0; c < N::ND; ++c) acc[c] = T(0);
+#pragma unroll
+        for (int s = 0; s < N::NN; ++s) {
+            const int ox = s & 1, oy = (s >> 1) & 1, oz = (s >> 2) & 1;
+            const int a = (N::NN - 1) ^ s;   // local index of this node in element slot s
+            T t[N::ND];
+#pragma unroll
+            for (int c = 0; c < N::ND; ++c) t[c] = T(0);
+#pragma unroll
+            for (int b = 0; b < N::NN; ++b) {
+                const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+                const int ts = N::slot(ox - 1 + bx, oy - 1 + by, DIM == 3 ? oz - 1 + bz : 0);
+#pragma unroll
+                for (int c = 0; c < N::ND; ++c)
+#pragma unroll
+                    for (int c2 = 0; c2 < N::ND; ++c2)
+                        t[c] += K0[(a * N::ND + c) * N::NDE + b * N::ND + c2] * xv[ts][c2];
+            }
+#pragma unroll
+            for (int c = 0; c < N::ND; ++c) acc[c] += Ee[s] * t[c];
+        }
+        double dsum = 0.0;
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < N::ND; ++c) {
+                const int64_t d = node * N::ND + c;
+                const T xown = xc[d];
+                const T ax = (own >> c) & 1 ? xown : acc[c];
+                const T rr = MODE == kModeY ? T(0) : r[col * ld + d];
+                const T di = MODE == kModeJacobi ? dinv[d] : T(0);
+                y[col * ld + d] = epilogue<T, MODE>(ax, xown, rr, di, omega);
+                if (DOT) dsum += (double)xown * (double)ax;
+            }
+        }
+        if (DOT) {
+            const double bs = block_sum(dsum, sh);
+            if (threadIdx.x == 0 && threadIdx.y == 0) part[col * nblk + blk] = bs;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-level apply from dense per-element matrices (SoA: entry-major,
+// stride m).  KRON: scalar nn x nn matrices acting on each component (G).
+
+template <int DIM, typename T, int MODE, bool KRON>
+__global__ __launch_bounds__(256) void k_apply_dense(Geo g, const T* __restrict__ Ke,
+                                                     const uint8_t* __restrict__ nmask, int ncols,
+                                                     int64_t ld, const T* __restrict__ x,
+                                                     T* __restrict__ y, const T* __restrict__ r,
+                                                     const T* __restrict__ dinv, T omega) {
+    using N = Nb<DIM>;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = DIM == 3 ? blockIdx.z : 0;
+    if (i >= g.nnx || j >= g.nny) return;
+    const int64_t node = i + (int64_t)g.nnx * (j + (int64_t)g.nny * k);
+    int64_t idx[N::NB];
+    uint8_t msk[N::NB];
+    neighbourhood<DIM>(g, i, j, k, nmask, idx, msk);
+    int64_t es[N::NN];
+    bool eok[N::NN];
+#pragma unroll
+    for (int s = 0; s < N::NN; ++s) es[s] = elem_of_slot<DIM>(g, i, j, k, s, eok[s]);
+    const uint8_t own = msk[N::slot(0, 0, 0)];
+    const int64_t m = g.m;
+    for (int col = 0; col < ncols; ++col) {
+        const T* xc = x + col * ld;
+        T xv[N::NB][N::ND];
+#pragma unroll
+        for (int t = 0; t < N::NB; ++t)
+#pragma unroll
+            for (int c = 0; c < N::ND; ++c)
+                xv[t][c] = (msk[t] >> c) & 1 ? T(0) : xc[idx[t] * N::ND + c];
+        T acc[N::ND];
+#pragma unroll
+        for (int c = 0; c < N::ND; ++c) acc[c] = T(0);
+#pragma unroll
+        for (int s = 0; s < N::NN; ++s) {
+            if (!eok[s]) continue;
+            const int ox = s & 1, oy = (s >> 1) & 1, oz = (s >> 2) & 1;
+            const int a = (N::NN - 1) ^ s;
+            const T* Kb = Ke + es[s];
+#pragma unroll
+            for (int b = 0; b < N::NN; ++b) {
+                const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+                const int ts = N::slot(ox - 1 + bx, oy - 1 + by, DIM == 3 ? oz - 1 + bz : 0);
+                if (KRON) {
+                    const T gv = Kb[(int64_t)(a * N::NN + b) * m];
+#pragma unroll
+                    for (int c = 0; c < N::ND; ++c) acc[c] += gv * xv[ts][c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < N::ND; ++c)
+#pragma unroll
+                        for (int c2 = 0; c2 < N::ND; ++c2)
+                            acc[c] += Kb[(int64_t)((a * N::ND + c) * N::NDE + b * N::ND + c2) * m] * xv[ts][c2];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < N::ND; ++c) {
+            const int64_t d = node * N::ND + c;
+            const T xown = xc[d];
+            const T ax = (own >> c) & 1 ? (KRON ? T(0) : xown) : acc[c];
+            const T rr = MODE == kModeY ? T(0) : r[col * ld + d];
+            const T di = MODE == kModeJacobi ? dinv[d] : T(0);
+            y[col * ld + d] = epilogue<T, MODE>(ax, xown, rr, di, omega);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level-1 stress-stiffness apply from element stresses S (SoA nv x m):
+// G_e = (sum_k S_k,e Hk_k) kron I.
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_apply_G_fine(Geo g, const double* __restrict__ S,
+                                                      const uint8_t* __restrict__ nmask,
+                                                      const double* __restrict__ Hk, int ncols, int64_t ld,
+                                                      const double* __restrict__ x, double* __restrict__ y) {
+    using N = Nb<DIM>;
+    constexpr int NV = DIM == 2 ? 3 : 6;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = DIM == 3 ? blockIdx.z : 0;
+    if (i >= g.nnx || j >= g.nny) return;
+    const int64_t node = i + (int64_t)g.nnx * (j + (int64_t)g.nny * k);
+    int64_t idx[N::NB];
+    uint8_t msk[N::NB];
+    neighbourhood<DIM>(g, i, j, k, nmask, idx, msk);
+    // row a of each adjacent element's scalar matrix g_e
+    double grow[N::NN][N::NN];
+#pragma unroll
+    for (int s = 0; s < N::NN; ++s) {
+        bool ok;
+        const int64_t e = elem_of_slot<DIM>(g, i, j, k, s, ok);
+        const int a = (N::NN - 1) ^ s;
+        double sv[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sv[q] = ok ? S[q * g.m + e] : 0.0;
+#pragma unroll
+        for (int b = 0; b < N::NN; ++b) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v += sv[q] * Hk[q * 64 + a * N::NN + b];
+            grow[s][b] = v;
+        }
+    }
+    const uint8_t own = msk[N::slot(0, 0, 0)];
+    for (int col = 0; col < ncols; ++col) {
+        const double* xc = x + col * ld;
+        double acc[N::ND];
+#pragma unroll
+        for (int c = 0; c < N::ND; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int s = 0; s < N::NN; ++s) {
+            const int ox = s & 1, oy = (s >> 1) & 1, oz = (s >> 2) & 1;
+#pragma unroll
+            for (int b = 0; b < N::NN; ++b) {
+                const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+                const int ts = N::slot(ox - 1 + bx, oy - 1 + by, DIM == 3 ? oz - 1 + bz : 0);
+#pragma unroll
+                for (int c = 0; c < N::ND; ++c) {
+                    const double xv = (msk[ts] >> c) & 1 ? 0.0 : xc[idx[ts] * N::ND + c];
+                    acc[c] += grow[s][b] * xv;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < N::ND; ++c) y[col * ld + node * N::ND + c] = (own >> c) & 1 ? 0.0 : acc[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse diagonals (Jacobi), FP64 and FP32 copies; 1 at fixed DOFs.
+
+template <int DIM>
+__global__ void k_dinv_fine(Geo g, const double* __restrict__ E, const uint8_t* __restrict__ nmask,
+                            const double* __restrict__ K0, double* __restrict__ dinv, float* __restrict__ dinvf) {
+    using N = Nb<DIM>;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = DIM == 3 ? blockIdx.z : 0;
+    if (i >= g.nnx || j >= g.nny) return;
+    const int64_t node = i + (int64_t)g.nnx * (j + (int64_t)g.nny * k);
+    const uint8_t own = nmask[node];
+#pragma unroll
+    for (int c = 0; c < N::ND; ++c) {
+        double d = 0.0;
+#pragma unroll
+        for (int s = 0; s < N::NN; ++s) {
+            bool ok;
+            const int64_t e = elem_of_slot<DIM>(g, i, j, k, s, ok);
+            const int a = (N::NN - 1) ^ s;
+            if (ok) d += E[e] * K0[(a * N::ND + c) * N::NDE + a * N::ND + c];
+        }
+        const double v = (own >> c) & 1 ? 1.0 : (d > 0.0 ? 1.0 / d : 0.0);
+        dinv[node * N::ND + c] = v;
+        dinvf[node * N::ND + c] = (float)v;
+    }
+}
+
+template <int DIM>
+__global__ void k_dinv_dense(Geo g, const double* __restrict__ Ke, const uint8_t* __restrict__ nmask,
+                             double* __restrict__ dinv, float* __restrict__ dinvf) {
+    using N = Nb<DIM>;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = DIM == 3 ? blockIdx.z : 0;
+    if (i >= g.nnx || j >= g.nny) return;
+    const int64_t node = i + (int64_t)g.nnx * (j + (int64_t)g.nny * k);
+    const uint8_t own = nmask[node];
+#pragma unroll
+    for (int c = 0; c < N::ND; ++c) {
+        double d = 0.0;
+#pragma unroll
+        for (int s = 0; s < N::NN; ++s) {
+            bool ok;
+            const int64_t e = elem_of_slot<DIM>(g, i, j, k, s, ok);
+            const int a = (N::NN - 1) ^ s;
+            const int row = a * N::ND + c;
+            if (ok) d += Ke[(int64_t)(row * N::NDE + row) * g.m + e];
+        }
+        const double v = (own >> c) & 1 ? 1.0 : (d > 0.0 ? 1.0 / d : 0.0);
+        dinv[node * N::ND + c] = v;
+        dinvf[node * N::ND + c] = (float)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Transfers between level j (fine, gf) and j+1 (coarse, gc): nodal
+// bilinear/trilinear interpolation P and its transpose, masked both sides.
+
+template <int DIM, typename T, bool ADD>
+__global__ void k_prolong(Geo gf, Geo gc, const uint8_t* __restrict__ mf, const uint8_t* __restrict__ mc,
+                          int ncols, int64_t ldf, int64_t ldc, const T* __restrict__ xc, T* __restrict__ yf) {
+    constexpr int ND = DIM;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = DIM == 3 ? blockIdx.z : 0;
+    if (i >= gf.nnx || j >= gf.nny) return;
+    const int64_t node = i + (int64_t)gf.nnx * (j + (int64_t)gf.nny * k);
+    const uint8_t own = mf[node];
+    const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
+    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
+    const T w = T(1) / T(ni * nj * nk);
+    for (int col = 0; col < ncols; ++col) {
+        T acc[ND];
+#pragma unroll
+        for (int c = 0; c < ND; ++c) acc[c] = T(0);
+        for (int dk = 0; dk < nk; ++dk)
+            for (int dj = 0; dj < nj; ++dj)
+                for (int di = 0; di < ni; ++di) {
+                    const int64_t cn = (i0 + di) + (int64_t)gc.nnx * ((j0 + dj) + (int64_t)gc.nny * (k0 + dk));
+                    const uint8_t cm = mc[cn];
+#pragma unroll
+                    for (int c = 0; c < ND; ++c)
+                        if (!((cm >> c) & 1)) acc[c] += xc[col * ldc + cn * ND + c];
+                }
+#pragma unroll
+        for (int c = 0; c < ND; ++c) {
+            const int64_t d = col * ldf + node * ND + c;
+            if ((own >> c) & 1) {
+                if (!ADD) yf[d] = T(0);
+            } else {
+                yf[d] = ADD ? yf[d] + w * acc[c] : w * acc[c];
+            }
+        }
+    }
+}
+
+template <int DIM, typename T>
+__global__ void k_restrict(Geo gf, Geo gc, const uint8_t* __restrict__ mf, const uint8_t* __restrict__ mc,
+                           int ncols, int64_t ldf, int64_t ldc, const T* __restrict__ xf, T* __restrict__ yc) {
+    constexpr int ND = DIM;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = DIM == 3 ? blockIdx.z : 0;
+    if (I >= gc.nnx || J >= gc.nny) return;
+    const int64_t cnode = I + (int64_t)gc.nnx * (J + (int64_t)gc.nny * K);
+    const uint8_t own = mc[cnode];
+    const int kr = DIM == 3 ? 1 : 0;
+    for (int col = 0; col < ncols; ++col) {
+        T acc[ND];
+#pragma unroll
+        for (int c = 0; c < ND; ++c) acc[c] = T(0);
+        for (int dk = -kr; dk <= kr; ++dk) {
+            const int kk = 2 * K + dk;
+            if (kk < 0 || kk >= gf.nnz) continue;
+            const T wk = dk == 0 ? T(1) : T(0.5);
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int jj = 2 * J + dj;
+                if (jj < 0 || jj >= gf.nny) continue;
+                const T wj = dj == 0 ? wk : wk * T(0.5);
+                for (int di = -1; di <= 1; ++di) {
+                    const int ii = 2 * I + di;
+                    if (ii < 0 || ii >= gf.nnx) continue;
+                    const T w = di == 0 ? wj : wj * T(0.5);
+                    const int64_t fn = ii + (int64_t)gf.nnx * (jj + (int64_t)gf.nny * kk);
+                    const uint8_t fm = mf[fn];
+#pragma unroll
+                    for (int c = 0; c < ND; ++c)
+                        if (!((fm >> c) & 1)) acc[c] += w * xf[col * ldf + fn * ND + c];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < ND; ++c)
+            yc[col * ldc + cnode * ND + c] = (own >> c) & 1 ? T(0) : acc[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+
+static dim3 node_grid(const Geo& g, dim3& block) {
+    block = dim3(64, 4, 1);
+    return dim3((g.nnx + 63) / 64, (g.nny + 3) / 4, g.nnz);
+}
+
+int64_t apply_fine_blocks(const Geo& g) {
+    dim3 b;
+    dim3 gr = node_grid(g, b);
+    return (int64_t)gr.x * gr.y * gr.z;
+}
+
+template <typename T>
+void launch_apply_fine(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* K0, int ncols,
+                       int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega,
+                       double* dot_part, hipStream_t st) {
+    dim3 b;
+    dim3 gr = node_grid(g, b);
+#define MLB_LAUNCH(D, M, DOT)                                                                     \
+    hipLaunchKernelGGL((k_apply_fine<D, T, M, DOT>), gr, b, 0, st, g, E, nmask, K0, ncols, ld, x, y, r, \
+                       dinv, omega, dot_part)
+    if (dim == 2) {
+        if (mode == kModeY && dot_part) MLB_LAUNCH(2, kModeY, true);
+        else if (mode == kModeY) MLB_LAUNCH(2, kModeY, false);
+        else if (mode == kModeResidual) MLB_LAUNCH(2, kModeResidual, false);
+        else MLB_LAUNCH(2, kModeJacobi, false);
+    } else {
+        if (mode == kModeY && dot_part) MLB_LAUNCH(3, kModeY, true);
+        else if (mode == kModeY) MLB_LAUNCH(3, kModeY, false);
+        else if (mode == kModeResidual) MLB_LAUNCH(3, kModeResidual, false);
+        else MLB_LAUNCH(3, kModeJacobi, false);
+    }
+#undef MLB_LAUNCH
+}
+
+template <typename T>
+void launch_apply_dense(int dim, const Geo& g, const T* Ke, bool kron, const uint8_t* nmask, int ncols,
+                        int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega,
+                        hipStream_t st) {
+    dim3 b;
+    dim3 gr = node_grid(g, b);
+#define MLB_LAUNCH(D, M, KR) \
+    hipLaunchKernelGGL((k_apply_dense<D, T, M, KR>), gr, b, 0, st, g, Ke, nmask, ncols, ld, x, y, r, dinv, omega)
+    if (kron) {
+        if (dim == 2) MLB_LAUNCH(2, kModeY, true);
+        else MLB_LAUNCH(3, kModeY, true);
+        return;
+    }
+    if (dim == 2) {
+        if (mode == kModeY) MLB_LAUNCH(2, kModeY, false);
+        else if (mode == kModeResidual) MLB_LAUNCH(2, kModeResidual, false);
+        else MLB_LAUNCH(2, kModeJacobi, false);
+    } else {
+        if (mode == kModeY) MLB_LAUNCH(3, kModeY, false);
+        else if (mode == kModeResidual) MLB_LAUNCH(3, kModeResidual, false);
+        else MLB_LAUNCH(3, kModeJacobi, false);
+    }
+#undef MLB_LAUNCH
+}
+
+void launch_apply_G_fine(int dim, const Geo& g, const double* S, const uint8_t* nmask, const double* Hk,
+                         int ncols, int64_t ld, const double* x, double* y, hipStream_t st) {
+    dim3 b;
+    dim3 gr = node_grid(g, b);
+    if (dim == 2) hipLaunchKernelGGL(k_apply_G_fine<2>, gr, b, 0, st, g, S, nmask, Hk, ncols, ld, x, y);
+    else hipLaunchKernelGGL(k_apply_G_fine<3>, gr, b, 0, st, g, S, nmask, Hk, ncols, ld, x, y);
+}
+
+void launch_dinv_fine(int dim, const Geo& g, const double* E, const uint8_t* nmask, const double* K0,
+                      double* dinv, float* dinvf, hipStream_t st) {
+    dim3 b;
+    dim3 gr = node_grid(g, b);
+    if (dim == 2) hipLaunchKernelGGL(k_dinv_fine<2>, gr, b, 0, st, g, E, nmask, K0, dinv, dinvf);
+    else hipLaunchKernelGGL(k_dinv_fine<3>, gr, b, 0, st, g, E, nmask, K0, dinv, dinvf);
+}
+
+void launch_dinv_dense(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, double* dinv,
+                       float* dinvf, hipStream_t st) {
+    dim3 b;
+    dim3 gr = node_grid(g, b);
+    if (dim == 2) hipLaunchKernelGGL(k_dinv_dense<2>, gr, b, 0, st, g, Ke, nmask, dinv, dinvf);
+    else hipLaunchKernelGGL(k_dinv_dense<3>, gr, b, 0, st, g, Ke, nmask, dinv, dinvf);
+}
+
+template <typename T>
+void launch_prolong(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
+                    int64_t ldf, int64_t ldc, const T* xc, T* yf, bool add, hipStream_t st) {
+    dim3 b;
+    dim3 gr = node_grid(gf, b);
+    if (dim == 2) {
+        if (add) hipLaunchKernelGGL((k_prolong<2, T, true>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xc, yf);
+        else hipLaunchKernelGGL((k_prolong<2, T, false>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xc, yf);
+    } else {
+        if (add) hipLaunchKernelGGL((k_prolong<3, T, true>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xc, yf);
+        else hipLaunchKernelGGL((k_prolong<3, T, false>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xc, yf);
+    }
+}
+
+template <typename T>
+void launch_restrict(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
+                     int64_t ldf, int64_t ldc, const T* xf, T* yc, hipStream_t st) {
+    dim3 b;
+    dim3 gr = node_grid(gc, b);
+    if (dim == 2) hipLaunchKernelGGL((k_restrict<2, T>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xf, yc);
+    else hipLaunchKernelGGL((k_restrict<3, T>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xf, yc);
+}
+
+template void launch_apply_fine<double>(int, const Geo&, const double*, const uint8_t*, const double*, int,
+                                        int64_t, const double*, double*, int, const double*, const double*,
+                                        double, double*, hipStream_t);
+template void launch_apply_fine<float>(int, const Geo&, const float*, const uint8_t*, const float*, int,
+                                       int64_t, const float*, float*, int, const float*, const float*, float,
+                                       double*, hipStream_t);
+template void launch_apply_dense<double>(int, const Geo&, const double*, bool, const uint8_t*, int, int64_t,
+                                         const double*, double*, int, const double*, const double*, double,
+                                         hipStream_t);
+template void launch_apply_dense<float>(int, const Geo&, const float*, bool, const uint8_t*, int, int64_t,
+                                        const float*, float*, int, const float*, const float*, float,
+                                        hipStream_t);
+template void launch_prolong<double>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
+                                     int64_t, const double*, double*, bool, hipStream_t);
+template void launch_prolong<float>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
+                                    int64_t, const float*, float*, bool, hipStream_t);
+template void launch_restrict<double>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
+                                      int64_t, const double*, double*, hipStream_t);
+template void launch_restrict<float>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
+                                     int64_t, const float*, float*, hipStream_t);
+
+}  // namespace mlb

@@ -1,0 +1,471 @@
+// Block-vector kernels of the Krylov solvers and the eigensolver.
+//
+// Reductions are two-stage and deterministic: each block writes one partial
+// per column (fixed-order wavefront trees), then a single block per output
+// sums the partials in index order.  No atomics.
+#include "kernels.h"
+
+namespace mlb {
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// block of kBlock threads (1D); result valid in thread 0
+__device__ inline double bsum(double v, double* sh) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wsum(v);
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    return s;
+}
+
+__device__ inline double bmax(double v, double* sh) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s = fmax(s, sh[w]);
+    return s;
+}
+
+static inline unsigned nb1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+int reduction_parts(int64_t n) {
+    int64_t p = (n + 4 * kBlock - 1) / (4 * kBlock);
+    if (p < 1) p = 1;
+    if (p > kMaxPartials) p = kMaxPartials;
+    return (int)p;
+}
+
+// ---- elementwise
+
+template <typename T>
+__global__ void k_jacobi0(int64_t n, int ncols, int64_t ld, const T* __restrict__ dinv, T omega,
+                          const T* __restrict__ r, T* __restrict__ z) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T d = omega * dinv[i];
+    for (int c = 0; c < ncols; ++c) z[c * ld + i] = d * r[c * ld + i];
+}
+
+__global__ void k_d2f(int64_t n, int ncols, int64_t ld, const double* __restrict__ a, float* __restrict__ b) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < ncols; ++c) b[c * ld + i] = (float)a[c * ld + i];
+}
+
+__global__ void k_f2d(int64_t n, int ncols, int64_t ld, const float* __restrict__ a, double* __restrict__ b) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < ncols; ++c) b[c * ld + i] = (double)a[c * ld + i];
+}
+
+// ---- dots: grid (nparts, ncols)
+
+__global__ void k_dot_part(int64_t n, int64_t lda, const double* __restrict__ a, int64_t ldb,
+                           const double* __restrict__ b, double* __restrict__ part) {
+    __shared__ double sh[16];
+    const int col = blockIdx.y;
+    const double* ac = a + col * lda;
+    const double* bc = b + col * ldb;
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s += ac[i] * bc[i];
+    s = bsum(s, sh);
+    if (threadIdx.x == 0) part[col * gridDim.x + blockIdx.x] = s;
+}
+
+// out[col] = sum_b part[col*nparts + b]  (one block per column)
+__global__ void k_sum_parts(int64_t nparts, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double sh[16];
+    const int col = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) s += part[col * nparts + i];
+    s = bsum(s, sh);
+    if (threadIdx.x == 0) out[col] = s;
+}
+
+// alpha = rz / pq per active column; flags[col] = 1 on breakdown (pq <= 0 / non-finite)
+__global__ void k_cg_alpha(int ncols, const double* __restrict__ rz, const double* __restrict__ pq,
+                           const int* __restrict__ active, double* __restrict__ alpha, int* __restrict__ flags) {
+    const int c = threadIdx.x;
+    if (c >= ncols) return;
+    double a = 0.0;
+    if (active[c]) {
+        const double d = pq[c];
+        if (d > 0.0 && isfinite(d) && isfinite(rz[c])) a = rz[c] / d;
+        else flags[c] = 1;
+    }
+    alpha[c] = a;
+}
+
+__global__ void k_cg_beta(int ncols, const double* __restrict__ rz_new, double* __restrict__ rz,
+                          const int* __restrict__ active, double* __restrict__ beta) {
+    const int c = threadIdx.x;
+    if (c >= ncols) return;
+    double b = 0.0;
+    if (active[c] && rz[c] != 0.0) b = rz_new[c] / rz[c];
+    beta[c] = b;
+    rz[c] = rz_new[c];
+}
+
+// x += alpha p; r -= alpha q; partial r.r  (grid (nparts, ncols))
+// flexible (Polak-Ribiere) beta = (r_{k+1}.z_{k+1} - r_{k+1}.z_k) / (r_k.z_k)
+__global__ void k_cg_beta_flex(int ncols, const double* __restrict__ rz_new, const double* __restrict__ rz_cross,
+                               double* __restrict__ rz, const int* __restrict__ active, double* __restrict__ beta) {
+    const int c = threadIdx.x;
+    if (c >= ncols) return;
+    double b = 0.0;
+    if (active[c] && rz[c] != 0.0) b = (rz_new[c] - rz_cross[c]) / rz[c];
+    beta[c] = b;
+    rz[c] = rz_new[c];
+}
+
+// generic y = a*x + b*y over a contiguous array
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+
+// out[i] = 1/sqrt(in[i]) (0 if in <= 0)
+__global__ void k_rsqrt(int ncols, const double* __restrict__ in, double* __restrict__ out) {
+    const int c = threadIdx.x;
+    if (c < ncols) out[c] = in[c] > 0.0 ? 1.0 / sqrt(in[c]) : 0.0;
+}
+
+__global__ void k_cg_update_xr(int64_t n, int64_t ld, const double* __restrict__ alpha, const double* __restrict__ p,
+                               const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
+                               double* __restrict__ part) {
+    __shared__ double sh[16];
+    const int col = blockIdx.y;
+    const double a = alpha[col];
+    const int64_t o = col * ld;
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[o + i] += a * p[o + i];
+        const double rv = r[o + i] - a * q[o + i];
+        r[o + i] = rv;
+        s += rv * rv;
+    }
+    s = bsum(s, sh);
+    if (threadIdx.x == 0) part[col * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_cg_update_p(int64_t n, int ncols, int64_t ld, const double* __restrict__ beta,
+                              const double* __restrict__ z, double* __restrict__ p) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < ncols; ++c) p[c * ld + i] = z[c * ld + i] + beta[c] * p[c * ld + i];
+}
+
+__global__ void k_copy_cols(int64_t n, int ncols, int64_t lds, const double* __restrict__ s, int64_t ldd,
+                            double* __restrict__ d) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < ncols; ++c) d[c * ldd + i] = s[c * lds + i];
+}
+
+// y[:,c] += sign * coef[c] * x[:,c]
+__global__ void k_axpy_cols(int64_t n, int ncols, int64_t ld, const double* __restrict__ coef, double sign,
+                            const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < ncols; ++c) y[c * ld + i] += sign * coef[c] * x[c * ld + i];
+}
+
+// ---- Gram products A^T B (n x k1, n x k2): partial per block of rows
+// Rows are staged through LDS in chunks of 32; each thread owns outputs.
+constexpr int kGramChunk = 32;
+constexpr int kGramMax = 96;
+
+__global__ __launch_bounds__(256) void k_gram_part(int64_t n, int k1, int64_t lda, const double* __restrict__ A,
+                                                   int k2, int64_t ldb, const double* __restrict__ B,
+                                                   double* __restrict__ part) {
+    __shared__ double sa[kGramChunk][kGramMax];
+    __shared__ double sb[kGramChunk][kGramMax];
+    const int nout = k1 * k2;
+    double acc[24];
+    const int per = (nout + blockDim.x - 1) / blockDim.x;   // <= 24 when k1*k2 <= 6144
+#pragma unroll
+    for (int t = 0; t < 24; ++t) acc[t] = 0.0;
+    const int64_t nchunks = (n + kGramChunk - 1) / kGramChunk;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t r0 = ch * kGramChunk;
+        __syncthreads();
+        for (int t = threadIdx.x; t < kGramChunk * k1; t += blockDim.x) {
+            const int rr = t % kGramChunk, cc = t / kGramChunk;
+            const int64_t row = r0 + rr;
+            sa[rr][cc] = row < n ? A[cc * lda + row] : 0.0;
+        }
+        for (int t = threadIdx.x; t < kGramChunk * k2; t += blockDim.x) {
+            const int rr = t % kGramChunk, cc = t / kGramChunk;
+            const int64_t row = r0 + rr;
+            sb[rr][cc] = row < n ? B[cc * ldb + row] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 24; ++t) {
+            if (t >= per) break;
+            const int o = threadIdx.x + t * blockDim.x;
+            if (o >= nout) break;
+            const int i = o % k1, j = o / k1;
+            double s = acc[t];
+            for (int rr = 0; rr < kGramChunk; ++rr) s += sa[rr][i] * sb[rr][j];
+            acc[t] = s;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 24; ++t) {
+        if (t >= per) break;
+        const int o = threadIdx.x + t * blockDim.x;
+        if (o >= nout) break;
+        part[(int64_t)blockIdx.x * nout + o] = acc[t];
+    }
+}
+
+// out[o] = sum_b part[b*nout + o] in block order (o = i + k1*j, column-major k1 x k2)
+__global__ void k_gram_sum(int nout, int nparts, const double* __restrict__ part, double* __restrict__ out) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nout) return;
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * nout + o];
+    out[o] = s;
+}
+
+// Y (n x k2) = S (n x k1) C (k1 x k2, column-major), k1 <= 96, k2 <= 32;
+// C staged in LDS, one row of Y per thread accumulated in registers.
+__global__ void k_gemm_small(int64_t n, int k1, int64_t lds, const double* __restrict__ S, int k2,
+                             const double* __restrict__ C, int64_t ldy, double* __restrict__ Y) {
+    __shared__ double sc[kGramMax * 32];
+    for (int t = threadIdx.x; t < k1 * k2; t += blockDim.x) sc[t] = C[t];
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+    for (int a = 0; a < k1; ++a) {
+        const double sv = S[a * lds + i];
+#pragma unroll
+        for (int j = 0; j < 32; ++j)
+            if (j < k2) acc[j] += sv * sc[j * k1 + a];
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+        if (j < k2) Y[j * ldy + i] = acc[j];
+}
+
+// R = AX - KX diag(mu)
+__global__ void k_residual_block(int64_t n, int ncols, int64_t ld, const double* __restrict__ AX,
+                                 const double* __restrict__ KX, const double* __restrict__ mu, double* __restrict__ R) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < ncols; ++c) R[c * ld + i] = AX[c * ld + i] - mu[c] * KX[c * ld + i];
+}
+
+// Counter-based uniform(-1, 1) from splitmix64 of (seed, column, row); zero at fixed DOFs.
+__device__ inline uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_random_fill(int64_t n, int ncols, int64_t ld, uint64_t seed, const uint8_t* __restrict__ nmask,
+                              int dim, double* __restrict__ X) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool fixed = (nmask[i / dim] >> (i % dim)) & 1;
+    for (int c = 0; c < ncols; ++c) {
+        const uint64_t h = splitmix64(seed ^ splitmix64((uint64_t)c * 0x100000001B3ull + (uint64_t)i));
+        const double u = (double)(h >> 11) * (1.0 / 9007199254740992.0);
+        X[c * ld + i] = fixed ? 0.0 : 2.0 * u - 1.0;
+    }
+}
+
+// Column-wise argmax |x| (ties: lowest index) -> signed value of that entry.
+__global__ void k_absmax_part(int64_t n, int64_t ld, const double* __restrict__ X, double* __restrict__ pval,
+                              int64_t* __restrict__ pidx) {
+    __shared__ double sv[kBlock];
+    __shared__ int64_t si[kBlock];
+    const int col = blockIdx.y;
+    double best = -1.0, bval = 0.0;
+    int64_t bidx = INT64_MAX;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = X[col * ld + i];
+        if (fabs(v) > best) {   // strictly greater keeps the lowest index on ties
+            best = fabs(v);
+            bval = v;
+            bidx = i;
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bidx;
+    __shared__ double sval[kBlock];
+    sval[threadIdx.x] = bval;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const int o = threadIdx.x + s;
+            if (sv[o] > sv[threadIdx.x] || (sv[o] == sv[threadIdx.x] && si[o] < si[threadIdx.x])) {
+                sv[threadIdx.x] = sv[o];
+                si[threadIdx.x] = si[o];
+                sval[threadIdx.x] = sval[o];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pval[(int64_t)col * gridDim.x + blockIdx.x] = sval[0];
+        pidx[(int64_t)col * gridDim.x + blockIdx.x] = sv[0] >= 0.0 ? si[0] : INT64_MAX;
+    }
+}
+
+__global__ void k_absmax_sum(int ncols, int nparts, const double* __restrict__ pval, const int64_t* __restrict__ pidx,
+                             double* __restrict__ out) {
+    const int col = threadIdx.x;
+    if (col >= ncols) return;
+    double best = -1.0, val = 0.0;
+    int64_t bi = INT64_MAX;
+    for (int b = 0; b < nparts; ++b) {
+        const double v = pval[(int64_t)col * nparts + b];
+        const int64_t ix = pidx[(int64_t)col * nparts + b];
+        if (fabs(v) > best || (fabs(v) == best && ix < bi)) {
+            best = fabs(v);
+            val = v;
+            bi = ix;
+        }
+    }
+    out[col] = val;
+}
+
+__global__ void k_infnorm_part(int64_t n, int64_t ld, const double* __restrict__ X, double* __restrict__ part) {
+    __shared__ double sh[16];
+    const int col = blockIdx.y;
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s = fmax(s, fabs(X[col * ld + i]));
+    s = bmax(s, sh);
+    if (threadIdx.x == 0) part[col * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_max_parts(int nparts, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double sh[16];
+    const int col = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s = fmax(s, part[col * nparts + i]);
+    s = bmax(s, sh);
+    if (threadIdx.x == 0) out[col] = s;
+}
+
+__global__ void k_scale_cols(int64_t n, int ncols, int64_t ld, const double* __restrict__ s, double* __restrict__ X) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < ncols; ++c) X[c * ld + i] *= s[c];
+}
+
+// ---- launchers
+
+template <typename T>
+void launch_jacobi0(int64_t n, int ncols, int64_t ld, const T* dinv, T omega, const T* r, T* z, hipStream_t st) {
+    hipLaunchKernelGGL((k_jacobi0<T>), dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, dinv, omega, r, z);
+}
+template void launch_jacobi0<double>(int64_t, int, int64_t, const double*, double, const double*, double*, hipStream_t);
+template void launch_jacobi0<float>(int64_t, int, int64_t, const float*, float, const float*, float*, hipStream_t);
+
+void launch_d2f(int64_t n, int ncols, int64_t ld, const double* a, float* b, hipStream_t st) {
+    hipLaunchKernelGGL(k_d2f, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, a, b);
+}
+void launch_f2d(int64_t n, int ncols, int64_t ld, const float* a, double* b, hipStream_t st) {
+    hipLaunchKernelGGL(k_f2d, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, a, b);
+}
+void launch_dot_part(int64_t n, int ncols, int64_t lda, const double* a, int64_t ldb, const double* b, int nparts,
+                     double* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_part, dim3(nparts, ncols), dim3(kBlock), 0, st, n, lda, a, ldb, b, part);
+}
+void launch_sum_parts(int ncols, int64_t nparts, const double* part, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_parts, dim3(ncols), dim3(kBlock), 0, st, nparts, part, out);
+}
+void launch_cg_alpha(int ncols, const double* rz, const double* pq, const int* active, double* alpha, int* flags,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64 * ((ncols + 63) / 64)), 0, st, ncols, rz, pq, active, alpha, flags);
+}
+void launch_cg_beta(int ncols, const double* rz_new, double* rz, const int* active, double* beta, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64 * ((ncols + 63) / 64)), 0, st, ncols, rz_new, rz, active, beta);
+}
+void launch_cg_beta_flex(int ncols, const double* rz_new, const double* rz_cross, double* rz, const int* active,
+                         double* beta, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_beta_flex, dim3(1), dim3(64 * ((ncols + 63) / 64)), 0, st, ncols, rz_new, rz_cross, rz,
+                       active, beta);
+}
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby, dim3(nb1(n)), dim3(kBlock), 0, st, n, a, x, b, y);
+}
+void launch_rsqrt(int ncols, const double* in, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_rsqrt, dim3(1), dim3(64 * ((ncols + 63) / 64)), 0, st, ncols, in, out);
+}
+void launch_cg_update_xr(int64_t n, int ncols, int64_t ld, const double* alpha, const double* p, const double* q,
+                         double* x, double* r, int nparts, double* rr_part, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_update_xr, dim3(nparts, ncols), dim3(kBlock), 0, st, n, ld, alpha, p, q, x, r, rr_part);
+}
+void launch_cg_update_p(int64_t n, int ncols, int64_t ld, const double* beta, const double* z, double* p,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_update_p, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, beta, z, p);
+}
+void launch_copy_cols(int64_t n, int ncols, int64_t lds, const double* s, int64_t ldd, double* d, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_cols, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, lds, s, ldd, d);
+}
+void launch_axpy_cols(int64_t n, int ncols, int64_t ld, const double* coef, double sign, const double* x, double* y,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy_cols, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, coef, sign, x, y);
+}
+void launch_gram_part(int64_t n, int k1, int64_t lda, const double* A, int k2, int64_t ldb, const double* B,
+                      int nparts, double* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_gram_part, dim3(nparts), dim3(256), 0, st, n, k1, lda, A, k2, ldb, B, part);
+}
+void launch_gram_sum(int k1, int k2, int nparts, const double* part, double* out, hipStream_t st) {
+    const int nout = k1 * k2;
+    hipLaunchKernelGGL(k_gram_sum, dim3((nout + 255) / 256), dim3(256), 0, st, nout, nparts, part, out);
+}
+void launch_gemm_small(int64_t n, int k1, int64_t lds, const double* S, int k2, const double* C, int64_t ldy,
+                       double* Y, hipStream_t st) {
+    hipLaunchKernelGGL(k_gemm_small, dim3(nb1(n)), dim3(kBlock), 0, st, n, k1, lds, S, k2, C, ldy, Y);
+}
+void launch_residual_block(int64_t n, int ncols, int64_t ld, const double* AX, const double* KX, const double* mu,
+                           double* R, hipStream_t st) {
+    hipLaunchKernelGGL(k_residual_block, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, AX, KX, mu, R);
+}
+void launch_random_fill(int64_t n, int ncols, int64_t ld, uint64_t seed, const uint8_t* nmask, int dim, double* X,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_random_fill, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, seed, nmask, dim, X);
+}
+void launch_absmax_part(int64_t n, int ncols, int64_t ld, const double* X, int nparts, double* pval, int64_t* pidx,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_absmax_part, dim3(nparts, ncols), dim3(kBlock), 0, st, n, ld, X, pval, pidx);
+}
+void launch_absmax_sum(int ncols, int nparts, const double* pval, const int64_t* pidx, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_absmax_sum, dim3(1), dim3(64 * ((ncols + 63) / 64)), 0, st, ncols, nparts, pval, pidx, out);
+}
+void launch_infnorm_part(int64_t n, int ncols, int64_t ld, const double* X, int nparts, double* part,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_infnorm_part, dim3(nparts, ncols), dim3(kBlock), 0, st, n, ld, X, part);
+}
+void launch_max_parts(int ncols, int nparts, const double* part, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_max_parts, dim3(ncols), dim3(kBlock), 0, st, nparts, part, out);
+}
+void launch_scale_cols(int64_t n, int ncols, int64_t ld, const double* s, double* X, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_cols, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, s, X);
+}
+
+}  // namespace mlb

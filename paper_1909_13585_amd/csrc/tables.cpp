@@ -1,0 +1,196 @@
+// Element and transfer tables of the Q4/H8 discretisation (host, FP64).
+//
+// Sec. 2: K_e = E_kappa(x_e) K_e0 and G_e = E_sigma(x_e) G_e0[u_e].  The
+// element is the bilinear (2D, plane stress, unit thickness) or trilinear
+// (3D) unit square/cube; K_e0 = integral B^T D0 B with 2 Gauss points per
+// axis (exact for these elements); G_e0 uses one stress per element, at the
+// centroid: G_e0 = (sum_ij sigma_ij H^ij) kron I_dim, H^ij = integral of
+// dN/dx_i dN/dx_j^T.  Voigt order: 2D (xx, yy, xy), 3D (xx, yy, zz, xy, yz,
+// xz), engineering shear strains.
+//
+// Galerkin coarsening (Sec. 2.1 step 1): a coarse element of level j+1 holds
+// 2^dim children of level j; child c = cx + 2cy + 4cz.  The child's local
+// node b sits at lattice point c + b (0..2 per axis) of the coarse element,
+// where nodal interpolation gives coarse node A the weight
+//   w = prod_axis w1(p, A),  w1(0,0) = w1(2,1) = 1, w1(1,*) = 1/2, else 0.
+// T[c][b][A] stores it; then K_E = sum_c T_c^T K_c T_c (kron I for vectors).
+#include "tables.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace mlb {
+
+static double shape(int dim, int a, const double* xi) {
+    double v = 1.0;
+    for (int k = 0; k < dim; ++k) {
+        int b = (a >> k) & 1;
+        v *= b ? xi[k] : 1.0 - xi[k];
+    }
+    return v;
+}
+
+static double shape_grad(int dim, int a, int i, const double* xi) {
+    double v = 1.0;
+    for (int k = 0; k < dim; ++k) {
+        int b = (a >> k) & 1;
+        if (k == i) v *= b ? 1.0 : -1.0;
+        else v *= b ? xi[k] : 1.0 - xi[k];
+    }
+    return v;
+}
+
+// Strain-displacement matrix at xi: rows Voigt strains, cols dim*a + c.
+static void strain_disp(int dim, const double* xi, double* B /* nv x nde */) {
+    const int nn = 1 << dim, nde = dim * nn, nv = dim == 2 ? 3 : 6;
+    std::memset(B, 0, sizeof(double) * nv * nde);
+    for (int a = 0; a < nn; ++a) {
+        double g[3];
+        for (int i = 0; i < dim; ++i) g[i] = shape_grad(dim, a, i, xi);
+        if (dim == 2) {
+            B[0 * nde + 2 * a + 0] = g[0];
+            B[1 * nde + 2 * a + 1] = g[1];
+            B[2 * nde + 2 * a + 0] = g[1];
+            B[2 * nde + 2 * a + 1] = g[0];
+        } else {
+            B[0 * nde + 3 * a + 0] = g[0];
+            B[1 * nde + 3 * a + 1] = g[1];
+            B[2 * nde + 3 * a + 2] = g[2];
+            B[3 * nde + 3 * a + 0] = g[1];  // gamma_xy
+            B[3 * nde + 3 * a + 1] = g[0];
+            B[4 * nde + 3 * a + 1] = g[2];  // gamma_yz
+            B[4 * nde + 3 * a + 2] = g[1];
+            B[5 * nde + 3 * a + 0] = g[2];  // gamma_xz
+            B[5 * nde + 3 * a + 2] = g[0];
+        }
+    }
+}
+
+static double interp_w1(int p, int A) {
+    if (p == 1) return 0.5;
+    if (p == 0) return A == 0 ? 1.0 : 0.0;
+    return A == 1 ? 1.0 : 0.0;  // p == 2
+}
+
+void build_tables(int dim, double nu, Tables* t) {
+    std::memset(t, 0, sizeof(Tables));
+    t->dim = dim;
+    const int nn = 1 << dim, nde = dim * nn, nv = dim == 2 ? 3 : 6;
+    t->nn = nn;
+    t->nde = nde;
+    t->nv = nv;
+
+    // unit-modulus constitutive matrix
+    if (dim == 2) {
+        const double s = 1.0 / (1.0 - nu * nu);
+        double D[9] = {s, s * nu, 0, s * nu, s, 0, 0, 0, s * (1.0 - nu) / 2.0};
+        std::memcpy(t->D0, D, sizeof(D));
+    } else {
+        const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        const double mu = 1.0 / (2.0 * (1.0 + nu));
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) t->D0[i * 6 + j] = lam + (i == j ? 2.0 * mu : 0.0);
+        for (int i = 3; i < 6; ++i) t->D0[i * 6 + i] = mu;
+    }
+
+    // Gauss points on [0,1]
+    const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+    const int ngp = 1 << dim;
+    const double wgp = 1.0 / ngp;
+    double B[6 * 24], DB[6 * 24];
+    double Hij[3][3][64];
+    std::memset(Hij, 0, sizeof(Hij));
+    for (int q = 0; q < ngp; ++q) {
+        double xi[3];
+        for (int k = 0; k < dim; ++k) xi[k] = gp[(q >> k) & 1];
+        strain_disp(dim, xi, B);
+        for (int i = 0; i < nv; ++i)
+            for (int j = 0; j < nde; ++j) {
+                double s = 0;
+                for (int k = 0; k < nv; ++k) s += t->D0[i * nv + k] * B[k * nde + j];
+                DB[i * nde + j] = s;
+            }
+        for (int i = 0; i < nde; ++i)
+            for (int j = 0; j < nde; ++j) {
+                double s = 0;
+                for (int k = 0; k < nv; ++k) s += B[k * nde + i] * DB[k * nde + j];
+                t->K0[i * nde + j] += wgp * s;
+            }
+        double g[8][3];
+        for (int a = 0; a < nn; ++a)
+            for (int i = 0; i < dim; ++i) g[a][i] = shape_grad(dim, a, i, xi);
+        for (int i = 0; i < dim; ++i)
+            for (int j = 0; j < dim; ++j)
+                for (int a = 0; a < nn; ++a)
+                    for (int b = 0; b < nn; ++b) Hij[i][j][a * nn + b] += wgp * g[a][i] * g[b][j];
+    }
+    // symmetrise K0 exactly
+    for (int i = 0; i < nde; ++i)
+        for (int j = 0; j < i; ++j) {
+            double v = 0.5 * (t->K0[i * nde + j] + t->K0[j * nde + i]);
+            t->K0[i * nde + j] = t->K0[j * nde + i] = v;
+        }
+    // Voigt-combined gradient products: normal H^ii, shear H^ij + H^ji
+    static const int pairs2[3][2] = {{0, 0}, {1, 1}, {0, 1}};
+    static const int pairs3[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {1, 2}, {0, 2}};
+    for (int k = 0; k < nv; ++k) {
+        int i = dim == 2 ? pairs2[k][0] : pairs3[k][0];
+        int j = dim == 2 ? pairs2[k][1] : pairs3[k][1];
+        for (int ab = 0; ab < nn * nn; ++ab)
+            t->Hk[k * 64 + ab] = (i == j) ? Hij[i][i][ab] : Hij[i][j][ab] + Hij[j][i][ab];
+    }
+    // centroid strain matrix and D0 * Bc
+    double xc[3] = {0.5, 0.5, 0.5};
+    strain_disp(dim, xc, B);
+    for (int i = 0; i < nv * nde; ++i) t->Bc[i] = B[i];
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nde; ++j) {
+            double s = 0;
+            for (int k = 0; k < nv; ++k) s += t->D0[i * nv + k] * B[k * nde + j];
+            t->D0Bc[i * nde + j] = s;
+        }
+
+    // child interpolation weights T[c][b][A]
+    const int nch = 1 << dim;
+    for (int c = 0; c < nch; ++c)
+        for (int b = 0; b < nn; ++b)
+            for (int A = 0; A < nn; ++A) {
+                double w = 1.0;
+                for (int k = 0; k < dim; ++k) {
+                    int p = ((c >> k) & 1) + ((b >> k) & 1);
+                    w *= interp_w1(p, (A >> k) & 1);
+                }
+                t->T[(c * 8 + b) * 8 + A] = w;
+            }
+    // Mc = T_c^T K0 T_c (vector form) and GHc_k = T_c^T H^k T_c (scalar form)
+    for (int c = 0; c < nch; ++c) {
+        for (int A = 0; A < nn; ++A)
+            for (int ca = 0; ca < dim; ++ca)
+                for (int Bn = 0; Bn < nn; ++Bn)
+                    for (int cb = 0; cb < dim; ++cb) {
+                        double s = 0;
+                        for (int b = 0; b < nn; ++b) {
+                            double wa = t->T[(c * 8 + b) * 8 + A];
+                            if (wa == 0.0) continue;
+                            for (int b2 = 0; b2 < nn; ++b2) {
+                                double wb = t->T[(c * 8 + b2) * 8 + Bn];
+                                if (wb == 0.0) continue;
+                                s += wa * wb * t->K0[(b * dim + ca) * nde + b2 * dim + cb];
+                            }
+                        }
+                        t->Mc[(size_t)c * 576 + (A * dim + ca) * nde + Bn * dim + cb] = s;
+                    }
+        for (int k = 0; k < nv; ++k)
+            for (int A = 0; A < nn; ++A)
+                for (int Bn = 0; Bn < nn; ++Bn) {
+                    double s = 0;
+                    for (int b = 0; b < nn; ++b)
+                        for (int b2 = 0; b2 < nn; ++b2)
+                            s += t->T[(c * 8 + b) * 8 + A] * t->T[(c * 8 + b2) * 8 + Bn] *
+                                 t->Hk[k * 64 + b * nn + b2];
+                    t->GHc[((size_t)c * 6 + k) * 64 + A * nn + Bn] = s;
+                }
+    }
+}
+
+}  // namespace mlb
