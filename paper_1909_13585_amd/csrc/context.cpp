@@ -61,6 +61,7 @@ struct mlb_ctx {
     double *dK0 = nullptr, *dHk = nullptr, *dBc = nullptr, *dD0Bc = nullptr, *dD0 = nullptr, *dT = nullptr,
            *dMc = nullptr, *dGHc = nullptr;
     float* fK0 = nullptr;
+    float* fMc = nullptr;
     std::vector<Level> lv;
     int64_t n = 0, m = 0;
     // fine-level problem data
@@ -231,20 +232,34 @@ const float* dinv_of<float>(Level& l) { return l.dinvf; }
 
 // y = A_j x (mode Y), y = r - A_j x (residual), y = x + omega D^-1 (r - A_j x) (Jacobi)
 template <typename T>
+const T* Mc_of(mlb_ctx* c);
+template <>
+const double* Mc_of<double>(mlb_ctx* c) { return c->dMc; }
+template <>
+const float* Mc_of<float>(mlb_ctx* c) { return c->fMc; }
+
+// y = A_j x (mode Y), y = r - A_j x (residual), y = x + omega D^-1 (r - A_j x) (Jacobi).
+// Level 1 is matrix free; level 2 forms its Galerkin element rows on the fly
+// from the fine moduli; deeper levels read stored Galerkin element matrices.
+template <typename T>
 void apply_K(mlb_ctx* c, int j, int nc, const T* x, T* y, int mode, const T* r, double* dot_part) {
     Level& l = c->lv[j - 1];
     if (j == 1)
         launch_apply_fine<T>(c->dim, l.g, E_of<T>(c), l.nmask, K0_of<T>(c), nc, l.n, x, y, mode, r,
                              dinv_of<T>(l), (T)l.omega, dot_part, c->st);
+    else if (j == 2)
+        launch_apply_coarse<T>(c->dim, l.g, c->lv[0].g, kSrcChildE, nullptr, E_of<T>(c), Mc_of<T>(c), l.nmask, nc,
+                               l.n, x, y, mode, r, dinv_of<T>(l), (T)l.omega, c->st);
     else
-        launch_apply_dense<T>(c->dim, l.g, Ke_of<T>(l), false, l.nmask, nc, l.n, x, y, mode, r, dinv_of<T>(l),
-                              (T)l.omega, c->st);
+        launch_apply_coarse<T>(c->dim, l.g, l.g, kSrcDense, Ke_of<T>(l), nullptr, nullptr, l.nmask, nc, l.n, x, y,
+                               mode, r, dinv_of<T>(l), (T)l.omega, c->st);
 }
 
 void apply_G(mlb_ctx* c, int j, int nc, const double* x, double* y) {
     Level& l = c->lv[j - 1];
     if (j == 1) launch_apply_G_fine(c->dim, l.g, c->S, l.nmask, c->dHk, nc, l.n, x, y, c->st);
-    else launch_apply_dense<double>(c->dim, l.g, c->Gl, true, l.nmask, nc, l.n, x, y, kModeY, nullptr, nullptr, 0.0, c->st);
+    else launch_apply_coarse<double>(c->dim, l.g, l.g, kSrcKron, c->Gl, nullptr, nullptr, l.nmask, nc, l.n, x, y,
+                                     kModeY, nullptr, nullptr, 0.0, c->st);
 }
 
 template <typename T>
@@ -275,13 +290,18 @@ void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z) {
         apply_K<T>(c, j, nc, a, b, kModeJacobi, r, nullptr);
         std::swap(a, b);
     }
-    apply_K<T>(c, j, nc, a, t, kModeResidual, r, nullptr);
     Level& lc = c->lv[j];
     T* rc = lbuf<T>(lc, 0);
     T* zc = lbuf<T>(lc, 1);
-    launch_restrict<T>(c->dim, l.g, lc.g, l.nmask, lc.nmask, nc, l.n, lc.n, t, rc, c->st);
-    vcycle<T>(c, j + 1, nc, rc, zc);
-    launch_prolong<T>(c->dim, l.g, lc.g, l.nmask, lc.nmask, nc, l.n, lc.n, zc, a, true, c->st);
+    // gamma coarse-grid corrections (1: V-cycle, 2: W-cycle; the coarsest
+    // solve is exact, so one visit suffices just above it)
+    const int gamma = (j + 1 == c->L) ? 1 : std::max(1, c->o.cycle);
+    for (int gi = 0; gi < gamma; ++gi) {
+        apply_K<T>(c, j, nc, a, t, kModeResidual, r, nullptr);
+        launch_restrict<T>(c->dim, l.g, lc.g, l.nmask, lc.nmask, nc, l.n, lc.n, t, rc, c->st);
+        vcycle<T>(c, j + 1, nc, rc, zc);
+        launch_prolong<T>(c->dim, l.g, lc.g, l.nmask, lc.nmask, nc, l.n, lc.n, zc, a, true, c->st);
+    }
     for (int s = 0; s < nu; ++s) {
         apply_K<T>(c, j, nc, a, b, kModeJacobi, r, nullptr);
         std::swap(a, b);
@@ -398,6 +418,11 @@ int pcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, 
                     nact += act[i];
                 }
                 HIPC(hipMemcpyAsync(active, act.data(), sizeof(int) * nc, hipMemcpyHostToDevice, c->st));
+                if (std::getenv("MLB_VERBOSE") && (it % 10 == 0 || nact == 0)) {
+                    double w = 0.0;
+                    for (int i = 0; i < nc; ++i) w = std::max(w, hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0);
+                    std::fprintf(stderr, "[mlb] pcg it %d worst rel %.3e active %d\n", it, w, nact);
+                }
                 if (nact == 0) break;
             }
             if (flex) dots(c, n, nc, c->R, c->Zb, sc(c, 8));   // r_{k+1} . z_k for the flexible beta
@@ -476,7 +501,7 @@ int build_hierarchy(mlb_ctx* c) {
         Level& lc = c->lv[j - 1];
         if (j == 2) launch_galerkin_from_E(dim, lf.g, lc.g, c->Ek, c->dMc, lc.Ke, c->st);
         else launch_galerkin_dense(dim, false, lf.g, lc.g, lf.Ke, c->dT, lc.Ke, c->st);
-        launch_to_float(lc.g.m * c->nde * c->nde, lc.Ke, lc.Kef, c->st);
+        if (j > 2) launch_to_float(lc.g.m * c->nde * c->nde, lc.Ke, lc.Kef, c->st);
         launch_dinv_dense(dim, lc.g, lc.Ke, lc.nmask, lc.dinv, lc.dinvf, c->st);
     }
     for (int j = 1; j < c->L; ++j) CHK(estimate_omega(c, j));
@@ -938,6 +963,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     c->o.eig_max_it = 400;
     c->o.check_every = 1;
     c->o.seed = 1;
+    c->o.cycle = 2;
     const int dim = desc->dim;
     auto bad = [&](const std::string& m) {
         c->err = m;
@@ -982,6 +1008,12 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     CHK(dalloc(c, &c->dGHc, 8 * 6 * 64));
     float k0f[576];
     for (int i = 0; i < 576; ++i) k0f[i] = (float)c->tab.K0[i];
+    CHK(dalloc(c, &c->fMc, 8 * 576));
+    {
+        std::vector<float> mcf(8 * 576);
+        for (int i = 0; i < 8 * 576; ++i) mcf[i] = (float)c->tab.Mc[i];
+        HIPC(hipMemcpy(c->fMc, mcf.data(), sizeof(float) * mcf.size(), hipMemcpyHostToDevice));
+    }
     HIPC(hipMemcpy(c->dK0, c->tab.K0, sizeof(double) * 576, hipMemcpyHostToDevice));
     HIPC(hipMemcpy(c->fK0, k0f, sizeof(float) * 576, hipMemcpyHostToDevice));
     HIPC(hipMemcpy(c->dHk, c->tab.Hk, sizeof(double) * 6 * 64, hipMemcpyHostToDevice));
@@ -1003,10 +1035,8 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
         HIPC(hipMemset(l.nmask, 0, (size_t)l.g.nodes));
         CHK(dalloc(c, &l.dinv, (size_t)l.n));
         CHK(dalloc(c, &l.dinvf, (size_t)l.n));
-        if (j > 0) {
-            CHK(dalloc(c, &l.Ke, (size_t)l.g.m * c->nde * c->nde));
-            CHK(dalloc(c, &l.Kef, (size_t)l.g.m * c->nde * c->nde));
-        }
+        if (j > 0) CHK(dalloc(c, &l.Ke, (size_t)l.g.m * c->nde * c->nde));
+        if (j > 1) CHK(dalloc(c, &l.Kef, (size_t)l.g.m * c->nde * c->nde));
     }
     c->n = c->lv[0].n;
     c->m = c->lv[0].g.m;
@@ -1048,7 +1078,7 @@ void mlb_destroy(mlb_ctx* c) {
         dfree(l.vr); dfree(l.vz); dfree(l.vz2); dfree(l.vt); dfree(l.fr); dfree(l.fz); dfree(l.fz2); dfree(l.ft);
     }
     dfree(c->dK0); dfree(c->fK0); dfree(c->dHk); dfree(c->dBc); dfree(c->dD0Bc); dfree(c->dD0); dfree(c->dT);
-    dfree(c->dMc); dfree(c->dGHc); dfree(c->x); dfree(c->Ek); dfree(c->Ekf); dfree(c->Es); dfree(c->fixed);
+    dfree(c->dMc); dfree(c->fMc); dfree(c->dGHc); dfree(c->x); dfree(c->Ek); dfree(c->Ekf); dfree(c->Es); dfree(c->fixed);
     dfree(c->F); dfree(c->U); dfree(c->S); dfree(c->Gl); dfree(c->Ainv); dfree(c->gj_r0); dfree(c->gj_c0);
     dfree(c->gj_r1); dfree(c->gj_c1); dfree(c->R); dfree(c->Zb); dfree(c->Pb); dfree(c->Qb); dfree(c->Zo);
     dfree(c->X1); dfree(c->X2); dfree(c->Phi); dfree(c->Zadj); dfree(c->dlam_l); dfree(c->eS); dfree(c->eK);
@@ -1069,6 +1099,7 @@ int mlb_set_opts(mlb_ctx* c, const mlb_opts* o) {
     if (o->eig_max_it > 0) c->o.eig_max_it = o->eig_max_it;
     if (o->check_every > 0) c->o.check_every = o->check_every;
     if (o->seed > 0) c->o.seed = o->seed;
+    if (o->cycle > 0) c->o.cycle = std::min(o->cycle, 2);
     if (o->jacobi_omega > 0 && c->has_density) {
         c->st = c->own;
         for (int j = 1; j < c->L; ++j) CHK(estimate_omega(c, j));

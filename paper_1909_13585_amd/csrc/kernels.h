@@ -11,10 +11,11 @@ template <typename T>
 void launch_apply_fine(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* K0, int ncols,
                        int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega,
                        double* dot_part, hipStream_t st);
+enum { kSrcDense = 0, kSrcKron = 1, kSrcChildE = 2 };
 template <typename T>
-void launch_apply_dense(int dim, const Geo& g, const T* Ke, bool kron, const uint8_t* nmask, int ncols,
-                        int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega,
-                        hipStream_t st);
+void launch_apply_coarse(int dim, const Geo& g, const Geo& gfine, int src, const T* Ke, const T* Efine,
+                         const T* Mc, const uint8_t* nmask, int ncols, int64_t ld, const T* x, T* y, int mode,
+                         const T* r, const T* dinv, T omega, hipStream_t st);
 void launch_apply_G_fine(int dim, const Geo& g, const double* S, const uint8_t* nmask, const double* Hk,
                          int ncols, int64_t ld, const double* x, double* y, hipStream_t st);
 void launch_dinv_fine(int dim, const Geo& g, const double* E, const uint8_t* nmask, const double* K0,

@@ -81,8 +81,12 @@ __device__ inline T epilogue(T ax, T xown, T rr, T di, T omega) {
 
 // ---------------------------------------------------------------------------
 // Level-1 stiffness apply, matrix free: y = sum_e E_e P_e^T K0 P_e x.
+// K0 is staged in LDS (uniform-address broadcast reads).  The 3^dim
+// neighbours are visited once each; every neighbour feeds the element slots
+// that contain it.  Columns are processed in chunks of CB so that each K0
+// entry is read once per chunk.
 
-template <int DIM, typename T, int MODE, bool DOT>
+template <int DIM, typename T, int MODE, bool DOT, int CB>
 __global__ __launch_bounds__(256) void k_apply_fine(Geo g, const T* __restrict__ E,
                                                     const uint8_t* __restrict__ nmask,
                                                     const T* __restrict__ K0, int ncols, int64_t ld,
@@ -90,16 +94,19 @@ __global__ __launch_bounds__(256) void k_apply_fine(Geo g, const T* __restrict__
                                                     const T* __restrict__ r, const T* __restrict__ dinv,
                                                     T omega, double* __restrict__ part) {
     using N = Nb<DIM>;
+    __shared__ T k0s[N::NDE * N::NDE];
     __shared__ double sh[16];
+    {
+        const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+        for (int q = tid; q < N::NDE * N::NDE; q += blockDim.x * blockDim.y) k0s[q] = K0[q];
+    }
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k = DIM == 3 ? blockIdx.z : 0;
     const bool active = i < g.nnx && j < g.nny;
     const int ic = active ? i : 0, jc = active ? j : 0;
     const int64_t node = ic + (int64_t)g.nnx * (jc + (int64_t)g.nny * k);
-    int64_t idx[N::NB];
-    uint8_t msk[N::NB];
-    neighbourhood<DIM>(g, ic, jc, k, nmask, idx, msk);
     T Ee[N::NN];
 #pragma unroll
     for (int s = 0; s < N::NN; ++s) {
@@ -107,127 +114,182 @@ __global__ __launch_bounds__(256) void k_apply_fine(Geo g, const T* __restrict__
         const int64_t e = elem_of_slot<DIM>(g, ic, jc, k, s, ok);
         Ee[s] = ok ? E[e] : T(0);
     }
-    const uint8_t own = msk[N::slot(0, 0, 0)];
+    const uint8_t own = nmask[node];
     const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
     const int64_t nblk = (int64_t)gridDim.x * gridDim.y * gridDim.z;
-    for (int col = 0; col < ncols; ++col) {
-        const T* xc = x + col * ld;
-        T xv[N::NB][N::ND];
+    for (int c0 = 0; c0 < ncols; c0 += CB) {
+        T tmp[N::NN][CB][N::ND];
 #pragma unroll
-        for (int t = 0; t < N::NB; ++t)
+        for (int s = 0; s < N::NN; ++s)
 #pragma unroll
-            for (int c = 0; c < N::ND; ++c)
-                xv[t][c] = (msk[t] >> c) & 1 ? T(0) : xc[idx[t] * N::ND + c];
-        T acc[N::ND];
+            for (int q = 0; q < CB; ++q)
 #pragma unroll
-        for (int c = 0; c < N::ND; ++c) acc[c] = T(0);
+                for (int c = 0; c < N::ND; ++c) tmp[s][q][c] = T(0);
+        // runtime loop over neighbours (wave-uniform), compile-time slots
+#pragma unroll 1
+        for (int t = 0; t < N::NB; ++t) {
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+            const int ii = ic + dx, jj = jc + dy, kk = k + dz;
+            const bool ok = ii >= 0 && ii < g.nnx && jj >= 0 && jj < g.nny && kk >= 0 && kk < g.nnz;
+            const int64_t nn = ok ? ii + (int64_t)g.nnx * (jj + (int64_t)g.nny * kk) : 0;
+            const uint8_t mb = ok ? nmask[nn] : (uint8_t)0xff;
+            T xv[CB][N::ND];
 #pragma unroll
-        for (int s = 0; s < N::NN; ++s) {
-            const int ox = s & 1, oy = (s >> 1) & 1, oz = (s >> 2) & 1;
-            const int a = (N::NN - 1) ^ s;   // local index of this node in element slot s
-            T t[N::ND];
+            for (int q = 0; q < CB; ++q)
 #pragma unroll
-            for (int c = 0; c < N::ND; ++c) t[c] = T(0);
+                for (int c = 0; c < N::ND; ++c)
+                    xv[q][c] = ((mb >> c) & 1) || (c0 + q >= ncols) ? T(0) : x[(c0 + q) * ld + nn * N::ND + c];
+            // element slots s = (ox,oy,oz) containing this neighbour: ox in {dx, dx+1} ∩ {0,1}
 #pragma unroll
-            for (int b = 0; b < N::NN; ++b) {
-                const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-                const int ts = N::slot(ox - 1 + bx, oy - 1 + by, DIM == 3 ? oz - 1 + bz : 0);
+            for (int s = 0; s < N::NN; ++s) {
+                const int ox = s & 1, oy = (s >> 1) & 1, oz = (s >> 2) & 1;
+                const int bx = dx + 1 - ox, by = dy + 1 - oy, bz = DIM == 3 ? dz + 1 - oz : 0;
+                if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+                const int b = bx + 2 * by + 4 * bz;
+                const int a = (N::NN - 1) ^ s;
 #pragma unroll
                 for (int c = 0; c < N::ND; ++c)
 #pragma unroll
-                    for (int c2 = 0; c2 < N::ND; ++c2)
-                        t[c] += K0[(a * N::ND + c) * N::NDE + b * N::ND + c2] * xv[ts][c2];
-            }
+                    for (int c2 = 0; c2 < N::ND; ++c2) {
+                        const T kv = k0s[(a * N::ND + c) * N::NDE + b * N::ND + c2];
 #pragma unroll
-            for (int c = 0; c < N::ND; ++c) acc[c] += Ee[s] * t[c];
-        }
-        double dsum = 0.0;
-        if (active) {
-#pragma unroll
-            for (int c = 0; c < N::ND; ++c) {
-                const int64_t d = node * N::ND + c;
-                const T xown = xc[d];
-                const T ax = (own >> c) & 1 ? xown : acc[c];
-                const T rr = MODE == kModeY ? T(0) : r[col * ld + d];
-                const T di = MODE == kModeJacobi ? dinv[d] : T(0);
-                y[col * ld + d] = epilogue<T, MODE>(ax, xown, rr, di, omega);
-                if (DOT) dsum += (double)xown * (double)ax;
+                        for (int q = 0; q < CB; ++q) tmp[s][q][c] += kv * xv[q][c2];
+                    }
             }
         }
-        if (DOT) {
-            const double bs = block_sum(dsum, sh);
-            if (threadIdx.x == 0 && threadIdx.y == 0) part[col * nblk + blk] = bs;
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+            double dsum = 0.0;
+            if (active && c0 + q < ncols) {
+                const int col = c0 + q;
+#pragma unroll
+                for (int c = 0; c < N::ND; ++c) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int s = 0; s < N::NN; ++s) acc += Ee[s] * tmp[s][q][c];
+                    const int64_t d = node * N::ND + c;
+                    const T xown = x[col * ld + d];
+                    const T ax = (own >> c) & 1 ? xown : acc;
+                    const T rr = MODE == kModeY ? T(0) : r[col * ld + d];
+                    const T di = MODE == kModeJacobi ? dinv[d] : T(0);
+                    y[col * ld + d] = epilogue<T, MODE>(ax, xown, rr, di, omega);
+                    if (DOT) dsum += (double)xown * (double)ax;
+                }
+            }
+            if (DOT) {
+                const double bs = block_sum(dsum, sh);
+                if (threadIdx.x == 0 && threadIdx.y == 0 && c0 + q < ncols) part[(c0 + q) * nblk + blk] = bs;
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Coarse-level apply from dense per-element matrices (SoA: entry-major,
-// stride m).  KRON: scalar nn x nn matrices acting on each component (G).
+// Coarse-level applies.  SRC selects where the element matrix entries come
+// from:
+//   kSrcDense   dense per-element matrices (SoA, entry-major, stride m);
+//   kSrcKron    dense scalar nn x nn matrices acting on each component (G);
+//   kSrcChildE  level 2 on the fly: K_E = sum_c E_c Mc[c] from the fine-level
+//               moduli of the 2^dim children (Mc = T_c^T K0 T_c, in LDS).
+// Column chunks of CB reuse every matrix entry.
 
-template <int DIM, typename T, int MODE, bool KRON>
-__global__ __launch_bounds__(256) void k_apply_dense(Geo g, const T* __restrict__ Ke,
-                                                     const uint8_t* __restrict__ nmask, int ncols,
-                                                     int64_t ld, const T* __restrict__ x,
-                                                     T* __restrict__ y, const T* __restrict__ r,
-                                                     const T* __restrict__ dinv, T omega) {
+template <int DIM, typename T, int MODE, int SRC, int CB>
+__global__ __launch_bounds__(256) void k_apply_coarse(Geo g, Geo gfine, const T* __restrict__ Ke,
+                                                      const T* __restrict__ Efine, const T* __restrict__ Mc,
+                                                      const uint8_t* __restrict__ nmask, int ncols,
+                                                      int64_t ld, const T* __restrict__ x, T* __restrict__ y,
+                                                      const T* __restrict__ r, const T* __restrict__ dinv,
+                                                      T omega) {
     using N = Nb<DIM>;
+    constexpr int NM = SRC == kSrcChildE ? (1 << DIM) * N::NDE * N::NDE : 1;
+    __shared__ T mcs[NM];
+    if (SRC == kSrcChildE) {
+        const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+        for (int q = tid; q < NM; q += blockDim.x * blockDim.y) {
+            const int ch = q / (N::NDE * N::NDE), ent = q % (N::NDE * N::NDE);
+            mcs[q] = Mc[ch * 576 + ent];
+        }
+        __syncthreads();
+    }
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k = DIM == 3 ? blockIdx.z : 0;
     if (i >= g.nnx || j >= g.nny) return;
     const int64_t node = i + (int64_t)g.nnx * (j + (int64_t)g.nny * k);
-    int64_t idx[N::NB];
-    uint8_t msk[N::NB];
-    neighbourhood<DIM>(g, i, j, k, nmask, idx, msk);
-    int64_t es[N::NN];
-    bool eok[N::NN];
-#pragma unroll
-    for (int s = 0; s < N::NN; ++s) es[s] = elem_of_slot<DIM>(g, i, j, k, s, eok[s]);
-    const uint8_t own = msk[N::slot(0, 0, 0)];
+    const uint8_t own = nmask[node];
     const int64_t m = g.m;
-    for (int col = 0; col < ncols; ++col) {
-        const T* xc = x + col * ld;
-        T xv[N::NB][N::ND];
+    for (int c0 = 0; c0 < ncols; c0 += CB) {
+        T acc[CB][N::ND];
 #pragma unroll
-        for (int t = 0; t < N::NB; ++t)
+        for (int q = 0; q < CB; ++q)
 #pragma unroll
-            for (int c = 0; c < N::ND; ++c)
-                xv[t][c] = (msk[t] >> c) & 1 ? T(0) : xc[idx[t] * N::ND + c];
-        T acc[N::ND];
-#pragma unroll
-        for (int c = 0; c < N::ND; ++c) acc[c] = T(0);
-#pragma unroll
+            for (int c = 0; c < N::ND; ++c) acc[q][c] = T(0);
         for (int s = 0; s < N::NN; ++s) {
-            if (!eok[s]) continue;
+            bool eok;
+            const int64_t e = elem_of_slot<DIM>(g, i, j, k, s, eok);
+            if (!eok) continue;
             const int ox = s & 1, oy = (s >> 1) & 1, oz = (s >> 2) & 1;
             const int a = (N::NN - 1) ^ s;
-            const T* Kb = Ke + es[s];
+            T Ech[1 << DIM];
+            if (SRC == kSrcChildE) {
+                const int ei = i - 1 + ox, ej = j - 1 + oy, ek = DIM == 3 ? k - 1 + oz : 0;
 #pragma unroll
+                for (int ch = 0; ch < (1 << DIM); ++ch)
+                    Ech[ch] = Efine[(2 * ei + (ch & 1)) +
+                                    (int64_t)gfine.nx * ((2 * ej + ((ch >> 1) & 1)) + (int64_t)gfine.ny * (2 * ek + ((ch >> 2) & 1)))];
+            }
+#pragma unroll 2
             for (int b = 0; b < N::NN; ++b) {
                 const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-                const int ts = N::slot(ox - 1 + bx, oy - 1 + by, DIM == 3 ? oz - 1 + bz : 0);
-                if (KRON) {
-                    const T gv = Kb[(int64_t)(a * N::NN + b) * m];
+                const int ii = i - 1 + ox + bx, jj = j - 1 + oy + by, kk = DIM == 3 ? k - 1 + oz + bz : 0;
+                const int64_t nn = ii + (int64_t)g.nnx * (jj + (int64_t)g.nny * kk);
+                const uint8_t mb = nmask[nn];
+                T xv[CB][N::ND];
 #pragma unroll
-                    for (int c = 0; c < N::ND; ++c) acc[c] += gv * xv[ts][c];
+                for (int q = 0; q < CB; ++q)
+#pragma unroll
+                    for (int c = 0; c < N::ND; ++c)
+                        xv[q][c] = ((mb >> c) & 1) || (c0 + q >= ncols) ? T(0) : x[(c0 + q) * ld + nn * N::ND + c];
+                if (SRC == kSrcKron) {
+                    const T gv = Ke[(int64_t)(a * N::NN + b) * m + e];
+#pragma unroll
+                    for (int q = 0; q < CB; ++q)
+#pragma unroll
+                        for (int c = 0; c < N::ND; ++c) acc[q][c] += gv * xv[q][c];
                 } else {
 #pragma unroll
                     for (int c = 0; c < N::ND; ++c)
 #pragma unroll
-                        for (int c2 = 0; c2 < N::ND; ++c2)
-                            acc[c] += Kb[(int64_t)((a * N::ND + c) * N::NDE + b * N::ND + c2) * m] * xv[ts][c2];
+                        for (int c2 = 0; c2 < N::ND; ++c2) {
+                            const int ent = (a * N::ND + c) * N::NDE + b * N::ND + c2;
+                            T kv;
+                            if (SRC == kSrcDense) {
+                                kv = Ke[(int64_t)ent * m + e];
+                            } else {
+                                kv = T(0);
+#pragma unroll
+                                for (int ch = 0; ch < (1 << DIM); ++ch)
+                                    kv += Ech[ch] * mcs[ch * N::NDE * N::NDE + ent];
+                            }
+#pragma unroll
+                            for (int q = 0; q < CB; ++q) acc[q][c] += kv * xv[q][c2];
+                        }
                 }
             }
         }
 #pragma unroll
-        for (int c = 0; c < N::ND; ++c) {
-            const int64_t d = node * N::ND + c;
-            const T xown = xc[d];
-            const T ax = (own >> c) & 1 ? (KRON ? T(0) : xown) : acc[c];
-            const T rr = MODE == kModeY ? T(0) : r[col * ld + d];
-            const T di = MODE == kModeJacobi ? dinv[d] : T(0);
-            y[col * ld + d] = epilogue<T, MODE>(ax, xown, rr, di, omega);
+        for (int q = 0; q < CB; ++q) {
+            if (c0 + q >= ncols) continue;
+            const int col = c0 + q;
+#pragma unroll
+            for (int c = 0; c < N::ND; ++c) {
+                const int64_t d = node * N::ND + c;
+                const T xown = x[col * ld + d];
+                const T ax = (own >> c) & 1 ? (SRC == kSrcKron ? T(0) : xown) : acc[q][c];
+                const T rr = MODE == kModeY ? T(0) : r[col * ld + d];
+                const T di = MODE == kModeJacobi ? dinv[d] : T(0);
+                y[col * ld + d] = epilogue<T, MODE>(ax, xown, rr, di, omega);
+            }
         }
     }
 }
@@ -453,45 +515,50 @@ void launch_apply_fine(int dim, const Geo& g, const T* E, const uint8_t* nmask, 
                        double* dot_part, hipStream_t st) {
     dim3 b;
     dim3 gr = node_grid(g, b);
-#define MLB_LAUNCH(D, M, DOT)                                                                     \
-    hipLaunchKernelGGL((k_apply_fine<D, T, M, DOT>), gr, b, 0, st, g, E, nmask, K0, ncols, ld, x, y, r, \
+#define MLB_LAUNCH(D, M, DOT, CB)                                                                         \
+    hipLaunchKernelGGL((k_apply_fine<D, T, M, DOT, CB>), gr, b, 0, st, g, E, nmask, K0, ncols, ld, x, y, r, \
                        dinv, omega, dot_part)
+#define MLB_MODES(D, CB)                                                       \
+    if (mode == kModeY && dot_part) MLB_LAUNCH(D, kModeY, true, CB);           \
+    else if (mode == kModeY) MLB_LAUNCH(D, kModeY, false, CB);                 \
+    else if (mode == kModeResidual) MLB_LAUNCH(D, kModeResidual, false, CB);   \
+    else MLB_LAUNCH(D, kModeJacobi, false, CB);
     if (dim == 2) {
-        if (mode == kModeY && dot_part) MLB_LAUNCH(2, kModeY, true);
-        else if (mode == kModeY) MLB_LAUNCH(2, kModeY, false);
-        else if (mode == kModeResidual) MLB_LAUNCH(2, kModeResidual, false);
-        else MLB_LAUNCH(2, kModeJacobi, false);
+        if (ncols == 1) { MLB_MODES(2, 1) } else { MLB_MODES(2, 4) }
     } else {
-        if (mode == kModeY && dot_part) MLB_LAUNCH(3, kModeY, true);
-        else if (mode == kModeY) MLB_LAUNCH(3, kModeY, false);
-        else if (mode == kModeResidual) MLB_LAUNCH(3, kModeResidual, false);
-        else MLB_LAUNCH(3, kModeJacobi, false);
+        if (ncols == 1) { MLB_MODES(3, 1) } else { MLB_MODES(3, 2) }
     }
+#undef MLB_MODES
 #undef MLB_LAUNCH
 }
 
 template <typename T>
-void launch_apply_dense(int dim, const Geo& g, const T* Ke, bool kron, const uint8_t* nmask, int ncols,
-                        int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega,
-                        hipStream_t st) {
+void launch_apply_coarse(int dim, const Geo& g, const Geo& gfine, int src, const T* Ke, const T* Efine,
+                         const T* Mc, const uint8_t* nmask, int ncols, int64_t ld, const T* x, T* y, int mode,
+                         const T* r, const T* dinv, T omega, hipStream_t st) {
     dim3 b;
     dim3 gr = node_grid(g, b);
-#define MLB_LAUNCH(D, M, KR) \
-    hipLaunchKernelGGL((k_apply_dense<D, T, M, KR>), gr, b, 0, st, g, Ke, nmask, ncols, ld, x, y, r, dinv, omega)
-    if (kron) {
-        if (dim == 2) MLB_LAUNCH(2, kModeY, true);
-        else MLB_LAUNCH(3, kModeY, true);
-        return;
-    }
+#define MLB_LAUNCH(D, M, S, CB)                                                                           \
+    hipLaunchKernelGGL((k_apply_coarse<D, T, M, S, CB>), gr, b, 0, st, g, gfine, Ke, Efine, Mc, nmask, ncols, \
+                       ld, x, y, r, dinv, omega)
+#define MLB_MODES(D, S, CB)                                                     \
+    if (mode == kModeY) MLB_LAUNCH(D, kModeY, S, CB);                           \
+    else if (mode == kModeResidual) MLB_LAUNCH(D, kModeResidual, S, CB);        \
+    else MLB_LAUNCH(D, kModeJacobi, S, CB);
+#define MLB_CB(D, S)                                \
+    if (ncols == 1) { MLB_MODES(D, S, 1) }          \
+    else { MLB_MODES(D, S, 4) }
     if (dim == 2) {
-        if (mode == kModeY) MLB_LAUNCH(2, kModeY, false);
-        else if (mode == kModeResidual) MLB_LAUNCH(2, kModeResidual, false);
-        else MLB_LAUNCH(2, kModeJacobi, false);
+        if (src == kSrcKron) { if (ncols == 1) MLB_LAUNCH(2, kModeY, kSrcKron, 1); else MLB_LAUNCH(2, kModeY, kSrcKron, 4); }
+        else if (src == kSrcChildE) { MLB_CB(2, kSrcChildE) }
+        else { MLB_CB(2, kSrcDense) }
     } else {
-        if (mode == kModeY) MLB_LAUNCH(3, kModeY, false);
-        else if (mode == kModeResidual) MLB_LAUNCH(3, kModeResidual, false);
-        else MLB_LAUNCH(3, kModeJacobi, false);
+        if (src == kSrcKron) { if (ncols == 1) MLB_LAUNCH(3, kModeY, kSrcKron, 1); else MLB_LAUNCH(3, kModeY, kSrcKron, 4); }
+        else if (src == kSrcChildE) { MLB_CB(3, kSrcChildE) }
+        else { MLB_CB(3, kSrcDense) }
     }
+#undef MLB_CB
+#undef MLB_MODES
 #undef MLB_LAUNCH
 }
 
@@ -548,12 +615,12 @@ template void launch_apply_fine<double>(int, const Geo&, const double*, const ui
 template void launch_apply_fine<float>(int, const Geo&, const float*, const uint8_t*, const float*, int,
                                        int64_t, const float*, float*, int, const float*, const float*, float,
                                        double*, hipStream_t);
-template void launch_apply_dense<double>(int, const Geo&, const double*, bool, const uint8_t*, int, int64_t,
-                                         const double*, double*, int, const double*, const double*, double,
-                                         hipStream_t);
-template void launch_apply_dense<float>(int, const Geo&, const float*, bool, const uint8_t*, int, int64_t,
-                                        const float*, float*, int, const float*, const float*, float,
-                                        hipStream_t);
+template void launch_apply_coarse<double>(int, const Geo&, const Geo&, int, const double*, const double*,
+                                          const double*, const uint8_t*, int, int64_t, const double*, double*, int,
+                                          const double*, const double*, double, hipStream_t);
+template void launch_apply_coarse<float>(int, const Geo&, const Geo&, int, const float*, const float*,
+                                         const float*, const uint8_t*, int, int64_t, const float*, float*, int,
+                                         const float*, const float*, float, hipStream_t);
 template void launch_prolong<double>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
                                      int64_t, const double*, double*, bool, hipStream_t);
 template void launch_prolong<float>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
