@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--modes", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the dominant-kernel timing and a copy of known size (for counter runs)")
     return ap.parse_args()
 
 
@@ -97,6 +99,18 @@ def main():
         lam, ei = ctx.buckling_dev(k, Phi, tol_eig=1e-10)
         ai = ctx.sensitivities_dev(dJ, dlam)
         return J, si, lam, ei, ai
+
+    if args.roofline_only:
+        ctx.set_density_dev(x_dev)
+        xa = torch.randn(n, dtype=torch.float64, device="cuda")
+        ya = torch.empty_like(xa)
+        for _ in range(args.apply_reps):
+            ctx.apply_K_dev(1, xa, ya)
+        ya.copy_(xa)   # calibration: reads and writes exactly 8 n bytes each
+        torch.cuda.synchronize()
+        print(json.dumps({"roofline_only": True, "n": n, "m": m, "copy_bytes": 8 * n}), flush=True)
+        ctx.close()
+        return
 
     for w in range(args.warmup):
         out = step()

@@ -92,7 +92,7 @@ typedef struct {
     int eig_max_it;       /* coarse eigensolver iteration limit (default 400) */
     int check_every;      /* CG iterations between host convergence checks (default 1) */
     uint64_t seed;        /* seed of the coarse eigensolver start block (default 1) */
-    int cycle;            /* coarse-grid visits per level: 1 = V-cycle, 2 = W-cycle (default 2) */
+    int cycle;            /* coarse-grid visits per level: 1 = V-cycle, 2 = W-cycle (default 1) */
 } mlb_opts;
 
 /* Per-call solver report; for blocks, the worst column is reported. */

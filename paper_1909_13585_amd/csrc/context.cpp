@@ -62,6 +62,8 @@ struct mlb_ctx {
            *dMc = nullptr, *dGHc = nullptr;
     float* fK0 = nullptr;
     float* fMc = nullptr;
+    bool level2_on_the_fly = false;   // level-2 rows from the fine moduli (no stored matrices read)
+    float whtf[72] = {};   // FP32 copy of the Walsh-Hadamard blocks (host; passed by value)
     std::vector<Level> lv;
     int64_t n = 0, m = 0;
     // fine-level problem data
@@ -232,6 +234,18 @@ const float* dinv_of<float>(Level& l) { return l.dinvf; }
 
 // y = A_j x (mode Y), y = r - A_j x (residual), y = x + omega D^-1 (r - A_j x) (Jacobi)
 template <typename T>
+const T* wht_of(mlb_ctx* c);
+template <>
+const double* wht_of<double>(mlb_ctx* c) { return c->tab.wht; }
+template <>
+const float* wht_of<float>(mlb_ctx* c) { return c->whtf; }
+
+// partial-sum blocks written by the level-1 apply with a fused dot product
+int64_t fine_apply_blocks(mlb_ctx* c) {
+    return c->tab.wht_ok ? apply_wht_blocks(c->dim, c->lv[0].g) : apply_fine_blocks(c->lv[0].g);
+}
+
+template <typename T>
 const T* Mc_of(mlb_ctx* c);
 template <>
 const double* Mc_of<double>(mlb_ctx* c) { return c->dMc; }
@@ -241,13 +255,20 @@ const float* Mc_of<float>(mlb_ctx* c) { return c->fMc; }
 // y = A_j x (mode Y), y = r - A_j x (residual), y = x + omega D^-1 (r - A_j x) (Jacobi).
 // Level 1 is matrix free; level 2 forms its Galerkin element rows on the fly
 // from the fine moduli; deeper levels read stored Galerkin element matrices.
+// `clean`: x is zero at every Dirichlet DOF (always true inside the solvers,
+// whose vectors never leave the free subspace), so the level-1 kernel may
+// skip masking its inputs.
 template <typename T>
-void apply_K(mlb_ctx* c, int j, int nc, const T* x, T* y, int mode, const T* r, double* dot_part) {
+void apply_K(mlb_ctx* c, int j, int nc, const T* x, T* y, int mode, const T* r, double* dot_part,
+             bool clean = true) {
     Level& l = c->lv[j - 1];
-    if (j == 1)
+    if (j == 1 && c->tab.wht_ok)
+        launch_apply_wht<T>(c->dim, l.g, E_of<T>(c), l.nmask, wht_of<T>(c), nc, l.n, x, y, mode, r, dinv_of<T>(l),
+                            (T)l.omega, dot_part, clean, c->st);
+    else if (j == 1)
         launch_apply_fine<T>(c->dim, l.g, E_of<T>(c), l.nmask, K0_of<T>(c), nc, l.n, x, y, mode, r,
                              dinv_of<T>(l), (T)l.omega, dot_part, c->st);
-    else if (j == 2)
+    else if (j == 2 && c->level2_on_the_fly)
         launch_apply_coarse<T>(c->dim, l.g, c->lv[0].g, kSrcChildE, nullptr, E_of<T>(c), Mc_of<T>(c), l.nmask, nc,
                                l.n, x, y, mode, r, dinv_of<T>(l), (T)l.omega, c->st);
     else
@@ -357,7 +378,7 @@ int pcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, 
     const double t0 = now_s();
     const int64_t n = c->n;
     CHK(ensure_cg(c, nc));
-    const int npa = (int)apply_fine_blocks(c->lv[0].g);
+    const int npa = (int)fine_apply_blocks(c);
     const int np = reduction_parts(n);
     CHK(ensure_part(c, (int64_t)std::max(npa, np) * nc));
     double* bb = sc(c, 0);
@@ -501,7 +522,7 @@ int build_hierarchy(mlb_ctx* c) {
         Level& lc = c->lv[j - 1];
         if (j == 2) launch_galerkin_from_E(dim, lf.g, lc.g, c->Ek, c->dMc, lc.Ke, c->st);
         else launch_galerkin_dense(dim, false, lf.g, lc.g, lf.Ke, c->dT, lc.Ke, c->st);
-        if (j > 2) launch_to_float(lc.g.m * c->nde * c->nde, lc.Ke, lc.Kef, c->st);
+        if (j > 2 || !c->level2_on_the_fly) launch_to_float(lc.g.m * c->nde * c->nde, lc.Ke, lc.Kef, c->st);
         launch_dinv_dense(dim, lc.g, lc.Ke, lc.nmask, lc.dinv, lc.dinvf, c->st);
     }
     for (int j = 1; j < c->L; ++j) CHK(estimate_omega(c, j));
@@ -677,6 +698,7 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
     if (c->warm_coarse_cols > 0 && (int64_t)c->warm_coarse.size() == n * c->warm_coarse_cols) {
         const int wc = std::min(c->warm_coarse_cols, nb);
         HIPC(hipMemcpyAsync(X, c->warm_coarse.data(), sizeof(double) * n * wc, hipMemcpyHostToDevice, c->st));
+        launch_mask_fixed(n, wc, n, l.nmask, c->dim, X, c->st);
         CHK(sync(c));
     }
     applyKA(nb, X, KX, AX);
@@ -963,7 +985,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     c->o.eig_max_it = 400;
     c->o.check_every = 1;
     c->o.seed = 1;
-    c->o.cycle = 2;
+    c->o.cycle = 1;
     const int dim = desc->dim;
     auto bad = [&](const std::string& m) {
         c->err = m;
@@ -996,6 +1018,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     HIPC(hipStreamCreate(&c->own));
     c->st = c->own;
     build_tables(dim, desc->nu, &c->tab);
+    for (int i = 0; i < 72; ++i) c->whtf[i] = (float)c->tab.wht[i];
     // device tables
     CHK(dalloc(c, &c->dK0, 576));
     CHK(dalloc(c, &c->fK0, 576));
@@ -1036,7 +1059,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
         CHK(dalloc(c, &l.dinv, (size_t)l.n));
         CHK(dalloc(c, &l.dinvf, (size_t)l.n));
         if (j > 0) CHK(dalloc(c, &l.Ke, (size_t)l.g.m * c->nde * c->nde));
-        if (j > 1) CHK(dalloc(c, &l.Kef, (size_t)l.g.m * c->nde * c->nde));
+        if (j > 0) CHK(dalloc(c, &l.Kef, (size_t)l.g.m * c->nde * c->nde));
     }
     c->n = c->lv[0].n;
     c->m = c->lv[0].g.m;
@@ -1254,6 +1277,7 @@ static int solve_static_common(mlb_ctx* c, double tol, int max_it, mlb_solve_inf
     bool x0 = false;
     if ((int64_t)c->warm_static.size() == c->n * c->ncases) {
         HIPC(hipMemcpyAsync(c->U, c->warm_static.data(), sizeof(double) * c->n * c->ncases, hipMemcpyHostToDevice, c->st));
+        launch_mask_fixed(c->n, c->ncases, c->n, c->lv[0].nmask, c->dim, c->U, c->st);
         x0 = true;
     }
     CHK(pcg(c, c->F, c->U, c->ncases, tol, max_it, x0, info));
@@ -1359,7 +1383,7 @@ int mlb_apply_K_dev(mlb_ctx* c, int level, int ncols, const double* x, double* y
     if (level < 1 || level > c->L) return fail(c, MLB_EINVAL, "level out of range");
     if (!c->has_density || !c->has_bc) return fail(c, MLB_ESTATE, "set the mask and the densities first");
     c->st = pick(c, stream);
-    apply_K<double>(c, level, ncols, x, y, kModeY, nullptr, nullptr);
+    apply_K<double>(c, level, ncols, x, y, kModeY, nullptr, nullptr, false);
     HIPC(hipGetLastError());
     return MLB_OK;
 }
@@ -1420,7 +1444,19 @@ int mlb_vcycle_dev(mlb_ctx* c, int level, int ncols, const double* r, double* z,
     if (!c->has_density || !c->has_bc) return fail(c, MLB_ESTATE, "set the mask and the densities first");
     c->st = pick(c, stream);
     CHK(ensure_level_cols(c, ncols));
-    precondition(c, level, ncols, r, z);
+    // the preconditioner acts on the free subspace: mask a copy of r
+    Level& lv = c->lv[level - 1];
+    launch_copy_cols(lv.n, ncols, lv.n, r, lv.n, lv.vt, c->st);
+    launch_mask_fixed(lv.n, ncols, lv.n, lv.nmask, c->dim, lv.vt, c->st);
+    if (level == 1 && c->d.precision != MLB_MIXED) {
+        // vcycle<double> at level 1 uses vt as scratch: stage through the CG buffers
+        CHK(ensure_cg(c, ncols));
+        launch_copy_cols(lv.n, ncols, lv.n, lv.vt, lv.n, c->R, c->st);
+        precondition(c, level, ncols, c->R, z);
+    } else {
+        launch_copy_cols(lv.n, ncols, lv.n, lv.vt, lv.n, lv.vr, c->st);
+        precondition(c, level, ncols, lv.vr, z);
+    }
     HIPC(hipGetLastError());
     return MLB_OK;
 }

@@ -29,6 +29,13 @@ template <typename T>
 void launch_restrict(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
                      int64_t ldf, int64_t ldc, const T* xf, T* yc, hipStream_t st);
 
+// ---- element-centric Walsh-Hadamard apply (kernels_wht.hip)
+int64_t apply_wht_blocks(int dim, const Geo& g);
+template <typename T>
+void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* blocks, int ncols,
+                      int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega, double* dot_part,
+                      bool clean, hipStream_t st);
+
 // ---- setup (kernels_setup.hip)
 void launch_material(int64_t m, const double* x, double E1, double E0, double p, double* Ek, float* Ekf,
                      double* Es, int nparts, double* bad_part, hipStream_t st);
@@ -83,6 +90,7 @@ void launch_residual_block(int64_t n, int ncols, int64_t ld, const double* AX, c
                            const double* mu, double* R, hipStream_t st);
 void launch_random_fill(int64_t n, int ncols, int64_t ld, uint64_t seed, const uint8_t* nmask, int dim,
                         double* X, hipStream_t st);
+void launch_mask_fixed(int64_t n, int ncols, int64_t ld, const uint8_t* nmask, int dim, double* X, hipStream_t st);
 void launch_absmax_part(int64_t n, int ncols, int64_t ld, const double* X, int nparts, double* pval,
                         int64_t* pidx, hipStream_t st);
 void launch_absmax_sum(int ncols, int nparts, const double* pval, const int64_t* pidx, double* out_val,

@@ -547,14 +547,15 @@ void launch_apply_coarse(int dim, const Geo& g, const Geo& gfine, int src, const
     else MLB_LAUNCH(D, kModeJacobi, S, CB);
 #define MLB_CB(D, S)                                \
     if (ncols == 1) { MLB_MODES(D, S, 1) }          \
-    else { MLB_MODES(D, S, 4) }
+    else if (ncols <= 4) { MLB_MODES(D, S, 4) }     \
+    else { MLB_MODES(D, S, 8) }
     if (dim == 2) {
         if (src == kSrcKron) { if (ncols == 1) MLB_LAUNCH(2, kModeY, kSrcKron, 1); else MLB_LAUNCH(2, kModeY, kSrcKron, 4); }
-        else if (src == kSrcChildE) { MLB_CB(2, kSrcChildE) }
+        else if (src == kSrcChildE) { if (ncols == 1) { MLB_MODES(2, kSrcChildE, 1) } else { MLB_MODES(2, kSrcChildE, 4) } }
         else { MLB_CB(2, kSrcDense) }
     } else {
         if (src == kSrcKron) { if (ncols == 1) MLB_LAUNCH(3, kModeY, kSrcKron, 1); else MLB_LAUNCH(3, kModeY, kSrcKron, 4); }
-        else if (src == kSrcChildE) { MLB_CB(3, kSrcChildE) }
+        else if (src == kSrcChildE) { if (ncols == 1) { MLB_MODES(3, kSrcChildE, 1) } else { MLB_MODES(3, kSrcChildE, 4) } }
         else { MLB_CB(3, kSrcDense) }
     }
 #undef MLB_CB

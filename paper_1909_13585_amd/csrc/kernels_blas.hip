@@ -294,6 +294,15 @@ __global__ void k_random_fill(int64_t n, int ncols, int64_t ld, uint64_t seed, c
     }
 }
 
+// Zero the Dirichlet entries of a block (restores the free-subspace invariant).
+__global__ void k_mask_fixed(int64_t n, int ncols, int64_t ld, const uint8_t* __restrict__ nmask, int dim,
+                             double* __restrict__ X) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!((nmask[i / dim] >> (i % dim)) & 1)) return;
+    for (int c = 0; c < ncols; ++c) X[c * ld + i] = 0.0;
+}
+
 // Column-wise argmax |x| (ties: lowest index) -> signed value of that entry.
 __global__ void k_absmax_part(int64_t n, int64_t ld, const double* __restrict__ X, double* __restrict__ pval,
                               int64_t* __restrict__ pidx) {
@@ -449,6 +458,9 @@ void launch_residual_block(int64_t n, int ncols, int64_t ld, const double* AX, c
 void launch_random_fill(int64_t n, int ncols, int64_t ld, uint64_t seed, const uint8_t* nmask, int dim, double* X,
                         hipStream_t st) {
     hipLaunchKernelGGL(k_random_fill, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, seed, nmask, dim, X);
+}
+void launch_mask_fixed(int64_t n, int ncols, int64_t ld, const uint8_t* nmask, int dim, double* X, hipStream_t st) {
+    hipLaunchKernelGGL(k_mask_fixed, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, nmask, dim, X);
 }
 void launch_absmax_part(int64_t n, int ncols, int64_t ld, const double* X, int nparts, double* pval, int64_t* pidx,
                         hipStream_t st) {

@@ -1,0 +1,444 @@
+// Level-1 stiffness apply, element-centric, in the symmetry-adapted
+// Walsh-Hadamard basis of the unit element.
+//
+// The unit square/cube element is invariant under the dim mid-plane
+// reflections.  Transforming each displacement component over the 2^dim
+// element nodes with the Walsh-Hadamard matrix H (H[k][a] = (-1)^popcount(k&a))
+// and grouping component c at index sigma ^ (1 << c) splits K0 exactly into
+// 2^dim independent dim x dim blocks B_sigma:
+//     K0 u = H diag(B_sigma) H u / 4^dim      (per element, times E_e)
+// i.e. ~ 200 operations per element instead of the 1152 of a dense 24 x 24
+// product, so the FP64 apply becomes bandwidth-bound.  The blocks (with the
+// 1/4^dim folded in) arrive as kernel arguments and live in SGPRs.
+//
+// Traversal: each thread walks a pencil of elements along the slowest axis
+// (z in 3D, y in 2D), carrying the shared node plane and the partial sums of
+// the next node plane in registers.  The contributions of the element columns
+// that share a node are combined with lane shuffles, always in the same
+// order, so the result is deterministic (no atomics) and no barriers are
+// needed.  Tiles overlap by one element column/row; a thread owns the node
+// at the low corner of its element column.
+#include "kernels.h"
+
+namespace mlb {
+
+template <typename T>
+struct WhtBlocks {
+    T v[8 * 9];   // B_sigma row-major dim x dim, sigma = 0 .. 2^dim - 1
+};
+
+__device__ inline double shfl_up_w(double v, int d, int width) { return __shfl_up(v, d, width); }
+__device__ inline float shfl_up_w(float v, int d, int width) { return __shfl_up(v, d, width); }
+
+// In-place 2^DIM-point Walsh-Hadamard transform of s[0 .. 2^DIM).
+template <int DIM, typename T>
+__device__ inline void wht(T* s) {
+#pragma unroll
+    for (int b = 0; b < DIM; ++b)
+#pragma unroll
+        for (int a = 0; a < (1 << DIM); ++a)
+            if (!((a >> b) & 1)) {
+                const T p = s[a], q = s[a | (1 << b)];
+                s[a] = p + q;
+                s[a | (1 << b)] = p - q;
+            }
+}
+
+// Structural nonzeros of B_sigma (from the reflection symmetry, independent
+// of the material): component c is a rigid translation when
+// sigma == 1 << c (zero row and column); components c != c2 couple only
+// when bits c and c2 of sigma are equal.  The host checks that every other
+// entry vanishes before this kernel is used.
+template <int DIM>
+__host__ __device__ constexpr bool wht_nz(int s, int c, int c2) {
+    return s != (1 << c) && s != (1 << c2) && (((s >> c) & 1) == ((s >> c2) & 1));
+}
+
+// out[a][c] = E * (H diag(B) H u)[a][c]  for one element.
+template <int DIM, typename T>
+__device__ inline void element_apply(const WhtBlocks<T>& B, T Ee, T (&u)[DIM][1 << DIM]) {
+    constexpr int NN = 1 << DIM;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) wht<DIM, T>(u[c]);
+#pragma unroll
+    for (int s = 0; s < NN; ++s) {
+        T v[DIM], t[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) v[c] = u[c][s ^ (1 << c)];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            T acc = T(0);
+#pragma unroll
+            for (int c2 = 0; c2 < DIM; ++c2)
+                if (wht_nz<DIM>(s, c, c2)) acc += B.v[s * DIM * DIM + c * DIM + c2] * v[c2];
+            t[c] = acc;
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) u[c][s ^ (1 << c)] = t[c];
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        wht<DIM, T>(u[c]);
+#pragma unroll
+        for (int a = 0; a < NN; ++a) u[c][a] *= Ee;
+    }
+}
+
+template <typename T, int MODE>
+__device__ inline T wht_epilogue(T ax, T xown, T rr, T di, T omega) {
+    if (MODE == kModeY) return ax;
+    if (MODE == kModeResidual) return rr - ax;
+    return xown + omega * di * (rr - ax);
+}
+
+__device__ inline double wht_block_sum(double v, double* sh) {
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int nthreads = blockDim.x * blockDim.y;
+    const int lane = tid & 63, wid = tid >> 6, nw = (nthreads + 63) >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (tid == 0)
+        for (int w = 0; w < nw; ++w) r += sh[w];
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// 3D: every wavefront is an independent 8 x 8 tile of element columns
+// (lane = tx + 8 ty) walking a pencil along z; tiles overlap by one column/row
+// and lanes with tx, ty >= 1 own the node at the low corner of their column.
+// x partners come from lane-1, y partners from lane-8 (shuffles, no
+// barriers); the next node plane is prefetched one step ahead.
+constexpr int kWT = 8;          // tile edge (element columns per wave edge)
+constexpr int kW3 = 4;          // waves per block
+
+#ifndef MLB_WHT3_WAVES
+#define MLB_WHT3_WAVES 2
+#endif
+// CLEAN: the caller guarantees x == 0 at every Dirichlet DOF (true for every
+// vector inside the solvers), so neighbour values need no masking; only the
+// owned node's mask is read (identity rows).
+template <typename T, int MODE, bool DOT, bool CLEAN>
+__global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(MLB_WHT3_WAVES, 8))) void k_apply_wht3(
+    Geo g, int kz_chunk, int ntiles_x, int ntiles_y, const T* __restrict__ E, const uint8_t* __restrict__ nmask,
+    WhtBlocks<T> B, int ncols, int64_t ld, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ r,
+    const T* __restrict__ dinv, T omega, double* __restrict__ part) {
+    __shared__ double sh[16];
+    const int lane = threadIdx.x;              // 0..63
+    const int tx = lane & 7, ty = lane >> 3;
+    const int64_t tile = (int64_t)blockIdx.x * kW3 + threadIdx.y;
+    const int64_t ntile_xy = (int64_t)ntiles_x * ntiles_y;
+    const int tzc = (int)(tile / ntile_xy);
+    const int txy = (int)(tile % ntile_xy);
+    const int ie = (txy % ntiles_x) * (kWT - 1) - 1 + tx;
+    const int je = (txy / ntiles_x) * (kWT - 1) - 1 + ty;
+    const int kz0 = tzc * kz_chunk;
+    const int kend = min(kz0 + kz_chunk, g.nnz);
+    const bool col_ok = ie >= 0 && ie < g.nx && je >= 0 && je < g.ny;
+    const bool owner = tx >= 1 && ty >= 1 && ie >= 0 && je >= 0 && ie <= g.nx && je <= g.ny;
+    const int64_t plane = (int64_t)g.nnx * g.nny;
+    const int64_t eplane = (int64_t)g.nx * g.ny;
+    const int64_t nblk = gridDim.x;
+    // per-lane node columns (ie+ax, je+ay): in-plane index and validity
+    int64_t base[4];
+    bool qok[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int ii = ie + (q & 1), jj = je + (q >> 1);
+        qok[q] = ii >= 0 && ii < g.nnx && jj >= 0 && jj < g.nny;
+        base[q] = qok[q] ? ii + (int64_t)g.nnx * jj : 0;
+    }
+    const int64_t ebase = col_ok ? ie + (int64_t)g.nx * je : 0;
+    for (int col = 0; col < ncols; ++col) {
+        const T* xc = x + col * ld;
+        double dsum = 0.0;
+        // values (and, unless CLEAN, masks) of the 4 nodes of node plane kk;
+        // clamped addresses keep every load valid and branch free
+        auto fetch = [&](int kk, T (&v)[3][4], uint8_t (&mk)[4]) {
+            const bool kin = kk >= 0 && kk < g.nnz;
+            const int64_t off = kin ? plane * kk : 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool ok = qok[q] && kin;
+                const int64_t nd = base[q] + off;
+                if (!CLEAN || q == 0) {
+                    const uint8_t mraw = nmask[nd];
+                    mk[q] = ok ? mraw : (uint8_t)0x07;
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T xv = xc[nd * 3 + c];
+                    v[c][q] = ok ? xv : T(0);
+                }
+            }
+        };
+        T lo[3][4], hi[3][4], pf[3][4];
+        uint8_t mlo[4], mhi[4], mpf[4];
+        T cout[3][4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cout[c][q] = T(0);
+        fetch(kz0 - 1, lo, mlo);
+        fetch(kz0, hi, mhi);
+        for (int ke = kz0 - 1; ke < kend; ++ke) {
+            fetch(ke + 2, pf, mpf);   // prefetch for the next step
+            const bool eok = col_ok && ke >= 0 && ke < g.nz;
+            const T Eraw = E[eok ? ebase + eplane * ke : 0];
+            const T Ee = eok ? Eraw : T(0);
+            T u[3][8];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (CLEAN) {
+                        u[c][q] = lo[c][q];
+                        u[c][q + 4] = hi[c][q];
+                    } else {
+                        u[c][q] = ((mlo[q] >> c) & 1) ? T(0) : lo[c][q];
+                        u[c][q + 4] = ((mhi[q] >> c) & 1) ? T(0) : hi[c][q];
+                    }
+                }
+            element_apply<3, T>(B, Ee, u);
+            T P[3][4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    P[c][q] = u[c][q] + cout[c][q];
+                    cout[c][q] = u[c][q + 4];
+                }
+            if (ke >= kz0) {
+                T acc[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    // x partners (lane-1), then y partners (lane-8)
+                    const T q0 = P[c][0] + shfl_up_w(P[c][1], 1, kWT);
+                    const T q1 = P[c][2] + shfl_up_w(P[c][3], 1, kWT);
+                    acc[c] = q0 + shfl_up_w(q1, kWT, 64);
+                }
+                if (owner && ke < g.nnz) {
+                    const int64_t nd = base[0] + plane * ke;
+                    const uint8_t own = mlo[0];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int64_t d = nd * 3 + c;
+                        const T xown = lo[c][0];
+                        const T ax = (own >> c) & 1 ? xown : acc[c];
+                        const T rr = MODE == kModeY ? T(0) : r[col * ld + d];
+                        const T di = MODE == kModeJacobi ? dinv[d] : T(0);
+                        y[col * ld + d] = wht_epilogue<T, MODE>(ax, xown, rr, di, omega);
+                        if (DOT) dsum += (double)xown * (double)ax;
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    lo[c][q] = hi[c][q];
+                    hi[c][q] = pf[c][q];
+                }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                mlo[q] = mhi[q];
+                mhi[q] = mpf[q];
+            }
+        }
+        if (DOT) {
+            const double bs = wht_block_sum(dsum, sh);
+            if (lane == 0 && threadIdx.y == 0) part[col * nblk + blockIdx.x] = bs;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D: block = 64 x 4 threads; each wave (row of the block) is an independent
+// pencil of elements along y for its own x tile.
+constexpr int kTX2 = 64, kTW2 = 4;
+
+template <typename T, int MODE, bool DOT>
+__global__ __launch_bounds__(kTX2* kTW2) void k_apply_wht2(Geo g, int ky_chunk, int ntiles_x, const T* __restrict__ E,
+                                                           const uint8_t* __restrict__ nmask, WhtBlocks<T> B,
+                                                           int ncols, int64_t ld, const T* __restrict__ x,
+                                                           T* __restrict__ y, const T* __restrict__ r,
+                                                           const T* __restrict__ dinv, T omega,
+                                                           double* __restrict__ part) {
+    __shared__ double sh[16];
+    const int tx = threadIdx.x;
+    const int64_t tile = (int64_t)blockIdx.x * kTW2 + threadIdx.y;
+    const int tile_x = (int)(tile % ntiles_x);
+    const int tile_y = (int)(tile / ntiles_x);
+    const int ie = tile_x * (kTX2 - 1) - 1 + tx;
+    const int ky0 = tile_y * ky_chunk;
+    const int kend = min(ky0 + ky_chunk, g.nny);
+    const bool col_ok = ie >= 0 && ie < g.nx;
+    const bool owner = tx >= 1 && ie >= 0 && ie <= g.nx;
+    const int64_t blk = blockIdx.x;
+    const int64_t nblk = gridDim.x;
+    for (int col = 0; col < ncols; ++col) {
+        const T* xc = x + col * ld;
+        T cx[2][2], craw[2], cout[2][2];
+        double dsum = 0.0;
+        auto load_row = [&](int jj, T (&v)[2][2], T (&raw)[2]) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int ii = ie + q;
+                const bool ok = ii >= 0 && ii < g.nnx && jj >= 0 && jj < g.nny;
+                const int64_t nd = ok ? ii + (int64_t)g.nnx * jj : 0;
+                const uint8_t mraw = nmask[nd];
+                const uint8_t mb = ok ? mraw : (uint8_t)0xff;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const T xl = xc[nd * 2 + c];
+                    const T xv = ok ? xl : T(0);
+                    if (q == 0) raw[c] = xv;
+                    v[c][q] = ((mb >> c) & 1) ? T(0) : xv;
+                }
+            }
+        };
+        load_row(ky0 - 1, cx, craw);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) cout[c][0] = cout[c][1] = T(0);
+        const bool live = tile_y * ky_chunk < g.nny;
+        for (int je = ky0 - 1; live && je < kend; ++je) {
+            T nx_[2][2], nraw[2];
+            load_row(je + 1, nx_, nraw);
+            const bool eok = col_ok && je >= 0 && je < g.ny;
+            const T Eraw = E[eok ? ie + (int64_t)g.nx * je : 0];
+            const T Ee = eok ? Eraw : T(0);
+            T u[2][4];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                u[c][0] = cx[c][0];
+                u[c][1] = cx[c][1];
+                u[c][2] = nx_[c][0];
+                u[c][3] = nx_[c][1];
+            }
+            element_apply<2, T>(B, Ee, u);
+            T P[2][2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                P[c][0] = u[c][0] + cout[c][0];
+                P[c][1] = u[c][1] + cout[c][1];
+                cout[c][0] = u[c][2];
+                cout[c][1] = u[c][3];
+            }
+            if (je >= ky0) {
+                T Q[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) Q[c] = P[c][0] + shfl_up_w(P[c][1], 1, kTX2);
+                if (owner && je < g.nny) {
+                    const int64_t nd = ie + (int64_t)g.nnx * je;
+                    const uint8_t own = nmask[nd];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int64_t d = nd * 2 + c;
+                        const T xown = craw[c];
+                        const T ax = (own >> c) & 1 ? xown : Q[c];
+                        const T rr = MODE == kModeY ? T(0) : r[col * ld + d];
+                        const T di = MODE == kModeJacobi ? dinv[d] : T(0);
+                        y[col * ld + d] = wht_epilogue<T, MODE>(ax, xown, rr, di, omega);
+                        if (DOT) dsum += (double)xown * (double)ax;
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                craw[c] = nraw[c];
+                cx[c][0] = nx_[c][0];
+                cx[c][1] = nx_[c][1];
+            }
+        }
+        if (DOT) {
+            const double bs = wht_block_sum(dsum, sh);
+            if (tx == 0 && threadIdx.y == 0) part[col * nblk + blk] = bs;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch geometry
+
+static void wht_geometry(int dim, const Geo& g, dim3& grid, dim3& block, int& chunk, int& ntx, int& nty) {
+    nty = 1;
+    if (dim == 3) {
+        const int tiles_x = (g.nnx + kWT - 2) / (kWT - 1);
+        const int tiles_y = (g.nny + kWT - 2) / (kWT - 1);
+#ifndef MLB_WHT3_CHUNK
+#define MLB_WHT3_CHUNK 8
+#endif
+        int nch = (g.nnz + MLB_WHT3_CHUNK - 1) / MLB_WHT3_CHUNK;
+        chunk = (g.nnz + nch - 1) / nch;
+        nch = (g.nnz + chunk - 1) / chunk;
+        const int64_t tiles = (int64_t)tiles_x * tiles_y * nch;
+        grid = dim3((unsigned)((tiles + kW3 - 1) / kW3), 1, 1);
+        block = dim3(64, kW3, 1);
+        ntx = tiles_x;
+        nty = tiles_y;
+    } else {
+        const int tiles_x = (g.nnx + kTX2 - 2) / (kTX2 - 1);
+        int nch = (g.nny + 15) / 16;
+        chunk = (g.nny + nch - 1) / nch;
+        nch = (g.nny + chunk - 1) / chunk;
+        const int tiles = tiles_x * nch;
+        grid = dim3((tiles + kTW2 - 1) / kTW2, 1, 1);
+        block = dim3(kTX2, kTW2, 1);
+        ntx = tiles_x;
+    }
+}
+
+int64_t apply_wht_blocks(int dim, const Geo& g) {
+    dim3 gr, b;
+    int ch, ntx, nty;
+    wht_geometry(dim, g, gr, b, ch, ntx, nty);
+    return (int64_t)gr.x * gr.y * gr.z;
+}
+
+template <typename T>
+void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* blocks, int ncols,
+                      int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega, double* dot_part,
+                      bool clean, hipStream_t st) {
+    WhtBlocks<T> B;
+    for (int i = 0; i < 72; ++i) B.v[i] = blocks[i];
+    dim3 gr, b;
+    int ch, ntx, nty;
+    wht_geometry(dim, g, gr, b, ch, ntx, nty);
+#define MLB_L3C(M, D, C)                                                                                         \
+    hipLaunchKernelGGL((k_apply_wht3<T, M, D, C>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B, ncols, ld, x, y, r, \
+                       dinv, omega, dot_part)
+#define MLB_L3(M, D)                       \
+    do {                                   \
+        if (clean) MLB_L3C(M, D, true);    \
+        else MLB_L3C(M, D, false);         \
+    } while (0)
+#define MLB_L2(M, D)                                                                                              \
+    hipLaunchKernelGGL((k_apply_wht2<T, M, D>), gr, b, 0, st, g, ch, ntx, E, nmask, B, ncols, ld, x, y, r, dinv, omega, \
+                       dot_part)
+    if (dim == 3) {
+        if (mode == kModeY && dot_part) MLB_L3(kModeY, true);
+        else if (mode == kModeY) MLB_L3(kModeY, false);
+        else if (mode == kModeResidual) MLB_L3(kModeResidual, false);
+        else MLB_L3(kModeJacobi, false);
+    } else {
+        if (mode == kModeY && dot_part) MLB_L2(kModeY, true);
+        else if (mode == kModeY) MLB_L2(kModeY, false);
+        else if (mode == kModeResidual) MLB_L2(kModeResidual, false);
+        else MLB_L2(kModeJacobi, false);
+    }
+#undef MLB_L3
+#undef MLB_L3C
+#undef MLB_L2
+}
+
+template void launch_apply_wht<double>(int, const Geo&, const double*, const uint8_t*, const double*, int, int64_t,
+                                       const double*, double*, int, const double*, const double*, double, double*,
+                                       bool, hipStream_t);
+template void launch_apply_wht<float>(int, const Geo&, const float*, const uint8_t*, const float*, int, int64_t,
+                                      const float*, float*, int, const float*, const float*, float, double*, bool,
+                                      hipStream_t);
+
+}  // namespace mlb

@@ -16,8 +16,10 @@
 // T[c][b][A] stores it; then K_E = sum_c T_c^T K_c T_c (kron I for vectors).
 #include "tables.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 namespace mlb {
 
@@ -191,6 +193,36 @@ void build_tables(int dim, double nu, Tables* t) {
                     t->GHc[((size_t)c * 6 + k) * 64 + A * nn + Bn] = s;
                 }
     }
+
+    // Symmetry-adapted Walsh-Hadamard blocks: D = (Hb kron I) K0 (Hb kron I)
+    // with Hb[k][a] = (-1)^popcount(k & a); component c of block sigma sits at
+    // transform index sigma ^ (1 << c).  K0 = H D H / 4^dim.
+    auto hb = [](int k, int a) { return (__builtin_popcount(k & a) & 1) ? -1.0 : 1.0; };
+    std::vector<double> D((size_t)nde * nde, 0.0);
+    for (int k = 0; k < nn; ++k)
+        for (int c = 0; c < dim; ++c)
+            for (int k2 = 0; k2 < nn; ++k2)
+                for (int c2 = 0; c2 < dim; ++c2) {
+                    double s = 0;
+                    for (int a = 0; a < nn; ++a)
+                        for (int b = 0; b < nn; ++b)
+                            s += hb(k, a) * t->K0[(a * dim + c) * nde + b * dim + c2] * hb(k2, b);
+                    D[(size_t)(k * dim + c) * nde + k2 * dim + c2] = s;
+                }
+    double dmax = 0, offmax = 0;
+    for (double v : D) dmax = std::max(dmax, std::fabs(v));
+    const double scale = 1.0 / (double)(nn * nn);
+    for (int row = 0; row < nde; ++row)
+        for (int colm = 0; colm < nde; ++colm) {
+            const int k = row / dim, c = row % dim, k2 = colm / dim, c2 = colm % dim;
+            const int s1 = k ^ (1 << c), s2 = k2 ^ (1 << c2);
+            // structural pattern: translation rows/columns vanish, components
+            // c != c2 couple only where bits c and c2 of the block index agree
+            const bool nz = s1 == s2 && s1 != (1 << c) && s1 != (1 << c2) && (((s1 >> c) & 1) == ((s1 >> c2) & 1));
+            if (!nz) offmax = std::max(offmax, std::fabs(D[(size_t)row * nde + colm]));
+            if (s1 == s2) t->wht[s1 * dim * dim + c * dim + c2] = nz ? D[(size_t)row * nde + colm] * scale : 0.0;
+        }
+    t->wht_ok = offmax <= 1e-13 * dmax;
 }
 
 }  // namespace mlb

@@ -13,6 +13,8 @@ struct Tables {
     double T[8 * 8 * 8];    // child c, child node b, coarse node A -> weight
     double Mc[8 * 576];     // child c: T_c^T K0 T_c (nde x nde)
     double GHc[8 * 6 * 64]; // child c, Voigt k: T_c^T H^k T_c (nn x nn)
+    double wht[8 * 9];      // symmetry-adapted Walsh-Hadamard blocks of K0 / 4^dim
+    bool wht_ok;            // K0 is exactly block diagonal in that basis
 };
 
 void build_tables(int dim, double nu, Tables* t);
