@@ -93,6 +93,7 @@ typedef struct {
     int check_every;      /* CG iterations between host convergence checks (default 1) */
     uint64_t seed;        /* seed of the coarse eigensolver start block (default 1) */
     int cycle;            /* coarse-grid visits per level: 1 = V-cycle, 2 = W-cycle (default 1) */
+    int block_cg;         /* multi-column solves: 1 = block CG (default), 2 = column-wise CG */
 } mlb_opts;
 
 /* Per-call solver report; for blocks, the worst column is reported. */

@@ -62,7 +62,8 @@ struct mlb_ctx {
            *dMc = nullptr, *dGHc = nullptr;
     float* fK0 = nullptr;
     float* fMc = nullptr;
-    bool level2_on_the_fly = false;   // level-2 rows from the fine moduli (no stored matrices read)
+    bool level2_on_the_fly = false;
+    int eig_cycle = 1;   // V (1) or W (2) cycle inside the coarse eigensolver's preconditioner   // level-2 rows from the fine moduli (no stored matrices read)
     float whtf[72] = {};   // FP32 copy of the Walsh-Hadamard blocks (host; passed by value)
     std::vector<Level> lv;
     int64_t n = 0, m = 0;
@@ -361,7 +362,8 @@ int read_scal(mlb_ctx* c, const double* dev, int count, double* host) {
 // Gram A^T B (n x k1, n x k2) -> host column-major k1 x k2 (G[i + k1*j]).
 int gram(mlb_ctx* c, int64_t n, int k1, const double* A, int64_t lda, int k2, const double* B, int64_t ldb,
          std::vector<double>& G) {
-    const int np = std::min<int>(reduction_parts(n), 256);
+    // enough blocks to fill the GPU even for the small eigen-level blocks
+    const int np = (int)std::max<int64_t>(1, std::min<int64_t>(256, n / 256));
     CHK(ensure_part(c, (int64_t)np * k1 * k2));
     launch_gram_part(n, k1, lda, A, k2, ldb, B, np, c->part, c->st);
     launch_gram_sum(k1, k2, np, c->part, c->gbuf, c->st);
@@ -631,6 +633,118 @@ static int svqb(int r0, const std::vector<double>& G, double drop, std::vector<d
     return r;
 }
 
+// ---- Block PCG (O'Leary's block conjugate gradients, in the breakdown-free
+// form of Ji & Li: the search block is A-orthonormalised by SVQB every
+// iteration, so converged or linearly dependent directions drop out):
+//   P^T A P = I,  alpha = P^T R,  X += P alpha,  R -= Q alpha  (Q = A P)
+//   Z = M R,  beta = -Q^T Z,  P <- orth_A(Z + P beta)
+// All columns share one block Krylov space, which deflates the outlying
+// eigenvalues of M A for every right-hand side at once.
+int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, bool use_x0, mlb_solve_info* info) {
+    const double t0 = now_s();
+    const int64_t n = c->n;
+    if (nc > 32) return fail(c, MLB_EINVAL, "block CG supports at most 32 columns");
+    CHK(ensure_cg(c, nc));
+    const int np = reduction_parts(n);
+    CHK(ensure_part(c, (int64_t)np * nc));
+    double* bb = sc(c, 0);
+    double* rr = sc(c, 1);
+    dots(c, n, nc, B, B, bb);
+    if (use_x0) {
+        apply_K<double>(c, 1, nc, X, c->R, kModeResidual, B, nullptr);
+    } else {
+        HIPC(hipMemsetAsync(X, 0, sizeof(double) * n * nc, c->st));
+        launch_copy_cols(n, nc, n, B, n, c->R, c->st);
+    }
+    std::vector<double> hb(nc), hr(nc);
+    CHK(read_scal(c, bb, nc, hb.data()));
+    for (int i = 0; i < nc; ++i)
+        if (!std::isfinite(hb[i])) return fail(c, MLB_EINVAL, "non-finite right-hand side");
+    double* P = c->Pb;    // n x sp (A-orthonormal)
+    double* Q = c->Qb;    // A P
+    double* Z = c->Zb;
+    double* T1 = c->Zo;   // scratch n x nc
+    int sp = 0;
+    std::vector<double> Gm, Tm, Cm;
+    // P <- orth_A(V), V in-place in P with its product AV in Q; returns rank
+    auto orthA = [&](int cols) -> int {
+        CHK(gram(c, n, cols, P, n, cols, Q, n, Gm));
+        const int r = svqb(cols, Gm, 1e-13, Tm);
+        if (r == 0) return MLB_OK;
+        CHK(upload_cm(c, c->cbuf, Tm));
+        launch_gemm_small(n, cols, n, P, r, c->cbuf, n, T1, c->st);
+        launch_copy_cols(n, r, n, T1, n, P, c->st);
+        launch_gemm_small(n, cols, n, Q, r, c->cbuf, n, T1, c->st);
+        launch_copy_cols(n, r, n, T1, n, Q, c->st);
+        sp = r;
+        return MLB_OK;
+    };
+    int it = 0, status = MLB_OK;
+    auto converged = [&](bool* done) -> int {
+        dots(c, n, nc, c->R, c->R, rr);
+        CHK(read_scal(c, rr, nc, hr.data()));
+        bool all = true;
+        double w = 0;
+        for (int i = 0; i < nc; ++i) {
+            if (!std::isfinite(hr[i])) return fail(c, MLB_EBREAKDOWN, "block CG residual not finite");
+            if (hr[i] > tol * tol * hb[i]) all = false;
+            w = std::max(w, hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0);
+        }
+        if (std::getenv("MLB_VERBOSE") && (it % 10 == 0 || all))
+            std::fprintf(stderr, "[mlb] bpcg it %d worst rel %.3e rank %d\n", it, w, sp);
+        *done = all;
+        return MLB_OK;
+    };
+    bool done = false;
+    CHK(converged(&done));
+    if (!done) {
+        precondition(c, 1, nc, c->R, P);
+        apply_K<double>(c, 1, nc, P, Q, kModeY, nullptr, nullptr);
+        CHK(orthA(nc));
+        for (it = 1; it <= max_it; ++it) {
+            if (sp == 0) return fail(c, MLB_EBREAKDOWN, "block CG: search space collapsed");
+            // alpha = P^T R (sp x nc); X += P alpha; R -= Q alpha
+            CHK(gram(c, n, sp, P, n, nc, c->R, n, Cm));
+            CHK(upload_cm(c, c->cbuf, Cm));
+            launch_gemm_small(n, sp, n, P, nc, c->cbuf, n, T1, c->st);
+            launch_axpby(n * nc, 1.0, T1, 1.0, X, c->st);
+            launch_gemm_small(n, sp, n, Q, nc, c->cbuf, n, T1, c->st);
+            launch_axpby(n * nc, -1.0, T1, 1.0, c->R, c->st);
+            CHK(converged(&done));
+            if (done) break;
+            // Z = M R; beta = -Q^T Z; P <- Z + P beta
+            precondition(c, 1, nc, c->R, Z);
+            CHK(gram(c, n, sp, Q, n, nc, Z, n, Cm));
+            for (auto& v : Cm) v = -v;
+            CHK(upload_cm(c, c->cbuf, Cm));
+            launch_gemm_small(n, sp, n, P, nc, c->cbuf, n, T1, c->st);
+            launch_axpby(n * nc, 1.0, Z, 1.0, T1, c->st);
+            launch_copy_cols(n, nc, n, T1, n, P, c->st);
+            apply_K<double>(c, 1, nc, P, Q, kModeY, nullptr, nullptr);
+            CHK(orthA(nc));
+        }
+        if (it > max_it) {
+            it = max_it;
+            status = MLB_ENOTCONV;
+        }
+    }
+    // true residual
+    apply_K<double>(c, 1, nc, X, c->R, kModeResidual, B, nullptr);
+    dots(c, n, nc, c->R, c->R, rr);
+    CHK(read_scal(c, rr, nc, hr.data()));
+    double worst = 0.0;
+    for (int i = 0; i < nc; ++i) worst = std::max(worst, hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0);
+    if (info) {
+        info->iterations = it;
+        info->converged = status == MLB_OK;
+        info->rel_residual = worst;
+        info->true_rel_residual = worst;
+        info->seconds = now_s() - t0;
+    }
+    if (status != MLB_OK) return fail(c, status, "block CG did not reach the tolerance");
+    return MLB_OK;
+}
+
 // LOBPCG for the largest mu of (-G) psi = mu K psi at level ell, in the
 // robust form: X K-orthonormal; W = T R orthogonalised twice against X (and
 // P) and orthonormalised by SVQB; P kept K-orthonormal; K X and -G X
@@ -754,7 +868,12 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         if (it >= 30 && !(mu[k - 1] > 0.0))
             return fail(c, MLB_ENOPOS, "fewer than k positive buckling factors at the coarse level");
         // W = T R, orthogonalised against X and P (twice), then K-orthonormalised
-        precondition(c, j, nb, c->eR, W);
+        {
+            const int saved = c->o.cycle;
+            c->o.cycle = c->eig_cycle;
+            precondition(c, j, nb, c->eR, W);
+            c->o.cycle = saved;
+        }
         for (int pass = 0; pass < 2; ++pass) {
             CHK(orth_against(W, nb, X, KX, nb));
             if (rp > 0) CHK(orth_against(W, nb, c->eP, c->ePK, rp));
@@ -879,7 +998,8 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
     // step 3: K Phi~ = G Psi
     apply_G(c, 1, k, c->X1, c->X2);
     mlb_solve_info si{};
-    CHK(pcg(c, c->X2, c->Phi, k, c->tol_solve, c->max_it, false, &si));
+    if (c->o.block_cg) CHK(bpcg(c, c->X2, c->Phi, k, c->tol_solve, c->max_it, false, &si));
+    else CHK(pcg(c, c->X2, c->Phi, k, c->tol_solve, c->max_it, false, &si));
     const double t2 = now_s();
     // step 4: Rayleigh-Ritz on span(Phi~)
     apply_K<double>(c, 1, k, c->Phi, c->X1, kModeY, nullptr, nullptr);
@@ -957,7 +1077,8 @@ int do_sens(mlb_ctx* c, double* dJ_dev, double* dlam_dev, mlb_solve_info* info) 
         launch_adj_gather(c->dim, g, k, V, c->dBc, c->lv[0].nmask, c->n, c->X2, c->st);
         CHK(sync(c));
         dfree(V);
-        CHK(pcg(c, c->X2, c->Zadj, k, c->tol_solve, c->max_it, false, info));
+        if (c->o.block_cg) CHK(bpcg(c, c->X2, c->Zadj, k, c->tol_solve, c->max_it, false, info));
+        else CHK(pcg(c, c->X2, c->Zadj, k, c->tol_solve, c->max_it, false, info));
         launch_dlam(c->dim, g, c->x, c->d.penal, c->d.E1, c->d.E0, c->U + (int64_t)c->ref_case_used * c->n, k,
                     c->n, c->Phi, c->Zadj, c->dlam_l, c->dK0, c->dHk, c->dD0Bc, dlam_dev, c->st);
     }
@@ -986,6 +1107,8 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     c->o.check_every = 1;
     c->o.seed = 1;
     c->o.cycle = 1;
+    c->o.block_cg = 1;
+    if (const char* ev = std::getenv("MLB_EIG_CYCLE")) c->eig_cycle = std::atoi(ev) == 2 ? 2 : 1;
     const int dim = desc->dim;
     auto bad = [&](const std::string& m) {
         c->err = m;
@@ -1123,6 +1246,7 @@ int mlb_set_opts(mlb_ctx* c, const mlb_opts* o) {
     if (o->check_every > 0) c->o.check_every = o->check_every;
     if (o->seed > 0) c->o.seed = o->seed;
     if (o->cycle > 0) c->o.cycle = std::min(o->cycle, 2);
+    if (o->block_cg > 0) c->o.block_cg = o->block_cg == 1 ? 1 : 0;
     if (o->jacobi_omega > 0 && c->has_density) {
         c->st = c->own;
         for (int j = 1; j < c->L; ++j) CHK(estimate_omega(c, j));
@@ -1280,7 +1404,8 @@ static int solve_static_common(mlb_ctx* c, double tol, int max_it, mlb_solve_inf
         launch_mask_fixed(c->n, c->ncases, c->n, c->lv[0].nmask, c->dim, c->U, c->st);
         x0 = true;
     }
-    CHK(pcg(c, c->F, c->U, c->ncases, tol, max_it, x0, info));
+    if (c->ncases > 1 && c->o.block_cg) CHK(bpcg(c, c->F, c->U, c->ncases, tol, max_it, x0, info));
+    else CHK(pcg(c, c->F, c->U, c->ncases, tol, max_it, x0, info));
     dots(c, c->n, c->ncases, c->F, c->U, sc(c, 0));
     CHK(read_scal(c, sc(c, 0), c->ncases, c->J.data()));
     c->has_static = true;
