@@ -41,7 +41,10 @@ struct Level {
     int64_t n = 0;
     uint8_t* nmask = nullptr;
     double* Ke = nullptr;     // dense element matrices (levels >= 2), SoA entry-major
-    float* Kef = nullptr;
+    double* A = nullptr;      // assembled node-block stencil of K (levels >= 2)
+    float* Af = nullptr;
+    double* Ge = nullptr;     // scalar element matrices of G (levels 2 .. ell)
+    double* Gs = nullptr;     // block-diagonal node stencil of G (level ell)
     double* dinv = nullptr;
     float* dinvf = nullptr;
     double omega = 0.6;
@@ -61,9 +64,7 @@ struct mlb_ctx {
     double *dK0 = nullptr, *dHk = nullptr, *dBc = nullptr, *dD0Bc = nullptr, *dD0 = nullptr, *dT = nullptr,
            *dMc = nullptr, *dGHc = nullptr;
     float* fK0 = nullptr;
-    float* fMc = nullptr;
-    bool level2_on_the_fly = false;
-    int eig_cycle = 1;   // V (1) or W (2) cycle inside the coarse eigensolver's preconditioner   // level-2 rows from the fine moduli (no stored matrices read)
+    int eig_cycle = 1;   // V (1) or W (2) cycle inside the coarse eigensolver's preconditioner
     float whtf[72] = {};   // FP32 copy of the Walsh-Hadamard blocks (host; passed by value)
     std::vector<Level> lv;
     int64_t n = 0, m = 0;
@@ -81,7 +82,6 @@ struct mlb_ctx {
     double tol_solve = 1e-8;
     int max_it = 1000;
     double* S = nullptr;   // element stresses of the reference case (SoA nv x m)
-    double* Gl = nullptr;  // scalar G element matrices at the eigen level (> 1)
     // coarsest level dense inverse
     double* Ainv = nullptr;
     double *gj_r0 = nullptr, *gj_c0 = nullptr, *gj_r1 = nullptr, *gj_c1 = nullptr;
@@ -102,10 +102,10 @@ struct mlb_ctx {
     int64_t part_cap = 0;
     int64_t* pidx = nullptr;
     double* scal = nullptr;   // 16 blocks of kScal doubles
-    double* gbuf = nullptr;   // summed Gram matrices (up to 96 x 96)
+    double* gbuf = nullptr;   // summed Gram matrices (up to 96 x 192)
     double *cbuf = nullptr, *cbuf2 = nullptr;   // small coefficient matrices
     int* iscal = nullptr;     // active / flags
-    double* hpin = nullptr;   // pinned host scalars (>= 96 x 96)
+    double* hpin = nullptr;   // pinned host staging (96 x 192 doubles)
     // warm starts
     std::vector<double> warm_coarse;
     int warm_coarse_cols = 0;
@@ -221,11 +221,11 @@ const double* K0_of<double>(mlb_ctx* c) { return c->dK0; }
 template <>
 const float* K0_of<float>(mlb_ctx* c) { return c->fK0; }
 template <typename T>
-const T* Ke_of(Level& l);
+const T* A_of(Level& l);
 template <>
-const double* Ke_of<double>(Level& l) { return l.Ke; }
+const double* A_of<double>(Level& l) { return l.A; }
 template <>
-const float* Ke_of<float>(Level& l) { return l.Kef; }
+const float* A_of<float>(Level& l) { return l.Af; }
 template <typename T>
 const T* dinv_of(Level& l);
 template <>
@@ -246,16 +246,9 @@ int64_t fine_apply_blocks(mlb_ctx* c) {
     return c->tab.wht_ok ? apply_wht_blocks(c->dim, c->lv[0].g) : apply_fine_blocks(c->lv[0].g);
 }
 
-template <typename T>
-const T* Mc_of(mlb_ctx* c);
-template <>
-const double* Mc_of<double>(mlb_ctx* c) { return c->dMc; }
-template <>
-const float* Mc_of<float>(mlb_ctx* c) { return c->fMc; }
-
 // y = A_j x (mode Y), y = r - A_j x (residual), y = x + omega D^-1 (r - A_j x) (Jacobi).
-// Level 1 is matrix free; level 2 forms its Galerkin element rows on the fly
-// from the fine moduli; deeper levels read stored Galerkin element matrices.
+// Level 1 is matrix free; the Galerkin levels read their assembled
+// node-block stencils.
 // `clean`: x is zero at every Dirichlet DOF (always true inside the solvers,
 // whose vectors never leave the free subspace), so the level-1 kernel may
 // skip masking its inputs.
@@ -269,19 +262,14 @@ void apply_K(mlb_ctx* c, int j, int nc, const T* x, T* y, int mode, const T* r, 
     else if (j == 1)
         launch_apply_fine<T>(c->dim, l.g, E_of<T>(c), l.nmask, K0_of<T>(c), nc, l.n, x, y, mode, r,
                              dinv_of<T>(l), (T)l.omega, dot_part, c->st);
-    else if (j == 2 && c->level2_on_the_fly)
-        launch_apply_coarse<T>(c->dim, l.g, c->lv[0].g, kSrcChildE, nullptr, E_of<T>(c), Mc_of<T>(c), l.nmask, nc,
-                               l.n, x, y, mode, r, dinv_of<T>(l), (T)l.omega, c->st);
     else
-        launch_apply_coarse<T>(c->dim, l.g, l.g, kSrcDense, Ke_of<T>(l), nullptr, nullptr, l.nmask, nc, l.n, x, y,
-                               mode, r, dinv_of<T>(l), (T)l.omega, c->st);
+        launch_apply_nb<T>(c->dim, l.g, A_of<T>(l), false, nc, l.n, x, y, mode, r, dinv_of<T>(l), (T)l.omega, c->st);
 }
 
 void apply_G(mlb_ctx* c, int j, int nc, const double* x, double* y) {
     Level& l = c->lv[j - 1];
     if (j == 1) launch_apply_G_fine(c->dim, l.g, c->S, l.nmask, c->dHk, nc, l.n, x, y, c->st);
-    else launch_apply_coarse<double>(c->dim, l.g, l.g, kSrcKron, c->Gl, nullptr, nullptr, l.nmask, nc, l.n, x, y,
-                                     kModeY, nullptr, nullptr, 0.0, c->st);
+    else launch_apply_nb<double>(c->dim, l.g, l.Gs, true, nc, l.n, x, y, kModeY, nullptr, nullptr, 0.0, c->st);
 }
 
 template <typename T>
@@ -320,9 +308,9 @@ void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z) {
     const int gamma = (j + 1 == c->L) ? 1 : std::max(1, c->o.cycle);
     for (int gi = 0; gi < gamma; ++gi) {
         apply_K<T>(c, j, nc, a, t, kModeResidual, r, nullptr);
-        launch_restrict<T>(c->dim, l.g, lc.g, l.nmask, lc.nmask, nc, l.n, lc.n, t, rc, c->st);
+        launch_restrict_nb<T>(c->dim, l.g, lc.g, l.nmask, lc.nmask, nc, l.n, lc.n, t, rc, c->st);
         vcycle<T>(c, j + 1, nc, rc, zc);
-        launch_prolong<T>(c->dim, l.g, lc.g, l.nmask, lc.nmask, nc, l.n, lc.n, zc, a, true, c->st);
+        launch_prolong_nb<T>(c->dim, l.g, lc.g, l.nmask, lc.nmask, nc, l.n, lc.n, zc, a, true, c->st);
     }
     for (int s = 0; s < nu; ++s) {
         apply_K<T>(c, j, nc, a, b, kModeJacobi, r, nullptr);
@@ -359,18 +347,31 @@ int read_scal(mlb_ctx* c, const double* dev, int count, double* host) {
     return MLB_OK;
 }
 
-// Gram A^T B (n x k1, n x k2) -> host column-major k1 x k2 (G[i + k1*j]).
+// Gram A^T [B B2] (n x k1; n x k2, n x k2b) -> host column-major
+// k1 x (k2 + k2b) (G[i + k1*j]).
 int gram(mlb_ctx* c, int64_t n, int k1, const double* A, int64_t lda, int k2, const double* B, int64_t ldb,
-         std::vector<double>& G) {
-    // enough blocks to fill the GPU even for the small eigen-level blocks
-    const int np = (int)std::max<int64_t>(1, std::min<int64_t>(256, n / 256));
-    CHK(ensure_part(c, (int64_t)np * k1 * k2));
-    launch_gram_part(n, k1, lda, A, k2, ldb, B, np, c->part, c->st);
-    launch_gram_sum(k1, k2, np, c->part, c->gbuf, c->st);
-    G.resize((size_t)k1 * k2);
-    HIPC(hipMemcpyAsync(c->hpin, c->gbuf, sizeof(double) * k1 * k2, hipMemcpyDeviceToHost, c->st));
+         std::vector<double>& G, int k2b = 0, const double* B2 = nullptr, int64_t ldb2 = 0) {
+    const int kt = k2 + k2b;
+    if ((int64_t)k1 * kt > 96 * 192) return fail(c, MLB_EINVAL, "Gram matrix larger than 96 x 192");
+    const int np = gram_parts(n, k1, kt);
+    CHK(ensure_part(c, (int64_t)np * k1 * kt));
+    if (launch_gram(n, k1, lda, A, k2, ldb, B, k2b, ldb2, B2, np, c->part, c->gbuf, c->st) != 0)
+        return fail(c, MLB_EINVAL, "Gram operands wider than 192 columns");
+    G.resize((size_t)k1 * kt);
+    HIPC(hipMemcpyAsync(c->hpin, c->gbuf, sizeof(double) * k1 * kt, hipMemcpyDeviceToHost, c->st));
     CHK(sync(c));
-    std::memcpy(G.data(), c->hpin, sizeof(double) * k1 * k2);
+    std::memcpy(G.data(), c->hpin, sizeof(double) * k1 * kt);
+    return MLB_OK;
+}
+
+// G1 = A^T B1, G2 = A^T B2 (each k1 x k2) in one pass over A.
+int gram2(mlb_ctx* c, int64_t n, int k1, const double* A, int k2, const double* B1, const double* B2,
+          std::vector<double>& G1, std::vector<double>& G2) {
+    std::vector<double> G;
+    CHK(gram(c, n, k1, A, n, k2, B1, n, G, k2, B2, n));
+    const size_t h = (size_t)k1 * k2;
+    G1.assign(G.begin(), G.begin() + h);
+    G2.assign(G.begin() + h, G.begin() + 2 * h);
     return MLB_OK;
 }
 
@@ -524,8 +525,7 @@ int build_hierarchy(mlb_ctx* c) {
         Level& lc = c->lv[j - 1];
         if (j == 2) launch_galerkin_from_E(dim, lf.g, lc.g, c->Ek, c->dMc, lc.Ke, c->st);
         else launch_galerkin_dense(dim, false, lf.g, lc.g, lf.Ke, c->dT, lc.Ke, c->st);
-        if (j > 2 || !c->level2_on_the_fly) launch_to_float(lc.g.m * c->nde * c->nde, lc.Ke, lc.Kef, c->st);
-        launch_dinv_dense(dim, lc.g, lc.Ke, lc.nmask, lc.dinv, lc.dinvf, c->st);
+        launch_assemble_nb(dim, lc.g, lc.Ke, lc.nmask, lc.A, lc.Af, lc.dinv, lc.dinvf, c->st);
     }
     for (int j = 1; j < c->L; ++j) CHK(estimate_omega(c, j));
     if (c->L == 1) {
@@ -635,9 +635,12 @@ static int svqb(int r0, const std::vector<double>& G, double drop, std::vector<d
 
 // ---- Block PCG (O'Leary's block conjugate gradients, in the breakdown-free
 // form of Ji & Li: the search block is A-orthonormalised by SVQB every
-// iteration, so converged or linearly dependent directions drop out):
-//   P^T A P = I,  alpha = P^T R,  X += P alpha,  R -= Q alpha  (Q = A P)
-//   Z = M R,  beta = -Q^T Z,  P <- orth_A(Z + P beta)
+// iteration, so converged or linearly dependent directions drop out).
+// Per iteration, with Q = A P:
+//   [P^T Q, P^T R]     one Gram pass over P, Q, R
+//   T = svqb(P^T Q),  alpha = T^T P^T R                      (host, tiny)
+//   P <- P T, Q <- Q T, X += P alpha, R -= Q alpha, |R|^2   one fused pass
+//   Z = M R,  beta = -Q^T Z,  P <- Z + P beta,  Q = A P
 // All columns share one block Krylov space, which deflates the outlying
 // eigenvalues of M A for every right-hand side at once.
 int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, bool use_x0, mlb_solve_info* info) {
@@ -645,7 +648,7 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
     const int64_t n = c->n;
     if (nc > 32) return fail(c, MLB_EINVAL, "block CG supports at most 32 columns");
     CHK(ensure_cg(c, nc));
-    const int np = reduction_parts(n);
+    const int np = std::max(reduction_parts(n), bcg_step_parts(n));
     CHK(ensure_part(c, (int64_t)np * nc));
     double* bb = sc(c, 0);
     double* rr = sc(c, 1);
@@ -660,28 +663,12 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
     CHK(read_scal(c, bb, nc, hb.data()));
     for (int i = 0; i < nc; ++i)
         if (!std::isfinite(hb[i])) return fail(c, MLB_EINVAL, "non-finite right-hand side");
-    double* P = c->Pb;    // n x sp (A-orthonormal)
+    double* P = c->Pb;    // n x sp
     double* Q = c->Qb;    // A P
     double* Z = c->Zb;
-    double* T1 = c->Zo;   // scratch n x nc
-    int sp = 0;
-    std::vector<double> Gm, Tm, Cm;
-    // P <- orth_A(V), V in-place in P with its product AV in Q; returns rank
-    auto orthA = [&](int cols) -> int {
-        CHK(gram(c, n, cols, P, n, cols, Q, n, Gm));
-        const int r = svqb(cols, Gm, 1e-13, Tm);
-        if (r == 0) return MLB_OK;
-        CHK(upload_cm(c, c->cbuf, Tm));
-        launch_gemm_small(n, cols, n, P, r, c->cbuf, n, T1, c->st);
-        launch_copy_cols(n, r, n, T1, n, P, c->st);
-        launch_gemm_small(n, cols, n, Q, r, c->cbuf, n, T1, c->st);
-        launch_copy_cols(n, r, n, T1, n, Q, c->st);
-        sp = r;
-        return MLB_OK;
-    };
+    int sp = nc;
     int it = 0, status = MLB_OK;
-    auto converged = [&](bool* done) -> int {
-        dots(c, n, nc, c->R, c->R, rr);
+    auto check = [&](bool* done) -> int {
         CHK(read_scal(c, rr, nc, hr.data()));
         bool all = true;
         double w = 0;
@@ -696,32 +683,42 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
         return MLB_OK;
     };
     bool done = false;
-    CHK(converged(&done));
+    dots(c, n, nc, c->R, c->R, rr);
+    CHK(check(&done));
+    std::vector<double> G, Tm, Al, Cm;
     if (!done) {
         precondition(c, 1, nc, c->R, P);
         apply_K<double>(c, 1, nc, P, Q, kModeY, nullptr, nullptr);
-        CHK(orthA(nc));
         for (it = 1; it <= max_it; ++it) {
-            if (sp == 0) return fail(c, MLB_EBREAKDOWN, "block CG: search space collapsed");
-            // alpha = P^T R (sp x nc); X += P alpha; R -= Q alpha
-            CHK(gram(c, n, sp, P, n, nc, c->R, n, Cm));
-            CHK(upload_cm(c, c->cbuf, Cm));
-            launch_gemm_small(n, sp, n, P, nc, c->cbuf, n, T1, c->st);
-            launch_axpby(n * nc, 1.0, T1, 1.0, X, c->st);
-            launch_gemm_small(n, sp, n, Q, nc, c->cbuf, n, T1, c->st);
-            launch_axpby(n * nc, -1.0, T1, 1.0, c->R, c->st);
-            CHK(converged(&done));
+            // [P^T Q | P^T R]
+            CHK(gram(c, n, sp, P, n, sp, Q, n, G, nc, c->R, n));
+            std::vector<double> PQ(G.begin(), G.begin() + (size_t)sp * sp);
+            const int r = svqb(sp, PQ, 1e-13, Tm);
+            if (r == 0) return fail(c, MLB_EBREAKDOWN, "block CG: search space collapsed");
+            // alpha = T^T (P^T R): r x nc
+            Al.assign((size_t)r * nc, 0.0);
+            for (int j = 0; j < r; ++j)
+                for (int q = 0; q < nc; ++q) {
+                    double a = 0.0;
+                    for (int i = 0; i < sp; ++i) a += Tm[i + (size_t)sp * j] * G[(size_t)sp * sp + i + (size_t)sp * q];
+                    Al[j + (size_t)r * q] = a;
+                }
+            CHK(upload_cm(c, c->cbuf, Tm));
+            CHK(upload_cm(c, c->cbuf2, Al));
+            const int nps = bcg_step_parts(n);
+            launch_bcg_step(n, sp, r, nc, c->cbuf, c->cbuf2, P, Q, X, c->R, c->part, c->st);
+            launch_sum_parts(nc, nps, c->part, rr, c->st);
+            sp = r;
+            CHK(check(&done));
             if (done) break;
-            // Z = M R; beta = -Q^T Z; P <- Z + P beta
+            // Z = M R; beta = -Q^T Z; P <- Z + P beta; Q = A P
             precondition(c, 1, nc, c->R, Z);
             CHK(gram(c, n, sp, Q, n, nc, Z, n, Cm));
             for (auto& v : Cm) v = -v;
             CHK(upload_cm(c, c->cbuf, Cm));
-            launch_gemm_small(n, sp, n, P, nc, c->cbuf, n, T1, c->st);
-            launch_axpby(n * nc, 1.0, Z, 1.0, T1, c->st);
-            launch_copy_cols(n, nc, n, T1, n, P, c->st);
+            launch_bcg_dir(n, sp, nc, c->cbuf, Z, P, c->st);
+            sp = nc;
             apply_K<double>(c, 1, nc, P, Q, kModeY, nullptr, nullptr);
-            CHK(orthA(nc));
         }
         if (it > max_it) {
             it = max_it;
@@ -818,8 +815,7 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
     applyKA(nb, X, KX, AX);
     std::vector<double> GK, GA, ev, C;
     {
-        CHK(gram(c, n, nb, X, n, nb, KX, n, GK));
-        CHK(gram(c, n, nb, X, n, nb, AX, n, GA));
+        CHK(gram2(c, n, nb, X, nb, KX, AX, GK, GA));
         if (!rayleigh_ritz_gram(nb, nb, GK, GA, nb, ev, C))
             return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: start block is rank deficient");
         CHK(upload_cm(c, c->cbuf, C));
@@ -893,8 +889,7 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
             launch_copy_cols(n, rp, n, c->ePA, n, c->eA + n * off, c->st);
         }
         int ncol = off + rp;
-        CHK(gram(c, n, ncol, c->eS, n, ncol, c->eK, n, GK));
-        CHK(gram(c, n, ncol, c->eS, n, ncol, c->eA, n, GA));
+        CHK(gram2(c, n, ncol, c->eS, ncol, c->eK, c->eA, GK, GA));
         if (!rayleigh_ritz_gram(ncol, ncol, GK, GA, nb, ev, C)) {
             if (rp > 0 && rayleigh_ritz_gram(off, ncol, GK, GA, nb, ev, C)) {
                 if (verbose) std::fprintf(stderr, "[mlb] lobpcg it %d: dropped P\n", it);
@@ -932,30 +927,20 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
 }
 
 // G element matrices at the eigen level from the reference stresses.
+// Galerkin G^j = P^T G^{j-1} P for j = 2 .. ell (scalar element matrices,
+// since G_e = g_e kron I), then the masked block-diagonal stencil at ell.
 int build_G_levels(mlb_ctx* c) {
     if (c->ell == 1) return MLB_OK;
-    const int dim = c->dim, nn2 = c->nn * c->nn;
-    double* prev = nullptr;
-    double* cur = nullptr;
+    const int dim = c->dim;
     for (int j = 2; j <= c->ell; ++j) {
         Level& lf = c->lv[j - 2];
         Level& lc = c->lv[j - 1];
-        double* out = (j == c->ell) ? c->Gl : nullptr;
-        if (!out) {
-            out = nullptr;
-            CHK(dalloc(c, &out, (size_t)lc.g.m * nn2));
-        }
-        if (j == 2) launch_galerkin_G_from_S(dim, lf.g, lc.g, c->S, c->dGHc, out, c->st);
-        else launch_galerkin_dense(dim, true, lf.g, lc.g, prev, c->dT, out, c->st);
-        if (prev) {
-            CHK(sync(c));
-            dfree(prev);
-        }
-        prev = (j == c->ell) ? nullptr : out;
-        cur = out;
+        if (j == 2) launch_galerkin_G_from_S(dim, lf.g, lc.g, c->S, c->dGHc, lc.Ge, c->st);
+        else launch_galerkin_dense(dim, true, lf.g, lc.g, lf.Ge, c->dT, lc.Ge, c->st);
     }
-    (void)cur;
-    CHK(sync(c));
+    Level& le = c->lv[c->ell - 1];
+    launch_assemble_nb_diag(dim, le.g, le.Ge, le.nmask, le.Gs, c->st);
+    HIPC(hipGetLastError());
     return MLB_OK;
 }
 
@@ -990,7 +975,7 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         Level& lf = c->lv[j - 1];
         Level& lc = c->lv[j];
         double* dst = j == 1 ? c->X1 : lf.vt;
-        launch_prolong<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, k, lf.n, ldc, cur, dst, false, c->st);
+        launch_prolong_nb<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, k, lf.n, ldc, cur, dst, false, c->st);
         cur = dst;
         ldc = lf.n;
     }
@@ -1005,8 +990,7 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
     apply_K<double>(c, 1, k, c->Phi, c->X1, kModeY, nullptr, nullptr);
     apply_G(c, 1, k, c->Phi, c->X2);
     std::vector<double> A, B;
-    CHK(gram(c, n, k, c->Phi, n, k, c->X1, n, A));
-    CHK(gram(c, n, k, c->Phi, n, k, c->X2, n, B));
+    CHK(gram2(c, n, k, c->Phi, k, c->X1, c->X2, A, B));
     std::vector<double> A2(k * k), B2(k * k), ev(k), Y(k * k);
     for (int a = 0; a < k; ++a)
         for (int q = 0; q < k; ++q) {
@@ -1154,12 +1138,6 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     CHK(dalloc(c, &c->dGHc, 8 * 6 * 64));
     float k0f[576];
     for (int i = 0; i < 576; ++i) k0f[i] = (float)c->tab.K0[i];
-    CHK(dalloc(c, &c->fMc, 8 * 576));
-    {
-        std::vector<float> mcf(8 * 576);
-        for (int i = 0; i < 8 * 576; ++i) mcf[i] = (float)c->tab.Mc[i];
-        HIPC(hipMemcpy(c->fMc, mcf.data(), sizeof(float) * mcf.size(), hipMemcpyHostToDevice));
-    }
     HIPC(hipMemcpy(c->dK0, c->tab.K0, sizeof(double) * 576, hipMemcpyHostToDevice));
     HIPC(hipMemcpy(c->fK0, k0f, sizeof(float) * 576, hipMemcpyHostToDevice));
     HIPC(hipMemcpy(c->dHk, c->tab.Hk, sizeof(double) * 6 * 64, hipMemcpyHostToDevice));
@@ -1181,8 +1159,12 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
         HIPC(hipMemset(l.nmask, 0, (size_t)l.g.nodes));
         CHK(dalloc(c, &l.dinv, (size_t)l.n));
         CHK(dalloc(c, &l.dinvf, (size_t)l.n));
-        if (j > 0) CHK(dalloc(c, &l.Ke, (size_t)l.g.m * c->nde * c->nde));
-        if (j > 0) CHK(dalloc(c, &l.Kef, (size_t)l.g.m * c->nde * c->nde));
+        if (j > 0) {
+            CHK(dalloc(c, &l.Ke, (size_t)l.g.m * c->nde * c->nde));
+            CHK(dalloc(c, &l.A, (size_t)stencil_entries(dim, l.g, false)));
+            CHK(dalloc(c, &l.Af, (size_t)stencil_entries(dim, l.g, false)));
+        }
+        if (j > 0 && j < c->ell) CHK(dalloc(c, &l.Ge, (size_t)l.g.m * c->nn * c->nn));
     }
     c->n = c->lv[0].n;
     c->m = c->lv[0].g.m;
@@ -1198,7 +1180,10 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
         CHK(dalloc(c, &c->gj_r1, (size_t)nL));
         CHK(dalloc(c, &c->gj_c1, (size_t)nL));
     }
-    if (c->ell > 1) CHK(dalloc(c, &c->Gl, (size_t)c->lv[c->ell - 1].g.m * c->nn * c->nn));
+    if (c->ell > 1) {
+        Level& le = c->lv[c->ell - 1];
+        CHK(dalloc(c, &le.Gs, (size_t)stencil_entries(dim, le.g, true)));
+    }
     CHK(dalloc(c, &c->x, (size_t)c->m));
     CHK(dalloc(c, &c->Ek, (size_t)c->m));
     CHK(dalloc(c, &c->Ekf, (size_t)c->m));
@@ -1207,10 +1192,10 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     CHK(dalloc(c, &c->fixed, (size_t)c->n));
     CHK(dalloc(c, &c->scal, (size_t)16 * kScal));
     CHK(dalloc(c, &c->iscal, (size_t)2 * kScal));
-    CHK(dalloc(c, &c->gbuf, (size_t)96 * 96));
+    CHK(dalloc(c, &c->gbuf, (size_t)96 * 192));
     CHK(dalloc(c, &c->cbuf, (size_t)96 * 96));
     CHK(dalloc(c, &c->cbuf2, (size_t)96 * 96));
-    HIPC(hipHostMalloc((void**)&c->hpin, sizeof(double) * 96 * 96, hipHostMallocDefault));
+    HIPC(hipHostMalloc((void**)&c->hpin, sizeof(double) * 96 * 192, hipHostMallocDefault));
     CHK(ensure_part(c, 4096));
     CHK(ensure_level_cols(c, 1));
     return MLB_OK;
@@ -1220,12 +1205,12 @@ void mlb_destroy(mlb_ctx* c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
     for (auto& l : c->lv) {
-        dfree(l.nmask); dfree(l.Ke); dfree(l.Kef); dfree(l.dinv); dfree(l.dinvf);
+        dfree(l.nmask); dfree(l.Ke); dfree(l.A); dfree(l.Af); dfree(l.Ge); dfree(l.Gs); dfree(l.dinv); dfree(l.dinvf);
         dfree(l.vr); dfree(l.vz); dfree(l.vz2); dfree(l.vt); dfree(l.fr); dfree(l.fz); dfree(l.fz2); dfree(l.ft);
     }
     dfree(c->dK0); dfree(c->fK0); dfree(c->dHk); dfree(c->dBc); dfree(c->dD0Bc); dfree(c->dD0); dfree(c->dT);
-    dfree(c->dMc); dfree(c->fMc); dfree(c->dGHc); dfree(c->x); dfree(c->Ek); dfree(c->Ekf); dfree(c->Es); dfree(c->fixed);
-    dfree(c->F); dfree(c->U); dfree(c->S); dfree(c->Gl); dfree(c->Ainv); dfree(c->gj_r0); dfree(c->gj_c0);
+    dfree(c->dMc); dfree(c->dGHc); dfree(c->x); dfree(c->Ek); dfree(c->Ekf); dfree(c->Es); dfree(c->fixed);
+    dfree(c->F); dfree(c->U); dfree(c->S); dfree(c->Ainv); dfree(c->gj_r0); dfree(c->gj_c0);
     dfree(c->gj_r1); dfree(c->gj_c1); dfree(c->R); dfree(c->Zb); dfree(c->Pb); dfree(c->Qb); dfree(c->Zo);
     dfree(c->X1); dfree(c->X2); dfree(c->Phi); dfree(c->Zadj); dfree(c->dlam_l); dfree(c->eS); dfree(c->eK);
     dfree(c->eA); dfree(c->eT); dfree(c->eTK); dfree(c->eTA); dfree(c->eR); dfree(c->eP); dfree(c->ePK); dfree(c->ePA); dfree(c->part); dfree(c->pidx);
@@ -1546,7 +1531,7 @@ int mlb_prolong_dev(mlb_ctx* c, int level, int ncols, const double* xc, double* 
     c->st = pick(c, stream);
     Level& lf = c->lv[level - 1];
     Level& lc = c->lv[level];
-    launch_prolong<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, ncols, lf.n, lc.n, xc, yf, false, c->st);
+    launch_prolong_nb<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, ncols, lf.n, lc.n, xc, yf, false, c->st);
     HIPC(hipGetLastError());
     return MLB_OK;
 }
@@ -1558,7 +1543,7 @@ int mlb_restrict_dev(mlb_ctx* c, int level, int ncols, const double* xf, double*
     c->st = pick(c, stream);
     Level& lf = c->lv[level - 1];
     Level& lc = c->lv[level];
-    launch_restrict<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, ncols, lf.n, lc.n, xf, yc, c->st);
+    launch_restrict_nb<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, ncols, lf.n, lc.n, xf, yc, c->st);
     HIPC(hipGetLastError());
     return MLB_OK;
 }

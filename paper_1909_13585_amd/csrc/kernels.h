@@ -11,23 +11,26 @@ template <typename T>
 void launch_apply_fine(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* K0, int ncols,
                        int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega,
                        double* dot_part, hipStream_t st);
-enum { kSrcDense = 0, kSrcKron = 1, kSrcChildE = 2 };
-template <typename T>
-void launch_apply_coarse(int dim, const Geo& g, const Geo& gfine, int src, const T* Ke, const T* Efine,
-                         const T* Mc, const uint8_t* nmask, int ncols, int64_t ld, const T* x, T* y, int mode,
-                         const T* r, const T* dinv, T omega, hipStream_t st);
 void launch_apply_G_fine(int dim, const Geo& g, const double* S, const uint8_t* nmask, const double* Hk,
                          int ncols, int64_t ld, const double* x, double* y, hipStream_t st);
 void launch_dinv_fine(int dim, const Geo& g, const double* E, const uint8_t* nmask, const double* K0,
                       double* dinv, float* dinvf, hipStream_t st);
-void launch_dinv_dense(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, double* dinv,
-                       float* dinvf, hipStream_t st);
+
+// ---- assembled node-block stencils and transfers (kernels_stencil.hip)
+int64_t stencil_entries(int dim, const Geo& g, bool diag);
+void launch_assemble_nb(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, double* A, float* Af,
+                        double* dinv, float* dinvf, hipStream_t st);
+void launch_assemble_nb_diag(int dim, const Geo& g, const double* Ge, const uint8_t* nmask, double* A,
+                             hipStream_t st);
 template <typename T>
-void launch_prolong(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
-                    int64_t ldf, int64_t ldc, const T* xc, T* yf, bool add, hipStream_t st);
+void launch_apply_nb(int dim, const Geo& g, const T* A, bool diag, int ncols, int64_t ld, const T* x, T* y, int mode,
+                     const T* r, const T* dinv, T omega, hipStream_t st);
 template <typename T>
-void launch_restrict(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
-                     int64_t ldf, int64_t ldc, const T* xf, T* yc, hipStream_t st);
+void launch_prolong_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
+                       int64_t ldf, int64_t ldc, const T* xc, T* yf, bool add, hipStream_t st);
+template <typename T>
+void launch_restrict_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
+                        int64_t ldf, int64_t ldc, const T* xf, T* yc, hipStream_t st);
 
 // ---- element-centric Walsh-Hadamard apply (kernels_wht.hip)
 int64_t apply_wht_blocks(int dim, const Geo& g);
@@ -81,9 +84,16 @@ void launch_copy_cols(int64_t n, int ncols, int64_t lds, const double* s, int64_
                       hipStream_t st);
 void launch_axpy_cols(int64_t n, int ncols, int64_t ld, const double* coef, double sign, const double* x,
                       double* y, hipStream_t st);
-void launch_gram_part(int64_t n, int k1, int64_t lda, const double* A, int k2, int64_t ldb, const double* B,
-                      int nparts, double* part, hipStream_t st);
-void launch_gram_sum(int k1, int k2, int nparts, const double* part, double* out, hipStream_t st);
+// G (device, column-major k1 x (k2a + k2b)) = A^T [B1 B2]; nparts blocks of
+// partials (gram_parts) in part; returns -1 if k1 + k2a + k2b > 192.
+int gram_parts(int64_t n, int k1, int k2);
+int launch_gram(int64_t n, int k1, int64_t lda, const double* A, int k2a, int64_t ldb1, const double* B1, int k2b,
+                int64_t ldb2, const double* B2, int nparts, double* part, double* out, hipStream_t st);
+// block CG row updates (sp, r, nc <= 32)
+int bcg_step_parts(int64_t n);
+void launch_bcg_step(int64_t n, int sp, int r, int nc, const double* T, const double* alpha, double* P, double* Q,
+                     double* X, double* R, double* rr_part, hipStream_t st);
+void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const double* Z, double* P, hipStream_t st);
 void launch_gemm_small(int64_t n, int k1, int64_t lds, const double* S, int k2, const double* C, int64_t ldy,
                        double* Y, hipStream_t st);
 void launch_residual_block(int64_t n, int ncols, int64_t ld, const double* AX, const double* KX,

@@ -193,107 +193,6 @@ __global__ __launch_bounds__(256) void k_apply_fine(Geo g, const T* __restrict__
 //               moduli of the 2^dim children (Mc = T_c^T K0 T_c, in LDS).
 // Column chunks of CB reuse every matrix entry.
 
-template <int DIM, typename T, int MODE, int SRC, int CB>
-__global__ __launch_bounds__(256) void k_apply_coarse(Geo g, Geo gfine, const T* __restrict__ Ke,
-                                                      const T* __restrict__ Efine, const T* __restrict__ Mc,
-                                                      const uint8_t* __restrict__ nmask, int ncols,
-                                                      int64_t ld, const T* __restrict__ x, T* __restrict__ y,
-                                                      const T* __restrict__ r, const T* __restrict__ dinv,
-                                                      T omega) {
-    using N = Nb<DIM>;
-    constexpr int NM = SRC == kSrcChildE ? (1 << DIM) * N::NDE * N::NDE : 1;
-    __shared__ T mcs[NM];
-    if (SRC == kSrcChildE) {
-        const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-        for (int q = tid; q < NM; q += blockDim.x * blockDim.y) {
-            const int ch = q / (N::NDE * N::NDE), ent = q % (N::NDE * N::NDE);
-            mcs[q] = Mc[ch * 576 + ent];
-        }
-        __syncthreads();
-    }
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = DIM == 3 ? blockIdx.z : 0;
-    if (i >= g.nnx || j >= g.nny) return;
-    const int64_t node = i + (int64_t)g.nnx * (j + (int64_t)g.nny * k);
-    const uint8_t own = nmask[node];
-    const int64_t m = g.m;
-    for (int c0 = 0; c0 < ncols; c0 += CB) {
-        T acc[CB][N::ND];
-#pragma unroll
-        for (int q = 0; q < CB; ++q)
-#pragma unroll
-            for (int c = 0; c < N::ND; ++c) acc[q][c] = T(0);
-        for (int s = 0; s < N::NN; ++s) {
-            bool eok;
-            const int64_t e = elem_of_slot<DIM>(g, i, j, k, s, eok);
-            if (!eok) continue;
-            const int ox = s & 1, oy = (s >> 1) & 1, oz = (s >> 2) & 1;
-            const int a = (N::NN - 1) ^ s;
-            T Ech[1 << DIM];
-            if (SRC == kSrcChildE) {
-                const int ei = i - 1 + ox, ej = j - 1 + oy, ek = DIM == 3 ? k - 1 + oz : 0;
-#pragma unroll
-                for (int ch = 0; ch < (1 << DIM); ++ch)
-                    Ech[ch] = Efine[(2 * ei + (ch & 1)) +
-                                    (int64_t)gfine.nx * ((2 * ej + ((ch >> 1) & 1)) + (int64_t)gfine.ny * (2 * ek + ((ch >> 2) & 1)))];
-            }
-#pragma unroll 2
-            for (int b = 0; b < N::NN; ++b) {
-                const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-                const int ii = i - 1 + ox + bx, jj = j - 1 + oy + by, kk = DIM == 3 ? k - 1 + oz + bz : 0;
-                const int64_t nn = ii + (int64_t)g.nnx * (jj + (int64_t)g.nny * kk);
-                const uint8_t mb = nmask[nn];
-                T xv[CB][N::ND];
-#pragma unroll
-                for (int q = 0; q < CB; ++q)
-#pragma unroll
-                    for (int c = 0; c < N::ND; ++c)
-                        xv[q][c] = ((mb >> c) & 1) || (c0 + q >= ncols) ? T(0) : x[(c0 + q) * ld + nn * N::ND + c];
-                if (SRC == kSrcKron) {
-                    const T gv = Ke[(int64_t)(a * N::NN + b) * m + e];
-#pragma unroll
-                    for (int q = 0; q < CB; ++q)
-#pragma unroll
-                        for (int c = 0; c < N::ND; ++c) acc[q][c] += gv * xv[q][c];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < N::ND; ++c)
-#pragma unroll
-                        for (int c2 = 0; c2 < N::ND; ++c2) {
-                            const int ent = (a * N::ND + c) * N::NDE + b * N::ND + c2;
-                            T kv;
-                            if (SRC == kSrcDense) {
-                                kv = Ke[(int64_t)ent * m + e];
-                            } else {
-                                kv = T(0);
-#pragma unroll
-                                for (int ch = 0; ch < (1 << DIM); ++ch)
-                                    kv += Ech[ch] * mcs[ch * N::NDE * N::NDE + ent];
-                            }
-#pragma unroll
-                            for (int q = 0; q < CB; ++q) acc[q][c] += kv * xv[q][c2];
-                        }
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < CB; ++q) {
-            if (c0 + q >= ncols) continue;
-            const int col = c0 + q;
-#pragma unroll
-            for (int c = 0; c < N::ND; ++c) {
-                const int64_t d = node * N::ND + c;
-                const T xown = x[col * ld + d];
-                const T ax = (own >> c) & 1 ? (SRC == kSrcKron ? T(0) : xown) : acc[q][c];
-                const T rr = MODE == kModeY ? T(0) : r[col * ld + d];
-                const T di = MODE == kModeJacobi ? dinv[d] : T(0);
-                y[col * ld + d] = epilogue<T, MODE>(ax, xown, rr, di, omega);
-            }
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Level-1 stress-stiffness apply from element stresses S (SoA nv x m):
 // G_e = (sum_k S_k,e Hk_k) kron I.
@@ -385,116 +284,6 @@ __global__ void k_dinv_fine(Geo g, const double* __restrict__ E, const uint8_t* 
     }
 }
 
-template <int DIM>
-__global__ void k_dinv_dense(Geo g, const double* __restrict__ Ke, const uint8_t* __restrict__ nmask,
-                             double* __restrict__ dinv, float* __restrict__ dinvf) {
-    using N = Nb<DIM>;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = DIM == 3 ? blockIdx.z : 0;
-    if (i >= g.nnx || j >= g.nny) return;
-    const int64_t node = i + (int64_t)g.nnx * (j + (int64_t)g.nny * k);
-    const uint8_t own = nmask[node];
-#pragma unroll
-    for (int c = 0; c < N::ND; ++c) {
-        double d = 0.0;
-#pragma unroll
-        for (int s = 0; s < N::NN; ++s) {
-            bool ok;
-            const int64_t e = elem_of_slot<DIM>(g, i, j, k, s, ok);
-            const int a = (N::NN - 1) ^ s;
-            const int row = a * N::ND + c;
-            if (ok) d += Ke[(int64_t)(row * N::NDE + row) * g.m + e];
-        }
-        const double v = (own >> c) & 1 ? 1.0 : (d > 0.0 ? 1.0 / d : 0.0);
-        dinv[node * N::ND + c] = v;
-        dinvf[node * N::ND + c] = (float)v;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Transfers between level j (fine, gf) and j+1 (coarse, gc): nodal
-// bilinear/trilinear interpolation P and its transpose, masked both sides.
-
-template <int DIM, typename T, bool ADD>
-__global__ void k_prolong(Geo gf, Geo gc, const uint8_t* __restrict__ mf, const uint8_t* __restrict__ mc,
-                          int ncols, int64_t ldf, int64_t ldc, const T* __restrict__ xc, T* __restrict__ yf) {
-    constexpr int ND = DIM;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = DIM == 3 ? blockIdx.z : 0;
-    if (i >= gf.nnx || j >= gf.nny) return;
-    const int64_t node = i + (int64_t)gf.nnx * (j + (int64_t)gf.nny * k);
-    const uint8_t own = mf[node];
-    const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
-    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
-    const T w = T(1) / T(ni * nj * nk);
-    for (int col = 0; col < ncols; ++col) {
-        T acc[ND];
-#pragma unroll
-        for (int c = 0; c < ND; ++c) acc[c] = T(0);
-        for (int dk = 0; dk < nk; ++dk)
-            for (int dj = 0; dj < nj; ++dj)
-                for (int di = 0; di < ni; ++di) {
-                    const int64_t cn = (i0 + di) + (int64_t)gc.nnx * ((j0 + dj) + (int64_t)gc.nny * (k0 + dk));
-                    const uint8_t cm = mc[cn];
-#pragma unroll
-                    for (int c = 0; c < ND; ++c)
-                        if (!((cm >> c) & 1)) acc[c] += xc[col * ldc + cn * ND + c];
-                }
-#pragma unroll
-        for (int c = 0; c < ND; ++c) {
-            const int64_t d = col * ldf + node * ND + c;
-            if ((own >> c) & 1) {
-                if (!ADD) yf[d] = T(0);
-            } else {
-                yf[d] = ADD ? yf[d] + w * acc[c] : w * acc[c];
-            }
-        }
-    }
-}
-
-template <int DIM, typename T>
-__global__ void k_restrict(Geo gf, Geo gc, const uint8_t* __restrict__ mf, const uint8_t* __restrict__ mc,
-                           int ncols, int64_t ldf, int64_t ldc, const T* __restrict__ xf, T* __restrict__ yc) {
-    constexpr int ND = DIM;
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    const int J = blockIdx.y * blockDim.y + threadIdx.y;
-    const int K = DIM == 3 ? blockIdx.z : 0;
-    if (I >= gc.nnx || J >= gc.nny) return;
-    const int64_t cnode = I + (int64_t)gc.nnx * (J + (int64_t)gc.nny * K);
-    const uint8_t own = mc[cnode];
-    const int kr = DIM == 3 ? 1 : 0;
-    for (int col = 0; col < ncols; ++col) {
-        T acc[ND];
-#pragma unroll
-        for (int c = 0; c < ND; ++c) acc[c] = T(0);
-        for (int dk = -kr; dk <= kr; ++dk) {
-            const int kk = 2 * K + dk;
-            if (kk < 0 || kk >= gf.nnz) continue;
-            const T wk = dk == 0 ? T(1) : T(0.5);
-            for (int dj = -1; dj <= 1; ++dj) {
-                const int jj = 2 * J + dj;
-                if (jj < 0 || jj >= gf.nny) continue;
-                const T wj = dj == 0 ? wk : wk * T(0.5);
-                for (int di = -1; di <= 1; ++di) {
-                    const int ii = 2 * I + di;
-                    if (ii < 0 || ii >= gf.nnx) continue;
-                    const T w = di == 0 ? wj : wj * T(0.5);
-                    const int64_t fn = ii + (int64_t)gf.nnx * (jj + (int64_t)gf.nny * kk);
-                    const uint8_t fm = mf[fn];
-#pragma unroll
-                    for (int c = 0; c < ND; ++c)
-                        if (!((fm >> c) & 1)) acc[c] += w * xf[col * ldf + fn * ND + c];
-                }
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < ND; ++c)
-            yc[col * ldc + cnode * ND + c] = (own >> c) & 1 ? T(0) : acc[c];
-    }
-}
-
 // ---------------------------------------------------------------------------
 // host launchers
 
@@ -532,37 +321,6 @@ void launch_apply_fine(int dim, const Geo& g, const T* E, const uint8_t* nmask, 
 #undef MLB_LAUNCH
 }
 
-template <typename T>
-void launch_apply_coarse(int dim, const Geo& g, const Geo& gfine, int src, const T* Ke, const T* Efine,
-                         const T* Mc, const uint8_t* nmask, int ncols, int64_t ld, const T* x, T* y, int mode,
-                         const T* r, const T* dinv, T omega, hipStream_t st) {
-    dim3 b;
-    dim3 gr = node_grid(g, b);
-#define MLB_LAUNCH(D, M, S, CB)                                                                           \
-    hipLaunchKernelGGL((k_apply_coarse<D, T, M, S, CB>), gr, b, 0, st, g, gfine, Ke, Efine, Mc, nmask, ncols, \
-                       ld, x, y, r, dinv, omega)
-#define MLB_MODES(D, S, CB)                                                     \
-    if (mode == kModeY) MLB_LAUNCH(D, kModeY, S, CB);                           \
-    else if (mode == kModeResidual) MLB_LAUNCH(D, kModeResidual, S, CB);        \
-    else MLB_LAUNCH(D, kModeJacobi, S, CB);
-#define MLB_CB(D, S)                                \
-    if (ncols == 1) { MLB_MODES(D, S, 1) }          \
-    else if (ncols <= 4) { MLB_MODES(D, S, 4) }     \
-    else { MLB_MODES(D, S, 8) }
-    if (dim == 2) {
-        if (src == kSrcKron) { if (ncols == 1) MLB_LAUNCH(2, kModeY, kSrcKron, 1); else MLB_LAUNCH(2, kModeY, kSrcKron, 4); }
-        else if (src == kSrcChildE) { if (ncols == 1) { MLB_MODES(2, kSrcChildE, 1) } else { MLB_MODES(2, kSrcChildE, 4) } }
-        else { MLB_CB(2, kSrcDense) }
-    } else {
-        if (src == kSrcKron) { if (ncols == 1) MLB_LAUNCH(3, kModeY, kSrcKron, 1); else MLB_LAUNCH(3, kModeY, kSrcKron, 4); }
-        else if (src == kSrcChildE) { if (ncols == 1) { MLB_MODES(3, kSrcChildE, 1) } else { MLB_MODES(3, kSrcChildE, 4) } }
-        else { MLB_CB(3, kSrcDense) }
-    }
-#undef MLB_CB
-#undef MLB_MODES
-#undef MLB_LAUNCH
-}
-
 void launch_apply_G_fine(int dim, const Geo& g, const double* S, const uint8_t* nmask, const double* Hk,
                          int ncols, int64_t ld, const double* x, double* y, hipStream_t st) {
     dim3 b;
@@ -579,56 +337,11 @@ void launch_dinv_fine(int dim, const Geo& g, const double* E, const uint8_t* nma
     else hipLaunchKernelGGL(k_dinv_fine<3>, gr, b, 0, st, g, E, nmask, K0, dinv, dinvf);
 }
 
-void launch_dinv_dense(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, double* dinv,
-                       float* dinvf, hipStream_t st) {
-    dim3 b;
-    dim3 gr = node_grid(g, b);
-    if (dim == 2) hipLaunchKernelGGL(k_dinv_dense<2>, gr, b, 0, st, g, Ke, nmask, dinv, dinvf);
-    else hipLaunchKernelGGL(k_dinv_dense<3>, gr, b, 0, st, g, Ke, nmask, dinv, dinvf);
-}
-
-template <typename T>
-void launch_prolong(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
-                    int64_t ldf, int64_t ldc, const T* xc, T* yf, bool add, hipStream_t st) {
-    dim3 b;
-    dim3 gr = node_grid(gf, b);
-    if (dim == 2) {
-        if (add) hipLaunchKernelGGL((k_prolong<2, T, true>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xc, yf);
-        else hipLaunchKernelGGL((k_prolong<2, T, false>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xc, yf);
-    } else {
-        if (add) hipLaunchKernelGGL((k_prolong<3, T, true>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xc, yf);
-        else hipLaunchKernelGGL((k_prolong<3, T, false>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xc, yf);
-    }
-}
-
-template <typename T>
-void launch_restrict(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
-                     int64_t ldf, int64_t ldc, const T* xf, T* yc, hipStream_t st) {
-    dim3 b;
-    dim3 gr = node_grid(gc, b);
-    if (dim == 2) hipLaunchKernelGGL((k_restrict<2, T>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xf, yc);
-    else hipLaunchKernelGGL((k_restrict<3, T>), gr, b, 0, st, gf, gc, mf, mc, ncols, ldf, ldc, xf, yc);
-}
-
 template void launch_apply_fine<double>(int, const Geo&, const double*, const uint8_t*, const double*, int,
                                         int64_t, const double*, double*, int, const double*, const double*,
                                         double, double*, hipStream_t);
 template void launch_apply_fine<float>(int, const Geo&, const float*, const uint8_t*, const float*, int,
                                        int64_t, const float*, float*, int, const float*, const float*, float,
                                        double*, hipStream_t);
-template void launch_apply_coarse<double>(int, const Geo&, const Geo&, int, const double*, const double*,
-                                          const double*, const uint8_t*, int, int64_t, const double*, double*, int,
-                                          const double*, const double*, double, hipStream_t);
-template void launch_apply_coarse<float>(int, const Geo&, const Geo&, int, const float*, const float*,
-                                         const float*, const uint8_t*, int, int64_t, const float*, float*, int,
-                                         const float*, const float*, float, hipStream_t);
-template void launch_prolong<double>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
-                                     int64_t, const double*, double*, bool, hipStream_t);
-template void launch_prolong<float>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
-                                    int64_t, const float*, float*, bool, hipStream_t);
-template void launch_restrict<double>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
-                                      int64_t, const double*, double*, hipStream_t);
-template void launch_restrict<float>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
-                                     int64_t, const float*, float*, hipStream_t);
 
 }  // namespace mlb

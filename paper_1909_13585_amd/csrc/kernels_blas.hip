@@ -3,6 +3,8 @@
 // Reductions are two-stage and deterministic: each block writes one partial
 // per column (fixed-order wavefront trees), then a single block per output
 // sums the partials in index order.  No atomics.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace mlb {
@@ -186,68 +188,238 @@ __global__ void k_axpy_cols(int64_t n, int ncols, int64_t ld, const double* __re
 
 // ---- Gram products A^T B (n x k1, n x k2): partial per block of rows
 // Rows are staged through LDS in chunks of 32; each thread owns outputs.
-constexpr int kGramChunk = 32;
-constexpr int kGramMax = 96;
+// ---------------------------------------------------------------------------
+// Gram matrices G = A^T [B1 B2] (A: n x k1, B1: n x k2a, B2: n x k2b, all
+// column-major).  Bandwidth-bound: every block streams slabs of `rows`
+// consecutive rows of all operands into LDS (coalesced, one wave per column),
+// then each thread accumulates a TS x TS tile of G over a strided subset of
+// the slab rows in registers.  Tiles x row-groups fill the 256 threads; the
+// row groups are summed through LDS in a fixed order at the end and every
+// block writes one partial G, reduced by k_gram_reduce in block order, so
+// the result is deterministic.
+constexpr int kGramThreads = 256;
+constexpr int kGramMaxCols = 192;   // k1 + k2a + k2b
 
-__global__ __launch_bounds__(256) void k_gram_part(int64_t n, int k1, int64_t lda, const double* __restrict__ A,
-                                                   int k2, int64_t ldb, const double* __restrict__ B,
-                                                   double* __restrict__ part) {
-    __shared__ double sa[kGramChunk][kGramMax];
-    __shared__ double sb[kGramChunk][kGramMax];
-    const int nout = k1 * k2;
-    double acc[24];
-    const int per = (nout + blockDim.x - 1) / blockDim.x;   // <= 24 when k1*k2 <= 6144
+template <int TS>
+__global__ __launch_bounds__(kGramThreads) void k_gram(int64_t n, int rows, int k1, int64_t lda,
+                                                       const double* __restrict__ A, int k2a, int64_t ldb1,
+                                                       const double* __restrict__ B1, int k2b, int64_t ldb2,
+                                                       const double* __restrict__ B2, double* __restrict__ part) {
+    extern __shared__ double sm[];
+    const int k2 = k2a + k2b;
+    const int stride = rows + 1;            // padded column stride (bank spread)
+    double* sa = sm;
+    double* sb = sm + (size_t)k1 * stride;
+    const int ti_n = (k1 + TS - 1) / TS, tj_n = (k2 + TS - 1) / TS;
+    const int ntile = ti_n * tj_n;
+    const int rg_n = max(1, min(rows, kGramThreads / ntile));
+    const int t = threadIdx.x;
+    const bool active = t < ntile * rg_n;
+    const int tile = active ? t / rg_n : 0, rg = active ? t % rg_n : 0;
+    const int ti = tile % ti_n, tj = tile / ti_n;
+    int ca[TS], cb[TS];
 #pragma unroll
-    for (int t = 0; t < 24; ++t) acc[t] = 0.0;
-    const int64_t nchunks = (n + kGramChunk - 1) / kGramChunk;
-    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const int64_t r0 = ch * kGramChunk;
-        __syncthreads();
-        for (int t = threadIdx.x; t < kGramChunk * k1; t += blockDim.x) {
-            const int rr = t % kGramChunk, cc = t / kGramChunk;
-            const int64_t row = r0 + rr;
-            sa[rr][cc] = row < n ? A[cc * lda + row] : 0.0;
-        }
-        for (int t = threadIdx.x; t < kGramChunk * k2; t += blockDim.x) {
-            const int rr = t % kGramChunk, cc = t / kGramChunk;
-            const int64_t row = r0 + rr;
-            sb[rr][cc] = row < n ? B[cc * ldb + row] : 0.0;
-        }
-        __syncthreads();
+    for (int u = 0; u < TS; ++u) {
+        ca[u] = min(ti * TS + u, k1 - 1) * stride;   // clamped: extra rows/cols are discarded
+        cb[u] = min(tj * TS + u, k2 - 1) * stride;
+    }
+    double acc[TS][TS];
 #pragma unroll
-        for (int t = 0; t < 24; ++t) {
-            if (t >= per) break;
-            const int o = threadIdx.x + t * blockDim.x;
-            if (o >= nout) break;
-            const int i = o % k1, j = o / k1;
-            double s = acc[t];
-            for (int rr = 0; rr < kGramChunk; ++rr) s += sa[rr][i] * sb[rr][j];
-            acc[t] = s;
+    for (int u = 0; u < TS; ++u)
+#pragma unroll
+        for (int v = 0; v < TS; ++v) acc[u][v] = 0.0;
+    const int64_t nslab = (n + rows - 1) / rows;
+    for (int64_t sl = blockIdx.x; sl < nslab; sl += gridDim.x) {
+        const int64_t r0 = sl * rows;
+        __syncthreads();
+        for (int e = t; e < k1 * rows; e += kGramThreads) {
+            const int r = e % rows, cc = e / rows;
+            const int64_t row = r0 + r;
+            sa[cc * stride + r] = row < n ? A[cc * lda + row] : 0.0;
+        }
+        for (int e = t; e < k2 * rows; e += kGramThreads) {
+            const int r = e % rows, cc = e / rows;
+            const int64_t row = r0 + r;
+            double v = 0.0;
+            if (row < n) v = cc < k2a ? B1[cc * ldb1 + row] : B2[(cc - k2a) * ldb2 + row];
+            sb[cc * stride + r] = v;
+        }
+        __syncthreads();
+        if (active) {
+            for (int r = rg; r < rows; r += rg_n) {
+                double av[TS], bv[TS];
+#pragma unroll
+                for (int u = 0; u < TS; ++u) {
+                    av[u] = sa[ca[u] + r];
+                    bv[u] = sb[cb[u] + r];
+                }
+#pragma unroll
+                for (int u = 0; u < TS; ++u)
+#pragma unroll
+                    for (int v = 0; v < TS; ++v) acc[u][v] += av[u] * bv[v];
+            }
         }
     }
+    // sum the row groups of each tile entry, one entry position at a time
+    const int nout = k1 * k2;
+    double* red = sm;
 #pragma unroll
-    for (int t = 0; t < 24; ++t) {
-        if (t >= per) break;
-        const int o = threadIdx.x + t * blockDim.x;
-        if (o >= nout) break;
-        part[(int64_t)blockIdx.x * nout + o] = acc[t];
+    for (int u = 0; u < TS; ++u)
+#pragma unroll
+        for (int v = 0; v < TS; ++v) {
+            __syncthreads();
+            red[t] = active ? acc[u][v] : 0.0;
+            __syncthreads();
+            if (t < ntile) {
+                const int tti = t % ti_n, ttj = t / ti_n;
+                const int i = tti * TS + u, j = ttj * TS + v;
+                double s = 0.0;
+                for (int g = 0; g < rg_n; ++g) s += red[t * rg_n + g];
+                if (i < k1 && j < k2) part[(int64_t)blockIdx.x * nout + i + (int64_t)k1 * j] = s;
+            }
+        }
+}
+
+// out[o] = sum_b part[b * nout + o], b ascending within each of 16 waves and
+// the 16 wave sums added in wave order.
+__global__ __launch_bounds__(1024) void k_gram_reduce(int nout, int nparts, const double* __restrict__ part,
+                                                      double* __restrict__ out) {
+    __shared__ double red[16][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + lane;
+    double s0 = 0.0, s1 = 0.0;
+    if (o < nout) {
+        int b = w;
+        for (; b + 16 < nparts; b += 32) {
+            s0 += part[(int64_t)b * nout + o];
+            s1 += part[(int64_t)(b + 16) * nout + o];
+        }
+        if (b < nparts) s0 += part[(int64_t)b * nout + o];
+    }
+    red[w][lane] = s0 + s1;
+    __syncthreads();
+    if (w == 0 && o < nout) {
+        double s = 0.0;
+        for (int q = 0; q < 16; ++q) s += red[q][lane];
+        out[o] = s;
     }
 }
 
-// out[o] = sum_b part[b*nout + o] in block order (o = i + k1*j, column-major k1 x k2)
-__global__ void k_gram_sum(int nout, int nparts, const double* __restrict__ part, double* __restrict__ out) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= nout) return;
-    double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * nout + o];
-    out[o] = s;
+// ---------------------------------------------------------------------------
+// Row-wise block updates of block CG (thread per row; small coefficient
+// matrices staged in LDS; rows are independent, so updates are in place).
+constexpr int kBcgMax = 32;
+
+// P <- P T, Q <- Q T (first r columns), X += P alpha, R -= Q alpha, and the
+// block partials of the column norms |R_q|^2.
+__global__ __launch_bounds__(256) void k_bcg_step(int64_t n, int sp, int r, int nc, const double* __restrict__ Tm,
+                                                  const double* __restrict__ alpha, double* __restrict__ P,
+                                                  double* __restrict__ Q, double* __restrict__ X,
+                                                  double* __restrict__ R, double* __restrict__ rr_part) {
+    __shared__ double sT[kBcgMax * kBcgMax];
+    __shared__ double sA[kBcgMax * kBcgMax];
+    __shared__ double sred[4][kBcgMax];
+    for (int e = threadIdx.x; e < sp * r; e += blockDim.x) sT[e] = Tm[e];
+    for (int e = threadIdx.x; e < r * nc; e += blockDim.x) sA[e] = alpha[e];
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool ok = i < n;
+    const int64_t ii = ok ? i : 0;
+    double v[kBcgMax], w[kBcgMax];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // P
+#pragma unroll
+    for (int a = 0; a < kBcgMax; ++a) v[a] = a < sp ? P[a * n + ii] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kBcgMax; ++j) {
+        double s = 0.0;
+        if (j < r)
+#pragma unroll
+            for (int a = 0; a < kBcgMax; ++a)
+                if (a < sp) s += v[a] * sT[a + sp * j];
+        w[j] = s;
+    }
+    if (ok)
+#pragma unroll
+        for (int j = 0; j < kBcgMax; ++j)
+            if (j < r) P[j * n + i] = w[j];
+#pragma unroll
+    for (int q = 0; q < kBcgMax; ++q) {
+        if (q >= nc) break;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kBcgMax; ++j)
+            if (j < r) s += w[j] * sA[j + r * q];
+        if (ok) X[q * n + i] += s;
+    }
+    // Q
+#pragma unroll
+    for (int a = 0; a < kBcgMax; ++a) v[a] = a < sp ? Q[a * n + ii] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kBcgMax; ++j) {
+        double s = 0.0;
+        if (j < r)
+#pragma unroll
+            for (int a = 0; a < kBcgMax; ++a)
+                if (a < sp) s += v[a] * sT[a + sp * j];
+        w[j] = s;
+    }
+    if (ok)
+#pragma unroll
+        for (int j = 0; j < kBcgMax; ++j)
+            if (j < r) Q[j * n + i] = w[j];
+    // R -= Q alpha with the wave sums of |R_q|^2 (fixed-order trees)
+#pragma unroll
+    for (int q = 0; q < kBcgMax; ++q) {
+        if (q >= nc) break;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kBcgMax; ++j)
+            if (j < r) s += w[j] * sA[j + r * q];
+        double e = 0.0;
+        if (ok) {
+            const double nr = R[q * n + i] - s;
+            R[q * n + i] = nr;
+            e = nr * nr;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) e += __shfl_down(e, off, 64);
+        if (lane == 0) sred[wv][q] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+        const int q = threadIdx.x;
+        rr_part[(int64_t)q * gridDim.x + blockIdx.x] = sred[0][q] + sred[1][q] + sred[2][q] + sred[3][q];
+    }
+}
+
+// P <- Z + P beta  (P: n x sp in, n x nc out; beta sp x nc).
+__global__ __launch_bounds__(256) void k_bcg_dir(int64_t n, int sp, int nc, const double* __restrict__ beta,
+                                                 const double* __restrict__ Z, double* __restrict__ P) {
+    __shared__ double sB[kBcgMax * kBcgMax];
+    for (int e = threadIdx.x; e < sp * nc; e += blockDim.x) sB[e] = beta[e];
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v[kBcgMax];
+#pragma unroll
+    for (int a = 0; a < kBcgMax; ++a) v[a] = a < sp ? P[a * n + i] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kBcgMax; ++q) {
+        if (q >= nc) break;
+        double s = Z[q * n + i];
+#pragma unroll
+        for (int a = 0; a < kBcgMax; ++a)
+            if (a < sp) s += v[a] * sB[a + sp * q];
+        P[q * n + i] = s;
+    }
 }
 
 // Y (n x k2) = S (n x k1) C (k1 x k2, column-major), k1 <= 96, k2 <= 32;
 // C staged in LDS, one row of Y per thread accumulated in registers.
 __global__ void k_gemm_small(int64_t n, int k1, int64_t lds, const double* __restrict__ S, int k2,
                              const double* __restrict__ C, int64_t ldy, double* __restrict__ Y) {
-    __shared__ double sc[kGramMax * 32];
+    __shared__ double sc[96 * 32];
     for (int t = threadIdx.x; t < k1 * k2; t += blockDim.x) sc[t] = C[t];
     __syncthreads();
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -439,14 +611,41 @@ void launch_axpy_cols(int64_t n, int ncols, int64_t ld, const double* coef, doub
                       hipStream_t st) {
     hipLaunchKernelGGL(k_axpy_cols, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, coef, sign, x, y);
 }
-void launch_gram_part(int64_t n, int k1, int64_t lda, const double* A, int k2, int64_t ldb, const double* B,
-                      int nparts, double* part, hipStream_t st) {
-    hipLaunchKernelGGL(k_gram_part, dim3(nparts), dim3(256), 0, st, n, k1, lda, A, k2, ldb, B, part);
+int gram_parts(int64_t n, int k1, int k2) {
+    const int rows = k1 + k2 > 120 ? 32 : 64;
+    const int64_t nslab = (n + rows - 1) / rows;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nslab, 1024));
 }
-void launch_gram_sum(int k1, int k2, int nparts, const double* part, double* out, hipStream_t st) {
+
+int launch_gram(int64_t n, int k1, int64_t lda, const double* A, int k2a, int64_t ldb1, const double* B1, int k2b,
+                int64_t ldb2, const double* B2, int nparts, double* part, double* out, hipStream_t st) {
+    const int k2 = k2a + k2b;
+    if (k1 < 1 || k2 < 1 || k1 + k2 > kGramMaxCols) return -1;
+    const int rows = k1 + k2 > 120 ? 32 : 64;
+    const size_t lds = std::max<size_t>((size_t)(k1 + k2) * (rows + 1), kGramThreads) * sizeof(double);
+    const int t4 = ((k1 + 3) / 4) * ((k2 + 3) / 4);
+    if (t4 <= kGramThreads)
+        hipLaunchKernelGGL(k_gram<4>, dim3(nparts), dim3(kGramThreads), lds, st, n, rows, k1, lda, A, k2a, ldb1, B1,
+                           k2b, ldb2, B2, part);
+    else
+        hipLaunchKernelGGL(k_gram<6>, dim3(nparts), dim3(kGramThreads), lds, st, n, rows, k1, lda, A, k2a, ldb1, B1,
+                           k2b, ldb2, B2, part);
     const int nout = k1 * k2;
-    hipLaunchKernelGGL(k_gram_sum, dim3((nout + 255) / 256), dim3(256), 0, st, nout, nparts, part, out);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((nout + 63) / 64), dim3(1024), 0, st, nout, nparts, part, out);
+    return 0;
 }
+
+void launch_bcg_step(int64_t n, int sp, int r, int nc, const double* T, const double* alpha, double* P, double* Q,
+                     double* X, double* R, double* rr_part, hipStream_t st) {
+    hipLaunchKernelGGL(k_bcg_step, dim3(nb1(n)), dim3(256), 0, st, n, sp, r, nc, T, alpha, P, Q, X, R, rr_part);
+}
+
+int bcg_step_parts(int64_t n) { return nb1(n); }
+
+void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const double* Z, double* P, hipStream_t st) {
+    hipLaunchKernelGGL(k_bcg_dir, dim3(nb1(n)), dim3(256), 0, st, n, sp, nc, beta, Z, P);
+}
+
 void launch_gemm_small(int64_t n, int k1, int64_t lds, const double* S, int k2, const double* C, int64_t ldy,
                        double* Y, hipStream_t st) {
     hipLaunchKernelGGL(k_gemm_small, dim3(nb1(n)), dim3(kBlock), 0, st, n, k1, lds, S, k2, C, ldy, Y);
