@@ -3,13 +3,16 @@
 One step = one complete analysis with the densities already in HBM:
 SIMP moduli + multigrid hierarchy (Galerkin levels, coarsest inverse),
 static MG-PCG solve to 1e-8, element stresses, Galerkin K^l/G^l, 12 coarse
-modes (LOBPCG), interpolation, 12-column fine block solve K Phi = G Psi,
-Rayleigh-Ritz, compliance sensitivities, 12 adjoint solves and buckling
-sensitivities.  Prints ONE JSON line (rank 0, N = 1 only).
+modes (LOBPCG to 1e-8), interpolation, 12-column fine block solve
+K Phi = G Psi to 1e-8, Rayleigh-Ritz, compliance sensitivities, 12 adjoint
+solves (block, 1e-8) and buckling sensitivities.  The default precision is
+mixed (FP32 multigrid cycle inside FP64 Krylov solvers, the workload's
+configuration); the plain FP64 path is timed in the same run and reported
+beside it.  Prints ONE JSON line (rank 0, N = 1 only).
 
 Also reported: MG-PCG throughput of the static solve (free DOFs x iterations
-/ solve time) and the roofline of the dominant kernel (fine-level H8
-stiffness apply), timed with HIP events on the library's stream.
+/ solve time) and the roofline of the fine-level H8 stiffness apply, timed
+with HIP events on the stream the library launches on.
 """
 import argparse
 import json
@@ -21,6 +24,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the fine 1-column apply: rocprofv3 FETCH_SIZE x 1.99966
+# + WRITE_SIZE x 1.0 (factors from a 256 MiB calibration copy), measured on the
+# current kernel: 17,377 KiB read counter + 19,153 KiB written
+# (profiles/fine_apply_h8_192x64x64_hbm_counters.md).
+TRAFFIC_BYTES = (17377 * 1.99966 + 19153) * 1024
 
 
 def parse():
@@ -28,7 +36,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--no-fp64-reference", action="store_true",
+                    help="skip timing the plain FP64 path next to the mixed one")
+    ap.add_argument("--tol-eig", type=float, default=1e-8)
     ap.add_argument("--nel", type=str, default="192,64,64")
     ap.add_argument("--levels", type=int, default=5)
     ap.add_argument("--eig-level", type=int, default=3)
@@ -40,9 +51,12 @@ def parse():
     return ap.parse_args()
 
 
+CPU_SAMPLE = (64, 12, 12)
+
+
 def cpu_baseline(args):
     """The oracle (sparse direct + LAPACK/ARPACK) on a bounded sample of the
-    same workload recipe: 48x16x16 H8 box, eigen level 2, 12 modes."""
+    same workload recipe: 64x12x12 H8 box, eigen level 2, 12 modes."""
     import numpy as np
     try:
         from threadpoolctl import threadpool_limits
@@ -50,7 +64,7 @@ def cpu_baseline(args):
         threadpool_limits = None
     import workloads as W
     from oracle import fem, lba, sens
-    nel = (48, 16, 16)
+    nel = CPU_SAMPLE
     p = W.box_3d(nel=nel, seed=3, sigma=1.0)
     mat = fem.Material()
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
@@ -63,6 +77,69 @@ def cpu_baseline(args):
         ctx.__exit__(None, None, None)
     n_sample = W.n_dofs(nel)
     return t, n_sample
+
+
+def run_path(args, precision, p, x_dev, steps, warmup, label):
+    """Times `steps` full analyses after `warmup` untimed ones."""
+    import torch
+    import paper_1909_13585_amd as mlb
+    nel = tuple(int(v) for v in args.nel.split(","))
+    ctx = mlb.Context(nel, mg_levels=args.levels, eig_level=args.eig_level, precision=precision)
+    ctx.set_bc(p["fixed"])
+    ctx.set_loads(p["F"])
+    n, m = ctx.level_size(1)
+    k = args.modes
+    U = torch.empty((ctx.ncases, n), dtype=torch.float64, device="cuda")
+    Phi = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    dJ = torch.empty((ctx.ncases, m), dtype=torch.float64, device="cuda")
+    dlam = torch.empty((k, m), dtype=torch.float64, device="cuda")
+
+    def step():
+        ctx.set_density_dev(x_dev)
+        J, si = ctx.solve_static_dev(U, tol=1e-8, max_it=2000)
+        lam, ei = ctx.buckling_dev(k, Phi, tol_eig=args.tol_eig)
+        ai = ctx.sensitivities_dev(dJ, dlam)
+        return J, si, lam, ei, ai
+
+    for w in range(warmup):
+        out = step()
+        print(f"# {label} warmup {w} static_it={out[1]['iterations']} coarse_it={out[3]['coarse_iterations']} "
+              f"fine_it={out[3]['fine_iterations']} adj_it={out[4]['iterations']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    out = None
+    t0 = time.perf_counter()
+    for s_ in range(steps):
+        ts = time.perf_counter()
+        out = step()
+        torch.cuda.synchronize()
+        print(f"# {label} step {s_} {time.perf_counter() - ts:.3f}s static_it={out[1]['iterations']} "
+              f"coarse_it={out[3]['coarse_iterations']} fine_it={out[3]['fine_iterations']} "
+              f"adj_it={out[4]['iterations']} lam1={out[2][0]:.9g}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / max(steps, 1)
+    return ctx, sec, out
+
+
+def apply_roofline(ctx, n, m, reps, ncols=1):
+    """Fine-level H8 apply (public entry, FP64), HIP events on the stream the
+    library launches on (the caller's current stream)."""
+    import torch
+    xa = torch.randn((ncols, n) if ncols > 1 else (n,), dtype=torch.float64, device="cuda")
+    ya = torch.empty_like(xa)
+    for _ in range(5):
+        ctx.apply_K_dev(1, xa, ya)
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        ctx.apply_K_dev(1, xa, ya)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nodes = n // 3
+    alg = ncols * 16 * n + 8 * m + nodes   # x read + y write per column, E_kappa, node mask
+    return ms, alg
 
 
 def main():
@@ -78,92 +155,64 @@ def main():
 
     torch.cuda.set_device(0)
     nel = tuple(int(v) for v in args.nel.split(","))
-    t_setup = time.perf_counter()
     p = W.box_3d(nel=nel, seed=3)
-    prec = mlb.MLB_MIXED if args.precision == "mixed" else mlb.MLB_FP64
-    ctx = mlb.Context(nel, mg_levels=args.levels, eig_level=args.eig_level, precision=prec)
-    ctx.set_bc(p["fixed"])
-    ctx.set_loads(p["F"])
     x_dev = torch.from_numpy(p["x"]).cuda()
-    n, m = ctx.level_size(1)
-    k = args.modes
-    U = torch.empty((ctx.ncases, n), dtype=torch.float64, device="cuda")
-    Phi = torch.empty((k, n), dtype=torch.float64, device="cuda")
-    dJ = torch.empty((ctx.ncases, m), dtype=torch.float64, device="cuda")
-    dlam = torch.empty((k, m), dtype=torch.float64, device="cuda")
-    print(f"# setup {time.perf_counter() - t_setup:.1f}s n={n} m={m}", file=sys.stderr, flush=True)
-
-    def step():
-        ctx.set_density_dev(x_dev)
-        J, si = ctx.solve_static_dev(U, tol=1e-8, max_it=2000)
-        lam, ei = ctx.buckling_dev(k, Phi, tol_eig=1e-10)
-        ai = ctx.sensitivities_dev(dJ, dlam)
-        return J, si, lam, ei, ai
 
     if args.roofline_only:
+        # counter runs: the fine apply, then a calibration copy of a buffer far
+        # larger than the L2 caches, written by a fill and flushed before
+        ctx = mlb.Context(nel, mg_levels=args.levels, eig_level=args.eig_level)
+        ctx.set_bc(p["fixed"])
+        ctx.set_loads(p["F"])
         ctx.set_density_dev(x_dev)
+        n, m = ctx.level_size(1)
         xa = torch.randn(n, dtype=torch.float64, device="cuda")
         ya = torch.empty_like(xa)
         for _ in range(args.apply_reps):
             ctx.apply_K_dev(1, xa, ya)
-        ya.copy_(xa)   # calibration: reads and writes exactly 8 n bytes each
+        cal = 1 << 25   # 32 Mi doubles = 256 MiB
+        src = torch.empty(cal, dtype=torch.float64, device="cuda").fill_(1.0)
+        flush = torch.empty(cal, dtype=torch.float64, device="cuda").fill_(2.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"roofline_only": True, "n": n, "m": m, "copy_bytes": 8 * n}), flush=True)
+        print(json.dumps({"roofline_only": True, "n": n, "m": m, "copy_bytes": 8 * cal,
+                          "flush_bytes": int(flush.numel() * 8)}), flush=True)
         ctx.close()
         return
 
-    for w in range(args.warmup):
-        out = step()
-        print(f"# warmup {w} static_it={out[1]['iterations']} coarse_it={out[3]['coarse_iterations']} "
-              f"fine_it={out[3]['fine_iterations']} adj_it={out[4]['iterations']}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    times = []
-    infos = []
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        ts = time.perf_counter()
-        out = step()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - ts)
-        infos.append(out)
-        print(f"# step {s} {times[-1]:.3f}s static_it={out[1]['iterations']} "
-              f"coarse_it={out[3]['coarse_iterations']} fine_it={out[3]['fine_iterations']} "
-              f"adj_it={out[4]['iterations']} lam1={out[2][0]:.6g}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    sec = total / max(args.steps, 1)
-    J, si, lam, ei, ai = infos[-1]
+    prec = mlb.MLB_MIXED if args.precision == "mixed" else mlb.MLB_FP64
+    ctx, sec, out = run_path(args, prec, p, x_dev, args.steps, args.warmup, args.precision)
+    J, si, lam, ei, ai = out
+    n, m = ctx.level_size(1)
+    k = args.modes
     free = int(n - p["fixed"].sum())
     gdofs = free * si["iterations"] / si["seconds"] / 1e9
 
-    # dominant kernel: fine-level stiffness apply, one column, timed with
-    # HIP events on the library's stream (the caller's current stream).
-    xa = torch.randn(n, dtype=torch.float64, device="cuda")
-    ya = torch.empty_like(xa)
-    for _ in range(5):
-        ctx.apply_K_dev(1, xa, ya)
-    st = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(args.apply_reps):
-        ctx.apply_K_dev(1, xa, ya)
-    e1.record(st)
-    torch.cuda.synchronize()
-    apply_ms = e0.elapsed_time(e1) / args.apply_reps
-    word = 8
-    nodes = n // 3
-    alg_bytes = 2 * word * n + word * m + nodes      # x read, y write, E_kappa, node mask
+    apply_ms, alg_bytes = apply_roofline(ctx, n, m, args.apply_reps, 1)
     achieved = alg_bytes / (apply_ms * 1e-3) / 1e9
+    apply12_ms, alg12 = apply_roofline(ctx, n, m, max(5, args.apply_reps // 5), 12)
+    ctx.close()
+
+    fp64 = None
+    if args.precision == "mixed" and not args.no_fp64_reference:
+        ctx64, sec64, out64 = run_path(args, mlb.MLB_FP64, p, x_dev, max(1, min(args.steps, 2)), 1, "fp64")
+        ctx64.close()
+        fp64 = {"s_per_analysis": sec64, "static_iterations": out64[1]["iterations"],
+                "coarse_iterations": out64[3]["coarse_iterations"],
+                "fine_block_iterations": out64[3]["fine_iterations"],
+                "adjoint_iterations": out64[4]["iterations"],
+                "max_rel_lambda_diff_vs_mixed": float(np.max(np.abs(np.asarray(out64[2]) / np.asarray(lam) - 1)))}
 
     cpu = None
     if not args.no_cpu_baseline:
         t_cpu, n_sample = cpu_baseline(args)
         cpu = {"value": t_cpu * n / n_sample, "unit": "s/analysis", "cores": 1, "kind": "oracle",
-               "sample": (f"oracle analysis (SuperLU static + adjoint solves, ARPACK coarse eigen, Ritz, "
-                          f"sensitivities) on the 48x16x16 H8 box of the same recipe ({n_sample} DOFs, eigen "
-                          f"level 2, {k} modes): {t_cpu:.2f}s, scaled linearly in DOFs to {n} DOFs "
-                          f"(a lower bound: direct solvers scale superlinearly)")}
+               "sample": (f"oracle analysis (SuperLU static + adjoint solves, dense/ARPACK coarse eigen, Ritz, "
+                          f"sensitivities) on the {CPU_SAMPLE[0]}x{CPU_SAMPLE[1]}x{CPU_SAMPLE[2]} H8 box of the "
+                          f"same recipe ({n_sample} DOFs, eigen level 2, {k} modes, one thread): {t_cpu:.2f}s, "
+                          f"scaled linearly in DOFs to {n} DOFs (a lower bound: direct solvers scale "
+                          f"superlinearly)")}
 
     line = {
         "metric": "buckling-analysis wall time @2.4M DOF, FP64 vs mixed/learned; MG-PCG GDOF/s",
@@ -178,9 +227,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"H8 box {nel[0]}x{nel[1]}x{nel[2]} ({n} DOFs), clamped x=0, axial load, "
-                               f"filtered density vf 0.3, {args.levels}-level MG, eigen level {args.eig_level}, "
-                               f"{k} modes, tol 1e-8",
+        "config": {"workload": f"H8 box {nel[0]}x{nel[1]}x{nel[2]} ({n} DOFs), clamped x=0, unit axial load, "
+                               f"Gaussian-filtered density vf 0.3 (seed 3), {args.levels}-level MG, eigen level "
+                               f"{args.eig_level}, {k} modes, solves to 1e-8, coarse eigen to {args.tol_eig:g}",
                    "precision": args.precision},
         "mgpcg_gdof_per_s": gdofs,
         "static_iterations": si["iterations"],
@@ -190,14 +239,16 @@ def main():
         "lambda": [float(v) for v in lam],
         "phase_s": {"coarse": ei["seconds_coarse"], "fine": ei["seconds_fine"], "ritz": ei["seconds_ritz"],
                     "static": si["seconds"], "adjoint": ai["seconds"]},
-        "roofline": {"bound": "hbm", "kernel": "k_apply_fine<3,double> (fine H8 K apply, 1 column)",
+        "fp64_reference": fp64,
+        "roofline": {"bound": "hbm", "kernel": "k_apply_wht3<double> (fine H8 K apply, 1 column)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "apply_ms": apply_ms,
-                     "alg_bytes": alg_bytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES, "apply_ms": apply_ms,
+                     "alg_bytes": alg_bytes,
+                     "apply_12col_ms": apply12_ms,
+                     "achieved_12col": alg12 / (apply12_ms * 1e-3) / 1e9},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -94,6 +94,7 @@ typedef struct {
     uint64_t seed;        /* seed of the coarse eigensolver start block (default 1) */
     int cycle;            /* coarse-grid visits per level: 1 = V-cycle, 2 = W-cycle (default 1) */
     int block_cg;         /* multi-column solves: 1 = block CG (default), 2 = column-wise CG */
+    int eig_sweeps;       /* multigrid sweeps per coarse-eigensolver preconditioner application (default 3) */
 } mlb_opts;
 
 /* Per-call solver report; for blocks, the worst column is reported. */

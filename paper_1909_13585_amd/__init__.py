@@ -100,8 +100,10 @@ class Context:
         return n.value, m.value
 
     def set_opts(self, smooth_steps=0, jacobi_omega=0.0, eig_guard=0, eig_max_it=0, check_every=0, seed=0,
-                 cycle=0, block_cg=0):
-        o = B.MlbOpts(smooth_steps, jacobi_omega, eig_guard, eig_max_it, check_every, seed, cycle, block_cg)
+                 cycle=0, block_cg=0, eig_sweeps=0):
+        """Zero (the default of every argument) keeps the current value."""
+        o = B.MlbOpts(smooth_steps, jacobi_omega, eig_guard, eig_max_it, check_every, seed, cycle, block_cg,
+                      eig_sweeps)
         self._check(self.lib.mlb_set_opts(self.h, C.byref(o)))
 
     # -- problem data (host)

@@ -38,7 +38,7 @@ class MlbDesc(C.Structure):
 class MlbOpts(C.Structure):
     _fields_ = [("smooth_steps", C.c_int), ("jacobi_omega", C.c_double), ("eig_guard", C.c_int),
                 ("eig_max_it", C.c_int), ("check_every", C.c_int), ("seed", C.c_uint64), ("cycle", C.c_int),
-                ("block_cg", C.c_int)]
+                ("block_cg", C.c_int), ("eig_sweeps", C.c_int)]
 
 
 class MlbSolveInfo(C.Structure):

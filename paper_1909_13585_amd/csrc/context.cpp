@@ -64,7 +64,6 @@ struct mlb_ctx {
     double *dK0 = nullptr, *dHk = nullptr, *dBc = nullptr, *dD0Bc = nullptr, *dD0 = nullptr, *dT = nullptr,
            *dMc = nullptr, *dGHc = nullptr;
     float* fK0 = nullptr;
-    int eig_cycle = 1;   // V (1) or W (2) cycle inside the coarse eigensolver's preconditioner
     float whtf[72] = {};   // FP32 copy of the Walsh-Hadamard blocks (host; passed by value)
     std::vector<Level> lv;
     int64_t n = 0, m = 0;
@@ -106,6 +105,8 @@ struct mlb_ctx {
     double *cbuf = nullptr, *cbuf2 = nullptr;   // small coefficient matrices
     int* iscal = nullptr;     // active / flags
     double* hpin = nullptr;   // pinned host staging (96 x 192 doubles)
+    double* hup = nullptr;    // pinned staging of coefficient uploads (2 x 96 x 96)
+    bool up_pending = false;  // an upload from hup may still be in flight
     // warm starts
     std::vector<double> warm_coarse;
     int warm_coarse_cols = 0;
@@ -168,6 +169,7 @@ int ensure_part(mlb_ctx* c, int64_t count) {
 
 int sync(mlb_ctx* c) {
     HIPC(hipStreamSynchronize(c->st));
+    c->up_pending = false;
     HIPC(hipGetLastError());
     return MLB_OK;
 }
@@ -550,10 +552,26 @@ int build_hierarchy(mlb_ctx* c) {
 // ---- coarse eigensolver: LOBPCG for the largest mu of (-G) psi = mu K psi
 // at level ell; X K-orthonormal on exit (columns eS[0..nb)).
 
+// Enqueues a host -> device copy of a small coefficient matrix without
+// waiting for it; the staging buffer is only rewritten after a sync.
 int upload_cm(mlb_ctx* c, double* dev, const std::vector<double>& cm) {
-    std::memcpy(c->hpin, cm.data(), sizeof(double) * cm.size());
-    HIPC(hipMemcpyAsync(dev, c->hpin, sizeof(double) * cm.size(), hipMemcpyHostToDevice, c->st));
-    CHK(sync(c));
+    if (cm.size() > (size_t)96 * 96) return fail(c, MLB_EINVAL, "coefficient matrix larger than 96 x 96");
+    if (c->up_pending) CHK(sync(c));
+    std::memcpy(c->hup, cm.data(), sizeof(double) * cm.size());
+    HIPC(hipMemcpyAsync(dev, c->hup, sizeof(double) * cm.size(), hipMemcpyHostToDevice, c->st));
+    c->up_pending = true;
+    return MLB_OK;
+}
+
+// Two coefficient matrices in one upload (both land in consecutive device
+// memory starting at dev; the second at dev + a.size()).
+int upload_cm2(mlb_ctx* c, double* dev, const std::vector<double>& a, const std::vector<double>& b) {
+    if (a.size() + b.size() > (size_t)2 * 96 * 96) return fail(c, MLB_EINVAL, "coefficient matrices too large");
+    if (c->up_pending) CHK(sync(c));
+    std::memcpy(c->hup, a.data(), sizeof(double) * a.size());
+    std::memcpy(c->hup + a.size(), b.data(), sizeof(double) * b.size());
+    HIPC(hipMemcpyAsync(dev, c->hup, sizeof(double) * (a.size() + b.size()), hipMemcpyHostToDevice, c->st));
+    c->up_pending = true;
     return MLB_OK;
 }
 
@@ -577,6 +595,51 @@ bool rayleigh_ritz_gram(int ncol, int ld, const std::vector<double>& GK, const s
             Ks[(size_t)a * ncol + q] = d[a] * d[q] * 0.5 * (GK[a + (size_t)ld * q] + GK[q + (size_t)ld * a]);
             As[(size_t)a * ncol + q] = d[a] * d[q] * 0.5 * (GA[a + (size_t)ld * q] + GA[q + (size_t)ld * a]);
         }
+    // Fast path: a well-conditioned basis (Cholesky pivots of the unit-diagonal
+    // Gram matrix all above 1e-5) is K-orthonormalised by its Cholesky factor,
+    // Ks = L L^T; the projected matrix is L^-1 As L^-T and C = diag(d) L^-T Y.
+    {
+        std::vector<double> L(Ks);
+        bool good = cholesky(ncol, L.data());
+        for (int i = 0; good && i < ncol; ++i) good = L[(size_t)i * ncol + i] > 1e-5;
+        if (good) {
+            // Y1 = L^-1 As (forward substitution, column by column)
+            std::vector<double> Y1((size_t)ncol * ncol), Ar((size_t)ncol * ncol);
+            for (int col = 0; col < ncol; ++col)
+                for (int i = 0; i < ncol; ++i) {
+                    double v = As[(size_t)i * ncol + col];
+                    for (int q = 0; q < i; ++q) v -= L[(size_t)i * ncol + q] * Y1[(size_t)q * ncol + col];
+                    Y1[(size_t)i * ncol + col] = v / L[(size_t)i * ncol + i];
+                }
+            // Ar = Y1 L^-T = (L^-1 Y1^T)^T ; Ar is symmetric
+            for (int row = 0; row < ncol; ++row)
+                for (int i = 0; i < ncol; ++i) {
+                    double v = Y1[(size_t)row * ncol + i];
+                    for (int q = 0; q < i; ++q) v -= L[(size_t)i * ncol + q] * Ar[(size_t)row * ncol + q];
+                    Ar[(size_t)row * ncol + i] = v / L[(size_t)i * ncol + i];
+                }
+            for (int a = 0; a < ncol; ++a)
+                for (int q = 0; q < a; ++q) {
+                    const double v = 0.5 * (Ar[(size_t)a * ncol + q] + Ar[(size_t)q * ncol + a]);
+                    Ar[(size_t)a * ncol + q] = Ar[(size_t)q * ncol + a] = v;
+                }
+            std::vector<double> ew(ncol), Y((size_t)ncol * ncol);
+            if (sym_eig(ncol, Ar.data(), ew.data(), Y.data())) {
+                ev.assign(ew.begin(), ew.begin() + nb);
+                C.assign((size_t)ncol * nb, 0.0);
+                // Z = L^-T Y (back substitution), C = diag(d) Z
+                for (int qc = 0; qc < nb; ++qc)
+                    for (int i = ncol - 1; i >= 0; --i) {
+                        double v = Y[(size_t)i * ncol + qc];
+                        for (int a = i + 1; a < ncol; ++a) v -= L[(size_t)a * ncol + i] * C[a + (size_t)ncol * qc];
+                        C[i + (size_t)ncol * qc] = v / L[(size_t)i * ncol + i];
+                    }
+                for (int qc = 0; qc < nb; ++qc)
+                    for (int a = 0; a < ncol; ++a) C[a + (size_t)ncol * qc] *= d[a];
+                return true;
+            }
+        }
+    }
     std::vector<double> w(ncol), V((size_t)ncol * ncol);
     if (!sym_eig(ncol, Ks.data(), w.data(), V.data())) return false;
     if (!(w[0] > 0)) return false;
@@ -703,10 +766,9 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
                     for (int i = 0; i < sp; ++i) a += Tm[i + (size_t)sp * j] * G[(size_t)sp * sp + i + (size_t)sp * q];
                     Al[j + (size_t)r * q] = a;
                 }
-            CHK(upload_cm(c, c->cbuf, Tm));
-            CHK(upload_cm(c, c->cbuf2, Al));
+            CHK(upload_cm2(c, c->cbuf, Tm, Al));
             const int nps = bcg_step_parts(n);
-            launch_bcg_step(n, sp, r, nc, c->cbuf, c->cbuf2, P, Q, X, c->R, c->part, c->st);
+            launch_bcg_step(n, sp, r, nc, c->cbuf, c->cbuf + Tm.size(), P, Q, X, c->R, c->part, c->st);
             launch_sum_parts(nc, nps, c->part, rr, c->st);
             sp = r;
             CHK(check(&done));
@@ -742,116 +804,106 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
     return MLB_OK;
 }
 
-// LOBPCG for the largest mu of (-G) psi = mu K psi at level ell, in the
-// robust form: X K-orthonormal; W = T R orthogonalised twice against X (and
-// P) and orthonormalised by SVQB; P kept K-orthonormal; K X and -G X
-// recomputed explicitly every iteration.  On exit X = eS[0..nb) holds the
-// K-orthonormal Ritz vectors, mu the Ritz values (descending).
+// LOBPCG for the largest mu of (-G) psi = mu K psi at level ell.
+// The basis S = [X P W] and its images K S, -G S live contiguously in one of
+// two buffers; each iteration writes the new X and P into the other buffer.
+//   R = -G X - K X diag(mu);  W = T R (multigrid preconditioner)
+//   W -= [X P] ([K X, K P]^T W)  (twice);  K W, -G W;  SVQB of W^T K W
+//   Rayleigh-Ritz on span(S) (rank revealing, K-orthonormal result)
+//   X' = S C, P' = [P W] C_pw;  K [X' P'] and -G [X' P'] applied explicitly,
+// so every Gram matrix is formed from exact operator images (updating them
+// by the same recurrences drifts once the basis becomes ill-conditioned).
+// On exit eS[0..nb) holds X (K-orthonormal), mu the Ritz values (descending).
 int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double* gap, std::vector<double>& mu) {
     const bool verbose = std::getenv("MLB_VERBOSE") != nullptr;
     const int j = c->ell;
     Level& l = c->lv[j - 1];
     const int64_t n = l.n;
     int guard = c->o.eig_guard > 0 ? c->o.eig_guard : std::max(4, k / 2);
-    int nb = std::min(k + guard, 24);
+    const int nb = std::min(k + guard, 24);
     if (nb <= k) return fail(c, MLB_EINVAL, "k must be at most 23");
     if (nb > n / 2) return fail(c, MLB_EINVAL, "eigen level too small for the requested modes");
     CHK(ensure_level_cols(c, nb));
     if (nb > c->eig_cap) {
-        const size_t s3 = (size_t)n * 3 * nb, s2 = (size_t)n * 2 * nb, s1 = (size_t)n * nb;
+        const size_t s3 = (size_t)n * 3 * nb, s1 = (size_t)n * nb;
         CHK(dalloc(c, &c->eS, s3));
         CHK(dalloc(c, &c->eK, s3));
         CHK(dalloc(c, &c->eA, s3));
-        CHK(dalloc(c, &c->eT, s2));
-        CHK(dalloc(c, &c->eTK, s2));
-        CHK(dalloc(c, &c->eTA, s2));
+        CHK(dalloc(c, &c->eT, s3));
+        CHK(dalloc(c, &c->eTK, s3));
+        CHK(dalloc(c, &c->eTA, s3));
         CHK(dalloc(c, &c->eR, s1));
         CHK(dalloc(c, &c->eP, s1));
         CHK(dalloc(c, &c->ePK, s1));
         CHK(dalloc(c, &c->ePA, s1));
         c->eig_cap = nb;
     }
-    double *X = c->eS, *W = c->eS + n * nb;
-    double *KX = c->eK, *KW = c->eK + n * nb;
-    double *AX = c->eA, *AW = c->eA + n * nb;
+    struct Buf {
+        double *S, *KS, *AS;
+    };
+    Buf bufs[2] = {{c->eS, c->eK, c->eA}, {c->eT, c->eTK, c->eTA}};
+    int cur = 0;
     auto applyKA = [&](int cols, const double* V, double* KV, double* AV) {
         apply_K<double>(c, j, cols, V, KV, kModeY, nullptr, nullptr);
         apply_G(c, j, cols, V, AV);
         launch_axpby(n * cols, -1.0, AV, 0.0, AV, c->st);
     };
-    // V -= B (KB^T V): K-orthogonalise V (cols cv) against a K-orthonormal B (cols cb)
-    auto orth_against = [&](double* V, int cv, const double* B, const double* KB, int cb) -> int {
-        std::vector<double> Cm;
-        CHK(gram(c, n, cb, KB, n, cv, V, n, Cm));
-        CHK(upload_cm(c, c->cbuf, Cm));
-        launch_gemm_small(n, cb, n, B, cv, c->cbuf, n, c->eT, c->st);
-        launch_axpby(n * cv, -1.0, c->eT, 1.0, V, c->st);
-        return MLB_OK;
-    };
-    // V <- V T with T from SVQB of V^T K V (directions below 1e-10 of the
-    // largest Gram eigenvalue dropped); K V and -G V are then recomputed
-    // explicitly so that they stay consistent with V to working precision.
-    auto orthonormalize = [&](double* V, double* KV, double* AV, int cv, int* rout) -> int {
-        std::vector<double> Gm, T;
-        CHK(gram(c, n, cv, V, n, cv, KV, n, Gm));
-        const int r = svqb(cv, Gm, 1e-10, T);
-        *rout = r;
-        if (r == 0) return MLB_OK;
-        CHK(upload_cm(c, c->cbuf, T));
-        launch_gemm_small(n, cv, n, V, r, c->cbuf, n, c->eT, c->st);
-        launch_copy_cols(n, r, n, c->eT, n, V, c->st);
-        applyKA(r, V, KV, AV);
-        return MLB_OK;
-    };
 
     // start block: warm-start columns first, seeded random for the rest
-    launch_random_fill(n, nb, n, c->o.seed, l.nmask, c->dim, X, c->st);
-    if (c->warm_coarse_cols > 0 && (int64_t)c->warm_coarse.size() == n * c->warm_coarse_cols) {
-        const int wc = std::min(c->warm_coarse_cols, nb);
-        HIPC(hipMemcpyAsync(X, c->warm_coarse.data(), sizeof(double) * n * wc, hipMemcpyHostToDevice, c->st));
-        launch_mask_fixed(n, wc, n, l.nmask, c->dim, X, c->st);
-        CHK(sync(c));
-    }
-    applyKA(nb, X, KX, AX);
-    std::vector<double> GK, GA, ev, C;
     {
-        CHK(gram2(c, n, nb, X, nb, KX, AX, GK, GA));
+        double* X = bufs[0].S;
+        launch_random_fill(n, nb, n, c->o.seed, l.nmask, c->dim, X, c->st);
+        if (c->warm_coarse_cols > 0 && (int64_t)c->warm_coarse.size() == n * c->warm_coarse_cols) {
+            const int wc = std::min(c->warm_coarse_cols, nb);
+            HIPC(hipMemcpyAsync(X, c->warm_coarse.data(), sizeof(double) * n * wc, hipMemcpyHostToDevice, c->st));
+            launch_mask_fixed(n, wc, n, l.nmask, c->dim, X, c->st);
+            CHK(sync(c));
+        }
+        applyKA(nb, X, bufs[0].KS, bufs[0].AS);
+    }
+    std::vector<double> GK, GA, ev, C, Cpw, G, Tm, Co;
+    {
+        CHK(gram2(c, n, nb, bufs[0].S, nb, bufs[0].KS, bufs[0].AS, GK, GA));
         if (!rayleigh_ritz_gram(nb, nb, GK, GA, nb, ev, C))
             return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: start block is rank deficient");
         CHK(upload_cm(c, c->cbuf, C));
-        launch_gemm_small(n, nb, n, X, nb, c->cbuf, n, c->eT, c->st);
-        launch_copy_cols(n, nb, n, c->eT, n, X, c->st);
-        applyKA(nb, X, KX, AX);
+        launch_gemm_cat(n, nb, n, bufs[0].S, 0, n, nullptr, nb, c->cbuf, 0.0, n, bufs[1].S, c->st);
+        applyKA(nb, bufs[1].S, bufs[1].KS, bufs[1].AS);
+        cur = 1;
         mu.assign(ev.begin(), ev.begin() + nb);
     }
-    int rp = 0;   // columns of P (K-orthonormal)
+    int rp = 0;   // columns of P
     int it = 0;
     bool stalled = false;
     std::vector<double> hist;
     double wres = 1e300;
-    std::vector<double> rn(nb), kn(nb);
+    std::vector<double> nrm(2 * nb);
     const int max_it = c->o.eig_max_it > 0 ? c->o.eig_max_it : 400;
+    double t_host = 0.0, t_pre = 0.0;
+    const double t_start = now_s();
     for (it = 0; it <= max_it; ++it) {
+        Buf& b = bufs[cur];
+        double *X = b.S, *KX = b.KS, *AX = b.AS;
+        const int64_t oW = n * (nb + rp);
+        double *W = b.S + oW, *KW = b.KS + oW, *AW = b.AS + oW;
         std::memcpy(c->hpin, mu.data(), sizeof(double) * nb);
         HIPC(hipMemcpyAsync(sc(c, 11), c->hpin, sizeof(double) * nb, hipMemcpyHostToDevice, c->st));
         launch_residual_block(n, nb, n, AX, KX, sc(c, 11), c->eR, c->st);
         dots(c, n, nb, c->eR, c->eR, sc(c, 12));
-        dots(c, n, nb, KX, KX, sc(c, 13));
-        CHK(read_scal(c, sc(c, 12), nb, rn.data()));
-        CHK(read_scal(c, sc(c, 13), nb, kn.data()));
+        dots(c, n, nb, KX, KX, sc(c, 12) + nb);
+        CHK(read_scal(c, sc(c, 12), 2 * nb, nrm.data()));
         wres = 0.0;
         for (int i = 0; i < k; ++i) {
-            const double den = std::fabs(mu[i]) * std::sqrt(kn[i]);
-            wres = std::max(wres, den > 0 ? std::sqrt(rn[i]) / den : 1e300);
+            const double den = std::fabs(mu[i]) * std::sqrt(nrm[nb + i]);
+            wres = std::max(wres, den > 0 ? std::sqrt(nrm[i]) / den : 1e300);
         }
         if (!std::isfinite(wres)) return fail(c, MLB_EBREAKDOWN, "coarse eigensolver residual not finite");
         if (verbose) std::fprintf(stderr, "[mlb] lobpcg it %d worst %.3e rp %d mu0 %.12g muk %.12g\n", it, wres, rp,
                                   mu[0], mu[k - 1]);
         if (wres <= tol || it == max_it) break;
         // Precision floor: the residual of the k-th pair cannot fall below
-        // about eps * ||K^-1 G|| / mu_k, and ||K^-1 G|| includes the (possibly
-        // huge) negative part of the spectrum.  Accept a residual that has
-        // stopped improving for 15 iterations once it is below sqrt(tol).
+        // about eps * ||K^-1 G|| / mu_k.  Accept a residual that has stopped
+        // improving for 15 iterations once it is below sqrt(tol).
         hist.push_back(wres);
         if ((int)hist.size() > 15) {
             const double best_old = *std::min_element(hist.begin(), hist.end() - 15);
@@ -863,59 +915,85 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         }
         if (it >= 30 && !(mu[k - 1] > 0.0))
             return fail(c, MLB_ENOPOS, "fewer than k positive buckling factors at the coarse level");
-        // W = T R, orthogonalised against X and P (twice), then K-orthonormalised
-        {
-            const int saved = c->o.cycle;
-            c->o.cycle = c->eig_cycle;
-            precondition(c, j, nb, c->eR, W);
-            c->o.cycle = saved;
+        // W = T R
+        if (verbose) {
+            CHK(sync(c));
+            t_pre -= now_s();
         }
+        // (eig_sweeps stationary multigrid iterations from zero: a symmetric
+        // preconditioner that approximates (K^l)^-1 better than one cycle)
+        precondition(c, j, nb, c->eR, W);
+        for (int sw = 1; sw < c->o.eig_sweeps; ++sw) {   // W += B (R - K W)
+            apply_K<double>(c, j, nb, W, c->eP, kModeResidual, c->eR, nullptr);
+            precondition(c, j, nb, c->eP, c->ePK);
+            launch_axpby(n * nb, 1.0, c->ePK, 1.0, W, c->st);
+        }
+        if (verbose) {
+            CHK(sync(c));
+            t_pre += now_s();
+        }
+        // W -= [X P] ([K X, K P]^T W), twice
+        const int nx = nb + rp;
         for (int pass = 0; pass < 2; ++pass) {
-            CHK(orth_against(W, nb, X, KX, nb));
-            if (rp > 0) CHK(orth_against(W, nb, c->eP, c->ePK, rp));
+            CHK(gram(c, n, nb, W, n, nx, KX, n, G));
+            Co.assign((size_t)nx * nb, 0.0);   // Co[a, q] = G[q, a]
+            for (int a = 0; a < nx; ++a)
+                for (int q = 0; q < nb; ++q) Co[a + (size_t)nx * q] = G[q + (size_t)nb * a];
+            CHK(upload_cm(c, c->cbuf2, Co));
+            launch_gemm_cat(n, nx, n, X, 0, n, nullptr, nb, c->cbuf2, 0.0, n, c->eR, c->st);
+            launch_axpby(n * nb, -1.0, c->eR, 1.0, W, c->st);
         }
-        apply_K<double>(c, j, nb, W, KW, kModeY, nullptr, nullptr);
-        int rw = 0;
-        CHK(orthonormalize(W, KW, AW, nb, &rw));
+        applyKA(nb, W, KW, AW);
+        CHK(gram(c, n, nb, W, n, nb, KW, n, G));
+        const int rw = svqb(nb, G, 1e-10, Tm);
         if (rw == 0) {   // nothing new to add: converged to working precision
             stalled = true;
             break;
         }
-        // S = [X | W (rw) | P (rp)]
-        const int off = nb + rw;
-        if (rp > 0) {
-            launch_copy_cols(n, rp, n, c->eP, n, c->eS + n * off, c->st);
-            launch_copy_cols(n, rp, n, c->ePK, n, c->eK + n * off, c->st);
-            launch_copy_cols(n, rp, n, c->ePA, n, c->eA + n * off, c->st);
-        }
-        int ncol = off + rp;
-        CHK(gram2(c, n, ncol, c->eS, ncol, c->eK, c->eA, GK, GA));
-        if (!rayleigh_ritz_gram(ncol, ncol, GK, GA, nb, ev, C)) {
-            if (rp > 0 && rayleigh_ritz_gram(off, ncol, GK, GA, nb, ev, C)) {
+        CHK(upload_cm(c, c->cbuf, Tm));
+        launch_xform_inplace(n, nb, rw, c->cbuf, n, W, c->st);
+        launch_xform_inplace(n, nb, rw, c->cbuf, n, KW, c->st);
+        launch_xform_inplace(n, nb, rw, c->cbuf, n, AW, c->st);
+        int ncol = nx + rw;
+        int np_ = rp;   // P columns inside the Ritz basis
+        CHK(gram2(c, n, ncol, b.S, ncol, b.KS, b.AS, GK, GA));
+        const double th0 = now_s();
+        const bool rr_ok = rayleigh_ritz_gram(ncol, ncol, GK, GA, nb, ev, C);
+        t_host += now_s() - th0;
+        if (!rr_ok) {
+            bool ok = false;
+            if (rp > 0) {   // retry on [X W]: move W down over P
+                for (int a = 0; a < 3; ++a) {
+                    double* base = a == 0 ? b.S : a == 1 ? b.KS : b.AS;
+                    launch_copy_cols(n, rw, n, base + oW, n, base + n * nb, c->st);
+                }
+                ncol = nb + rw;
+                np_ = 0;
+                CHK(gram2(c, n, ncol, b.S, ncol, b.KS, b.AS, GK, GA));
+                ok = rayleigh_ritz_gram(ncol, ncol, GK, GA, nb, ev, C);
                 if (verbose) std::fprintf(stderr, "[mlb] lobpcg it %d: dropped P\n", it);
-                ncol = off;
-            } else {
-                return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: search space collapsed");
             }
+            if (!ok) return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: search space collapsed");
         }
-        // P_new = [W P] C[nb:ncol, :], then X_new = S C
-        std::vector<double> Cp((size_t)(ncol - nb) * nb);
+        (void)np_;
+        // X' = S C, P' = S[nb:ncol] C[nb:ncol, :] into the other buffer
+        Cpw.assign((size_t)(ncol - nb) * nb, 0.0);
         for (int a = nb; a < ncol; ++a)
-            for (int q = 0; q < nb; ++q) Cp[(a - nb) + (size_t)(ncol - nb) * q] = C[a + (size_t)ncol * q];
-        CHK(upload_cm(c, c->cbuf2, Cp));
-        launch_gemm_small(n, ncol - nb, n, W, nb, c->cbuf2, n, c->eP, c->st);
-        launch_gemm_small(n, ncol - nb, n, KW, nb, c->cbuf2, n, c->ePK, c->st);
-        launch_gemm_small(n, ncol - nb, n, AW, nb, c->cbuf2, n, c->ePA, c->st);
-        CHK(upload_cm(c, c->cbuf, C));
-        launch_gemm_small(n, ncol, n, c->eS, nb, c->cbuf, n, c->eT, c->st);
-        launch_copy_cols(n, nb, n, c->eT, n, X, c->st);
-        applyKA(nb, X, KX, AX);
-        // keep P K-orthonormal (and K-orthogonal to the new X)
-        CHK(orth_against(c->eP, nb, X, KX, nb));
-        apply_K<double>(c, j, nb, c->eP, c->ePK, kModeY, nullptr, nullptr);
-        CHK(orthonormalize(c->eP, c->ePK, c->ePA, nb, &rp));
+            for (int q = 0; q < nb; ++q) Cpw[(a - nb) + (size_t)(ncol - nb) * q] = C[a + (size_t)ncol * q];
+        CHK(upload_cm2(c, c->cbuf, C, Cpw));
+        Buf& nbf = bufs[cur ^ 1];
+        launch_gemm_cat(n, ncol, n, b.S, 0, n, nullptr, nb, c->cbuf, 0.0, n, nbf.S, c->st);
+        launch_gemm_cat(n, ncol - nb, n, b.S + n * nb, 0, n, nullptr, nb, c->cbuf + C.size(), 0.0, n,
+                        nbf.S + n * nb, c->st);
+        applyKA(2 * nb, nbf.S, nbf.KS, nbf.AS);
+        rp = nb;
+        cur ^= 1;
         mu.assign(ev.begin(), ev.begin() + nb);
     }
+    if (cur == 1) launch_copy_cols(n, nb, n, bufs[1].S, n, c->eS, c->st);
+    if (verbose)
+        std::fprintf(stderr, "[mlb] lobpcg %d its: total %.3f s, preconditioner %.3f s, host Rayleigh-Ritz %.3f s\n", it,
+                     now_s() - t_start, t_pre, t_host);
     *iters = it;
     *worst = wres;
     *gap = mu[k - 1] > 0 ? (mu[k - 1] - mu[k]) / mu[k - 1] : 0.0;
@@ -1092,7 +1170,8 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     c->o.seed = 1;
     c->o.cycle = 1;
     c->o.block_cg = 1;
-    if (const char* ev = std::getenv("MLB_EIG_CYCLE")) c->eig_cycle = std::atoi(ev) == 2 ? 2 : 1;
+    c->o.eig_sweeps = 3;
+
     const int dim = desc->dim;
     auto bad = [&](const std::string& m) {
         c->err = m;
@@ -1193,9 +1272,10 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     CHK(dalloc(c, &c->scal, (size_t)16 * kScal));
     CHK(dalloc(c, &c->iscal, (size_t)2 * kScal));
     CHK(dalloc(c, &c->gbuf, (size_t)96 * 192));
-    CHK(dalloc(c, &c->cbuf, (size_t)96 * 96));
+    CHK(dalloc(c, &c->cbuf, (size_t)2 * 96 * 96));
     CHK(dalloc(c, &c->cbuf2, (size_t)96 * 96));
     HIPC(hipHostMalloc((void**)&c->hpin, sizeof(double) * 96 * 192, hipHostMallocDefault));
+    HIPC(hipHostMalloc((void**)&c->hup, sizeof(double) * 2 * 96 * 96, hipHostMallocDefault));
     CHK(ensure_part(c, 4096));
     CHK(ensure_level_cols(c, 1));
     return MLB_OK;
@@ -1216,6 +1296,7 @@ void mlb_destroy(mlb_ctx* c) {
     dfree(c->eA); dfree(c->eT); dfree(c->eTK); dfree(c->eTA); dfree(c->eR); dfree(c->eP); dfree(c->ePK); dfree(c->ePA); dfree(c->part); dfree(c->pidx);
     dfree(c->scal); dfree(c->iscal); dfree(c->gbuf); dfree(c->cbuf); dfree(c->cbuf2);
     if (c->hpin) (void)hipHostFree(c->hpin);
+    if (c->hup) (void)hipHostFree(c->hup);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
 }
@@ -1232,6 +1313,7 @@ int mlb_set_opts(mlb_ctx* c, const mlb_opts* o) {
     if (o->seed > 0) c->o.seed = o->seed;
     if (o->cycle > 0) c->o.cycle = std::min(o->cycle, 2);
     if (o->block_cg > 0) c->o.block_cg = o->block_cg == 1 ? 1 : 0;
+    if (o->eig_sweeps > 0) c->o.eig_sweeps = std::min(o->eig_sweeps, 8);
     if (o->jacobi_omega > 0 && c->has_density) {
         c->st = c->own;
         for (int j = 1; j < c->L; ++j) CHK(estimate_omega(c, j));

@@ -94,6 +94,11 @@ int bcg_step_parts(int64_t n);
 void launch_bcg_step(int64_t n, int sp, int r, int nc, const double* T, const double* alpha, double* P, double* Q,
                      double* X, double* R, double* rr_part, hipStream_t st);
 void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const double* Z, double* P, hipStream_t st);
+// Y = alpha Y + [A1 A2] C (k1a + k1b <= 96, k2 <= 32; Y disjoint from A1, A2)
+void launch_gemm_cat(int64_t n, int k1a, int64_t lda1, const double* A1, int k1b, int64_t lda2, const double* A2,
+                     int k2, const double* C, double alpha, int64_t ldy, double* Y, hipStream_t st);
+// V[:, :k2] = V[:, :k1] T in place (k1, k2 <= 32)
+void launch_xform_inplace(int64_t n, int k1, int k2, const double* T, int64_t ld, double* V, hipStream_t st);
 void launch_gemm_small(int64_t n, int k1, int64_t lds, const double* S, int k2, const double* C, int64_t ldy,
                        double* Y, hipStream_t st);
 void launch_residual_block(int64_t n, int ncols, int64_t ld, const double* AX, const double* KX,

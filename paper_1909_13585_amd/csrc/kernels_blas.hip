@@ -311,70 +311,71 @@ __global__ __launch_bounds__(1024) void k_gram_reduce(int nout, int nparts, cons
 constexpr int kBcgMax = 32;
 
 // P <- P T, Q <- Q T (first r columns), X += P alpha, R -= Q alpha, and the
-// block partials of the column norms |R_q|^2.
+// block partials of the column norms |R_q|^2.  MC bounds sp, r and nc.
+template <int MC>
 __global__ __launch_bounds__(256) void k_bcg_step(int64_t n, int sp, int r, int nc, const double* __restrict__ Tm,
                                                   const double* __restrict__ alpha, double* __restrict__ P,
                                                   double* __restrict__ Q, double* __restrict__ X,
                                                   double* __restrict__ R, double* __restrict__ rr_part) {
-    __shared__ double sT[kBcgMax * kBcgMax];
-    __shared__ double sA[kBcgMax * kBcgMax];
-    __shared__ double sred[4][kBcgMax];
+    __shared__ double sT[MC * MC];
+    __shared__ double sA[MC * MC];
+    __shared__ double sred[4][MC];
     for (int e = threadIdx.x; e < sp * r; e += blockDim.x) sT[e] = Tm[e];
     for (int e = threadIdx.x; e < r * nc; e += blockDim.x) sA[e] = alpha[e];
     __syncthreads();
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool ok = i < n;
     const int64_t ii = ok ? i : 0;
-    double v[kBcgMax], w[kBcgMax];
+    double v[MC], w[MC];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // P
 #pragma unroll
-    for (int a = 0; a < kBcgMax; ++a) v[a] = a < sp ? P[a * n + ii] : 0.0;
+    for (int a = 0; a < MC; ++a) v[a] = a < sp ? P[a * n + ii] : 0.0;
 #pragma unroll
-    for (int j = 0; j < kBcgMax; ++j) {
+    for (int j = 0; j < MC; ++j) {
         double s = 0.0;
         if (j < r)
 #pragma unroll
-            for (int a = 0; a < kBcgMax; ++a)
+            for (int a = 0; a < MC; ++a)
                 if (a < sp) s += v[a] * sT[a + sp * j];
         w[j] = s;
     }
     if (ok)
 #pragma unroll
-        for (int j = 0; j < kBcgMax; ++j)
+        for (int j = 0; j < MC; ++j)
             if (j < r) P[j * n + i] = w[j];
 #pragma unroll
-    for (int q = 0; q < kBcgMax; ++q) {
+    for (int q = 0; q < MC; ++q) {
         if (q >= nc) break;
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < kBcgMax; ++j)
+        for (int j = 0; j < MC; ++j)
             if (j < r) s += w[j] * sA[j + r * q];
         if (ok) X[q * n + i] += s;
     }
     // Q
 #pragma unroll
-    for (int a = 0; a < kBcgMax; ++a) v[a] = a < sp ? Q[a * n + ii] : 0.0;
+    for (int a = 0; a < MC; ++a) v[a] = a < sp ? Q[a * n + ii] : 0.0;
 #pragma unroll
-    for (int j = 0; j < kBcgMax; ++j) {
+    for (int j = 0; j < MC; ++j) {
         double s = 0.0;
         if (j < r)
 #pragma unroll
-            for (int a = 0; a < kBcgMax; ++a)
+            for (int a = 0; a < MC; ++a)
                 if (a < sp) s += v[a] * sT[a + sp * j];
         w[j] = s;
     }
     if (ok)
 #pragma unroll
-        for (int j = 0; j < kBcgMax; ++j)
+        for (int j = 0; j < MC; ++j)
             if (j < r) Q[j * n + i] = w[j];
     // R -= Q alpha with the wave sums of |R_q|^2 (fixed-order trees)
 #pragma unroll
-    for (int q = 0; q < kBcgMax; ++q) {
+    for (int q = 0; q < MC; ++q) {
         if (q >= nc) break;
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < kBcgMax; ++j)
+        for (int j = 0; j < MC; ++j)
             if (j < r) s += w[j] * sA[j + r * q];
         double e = 0.0;
         if (ok) {
@@ -394,29 +395,30 @@ __global__ __launch_bounds__(256) void k_bcg_step(int64_t n, int sp, int r, int 
 }
 
 // P <- Z + P beta  (P: n x sp in, n x nc out; beta sp x nc).
+template <int MC>
 __global__ __launch_bounds__(256) void k_bcg_dir(int64_t n, int sp, int nc, const double* __restrict__ beta,
                                                  const double* __restrict__ Z, double* __restrict__ P) {
-    __shared__ double sB[kBcgMax * kBcgMax];
+    __shared__ double sB[MC * MC];
     for (int e = threadIdx.x; e < sp * nc; e += blockDim.x) sB[e] = beta[e];
     __syncthreads();
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double v[kBcgMax];
+    double v[MC];
 #pragma unroll
-    for (int a = 0; a < kBcgMax; ++a) v[a] = a < sp ? P[a * n + i] : 0.0;
+    for (int a = 0; a < MC; ++a) v[a] = a < sp ? P[a * n + i] : 0.0;
 #pragma unroll
-    for (int q = 0; q < kBcgMax; ++q) {
+    for (int q = 0; q < MC; ++q) {
         if (q >= nc) break;
         double s = Z[q * n + i];
 #pragma unroll
-        for (int a = 0; a < kBcgMax; ++a)
+        for (int a = 0; a < MC; ++a)
             if (a < sp) s += v[a] * sB[a + sp * q];
         P[q * n + i] = s;
     }
 }
 
 // Y (n x k2) = S (n x k1) C (k1 x k2, column-major), k1 <= 96, k2 <= 32;
-// C staged in LDS, one row of Y per thread accumulated in registers.
+// C staged in LDS; thread per (row, group of 8 output columns).
 __global__ void k_gemm_small(int64_t n, int k1, int64_t lds, const double* __restrict__ S, int k2,
                              const double* __restrict__ C, int64_t ldy, double* __restrict__ Y) {
     __shared__ double sc[96 * 32];
@@ -424,18 +426,75 @@ __global__ void k_gemm_small(int64_t n, int k1, int64_t lds, const double* __res
     __syncthreads();
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double acc[32];
+    const int j0 = blockIdx.y * 8;
+    const int nj = min(8, k2 - j0);
+    double acc[8];
 #pragma unroll
-    for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+    for (int j = 0; j < 8; ++j) acc[j] = 0.0;
     for (int a = 0; a < k1; ++a) {
         const double sv = S[a * lds + i];
 #pragma unroll
-        for (int j = 0; j < 32; ++j)
-            if (j < k2) acc[j] += sv * sc[j * k1 + a];
+        for (int j = 0; j < 8; ++j)
+            if (j < nj) acc[j] += sv * sc[(j0 + j) * k1 + a];
     }
 #pragma unroll
-    for (int j = 0; j < 32; ++j)
-        if (j < k2) Y[j * ldy + i] = acc[j];
+    for (int j = 0; j < 8; ++j)
+        if (j < nj) Y[(j0 + j) * ldy + i] = acc[j];
+}
+
+// Y = alpha Y + [A1 A2] C  (A1: n x k1a, A2: n x k1b, C: (k1a + k1b) x k2
+// column-major, k1a + k1b <= 96, k2 <= 32); Y must not overlap A1 or A2.
+// Thread per (row, group of 8 output columns); alpha == 0 never reads Y.
+__global__ void k_gemm_cat(int64_t n, int k1a, int64_t lda1, const double* __restrict__ A1, int k1b, int64_t lda2,
+                           const double* __restrict__ A2, int k2, const double* __restrict__ C, double alpha,
+                           int64_t ldy, double* __restrict__ Y) {
+    __shared__ double sc[96 * 32];
+    const int k1 = k1a + k1b;
+    for (int t = threadIdx.x; t < k1 * k2; t += blockDim.x) sc[t] = C[t];
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int j0 = blockIdx.y * 8;
+    const int nj = min(8, k2 - j0);
+    double acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+    for (int a = 0; a < k1; ++a) {
+        const double sv = a < k1a ? A1[a * lda1 + i] : A2[(a - k1a) * lda2 + i];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (j < nj) acc[j] += sv * sc[(j0 + j) * k1 + a];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j < nj) {
+            const int64_t o = (j0 + j) * ldy + i;
+            Y[o] = alpha == 0.0 ? acc[j] : alpha * Y[o] + acc[j];
+        }
+}
+
+// V[:, 0:k2] = V[:, 0:k1] T in place (T: k1 x k2 column-major, both <= MC):
+// every thread reads its whole row before writing it.
+template <int MC>
+__global__ __launch_bounds__(256) void k_xform_inplace(int64_t n, int k1, int k2, const double* __restrict__ Tm,
+                                                       int64_t ld, double* __restrict__ V) {
+    __shared__ double sT[MC * MC];
+    for (int e = threadIdx.x; e < k1 * k2; e += blockDim.x) sT[e] = Tm[e];
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v[MC];
+#pragma unroll
+    for (int a = 0; a < MC; ++a) v[a] = a < k1 ? V[a * ld + i] : 0.0;
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+        if (j >= k2) break;
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < MC; ++a)
+            if (a < k1) s += v[a] * sT[a + k1 * j];
+        V[j * ld + i] = s;
+    }
 }
 
 // R = AX - KX diag(mu)
@@ -637,18 +696,48 @@ int launch_gram(int64_t n, int k1, int64_t lda, const double* A, int k2a, int64_
 
 void launch_bcg_step(int64_t n, int sp, int r, int nc, const double* T, const double* alpha, double* P, double* Q,
                      double* X, double* R, double* rr_part, hipStream_t st) {
-    hipLaunchKernelGGL(k_bcg_step, dim3(nb1(n)), dim3(256), 0, st, n, sp, r, nc, T, alpha, P, Q, X, R, rr_part);
+    const int mc = std::max(sp, nc);
+#define MLB_BS(M) hipLaunchKernelGGL(k_bcg_step<M>, dim3(nb1(n)), dim3(256), 0, st, n, sp, r, nc, T, alpha, P, Q, X, R, rr_part)
+    if (mc <= 4) MLB_BS(4);
+    else if (mc <= 8) MLB_BS(8);
+    else if (mc <= 12) MLB_BS(12);
+    else if (mc <= 16) MLB_BS(16);
+    else if (mc <= 24) MLB_BS(24);
+    else MLB_BS(32);
+#undef MLB_BS
 }
 
 int bcg_step_parts(int64_t n) { return nb1(n); }
 
 void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const double* Z, double* P, hipStream_t st) {
-    hipLaunchKernelGGL(k_bcg_dir, dim3(nb1(n)), dim3(256), 0, st, n, sp, nc, beta, Z, P);
+    const int mc = std::max(sp, nc);
+#define MLB_BD(M) hipLaunchKernelGGL(k_bcg_dir<M>, dim3(nb1(n)), dim3(256), 0, st, n, sp, nc, beta, Z, P)
+    if (mc <= 4) MLB_BD(4);
+    else if (mc <= 8) MLB_BD(8);
+    else if (mc <= 12) MLB_BD(12);
+    else if (mc <= 16) MLB_BD(16);
+    else if (mc <= 24) MLB_BD(24);
+    else MLB_BD(32);
+#undef MLB_BD
 }
 
 void launch_gemm_small(int64_t n, int k1, int64_t lds, const double* S, int k2, const double* C, int64_t ldy,
                        double* Y, hipStream_t st) {
-    hipLaunchKernelGGL(k_gemm_small, dim3(nb1(n)), dim3(kBlock), 0, st, n, k1, lds, S, k2, C, ldy, Y);
+    hipLaunchKernelGGL(k_gemm_small, dim3(nb1(n), (k2 + 7) / 8), dim3(kBlock), 0, st, n, k1, lds, S, k2, C, ldy, Y);
+}
+void launch_gemm_cat(int64_t n, int k1a, int64_t lda1, const double* A1, int k1b, int64_t lda2, const double* A2,
+                     int k2, const double* C, double alpha, int64_t ldy, double* Y, hipStream_t st) {
+    hipLaunchKernelGGL(k_gemm_cat, dim3(nb1(n), (k2 + 7) / 8), dim3(kBlock), 0, st, n, k1a, lda1, A1, k1b, lda2, A2,
+                       k2, C, alpha, ldy, Y);
+}
+void launch_xform_inplace(int64_t n, int k1, int k2, const double* T, int64_t ld, double* V, hipStream_t st) {
+    const int mc = std::max(k1, k2);
+#define MLB_XF(M) hipLaunchKernelGGL(k_xform_inplace<M>, dim3(nb1(n)), dim3(256), 0, st, n, k1, k2, T, ld, V)
+    if (mc <= 8) MLB_XF(8);
+    else if (mc <= 16) MLB_XF(16);
+    else if (mc <= 24) MLB_XF(24);
+    else MLB_XF(32);
+#undef MLB_XF
 }
 void launch_residual_block(int64_t n, int ncols, int64_t ld, const double* AX, const double* KX, const double* mu,
                            double* R, hipStream_t st) {

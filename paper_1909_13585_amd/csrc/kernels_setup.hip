@@ -203,19 +203,34 @@ __global__ void k_gj_step(int64_t n, int64_t k, double* __restrict__ A, const do
 }
 
 // y = A x for a dense symmetric FP64 matrix, one wavefront per row.
-template <typename T>
+// y = A x for a dense row-major A (coarsest inverse), one wave per row, up
+// to 8 columns per pass so each row is read once per 8 columns.
+template <typename T, int CB>
 __global__ void k_dense_matvec(int64_t n, int ncols, int64_t ld, const double* __restrict__ A,
                                const T* __restrict__ x, T* __restrict__ y) {
     const int lane = threadIdx.x & 63;
     const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     if (row >= n) return;
     const double* Ar = A + row * n;
-    for (int col = 0; col < ncols; ++col) {
-        double s = 0.0;
-        for (int64_t j = lane; j < n; j += 64) s += Ar[j] * (double)x[col * ld + j];
+    for (int c0 = 0; c0 < ncols; c0 += CB) {
+        const int nq = min(CB, ncols - c0);
+        double s[CB];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) y[col * ld + row] = (T)s;
+        for (int q = 0; q < CB; ++q) s[q] = 0.0;
+#pragma unroll 4
+        for (int64_t j = lane; j < n; j += 64) {
+            const double a = Ar[j];
+#pragma unroll
+            for (int q = 0; q < CB; ++q)
+                if (q < nq) s[q] += a * (double)x[(c0 + q) * ld + j];
+        }
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+            double v = s[q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0 && q < nq) y[(c0 + q) * ld + row] = (T)v;
+        }
     }
 }
 
@@ -276,7 +291,10 @@ void launch_gj_step(int64_t n, int64_t k, double* A, const double* rowk, const d
 }
 template <typename T>
 void launch_dense_matvec(int64_t n, int ncols, int64_t ld, const double* A, const T* x, T* y, hipStream_t st) {
-    hipLaunchKernelGGL((k_dense_matvec<T>), dim3(nb1(n * 64)), dim3(kBlock), 0, st, n, ncols, ld, A, x, y);
+    if (ncols == 1)
+        hipLaunchKernelGGL((k_dense_matvec<T, 1>), dim3(nb1(n * 64)), dim3(kBlock), 0, st, n, ncols, ld, A, x, y);
+    else
+        hipLaunchKernelGGL((k_dense_matvec<T, 8>), dim3(nb1(n * 64)), dim3(kBlock), 0, st, n, ncols, ld, A, x, y);
 }
 template void launch_dense_matvec<double>(int64_t, int, int64_t, const double*, const double*, double*, hipStream_t);
 template void launch_dense_matvec<float>(int64_t, int, int64_t, const double*, const float*, float*, hipStream_t);

@@ -16,9 +16,9 @@
 //
 // Apply mapping: one thread per (node, component, column chunk); lanes run
 // over consecutive nodes (coalesced stencil loads, stride-dim vector loads
-// that hit the same cache lines).  The blocks that share a node range are
-// placed on the same XCD (blocks are dealt round-robin over the 8 XCDs), so
-// the x values they all read come from one L2.
+// that hit the same cache lines).  Each XCD (blocks are dealt round robin
+// over the 8 XCDs) works on one contiguous range of nodes with every
+// component and column chunk, so the x values they share come from one L2.
 #include "kernels.h"
 
 namespace mlb {
@@ -41,13 +41,16 @@ __device__ inline void node_ijk(const Geo& g, int64_t node, int& i, int& j, int&
     k = (int)(r / g.nny);
 }
 
-// XCD-aware decode of a 1-D grid into (node block, group): blocks with the
-// same node block and different groups share blockIdx.x mod 8.
+// XCD-aware decode of a 1-D grid into (node block, group).  Blocks are
+// dealt round robin over the 8 XCDs; XCD x gets the contiguous node-block
+// range [x P, (x+1) P) (P = padded node blocks / 8) with all groups of each
+// node block, so neighbouring nodes' vector values are shared through one L2.
 __device__ inline bool xcd_decode(int64_t nblocks_nodes, int ngroups, int64_t& nodeblk, int& grp) {
     const int64_t b = blockIdx.x;
     const int64_t xcd = b % kXcd, slot = b / kXcd;
+    const int64_t per = (int64_t)gridDim.x / ngroups / kXcd;   // node blocks per XCD
     grp = (int)(slot % ngroups);
-    nodeblk = (slot / ngroups) * kXcd + xcd;
+    nodeblk = xcd * per + slot / ngroups;
     return nodeblk < nblocks_nodes;
 }
 
@@ -335,10 +338,11 @@ template <typename T>
 void launch_apply_nb(int dim, const Geo& g, const T* A, bool diag, int ncols, int64_t ld, const T* x, T* y, int mode,
                      const T* r, const T* dinv, T omega, hipStream_t st) {
     const int64_t nbn = (g.nodes + kNbThreads - 1) / kNbThreads;
-    // columns per thread: at most 8, split evenly (each chunk re-reads the stencil)
-    const int per = (ncols + 7) / 8;
+    // columns per thread: at most 6, split evenly (each chunk re-reads the
+    // stencil; wider chunks lose more in parallelism than they save)
+    const int per = (ncols + 5) / 6;
     const int want = (ncols + per - 1) / per;
-    const int cb = want <= 1 ? 1 : want <= 2 ? 2 : want <= 3 ? 3 : want <= 4 ? 4 : want <= 6 ? 6 : 8;
+    const int cb = want <= 1 ? 1 : want <= 2 ? 2 : want <= 3 ? 3 : want <= 4 ? 4 : want <= 6 ? 6 : want <= 8 ? 8 : 12;
     const int nchunks = (ncols + cb - 1) / cb;
     const dim3 gr = xcd_grid(g.nodes, dim * nchunks);
     const dim3 b(kNbThreads);
@@ -359,7 +363,8 @@ void launch_apply_nb(int dim, const Geo& g, const T* A, bool diag, int ncols, in
         else if (cb == 3) MLB_NB_M(D, 3); \
         else if (cb == 4) MLB_NB_M(D, 4); \
         else if (cb == 6) MLB_NB_M(D, 6); \
-        else MLB_NB_M(D, 8);              \
+        else if (cb == 8) MLB_NB_M(D, 8); \
+        else MLB_NB_M(D, 12);             \
     } while (0)
     if (dim == 2) MLB_NB_C(2);
     else MLB_NB_C(3);

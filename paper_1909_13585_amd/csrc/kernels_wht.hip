@@ -114,6 +114,7 @@ __device__ inline double wht_block_sum(double v, double* sh) {
 // barriers); the next node plane is prefetched one step ahead.
 constexpr int kWT = 8;          // tile edge (element columns per wave edge)
 constexpr int kW3 = 4;          // waves per block
+constexpr int kXcd3 = 8;        // XCDs the blocks are dealt over
 
 #ifndef MLB_WHT3_WAVES
 #define MLB_WHT3_WAVES 2
@@ -129,7 +130,12 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(MLB_WH
     __shared__ double sh[16];
     const int lane = threadIdx.x;              // 0..63
     const int tx = lane & 7, ty = lane >> 3;
-    const int64_t tile = (int64_t)blockIdx.x * kW3 + threadIdx.y;
+    // Blocks are dealt round robin over the 8 XCDs; each XCD gets one
+    // contiguous range of the (z-chunk major) tile order, so the node planes
+    // and columns that neighbouring tiles share are re-read from its own L2.
+    const int64_t per_xcd = gridDim.x / kXcd3;   // grid is a multiple of kXcd3
+    const int64_t bl = (blockIdx.x % kXcd3) * per_xcd + blockIdx.x / kXcd3;
+    const int64_t tile = bl * kW3 + threadIdx.y;
     const int64_t ntile_xy = (int64_t)ntiles_x * ntiles_y;
     const int tzc = (int)(tile / ntile_xy);
     const int txy = (int)(tile % ntile_xy);
@@ -375,7 +381,8 @@ static void wht_geometry(int dim, const Geo& g, dim3& grid, dim3& block, int& ch
         chunk = (g.nnz + nch - 1) / nch;
         nch = (g.nnz + chunk - 1) / chunk;
         const int64_t tiles = (int64_t)tiles_x * tiles_y * nch;
-        grid = dim3((unsigned)((tiles + kW3 - 1) / kW3), 1, 1);
+        const int64_t blocks = (tiles + kW3 - 1) / kW3;
+        grid = dim3((unsigned)((blocks + kXcd3 - 1) / kXcd3 * kXcd3), 1, 1);
         block = dim3(64, kW3, 1);
         ntx = tiles_x;
         nty = tiles_y;
