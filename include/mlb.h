@@ -185,9 +185,10 @@ int mlb_sensitivities_dev(mlb_ctx* ctx, double* dJ, double* dlam, mlb_solve_info
 
 /* Warm starts.  kind MLB_WARM_COARSE: `data` holds ncols start vectors of
  * the eigen level (n_l x ncols, column-major, host); MLB_WARM_STATIC: one
- * fine initial guess per load case (n x ncases, host).  MLB_WARM_NONE
- * clears both.  A warm start only changes iteration counts, never the
- * tolerance the solvers reach. */
+ * fine initial guess per load case (n x ncases, host), scaled per column
+ * by alpha = f^T u0 / u0^T K u0 before the solve.  MLB_WARM_NONE clears both.
+ * A warm start only changes iteration counts, never the tolerance the
+ * solvers reach. */
 int mlb_set_warm_start(mlb_ctx* ctx, int kind, int ncols, const double* data);
 
 /* ---- kernel-level entry points (device pointers, enqueue only) -------- */
@@ -207,6 +208,10 @@ int mlb_set_state_dev(mlb_ctx* ctx, const double* u, double* stress_out, void* s
  * of ncols columns, masked at fixed DOFs of both levels. */
 int mlb_prolong_dev(mlb_ctx* ctx, int level, int ncols, const double* xc, double* yf, void* stream);
 int mlb_restrict_dev(mlb_ctx* ctx, int level, int ncols, const double* xf, double* yc, void* stream);
+/* The K^l-orthonormal coarse modes Psi^l (n_l x k, column-major) of the last
+   mlb_buckling (Sec. 2.1 step 1), e.g. as training targets of a warm start. */
+int mlb_coarse_modes_dev(mlb_ctx* ctx, int k, double* Psi, void* stream);
+
 /* One multigrid V-cycle z = M^-1 r starting at `level` (ncols columns). */
 int mlb_vcycle_dev(mlb_ctx* ctx, int level, int ncols, const double* r, double* z, void* stream);
 

@@ -209,6 +209,10 @@ class Context:
         self._check(self.lib.mlb_restrict_dev(self.h, level, xf.shape[0] if xf.dim() > 1 else 1,
                                               _dptr(xf), _dptr(yc), _stream()))
 
+    def coarse_modes_dev(self, k, Psi):
+        """Copies the K^l-orthonormal coarse modes of the last buckling call into Psi (k, n_l)."""
+        self._check(self.lib.mlb_coarse_modes_dev(self.h, k, _dptr(Psi), _stream()))
+
     def vcycle_dev(self, level, r, z):
         self._check(self.lib.mlb_vcycle_dev(self.h, level, r.shape[0] if r.dim() > 1 else 1,
                                             _dptr(r), _dptr(z), _stream()))

@@ -81,6 +81,22 @@ _SIGS = {
     "mlb_prolong_dev": (_I, [_P, _I, _I, _P, _P, _P]),
     "mlb_restrict_dev": (_I, [_P, _I, _I, _P, _P, _P]),
     "mlb_vcycle_dev": (_I, [_P, _I, _I, _P, _P, _P]),
+    "mlb_coarse_modes_dev": (_I, [_P, _I, _P, _P]),
+    # warm-start network kernels (include/mlb_nn.h)
+    "mlb_nn_conv3d": (_I, [_I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P]),
+    "mlb_nn_conv3d_wgrad": (_I, [_I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),
+    "mlb_nn_relu_mask": (_I, [C.c_int64, _P, _P, _P]),
+    "mlb_nn_pool2": (_I, [C.c_int64, _I, _I, _I, C.c_float, _P, _P, _P]),
+    "mlb_nn_axpy": (_I, [C.c_int64, C.c_float, _P, _P, _P]),
+    "mlb_nn_unpool2": (_I, [C.c_int64, _I, _I, _I, C.c_float, _P, _P, _P]),
+    "mlb_nn_concat": (_I, [_I, _I, _I, C.c_int64, _P, _P, _P, _P]),
+    "mlb_nn_split": (_I, [_I, _I, _I, C.c_int64, _P, _P, _P, _P]),
+    "mlb_nn_cell2node": (_I, [C.c_int64, _I, _I, _I, _P, _P, _P]),
+    "mlb_nn_node2cell_grad": (_I, [C.c_int64, _I, _I, _I, _P, _P, _P]),
+    "mlb_nn_mse_work": (C.c_int64, [C.c_int64]),
+    "mlb_nn_mse": (_I, [C.c_int64, _P, _P, _P, C.c_float, _P, _P, _P, _P]),
+    "mlb_nn_adam": (_I, [C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _I, _P, _P, _P, _P, _P, _P]),
+    "mlb_nn_to_bf16": (_I, [C.c_int64, _P, _P, _P]),
 }
 
 _lib = None

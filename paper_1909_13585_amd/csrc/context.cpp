@@ -1467,8 +1467,22 @@ static int solve_static_common(mlb_ctx* c, double tol, int max_it, mlb_solve_inf
     c->has_static = c->has_buck = false;
     bool x0 = false;
     if ((int64_t)c->warm_static.size() == c->n * c->ncases) {
-        HIPC(hipMemcpyAsync(c->U, c->warm_static.data(), sizeof(double) * c->n * c->ncases, hipMemcpyHostToDevice, c->st));
-        launch_mask_fixed(c->n, c->ncases, c->n, c->lv[0].nmask, c->dim, c->U, c->st);
+        // initial guess scaled per column to its energy-optimal multiple
+        // alpha = f^T u0 / u0^T K u0 (the minimiser of the energy-norm error
+        // along u0), so a guess of the right shape but any scale helps
+        const int nc = c->ncases;
+        CHK(ensure_cg(c, nc));
+        HIPC(hipMemcpyAsync(c->U, c->warm_static.data(), sizeof(double) * c->n * nc, hipMemcpyHostToDevice, c->st));
+        launch_mask_fixed(c->n, nc, c->n, c->lv[0].nmask, c->dim, c->U, c->st);
+        apply_K<double>(c, 1, nc, c->U, c->R, kModeY, nullptr, nullptr);
+        dots(c, c->n, nc, c->F, c->U, sc(c, 0));
+        dots(c, c->n, nc, c->U, c->R, sc(c, 0) + nc);
+        std::vector<double> fu(2 * nc);
+        CHK(read_scal(c, sc(c, 0), 2 * nc, fu.data()));
+        std::vector<double> alpha(nc);
+        for (int i = 0; i < nc; ++i) alpha[i] = fu[nc + i] > 0 ? fu[i] / fu[nc + i] : 0.0;
+        CHK(upload_cm(c, sc(c, 1), alpha));
+        launch_scale_cols(c->n, nc, c->n, sc(c, 1), c->U, c->st);
         x0 = true;
     }
     if (c->ncases > 1 && c->o.block_cg) CHK(bpcg(c, c->F, c->U, c->ncases, tol, max_it, x0, info));
@@ -1544,6 +1558,15 @@ int mlb_sensitivities_dev(mlb_ctx* c, double* dJ, double* dlam, mlb_solve_info* 
     if (!c) return MLB_EINVAL;
     c->st = pick(c, stream);
     return do_sens(c, dJ, dlam, info);
+}
+
+int mlb_coarse_modes_dev(mlb_ctx* c, int k, double* Psi, void* stream) {
+    if (!c || !Psi || k < 1) return MLB_EINVAL;
+    if (!c->has_buck || k > c->k) return fail(c, MLB_ESTATE, "no coarse modes: call mlb_buckling with at least k modes");
+    c->st = pick(c, stream);
+    const int64_t nl = c->lv[c->ell - 1].n;
+    HIPC(hipMemcpyAsync(Psi, c->eS, sizeof(double) * nl * k, hipMemcpyDeviceToDevice, c->st));
+    return MLB_OK;
 }
 
 int mlb_set_warm_start(mlb_ctx* c, int kind, int ncols, const double* data) {

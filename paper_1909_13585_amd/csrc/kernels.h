@@ -128,4 +128,24 @@ void launch_dlam(int dim, const Geo& g, const double* x, double p, double E1, do
                  int64_t ld, const double* Phi, const double* Z, const double* lam, const double* K0,
                  const double* Hk, const double* D0Bc, double* out, hipStream_t st);
 
+// ---- warm-start network (kernels_nn.hip)
+int launch_nn_conv3d(int N, int Ci, int Co, int D, int H, int W, int K, int trans, const float* x, const uint16_t* w,
+                     const float* bias, float* y, int relu, hipStream_t st);
+int launch_nn_conv3d_wgrad(int N, int Ci, int Co, int D, int H, int W, int K, const float* x, const float* dy,
+                           float* dw, float* db, hipStream_t st);
+void launch_nn_relu_mask(int64_t n, const float* y, float* g, hipStream_t st);
+void launch_nn_pool2(int64_t planes, int D, int H, int W, float scale, const float* x, float* y, hipStream_t st);
+void launch_nn_axpy(int64_t n, float a, const float* x, float* y, hipStream_t st);
+void launch_nn_unpool2(int64_t planes, int D, int H, int W, float scale, const float* gy, float* gx, hipStream_t st);
+void launch_nn_concat(int N, int Ca, int Cb, int64_t V, const float* a, const float* b, float* y, hipStream_t st);
+void launch_nn_split(int N, int Ca, int Cb, int64_t V, const float* y, float* a, float* b, hipStream_t st);
+void launch_nn_cell2node(int64_t planes, int D, int H, int W, const float* c, float* nd, hipStream_t st);
+void launch_nn_node2cell_grad(int64_t planes, int D, int H, int W, const float* gn, float* gc, hipStream_t st);
+int nn_mse_parts(int64_t n);
+void launch_nn_mse(int64_t n, const float* pred, const float* target, const float* weight, float scale, float* grad,
+                   int nparts, double* part, hipStream_t st);
+void launch_nn_adam(int64_t n, float lr, float b1, float b2, float eps, int step, float* w, uint16_t* wb,
+                    const float* g, float* m, float* v, hipStream_t st);
+void launch_nn_to_bf16(int64_t n, const float* a, uint16_t* b, hipStream_t st);
+
 }  // namespace mlb

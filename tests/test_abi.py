@@ -11,11 +11,15 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "mlb.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 def _header():
-    with open(HEADER) as fh:
-        text = fh.read()
+    text = ""
+    for h in HEADERS:
+        with open(h) as fh:
+            text += fh.read() + "\n"
     return re.sub(r"/\*.*?\*/", "", text, flags=re.S)
 
 
@@ -62,7 +66,7 @@ def _lib():
 def test_header_parses():
     fns = _declared_functions()
     assert len(fns) >= 20
-    assert {"mlb_create", "mlb_buckling_dev", "mlb_sensitivities_dev", "mlb_vcycle_dev"} <= set(fns)
+    assert {"mlb_create", "mlb_buckling_dev", "mlb_sensitivities_dev", "mlb_vcycle_dev", "mlb_nn_conv3d"} <= set(fns)
 
 
 def test_library_exports_every_declared_symbol():
