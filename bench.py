@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="skip timing the plain FP64 path next to the mixed one")
     ap.add_argument("--tol-eig", type=float, default=1e-8)
+    ap.add_argument("--learned", default=os.path.join(ROOT, "paper_1909_13585_amd", "data", "warmstart_unet.npz"),
+                    help="trained warm-start network; the learned leg is timed when the file exists")
     ap.add_argument("--nel", type=str, default="192,64,64")
     ap.add_argument("--levels", type=int, default=5)
     ap.add_argument("--eig-level", type=int, default=3)
@@ -79,8 +81,9 @@ def cpu_baseline(args):
     return t, n_sample
 
 
-def run_path(args, precision, p, x_dev, steps, warmup, label):
-    """Times `steps` full analyses after `warmup` untimed ones."""
+def run_path(args, precision, p, x_dev, steps, warmup, label, net=None):
+    """Times `steps` full analyses after `warmup` untimed ones.  With `net`,
+    every timed analysis first predicts its warm starts from the density."""
     import torch
     import paper_1909_13585_amd as mlb
     nel = tuple(int(v) for v in args.nel.split(","))
@@ -95,6 +98,9 @@ def run_path(args, precision, p, x_dev, steps, warmup, label):
     dlam = torch.empty((k, m), dtype=torch.float64, device="cuda")
 
     def step():
+        if net is not None:
+            from paper_1909_13585_amd import warmstart as ws
+            ws.set_learned_warm_start(ctx, net, p["x"], nel, args.eig_level)
         ctx.set_density_dev(x_dev)
         J, si = ctx.solve_static_dev(U, tol=1e-8, max_it=2000)
         lam, ei = ctx.buckling_dev(k, Phi, tol_eig=args.tol_eig)
@@ -194,6 +200,19 @@ def main():
     apply12_ms, alg12 = apply_roofline(ctx, n, m, max(5, args.apply_reps // 5), 12)
     ctx.close()
 
+    learned = None
+    if os.path.exists(args.learned):
+        from paper_1909_13585_amd.warmstart import UNet3D
+        net = UNet3D.from_file(args.learned)
+        ctxl, secl, outl = run_path(args, prec, p, x_dev, args.steps, 1, "learned", net=net)
+        ctxl.close()
+        learned = {"s_per_analysis": secl, "static_iterations": outl[1]["iterations"],
+                   "coarse_iterations": outl[3]["coarse_iterations"],
+                   "fine_block_iterations": outl[3]["fine_iterations"],
+                   "adjoint_iterations": outl[4]["iterations"],
+                   "max_rel_lambda_diff_vs_cold": float(np.max(np.abs(np.asarray(outl[2]) / np.asarray(lam) - 1))),
+                   "weights": os.path.relpath(args.learned, ROOT)}
+
     fp64 = None
     if args.precision == "mixed" and not args.no_fp64_reference:
         ctx64, sec64, out64 = run_path(args, mlb.MLB_FP64, p, x_dev, max(1, min(args.steps, 2)), 1, "fp64")
@@ -240,6 +259,7 @@ def main():
         "phase_s": {"coarse": ei["seconds_coarse"], "fine": ei["seconds_fine"], "ritz": ei["seconds_ritz"],
                     "static": si["seconds"], "adjoint": ai["seconds"]},
         "fp64_reference": fp64,
+        "learned_warm_start": learned,
         "roofline": {"bound": "hbm", "kernel": "k_apply_wht3<double> (fine H8 K apply, 1 column)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES, "apply_ms": apply_ms,

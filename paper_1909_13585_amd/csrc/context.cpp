@@ -64,7 +64,7 @@ struct mlb_ctx {
     double *dK0 = nullptr, *dHk = nullptr, *dBc = nullptr, *dD0Bc = nullptr, *dD0 = nullptr, *dT = nullptr,
            *dMc = nullptr, *dGHc = nullptr;
     float* fK0 = nullptr;
-    float whtf[72] = {};   // FP32 copy of the Walsh-Hadamard blocks (host; passed by value)
+    float whtf[9] = {};    // FP32 copy of the Walsh-Hadamard block numbers (host; passed by value)
     std::vector<Level> lv;
     int64_t n = 0, m = 0;
     // fine-level problem data
@@ -239,7 +239,7 @@ const float* dinv_of<float>(Level& l) { return l.dinvf; }
 template <typename T>
 const T* wht_of(mlb_ctx* c);
 template <>
-const double* wht_of<double>(mlb_ctx* c) { return c->tab.wht; }
+const double* wht_of<double>(mlb_ctx* c) { return c->tab.whs; }
 template <>
 const float* wht_of<float>(mlb_ctx* c) { return c->whtf; }
 
@@ -1204,7 +1204,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     HIPC(hipStreamCreate(&c->own));
     c->st = c->own;
     build_tables(dim, desc->nu, &c->tab);
-    for (int i = 0; i < 72; ++i) c->whtf[i] = (float)c->tab.wht[i];
+    for (int i = 0; i < 9; ++i) c->whtf[i] = (float)c->tab.whs[i];
     // device tables
     CHK(dalloc(c, &c->dK0, 576));
     CHK(dalloc(c, &c->fK0, 576));

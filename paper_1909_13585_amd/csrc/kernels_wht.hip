@@ -8,8 +8,9 @@
 // 2^dim independent dim x dim blocks B_sigma:
 //     K0 u = H diag(B_sigma) H u / 4^dim      (per element, times E_e)
 // i.e. ~ 200 operations per element instead of the 1152 of a dense 24 x 24
-// product, so the FP64 apply becomes bandwidth-bound.  The blocks (with the
-// 1/4^dim folded in) arrive as kernel arguments and live in SGPRs.
+// product.  Because the cell is also symmetric under axis permutations, the
+// blocks are made of 9 (3D) or 5 (2D) numbers (with the 1/4^dim folded in);
+// they arrive as kernel arguments and stay in scalar registers.
 //
 // Traversal: each thread walks a pencil of elements along the slowest axis
 // (z in 3D, y in 2D), carrying the shared node plane and the partial sums of
@@ -22,9 +23,10 @@
 
 namespace mlb {
 
+// 3D: d0, o0, d7, o7, e1, f1, g2d, g2o, h2;  2D: d0, o0, q1, d3, o3
 template <typename T>
 struct WhtBlocks {
-    T v[8 * 9];   // B_sigma row-major dim x dim, sigma = 0 .. 2^dim - 1
+    T v[9];
 };
 
 __device__ inline double shfl_up_w(double v, int d, int width) { return __shfl_up(v, d, width); }
@@ -44,37 +46,65 @@ __device__ inline void wht(T* s) {
             }
 }
 
-// Structural nonzeros of B_sigma (from the reflection symmetry, independent
-// of the material): component c is a rigid translation when
-// sigma == 1 << c (zero row and column); components c != c2 couple only
-// when bits c and c2 of sigma are equal.  The host checks that every other
-// entry vanishes before this kernel is used.
-template <int DIM>
-__host__ __device__ constexpr bool wht_nz(int s, int c, int c2) {
-    return s != (1 << c) && s != (1 << c2) && (((s >> c) & 1) == ((s >> c2) & 1));
-}
-
-// out[a][c] = E * (H diag(B) H u)[a][c]  for one element.
+// out[a][c] = E * (H diag(B) H u)[a][c] for one element; component c of
+// block sigma sits at Walsh index sigma ^ (1 << c).
 template <int DIM, typename T>
 __device__ inline void element_apply(const WhtBlocks<T>& B, T Ee, T (&u)[DIM][1 << DIM]) {
     constexpr int NN = 1 << DIM;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) wht<DIM, T>(u[c]);
-#pragma unroll
-    for (int s = 0; s < NN; ++s) {
-        T v[DIM], t[DIM];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) v[c] = u[c][s ^ (1 << c)];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            T acc = T(0);
-#pragma unroll
-            for (int c2 = 0; c2 < DIM; ++c2)
-                if (wht_nz<DIM>(s, c, c2)) acc += B.v[s * DIM * DIM + c * DIM + c2] * v[c2];
-            t[c] = acc;
+    if constexpr (DIM == 3) {
+        const T d0 = B.v[0], o0 = B.v[1], d7 = B.v[2], o7 = B.v[3], e1 = B.v[4], f1 = B.v[5], g2d = B.v[6],
+                g2o = B.v[7], h2 = B.v[8];
+        {   // sigma = 0: components at 1, 2, 4
+            const T a = u[0][1], b = u[1][2], c3 = u[2][4];
+            const T sum = o0 * (a + b + c3), dd = d0 - o0;
+            u[0][1] = dd * a + sum;
+            u[1][2] = dd * b + sum;
+            u[2][4] = dd * c3 + sum;
+        }
+        {   // sigma = 7: components at 6, 5, 3
+            const T a = u[0][6], b = u[1][5], c3 = u[2][3];
+            const T sum = o7 * (a + b + c3), dd = d7 - o7;
+            u[0][6] = dd * a + sum;
+            u[1][5] = dd * b + sum;
+            u[2][3] = dd * c3 + sum;
         }
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) u[c][s ^ (1 << c)] = t[c];
+        for (int c = 0; c < 3; ++c) {
+            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            // sigma = 1 << c: component c is a rigid translation (index 0),
+            // components c1, c2 at indices with bits {c, c1} and {c, c2}
+            const int i1 = (1 << c) | (1 << c1), i2 = (1 << c) | (1 << c2);
+            const T v1 = u[c1][i1], v2 = u[c2][i2];
+            u[c1][i1] = e1 * v1 + f1 * v2;
+            u[c2][i2] = f1 * v1 + e1 * v2;
+            u[c][0] = T(0);
+            // sigma = 7 ^ (1 << c): components c1, c2 at indices 1 << c2 and
+            // 1 << c1, component c at index 7
+            const T w1 = u[c1][1 << c2], w2 = u[c2][1 << c1];
+            u[c1][1 << c2] = g2d * w1 + g2o * w2;
+            u[c2][1 << c1] = g2o * w1 + g2d * w2;
+            u[c][7] = h2 * u[c][7];
+        }
+    } else {
+        const T d0 = B.v[0], o0 = B.v[1], q1 = B.v[2], d3 = B.v[3], o3 = B.v[4];
+        {   // sigma = 0: components at 1, 2
+            const T a = u[0][1], b = u[1][2];
+            u[0][1] = d0 * a + o0 * b;
+            u[1][2] = o0 * a + d0 * b;
+        }
+        {   // sigma = 3: components at 2, 1
+            const T a = u[0][2], b = u[1][1];
+            u[0][2] = d3 * a + o3 * b;
+            u[1][1] = o3 * a + d3 * b;
+        }
+        // sigma = 1: component 0 is a translation, component 1 at 3;
+        // sigma = 2: component 1 is a translation, component 0 at 3
+        u[0][0] = T(0);
+        u[1][0] = T(0);
+        u[1][3] = q1 * u[1][3];
+        u[0][3] = q1 * u[0][3];
     }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
@@ -410,7 +440,7 @@ void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, c
                       int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega, double* dot_part,
                       bool clean, hipStream_t st) {
     WhtBlocks<T> B;
-    for (int i = 0; i < 72; ++i) B.v[i] = blocks[i];
+    for (int i = 0; i < 9; ++i) B.v[i] = blocks[i];
     dim3 gr, b;
     int ch, ntx, nty;
     wht_geometry(dim, g, gr, b, ch, ntx, nty);

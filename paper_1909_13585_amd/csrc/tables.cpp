@@ -222,7 +222,58 @@ void build_tables(int dim, double nu, Tables* t) {
             if (!nz) offmax = std::max(offmax, std::fabs(D[(size_t)row * nde + colm]));
             if (s1 == s2) t->wht[s1 * dim * dim + c * dim + c2] = nz ? D[(size_t)row * nde + colm] * scale : 0.0;
         }
-    t->wht_ok = offmax <= 1e-13 * dmax;
+    // The unit square/cube with an isotropic material is also invariant under
+    // axis permutations, which ties the blocks to a few numbers:
+    //   3D: B_0 = d0 I + o0 (J - I), B_7 = d7 I + o7 (J - I); for sigma = 1<<c
+    //   the two other components form [[e1, f1], [f1, e1]]; for sigma with two
+    //   bits set those components form [[g2d, g2o], [g2o, g2d]] and the third
+    //   has h2.  2D: B_0 = [[d0, o0], [o0, d0]], one-bit blocks q1, B_3 =
+    //   [[d3, o3], [o3, d3]].  The kernel uses these numbers; check that they
+    //   reproduce every block exactly.
+    double rec[72] = {};
+    if (dim == 3) {
+        const double* w = t->wht;
+        double* v = t->whs;
+        v[0] = w[0];          v[1] = w[1];            // d0, o0
+        v[2] = w[7 * 9 + 0];  v[3] = w[7 * 9 + 1];    // d7, o7
+        v[4] = w[1 * 9 + 4];  v[5] = w[1 * 9 + 5];    // e1, f1
+        v[6] = w[3 * 9 + 0];  v[7] = w[3 * 9 + 1];    // g2d, g2o
+        v[8] = w[3 * 9 + 8];                          // h2
+        for (int sg = 0; sg < 8; ++sg)
+            for (int c = 0; c < 3; ++c)
+                for (int c2 = 0; c2 < 3; ++c2) {
+                    const int bits = __builtin_popcount(sg);
+                    double r = 0.0;
+                    if (bits == 0) r = c == c2 ? v[0] : v[1];
+                    else if (bits == 3) r = c == c2 ? v[2] : v[3];
+                    else if (bits == 1) {
+                        if (((sg >> c) & 1) == 0 && ((sg >> c2) & 1) == 0) r = c == c2 ? v[4] : v[5];
+                    } else {
+                        const bool in1 = (sg >> c) & 1, in2 = (sg >> c2) & 1;
+                        if (in1 && in2) r = c == c2 ? v[6] : v[7];
+                        else if (!in1 && !in2 && c == c2) r = v[8];
+                    }
+                    rec[sg * 9 + c * 3 + c2] = r;
+                }
+    } else {
+        const double* w = t->wht;
+        double* v = t->whs;
+        v[0] = w[0];          v[1] = w[1];            // d0, o0
+        v[2] = w[1 * 4 + 3];                          // q1
+        v[3] = w[3 * 4 + 0];  v[4] = w[3 * 4 + 1];    // d3, o3
+        for (int sg = 0; sg < 4; ++sg)
+            for (int c = 0; c < 2; ++c)
+                for (int c2 = 0; c2 < 2; ++c2) {
+                    double r = 0.0;
+                    if (sg == 0) r = c == c2 ? v[0] : v[1];
+                    else if (sg == 3) r = c == c2 ? v[3] : v[4];
+                    else if (c == c2 && ((sg >> c) & 1) == 0) r = v[2];
+                    rec[sg * 4 + c * 2 + c2] = r;
+                }
+    }
+    double symdiff = 0.0;
+    for (int i = 0; i < nn * dim * dim; ++i) symdiff = std::max(symdiff, std::fabs(rec[i] - t->wht[i]));
+    t->wht_ok = offmax <= 1e-13 * dmax && symdiff <= 1e-13 * dmax;
 }
 
 }  // namespace mlb

@@ -14,7 +14,8 @@ struct Tables {
     double Mc[8 * 576];     // child c: T_c^T K0 T_c (nde x nde)
     double GHc[8 * 6 * 64]; // child c, Voigt k: T_c^T H^k T_c (nn x nn)
     double wht[8 * 9];      // symmetry-adapted Walsh-Hadamard blocks of K0 / 4^dim
-    bool wht_ok;            // K0 is exactly block diagonal in that basis
+    double whs[9];          // the few numbers those blocks are made of (see tables.cpp)
+    bool wht_ok;            // K0 is exactly block diagonal in that basis, with that structure
 };
 
 void build_tables(int dim, double nu, Tables* t);
