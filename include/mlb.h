@@ -211,6 +211,9 @@ int mlb_restrict_dev(mlb_ctx* ctx, int level, int ncols, const double* xf, doubl
 /* The K^l-orthonormal coarse modes Psi^l (n_l x k, column-major) of the last
    mlb_buckling (Sec. 2.1 step 1), e.g. as training targets of a warm start. */
 int mlb_coarse_modes_dev(mlb_ctx* ctx, int k, double* Psi, void* stream);
+/* The adjoint solutions z_i of K z_i = grad_u(phi_i^T G phi_i) (eq. AdjointSystem),
+   n x k column-major, from the last mlb_sensitivities with dlam requested. */
+int mlb_adjoints_dev(mlb_ctx* ctx, int k, double* Z, void* stream);
 
 /* One multigrid V-cycle z = M^-1 r starting at `level` (ncols columns). */
 int mlb_vcycle_dev(mlb_ctx* ctx, int level, int ncols, const double* r, double* z, void* stream);

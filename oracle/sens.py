@@ -26,15 +26,19 @@ import numpy as np
 from . import fem
 
 
-def compliance_sensitivity(nel, x, U, mat):
-    """dJ/dx_e = -p x^(p-1) (E1 - E0) u_e^T K_e0 u_e for each load case column."""
+def compliance_sensitivity(nel, x, U, mat, elements=None):
+    """dJ/dx_e = -p x^(p-1) (E1 - E0) u_e^T K_e0 u_e for each load case column
+    (for the listed elements only when ``elements`` is given)."""
     dim = len(nel)
     Ke0 = fem.element_stiffness(dim, mat.nu)
     ed = fem.element_dofs(nel)
+    xs = np.asarray(x, dtype=np.float64)
+    if elements is not None:
+        ed, xs = ed[elements], xs[elements]
     U = np.asarray(U)
     Um = U[:, None] if U.ndim == 1 else U
-    dE = mat.p * np.power(x, mat.p - 1.0) * (mat.E1 - mat.E0)
-    out = np.empty((len(x), Um.shape[1]))
+    dE = mat.p * np.power(xs, mat.p - 1.0) * (mat.E1 - mat.E0)
+    out = np.empty((len(xs), Um.shape[1]))
     for c in range(Um.shape[1]):
         ue = Um[ed, c]
         out[:, c] = -dE * np.einsum("ei,ij,ej->e", ue, Ke0, ue)
@@ -70,26 +74,36 @@ def adjoint_rhs(nel, x, phi, fixed, mat):
 def buckling_sensitivity(nel, x, u, lam, phi, fixed, mat, solver):
     """dlambda_i/dx_e for each column of phi (K-normalised), with adjoints z_i
     from K z_i = b_i (eq. AdjointSystem).  Returns (dlam (m, q), Z (n, q))."""
+    q = phi.shape[1]
+    B = np.stack([adjoint_rhs(nel, x, phi[:, i], fixed, mat) for i in range(q)], axis=1)
+    Z = solver.solve(B)
+    return buckling_sensitivity_from_adjoints(nel, x, u, lam, phi, Z, mat), Z
+
+
+def buckling_sensitivity_from_adjoints(nel, x, u, lam, phi, Z, mat, elements=None):
+    """eq. SensitivityLambda (times lambda, see the module notes) given the
+    adjoint solutions Z; for the listed elements only when ``elements`` is given."""
     dim = len(nel)
     Ke0 = fem.element_stiffness(dim, mat.nu)
     D = fem.constitutive(dim, mat.nu)
     Bc = fem.strain_matrix(dim, np.full(dim, 0.5))
     ed = fem.element_dofs(nel)
+    xs = np.asarray(x, dtype=np.float64)
+    if elements is not None:
+        ed, xs = ed[elements], xs[elements]
     q = phi.shape[1]
-    B = np.stack([adjoint_rhs(nel, x, phi[:, i], fixed, mat) for i in range(q)], axis=1)
-    Z = solver.solve(B)
     ue = np.asarray(u)[ed]
     s0 = ue @ (D @ Bc).T                                   # unit-modulus stress
-    xp1 = mat.p * np.power(x, mat.p - 1.0)
+    xp1 = mat.p * np.power(xs, mat.p - 1.0)
     dEk = xp1 * (mat.E1 - mat.E0)
     dEs = xp1 * mat.E1
     H = fem.gradient_products(dim)
     nn = 2 ** dim
-    g0 = np.zeros((len(x), nn, nn))
+    g0 = np.zeros((len(xs), nn, nn))
     for k, (i, j) in enumerate(fem.voigt_pairs(dim)):
         Hk = H[i, i] if i == j else H[i, j] + H[j, i]
         g0 += s0[:, k, None, None] * Hk[None]
-    dlam = np.empty((len(x), q))
+    dlam = np.empty((len(xs), q))
     for i in range(q):
         pe = phi[ed, i]
         ze = Z[ed, i]
@@ -98,7 +112,7 @@ def buckling_sensitivity(nel, x, u, lam, phi, fixed, mat, solver):
         pG = np.einsum("eac,eab,ebc->e", pr, g0, pr)
         zKu = np.einsum("ei,ij,ej->e", ze, Ke0, ue)
         dlam[:, i] = lam[i] * (dEk * pK + lam[i] * (dEs * pG - dEk * zKu))
-    return dlam, Z
+    return dlam
 
 
 def rayleigh_quotient(K, G, v):

@@ -213,6 +213,10 @@ class Context:
         """Copies the K^l-orthonormal coarse modes of the last buckling call into Psi (k, n_l)."""
         self._check(self.lib.mlb_coarse_modes_dev(self.h, k, _dptr(Psi), _stream()))
 
+    def adjoints_dev(self, k, Z):
+        """Copies the adjoint solutions of the last sensitivities call into Z (k, n)."""
+        self._check(self.lib.mlb_adjoints_dev(self.h, k, _dptr(Z), _stream()))
+
     def vcycle_dev(self, level, r, z):
         self._check(self.lib.mlb_vcycle_dev(self.h, level, r.shape[0] if r.dim() > 1 else 1,
                                             _dptr(r), _dptr(z), _stream()))

@@ -82,6 +82,7 @@ _SIGS = {
     "mlb_restrict_dev": (_I, [_P, _I, _I, _P, _P, _P]),
     "mlb_vcycle_dev": (_I, [_P, _I, _I, _P, _P, _P]),
     "mlb_coarse_modes_dev": (_I, [_P, _I, _P, _P]),
+    "mlb_adjoints_dev": (_I, [_P, _I, _P, _P]),
     # warm-start network kernels (include/mlb_nn.h)
     "mlb_nn_conv3d": (_I, [_I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P]),
     "mlb_nn_conv3d_wgrad": (_I, [_I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),

@@ -73,6 +73,7 @@ struct mlb_ctx {
     uint8_t* fixed = nullptr;
     std::vector<uint8_t> fixed_host;
     bool has_bc = false, has_density = false, has_static = false, has_stress = false, has_buck = false;
+    bool has_adj = false;
     int ncases = 0;
     int ref_case_used = 0;
     double* F = nullptr;
@@ -1030,6 +1031,7 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
     const double t0 = now_s();
     const int64_t n = c->n;
     c->has_buck = false;
+    c->has_adj = false;
     launch_stress(c->dim, c->lv[0].g, c->Es, c->U + (int64_t)ref_case * n, c->dD0Bc, c->S, c->st);
     c->has_stress = true;
     c->ref_case_used = ref_case;
@@ -1143,6 +1145,7 @@ int do_sens(mlb_ctx* c, double* dJ_dev, double* dlam_dev, mlb_solve_info* info) 
         else CHK(pcg(c, c->X2, c->Zadj, k, c->tol_solve, c->max_it, false, info));
         launch_dlam(c->dim, g, c->x, c->d.penal, c->d.E1, c->d.E0, c->U + (int64_t)c->ref_case_used * c->n, k,
                     c->n, c->Phi, c->Zadj, c->dlam_l, c->dK0, c->dHk, c->dD0Bc, dlam_dev, c->st);
+        c->has_adj = true;
     }
     CHK(sync(c));
     if (info) info->seconds = now_s() - t0;
@@ -1392,6 +1395,7 @@ static int set_loads_common(mlb_ctx* c, int ncases) {
     c->ncases = ncases;
     c->J.assign(ncases, 0.0);
     c->has_static = c->has_buck = false;
+    c->has_adj = false;
     CHK(ensure_cg(c, std::max(ncases, c->k)));
     return MLB_OK;
 }
@@ -1435,7 +1439,7 @@ static int set_density_common(mlb_ctx* c) {
         c->has_density = false;
         return fail(c, MLB_EINVAL, "densities must be finite and lie in [0, 1]");
     }
-    c->has_static = c->has_buck = c->has_stress = false;
+    c->has_static = c->has_buck = c->has_stress = c->has_adj = false;
     c->has_density = true;
     if (!c->has_bc) return MLB_OK;   // the hierarchy is built when the mask arrives
     return build_hierarchy(c);
@@ -1465,6 +1469,7 @@ static int solve_static_common(mlb_ctx* c, double tol, int max_it, mlb_solve_inf
     c->tol_solve = tol;
     c->max_it = max_it;
     c->has_static = c->has_buck = false;
+    c->has_adj = false;
     bool x0 = false;
     if ((int64_t)c->warm_static.size() == c->n * c->ncases) {
         // initial guess scaled per column to its energy-optimal multiple
@@ -1569,6 +1574,14 @@ int mlb_coarse_modes_dev(mlb_ctx* c, int k, double* Psi, void* stream) {
     return MLB_OK;
 }
 
+int mlb_adjoints_dev(mlb_ctx* c, int k, double* Z, void* stream) {
+    if (!c || !Z || k < 1) return MLB_EINVAL;
+    if (!c->has_adj || k > c->k) return fail(c, MLB_ESTATE, "no adjoints: call mlb_sensitivities with dlam first");
+    c->st = pick(c, stream);
+    HIPC(hipMemcpyAsync(Z, c->Zadj, sizeof(double) * c->n * k, hipMemcpyDeviceToDevice, c->st));
+    return MLB_OK;
+}
+
 int mlb_set_warm_start(mlb_ctx* c, int kind, int ncols, const double* data) {
     if (!c) return MLB_EINVAL;
     if (kind == MLB_WARM_NONE) {
@@ -1625,6 +1638,7 @@ int mlb_set_state_dev(mlb_ctx* c, const double* u, double* stress_out, void* str
         HIPC(hipMemcpyAsync(stress_out, c->S, sizeof(double) * c->m * c->nv, hipMemcpyDeviceToDevice, c->st));
     c->has_stress = true;
     c->has_buck = false;
+    c->has_adj = false;
     HIPC(hipGetLastError());
     return MLB_OK;
 }
