@@ -24,11 +24,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the fine 1-column apply: rocprofv3 FETCH_SIZE x 1.99966
+# HBM bytes per launch of the fine 1-column apply: rocprofv3 FETCH_SIZE x 1.99977
 # + WRITE_SIZE x 1.0 (factors from a 256 MiB calibration copy), measured on the
-# current kernel: 17,377 KiB read counter + 19,153 KiB written
+# current kernel: 17,363 KiB read counter + 19,153 KiB written
 # (profiles/fine_apply_h8_192x64x64_hbm_counters.md).
-TRAFFIC_BYTES = (17377 * 1.99966 + 19153) * 1024
+TRAFFIC_BYTES = (17363 * 1.99977 + 19153) * 1024
 
 
 def parse():
