@@ -95,6 +95,7 @@ typedef struct {
     int cycle;            /* coarse-grid visits per level: 1 = V-cycle, 2 = W-cycle (default 1) */
     int block_cg;         /* multi-column solves: 1 = block CG (default), 2 = column-wise CG */
     int eig_sweeps;       /* multigrid sweeps per coarse-eigensolver preconditioner application (default 3) */
+    int graphs;           /* 1 = replay each multigrid cycle as a captured HIP graph (default), 2 = launch eagerly */
 } mlb_opts;
 
 /* Per-call solver report; for blocks, the worst column is reported. */
@@ -214,6 +215,16 @@ int mlb_coarse_modes_dev(mlb_ctx* ctx, int k, double* Psi, void* stream);
 /* The adjoint solutions z_i of K z_i = grad_u(phi_i^T G phi_i) (eq. AdjointSystem),
    n x k column-major, from the last mlb_sensitivities with dlam requested. */
 int mlb_adjoints_dev(mlb_ctx* ctx, int k, double* Z, void* stream);
+/* The adjoint right-hand sides b_i = grad_u(phi_i^T G phi_i) (n x k) of the
+   last mlb_sensitivities with dlam requested. */
+int mlb_adjoint_rhs_dev(mlb_ctx* ctx, int k, double* B, void* stream);
+
+/* K X = B for ncols <= 32 arbitrary right-hand sides (n x ncols, device) on the
+   current density, as one block CG (App. B, block mgPCG) from X = 0, to the
+   relative residual tol per column.  B is masked at Dirichlet DOFs; X receives
+   zeros there.  Invalidates the adjoint accessors. */
+int mlb_solve_block_dev(mlb_ctx* ctx, int ncols, const double* B, double* X, double tol, int max_it,
+                        mlb_solve_info* info, void* stream);
 
 /* One multigrid V-cycle z = M^-1 r starting at `level` (ncols columns). */
 int mlb_vcycle_dev(mlb_ctx* ctx, int level, int ncols, const double* r, double* z, void* stream);

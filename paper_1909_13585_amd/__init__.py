@@ -100,10 +100,10 @@ class Context:
         return n.value, m.value
 
     def set_opts(self, smooth_steps=0, jacobi_omega=0.0, eig_guard=0, eig_max_it=0, check_every=0, seed=0,
-                 cycle=0, block_cg=0, eig_sweeps=0):
+                 cycle=0, block_cg=0, eig_sweeps=0, graphs=0):
         """Zero (the default of every argument) keeps the current value."""
         o = B.MlbOpts(smooth_steps, jacobi_omega, eig_guard, eig_max_it, check_every, seed, cycle, block_cg,
-                      eig_sweeps)
+                      eig_sweeps, graphs)
         self._check(self.lib.mlb_set_opts(self.h, C.byref(o)))
 
     # -- problem data (host)
@@ -212,6 +212,17 @@ class Context:
     def coarse_modes_dev(self, k, Psi):
         """Copies the K^l-orthonormal coarse modes of the last buckling call into Psi (k, n_l)."""
         self._check(self.lib.mlb_coarse_modes_dev(self.h, k, _dptr(Psi), _stream()))
+
+    def adjoint_rhs_dev(self, k, B):
+        """Copies the adjoint right-hand sides of the last sensitivities call into B (k, n)."""
+        self._check(self.lib.mlb_adjoint_rhs_dev(self.h, k, _dptr(B), _stream()))
+
+    def solve_block_dev(self, B, X, tol=1e-8, max_it=1000):
+        """K X = B for the columns of B (ncols, n) as one block CG; returns the solve info."""
+        info = MlbSolveInfo()
+        self._check(self.lib.mlb_solve_block_dev(self.h, B.shape[0], _dptr(B), _dptr(X), tol, max_it, C.byref(info),
+                                                 _stream()))
+        return _info_dict(info)
 
     def adjoints_dev(self, k, Z):
         """Copies the adjoint solutions of the last sensitivities call into Z (k, n)."""

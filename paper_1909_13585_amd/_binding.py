@@ -38,7 +38,7 @@ class MlbDesc(C.Structure):
 class MlbOpts(C.Structure):
     _fields_ = [("smooth_steps", C.c_int), ("jacobi_omega", C.c_double), ("eig_guard", C.c_int),
                 ("eig_max_it", C.c_int), ("check_every", C.c_int), ("seed", C.c_uint64), ("cycle", C.c_int),
-                ("block_cg", C.c_int), ("eig_sweeps", C.c_int)]
+                ("block_cg", C.c_int), ("eig_sweeps", C.c_int), ("graphs", C.c_int)]
 
 
 class MlbSolveInfo(C.Structure):
@@ -83,6 +83,8 @@ _SIGS = {
     "mlb_vcycle_dev": (_I, [_P, _I, _I, _P, _P, _P]),
     "mlb_coarse_modes_dev": (_I, [_P, _I, _P, _P]),
     "mlb_adjoints_dev": (_I, [_P, _I, _P, _P]),
+    "mlb_adjoint_rhs_dev": (_I, [_P, _I, _P, _P]),
+    "mlb_solve_block_dev": (_I, [_P, _I, _P, _P, _D, _I, C.POINTER(MlbSolveInfo), _P]),
     # warm-start network kernels (include/mlb_nn.h)
     "mlb_nn_conv3d": (_I, [_I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P]),
     "mlb_nn_conv3d_wgrad": (_I, [_I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),

@@ -60,6 +60,14 @@ struct mlb_ctx {
     mlb_opts o{};
     int dim = 0, nn = 0, nde = 0, nv = 0, L = 1, ell = 1;
     hipStream_t own = nullptr, st = nullptr;
+    hipStream_t cap = nullptr;   // capture stream for the preconditioner graphs
+    struct Graph {
+        int j, nc;
+        const void* r;
+        void* z;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;   // captured preconditioner applications of this hierarchy
     Tables tab{};
     double *dK0 = nullptr, *dHk = nullptr, *dBc = nullptr, *dD0Bc = nullptr, *dD0 = nullptr, *dT = nullptr,
            *dMc = nullptr, *dGHc = nullptr;
@@ -175,10 +183,13 @@ int sync(mlb_ctx* c) {
     return MLB_OK;
 }
 
+void drop_graphs(mlb_ctx* c);
+
 // ---- level buffers
 
 int ensure_level_cols(mlb_ctx* c, int cols) {
     if (cols <= c->wcols) return MLB_OK;
+    drop_graphs(c);   // captured cycles point at the old buffers
     for (auto& l : c->lv) {
         const size_t s = (size_t)l.n * cols;
         CHK(dalloc(c, &l.vr, s));
@@ -197,6 +208,7 @@ int ensure_level_cols(mlb_ctx* c, int cols) {
 int ensure_cg(mlb_ctx* c, int cols) {
     CHK(ensure_level_cols(c, cols));
     if (cols <= c->cg_cap) return MLB_OK;
+    drop_graphs(c);
     const size_t s = (size_t)c->n * cols;
     CHK(dalloc(c, &c->R, s));
     CHK(dalloc(c, &c->Zb, s));
@@ -323,7 +335,7 @@ void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z) {
 }
 
 // z = M^-1 r at level j in FP64 or mixed precision (FP32 inside).
-void precondition(mlb_ctx* c, int j, int nc, const double* r, double* z) {
+void precondition_eager(mlb_ctx* c, int j, int nc, const double* r, double* z) {
     Level& l = c->lv[j - 1];
     if (c->d.precision == MLB_MIXED) {
         launch_d2f(l.n, nc, l.n, r, l.fr, c->st);
@@ -332,6 +344,45 @@ void precondition(mlb_ctx* c, int j, int nc, const double* r, double* z) {
     } else {
         vcycle<double>(c, j, nc, r, z);
     }
+}
+
+void drop_graphs(mlb_ctx* c) {
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+// z = M^-1 r.  With graphs on, each (level, columns, r, z) application is
+// captured once per hierarchy as a HIP graph (its 20-50 launches then cost
+// one) and replayed; the graphs hold kernel arguments such as the Jacobi
+// weights, so they are dropped whenever the hierarchy or the options change.
+// The cycle records kernels only (no memset or copy nodes).
+int precondition(mlb_ctx* c, int j, int nc, const double* r, double* z) {
+    if (c->o.graphs != 1) {
+        precondition_eager(c, j, nc, r, z);
+        return MLB_OK;
+    }
+    for (auto& g : c->graphs)
+        if (g.j == j && g.nc == nc && g.r == r && g.z == z) {
+            HIPC(hipGraphLaunch(g.exec, c->st));
+            return MLB_OK;
+        }
+    if (c->graphs.size() >= 32) drop_graphs(c);
+    if (!c->cap) HIPC(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipStream_t saved = c->st;
+    c->st = c->cap;
+    HIPC(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    precondition_eager(c, j, nc, r, z);
+    hipGraph_t graph = nullptr;
+    const hipError_t e1 = hipStreamEndCapture(c->cap, &graph);
+    c->st = saved;
+    HIPC(e1);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPC(e2);
+    c->graphs.push_back({j, nc, r, z, exec});
+    HIPC(hipGraphLaunch(exec, c->st));
+    return MLB_OK;
 }
 
 // ---- reductions
@@ -422,7 +473,7 @@ int pcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, 
     int it = 0;
     int status = MLB_OK;
     if (nact > 0) {
-        precondition(c, 1, nc, c->R, c->Zb);
+        CHK(precondition(c, 1, nc, c->R, c->Zb));
         dots(c, n, nc, c->R, c->Zb, rz);
         launch_copy_cols(n, nc, n, c->Zb, n, c->Pb, c->st);
         const int every = std::max(1, c->o.check_every);
@@ -453,7 +504,7 @@ int pcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, 
                 if (nact == 0) break;
             }
             if (flex) dots(c, n, nc, c->R, c->Zb, sc(c, 8));   // r_{k+1} . z_k for the flexible beta
-            precondition(c, 1, nc, c->R, c->Zb);
+            CHK(precondition(c, 1, nc, c->R, c->Zb));
             dots(c, n, nc, c->R, c->Zb, rzn);
             if (flex) launch_cg_beta_flex(nc, rzn, sc(c, 8), rz, active, beta, c->st);
             else launch_cg_beta(nc, rzn, rz, active, beta, c->st);
@@ -520,6 +571,7 @@ int estimate_omega(mlb_ctx* c, int j) {
 }
 
 int build_hierarchy(mlb_ctx* c) {
+    drop_graphs(c);
     const int dim = c->dim;
     Level& l1 = c->lv[0];
     launch_dinv_fine(dim, l1.g, c->Ek, l1.nmask, c->dK0, l1.dinv, l1.dinvf, c->st);
@@ -751,7 +803,7 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
     CHK(check(&done));
     std::vector<double> G, Tm, Al, Cm;
     if (!done) {
-        precondition(c, 1, nc, c->R, P);
+        CHK(precondition(c, 1, nc, c->R, P));
         apply_K<double>(c, 1, nc, P, Q, kModeY, nullptr, nullptr);
         for (it = 1; it <= max_it; ++it) {
             // [P^T Q | P^T R]
@@ -775,7 +827,7 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
             CHK(check(&done));
             if (done) break;
             // Z = M R; beta = -Q^T Z; P <- Z + P beta; Q = A P
-            precondition(c, 1, nc, c->R, Z);
+            CHK(precondition(c, 1, nc, c->R, Z));
             CHK(gram(c, n, sp, Q, n, nc, Z, n, Cm));
             for (auto& v : Cm) v = -v;
             CHK(upload_cm(c, c->cbuf, Cm));
@@ -923,10 +975,10 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         }
         // (eig_sweeps stationary multigrid iterations from zero: a symmetric
         // preconditioner that approximates (K^l)^-1 better than one cycle)
-        precondition(c, j, nb, c->eR, W);
+        CHK(precondition(c, j, nb, c->eR, W));
         for (int sw = 1; sw < c->o.eig_sweeps; ++sw) {   // W += B (R - K W)
             apply_K<double>(c, j, nb, W, c->eP, kModeResidual, c->eR, nullptr);
-            precondition(c, j, nb, c->eP, c->ePK);
+            CHK(precondition(c, j, nb, c->eP, c->ePK));
             launch_axpby(n * nb, 1.0, c->ePK, 1.0, W, c->st);
         }
         if (verbose) {
@@ -1174,6 +1226,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     c->o.cycle = 1;
     c->o.block_cg = 1;
     c->o.eig_sweeps = 3;
+    c->o.graphs = 1;
 
     const int dim = desc->dim;
     auto bad = [&](const std::string& m) {
@@ -1300,6 +1353,8 @@ void mlb_destroy(mlb_ctx* c) {
     dfree(c->scal); dfree(c->iscal); dfree(c->gbuf); dfree(c->cbuf); dfree(c->cbuf2);
     if (c->hpin) (void)hipHostFree(c->hpin);
     if (c->hup) (void)hipHostFree(c->hup);
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
 }
@@ -1317,6 +1372,8 @@ int mlb_set_opts(mlb_ctx* c, const mlb_opts* o) {
     if (o->cycle > 0) c->o.cycle = std::min(o->cycle, 2);
     if (o->block_cg > 0) c->o.block_cg = o->block_cg == 1 ? 1 : 0;
     if (o->eig_sweeps > 0) c->o.eig_sweeps = std::min(o->eig_sweeps, 8);
+    if (o->graphs > 0) c->o.graphs = o->graphs == 1 ? 1 : 2;
+    drop_graphs(c);
     if (o->jacobi_omega > 0 && c->has_density) {
         c->st = c->own;
         for (int j = 1; j < c->L; ++j) CHK(estimate_omega(c, j));
@@ -1574,6 +1631,33 @@ int mlb_coarse_modes_dev(mlb_ctx* c, int k, double* Psi, void* stream) {
     return MLB_OK;
 }
 
+int mlb_adjoint_rhs_dev(mlb_ctx* c, int k, double* Bout, void* stream) {
+    if (!c || !Bout || k < 1) return MLB_EINVAL;
+    if (!c->has_adj || k > c->k) return fail(c, MLB_ESTATE, "no adjoints: call mlb_sensitivities with dlam first");
+    c->st = pick(c, stream);
+    HIPC(hipMemcpyAsync(Bout, c->X2, sizeof(double) * c->n * k, hipMemcpyDeviceToDevice, c->st));
+    return MLB_OK;
+}
+
+int mlb_solve_block_dev(mlb_ctx* c, int ncols, const double* B, double* X, double tol, int max_it,
+                        mlb_solve_info* info, void* stream) {
+    if (!c || !B || !X || ncols < 1) return MLB_EINVAL;
+    if (ncols > 32) return fail(c, MLB_EINVAL, "at most 32 right-hand sides per block");
+    if (!c->has_bc || !c->has_density) return fail(c, MLB_ESTATE, "set the mask and the densities first");
+    if (!(tol > 0) || max_it < 1) return fail(c, MLB_EINVAL, "need tol > 0 and max_it >= 1");
+    c->st = pick(c, stream);
+    CHK(ensure_cg(c, ncols));
+    // the solvers keep every vector zero at Dirichlet DOFs: mask a copy of B
+    HIPC(hipMemcpyAsync(c->X1, B, sizeof(double) * c->n * ncols, hipMemcpyDeviceToDevice, c->st));
+    launch_mask_fixed(c->n, ncols, c->n, c->lv[0].nmask, c->dim, c->X1, c->st);
+    c->has_adj = false;   // X1/X2 are shared work space
+    if (c->o.block_cg || ncols == 1) CHK(ncols == 1 ? pcg(c, c->X1, X, 1, tol, max_it, false, info)
+                                                    : bpcg(c, c->X1, X, ncols, tol, max_it, false, info));
+    else CHK(pcg(c, c->X1, X, ncols, tol, max_it, false, info));
+    CHK(sync(c));
+    return MLB_OK;
+}
+
 int mlb_adjoints_dev(mlb_ctx* c, int k, double* Z, void* stream) {
     if (!c || !Z || k < 1) return MLB_EINVAL;
     if (!c->has_adj || k > c->k) return fail(c, MLB_ESTATE, "no adjoints: call mlb_sensitivities with dlam first");
@@ -1681,10 +1765,10 @@ int mlb_vcycle_dev(mlb_ctx* c, int level, int ncols, const double* r, double* z,
         // vcycle<double> at level 1 uses vt as scratch: stage through the CG buffers
         CHK(ensure_cg(c, ncols));
         launch_copy_cols(lv.n, ncols, lv.n, lv.vt, lv.n, c->R, c->st);
-        precondition(c, level, ncols, c->R, z);
+        CHK(precondition(c, level, ncols, c->R, z));
     } else {
         launch_copy_cols(lv.n, ncols, lv.n, lv.vt, lv.n, lv.vr, c->st);
-        precondition(c, level, ncols, lv.vr, z);
+        CHK(precondition(c, level, ncols, lv.vr, z));
     }
     HIPC(hipGetLastError());
     return MLB_OK;
