@@ -70,6 +70,16 @@ extern "C" {
 
 typedef struct mlb_ctx mlb_ctx;
 
+/* Result of mlb_autotune: the chosen tile parameters and the mean time (ms)
+   of a Jacobi sweep for each candidate (z chunk 4, 6, 8, 12, 16; stencil
+   columns per thread 2, 3, 4, 6, 8). */
+typedef struct {
+    int wht_zchunk;
+    int stencil_cols;
+    float wht_ms[5];
+    float stencil_ms[5];
+} mlb_tune_info;
+
 /* Problem description (copied by mlb_create). */
 typedef struct {
     int dim;            /* 2 (Q4) or 3 (H8) */
@@ -183,6 +193,16 @@ int mlb_eig_residuals(mlb_ctx* ctx, double* res_inf);
 int mlb_sensitivities(mlb_ctx* ctx, double* dJ, double* dlam, mlb_solve_info* info);
 int mlb_sensitivities_dev(mlb_ctx* ctx, double* dJ, double* dlam, mlb_solve_info* info,
                           void* stream);
+
+/* Tile parameters of the fine apply (pencil length in node planes, 1..64) and
+   of the stencil applies (columns per thread, 1..12); 0 keeps a value.  The
+   operator applies give bitwise the same results for every choice; dot
+   products fused into the fine apply group their partial sums by tile, so
+   solver iterates may differ in the last bits. */
+int mlb_set_tiles(mlb_ctx* ctx, int wht_zchunk, int stencil_cols);
+/* Times Jacobi sweeps of ncols (<= 32) columns on the current hierarchy for
+   each candidate tile and keeps the fastest (needs mask and densities). */
+int mlb_autotune(mlb_ctx* ctx, int ncols, mlb_tune_info* info, void* stream);
 
 /* Warm starts.  kind MLB_WARM_COARSE: `data` holds ncols start vectors of
  * the eigen level (n_l x ncols, column-major, host); MLB_WARM_STATIC: one

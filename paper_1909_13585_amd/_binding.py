@@ -52,6 +52,11 @@ class MlbEigInfo(C.Structure):
                 ("seconds_fine", C.c_double), ("seconds_ritz", C.c_double)]
 
 
+class MlbTuneInfo(C.Structure):
+    _fields_ = [("wht_zchunk", C.c_int), ("stencil_cols", C.c_int), ("wht_ms", C.c_float * 5),
+                ("stencil_ms", C.c_float * 5)]
+
+
 _P = C.c_void_p
 _I = C.c_int
 _D = C.c_double
@@ -84,6 +89,8 @@ _SIGS = {
     "mlb_coarse_modes_dev": (_I, [_P, _I, _P, _P]),
     "mlb_adjoints_dev": (_I, [_P, _I, _P, _P]),
     "mlb_adjoint_rhs_dev": (_I, [_P, _I, _P, _P]),
+    "mlb_set_tiles": (_I, [_P, _I, _I]),
+    "mlb_autotune": (_I, [_P, _I, C.POINTER(MlbTuneInfo), _P]),
     "mlb_solve_block_dev": (_I, [_P, _I, _P, _P, _D, _I, C.POINTER(MlbSolveInfo), _P]),
     # warm-start network kernels (include/mlb_nn.h)
     "mlb_nn_conv3d": (_I, [_I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P]),

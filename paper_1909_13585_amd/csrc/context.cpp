@@ -68,6 +68,10 @@ struct mlb_ctx {
         hipGraphExec_t exec;
     };
     std::vector<Graph> graphs;   // captured preconditioner applications of this hierarchy
+    // tile parameters (mlb_autotune / mlb_set_tiles); operator results do not
+    // depend on them (fused dot products group their partials by tile)
+    int wht_zchunk = 8;          // fine apply: pencil length in node planes
+    int nb_cbmax = 6;            // stencil apply: columns per thread
     Tables tab{};
     double *dK0 = nullptr, *dHk = nullptr, *dBc = nullptr, *dD0Bc = nullptr, *dD0 = nullptr, *dT = nullptr,
            *dMc = nullptr, *dGHc = nullptr;
@@ -258,7 +262,7 @@ const float* wht_of<float>(mlb_ctx* c) { return c->whtf; }
 
 // partial-sum blocks written by the level-1 apply with a fused dot product
 int64_t fine_apply_blocks(mlb_ctx* c) {
-    return c->tab.wht_ok ? apply_wht_blocks(c->dim, c->lv[0].g) : apply_fine_blocks(c->lv[0].g);
+    return c->tab.wht_ok ? apply_wht_blocks(c->dim, c->lv[0].g, c->wht_zchunk) : apply_fine_blocks(c->lv[0].g);
 }
 
 // y = A_j x (mode Y), y = r - A_j x (residual), y = x + omega D^-1 (r - A_j x) (Jacobi).
@@ -273,18 +277,20 @@ void apply_K(mlb_ctx* c, int j, int nc, const T* x, T* y, int mode, const T* r, 
     Level& l = c->lv[j - 1];
     if (j == 1 && c->tab.wht_ok)
         launch_apply_wht<T>(c->dim, l.g, E_of<T>(c), l.nmask, wht_of<T>(c), nc, l.n, x, y, mode, r, dinv_of<T>(l),
-                            (T)l.omega, dot_part, clean, c->st);
+                            (T)l.omega, dot_part, clean, c->wht_zchunk, c->st);
     else if (j == 1)
         launch_apply_fine<T>(c->dim, l.g, E_of<T>(c), l.nmask, K0_of<T>(c), nc, l.n, x, y, mode, r,
                              dinv_of<T>(l), (T)l.omega, dot_part, c->st);
     else
-        launch_apply_nb<T>(c->dim, l.g, A_of<T>(l), false, nc, l.n, x, y, mode, r, dinv_of<T>(l), (T)l.omega, c->st);
+        launch_apply_nb<T>(c->dim, l.g, A_of<T>(l), false, nc, l.n, x, y, mode, r, dinv_of<T>(l), (T)l.omega,
+                           c->nb_cbmax, c->st);
 }
 
 void apply_G(mlb_ctx* c, int j, int nc, const double* x, double* y) {
     Level& l = c->lv[j - 1];
     if (j == 1) launch_apply_G_fine(c->dim, l.g, c->S, l.nmask, c->dHk, nc, l.n, x, y, c->st);
-    else launch_apply_nb<double>(c->dim, l.g, l.Gs, true, nc, l.n, x, y, kModeY, nullptr, nullptr, 0.0, c->st);
+    else launch_apply_nb<double>(c->dim, l.g, l.Gs, true, nc, l.n, x, y, kModeY, nullptr, nullptr, 0.0, c->nb_cbmax,
+                                 c->st);
 }
 
 template <typename T>
@@ -1208,6 +1214,79 @@ hipStream_t pick(mlb_ctx* c, void* stream) { return stream ? (hipStream_t)stream
 
 }  // namespace
 
+namespace {
+// Mean time (ms) of `reps` calls of f after one untimed call, HIP events on c->st.
+template <typename F>
+int time_ms(mlb_ctx* c, int reps, F f, float* ms) {
+    hipEvent_t a, b;
+    HIPC(hipEventCreate(&a));
+    HIPC(hipEventCreate(&b));
+    f();
+    HIPC(hipEventRecord(a, c->st));
+    for (int i = 0; i < reps; ++i) f();
+    HIPC(hipEventRecord(b, c->st));
+    HIPC(hipEventSynchronize(b));
+    float t = 0.f;
+    HIPC(hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = t / (float)reps;
+    return MLB_OK;
+}
+
+// Tunes the pencil length of the fine apply and the column chunk of the
+// stencil applies for blocks of ncols columns in the precision of the
+// multigrid cycle, on Jacobi sweeps (the dominant launches), and keeps the
+// fastest of each.
+template <typename T>
+int autotune_t(mlb_ctx* c, int ncols, mlb_tune_info* info) {
+    Level& l1 = c->lv[0];
+    T* x = lbuf<T>(l1, 1);
+    T* y = lbuf<T>(l1, 2);
+    T* r = lbuf<T>(l1, 0);
+    launch_random_fill(l1.n, 1, l1.n, 77, l1.nmask, c->dim, l1.vt, c->st);
+    if (sizeof(T) == 4) launch_d2f(l1.n, 1, l1.n, l1.vt, (float*)(void*)l1.ft, c->st);
+    const T* src = sizeof(T) == 4 ? (const T*)(const void*)l1.ft : (const T*)(const void*)l1.vt;
+    for (int q = 0; q < ncols; ++q) {
+        HIPC(hipMemcpyAsync(x + (int64_t)q * l1.n, src, sizeof(T) * l1.n, hipMemcpyDeviceToDevice, c->st));
+        HIPC(hipMemcpyAsync(r + (int64_t)q * l1.n, src, sizeof(T) * l1.n, hipMemcpyDeviceToDevice, c->st));
+    }
+    const int zc[] = {4, 6, 8, 12, 16};
+    float best = 1e30f;
+    int bz = c->wht_zchunk;
+    for (int i = 0; i < 5; ++i) {
+        c->wht_zchunk = zc[i];
+        float ms = 0.f;
+        CHK(time_ms(c, 5, [&] { apply_K<T>(c, 1, ncols, x, y, kModeJacobi, r, nullptr); }, &ms));
+        if (info) info->wht_ms[i] = ms;
+        if (ms < best) best = ms, bz = zc[i];
+    }
+    c->wht_zchunk = bz;
+    if (c->L > 1) {
+        Level& l2 = c->lv[1];
+        T* x2 = lbuf<T>(l2, 1);
+        T* y2 = lbuf<T>(l2, 2);
+        T* r2 = lbuf<T>(l2, 0);
+        launch_restrict_nb<T>(c->dim, l1.g, l2.g, l1.nmask, l2.nmask, ncols, l1.n, l2.n, x, x2, c->st);
+        launch_restrict_nb<T>(c->dim, l1.g, l2.g, l1.nmask, l2.nmask, ncols, l1.n, l2.n, r, r2, c->st);
+        const int cb[] = {2, 3, 4, 6, 8};
+        best = 1e30f;
+        int bc = c->nb_cbmax;
+        for (int i = 0; i < 5; ++i) {
+            c->nb_cbmax = cb[i];
+            float ms = 0.f;
+            CHK(time_ms(c, 5, [&] { apply_K<T>(c, 2, ncols, x2, y2, kModeJacobi, r2, nullptr); }, &ms));
+            if (info) info->stencil_ms[i] = ms;
+            if (ms < best) best = ms, bc = cb[i];
+        }
+        c->nb_cbmax = bc;
+    }
+    CHK(sync(c));
+    return MLB_OK;
+}
+}  // namespace
+
+
 // ============================ C ABI ======================================
 
 extern "C" {
@@ -1628,6 +1707,33 @@ int mlb_coarse_modes_dev(mlb_ctx* c, int k, double* Psi, void* stream) {
     c->st = pick(c, stream);
     const int64_t nl = c->lv[c->ell - 1].n;
     HIPC(hipMemcpyAsync(Psi, c->eS, sizeof(double) * nl * k, hipMemcpyDeviceToDevice, c->st));
+    return MLB_OK;
+}
+
+int mlb_set_tiles(mlb_ctx* c, int wht_zchunk, int stencil_cols) {
+    if (!c) return MLB_EINVAL;
+    if (wht_zchunk < 0 || wht_zchunk > 64 || stencil_cols < 0 || stencil_cols > 12)
+        return fail(c, MLB_EINVAL, "tile parameters out of range (z chunk 1..64, stencil columns 1..12)");
+    if (wht_zchunk > 0) c->wht_zchunk = wht_zchunk;
+    if (stencil_cols > 0) c->nb_cbmax = stencil_cols;
+    drop_graphs(c);
+    return MLB_OK;
+}
+
+int mlb_autotune(mlb_ctx* c, int ncols, mlb_tune_info* info, void* stream) {
+    if (!c || ncols < 1 || ncols > 32) return MLB_EINVAL;
+    if (!c->has_bc || !c->has_density) return fail(c, MLB_ESTATE, "set the mask and the densities first");
+    c->st = pick(c, stream);
+    CHK(ensure_level_cols(c, ncols));
+    drop_graphs(c);
+    if (info) *info = mlb_tune_info{};
+    if (c->d.precision == MLB_MIXED) CHK(autotune_t<float>(c, ncols, info));
+    else CHK(autotune_t<double>(c, ncols, info));
+    if (info) {
+        info->wht_zchunk = c->wht_zchunk;
+        info->stencil_cols = c->nb_cbmax;
+    }
+    drop_graphs(c);
     return MLB_OK;
 }
 

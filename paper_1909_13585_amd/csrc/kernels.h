@@ -24,7 +24,7 @@ void launch_assemble_nb_diag(int dim, const Geo& g, const double* Ge, const uint
                              hipStream_t st);
 template <typename T>
 void launch_apply_nb(int dim, const Geo& g, const T* A, bool diag, int ncols, int64_t ld, const T* x, T* y, int mode,
-                     const T* r, const T* dinv, T omega, hipStream_t st);
+                     const T* r, const T* dinv, T omega, int cbmax, hipStream_t st);
 template <typename T>
 void launch_prolong_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
                        int64_t ldf, int64_t ldc, const T* xc, T* yf, bool add, hipStream_t st);
@@ -33,11 +33,11 @@ void launch_restrict_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf
                         int64_t ldf, int64_t ldc, const T* xf, T* yc, hipStream_t st);
 
 // ---- element-centric Walsh-Hadamard apply (kernels_wht.hip)
-int64_t apply_wht_blocks(int dim, const Geo& g);
+int64_t apply_wht_blocks(int dim, const Geo& g, int zchunk);
 template <typename T>
 void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* blocks, int ncols,
                       int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega, double* dot_part,
-                      bool clean, hipStream_t st);
+                      bool clean, int zchunk, hipStream_t st);
 
 // ---- setup (kernels_setup.hip)
 void launch_material(int64_t m, const double* x, double E1, double E0, double p, double* Ek, float* Ekf,

@@ -336,11 +336,12 @@ int64_t stencil_entries(int dim, const Geo& g, bool diag) {
 
 template <typename T>
 void launch_apply_nb(int dim, const Geo& g, const T* A, bool diag, int ncols, int64_t ld, const T* x, T* y, int mode,
-                     const T* r, const T* dinv, T omega, hipStream_t st) {
+                     const T* r, const T* dinv, T omega, int cbmax, hipStream_t st) {
     const int64_t nbn = (g.nodes + kNbThreads - 1) / kNbThreads;
-    // columns per thread: at most 6, split evenly (each chunk re-reads the
-    // stencil; wider chunks lose more in parallelism than they save)
-    const int per = (ncols + 5) / 6;
+    // columns per thread: at most cbmax (tunable, default 6), split evenly;
+    // each chunk re-reads the stencil, wider chunks run fewer threads
+    const int cap = cbmax >= 1 && cbmax <= 12 ? cbmax : 6;
+    const int per = (ncols + cap - 1) / cap;
     const int want = (ncols + per - 1) / per;
     const int cb = want <= 1 ? 1 : want <= 2 ? 2 : want <= 3 ? 3 : want <= 4 ? 4 : want <= 6 ? 6 : want <= 8 ? 8 : 12;
     const int nchunks = (ncols + cb - 1) / cb;
@@ -404,9 +405,9 @@ void launch_restrict_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf
 }
 
 template void launch_apply_nb<double>(int, const Geo&, const double*, bool, int, int64_t, const double*, double*,
-                                      int, const double*, const double*, double, hipStream_t);
+                                      int, const double*, const double*, double, int, hipStream_t);
 template void launch_apply_nb<float>(int, const Geo&, const float*, bool, int, int64_t, const float*, float*, int,
-                                     const float*, const float*, float, hipStream_t);
+                                     const float*, const float*, float, int, hipStream_t);
 template void launch_prolong_nb<double>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,
                                         int64_t, const double*, double*, bool, hipStream_t);
 template void launch_prolong_nb<float>(int, const Geo&, const Geo&, const uint8_t*, const uint8_t*, int, int64_t,

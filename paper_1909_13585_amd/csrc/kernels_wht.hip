@@ -399,15 +399,15 @@ __global__ __launch_bounds__(kTX2* kTW2) void k_apply_wht2(Geo g, int ky_chunk, 
 // ---------------------------------------------------------------------------
 // launch geometry
 
-static void wht_geometry(int dim, const Geo& g, dim3& grid, dim3& block, int& chunk, int& ntx, int& nty) {
+// zchunk: target pencil length in node planes (3D; tunable, results do not
+// depend on it: every owned node is summed in the same order)
+static void wht_geometry(int dim, const Geo& g, int zchunk, dim3& grid, dim3& block, int& chunk, int& ntx, int& nty) {
     nty = 1;
     if (dim == 3) {
         const int tiles_x = (g.nnx + kWT - 2) / (kWT - 1);
         const int tiles_y = (g.nny + kWT - 2) / (kWT - 1);
-#ifndef MLB_WHT3_CHUNK
-#define MLB_WHT3_CHUNK 8
-#endif
-        int nch = (g.nnz + MLB_WHT3_CHUNK - 1) / MLB_WHT3_CHUNK;
+        const int zc = zchunk > 0 ? zchunk : 8;
+        int nch = (g.nnz + zc - 1) / zc;
         chunk = (g.nnz + nch - 1) / nch;
         nch = (g.nnz + chunk - 1) / chunk;
         const int64_t tiles = (int64_t)tiles_x * tiles_y * nch;
@@ -428,22 +428,22 @@ static void wht_geometry(int dim, const Geo& g, dim3& grid, dim3& block, int& ch
     }
 }
 
-int64_t apply_wht_blocks(int dim, const Geo& g) {
+int64_t apply_wht_blocks(int dim, const Geo& g, int zchunk) {
     dim3 gr, b;
     int ch, ntx, nty;
-    wht_geometry(dim, g, gr, b, ch, ntx, nty);
+    wht_geometry(dim, g, zchunk, gr, b, ch, ntx, nty);
     return (int64_t)gr.x * gr.y * gr.z;
 }
 
 template <typename T>
 void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* blocks, int ncols,
                       int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega, double* dot_part,
-                      bool clean, hipStream_t st) {
+                      bool clean, int zchunk, hipStream_t st) {
     WhtBlocks<T> B;
     for (int i = 0; i < 9; ++i) B.v[i] = blocks[i];
     dim3 gr, b;
     int ch, ntx, nty;
-    wht_geometry(dim, g, gr, b, ch, ntx, nty);
+    wht_geometry(dim, g, zchunk, gr, b, ch, ntx, nty);
 #define MLB_L3C(M, D, C)                                                                                         \
     hipLaunchKernelGGL((k_apply_wht3<T, M, D, C>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B, ncols, ld, x, y, r, \
                        dinv, omega, dot_part)
@@ -473,9 +473,9 @@ void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, c
 
 template void launch_apply_wht<double>(int, const Geo&, const double*, const uint8_t*, const double*, int, int64_t,
                                        const double*, double*, int, const double*, const double*, double, double*,
-                                       bool, hipStream_t);
+                                       bool, int, hipStream_t);
 template void launch_apply_wht<float>(int, const Geo&, const float*, const uint8_t*, const float*, int, int64_t,
                                       const float*, float*, int, const float*, const float*, float, double*, bool,
-                                      hipStream_t);
+                                      int, hipStream_t);
 
 }  // namespace mlb
