@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="skip timing the plain FP64 path next to the mixed one")
     ap.add_argument("--tol-eig", type=float, default=1e-8)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile parameters")
     ap.add_argument("--learned", default=os.path.join(ROOT, "paper_1909_13585_amd", "data", "warmstart_unet.npz"),
                     help="trained warm-start network; the learned leg is timed when the file exists")
     ap.add_argument("--nel", type=str, default="192,64,64")
@@ -96,6 +97,9 @@ def run_path(args, precision, p, x_dev, steps, warmup, label, net=None):
     Phi = torch.empty((k, n), dtype=torch.float64, device="cuda")
     dJ = torch.empty((ctx.ncases, m), dtype=torch.float64, device="cuda")
     dlam = torch.empty((k, m), dtype=torch.float64, device="cuda")
+    ctx.set_density_dev(x_dev)
+    ctx.tune = ctx.autotune(k) if not args.no_autotune else None   # untimed, once per context
+    print(f"# {label} tiles {ctx.tune}", file=sys.stderr, flush=True)
 
     def step():
         if net is not None:
@@ -250,6 +254,7 @@ def main():
                                f"Gaussian-filtered density vf 0.3 (seed 3), {args.levels}-level MG, eigen level "
                                f"{args.eig_level}, {k} modes, solves to 1e-8, coarse eigen to {args.tol_eig:g}",
                    "precision": args.precision},
+        "tiles": {"wht_zchunk": ctx.tune["wht_zchunk"], "stencil_cols": ctx.tune["stencil_cols"]} if ctx.tune else None,
         "mgpcg_gdof_per_s": gdofs,
         "static_iterations": si["iterations"],
         "coarse_iterations": ei["coarse_iterations"],
