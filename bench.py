@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--eig-level", type=int, default=3)
     ap.add_argument("--modes", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-instances", action="store_true",
+                    help="skip the 32 independent 2D instances (batched vs one context at a time)")
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the dominant-kernel timing and a copy of known size (for counter runs)")
@@ -128,6 +130,81 @@ def run_path(args, precision, p, x_dev, steps, warmup, label, net=None):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / max(steps, 1)
     return ctx, sec, out
+
+
+def batched_instances(reps=3):
+    """The 32 independent Q4 instances (64x32 ... 512x128, mixed precision,
+    1e-8): static solve + compliance gradient of all of them as one batch
+    (one launch per solver step for all instances), against the same analyses
+    run one context at a time.  Both start from densities on the device."""
+    import numpy as np
+    import torch
+    import paper_1909_13585_amd as mlb
+    from paper_1909_13585_amd import batch as mlb_batch
+    import workloads as W
+    insts = W.small_instances_2d()
+    b = mlb_batch.Batch([q["nel"] for q in insts], precision=mlb.MLB_MIXED)
+    fixed = torch.from_numpy(b.concat([q["fixed"] for q in insts], np.uint8)).cuda()
+    F = torch.from_numpy(b.concat([q["F"][:, 0] for q in insts], np.float64)).cuda()
+    x = torch.from_numpy(b.concat([q["x"] for q in insts], np.float64)).cuda()
+    U = torch.empty(b.n, dtype=torch.float64, device="cuda")
+    dJ = torch.empty(b.m, dtype=torch.float64, device="cuda")
+
+    def batched(opts):
+        b.set_opts(**opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.set_problem_dev(fixed, F, x)
+        J, its, info = b.solve_dev(U, tol=1e-8, max_it=3000)
+        b.compliance_sens_dev(dJ)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, J, its, info
+
+    variants = {}
+    for name, opts in (("queue+graph", dict(queue=1, graphs=1)), ("queue", dict(queue=1, graphs=0)),
+                       ("per-item+graph", dict(queue=0, graphs=1)), ("per-item", dict(queue=0, graphs=0))):
+        batched(opts)   # warm-up (captures the graph)
+        ts = [batched(opts) for _ in range(reps)]
+        t = min(ts, key=lambda r: r[0])
+        variants[name] = {"s": t[0], "setup_s": t[3]["setup_s"], "solve_s": t[3]["solve_s"],
+                          "batch_iterations": t[3]["batch_iterations"]}
+        print(f"# instances {name}: {t[0]:.4f} s (setup {t[3]['setup_s']:.4f}, solve {t[3]['solve_s']:.4f}, "
+              f"{t[3]['batch_iterations']} batched iterations)", file=sys.stderr, flush=True)
+    _, J, its, info = batched(dict(queue=1, graphs=1))
+    levels = [int(v) for v in b.levels]
+    b.close()
+    ctxs = []
+    for q, L in zip(insts, levels):
+        c = mlb.Context(q["nel"], mg_levels=L, eig_level=1, precision=mlb.MLB_MIXED)
+        c.set_bc(q["fixed"])
+        c.set_loads(q["F"])
+        ctxs.append((c, torch.from_numpy(q["x"]).cuda(), torch.empty((1, c.n), dtype=torch.float64, device="cuda"),
+                     torch.empty((1, c.m), dtype=torch.float64, device="cuda")))
+
+    def sequential():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Js = []
+        for c, xd, Ud, dJd in ctxs:
+            c.set_density_dev(xd)
+            Jc, _ = c.solve_static_dev(Ud, tol=1e-8, max_it=3000)
+            c.sensitivities_dev(dJd, None)
+            Js.append(Jc[0])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, Js
+
+    sequential()
+    tseq, Js = min((sequential() for _ in range(reps)), key=lambda r: r[0])
+    for c, *_ in ctxs:
+        c.close()
+    best_name = min(variants, key=lambda k: variants[k]["s"])
+    best = variants[best_name]["s"]
+    return {"instances": len(insts), "dofs": int(sum(int(np.prod([v + 1 for v in q["nel"]])) * 2 for q in insts)),
+            "levels": levels, "precision": "mixed", "tol": 1e-8,
+            "s_batched": best, "batched_variant": best_name, "variants": variants, "s_one_context_at_a_time": tseq, "speedup": tseq / best,
+            "max_iterations": int(info["max_iterations"]), "total_iterations": int(info["total_iterations"]),
+            "worst_true_rel_res": info["worst_true_rel_res"],
+            "max_rel_J_diff_vs_contexts": float(np.max(np.abs(np.asarray(Js) / J - 1)))}
 
 
 def apply_roofline(ctx, n, m, reps, ncols=1):
@@ -227,6 +304,8 @@ def main():
                 "adjoint_iterations": out64[4]["iterations"],
                 "max_rel_lambda_diff_vs_mixed": float(np.max(np.abs(np.asarray(out64[2]) / np.asarray(lam) - 1)))}
 
+    inst = None if args.no_instances else batched_instances()
+
     cpu = None
     if not args.no_cpu_baseline:
         t_cpu, n_sample = cpu_baseline(args)
@@ -265,6 +344,7 @@ def main():
                     "static": si["seconds"], "adjoint": ai["seconds"]},
         "fp64_reference": fp64,
         "learned_warm_start": learned,
+        "batched_instances": inst,
         "roofline": {"bound": "hbm", "kernel": "k_apply_wht3<double> (fine H8 K apply, 1 column)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES, "apply_ms": apply_ms,

@@ -139,7 +139,7 @@ int mlb_set_opts(mlb_ctx* ctx, const mlb_opts* opts);
 /* Sizes: DOFs and elements of level `level` (1 = fine). */
 int mlb_level_size(const mlb_ctx* ctx, int level, int64_t* n_dofs, int64_t* n_elems);
 
-/* ---- problem data (Alg. 1 line 1; Sec. 2) ------------------------------ */
+/* ---- problem data (Alg. 1, reference load; Sec. 2) ------------------------------ */
 
 /* Dirichlet mask, one byte per DOF (nonzero = fixed).  The fixed set must be
  * nested: every fixed fine DOF may interpolate only from fixed coarse DOFs
@@ -156,7 +156,7 @@ int mlb_set_density_dev(mlb_ctx* ctx, const double* x, void* stream);
 
 /* ---- analysis -------------------------------------------------------- */
 
-/* LA (Alg. 1 line 2): U = K^-1 F for every load case by multigrid-
+/* LA (Alg. 1, static solve): U = K^-1 F for every load case by multigrid-
  * preconditioned CG to ||F - K U|| <= tol ||F|| per column; J = f^T u.
  * U (n x ncases) and J (ncases) may be NULL.  ENOTCONV after max_it. */
 int mlb_solve_static(mlb_ctx* ctx, double tol, int max_it, double* U, double* J,

@@ -11,7 +11,7 @@ problems with buckling constraints at the cost of linear analyses"):
   * ``fem``        element matrices and assembled sparse K[x], G[x, u]
                    (Sec. 2, eq. interpolationSIMP2-SIMP; element choice Q4/H8)
   * ``levels``     nested grids, interpolation/restriction and Galerkin
-                   coarse operators (Sec. 2.1 step 1; Alg. 2 lines 1 and 5)
+                   coarse operators (Sec. 2.1 step 1; Alg. 2, hierarchy and Galerkin steps)
   * ``lba``        linear analysis, coarse eigenproblem, prolongation, fine
                    block solve, Rayleigh-Ritz (Alg. 1; Sec. 2.1 steps 1-4)
   * ``sens``       compliance and buckling-factor sensitivities with the

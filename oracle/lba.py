@@ -14,7 +14,7 @@ Readings:
     Rayleigh-Ritz values of span(Phi~) (Alg. 2 calls it a Ritz projection):
     A = Phi~^T K Phi~, B = -Phi~^T G Phi~, B y = mu A y, lambda~ = 1/mu.
   * The main text (no intermediate-level smoothing) is followed, not the
-    Kaczmarz smoothing of Alg. 2 lines 11-13.
+    Kaczmarz smoothing of Alg. 2.
   * Modes are K-normalised (phi_i^T K phi_j = delta_ij, Sec. 2) and signed so
     that the entry of largest magnitude is positive (ties: lowest index).
   * Loads: the reference load is one column of F; Dirichlet rows of F are
@@ -60,7 +60,7 @@ class FreeSolver:
 
 
 def static_solve(K, F, fixed, solver=None):
-    """Alg. 1 line 2 / Alg. 2 line 3: u = K^-1 f for every column of F;
+    """Alg. 1 / Alg. 2, linear analysis: u = K^-1 f for every column of F;
     compliance J = f^T u (Sec. 3, problem P1 objective)."""
     solver = solver or FreeSolver(K, fixed)
     F = np.asarray(F, dtype=np.float64)
@@ -149,7 +149,7 @@ def operators(nel, x, u, fixed, mat):
 
 
 def exact_buckling(K, G, fixed, q, dense_limit=6000):
-    """Alg. 1 line 4 on the fine grid (l = 1): exact lowest q positive pairs."""
+    """Alg. 1 eigenproblem on the fine grid (l = 1): exact lowest q positive pairs."""
     free = _free(fixed)
     Kff = K[free][:, free]
     Gff = G[free][:, free]

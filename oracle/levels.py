@@ -1,7 +1,7 @@
 """Nested grids, transfer operators and Galerkin coarse operators (oracle).
 
 Follows Sec. 2.1 step 1 (coarse operators by Galerkin projection of the fine
-ones) and Alg. 2 lines 1, 5 and 9 (nested discretizations Omega_1 > ... >
+ones) and Alg. 2 (nested discretizations Omega_1 > ... >
 Omega_l, restriction of K and G, interpolation of modes).
 
 Readings:
@@ -98,7 +98,7 @@ def hierarchy(nel, fixed, levels):
 
 
 def composite_prolongation(Ps, ell):
-    """P_{1<-ell} = P_hat_1 P_hat_2 ... P_hat_{ell-1} (Alg. 2 line 9 repeated)."""
+    """P_{1<-ell} = P_hat_1 P_hat_2 ... P_hat_{ell-1} (the level-by-level prolongation of Alg. 2, repeated)."""
     n = Ps[0].shape[0] if Ps else None
     P = sp.eye(n).tocsr() if ell > 1 else None
     for j in range(ell - 1):

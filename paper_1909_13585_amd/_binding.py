@@ -57,6 +57,23 @@ class MlbTuneInfo(C.Structure):
                 ("stencil_ms", C.c_float * 5)]
 
 
+class MlbBatchDesc(C.Structure):
+    _fields_ = [("ninst", C.c_int), ("nel", C.c_int * 128), ("E1", C.c_double), ("E0", C.c_double),
+                ("nu", C.c_double), ("penal", C.c_double), ("precision", C.c_int), ("device", C.c_int),
+                ("max_coarse_dofs", C.c_int)]
+
+
+class MlbBatchOpts(C.Structure):
+    _fields_ = [("smooth_steps", C.c_int), ("jacobi_omega", C.c_double), ("queue", C.c_int), ("graphs", C.c_int),
+                ("check_every", C.c_int)]
+
+
+class MlbBatchInfo(C.Structure):
+    _fields_ = [("max_iterations", C.c_int), ("total_iterations", C.c_int), ("batch_iterations", C.c_int),
+                ("converged", C.c_int), ("worst_true_rel_res", C.c_double), ("setup_s", C.c_double),
+                ("solve_s", C.c_double)]
+
+
 _P = C.c_void_p
 _I = C.c_int
 _D = C.c_double
@@ -107,6 +124,16 @@ _SIGS = {
     "mlb_nn_mse": (_I, [C.c_int64, _P, _P, _P, C.c_float, _P, _P, _P, _P]),
     "mlb_nn_adam": (_I, [C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _I, _P, _P, _P, _P, _P, _P]),
     "mlb_nn_to_bf16": (_I, [C.c_int64, _P, _P, _P]),
+    # batched independent 2D instances (include/mlb_batch.h)
+    "mlb_batch_create": (_I, [C.POINTER(MlbBatchDesc), C.POINTER(_P)]),
+    "mlb_batch_destroy": (None, [_P]),
+    "mlb_batch_last_error": (C.c_char_p, [_P]),
+    "mlb_batch_set_opts": (_I, [_P, C.POINTER(MlbBatchOpts)]),
+    "mlb_batch_get_opts": (_I, [_P, C.POINTER(MlbBatchOpts)]),
+    "mlb_batch_layout": (_I, [_P, _P, _P, _P]),
+    "mlb_batch_set_problem_dev": (_I, [_P, _P, _P, _P, _P]),
+    "mlb_batch_solve_dev": (_I, [_P, _D, _I, _P, _P, _P, C.POINTER(MlbBatchInfo), _P]),
+    "mlb_batch_compliance_sens_dev": (_I, [_P, _P, _P]),
 }
 
 _lib = None

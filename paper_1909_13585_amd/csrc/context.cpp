@@ -3,12 +3,12 @@
 //
 // The analysis follows the paper (Alg. 1 and Sec. 2.1):
 //   LA       K u = f by CG preconditioned with a geometric-multigrid V-cycle
-//            on the nested grids (Alg. 2 line 3, "mgPCG");
-//   step 1   Galerkin K^l = P^T K P, G^l = P^T G P (Alg. 2 line 5) and the
+//            on the nested grids (Alg. 2, "mgPCG");
+//   step 1   Galerkin K^l = P^T K P, G^l = P^T G P (Alg. 2) and the
 //            lowest k positive pairs of (K^l + lambda G^l) psi = 0;
 //   step 2   Psi = P_{1<-l} Psi^l;
-//   step 3   K Phi~ = G Psi as one multi-column PCG (Alg. 2 line 16);
-//   step 4   Rayleigh-Ritz on span(Phi~) (Alg. 2 line 17).
+//   step 3   K Phi~ = G Psi as one multi-column PCG (Alg. 2);
+//   step 4   Rayleigh-Ritz on span(Phi~) (Alg. 2).
 // The coarse eigensolver is LOBPCG for the largest mu = 1/lambda of
 // (-G^l) psi = mu K^l psi, preconditioned by the V-cycle of the levels below
 // l.  (The paper uses Krylov-Schur; that choice is prior art here.)

@@ -105,7 +105,8 @@ def test_struct_fields_match_header():
     B = _binding()
     structs = _declared_structs()
     pairs = {"mlb_desc": B.MlbDesc, "mlb_opts": B.MlbOpts, "mlb_solve_info": B.MlbSolveInfo,
-             "mlb_eig_info": B.MlbEigInfo, "mlb_tune_info": B.MlbTuneInfo}
+             "mlb_eig_info": B.MlbEigInfo, "mlb_tune_info": B.MlbTuneInfo, "mlb_batch_desc": B.MlbBatchDesc,
+             "mlb_batch_opts": B.MlbBatchOpts, "mlb_batch_info": B.MlbBatchInfo}
     assert set(pairs) <= set(structs)
     for cname, py in pairs.items():
         assert [f for f, _ in py._fields_] == structs[cname], cname
@@ -115,8 +116,9 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     """sizeof/offsetof from gcc on the header equal the ctypes layout."""
     B = _binding()
     pairs = {"mlb_desc": B.MlbDesc, "mlb_opts": B.MlbOpts, "mlb_solve_info": B.MlbSolveInfo,
-             "mlb_eig_info": B.MlbEigInfo, "mlb_tune_info": B.MlbTuneInfo}
-    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+             "mlb_eig_info": B.MlbEigInfo, "mlb_tune_info": B.MlbTuneInfo, "mlb_batch_desc": B.MlbBatchDesc,
+             "mlb_batch_opts": B.MlbBatchOpts, "mlb_batch_info": B.MlbBatchInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>'] + [f'#include "{h}"' for h in HEADERS] + ["int main(void) {"]
     for cname, py in pairs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:

@@ -1,0 +1,205 @@
+"""Batched independent 2D instances (one launch per solver step for all of them).
+
+Every instance's result is checked against the oracle's own solve of that
+instance alone (sparse direct K_ff u = f, its compliance, the closed-form
+compliance gradient): the batch must reach the same answers as separate
+analyses.  Also: the work-queue and one-block-per-item launch modes, and
+graph replay against eager launches, give bit-identical results; a zero load
+gives u = 0 after zero iterations; bad densities are rejected.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fem, lba, sens
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return torch
+
+
+def _small_instances():
+    out = []
+    for k, nel in enumerate([(16, 8), (64, 32), (48, 16), (32, 32), (96, 8)]):
+        x = W.random_small(2, nel, 700 + k, lo=0.1, hi=1.0)
+        out.append(dict(nel=nel, x=x, fixed=W.clamp_mask(nel), F=W.axial_load(nel)[:, None]))
+    return out
+
+
+def _step(msg):
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def _run(torch, mlb_batch, insts, precision, tol=1e-10, max_it=2000, **opts):
+    _step(f"batch of {len(insts)}: create (precision {precision}, opts {opts})")
+    b = mlb_batch.Batch([p["nel"] for p in insts], precision=precision)
+    if opts:
+        b.set_opts(**opts)
+    fixed = torch.from_numpy(b.concat([p["fixed"] for p in insts], np.uint8)).cuda()
+    F = torch.from_numpy(b.concat([p["F"][:, 0] for p in insts], np.float64)).cuda()
+    x = torch.from_numpy(b.concat([p["x"] for p in insts], np.float64)).cuda()
+    _step("set problem")
+    b.set_problem_dev(fixed, F, x)
+    U = torch.empty(b.n, dtype=torch.float64, device="cuda")
+    _step(f"solve (levels {list(b.levels)})")
+    J, its, info = b.solve_dev(U, tol=tol, max_it=max_it)
+    _step(f"sensitivities (iterations {list(its)})")
+    dJ = torch.empty(b.m, dtype=torch.float64, device="cuda")
+    b.compliance_sens_dev(dJ)
+    torch.cuda.synchronize()
+    _step("done")
+    out = dict(U=b.split_dofs(U.cpu().numpy()), dJ=b.split_elems(dJ.cpu().numpy()), J=J, its=its, info=info,
+               levels=b.levels.copy())
+    b.close()
+    return out
+
+
+def _check_against_oracle(insts, r, tol, e_tol, verbose=False):
+    """Per instance, against the oracle's own direct solve of that instance:
+    true residual within tol or the instance's FP64 floor; relative error in
+    the energy norm (well posed even for nearly singular designs, where the
+    max-norm error of u reflects the conditioning, not the solver); the
+    compliance; the gradient against the closed form with the batch's u
+    (per-element rounding bound) and with the oracle's u (1e-5 of the largest
+    entry)."""
+    mat = fem.Material()
+    Ka = np.abs(fem.element_stiffness(2, mat.nu))
+    rows, failures = [], []
+    for i, p in enumerate(insts):
+        nel, x, f = p["nel"], p["x"], p["F"][:, 0]
+        free = p["fixed"] == 0
+        u = r["U"][i]
+        K = fem.assemble_K(nel, x, mat)
+        Uo, Jo, _ = lba.static_solve(K, f, p["fixed"])
+        uo = Uo[:, 0]
+        res = f * free - fem.apply_K_matfree(nel, x, u, mat)
+        res[~free] = 0.0
+        rel = np.linalg.norm(res) / np.linalg.norm(f[free])
+        Ek, _ = fem.moduli(x, mat)
+        ed = fem.element_dofs(nel)
+        aK = np.bincount(ed.ravel(), weights=(Ek[:, None] * (np.abs(u)[ed] @ Ka.T)).ravel(), minlength=u.size)
+        floor = 4 * EPS * np.linalg.norm(aK[free]) / np.linalg.norm(f[free])
+        d = u - uo
+        Kd = fem.apply_K_matfree(nel, x, d, mat)
+        e_rel = np.sqrt(max(float(d[free] @ Kd[free]), 0.0) / Jo[0])
+        j_rel = abs(r["J"][i] / Jo[0] - 1)
+        g_own = sens.compliance_sensitivity(nel, x, u, mat)[:, 0]
+        # two summation orders of u_e^T K0 u_e differ by at most
+        # 2 gamma_16 |u_e|^T |K0| |u_e| per element (Higham, Sec. 3.1); nearly
+        # rigid element motions of large amplitude make that far exceed eps of
+        # the value itself
+        ue = np.abs(u)[ed]
+        dEa = mat.p * np.power(x, mat.p - 1.0) * (mat.E1 - mat.E0)
+        bound = 2 * 16 * EPS * dEa * np.einsum("ei,ij,ej->e", ue, Ka, ue) + 1e-300
+        g_orc = sens.compliance_sensitivity(nel, x, uo, mat)[:, 0]
+        s_rel = np.abs(r["dJ"][i] - g_orc).max() / np.abs(g_orc).max()
+        rows.append((i, nel, int(r["its"][i]), rel, floor, e_rel, j_rel, s_rel))
+        if verbose:
+            print(f"instance {i} {nel}: {r['its'][i]} it, true res {rel:.2e} (floor {floor:.2e}), energy err "
+                  f"{e_rel:.2e}, J err {j_rel:.2e}, dJ err {s_rel:.2e}, |u|max {np.abs(uo).max():.2e}")
+        if not rel <= max(tol, floor):
+            failures.append((i, "residual", rel, floor))
+        if not np.all(u[~free] == 0.0):
+            failures.append((i, "fixed DOFs not zero"))
+        if not e_rel <= e_tol:
+            failures.append((i, "energy error", e_rel))
+        if not j_rel <= max(10 * e_tol ** 2, 1e3 * EPS, 10 * floor):
+            failures.append((i, "compliance", j_rel, floor))
+        if not np.all(np.abs(r["dJ"][i] - g_own) <= bound):
+            failures.append((i, "dJ formula", float(np.max(np.abs(r["dJ"][i] - g_own) / bound))))
+        # where the instance's FP64 floor exceeds the solve tolerance (nearly
+        # singular designs), no solution agrees better than a multiple of it
+        if not s_rel <= max(1e-5, 10 * floor):
+            failures.append((i, "dJ vs oracle", s_rel, floor))
+    assert not failures, failures
+    return rows
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_instances_match_separate_oracle_solves(torch_mod, precision):
+    from paper_1909_13585_amd import batch as mlb_batch
+    insts = _small_instances()
+    r = _run(torch_mod, mlb_batch, insts, precision)
+    print(f"levels {list(r['levels'])} iterations {list(r['its'])} info {r['info']}")
+    assert r["info"]["converged"] == len(insts)
+    assert r["info"]["worst_true_rel_res"] <= 1e-9
+    _check_against_oracle(insts, r, 1e-10, 1e-6)
+
+
+def test_queue_modes_and_graphs_are_bitwise_identical(torch_mod):
+    from paper_1909_13585_amd import batch as mlb_batch
+    insts = _small_instances()
+    ref = _run(torch_mod, mlb_batch, insts, 1, queue=1, graphs=1)
+    for opts in (dict(queue=0, graphs=1), dict(queue=1, graphs=0), dict(queue=0, graphs=0)):
+        r = _run(torch_mod, mlb_batch, insts, 1, **opts)
+        assert list(r["its"]) == list(ref["its"]), opts
+        for a, b in zip(r["U"], ref["U"]):
+            assert np.array_equal(a, b), opts
+        for a, b in zip(r["dJ"], ref["dJ"]):
+            assert np.array_equal(a, b), opts
+
+
+def test_zero_load_and_bad_density(torch_mod):
+    from paper_1909_13585_amd import batch as mlb_batch
+    from paper_1909_13585_amd import MlbError
+    insts = _small_instances()[:3]
+    insts[1] = dict(insts[1], F=np.zeros_like(insts[1]["F"]))
+    r = _run(torch_mod, mlb_batch, insts, 0)
+    assert r["its"][1] == 0 and np.all(r["U"][1] == 0.0) and r["J"][1] == 0.0
+    assert r["its"][0] > 0 and r["its"][2] > 0
+    torch = torch_mod
+    b = mlb_batch.Batch([p["nel"] for p in insts])
+    fixed = torch.from_numpy(b.concat([p["fixed"] for p in insts], np.uint8)).cuda()
+    F = torch.from_numpy(b.concat([p["F"][:, 0] for p in insts], np.float64)).cuda()
+    xs = b.concat([p["x"] for p in insts], np.float64)
+    xs[5] = 1.5
+    with pytest.raises(MlbError):
+        b.set_problem_dev(fixed, F, torch.from_numpy(xs).cuda())
+    U = torch.empty(b.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(MlbError):   # no valid problem set
+        b.solve_dev(U)
+    b.close()
+
+
+def test_thirty_two_instances_match_oracle_and_separate_contexts(torch_mod):
+    """The 32-instance workload (64x32 ... 512x128, mixed precision, 1e-8)."""
+    torch = torch_mod
+    import paper_1909_13585_amd as mlb
+    from paper_1909_13585_amd import batch as mlb_batch
+    insts = W.small_instances_2d()
+    t0 = time.perf_counter()
+    r = _run(torch, mlb_batch, insts, mlb.MLB_MIXED, tol=1e-8, max_it=3000)
+    t_batch = time.perf_counter() - t0
+    assert r["info"]["converged"] == 32
+    print(f"iterations {list(r['its'])}, worst true relative residual {r['info']['worst_true_rel_res']:.3e}")
+    # per instance: true residual within 1e-8 or the FP64 floor of that instance
+    rows = _check_against_oracle(insts, r, 1e-8, 1e-3, verbose=True)
+    floors = np.array([row[4] for row in rows])
+    # the same analyses one context at a time (same levels per instance)
+    t0 = time.perf_counter()
+    Js = []
+    for p, L in zip(insts, r["levels"]):
+        ctx = mlb.Context(p["nel"], mg_levels=int(L), eig_level=1, precision=mlb.MLB_MIXED)
+        ctx.set_bc(p["fixed"])
+        ctx.set_loads(p["F"])
+        ctx.set_density_dev(torch.from_numpy(p["x"]).cuda())
+        U = torch.empty((1, ctx.n), dtype=torch.float64, device="cuda")
+        J, si = ctx.solve_static_dev(U, tol=1e-8, max_it=3000)
+        print(f"  context {p['nel']}: {si['iterations']} iterations, true rel residual {si['true_rel_residual']:.2e}")
+        Js.append(J[0])
+        ctx.close()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    print(f"32 instances: batched {t_batch:.3f} s (setup {r['info']['setup_s']:.3f}, solve {r['info']['solve_s']:.3f},"
+          f" {r['info']['batch_iterations']} batched iterations), one context at a time {t_seq:.3f} s")
+    assert np.all(np.abs(np.asarray(Js) / r["J"] - 1) <= np.maximum(1e-6, 10 * floors))
