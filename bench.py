@@ -24,11 +24,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the fine 1-column apply: rocprofv3 FETCH_SIZE x 1.99977
-# + WRITE_SIZE x 1.0 (factors from a 256 MiB calibration copy), measured on the
-# current kernel: 17,363 KiB read counter + 19,153 KiB written
-# (profiles/fine_apply_h8_192x64x64_hbm_counters.md).
-TRAFFIC_BYTES = (17363 * 1.99977 + 19153) * 1024
+# HBM bytes per launch of the fine FP64 1-column apply, per 3D variant (0
+# register tiles, 1 LDS tiles): rocprofv3 FETCH_SIZE x 1.99977 + WRITE_SIZE x
+# 1.0 (factors from a 256 MiB calibration copy), KiB per dispatch, from
+# profiles/fine_apply_h8_192x64x64_hbm_counters.md; None where the counters
+# were not taken for the current kernel.
+FINE_KERNELS = {0: "k_apply_wht3", 1: "k_apply_wht3_lds", 2: "k_apply_wht3 (no prefetch)"}
+TRAFFIC_BYTES = {0: (17363 * 1.99977 + 19153) * 1024, 1: None, 2: None}
 
 
 def parse():
@@ -51,6 +53,9 @@ def parse():
     ap.add_argument("--no-instances", action="store_true",
                     help="skip the 32 independent 2D instances (batched vs one context at a time)")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--wht-variant", type=int, default=-1,
+                    help="with --roofline-only: fine-apply variant to run (0 register tiles, 1 LDS tiles, "
+                         "2 register tiles without prefetch)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the dominant-kernel timing and a copy of known size (for counter runs)")
     return ap.parse_args()
@@ -252,6 +257,8 @@ def main():
         ctx.set_bc(p["fixed"])
         ctx.set_loads(p["F"])
         ctx.set_density_dev(x_dev)
+        if args.wht_variant >= 0:
+            ctx.set_tiles(0, 0, args.wht_variant)
         n, m = ctx.level_size(1)
         xa = torch.randn(n, dtype=torch.float64, device="cuda")
         ya = torch.empty_like(xa)
@@ -276,6 +283,7 @@ def main():
     free = int(n - p["fixed"].sum())
     gdofs = free * si["iterations"] / si["seconds"] / 1e9
 
+    var64 = ctx.tune["wht64_variant"] if ctx.tune else 0
     apply_ms, alg_bytes = apply_roofline(ctx, n, m, args.apply_reps, 1)
     achieved = alg_bytes / (apply_ms * 1e-3) / 1e9
     apply12_ms, alg12 = apply_roofline(ctx, n, m, max(5, args.apply_reps // 5), 12)
@@ -333,7 +341,7 @@ def main():
                                f"Gaussian-filtered density vf 0.3 (seed 3), {args.levels}-level MG, eigen level "
                                f"{args.eig_level}, {k} modes, solves to 1e-8, coarse eigen to {args.tol_eig:g}",
                    "precision": args.precision},
-        "tiles": {"wht_zchunk": ctx.tune["wht_zchunk"], "stencil_cols": ctx.tune["stencil_cols"]} if ctx.tune else None,
+        "tiles": {k: ctx.tune[k] for k in ("wht_zchunk", "wht_variant", "wht64_zchunk", "wht64_variant", "stencil_cols")} if ctx.tune else None,
         "mgpcg_gdof_per_s": gdofs,
         "static_iterations": si["iterations"],
         "coarse_iterations": ei["coarse_iterations"],
@@ -345,9 +353,9 @@ def main():
         "fp64_reference": fp64,
         "learned_warm_start": learned,
         "batched_instances": inst,
-        "roofline": {"bound": "hbm", "kernel": "k_apply_wht3<double> (fine H8 K apply, 1 column)",
+        "roofline": {"bound": "hbm", "kernel": f"{FINE_KERNELS[var64]}<double> (fine H8 K apply, 1 column)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES, "apply_ms": apply_ms,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES.get(var64), "apply_ms": apply_ms,
                      "alg_bytes": alg_bytes,
                      "apply_12col_ms": apply12_ms,
                      "achieved_12col": alg12 / (apply12_ms * 1e-3) / 1e9},

@@ -213,15 +213,18 @@ class Context:
         """Copies the K^l-orthonormal coarse modes of the last buckling call into Psi (k, n_l)."""
         self._check(self.lib.mlb_coarse_modes_dev(self.h, k, _dptr(Psi), _stream()))
 
-    def set_tiles(self, wht_zchunk=0, stencil_cols=0):
-        self._check(self.lib.mlb_set_tiles(self.h, wht_zchunk, stencil_cols))
+    def set_tiles(self, wht_zchunk=0, stencil_cols=0, wht_variant=-1):
+        self._check(self.lib.mlb_set_tiles(self.h, wht_zchunk, stencil_cols, wht_variant))
 
     def autotune(self, ncols):
         """Times the candidate tiles on Jacobi sweeps of ncols columns and keeps the fastest."""
         info = B.MlbTuneInfo()
         self._check(self.lib.mlb_autotune(self.h, ncols, C.byref(info), _stream()))
-        return {"wht_zchunk": info.wht_zchunk, "stencil_cols": info.stencil_cols,
-                "wht_ms": list(info.wht_ms), "stencil_ms": list(info.stencil_ms)}
+        out = {}
+        for f, _ in info._fields_:
+            v = getattr(info, f)
+            out[f] = list(v) if hasattr(v, "__len__") else v
+        return out
 
     def adjoint_rhs_dev(self, k, B):
         """Copies the adjoint right-hand sides of the last sensitivities call into B (k, n)."""

@@ -54,7 +54,9 @@ class MlbEigInfo(C.Structure):
 
 class MlbTuneInfo(C.Structure):
     _fields_ = [("wht_zchunk", C.c_int), ("stencil_cols", C.c_int), ("wht_ms", C.c_float * 5),
-                ("stencil_ms", C.c_float * 5)]
+                ("stencil_ms", C.c_float * 5), ("wht_variant", C.c_int), ("wht_lds_ms", C.c_float * 5),
+                ("wht_nopf_ms", C.c_float * 5), ("wht64_zchunk", C.c_int), ("wht64_variant", C.c_int),
+                ("wht64_ms", C.c_float * 5), ("wht64_lds_ms", C.c_float * 5), ("wht64_nopf_ms", C.c_float * 5)]
 
 
 class MlbBatchDesc(C.Structure):
@@ -106,7 +108,7 @@ _SIGS = {
     "mlb_coarse_modes_dev": (_I, [_P, _I, _P, _P]),
     "mlb_adjoints_dev": (_I, [_P, _I, _P, _P]),
     "mlb_adjoint_rhs_dev": (_I, [_P, _I, _P, _P]),
-    "mlb_set_tiles": (_I, [_P, _I, _I]),
+    "mlb_set_tiles": (_I, [_P, _I, _I, _I]),
     "mlb_autotune": (_I, [_P, _I, C.POINTER(MlbTuneInfo), _P]),
     "mlb_solve_block_dev": (_I, [_P, _I, _P, _P, _D, _I, C.POINTER(MlbSolveInfo), _P]),
     # warm-start network kernels (include/mlb_nn.h)

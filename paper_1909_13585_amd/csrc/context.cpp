@@ -70,8 +70,10 @@ struct mlb_ctx {
     std::vector<Graph> graphs;   // captured preconditioner applications of this hierarchy
     // tile parameters (mlb_autotune / mlb_set_tiles); operator results do not
     // depend on them (fused dot products group their partials by tile)
-    int wht_zchunk = 8;          // fine apply: pencil length in node planes
+    int wz[2] = {8, 8};          // fine apply, FP64 / FP32: pencil length in node planes
+    int wv[2] = {0, 0};          // fine apply, FP64 / FP32: 3D variant (register / LDS tiles)
     int nb_cbmax = 6;            // stencil apply: columns per thread
+    float tune_stencil_ms[5] = {};
     Tables tab{};
     double *dK0 = nullptr, *dHk = nullptr, *dBc = nullptr, *dD0Bc = nullptr, *dD0 = nullptr, *dT = nullptr,
            *dMc = nullptr, *dGHc = nullptr;
@@ -260,9 +262,12 @@ const double* wht_of<double>(mlb_ctx* c) { return c->tab.whs; }
 template <>
 const float* wht_of<float>(mlb_ctx* c) { return c->whtf; }
 
+template <typename T>
+constexpr int tix() { return sizeof(T) == 8 ? 0 : 1; }   // per-precision tile settings
+
 // partial-sum blocks written by the level-1 apply with a fused dot product
 int64_t fine_apply_blocks(mlb_ctx* c) {
-    return c->tab.wht_ok ? apply_wht_blocks(c->dim, c->lv[0].g, c->wht_zchunk) : apply_fine_blocks(c->lv[0].g);
+    return c->tab.wht_ok ? apply_wht_blocks(c->dim, c->lv[0].g, c->wz[0], c->wv[0]) : apply_fine_blocks(c->lv[0].g);
 }
 
 // y = A_j x (mode Y), y = r - A_j x (residual), y = x + omega D^-1 (r - A_j x) (Jacobi).
@@ -277,7 +282,7 @@ void apply_K(mlb_ctx* c, int j, int nc, const T* x, T* y, int mode, const T* r, 
     Level& l = c->lv[j - 1];
     if (j == 1 && c->tab.wht_ok)
         launch_apply_wht<T>(c->dim, l.g, E_of<T>(c), l.nmask, wht_of<T>(c), nc, l.n, x, y, mode, r, dinv_of<T>(l),
-                            (T)l.omega, dot_part, clean, c->wht_zchunk, c->st);
+                            (T)l.omega, dot_part, clean, c->wz[tix<T>()], c->wv[tix<T>()], c->st);
     else if (j == 1)
         launch_apply_fine<T>(c->dim, l.g, E_of<T>(c), l.nmask, K0_of<T>(c), nc, l.n, x, y, mode, r,
                              dinv_of<T>(l), (T)l.omega, dot_part, c->st);
@@ -1239,7 +1244,8 @@ int time_ms(mlb_ctx* c, int reps, F f, float* ms) {
 // multigrid cycle, on Jacobi sweeps (the dominant launches), and keeps the
 // fastest of each.
 template <typename T>
-int autotune_t(mlb_ctx* c, int ncols, mlb_tune_info* info) {
+int autotune_t(mlb_ctx* c, int ncols, bool stencils, int* zout, int* vout, float* ms_reg, float* ms_lds,
+               float* ms_nopf) {
     Level& l1 = c->lv[0];
     T* x = lbuf<T>(l1, 1);
     T* y = lbuf<T>(l1, 2);
@@ -1253,16 +1259,22 @@ int autotune_t(mlb_ctx* c, int ncols, mlb_tune_info* info) {
     }
     const int zc[] = {4, 6, 8, 12, 16};
     float best = 1e30f;
-    int bz = c->wht_zchunk;
-    for (int i = 0; i < 5; ++i) {
-        c->wht_zchunk = zc[i];
-        float ms = 0.f;
-        CHK(time_ms(c, 5, [&] { apply_K<T>(c, 1, ncols, x, y, kModeJacobi, r, nullptr); }, &ms));
-        if (info) info->wht_ms[i] = ms;
-        if (ms < best) best = ms, bz = zc[i];
-    }
-    c->wht_zchunk = bz;
-    if (c->L > 1) {
+    int bz = c->wz[tix<T>()], bv = c->wv[tix<T>()];
+    const int nvar = c->dim == 3 ? 3 : 1;
+    for (int v = 0; v < nvar; ++v)
+        for (int i = 0; i < 5; ++i) {
+            c->wz[tix<T>()] = zc[i];
+            c->wv[tix<T>()] = v;
+            float ms = 0.f;
+            CHK(time_ms(c, 5, [&] { apply_K<T>(c, 1, ncols, x, y, kModeJacobi, r, nullptr); }, &ms));
+            (v == 0 ? ms_reg : v == 1 ? ms_lds : ms_nopf)[i] = ms;
+            if (ms < best) best = ms, bz = zc[i], bv = v;
+        }
+    c->wz[tix<T>()] = bz;
+    c->wv[tix<T>()] = bv;
+    *zout = bz;
+    *vout = bv;
+    if (stencils && c->L > 1) {
         Level& l2 = c->lv[1];
         T* x2 = lbuf<T>(l2, 1);
         T* y2 = lbuf<T>(l2, 2);
@@ -1276,7 +1288,7 @@ int autotune_t(mlb_ctx* c, int ncols, mlb_tune_info* info) {
             c->nb_cbmax = cb[i];
             float ms = 0.f;
             CHK(time_ms(c, 5, [&] { apply_K<T>(c, 2, ncols, x2, y2, kModeJacobi, r2, nullptr); }, &ms));
-            if (info) info->stencil_ms[i] = ms;
+            c->tune_stencil_ms[i] = ms;
             if (ms < best) best = ms, bc = cb[i];
         }
         c->nb_cbmax = bc;
@@ -1710,11 +1722,14 @@ int mlb_coarse_modes_dev(mlb_ctx* c, int k, double* Psi, void* stream) {
     return MLB_OK;
 }
 
-int mlb_set_tiles(mlb_ctx* c, int wht_zchunk, int stencil_cols) {
+int mlb_set_tiles(mlb_ctx* c, int wht_zchunk, int stencil_cols, int wht_variant) {
     if (!c) return MLB_EINVAL;
-    if (wht_zchunk < 0 || wht_zchunk > 64 || stencil_cols < 0 || stencil_cols > 12)
-        return fail(c, MLB_EINVAL, "tile parameters out of range (z chunk 1..64, stencil columns 1..12)");
-    if (wht_zchunk > 0) c->wht_zchunk = wht_zchunk;
+    if (wht_zchunk < 0 || wht_zchunk > 64 || stencil_cols < 0 || stencil_cols > 12 || wht_variant < -1 ||
+        wht_variant > 2)
+        return fail(c, MLB_EINVAL,
+                    "tile parameters out of range (z chunk 1..64, stencil columns 1..12, variant -1..2)");
+    if (wht_zchunk > 0) c->wz[0] = c->wz[1] = wht_zchunk;
+    if (wht_variant >= 0) c->wv[0] = c->wv[1] = wht_variant;
     if (stencil_cols > 0) c->nb_cbmax = stencil_cols;
     drop_graphs(c);
     return MLB_OK;
@@ -1726,13 +1741,26 @@ int mlb_autotune(mlb_ctx* c, int ncols, mlb_tune_info* info, void* stream) {
     c->st = pick(c, stream);
     CHK(ensure_level_cols(c, ncols));
     drop_graphs(c);
-    if (info) *info = mlb_tune_info{};
-    if (c->d.precision == MLB_MIXED) CHK(autotune_t<float>(c, ncols, info));
-    else CHK(autotune_t<double>(c, ncols, info));
-    if (info) {
-        info->wht_zchunk = c->wht_zchunk;
-        info->stencil_cols = c->nb_cbmax;
+    mlb_tune_info t{};
+    if (c->d.precision == MLB_MIXED) {
+        CHK(autotune_t<float>(c, ncols, true, &t.wht_zchunk, &t.wht_variant, t.wht_ms, t.wht_lds_ms,
+                              t.wht_nopf_ms));
+        CHK(autotune_t<double>(c, ncols, false, &t.wht64_zchunk, &t.wht64_variant, t.wht64_ms, t.wht64_lds_ms,
+                               t.wht64_nopf_ms));
+    } else {
+        CHK(autotune_t<double>(c, ncols, true, &t.wht_zchunk, &t.wht_variant, t.wht_ms, t.wht_lds_ms,
+                               t.wht_nopf_ms));
+        t.wht64_zchunk = t.wht_zchunk;
+        t.wht64_variant = t.wht_variant;
+        for (int i = 0; i < 5; ++i) {
+            t.wht64_ms[i] = t.wht_ms[i];
+            t.wht64_lds_ms[i] = t.wht_lds_ms[i];
+            t.wht64_nopf_ms[i] = t.wht_nopf_ms[i];
+        }
     }
+    t.stencil_cols = c->nb_cbmax;
+    for (int i = 0; i < 5; ++i) t.stencil_ms[i] = c->tune_stencil_ms[i];
+    if (info) *info = t;
     drop_graphs(c);
     return MLB_OK;
 }

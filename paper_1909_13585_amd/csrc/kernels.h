@@ -33,11 +33,14 @@ void launch_restrict_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf
                         int64_t ldf, int64_t ldc, const T* xf, T* yc, hipStream_t st);
 
 // ---- element-centric Walsh-Hadamard apply (kernels_wht.hip)
-int64_t apply_wht_blocks(int dim, const Geo& g, int zchunk);
+// variant (3D): 0 register tiles of 8 x 8 element columns per wave with the
+// next node plane prefetched, 1 tiles of 16 x 16 columns per block staged in
+// LDS, 2 register tiles without prefetch (fewer registers, more waves)
+int64_t apply_wht_blocks(int dim, const Geo& g, int zchunk, int variant);
 template <typename T>
 void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* blocks, int ncols,
                       int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega, double* dot_part,
-                      bool clean, int zchunk, hipStream_t st);
+                      bool clean, int zchunk, int variant, hipStream_t st);
 
 // ---- setup (kernels_setup.hip)
 void launch_material(int64_t m, const double* x, double E1, double E0, double p, double* Ek, float* Ekf,

@@ -152,8 +152,11 @@ constexpr int kXcd3 = 8;        // XCDs the blocks are dealt over
 // CLEAN: the caller guarantees x == 0 at every Dirichlet DOF (true for every
 // vector inside the solvers), so neighbour values need no masking; only the
 // owned node's mask is read (identity rows).
-template <typename T, int MODE, bool DOT, bool CLEAN>
-__global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(MLB_WHT3_WAVES, 8))) void k_apply_wht3(
+// PF: prefetch the next node plane one step ahead (more registers, fewer
+// waves per SIMD); without it the next plane is loaded at the end of a step
+// and latency is hidden by the other waves only.
+template <typename T, int MODE, bool DOT, bool CLEAN, bool PF>
+__global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(PF || DOT ? MLB_WHT3_WAVES : 3, 8))) void k_apply_wht3(
     Geo g, int kz_chunk, int ntiles_x, int ntiles_y, const T* __restrict__ E, const uint8_t* __restrict__ nmask,
     WhtBlocks<T> B, int ncols, int64_t ld, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ r,
     const T* __restrict__ dinv, T omega, double* __restrict__ part) {
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(MLB_WH
         fetch(kz0 - 1, lo, mlo);
         fetch(kz0, hi, mhi);
         for (int ke = kz0 - 1; ke < kend; ++ke) {
-            fetch(ke + 2, pf, mpf);   // prefetch for the next step
+            if (PF) fetch(ke + 2, pf, mpf);   // prefetch for the next step
             const bool eok = col_ok && ke >= 0 && ke < g.nz;
             const T Eraw = E[eok ? ebase + eplane * ke : 0];
             const T Ee = eok ? Eraw : T(0);
@@ -276,17 +279,185 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(MLB_WH
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     lo[c][q] = hi[c][q];
-                    hi[c][q] = pf[c][q];
+                    if (PF) hi[c][q] = pf[c][q];
                 }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 mlo[q] = mhi[q];
-                mhi[q] = mpf[q];
+                if (PF) mhi[q] = mpf[q];
             }
+            if (!PF) fetch(ke + 2, hi, mhi);
         }
         if (DOT) {
             const double bs = wht_block_sum(dsum, sh);
             if (lane == 0 && threadIdx.y == 0) part[col * nblk + blockIdx.x] = bs;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3D, LDS variant: one block of 16 x 16 threads is a tile of 16 x 16 element
+// columns (tiles overlap by one column/row, the 15 x 15 interior node columns
+// are owned) walking a pencil of element layers along z.  Each node plane of
+// the tile (17 x 17 nodes x 3 components, component-major) is loaded once,
+// coalesced, into a ring of 3 LDS planes, one step ahead of its use; every
+// thread reads its element's 8 nodes from LDS, applies the element in the
+// Walsh-Hadamard basis, and writes its 4 low-plane node contributions (plus
+// the carried high-plane part of the element below) to LDS, where each owned
+// node sums its 4 columns in a fixed order.  Per lane this keeps no node
+// planes in registers (the register-tile variant holds 3 x 12 values).
+// Dirichlet masking happens when a plane is loaded; identity rows take the
+// owned node's raw value.
+constexpr int kLT = 16;                    // tile edge in element columns
+constexpr int kLN = kLT + 1;               // tile edge in nodes
+constexpr int kLP = kLN * kLN;             // nodes per tile plane
+constexpr int kLThreads = kLT * kLT;
+#ifndef MLB_WHTL_WAVES
+#define MLB_WHTL_WAVES 2
+#endif
+
+template <typename T, int MODE, bool DOT>
+__global__ __launch_bounds__(kLThreads) __attribute__((amdgpu_waves_per_eu(MLB_WHTL_WAVES, 8))) void k_apply_wht3_lds(Geo g, int kz_chunk, int ntiles_x, int ntiles_y,
+                                                              const T* __restrict__ E,
+                                                              const uint8_t* __restrict__ nmask, WhtBlocks<T> B,
+                                                              int ncols, int64_t ld, const T* __restrict__ x,
+                                                              T* __restrict__ y, const T* __restrict__ r,
+                                                              const T* __restrict__ dinv, T omega,
+                                                              double* __restrict__ part) {
+    __shared__ T plane[3][3][kLP];         // [slot][component][node]
+    __shared__ T pc[3][4][kLThreads];      // [component][corner][element column]
+    __shared__ double sh[kLThreads / 64];
+    const int tid = threadIdx.x;
+    const int tx = tid % kLT, ty = tid / kLT;
+    // blocks dealt round robin over the XCDs; each XCD takes a contiguous
+    // range of the (z-chunk major) tile order
+    const int64_t per_xcd = gridDim.x / kXcd3;
+    const int64_t tile = (blockIdx.x % kXcd3) * per_xcd + blockIdx.x / kXcd3;
+    const int64_t ntile_xy = (int64_t)ntiles_x * ntiles_y;
+    const int tzc = (int)(tile / ntile_xy);
+    const int txy = (int)(tile % ntile_xy);
+    const int i0 = (txy % ntiles_x) * (kLT - 1) - 1;   // node / element origin of the tile
+    const int j0 = (txy / ntiles_x) * (kLT - 1) - 1;
+    const int kz0 = tzc * kz_chunk;
+    const int kend = min(kz0 + kz_chunk, g.nnz);
+    const bool live = kz0 < g.nnz;                      // padding blocks of the XCD-rounded grid
+    const int ie = i0 + tx, je = j0 + ty;
+    const bool col_ok = ie >= 0 && ie < g.nx && je >= 0 && je < g.ny;
+    const bool owner = tx >= 1 && ty >= 1 && ie <= g.nx && je <= g.ny;
+    const int64_t pl = (int64_t)g.nnx * g.nny;
+    const int64_t epl = (int64_t)g.nx * g.ny;
+    const int64_t ebase = col_ok ? ie + (int64_t)g.nx * je : 0;
+    const int64_t own = owner ? ie + (int64_t)g.nnx * je : 0;
+    constexpr int kPer = (3 * kLP + kLThreads - 1) / kLThreads;   // plane entries per thread
+    for (int col = 0; col < ncols; ++col) {
+        const T* xc = x + col * ld;
+        double dsum = 0.0;
+        // entries e = tid + kLThreads * k of a plane: row ly, then x-major
+        // interleaved (node, component), so consecutive threads read
+        // consecutive addresses
+        auto load = [&](int kk, T (&v)[kPer]) {
+            const bool kin = kk >= 0 && kk < g.nnz;
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int e = tid + kLThreads * k;
+                const int ly = e / (3 * kLN), rem = e % (3 * kLN);
+                const int lx = rem / 3, c = rem % 3;
+                const int gi = i0 + lx, gj = j0 + ly;
+                const bool ok = e < 3 * kLP && kin && gi >= 0 && gi < g.nnx && gj >= 0 && gj < g.nny;
+                const int64_t nd = ok ? gi + (int64_t)g.nnx * gj + pl * kk : 0;
+                const T xv = xc[nd * 3 + c];
+                const uint8_t m = nmask[nd];
+                v[k] = (ok && !((m >> c) & 1)) ? xv : T(0);
+            }
+        };
+        auto stash = [&](int kk, const T (&v)[kPer]) {
+            const int slot = (kk + 3) % 3;
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int e = tid + kLThreads * k;
+                if (e < 3 * kLP) {
+                    const int ly = e / (3 * kLN), rem = e % (3 * kLN);
+                    plane[slot][rem % 3][ly * kLN + rem / 3] = v[k];
+                }
+            }
+        };
+        T pf[kPer];
+        if (live) {
+            load(kz0 - 1, pf);
+            stash(kz0 - 1, pf);
+            load(kz0, pf);
+            stash(kz0, pf);
+        }
+        __syncthreads();
+        T cout[3][4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cout[c][q] = T(0);
+        for (int ke = kz0 - 1; live && ke < kend; ++ke) {
+            const bool more = ke + 2 <= kend;
+            if (more) load(ke + 2, pf);   // in flight during this step
+            const bool eok = col_ok && ke >= 0 && ke < g.nz;
+            const T Eraw = E[eok ? ebase + epl * ke : 0];
+            const T Ee = eok ? Eraw : T(0);
+            const int slo = (ke + 3) % 3, shi = (ke + 4) % 3;
+            T u[3][8];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int ln = (ty + (q >> 1)) * kLN + tx + (q & 1);
+                    u[c][q] = plane[slo][c][ln];
+                    u[c][q + 4] = plane[shi][c][ln];
+                }
+            const T xo0 = u[0][0], xo1 = u[1][0], xo2 = u[2][0];   // owned node (masked)
+            element_apply<3, T>(B, Ee, u);
+            if (ke >= kz0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) pc[c][q][tid] = u[c][q] + cout[c][q];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cout[c][q] = u[c][q + 4];
+            if (ke >= kz0) {
+                __syncthreads();
+                if (owner && ke < g.nnz) {
+                    const int64_t nd = own + pl * ke;
+                    const uint8_t m = nmask[nd];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        // fixed order: own column, x neighbour, y neighbour, diagonal
+                        const T acc = ((pc[c][0][tid] + pc[c][1][tid - 1]) + pc[c][2][tid - kLT]) +
+                                      pc[c][3][tid - kLT - 1];
+                        const int64_t d = nd * 3 + c;
+                        const T xm = c == 0 ? xo0 : c == 1 ? xo1 : xo2;
+                        const bool fixed = (m >> c) & 1;
+                        const T xraw = fixed ? xc[d] : xm;
+                        const T ax = fixed ? xraw : acc;
+                        const T rr = MODE == kModeY ? T(0) : r[col * ld + d];
+                        const T di = MODE == kModeJacobi ? dinv[d] : T(0);
+                        y[col * ld + d] = wht_epilogue<T, MODE>(ax, xraw, rr, di, omega);
+                        if (DOT) dsum += (double)xraw * (double)ax;
+                    }
+                }
+            }
+            if (more) stash(ke + 2, pf);   // the slot of plane ke - 1, no longer read
+            __syncthreads();
+        }
+        if (DOT) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) dsum += __shfl_down(dsum, off, 64);
+            sh[tid >> 6] = __shfl(dsum, 0, 64);
+            __syncthreads();
+            if (tid < 64) {
+                double s2 = 0.0;
+                for (int w = 0; w < kLThreads / 64; ++w) s2 += sh[w];
+                part[col * (int64_t)gridDim.x + blockIdx.x] = s2;
+            }
+            __syncthreads();
         }
     }
 }
@@ -401,9 +572,22 @@ __global__ __launch_bounds__(kTX2* kTW2) void k_apply_wht2(Geo g, int ky_chunk, 
 
 // zchunk: target pencil length in node planes (3D; tunable, results do not
 // depend on it: every owned node is summed in the same order)
-static void wht_geometry(int dim, const Geo& g, int zchunk, dim3& grid, dim3& block, int& chunk, int& ntx, int& nty) {
+static void wht_geometry(int dim, const Geo& g, int zchunk, int variant, dim3& grid, dim3& block, int& chunk,
+                         int& ntx, int& nty) {
     nty = 1;
-    if (dim == 3) {
+    if (dim == 3 && variant == 1) {
+        const int tiles_x = (g.nnx + kLT - 2) / (kLT - 1);
+        const int tiles_y = (g.nny + kLT - 2) / (kLT - 1);
+        const int zc = zchunk > 0 ? zchunk : 8;
+        int nch = (g.nnz + zc - 1) / zc;
+        chunk = (g.nnz + nch - 1) / nch;
+        nch = (g.nnz + chunk - 1) / chunk;
+        const int64_t tiles = (int64_t)tiles_x * tiles_y * nch;
+        grid = dim3((unsigned)((tiles + kXcd3 - 1) / kXcd3 * kXcd3), 1, 1);
+        block = dim3(kLThreads, 1, 1);
+        ntx = tiles_x;
+        nty = tiles_y;
+    } else if (dim == 3) {
         const int tiles_x = (g.nnx + kWT - 2) / (kWT - 1);
         const int tiles_y = (g.nny + kWT - 2) / (kWT - 1);
         const int zc = zchunk > 0 ? zchunk : 8;
@@ -428,25 +612,31 @@ static void wht_geometry(int dim, const Geo& g, int zchunk, dim3& grid, dim3& bl
     }
 }
 
-int64_t apply_wht_blocks(int dim, const Geo& g, int zchunk) {
+int64_t apply_wht_blocks(int dim, const Geo& g, int zchunk, int variant) {
     dim3 gr, b;
     int ch, ntx, nty;
-    wht_geometry(dim, g, zchunk, gr, b, ch, ntx, nty);
+    wht_geometry(dim, g, zchunk, variant, gr, b, ch, ntx, nty);
     return (int64_t)gr.x * gr.y * gr.z;
 }
 
 template <typename T>
 void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* blocks, int ncols,
                       int64_t ld, const T* x, T* y, int mode, const T* r, const T* dinv, T omega, double* dot_part,
-                      bool clean, int zchunk, hipStream_t st) {
+                      bool clean, int zchunk, int variant, hipStream_t st) {
     WhtBlocks<T> B;
     for (int i = 0; i < 9; ++i) B.v[i] = blocks[i];
     dim3 gr, b;
     int ch, ntx, nty;
-    wht_geometry(dim, g, zchunk, gr, b, ch, ntx, nty);
-#define MLB_L3C(M, D, C)                                                                                         \
-    hipLaunchKernelGGL((k_apply_wht3<T, M, D, C>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B, ncols, ld, x, y, r, \
-                       dinv, omega, dot_part)
+    wht_geometry(dim, g, zchunk, variant, gr, b, ch, ntx, nty);
+#define MLB_L3C(M, D, C)                                                                                          \
+    do {                                                                                                          \
+        if (variant == 2)                                                                                         \
+            hipLaunchKernelGGL((k_apply_wht3<T, M, D, C, false>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B,      \
+                               ncols, ld, x, y, r, dinv, omega, dot_part);                                        \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_apply_wht3<T, M, D, C, true>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B,       \
+                               ncols, ld, x, y, r, dinv, omega, dot_part);                                        \
+    } while (0)
 #define MLB_L3(M, D)                       \
     do {                                   \
         if (clean) MLB_L3C(M, D, true);    \
@@ -455,7 +645,15 @@ void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, c
 #define MLB_L2(M, D)                                                                                              \
     hipLaunchKernelGGL((k_apply_wht2<T, M, D>), gr, b, 0, st, g, ch, ntx, E, nmask, B, ncols, ld, x, y, r, dinv, omega, \
                        dot_part)
-    if (dim == 3) {
+#define MLB_LL(M, D)                                                                                              \
+    hipLaunchKernelGGL((k_apply_wht3_lds<T, M, D>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B, ncols, ld, x, y, r,  \
+                       dinv, omega, dot_part)
+    if (dim == 3 && variant == 1) {
+        if (mode == kModeY && dot_part) MLB_LL(kModeY, true);
+        else if (mode == kModeY) MLB_LL(kModeY, false);
+        else if (mode == kModeResidual) MLB_LL(kModeResidual, false);
+        else MLB_LL(kModeJacobi, false);
+    } else if (dim == 3) {
         if (mode == kModeY && dot_part) MLB_L3(kModeY, true);
         else if (mode == kModeY) MLB_L3(kModeY, false);
         else if (mode == kModeResidual) MLB_L3(kModeResidual, false);
@@ -469,13 +667,14 @@ void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, c
 #undef MLB_L3
 #undef MLB_L3C
 #undef MLB_L2
+#undef MLB_LL
 }
 
 template void launch_apply_wht<double>(int, const Geo&, const double*, const uint8_t*, const double*, int, int64_t,
                                        const double*, double*, int, const double*, const double*, double, double*,
-                                       bool, int, hipStream_t);
+                                       bool, int, int, hipStream_t);
 template void launch_apply_wht<float>(int, const Geo&, const float*, const uint8_t*, const float*, int, int64_t,
                                       const float*, float*, int, const float*, const float*, float, double*, bool,
-                                      int, hipStream_t);
+                                      int, int, hipStream_t);
 
 }  // namespace mlb

@@ -1,5 +1,6 @@
-"""Tile parameters and the autotuner: operator applies are bitwise independent
-of the tiles, and the autotuner picks one of its candidates."""
+"""Tile parameters and the autotuner: for each fine-apply variant the operator
+applies are bitwise independent of the tiles, both variants match the
+oracle's element loop, and the autotuner picks one of its candidates."""
 import numpy as np
 import pytest
 
@@ -24,21 +25,46 @@ def test_tiles_do_not_change_applies_and_autotune_picks_a_candidate():
     g = torch.Generator(device="cuda").manual_seed(3)
     x1 = torch.randn((5, n1), dtype=torch.float64, device="cuda", generator=g)
     x2 = torch.randn((7, n2), dtype=torch.float64, device="cuda", generator=g)
-    outs = []
-    for zc, cb in [(4, 2), (8, 6), (16, 3), (12, 8)]:
-        ctx.set_tiles(zc, cb)
+    outs = {0: [], 1: [], 2: []}
+    for zc, cb, var in [(4, 2, 0), (8, 6, 0), (16, 3, 0), (12, 8, 0), (4, 2, 1), (6, 6, 1), (16, 3, 1), (12, 8, 1),
+                        (4, 2, 2), (12, 6, 2)]:
+        ctx.set_tiles(zc, cb, var)
         y1 = torch.empty_like(x1)
         y2 = torch.empty_like(x2)
         ctx.apply_K_dev(1, x1, y1)
         ctx.apply_K_dev(2, x2, y2)
         torch.cuda.synchronize()
-        outs.append((y1.cpu().numpy(), y2.cpu().numpy()))
-    for a, b in outs[1:]:
-        assert np.array_equal(a, outs[0][0]) and np.array_equal(b, outs[0][1])
+        outs[var].append((y1.cpu().numpy(), y2.cpu().numpy()))
+    # within a variant: bitwise the same for every tile choice
+    for var in (0, 1, 2):
+        for a, b in outs[var][1:]:
+            assert np.array_equal(a, outs[var][0][0]) and np.array_equal(b, outs[var][0][1]), var
+    # the stencil levels do not depend on the fine variant; the register
+    # tiles with and without prefetch sum in the same order
+    assert np.array_equal(outs[0][0][1], outs[1][0][1])
+    assert np.array_equal(outs[0][0][0], outs[2][0][0])
+    # both fine variants against the oracle's element loop (input not zero at
+    # Dirichlet DOFs: masked columns, identity rows)
+    from oracle import fem
+    mat = fem.Material()
+    xh = x1.cpu().numpy()
+    fixed = p["fixed"].astype(bool)
+    for var in (0, 1, 2):
+        yv = outs[var][0][0]
+        for j in range(xh.shape[0]):
+            xin = xh[j].copy()
+            xin[fixed] = 0.0
+            ref = fem.apply_K_matfree(nel, p["x"], xin, mat)
+            ref[fixed] = xh[j][fixed]
+            err = np.abs(yv[j] - ref).max() / np.abs(ref).max()
+            assert err < 1e-13, (var, j, err)
     info = ctx.autotune(12)
-    assert info["wht_zchunk"] in (4, 6, 8, 12, 16)
+    assert info["wht_zchunk"] in (4, 6, 8, 12, 16) and info["wht64_zchunk"] in (4, 6, 8, 12, 16)
+    assert info["wht_variant"] in (0, 1, 2) and info["wht64_variant"] in (0, 1, 2)
     assert info["stencil_cols"] in (2, 3, 4, 6, 8)
-    assert all(t > 0 for t in info["wht_ms"]) and all(t > 0 for t in info["stencil_ms"])
+    assert all(t > 0 for k in ("wht_ms", "wht_lds_ms", "wht_nopf_ms", "wht64_ms", "wht64_lds_ms", "wht64_nopf_ms")
+               for t in info[k])
+    assert all(t > 0 for t in info["stencil_ms"])
     U = torch.empty((1, n1), dtype=torch.float64, device="cuda")
     J, si = ctx.solve_static_dev(U, tol=1e-8, max_it=2000)
     assert si["converged"] == 1
