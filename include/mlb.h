@@ -139,6 +139,9 @@ typedef struct {
     double seconds_coarse;      /* Galerkin operators + coarse eigensolve */
     double seconds_fine;        /* interpolation + fine block solve */
     double seconds_ritz;        /* Rayleigh-Ritz + residuals */
+    int coarse_warm_used;       /* 1 if a MLB_WARM_COARSE block started the coarse eigensolve
+                                   (it is dropped for the plain start when its initial Ritz
+                                   residual is worse or the block is rank deficient) */
 } mlb_eig_info;
 
 /* ---- lifetime --------------------------------------------------------- */

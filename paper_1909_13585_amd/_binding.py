@@ -49,7 +49,7 @@ class MlbSolveInfo(C.Structure):
 class MlbEigInfo(C.Structure):
     _fields_ = [("coarse_iterations", C.c_int), ("coarse_residual", C.c_double), ("coarse_gap", C.c_double),
                 ("fine_iterations", C.c_int), ("fine_true_residual", C.c_double), ("seconds_coarse", C.c_double),
-                ("seconds_fine", C.c_double), ("seconds_ritz", C.c_double)]
+                ("seconds_fine", C.c_double), ("seconds_ritz", C.c_double), ("coarse_warm_used", C.c_int)]
 
 
 class MlbTuneInfo(C.Structure):

@@ -878,7 +878,8 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
 // so every Gram matrix is formed from exact operator images (updating them
 // by the same recurrences drifts once the basis becomes ill-conditioned).
 // On exit eS[0..nb) holds X (K-orthonormal), mu the Ritz values (descending).
-int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double* gap, std::vector<double>& mu) {
+int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double* gap, std::vector<double>& mu,
+                int* warm_used) {
     const bool verbose = std::getenv("MLB_VERBOSE") != nullptr;
     const int j = c->ell;
     Level& l = c->lv[j - 1];
@@ -913,35 +914,85 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         launch_axpby(n * cols, -1.0, AV, 0.0, AV, c->st);
     };
 
-    // start block: warm-start columns first, seeded random for the rest
-    {
+    // Start block: seeded random columns, Rayleigh-Ritz on their span, the
+    // Ritz block in bufs[1].  With a warm start (its columns first, random
+    // guard columns after) both blocks are built and the warm one is kept
+    // only if the worst initial residual of the k wanted Ritz pairs is not
+    // larger than the plain block's (a rank-deficient warm block is dropped).
+    std::vector<double> GK, GA, ev, C, Cpw, G, Tm, Co;
+    std::vector<double> nrm(2 * nb);
+    auto ritz_residual = [&](const std::vector<double>& m, double* out) -> int {
+        std::memcpy(c->hpin, m.data(), sizeof(double) * nb);
+        HIPC(hipMemcpyAsync(sc(c, 11), c->hpin, sizeof(double) * nb, hipMemcpyHostToDevice, c->st));
+        launch_residual_block(n, nb, n, bufs[1].AS, bufs[1].KS, sc(c, 11), c->eR, c->st);
+        dots(c, n, nb, c->eR, c->eR, sc(c, 12));
+        dots(c, n, nb, bufs[1].KS, bufs[1].KS, sc(c, 12) + nb);
+        CHK(read_scal(c, sc(c, 12), 2 * nb, nrm.data()));
+        double w = 0.0;
+        for (int i = 0; i < k; ++i) {
+            const double den = std::fabs(m[i]) * std::sqrt(nrm[nb + i]);
+            w = std::max(w, den > 0 ? std::sqrt(nrm[i]) / den : 1e300);
+        }
+        *out = std::isfinite(w) ? w : 1e300;
+        return MLB_OK;
+    };
+    // build + Rayleigh-Ritz of one start block; ok = false if rank deficient
+    auto start_block = [&](bool warm, bool* ok) -> int {
         double* X = bufs[0].S;
         launch_random_fill(n, nb, n, c->o.seed, l.nmask, c->dim, X, c->st);
-        if (c->warm_coarse_cols > 0 && (int64_t)c->warm_coarse.size() == n * c->warm_coarse_cols) {
+        if (warm) {
             const int wc = std::min(c->warm_coarse_cols, nb);
             HIPC(hipMemcpyAsync(X, c->warm_coarse.data(), sizeof(double) * n * wc, hipMemcpyHostToDevice, c->st));
             launch_mask_fixed(n, wc, n, l.nmask, c->dim, X, c->st);
             CHK(sync(c));
         }
         applyKA(nb, X, bufs[0].KS, bufs[0].AS);
-    }
-    std::vector<double> GK, GA, ev, C, Cpw, G, Tm, Co;
-    {
         CHK(gram2(c, n, nb, bufs[0].S, nb, bufs[0].KS, bufs[0].AS, GK, GA));
-        if (!rayleigh_ritz_gram(nb, nb, GK, GA, nb, ev, C))
-            return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: start block is rank deficient");
+        *ok = rayleigh_ritz_gram(nb, nb, GK, GA, nb, ev, C);
+        if (!*ok) return MLB_OK;
         CHK(upload_cm(c, c->cbuf, C));
         launch_gemm_cat(n, nb, n, bufs[0].S, 0, n, nullptr, nb, c->cbuf, 0.0, n, bufs[1].S, c->st);
         applyKA(nb, bufs[1].S, bufs[1].KS, bufs[1].AS);
-        cur = 1;
+        return MLB_OK;
+    };
+    {
+        bool ok = false;
+        CHK(start_block(false, &ok));
+        if (!ok) return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: start block is rank deficient");
         mu.assign(ev.begin(), ev.begin() + nb);
+        *warm_used = 0;
+        if (c->warm_coarse_cols > 0 && (int64_t)c->warm_coarse.size() == n * c->warm_coarse_cols) {
+            double w_plain = 0.0, w_warm = 0.0;
+            CHK(ritz_residual(mu, &w_plain));
+            // keep the plain Ritz block in the P buffers while the warm one is built
+            launch_copy_cols(n, nb, n, bufs[1].S, n, c->eP, c->st);
+            launch_copy_cols(n, nb, n, bufs[1].KS, n, c->ePK, c->st);
+            launch_copy_cols(n, nb, n, bufs[1].AS, n, c->ePA, c->st);
+            CHK(start_block(true, &ok));
+            std::vector<double> mu_w;
+            if (ok) {
+                mu_w.assign(ev.begin(), ev.begin() + nb);
+                CHK(ritz_residual(mu_w, &w_warm));
+            }
+            if (ok && w_warm <= w_plain) {
+                mu = mu_w;
+                *warm_used = 1;
+            } else {
+                launch_copy_cols(n, nb, n, c->eP, n, bufs[1].S, c->st);
+                launch_copy_cols(n, nb, n, c->ePK, n, bufs[1].KS, c->st);
+                launch_copy_cols(n, nb, n, c->ePA, n, bufs[1].AS, c->st);
+            }
+            if (verbose)
+                std::fprintf(stderr, "[mlb] coarse start: plain %.3e warm %.3e -> %s\n", w_plain,
+                             ok ? w_warm : -1.0, *warm_used ? "warm" : "plain");
+        }
+        cur = 1;
     }
     int rp = 0;   // columns of P
     int it = 0;
     bool stalled = false;
     std::vector<double> hist;
     double wres = 1e300;
-    std::vector<double> nrm(2 * nb);
     const int max_it = c->o.eig_max_it > 0 ? c->o.eig_max_it : 400;
     double t_host = 0.0, t_pre = 0.0;
     const double t_start = now_s();
@@ -1102,7 +1153,8 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
     int cit = 0;
     double cres = 0, gap = 0;
     std::vector<double> mu;
-    CHK(coarse_eigs(c, k, tol_eig, &cit, &cres, &gap, mu));
+    int warm_used = 0;
+    CHK(coarse_eigs(c, k, tol_eig, &cit, &cres, &gap, mu, &warm_used));
     const double t1 = now_s();
     // step 2: interpolate the coarse modes to the fine grid
     CHK(ensure_cg(c, std::max(k, c->ncases)));
@@ -1178,6 +1230,7 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         info->coarse_iterations = cit;
         info->coarse_residual = cres;
         info->coarse_gap = gap;
+        info->coarse_warm_used = warm_used;
         info->fine_iterations = si.iterations;
         info->fine_true_residual = si.true_rel_residual;
         info->seconds_coarse = t1 - t0;
@@ -1632,11 +1685,17 @@ static int solve_static_common(mlb_ctx* c, double tol, int max_it, mlb_solve_inf
         dots(c, c->n, nc, c->U, c->R, sc(c, 0) + nc);
         std::vector<double> fu(2 * nc);
         CHK(read_scal(c, sc(c, 0), 2 * nc, fu.data()));
-        std::vector<double> alpha(nc);
-        for (int i = 0; i < nc; ++i) alpha[i] = fu[nc + i] > 0 ? fu[i] / fu[nc + i] : 0.0;
-        CHK(upload_cm(c, sc(c, 1), alpha));
-        launch_scale_cols(c->n, nc, c->n, sc(c, 1), c->U, c->st);
-        x0 = true;
+        // (this never does worse than the zero start in the energy norm; a
+        // non-finite guess falls back to the zero start)
+        bool finite = true;
+        for (double v : fu) finite = finite && std::isfinite(v);
+        if (finite) {
+            std::vector<double> alpha(nc);
+            for (int i = 0; i < nc; ++i) alpha[i] = fu[nc + i] > 0 ? fu[i] / fu[nc + i] : 0.0;
+            CHK(upload_cm(c, sc(c, 1), alpha));
+            launch_scale_cols(c->n, nc, c->n, sc(c, 1), c->U, c->st);
+            x0 = true;
+        }
     }
     if (c->ncases > 1 && c->o.block_cg) CHK(bpcg(c, c->F, c->U, c->ncases, tol, max_it, x0, info));
     else CHK(pcg(c, c->F, c->U, c->ncases, tol, max_it, x0, info));
