@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # 1.0 (factors from a 256 MiB calibration copy), KiB per dispatch, from
 # profiles/fine_apply_h8_192x64x64_hbm_counters.md; None where the counters
 # were not taken for the current kernel.
-FINE_KERNELS = {0: "k_apply_wht3", 1: "k_apply_wht3_lds", 2: "k_apply_wht3 (no prefetch)"}
-TRAFFIC_BYTES = {0: (17363 * 1.99977 + 19153) * 1024, 1: None, 2: None}
+FINE_KERNELS = {0: "k_apply_wht3", 1: "k_apply_wht3_lds", 2: "k_apply_wht3 (no prefetch)", 3: "k_apply_wht3r"}
+TRAFFIC_BYTES = {0: (17363 * 1.99977 + 19153) * 1024, 1: None, 2: None, 3: None}
 
 
 def parse():
@@ -57,7 +57,9 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--wht-variant", type=int, default=-1,
                     help="with --roofline-only: fine-apply variant to run (0 register tiles, 1 LDS tiles, "
-                         "2 register tiles without prefetch)")
+                         "2 register tiles without prefetch, 3 register tiles with per-plane transforms)")
+    ap.add_argument("--wht-zchunk", type=int, default=0,
+                    help="with --roofline-only: pencil length of the fine apply (0 keeps the default)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the dominant-kernel timing and a copy of known size (for counter runs)")
     return ap.parse_args()
@@ -262,8 +264,8 @@ def main():
         ctx.set_bc(p["fixed"])
         ctx.set_loads(p["F"])
         ctx.set_density_dev(x_dev)
-        if args.wht_variant >= 0:
-            ctx.set_tiles(0, 0, args.wht_variant)
+        if args.wht_variant >= 0 or args.wht_zchunk > 0:
+            ctx.set_tiles(args.wht_zchunk, 0, args.wht_variant)
         n, m = ctx.level_size(1)
         xa = torch.randn(n, dtype=torch.float64, device="cuda")
         ya = torch.empty_like(xa)

@@ -71,13 +71,17 @@ extern "C" {
 typedef struct mlb_ctx mlb_ctx;
 
 /* Result of mlb_autotune: the chosen tile parameters and the mean time (ms)
-   of a Jacobi sweep for each candidate (z chunk 4, 6, 8, 12, 16; stencil
+   of a Jacobi sweep for each candidate (z chunk 4, 6, 8, 10, 12; stencil
    columns per thread 2, 3, 4, 6, 8; 3D fine-apply variant 0 = register tiles
    of 8 x 8 element columns per wave prefetching the next node plane, 1 =
-   16 x 16 tiles staged in LDS, 2 = register tiles without prefetch).  The
+   16 x 16 tiles staged in LDS, 2 = register tiles without prefetch, 3 = the
+   register tiles of variant 0 with each node plane transformed once, plane
+   contributions summed in the transformed basis and range-checked buffer
+   accesses; levels whose vectors exceed 1 GiB run variant 0 instead).  The
    first fields describe the apply in the precision of the multigrid cycle,
    the wht64_* fields the FP64 apply of the outer solvers (tuned separately
-   in mixed precision, equal to the first ones otherwise). */
+   in mixed precision on plain products K x, the only FP64 use of the fine
+   apply there; equal to the first ones otherwise). */
 typedef struct {
     int wht_zchunk;
     int stencil_cols;
@@ -91,6 +95,8 @@ typedef struct {
     float wht64_ms[5];
     float wht64_lds_ms[5];
     float wht64_nopf_ms[5];
+    float wht_v3_ms[5];
+    float wht64_v3_ms[5];
 } mlb_tune_info;
 
 /* Problem description (copied by mlb_create). */
@@ -211,12 +217,12 @@ int mlb_sensitivities_dev(mlb_ctx* ctx, double* dJ, double* dlam, mlb_solve_info
                           void* stream);
 
 /* Tile parameters of the fine apply (pencil length in node planes, 1..64;
-   3D variant 0, 1 or 2 as in mlb_tune_info, -1 keeps it) and of the stencil
+   3D variant 0..3 as in mlb_tune_info, -1 keeps it) and of the stencil
    applies (columns per thread, 1..12); 0 keeps a value; both precisions are
    set.  For a given variant the operator applies give bitwise the same
-   results for every pencil length and column count; the two variants sum a
-   node's element contributions in different orders (results agree to
-   rounding).  Dot products fused into the fine apply group their partial
+   results for every pencil length and column count; variants 0 and 2 agree
+   bitwise, variants 1 and 3 sum a node's element contributions in other
+   orders (results agree to rounding).  Dot products fused into the fine apply group their partial
    sums by tile, so solver iterates may differ in the last bits. */
 int mlb_set_tiles(mlb_ctx* ctx, int wht_zchunk, int stencil_cols, int wht_variant);
 /* Times Jacobi sweeps of ncols (<= 32) columns on the current hierarchy for

@@ -1297,8 +1297,12 @@ int time_ms(mlb_ctx* c, int reps, F f, float* ms) {
 // multigrid cycle, on Jacobi sweeps (the dominant launches), and keeps the
 // fastest of each.
 template <typename T>
-int autotune_t(mlb_ctx* c, int ncols, bool stencils, int* zout, int* vout, float* ms_reg, float* ms_lds,
-               float* ms_nopf) {
+// Times the fine apply for every variant and pencil length, in `mode`
+// (Jacobi sweeps for the multigrid cycle, plain products for the FP64
+// operator of the outer solvers in mixed precision), and keeps the fastest;
+// with `stencils`, also the stencil applies of level 2.
+int autotune_t(mlb_ctx* c, int ncols, bool stencils, int mode, int* zout, int* vout, float* ms_reg, float* ms_lds,
+               float* ms_nopf, float* ms_v3) {
     Level& l1 = c->lv[0];
     T* x = lbuf<T>(l1, 1);
     T* y = lbuf<T>(l1, 2);
@@ -1310,17 +1314,17 @@ int autotune_t(mlb_ctx* c, int ncols, bool stencils, int* zout, int* vout, float
         HIPC(hipMemcpyAsync(x + (int64_t)q * l1.n, src, sizeof(T) * l1.n, hipMemcpyDeviceToDevice, c->st));
         HIPC(hipMemcpyAsync(r + (int64_t)q * l1.n, src, sizeof(T) * l1.n, hipMemcpyDeviceToDevice, c->st));
     }
-    const int zc[] = {4, 6, 8, 12, 16};
+    const int zc[] = {4, 6, 8, 10, 12};
     float best = 1e30f;
     int bz = c->wz[tix<T>()], bv = c->wv[tix<T>()];
-    const int nvar = c->dim == 3 ? 3 : 1;
+    const int nvar = c->dim == 3 ? 4 : 1;
     for (int v = 0; v < nvar; ++v)
         for (int i = 0; i < 5; ++i) {
             c->wz[tix<T>()] = zc[i];
             c->wv[tix<T>()] = v;
             float ms = 0.f;
-            CHK(time_ms(c, 5, [&] { apply_K<T>(c, 1, ncols, x, y, kModeJacobi, r, nullptr); }, &ms));
-            (v == 0 ? ms_reg : v == 1 ? ms_lds : ms_nopf)[i] = ms;
+            CHK(time_ms(c, 5, [&] { apply_K<T>(c, 1, ncols, x, y, mode, r, nullptr); }, &ms));
+            (v == 0 ? ms_reg : v == 1 ? ms_lds : v == 2 ? ms_nopf : ms_v3)[i] = ms;
             if (ms < best) best = ms, bz = zc[i], bv = v;
         }
     c->wz[tix<T>()] = bz;
@@ -1784,9 +1788,9 @@ int mlb_coarse_modes_dev(mlb_ctx* c, int k, double* Psi, void* stream) {
 int mlb_set_tiles(mlb_ctx* c, int wht_zchunk, int stencil_cols, int wht_variant) {
     if (!c) return MLB_EINVAL;
     if (wht_zchunk < 0 || wht_zchunk > 64 || stencil_cols < 0 || stencil_cols > 12 || wht_variant < -1 ||
-        wht_variant > 2)
+        wht_variant > 3)
         return fail(c, MLB_EINVAL,
-                    "tile parameters out of range (z chunk 1..64, stencil columns 1..12, variant -1..2)");
+                    "tile parameters out of range (z chunk 1..64, stencil columns 1..12, variant -1..3)");
     if (wht_zchunk > 0) c->wz[0] = c->wz[1] = wht_zchunk;
     if (wht_variant >= 0) c->wv[0] = c->wv[1] = wht_variant;
     if (stencil_cols > 0) c->nb_cbmax = stencil_cols;
@@ -1802,19 +1806,20 @@ int mlb_autotune(mlb_ctx* c, int ncols, mlb_tune_info* info, void* stream) {
     drop_graphs(c);
     mlb_tune_info t{};
     if (c->d.precision == MLB_MIXED) {
-        CHK(autotune_t<float>(c, ncols, true, &t.wht_zchunk, &t.wht_variant, t.wht_ms, t.wht_lds_ms,
-                              t.wht_nopf_ms));
-        CHK(autotune_t<double>(c, ncols, false, &t.wht64_zchunk, &t.wht64_variant, t.wht64_ms, t.wht64_lds_ms,
-                               t.wht64_nopf_ms));
+        CHK(autotune_t<float>(c, ncols, true, kModeJacobi, &t.wht_zchunk, &t.wht_variant, t.wht_ms, t.wht_lds_ms,
+                              t.wht_nopf_ms, t.wht_v3_ms));
+        CHK(autotune_t<double>(c, ncols, false, kModeY, &t.wht64_zchunk, &t.wht64_variant, t.wht64_ms, t.wht64_lds_ms,
+                               t.wht64_nopf_ms, t.wht64_v3_ms));
     } else {
-        CHK(autotune_t<double>(c, ncols, true, &t.wht_zchunk, &t.wht_variant, t.wht_ms, t.wht_lds_ms,
-                               t.wht_nopf_ms));
+        CHK(autotune_t<double>(c, ncols, true, kModeJacobi, &t.wht_zchunk, &t.wht_variant, t.wht_ms, t.wht_lds_ms,
+                               t.wht_nopf_ms, t.wht_v3_ms));
         t.wht64_zchunk = t.wht_zchunk;
         t.wht64_variant = t.wht_variant;
         for (int i = 0; i < 5; ++i) {
             t.wht64_ms[i] = t.wht_ms[i];
             t.wht64_lds_ms[i] = t.wht_lds_ms[i];
             t.wht64_nopf_ms[i] = t.wht_nopf_ms[i];
+            t.wht64_v3_ms[i] = t.wht_v3_ms[i];
         }
     }
     t.stencil_cols = c->nb_cbmax;

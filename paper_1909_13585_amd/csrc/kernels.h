@@ -35,7 +35,9 @@ void launch_restrict_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf
 // ---- element-centric Walsh-Hadamard apply (kernels_wht.hip)
 // variant (3D): 0 register tiles of 8 x 8 element columns per wave with the
 // next node plane prefetched, 1 tiles of 16 x 16 columns per block staged in
-// LDS, 2 register tiles without prefetch (fewer registers, more waves)
+// LDS, 2 register tiles without prefetch (fewer registers, more waves), 3
+// register tiles with per-plane transforms and buffer accesses (levels whose
+// vectors exceed 1 GiB run variant 0)
 int64_t apply_wht_blocks(int dim, const Geo& g, int zchunk, int variant);
 template <typename T>
 void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, const T* blocks, int ncols,

@@ -296,6 +296,316 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(PF || 
 }
 
 // ---------------------------------------------------------------------------
+// 3D, variant 3: the wave tiles of k_apply_wht3 with far fewer instructions
+// per element layer (the register-tile kernels are bound by instruction
+// issue, not by memory):
+//  - the 8-point transform factors as H8 = H2 (z) x H4 (xy), so each node
+//    plane is transformed over its 4 column corners once, when it arrives,
+//    and an element's transform is the sum and the difference of its two
+//    planes' transforms;
+//  - the part of an element's result that falls on its lower plane and the
+//    part the element below put on the same plane are added in the
+//    transformed basis, and one inverse 4-point transform per plane gives
+//    the corner values;
+//  - the element modulus scales the 9 block coefficients instead of the 21
+//    nonzero outputs;
+//  - loads and stores are buffer operations with 32-bit byte offsets: a lane
+//    whose node column lies outside the grid, and a plane or element layer
+//    outside the box, carry offsets beyond the buffer's size, so the
+//    hardware range check returns zeros (and drops stores of lanes that own
+//    no node) without per-value selects;
+//  - Dirichlet masks of inputs that may be nonzero at fixed DOFs are applied
+//    only in waves that see a fixed DOF (wave-uniform branch).
+// Memory schedule of a step: 0 stores at the end of the step, loads placed
+// by the compiler; 1 stores of plane ke issued at the start of step ke + 1;
+// 2 as 1, with every load of the step issued before its arithmetic.
+#ifndef MLB_WHT3R_SCHED
+#define MLB_WHT3R_SCHED 2
+#endif
+constexpr int kW3rSched = MLB_WHT3R_SCHED;
+constexpr uint32_t kOffLane = 0x80000000u;    // offset of a lane outside the grid
+constexpr uint32_t kOffPlane = 0x40000000u;   // offset of a plane/layer outside the box
+constexpr uint32_t kMaxBufBytes = 0x40000000u;  // largest array the offsets can address
+constexpr int kBufFlags = 0x00020000;          // buffer descriptor word 3 (raw 32-bit data)
+
+template <typename T>
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const T* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, (int)bytes, kBufFlags);
+}
+__device__ inline void buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t off, double& v) {
+    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+}
+__device__ inline void buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t off, float& v) {
+    v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+}
+__device__ inline void buf_store(__amdgpu_buffer_rsrc_t rs, uint32_t off, double v) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), rs, (int)off, 0, 0);
+}
+__device__ inline void buf_store(__amdgpu_buffer_rsrc_t rs, uint32_t off, float v) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b32(rs, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, v), rs, (int)off, 0, 0);
+}
+
+__device__ inline double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// wht_epilogue with an explicit fused multiply-add (no contraction choices)
+template <typename T, int MODE>
+__device__ inline T wht_epilogue_fixed(T ax, T xown, T rr, T di, T omega) {
+#pragma clang fp contract(off)
+    if (MODE == kModeY) return ax;
+    if (MODE == kModeResidual) return rr - ax;
+    return fmat(omega * di, rr - ax, xown);
+}
+
+// The 3D blocks of element_apply with coefficients already scaled by the
+// element modulus: s = E * (o0, d0 - o0, o7, d7 - o7, e1, f1, g2d, g2o, h2).
+// The translation entries u[c][0] are left untouched (they are zero).
+// Contraction is off and the fused multiply-adds are explicit, so every
+// inlined copy rounds the same way.
+template <typename T>
+__device__ inline void blocks3_scaled(const T (&s)[9], T (&u)[3][8]) {
+#pragma clang fp contract(off)
+    {
+        const T a = u[0][1], b = u[1][2], c3 = u[2][4];
+        const T sum = s[0] * ((a + b) + c3);
+        u[0][1] = fmat(s[1], a, sum);
+        u[1][2] = fmat(s[1], b, sum);
+        u[2][4] = fmat(s[1], c3, sum);
+    }
+    {
+        const T a = u[0][6], b = u[1][5], c3 = u[2][3];
+        const T sum = s[2] * ((a + b) + c3);
+        u[0][6] = fmat(s[3], a, sum);
+        u[1][5] = fmat(s[3], b, sum);
+        u[2][3] = fmat(s[3], c3, sum);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        const int i1 = (1 << c) | (1 << c1), i2 = (1 << c) | (1 << c2);
+        const T v1 = u[c1][i1], v2 = u[c2][i2];
+        u[c1][i1] = fmat(s[4], v1, s[5] * v2);
+        u[c2][i2] = fmat(s[5], v1, s[4] * v2);
+        const T w1 = u[c1][1 << c2], w2 = u[c2][1 << c1];
+        u[c1][1 << c2] = fmat(s[6], w1, s[7] * w2);
+        u[c2][1 << c1] = fmat(s[7], w1, s[6] * w2);
+        u[c][7] = s[8] * u[c][7];
+    }
+}
+
+template <typename T, int MODE, bool DOT, bool CLEAN>
+__global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(MLB_WHT3_WAVES, 8))) void k_apply_wht3r(
+    Geo g, int kz_chunk, int ntiles_x, int ntiles_y, const T* __restrict__ E, const uint8_t* __restrict__ nmask,
+    WhtBlocks<T> B, int ncols, int64_t ld, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ r,
+    const T* __restrict__ dinv, T omega, double* __restrict__ part) {
+    // no contraction: the loop is unrolled twice and both copies must round
+    // alike, so that results do not depend on the pencil length
+#pragma clang fp contract(off)
+    __shared__ double sh[16];
+    const int lane = threadIdx.x;
+    const int tx = lane & 7, ty = lane >> 3;
+    const int64_t per_xcd = gridDim.x / kXcd3;
+    const int64_t bl = (blockIdx.x % kXcd3) * per_xcd + blockIdx.x / kXcd3;
+    // the wave's index in its block, as a wave-uniform value: everything
+    // derived from it (pencil, loop bounds, plane offsets) stays scalar
+    const int wib = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int64_t tile = bl * kW3 + wib;
+    const int64_t ntile_xy = (int64_t)ntiles_x * ntiles_y;
+    const int tzc = (int)(tile / ntile_xy);
+    const int txy = (int)(tile % ntile_xy);
+    const int ie = (txy % ntiles_x) * (kWT - 1) - 1 + tx;
+    const int je = (txy / ntiles_x) * (kWT - 1) - 1 + ty;
+    const int kz0 = tzc * kz_chunk;
+    const int kend = min(kz0 + kz_chunk, g.nnz);
+    const bool col_ok = ie >= 0 && ie < g.nx && je >= 0 && je < g.ny;
+    const bool owner = tx >= 1 && ty >= 1 && ie >= 0 && je >= 0 && ie <= g.nx && je <= g.ny;
+    const uint32_t plane = (uint32_t)g.nnx * (uint32_t)g.nny;
+    const uint32_t xnode = 3u * sizeof(T);                 // bytes per node
+    const uint32_t xplane = plane * xnode;                 // bytes per node plane
+    const uint32_t eplane = (uint32_t)g.nx * (uint32_t)g.ny * sizeof(T);
+    const uint32_t xbytes = (uint32_t)g.nodes * xnode;
+    uint32_t vo[4], mo[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int ii = ie + (q & 1), jj = je + (q >> 1);
+        const bool ok = ii >= 0 && ii < g.nnx && jj >= 0 && jj < g.nny;
+        const uint32_t nd = (uint32_t)ii + (uint32_t)g.nnx * (uint32_t)jj;
+        vo[q] = ok ? nd * xnode : kOffLane;
+        mo[q] = ok ? nd : kOffLane;
+    }
+    const uint32_t eo = col_ok ? ((uint32_t)ie + (uint32_t)g.nx * (uint32_t)je) * sizeof(T) : kOffLane;
+    const __amdgpu_buffer_rsrc_t rE = buf_rsrc(E, (uint32_t)g.m * sizeof(T));
+    const __amdgpu_buffer_rsrc_t rM = buf_rsrc(nmask, (uint32_t)g.nodes);
+    const __amdgpu_buffer_rsrc_t rD = buf_rsrc(dinv, MODE == kModeJacobi ? xbytes : 0u);
+    const T dd0 = B.v[0] - B.v[1], dd7 = B.v[2] - B.v[3];
+    const int64_t nblk = gridDim.x;
+    // byte offsets of node plane kk / element layer ke (out of range: zeros)
+    auto poff = [&](int kk) -> uint32_t { return kk >= 0 && kk < g.nnz ? (uint32_t)kk * xplane : kOffPlane; };
+    auto moff = [&](int kk) -> uint32_t { return kk >= 0 && kk < g.nnz ? (uint32_t)kk * plane : kOffPlane; };
+    auto eoff = [&](int ke) -> uint32_t { return ke >= 0 && ke < g.nz ? (uint32_t)ke * eplane : kOffPlane; };
+    for (int col = 0; col < ncols; ++col) {
+        const __amdgpu_buffer_rsrc_t rX = buf_rsrc(x + col * ld, xbytes);
+        const __amdgpu_buffer_rsrc_t rY = buf_rsrc(y + col * ld, xbytes);
+        const __amdgpu_buffer_rsrc_t rR = buf_rsrc(r + col * ld, MODE == kModeY ? 0u : xbytes);
+        double dsum = 0.0;
+        auto load_plane = [&](int kk, T (&v)[3][4], uint8_t (&mk)[4]) {
+            const uint32_t po = poff(kk), pm = moff(kk);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) buf_load(rX, vo[q] + po + c * (uint32_t)sizeof(T), v[c][q]);
+                if (!CLEAN || q == 0) mk[q] = __builtin_amdgcn_raw_buffer_load_b8(rM, (int)(mo[q] + pm), 0, 0);
+            }
+        };
+        // Walsh-Hadamard transform of a plane over the 4 column corners
+        // (values at fixed DOFs taken as zero)
+        auto transform = [&](T (&v)[3][4], const uint8_t (&mk)[4], T (&h)[3][4]) {
+            if (!CLEAN) {
+                if (__any((mk[0] | mk[1] | mk[2] | mk[3]) != 0)) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            if ((mk[q] >> c) & 1) v[c][q] = T(0);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) h[c][q] = v[c][q];
+                wht<2, T>(h[c]);
+            }
+        };
+        // Each step works on element layer ke between node planes ke (lo)
+        // and ke + 1 (hi), writes plane ke, and transforms plane ke + 2 into
+        // the slot that plane ke leaves free; the loop is unrolled twice so
+        // that the two slots swap roles instead of being copied.
+        T hA[3][4], hB[3][4], carry[3][4], oA[3], oB[3], EA, EB;
+        uint8_t mA, mB;
+        {
+            T v[3][4];
+            uint8_t mk[4];
+            load_plane(kz0 - 1, v, mk);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) oA[c] = v[c][0];
+            mA = mk[0];
+            transform(v, mk, hA);
+            load_plane(kz0, v, mk);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) oB[c] = v[c][0];
+            mB = mk[0];
+            transform(v, mk, hB);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) carry[c][q] = T(0);
+        buf_load(rE, eo + eoff(kz0 - 1), EA);
+        // Results of plane ke are stored at the start of step ke + 1.  Loads
+        // and stores share one completion counter here, and a wait for a
+        // load issued before a store still in flight waits for that store
+        // too; issued after the step's first wait (the modulus) and before
+        // its loads, the stores complete during the element arithmetic.
+        T py[3] = {T(0), T(0), T(0)};
+        uint32_t pod = kOffLane;
+        auto flush = [&]() {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) buf_store(rY, pod + c * (uint32_t)sizeof(T), py[c]);
+        };
+        auto step = [&](int ke, T (&hl)[3][4], const T (&hh)[3][4], T (&olo)[3], uint8_t& mlo, const T& Ecur,
+                        T& Enext) {
+            T s[9];
+            s[0] = Ecur * B.v[1];
+            s[1] = Ecur * dd0;
+            s[2] = Ecur * B.v[3];
+            s[3] = Ecur * dd7;
+#pragma unroll
+            for (int i = 4; i < 9; ++i) s[i] = Ecur * B.v[i];
+            if (kW3rSched >= 1) {
+                __builtin_amdgcn_sched_barrier(0);
+                flush();
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // next plane, next modulus, and this plane's right-hand data
+            T pf[3][4];
+            uint8_t mpf[4];
+            load_plane(ke + 2, pf, mpf);
+            buf_load(rE, eo + eoff(ke + 1), Enext);
+            const bool out = ke >= kz0;   // wave-uniform
+            const uint32_t od = owner && out ? vo[0] + poff(ke) : kOffLane;
+            T rr[3], di[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                rr[c] = T(0);
+                di[c] = T(0);
+                if (MODE != kModeY) buf_load(rR, od + c * (uint32_t)sizeof(T), rr[c]);
+                if (MODE == kModeJacobi) buf_load(rD, od + c * (uint32_t)sizeof(T), di[c]);
+            }
+            // all of the step's loads are issued before its arithmetic
+            if (kW3rSched >= 2) __builtin_amdgcn_sched_barrier(0);
+            T u[3][8];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    u[c][k] = hl[c][k] + hh[c][k];
+                    u[c][k + 4] = hl[c][k] - hh[c][k];
+                }
+            blocks3_scaled<T>(s, u);
+            // plane ke: this element's lower half plus the carried upper half
+            // of the element below, in the transformed basis; then back to
+            // the 4 corners
+            T a[3][4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a[c][0] = carry[c][0] + u[c][4];
+                carry[c][0] = -u[c][4];
+#pragma unroll
+                for (int k = 1; k < 4; ++k) {
+                    a[c][k] = carry[c][k] + (u[c][k] + u[c][k + 4]);
+                    carry[c][k] = u[c][k] - u[c][k + 4];
+                }
+                wht<2, T>(a[c]);
+            }
+            // (also in the first step of a pencil, whose plane is not ours:
+            // its results go to an out-of-range offset, and a branch here
+            // would let the compiler sink the right-hand loads into it)
+            if (kW3rSched >= 2 || out) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T q0 = a[c][0] + shfl_up_w(a[c][1], 1, kWT);
+                    const T q1 = a[c][2] + shfl_up_w(a[c][3], 1, kWT);
+                    const T acc = q0 + shfl_up_w(q1, kWT, 64);
+                    const T xown = olo[c];
+                    const T ax = (mlo >> c) & 1 ? xown : acc;
+                    py[c] = wht_epilogue_fixed<T, MODE>(ax, xown, rr[c], di[c], omega);
+                    if (DOT && owner && out) dsum += (double)xown * (double)ax;
+                }
+            }
+            pod = od;
+            if (kW3rSched == 0) flush();
+            // plane ke + 2 takes the slot of plane ke
+#pragma unroll
+            for (int c = 0; c < 3; ++c) olo[c] = pf[c][0];
+            mlo = mpf[0];
+            transform(pf, mpf, hl);
+        };
+        for (int ke = kz0 - 1; ke < kend; ke += 2) {
+            step(ke, hA, hB, oA, mA, EA, EB);
+            if (ke + 1 >= kend) break;
+            step(ke + 1, hB, hA, oB, mB, EB, EA);
+        }
+        if (kW3rSched >= 1) flush();
+        if (DOT) {
+            const double bs = wht_block_sum(dsum, sh);
+            if (lane == 0 && threadIdx.y == 0) part[col * nblk + blockIdx.x] = bs;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 3D, LDS variant: one block of 16 x 16 threads is a tile of 16 x 16 element
 // columns (tiles overlap by one column/row, the 15 x 15 interior node columns
 // are owned) walking a pencil of element layers along z.  Each node plane of
@@ -628,9 +938,16 @@ void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, c
     dim3 gr, b;
     int ch, ntx, nty;
     wht_geometry(dim, g, zchunk, variant, gr, b, ch, ntx, nty);
+    // variant 3 addresses each array with 32-bit byte offsets
+    if (dim == 3 && variant == 3 &&
+        ((uint64_t)g.nodes * 3 * sizeof(T) > kMaxBufBytes || (uint64_t)g.m * sizeof(T) > kMaxBufBytes))
+        variant = 0;
 #define MLB_L3C(M, D, C)                                                                                          \
     do {                                                                                                          \
-        if (variant == 2)                                                                                         \
+        if (variant == 3)                                                                                         \
+            hipLaunchKernelGGL((k_apply_wht3r<T, M, D, C>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B, ncols, ld, \
+                               x, y, r, dinv, omega, dot_part);                                                   \
+        else if (variant == 2)                                                                                    \
             hipLaunchKernelGGL((k_apply_wht3<T, M, D, C, false>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B,      \
                                ncols, ld, x, y, r, dinv, omega, dot_part);                                        \
         else                                                                                                      \
