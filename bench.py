@@ -25,12 +25,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the fine FP64 1-column apply, per 3D variant (0
-# register tiles, 1 LDS tiles): rocprofv3 FETCH_SIZE x 1.99977 + WRITE_SIZE x
-# 1.0 (factors from a 256 MiB calibration copy), KiB per dispatch, from
+# register tiles, 1 LDS tiles, 2 register tiles without prefetch, 3 register
+# tiles with per-plane transforms): rocprofv3 FETCH_SIZE x (copy factor,
+# 1.99977 and 1.99963 in the two runs) + WRITE_SIZE x 1.0 (factors from a
+# 256 MiB calibration copy), KiB per dispatch, from
 # profiles/fine_apply_h8_192x64x64_hbm_counters.md; None where the counters
 # were not taken for the current kernel.
 FINE_KERNELS = {0: "k_apply_wht3", 1: "k_apply_wht3_lds", 2: "k_apply_wht3 (no prefetch)", 3: "k_apply_wht3r"}
-TRAFFIC_BYTES = {0: (17363 * 1.99977 + 19153) * 1024, 1: None, 2: None, 3: None}
+TRAFFIC_BYTES = {0: (17363 * 1.99977 + 19153) * 1024, 1: None, 2: None, 3: (17031 * 1.99963 + 19169) * 1024}
 
 
 def parse():
