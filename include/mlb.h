@@ -125,6 +125,12 @@ typedef struct {
     int block_cg;         /* multi-column solves: 1 = block CG (default), 2 = column-wise CG */
     int eig_sweeps;       /* multigrid sweeps per coarse-eigensolver preconditioner application (default 3) */
     int graphs;           /* 1 = replay each multigrid cycle as a captured HIP graph (default), 2 = launch eagerly */
+    int pinvit_steps;     /* preconditioned inverse iteration steps on the fine modes after their
+                             Rayleigh-Ritz (App. A, eq. PInvIt-GeneralInteration): each Ritz vector
+                             takes phi_i <- phi_i - M^-1 (K + lam~_i G) phi_i with M^-1 one multigrid
+                             cycle of the static solves and lam~_i its Ritz value, then the block is
+                             replaced by its Ritz vectors again.  > 0 sets the count (at most 64),
+                             < 0 sets none (the default), 0 keeps the current value */
 } mlb_opts;
 
 /* Per-call solver report; for blocks, the worst column is reported. */
@@ -148,6 +154,9 @@ typedef struct {
     int coarse_warm_used;       /* 1 if a MLB_WARM_COARSE block started the coarse eigensolve
                                    (it is dropped for the plain start when its initial Ritz
                                    residual is worse or the block is rank deficient) */
+    int pinvit_steps;           /* preconditioned inverse iteration steps taken (mlb_opts) */
+    double lambda1_before_pinvit; /* lam~_1 of the first Rayleigh-Ritz, before those steps */
+    double seconds_pinvit;      /* wall time of those steps */
 } mlb_eig_info;
 
 /* ---- lifetime --------------------------------------------------------- */
@@ -225,6 +234,16 @@ int mlb_sensitivities_dev(mlb_ctx* ctx, double* dJ, double* dlam, mlb_solve_info
    orders (results agree to rounding).  Dot products fused into the fine apply group their partial
    sums by tile, so solver iterates may differ in the last bits. */
 int mlb_set_tiles(mlb_ctx* ctx, int wht_zchunk, int stencil_cols, int wht_variant);
+/* Jacobi weights omega_j of the multigrid smoother on levels 1 .. nlevels
+   (nlevels <= the number of levels - 1; the coarsest level is solved
+   exactly).  mlb_set_density* estimates them as jacobi_omega / (1.05 rho_j)
+   with rho_j from 12 power iterations on D_j^-1 A_j; mlb_set_omegas replaces
+   them (each in (0, 2 / rho_j) for a convergent smoother) until the next
+   mlb_set_density*, so that a cycle can be reproduced exactly elsewhere.
+   MLB_ESTATE before the densities are set, MLB_EINVAL for a weight that is
+   not positive and finite. */
+int mlb_set_omegas(mlb_ctx* ctx, int nlevels, const double* omega);
+int mlb_get_omegas(const mlb_ctx* ctx, int nlevels, double* omega);
 /* Times Jacobi sweeps of ncols (<= 32) columns on the current hierarchy for
    each candidate tile and keeps the fastest (needs mask and densities). */
 int mlb_autotune(mlb_ctx* ctx, int ncols, mlb_tune_info* info, void* stream);

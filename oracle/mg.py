@@ -7,11 +7,11 @@ App. A (eq. PInvIt-GeneralInteration) improves the fine-scale modes after the
 Ritz step by preconditioned inverse iteration: every vector of the block takes
 steps
 
-    phi <- phi - P^-1 (K + lambda~_1 G) phi
+    phi_i <- phi_i - P^-1 (K + lambda~_i G) phi_i
 
-with P the multigrid preconditioner of the static solves and lambda~_1 the
-smallest current Ritz value; eq. errorEstimate states that the Rayleigh
-quotients then decrease monotonically towards the eigenvalues.
+with P the multigrid preconditioner of the static solves and lambda~_i the
+current Rayleigh quotient of phi_i; eq. errorEstimate states that the
+Rayleigh quotients then decrease monotonically towards the eigenvalues.
 
 Readings (the paper names the ingredients, not their arrangement):
   * P^-1 is one V(nu, nu)-cycle on the hierarchy of the static solves:
@@ -20,9 +20,14 @@ Readings (the paper names the ingredients, not their arrangement):
     the first pre-smoothing sweep starts from zero, nu - 1 more follow, then
     one coarse-grid correction (restriction = interpolation^T) and nu
     post-smoothing sweeps; the coarsest level is solved exactly.
+  * The printed step shifts every vector by lambda~_1, but the text calls it
+    the gradient step of R_i, whose shift is R_i itself, and states the
+    convergence estimate for every R_i.  A common shift lambda~_1 drives the
+    whole block towards the first mode and raises the higher Ritz values;
+    the shift is taken as each vector's own Ritz value lambda~_i.
   * After each step the block is replaced by its Ritz vectors on its span
-    (the Rayleigh-Ritz of Sec. 2.1 step 4), so lambda~_1 is always the
-    smallest Ritz value of the current block.
+    (the Rayleigh-Ritz of Sec. 2.1 step 4), so lambda~_i is the i-th Ritz
+    value of the current block.
 """
 from __future__ import annotations
 
@@ -94,17 +99,17 @@ class VCycle:
 
 
 def pinvit(Kff, Gff, Phi, lam, apply_P, steps):
-    """``steps`` preconditioned inverse iteration steps on the block Phi (free
-    DOFs), each followed by Rayleigh-Ritz.  Returns the final Ritz values and
-    vectors and lambda~_1 before and after every step."""
-    hist = [float(lam[0])]
+    """``steps`` preconditioned inverse iteration steps on the Ritz block Phi
+    (free DOFs, columns paired with the Ritz values lam), each followed by
+    Rayleigh-Ritz.  Returns the final Ritz values and vectors and the Ritz
+    values before and after every step."""
+    hist = [np.array(lam, dtype=np.float64)]
     q = Phi.shape[1]
     for _ in range(steps):
-        sigma = float(lam[0])
-        R = Kff @ Phi + sigma * (Gff @ Phi)
+        R = Kff @ Phi + (Gff @ Phi) * np.asarray(lam)[None, :]
         Phi = Phi - apply_P(R)
         lam, Phi = rayleigh_ritz(Kff, Gff, Phi)
         if len(lam) < q:
             raise ValueError("fewer than q positive Ritz values after a step")
-        hist.append(float(lam[0]))
+        hist.append(np.array(lam))
     return lam, Phi, hist

@@ -38,7 +38,7 @@ class MlbDesc(C.Structure):
 class MlbOpts(C.Structure):
     _fields_ = [("smooth_steps", C.c_int), ("jacobi_omega", C.c_double), ("eig_guard", C.c_int),
                 ("eig_max_it", C.c_int), ("check_every", C.c_int), ("seed", C.c_uint64), ("cycle", C.c_int),
-                ("block_cg", C.c_int), ("eig_sweeps", C.c_int), ("graphs", C.c_int)]
+                ("block_cg", C.c_int), ("eig_sweeps", C.c_int), ("graphs", C.c_int), ("pinvit_steps", C.c_int)]
 
 
 class MlbSolveInfo(C.Structure):
@@ -49,7 +49,8 @@ class MlbSolveInfo(C.Structure):
 class MlbEigInfo(C.Structure):
     _fields_ = [("coarse_iterations", C.c_int), ("coarse_residual", C.c_double), ("coarse_gap", C.c_double),
                 ("fine_iterations", C.c_int), ("fine_true_residual", C.c_double), ("seconds_coarse", C.c_double),
-                ("seconds_fine", C.c_double), ("seconds_ritz", C.c_double), ("coarse_warm_used", C.c_int)]
+                ("seconds_fine", C.c_double), ("seconds_ritz", C.c_double), ("coarse_warm_used", C.c_int),
+                ("pinvit_steps", C.c_int), ("lambda1_before_pinvit", C.c_double), ("seconds_pinvit", C.c_double)]
 
 
 class MlbTuneInfo(C.Structure):
@@ -111,6 +112,8 @@ _SIGS = {
     "mlb_adjoint_rhs_dev": (_I, [_P, _I, _P, _P]),
     "mlb_set_tiles": (_I, [_P, _I, _I, _I]),
     "mlb_autotune": (_I, [_P, _I, C.POINTER(MlbTuneInfo), _P]),
+    "mlb_set_omegas": (_I, [_P, _I, _P]),
+    "mlb_get_omegas": (_I, [_P, _I, _P]),
     "mlb_solve_block_dev": (_I, [_P, _I, _P, _P, _D, _I, C.POINTER(MlbSolveInfo), _P]),
     # warm-start network kernels (include/mlb_nn.h)
     "mlb_nn_conv3d": (_I, [_I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P]),

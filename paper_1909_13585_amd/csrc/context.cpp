@@ -1181,29 +1181,51 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
     if (c->o.block_cg) CHK(bpcg(c, c->X2, c->Phi, k, c->tol_solve, c->max_it, false, &si));
     else CHK(pcg(c, c->X2, c->Phi, k, c->tol_solve, c->max_it, false, &si));
     const double t2 = now_s();
-    // step 4: Rayleigh-Ritz on span(Phi~)
-    apply_K<double>(c, 1, k, c->Phi, c->X1, kModeY, nullptr, nullptr);
-    apply_G(c, 1, k, c->Phi, c->X2);
-    std::vector<double> A, B;
-    CHK(gram2(c, n, k, c->Phi, k, c->X1, c->X2, A, B));
-    std::vector<double> A2(k * k), B2(k * k), ev(k), Y(k * k);
-    for (int a = 0; a < k; ++a)
-        for (int q = 0; q < k; ++q) {
-            A2[a * k + q] = 0.5 * (A[a + k * q] + A[q + k * a]);
-            B2[a * k + q] = -0.5 * (B[a + k * q] + B[q + k * a]);
+    // step 4: Rayleigh-Ritz on span(Phi~); then, optionally, preconditioned
+    // inverse iteration steps on the Ritz block (App. A, eq.
+    // PInvIt-GeneralInteration), each followed by Rayleigh-Ritz again:
+    // phi_i <- phi_i - M^-1 (K + lam~_i G) phi_i, M^-1 one multigrid cycle,
+    // each vector shifted by its own Ritz value (the gradient step of its
+    // Rayleigh quotient).  After each Ritz step Zo holds the Ritz vectors,
+    // R = K Zo, Qb = G Zo.
+    const int steps = c->o.pinvit_steps;
+    double lam1_before = 0.0, t_pinvit = 0.0;
+    for (int s = 0; s <= steps; ++s) {
+        if (s > 0) {
+            const double ts = now_s();
+            if (s == 1) lam1_before = c->lam[0];
+            for (int i = 0; i < k; ++i) c->hpin[i] = c->lam[i];
+            HIPC(hipMemcpyAsync(c->dlam_l, c->hpin, sizeof(double) * k, hipMemcpyHostToDevice, c->st));
+            launch_axpy_cols(n, k, n, c->dlam_l, 1.0, c->Qb, c->R, c->st);   // (K + lam~_i G) phi_i
+            CHK(precondition(c, 1, k, c->R, c->Zb));
+            launch_copy_cols(n, k, n, c->Zo, n, c->Phi, c->st);
+            launch_axpby((int64_t)n * k, -1.0, c->Zb, 1.0, c->Phi, c->st);
+            CHK(sync(c));
+            t_pinvit += now_s() - ts;
         }
-    if (!gen_eig(k, A2.data(), B2.data(), ev.data(), Y.data()))
-        return fail(c, MLB_EBREAKDOWN, "Rayleigh-Ritz: Phi~^T K Phi~ not positive definite");
-    if (!(ev[k - 1] > 0.0)) return fail(c, MLB_ENOPOS, "fewer than k positive Ritz values");
-    c->lam.assign(k, 0.0);
-    for (int i = 0; i < k; ++i) c->lam[i] = 1.0 / ev[i];
-    std::vector<double> C(k * k);
-    for (int a = 0; a < k; ++a)
-        for (int q = 0; q < k; ++q) C[a + k * q] = Y[a * k + q];
-    CHK(upload_cm(c, c->cbuf, C));
-    launch_gemm_small(n, k, n, c->Phi, k, c->cbuf, n, c->Zo, c->st);
-    launch_gemm_small(n, k, n, c->X1, k, c->cbuf, n, c->R, c->st);
-    launch_gemm_small(n, k, n, c->X2, k, c->cbuf, n, c->Qb, c->st);
+        apply_K<double>(c, 1, k, c->Phi, c->X1, kModeY, nullptr, nullptr);
+        apply_G(c, 1, k, c->Phi, c->X2);
+        std::vector<double> A, B;
+        CHK(gram2(c, n, k, c->Phi, k, c->X1, c->X2, A, B));
+        std::vector<double> A2(k * k), B2(k * k), ev(k), Y(k * k);
+        for (int a = 0; a < k; ++a)
+            for (int q = 0; q < k; ++q) {
+                A2[a * k + q] = 0.5 * (A[a + k * q] + A[q + k * a]);
+                B2[a * k + q] = -0.5 * (B[a + k * q] + B[q + k * a]);
+            }
+        if (!gen_eig(k, A2.data(), B2.data(), ev.data(), Y.data()))
+            return fail(c, MLB_EBREAKDOWN, "Rayleigh-Ritz: Phi~^T K Phi~ not positive definite");
+        if (!(ev[k - 1] > 0.0)) return fail(c, MLB_ENOPOS, "fewer than k positive Ritz values");
+        c->lam.assign(k, 0.0);
+        for (int i = 0; i < k; ++i) c->lam[i] = 1.0 / ev[i];
+        std::vector<double> C(k * k);
+        for (int a = 0; a < k; ++a)
+            for (int q = 0; q < k; ++q) C[a + k * q] = Y[a * k + q];
+        CHK(upload_cm(c, c->cbuf, C));
+        launch_gemm_small(n, k, n, c->Phi, k, c->cbuf, n, c->Zo, c->st);
+        launch_gemm_small(n, k, n, c->X1, k, c->cbuf, n, c->R, c->st);
+        launch_gemm_small(n, k, n, c->X2, k, c->cbuf, n, c->Qb, c->st);
+    }
     std::memcpy(c->hpin, c->lam.data(), sizeof(double) * k);
     HIPC(hipMemcpyAsync(c->dlam_l, c->hpin, sizeof(double) * k, hipMemcpyHostToDevice, c->st));
     launch_axpy_cols(n, k, n, c->dlam_l, 1.0, c->Qb, c->R, c->st);   // (K + lam G) phi
@@ -1235,7 +1257,10 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         info->fine_true_residual = si.true_rel_residual;
         info->seconds_coarse = t1 - t0;
         info->seconds_fine = t2 - t1;
-        info->seconds_ritz = t3 - t2;
+        info->seconds_ritz = t3 - t2 - t_pinvit;
+        info->pinvit_steps = steps;
+        info->lambda1_before_pinvit = steps > 0 ? lam1_before : c->lam[0];
+        info->seconds_pinvit = t_pinvit;
     }
     return MLB_OK;
 }
@@ -1521,6 +1546,8 @@ int mlb_set_opts(mlb_ctx* c, const mlb_opts* o) {
     if (o->block_cg > 0) c->o.block_cg = o->block_cg == 1 ? 1 : 0;
     if (o->eig_sweeps > 0) c->o.eig_sweeps = std::min(o->eig_sweeps, 8);
     if (o->graphs > 0) c->o.graphs = o->graphs == 1 ? 1 : 2;
+    if (o->pinvit_steps > 0) c->o.pinvit_steps = std::min(o->pinvit_steps, 64);
+    else if (o->pinvit_steps < 0) c->o.pinvit_steps = 0;
     drop_graphs(c);
     if (o->jacobi_omega > 0 && c->has_density) {
         c->st = c->own;
@@ -1782,6 +1809,23 @@ int mlb_coarse_modes_dev(mlb_ctx* c, int k, double* Psi, void* stream) {
     c->st = pick(c, stream);
     const int64_t nl = c->lv[c->ell - 1].n;
     HIPC(hipMemcpyAsync(Psi, c->eS, sizeof(double) * nl * k, hipMemcpyDeviceToDevice, c->st));
+    return MLB_OK;
+}
+
+int mlb_set_omegas(mlb_ctx* c, int nlevels, const double* omega) {
+    if (!c || !omega || nlevels < 1 || nlevels > c->L - 1)
+        return c ? fail(c, MLB_EINVAL, "nlevels must be in 1 .. levels - 1") : MLB_EINVAL;
+    if (!c->has_density) return fail(c, MLB_ESTATE, "set the densities first");
+    for (int j = 0; j < nlevels; ++j)
+        if (!(omega[j] > 0.0) || !std::isfinite(omega[j])) return fail(c, MLB_EINVAL, "Jacobi weights must be positive");
+    for (int j = 0; j < nlevels; ++j) c->lv[j].omega = omega[j];
+    drop_graphs(c);
+    return MLB_OK;
+}
+
+int mlb_get_omegas(const mlb_ctx* c, int nlevels, double* omega) {
+    if (!c || !omega || nlevels < 1 || nlevels > c->L - 1) return MLB_EINVAL;
+    for (int j = 0; j < nlevels; ++j) omega[j] = c->lv[j].omega;
     return MLB_OK;
 }
 
