@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-instances", action="store_true",
                     help="skip the 32 independent 2D instances (batched vs one context at a time)")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-pinvit", action="store_true",
+                    help="skip the leg with preconditioned inverse iteration steps on the fine modes")
     ap.add_argument("--wht-variant", type=int, default=-1,
                     help="with --roofline-only: fine-apply variant to run (0 register tiles, 1 LDS tiles, "
                          "2 register tiles without prefetch, 3 register tiles with per-plane transforms)")
@@ -218,6 +220,30 @@ def batched_instances(reps=3):
             "max_rel_J_diff_vs_contexts": float(np.max(np.abs(np.asarray(Js) / J - 1)))}
 
 
+def pinvit_leg(ctx, k, n, tol_eig, lam0):
+    """Buckling with 1 and 2 preconditioned inverse iteration steps on the fine
+    modes after the multilevel Ritz step (same context, after the timed
+    analyses); reports their cost and how far the Ritz values drop."""
+    import numpy as np
+    import torch
+    Phi = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    out = {}
+    for s in (1, 2):
+        ctx.set_opts(pinvit_steps=s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, ei = ctx.buckling_dev(k, Phi, tol_eig=tol_eig)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rel = (np.asarray(lam0) - np.asarray(lam)) / np.asarray(lam0)
+        out[f"steps_{s}"] = {"buckling_s": t, "pinvit_s": ei["seconds_pinvit"],
+                             "lambda": [float(v) for v in lam],
+                             "rel_drop_min": float(rel.min()), "rel_drop_max": float(rel.max()),
+                             "lambda1_before": ei["lambda1_before_pinvit"]}
+    ctx.set_opts(pinvit_steps=-1)
+    return out
+
+
 def apply_roofline(ctx, n, m, reps, ncols=1):
     """Fine-level H8 apply (public entry, FP64), HIP events on the stream the
     library launches on (the caller's current stream)."""
@@ -295,6 +321,7 @@ def main():
     var64 = ctx.tune["wht64_variant"] if ctx.tune else 0
     apply_ms, alg_bytes = apply_roofline(ctx, n, m, args.apply_reps, 1)
     achieved = alg_bytes / (apply_ms * 1e-3) / 1e9
+    pinv = None if args.no_pinvit else pinvit_leg(ctx, k, n, args.tol_eig, lam)
     ctx.close()
 
     learned = None
@@ -360,6 +387,7 @@ def main():
                     "static": si["seconds"], "adjoint": ai["seconds"]},
         "fp64_reference": fp64,
         "learned_warm_start": learned,
+        "pinvit_refinement": pinv,
         "batched_instances": inst,
         "roofline": {"bound": "hbm", "kernel": f"{FINE_KERNELS[var64]}<double> (fine H8 K apply, 1 column)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
