@@ -16,9 +16,11 @@ problems with buckling constraints at the cost of linear analyses"):
                    block solve, Rayleigh-Ritz (Alg. 1; Sec. 2.1 steps 1-4)
   * ``sens``       compliance and buckling-factor sensitivities with the
                    adjoint system (eqs. SensitivityLambda and AdjointSystem)
-  * ``mg``         the multigrid V-cycle and the preconditioned inverse
+  * ``mg``         the multigrid V-cycle, the preconditioned inverse
                    iteration on the fine modes (App. A, eqs.
-                   PInvIt-GeneralInteration and errorEstimate)
+                   PInvIt-GeneralInteration and errorEstimate) and the
+                   intermediate-level Kaczmarz smoothing and Ritz steps of
+                   Alg. 2
 
 Every function cites the passage it follows.  Readings of passages that are
 silent or garbled are listed in each module header.

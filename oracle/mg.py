@@ -35,7 +35,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from . import levels as lv
-from .lba import rayleigh_ritz
+from .lba import generalized_lowest_positive, rayleigh_ritz
 
 
 def _free(mask):
@@ -113,3 +113,116 @@ def pinvit(Kff, Gff, Phi, lam, apply_P, steps):
             raise ValueError("fewer than q positive Ritz values after a step")
         hist.append(np.array(lam))
     return lam, Phi, hist
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2, intermediate levels: on each level j = l-1 .. 2 the prolonged modes
+# are smoothed by Kaczmarz sweeps on (K^j + sigma_j G^j) psi = 0, sigma_j the
+# smallest Ritz value of the coarser level, and replaced by the Ritz vectors
+# of the level-j pencil on their span (App. A; Kaczmarz as in the paper: row
+# projections, i.e. Gauss-Seidel on A A^T).
+#
+# Readings:
+#   * The loop of Alg. 2 is printed as j = l-1, ..., 0 with the fine grid
+#     called Omega_1; it is read as the intermediate levels l-1 .. 2, the
+#     fine level being handled by the block solve and Ritz step that follow.
+#   * The row order of a sweep is fixed by colour: node (i, j, k) has colour
+#     (i mod 3) + 3 (j mod 3) + 9 (k mod 3); colours are visited in
+#     increasing order, the nodes of a colour in any order (their rows touch
+#     disjoint columns, as every row couples a node to its 3^d neighbours
+#     only), and the components of a node in increasing order.  Each free row
+#     r replaces psi by its projection onto a_r . psi = 0 (no damping); rows of
+#     Dirichlet DOFs are skipped.
+#   * The number of sweeps is an input (the paper does not give it).
+
+
+def node_colors(nel):
+    """Colour (i mod 3) + 3 (j mod 3) [+ 9 (k mod 3)] of every node of a grid."""
+    nn = [v + 1 for v in nel]
+    idx = np.indices(nn[::-1]).reshape(len(nn), -1)[::-1]   # (i, j[, k]) with i fastest
+    col = idx[0] % 3 + 3 * (idx[1] % 3)
+    if len(nn) == 3:
+        col = col + 9 * (idx[2] % 3)
+    return col
+
+
+def kaczmarz_sweep(A, X, nel, fixed):
+    """One Kaczmarz sweep for A x = 0 on every column of X (full-length
+    vectors of a level with Dirichlet mask ``fixed``)."""
+    A = A.tocsr()
+    dim = len(nel)
+    X = np.array(X, dtype=np.float64, copy=True)
+    col = node_colors(nel)
+    fixed = np.asarray(fixed)
+    for cidx in range(3 ** dim):
+        nodes = np.flatnonzero(col == cidx)
+        for c in range(dim):
+            rows = nodes * dim + c
+            rows = rows[fixed[rows] == 0]
+            if rows.size == 0:
+                continue
+            Ar = A[rows]
+            nrm = np.asarray(Ar.multiply(Ar).sum(axis=1)).ravel()
+            keep = nrm > 0
+            Ar, nrm = Ar[keep], nrm[keep]
+            res = Ar @ X
+            X -= Ar.T @ (res / nrm[:, None])
+    return X
+
+
+def kaczmarz_sweep_rowwise(A, X, nel, fixed):
+    """The same sweep one row at a time (definition; for small grids)."""
+    A = A.tocsr()
+    dim = len(nel)
+    X = np.array(X, dtype=np.float64, copy=True)
+    col = node_colors(nel)
+    for cidx in range(3 ** dim):
+        for node in np.flatnonzero(col == cidx):
+            for c in range(dim):
+                r = node * dim + c
+                if fixed[r]:
+                    continue
+                lo, hi = A.indptr[r], A.indptr[r + 1]
+                cols, a = A.indices[lo:hi], A.data[lo:hi]
+                nrm = float(a @ a)
+                if nrm > 0:
+                    X[cols] -= np.outer(a, (a @ X[cols]) / nrm)
+    return X
+
+
+def multilevel_buckling_refined(nel, K, G, fixed, ell, q, sweeps, dense_limit=6000):
+    """Sec. 2.1 steps 1-4 with the intermediate-level smoothing and Ritz steps
+    of Alg. 2 (``sweeps`` Kaczmarz sweeps per level).  K, G: constrained fine
+    operators.  Returns the fine Ritz values and vectors and, per refined
+    level (l-1 first), its Ritz values."""
+    grids, masks, Ps = lv.hierarchy(nel, fixed, ell)
+    Ks, Gs = [K], [G]
+    for j in range(ell - 1):
+        Ks.append(lv.galerkin(Ks[-1], Ps[j], masks[j + 1], 1.0))
+        Gs.append(lv.galerkin(Gs[-1], Ps[j], masks[j + 1], 0.0))
+    fl = _free(masks[ell - 1])
+    lam_l, V, _ = generalized_lowest_positive(Ks[-1][fl][:, fl], Gs[-1][fl][:, fl], q, dense_limit=dense_limit)
+    Psi = np.zeros((Ks[-1].shape[0], q))
+    Psi[fl] = V
+    sigma = float(lam_l[0])
+    per_level = []
+    for j in range(ell - 2, 0, -1):           # 0-based index of levels l-1 .. 2
+        Psi = Ps[j] @ Psi
+        A = (Ks[j] + sigma * Gs[j]).tocsr()
+        for _ in range(sweeps):
+            Psi = kaczmarz_sweep(A, Psi, grids[j], masks[j])
+        fj = _free(masks[j])
+        lam_j, Vj = rayleigh_ritz(Ks[j][fj][:, fj], Gs[j][fj][:, fj], Psi[fj])
+        if len(lam_j) < q:
+            raise ValueError("fewer than q positive Ritz values on an intermediate level")
+        Psi = np.zeros((Ks[j].shape[0], q))
+        Psi[fj] = Vj
+        sigma = float(lam_j[0])
+        per_level.append(lam_j)
+    Psi = Ps[0] @ Psi if ell > 1 else Psi
+    f0 = _free(fixed)
+    Kff = K[f0][:, f0].tocsc()
+    import scipy.sparse.linalg as spla
+    Phi_t = spla.splu(Kff).solve(np.ascontiguousarray((G @ Psi)[f0]))
+    lam, Vf = rayleigh_ritz(K[f0][:, f0], G[f0][:, f0], Phi_t)
+    return lam, Vf, lam_l, per_level
