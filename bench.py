@@ -58,7 +58,8 @@ def parse():
                     help="skip the 32 independent 2D instances (batched vs one context at a time)")
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-pinvit", action="store_true",
-                    help="skip the leg with preconditioned inverse iteration steps on the fine modes")
+                    help="skip the legs with preconditioned inverse iteration steps on the fine modes and with "
+                         "the intermediate-level refinement")
     ap.add_argument("--wht-variant", type=int, default=-1,
                     help="with --roofline-only: fine-apply variant to run (0 register tiles, 1 LDS tiles, "
                          "2 register tiles without prefetch, 3 register tiles with per-plane transforms)")
@@ -244,6 +245,31 @@ def pinvit_leg(ctx, k, n, tol_eig, lam0):
     return out
 
 
+def refine_leg(ctx, k, n, tol_eig, lam0):
+    """Buckling with 1 and 2 Kaczmarz sweeps plus a Ritz step on every
+    intermediate level (Alg. 2) on the same context, after the timed
+    analyses; reports their cost and how far the fine Ritz values drop."""
+    import numpy as np
+    import torch
+    Phi = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    out = {}
+    for s in (1, 2):
+        ctx.set_opts(refine_sweeps=s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, ei = ctx.buckling_dev(k, Phi, tol_eig=tol_eig)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rel = (np.asarray(lam0) - np.asarray(lam)) / np.asarray(lam0)
+        out[f"sweeps_{s}"] = {"buckling_s": t, "refine_s": ei["seconds_refine"],
+                              "levels": ei["refine_levels"],
+                              "level_lambda1": [float(v) for v in ei["refine_lambda1"][:ei["refine_levels"]]],
+                              "lambda": [float(v) for v in lam],
+                              "rel_drop_min": float(rel.min()), "rel_drop_max": float(rel.max())}
+    ctx.set_opts(refine_sweeps=-1)
+    return out
+
+
 def apply_roofline(ctx, n, m, reps, ncols=1):
     """Fine-level H8 apply (public entry, FP64), HIP events on the stream the
     library launches on (the caller's current stream)."""
@@ -322,6 +348,7 @@ def main():
     apply_ms, alg_bytes = apply_roofline(ctx, n, m, args.apply_reps, 1)
     achieved = alg_bytes / (apply_ms * 1e-3) / 1e9
     pinv = None if args.no_pinvit else pinvit_leg(ctx, k, n, args.tol_eig, lam)
+    refine = None if args.no_pinvit else refine_leg(ctx, k, n, args.tol_eig, lam)
     ctx.close()
 
     learned = None
@@ -388,6 +415,7 @@ def main():
         "fp64_reference": fp64,
         "learned_warm_start": learned,
         "pinvit_refinement": pinv,
+        "intermediate_refinement": refine,
         "batched_instances": inst,
         "roofline": {"bound": "hbm", "kernel": f"{FINE_KERNELS[var64]}<double> (fine H8 K apply, 1 column)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -131,6 +131,13 @@ typedef struct {
                              cycle of the static solves and lam~_i its Ritz value, then the block is
                              replaced by its Ritz vectors again.  > 0 sets the count (at most 64),
                              < 0 sets none (the default), 0 keeps the current value */
+    int refine_sweeps;    /* intermediate-level refinement of Alg. 2: on every level l-1 .. 2 the
+                             prolonged modes take this many Kaczmarz sweeps on
+                             (K^j + sigma_j G^j) psi = 0, sigma_j the smallest Ritz value of the
+                             coarser level, and are replaced by their level-j Ritz vectors.  Rows
+                             are visited by colour (i mod 3) + 3 (j mod 3) + 9 (k mod 3), then by
+                             component.  > 0 sets the count (at most 16), < 0 sets none (the
+                             default: the main text's method), 0 keeps the current value */
 } mlb_opts;
 
 /* Per-call solver report; for blocks, the worst column is reported. */
@@ -157,6 +164,9 @@ typedef struct {
     int pinvit_steps;           /* preconditioned inverse iteration steps taken (mlb_opts) */
     double lambda1_before_pinvit; /* lam~_1 of the first Rayleigh-Ritz, before those steps */
     double seconds_pinvit;      /* wall time of those steps */
+    int refine_levels;          /* intermediate levels refined (mlb_opts.refine_sweeps) */
+    double refine_lambda1[8];   /* smallest Ritz value on each of them, level l-1 first */
+    double seconds_refine;      /* wall time of the sweeps and Ritz steps */
 } mlb_eig_info;
 
 /* ---- lifetime --------------------------------------------------------- */

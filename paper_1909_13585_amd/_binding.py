@@ -38,7 +38,8 @@ class MlbDesc(C.Structure):
 class MlbOpts(C.Structure):
     _fields_ = [("smooth_steps", C.c_int), ("jacobi_omega", C.c_double), ("eig_guard", C.c_int),
                 ("eig_max_it", C.c_int), ("check_every", C.c_int), ("seed", C.c_uint64), ("cycle", C.c_int),
-                ("block_cg", C.c_int), ("eig_sweeps", C.c_int), ("graphs", C.c_int), ("pinvit_steps", C.c_int)]
+                ("block_cg", C.c_int), ("eig_sweeps", C.c_int), ("graphs", C.c_int), ("pinvit_steps", C.c_int),
+                ("refine_sweeps", C.c_int)]
 
 
 class MlbSolveInfo(C.Structure):
@@ -50,7 +51,8 @@ class MlbEigInfo(C.Structure):
     _fields_ = [("coarse_iterations", C.c_int), ("coarse_residual", C.c_double), ("coarse_gap", C.c_double),
                 ("fine_iterations", C.c_int), ("fine_true_residual", C.c_double), ("seconds_coarse", C.c_double),
                 ("seconds_fine", C.c_double), ("seconds_ritz", C.c_double), ("coarse_warm_used", C.c_int),
-                ("pinvit_steps", C.c_int), ("lambda1_before_pinvit", C.c_double), ("seconds_pinvit", C.c_double)]
+                ("pinvit_steps", C.c_int), ("lambda1_before_pinvit", C.c_double), ("seconds_pinvit", C.c_double),
+                ("refine_levels", C.c_int), ("refine_lambda1", C.c_double * 8), ("seconds_refine", C.c_double)]
 
 
 class MlbTuneInfo(C.Structure):

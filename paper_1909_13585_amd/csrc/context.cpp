@@ -1133,6 +1133,13 @@ int build_G_levels(mlb_ctx* c) {
     }
     Level& le = c->lv[c->ell - 1];
     launch_assemble_nb_diag(dim, le.g, le.Ge, le.nmask, le.Gs, c->st);
+    // the intermediate-level refinement also needs G^j on levels 2 .. ell-1
+    if (c->o.refine_sweeps > 0)
+        for (int j = 2; j < c->ell; ++j) {
+            Level& l = c->lv[j - 1];
+            if (!l.Gs) CHK(dalloc(c, &l.Gs, (size_t)stencil_entries(dim, l.g, true)));
+            launch_assemble_nb_diag(dim, l.g, l.Ge, l.nmask, l.Gs, c->st);
+        }
     HIPC(hipGetLastError());
     return MLB_OK;
 }
@@ -1164,6 +1171,16 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         CHK(dalloc(c, &c->dlam_l, (size_t)k));
         c->k = k;
     }
+    // Optionally (Alg. 2, intermediate levels): on every level ell-1 .. 2
+    // smooth the prolonged modes by Kaczmarz sweeps on (K^j + sigma G^j) psi
+    // = 0, sigma the smallest Ritz value of the coarser level, and replace
+    // them by their level-j Ritz vectors.
+    const int sweeps = c->o.refine_sweeps;
+    int nref = 0;
+    double lam1_ref[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double t_refine = 0.0;
+    double sigma = mu.empty() ? 0.0 : 1.0 / mu[0];
+    if (sweeps > 0) CHK(ensure_level_cols(c, k));
     const double* cur = c->eS;
     int64_t ldc = c->lv[c->ell - 1].n;
     for (int j = c->ell - 1; j >= 1; --j) {
@@ -1173,6 +1190,35 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         launch_prolong_nb<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, k, lf.n, ldc, cur, dst, false, c->st);
         cur = dst;
         ldc = lf.n;
+        if (sweeps > 0 && j >= 2) {
+            const double ts = now_s();
+            for (int sw = 0; sw < sweeps; ++sw)
+                launch_kaczmarz_sweep(c->dim, lf.g, lf.A, lf.Gs, sigma, lf.nmask, k, lf.n, dst, c->st);
+            apply_K<double>(c, j, k, dst, lf.vr, kModeY, nullptr, nullptr);
+            apply_G(c, j, k, dst, lf.vz);
+            std::vector<double> A, B;
+            CHK(gram2(c, lf.n, k, dst, k, lf.vr, lf.vz, A, B));
+            std::vector<double> A2(k * k), B2(k * k), ev(k), Y(k * k);
+            for (int a = 0; a < k; ++a)
+                for (int q = 0; q < k; ++q) {
+                    A2[a * k + q] = 0.5 * (A[a + k * q] + A[q + k * a]);
+                    B2[a * k + q] = -0.5 * (B[a + k * q] + B[q + k * a]);
+                }
+            if (!gen_eig(k, A2.data(), B2.data(), ev.data(), Y.data()))
+                return fail(c, MLB_EBREAKDOWN, "level Rayleigh-Ritz: Psi^T K^j Psi not positive definite");
+            if (!(ev[k - 1] > 0.0)) return fail(c, MLB_ENOPOS, "fewer than k positive Ritz values on a refined level");
+            std::vector<double> C(k * k);
+            for (int a = 0; a < k; ++a)
+                for (int q = 0; q < k; ++q) C[a + k * q] = Y[a * k + q];
+            CHK(upload_cm(c, c->cbuf, C));
+            launch_gemm_small(lf.n, k, lf.n, dst, k, c->cbuf, lf.n, lf.vz2, c->st);
+            cur = lf.vz2;
+            sigma = 1.0 / ev[0];
+            if (nref < 8) lam1_ref[nref] = sigma;
+            ++nref;
+            CHK(sync(c));
+            t_refine += now_s() - ts;
+        }
     }
     if (c->ell == 1) launch_copy_cols(n, k, n, c->eS, n, c->X1, c->st);
     // step 3: K Phi~ = G Psi
@@ -1261,6 +1307,9 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         info->pinvit_steps = steps;
         info->lambda1_before_pinvit = steps > 0 ? lam1_before : c->lam[0];
         info->seconds_pinvit = t_pinvit;
+        info->refine_levels = nref;
+        for (int i = 0; i < 8; ++i) info->refine_lambda1[i] = lam1_ref[i];
+        info->seconds_refine = t_refine;
     }
     return MLB_OK;
 }
@@ -1548,6 +1597,8 @@ int mlb_set_opts(mlb_ctx* c, const mlb_opts* o) {
     if (o->graphs > 0) c->o.graphs = o->graphs == 1 ? 1 : 2;
     if (o->pinvit_steps > 0) c->o.pinvit_steps = std::min(o->pinvit_steps, 64);
     else if (o->pinvit_steps < 0) c->o.pinvit_steps = 0;
+    if (o->refine_sweeps > 0) c->o.refine_sweeps = std::min(o->refine_sweeps, 16);
+    else if (o->refine_sweeps < 0) c->o.refine_sweeps = 0;
     drop_graphs(c);
     if (o->jacobi_omega > 0 && c->has_density) {
         c->st = c->own;

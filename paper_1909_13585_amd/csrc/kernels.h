@@ -20,6 +20,11 @@ void launch_dinv_fine(int dim, const Geo& g, const double* E, const uint8_t* nma
 int64_t stencil_entries(int dim, const Geo& g, bool diag);
 void launch_assemble_nb(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, double* A, float* Af,
                         double* dinv, float* dinvf, hipStream_t st);
+// One Kaczmarz sweep for (K + sigma G) x = 0 on every column of X (a
+// Galerkin level: K full node-block stencil, Gd block-diagonal stencil), rows
+// in colour order (i mod 3) + 3 (j mod 3) + 9 (k mod 3); Dirichlet rows skipped.
+void launch_kaczmarz_sweep(int dim, const Geo& g, const double* A, const double* Gd, double sigma,
+                           const uint8_t* nmask, int ncols, int64_t ld, double* X, hipStream_t st);
 void launch_assemble_nb_diag(int dim, const Geo& g, const double* Ge, const uint8_t* nmask, double* A,
                              hipStream_t st);
 template <typename T>

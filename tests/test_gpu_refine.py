@@ -1,0 +1,104 @@
+"""Intermediate-level refinement of Alg. 2 (Kaczmarz sweeps on
+(K^j + sigma_j G^j) psi = 0 and a Ritz step on every level between the eigen
+level and the fine grid) against the oracle.
+
+The sweep is deterministic (a fixed colour order, no damping), so the oracle
+and the library take the same steps: the smallest Ritz value on every
+refined level and the final fine Ritz values must agree.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fem, lba, mg
+
+pytestmark = pytest.mark.gpu
+MAT = fem.Material()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return torch
+
+
+def _step(msg):
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+CASES = {
+    "column_2d_l3": dict(nel=(64, 16), levels=3, ell=3, q=4, seed=51),
+    "box_3d_l3": dict(nel=(16, 8, 8), levels=3, ell=3, q=4, seed=52),
+    "box_3d_l4": dict(nel=(32, 16, 16), levels=4, ell=4, q=4, seed=53),
+}
+
+
+def _problem(c):
+    nel = c["nel"]
+    x = W.density_uniform_noise(nel, c["seed"], sigma=1.0)
+    fixed = W.clamp_mask(nel)
+    F = W.axial_load(nel)[:, None]
+    K = fem.constrain(fem.assemble_K(nel, x, MAT), fixed, 1.0)
+    U, _, _ = lba.static_solve(K, F, fixed)
+    K, G, _ = lba.operators(nel, x, U[:, 0], fixed, MAT)
+    return x, fixed, F, K, G
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_refinement_matches_oracle(torch_mod, case, precision):
+    torch = torch_mod
+    import paper_1909_13585_amd as mlb
+    c = CASES[case]
+    x, fixed, F, K, G = _problem(c)
+    tol = 1e-9 if precision == mlb.MLB_FP64 else 1e-6
+    for sweeps in (1, 3):
+        lam_o, _, _, per = mg.multilevel_buckling_refined(c["nel"], K, G, fixed, c["ell"], c["q"], sweeps)
+        plain = lba.multilevel_buckling(c["nel"], x, None, fixed, MAT, c["ell"], c["q"], K=K, G=G)
+        _step(f"{case} precision {precision}: {sweeps} sweep(s)")
+        ctx = mlb.Context(c["nel"], mg_levels=c["levels"], eig_level=c["ell"], precision=precision)
+        ctx.set_bc(fixed)
+        ctx.set_loads(F)
+        ctx.set_density_dev(torch.from_numpy(x).cuda())
+        ctx.set_opts(refine_sweeps=sweeps)
+        U = torch.empty((1, ctx.n), dtype=torch.float64, device="cuda")
+        ctx.solve_static_dev(U, tol=1e-10, max_it=3000)
+        lam, _, info = ctx.buckling(c["q"], tol_eig=1e-12, want_modes=False)
+        ctx.close()
+        nref = c["ell"] - 2
+        got1 = np.asarray(info["refine_lambda1"][:nref])
+        ref1 = np.asarray([p[0] for p in per])
+        err = np.abs(lam / lam_o - 1).max()
+        err1 = np.abs(got1 / ref1 - 1).max()
+        print(f"  levels lam1 {got1} oracle {ref1} ({err1:.1e}); lam {lam} oracle {lam_o} ({err:.1e}); "
+              f"plain {plain.lam}; {info['seconds_refine']*1e3:.1f} ms")
+        assert info["refine_levels"] == nref
+        assert err1 <= tol, (got1, ref1)
+        assert err <= tol, (lam, lam_o)
+        assert np.all(lam <= plain.lam * (1 + 1e-9))
+
+
+def test_refinement_off_is_the_plain_method(torch_mod):
+    torch = torch_mod
+    import paper_1909_13585_amd as mlb
+    c = CASES["box_3d_l3"]
+    x, fixed, F, _, _ = _problem(c)
+    ctx = mlb.Context(c["nel"], mg_levels=c["levels"], eig_level=c["ell"])
+    ctx.set_bc(fixed)
+    ctx.set_loads(F)
+    ctx.set_density_dev(torch.from_numpy(x).cuda())
+    U = torch.empty((1, ctx.n), dtype=torch.float64, device="cuda")
+    ctx.solve_static_dev(U, tol=1e-10, max_it=3000)
+    lam0, _, i0 = ctx.buckling(c["q"], tol_eig=1e-12, want_modes=False)
+    ctx.set_opts(refine_sweeps=2)
+    lam2, _, i2 = ctx.buckling(c["q"], tol_eig=1e-12, want_modes=False)
+    ctx.set_opts(refine_sweeps=-1)
+    lam0b, _, i0b = ctx.buckling(c["q"], tol_eig=1e-12, want_modes=False)
+    ctx.close()
+    assert i0["refine_levels"] == 0 and i2["refine_levels"] == 1 and i0b["refine_levels"] == 0
+    assert np.allclose(lam0b, lam0, rtol=1e-10)
+    assert np.all(lam2 <= lam0 * (1 + 1e-9))
