@@ -6,9 +6,18 @@ interpolations of eq. interpolationSIMP2-SIMP.
 
 Readings (the paper is silent or chooses otherwise):
   * Elements: bilinear Q4 (2D, plane stress, unit thickness) and trilinear H8
-    (3D) on unit squares/cubes, not the paper's incompatible Q6/H11 elements.
+    (3D) on unit squares/cubes by default.  The paper's own incompatible
+    elements (Q6/H11, Sec. 2) are the option ``Material.element =
+    "incompatible"``: every displacement component gets one extra mode
+    4 x_m (1 - x_m) per axis m (zero at the nodes), condensed out element by
+    element (K_e0 = K_cc - K_ci K_ii^-1 K_ic).  On rectangles these modes pass
+    the patch test without correction.
   * K_e0 = integral of B^T D0 B with 2 Gauss points per axis (exact on a
-    rectangle); D0 is the unit-modulus constitutive matrix.
+    rectangle, also with the incompatible modes); D0 is the unit-modulus
+    constitutive matrix.
+  * With the incompatible element, G_e0 keeps the bilinear/trilinear
+    interpolation (the condensed modes do not enter the stress stiffness),
+    and the centroid stress is unchanged: the modes' gradients vanish there.
   * G_e0[u_e] uses ONE stress per element, evaluated at the element centroid:
     sigma0 = D0 B_c u_e, and G_e0 = (sum_ij sigma0_ij H^ij) kron I_d with
     H^ij = integral of dN/dx_i dN/dx_j^T.  The stress entering G is therefore
@@ -32,11 +41,13 @@ H8_NODES = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
 
 @dataclass(frozen=True)
 class Material:
-    """SIMP data of eq. interpolationSIMP2-SIMP: E1, E0, Poisson ratio, penalty."""
+    """SIMP data of eq. interpolationSIMP2-SIMP: E1, E0, Poisson ratio, penalty;
+    element "conforming" (Q4/H8) or "incompatible" (Q6/H11)."""
     E1: float = 1.0
     E0: float = 1e-6
     nu: float = 0.3
     p: float = 3.0
+    element: str = "conforming"
 
 
 def local_nodes(dim):
@@ -116,16 +127,48 @@ def strain_matrix(dim, pt):
     return B
 
 
-def element_stiffness(dim, nu):
-    """K_e0 = sum over Gauss points of w B^T D0 B (unit modulus, unit element)."""
+def bubble_strain_matrix(dim, pt):
+    """Strains (nv x dim^2) of the incompatible modes: column d*c + m is the
+    field u_c = 4 x_m (1 - x_m) (component c, axis m)."""
+    pairs = voigt_pairs(dim)
+    Bt = np.zeros((len(pairs), dim * dim))
+    for c in range(dim):
+        for m in range(dim):
+            grad = np.zeros(dim)            # d u_c / d x_k
+            grad[m] = 4.0 - 8.0 * pt[m]
+            for k, (i, j) in enumerate(pairs):
+                if i == j:
+                    Bt[k, dim * c + m] = grad[i] if c == i else 0.0
+                else:
+                    Bt[k, dim * c + m] = (grad[j] if c == i else 0.0) + (grad[i] if c == j else 0.0)
+    return Bt
+
+
+def element_stiffness(dim, nu, incompatible=False):
+    """K_e0 = sum over Gauss points of w B^T D0 B (unit modulus, unit element);
+    with ``incompatible``, the incompatible modes are added and condensed."""
     D = constitutive(dim, nu)
     pts, ws = gauss_points(dim)
     nde = dim * (2 ** dim)
     K = np.zeros((nde, nde))
+    Kci = np.zeros((nde, dim * dim))
+    Kii = np.zeros((dim * dim, dim * dim))
     for pt, w in zip(pts, ws):
         B = strain_matrix(dim, pt)
         K += w * B.T @ D @ B
+        if incompatible:
+            Bt = bubble_strain_matrix(dim, pt)
+            Kci += w * B.T @ D @ Bt
+            Kii += w * Bt.T @ D @ Bt
+    if incompatible:
+        K = K - Kci @ np.linalg.solve(Kii, Kci.T)
+        K = 0.5 * (K + K.T)
     return K
+
+
+def material_stiffness(dim, mat):
+    """K_e0 of the element the material selects."""
+    return element_stiffness(dim, mat.nu, incompatible=(mat.element == "incompatible"))
 
 
 def gradient_products(dim):
@@ -207,7 +250,7 @@ def assemble(nel, elem_mats):
 def assemble_K(nel, x, mat):
     """Unconstrained K[x] = sum_e E_kappa(x_e) K_e0 (Sec. 2)."""
     dim = len(nel)
-    Ke0 = element_stiffness(dim, mat.nu)
+    Ke0 = material_stiffness(dim, mat)
     Ek, _ = moduli(np.asarray(x, dtype=np.float64), mat)
     ed = element_dofs(nel)
     n = n_dofs(nel)
@@ -253,7 +296,7 @@ def constrain(A, fixed, diag_value):
 def apply_K_matfree(nel, x, v, mat):
     """y = K[x] v by an element loop (no assembly); for large-size checks."""
     dim = len(nel)
-    Ke0 = element_stiffness(dim, mat.nu)
+    Ke0 = material_stiffness(dim, mat)
     Ek, _ = moduli(np.asarray(x, dtype=np.float64), mat)
     ed = element_dofs(nel)
     contrib = Ek[:, None] * (np.asarray(v)[ed] @ Ke0.T)

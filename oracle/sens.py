@@ -30,7 +30,7 @@ def compliance_sensitivity(nel, x, U, mat, elements=None):
     """dJ/dx_e = -p x^(p-1) (E1 - E0) u_e^T K_e0 u_e for each load case column
     (for the listed elements only when ``elements`` is given)."""
     dim = len(nel)
-    Ke0 = fem.element_stiffness(dim, mat.nu)
+    Ke0 = fem.material_stiffness(dim, mat)
     ed = fem.element_dofs(nel)
     xs = np.asarray(x, dtype=np.float64)
     if elements is not None:
@@ -84,7 +84,7 @@ def buckling_sensitivity_from_adjoints(nel, x, u, lam, phi, Z, mat, elements=Non
     """eq. SensitivityLambda (times lambda, see the module notes) given the
     adjoint solutions Z; for the listed elements only when ``elements`` is given."""
     dim = len(nel)
-    Ke0 = fem.element_stiffness(dim, mat.nu)
+    Ke0 = fem.material_stiffness(dim, mat)
     D = fem.constitutive(dim, mat.nu)
     Bc = fem.strain_matrix(dim, np.full(dim, 0.5))
     ed = fem.element_dofs(nel)
