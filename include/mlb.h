@@ -59,6 +59,10 @@ extern "C" {
 #define MLB_ENOPOS     -6   /* fewer than k positive buckling factors */
 #define MLB_EBREAKDOWN -7   /* CG breakdown (p^T K p <= 0) or singular Gram matrix */
 
+/* element of mlb_desc */
+#define MLB_ELEM_CONFORMING   0
+#define MLB_ELEM_INCOMPATIBLE 1
+
 /* precision of the preconditioner (the outer Krylov solvers are FP64) */
 #define MLB_FP64   0
 #define MLB_MIXED  1        /* FP32 V-cycle; FP64 outer CG, coarsest solve, Rayleigh-Ritz */
@@ -111,6 +115,10 @@ typedef struct {
     int eig_level;      /* level l of the coarse eigenproblem, 1..mg_levels */
     int precision;      /* MLB_FP64 or MLB_MIXED */
     int device;         /* HIP device ordinal */
+    int element;        /* MLB_ELEM_CONFORMING (bilinear Q4 / trilinear H8, the default) or
+                           MLB_ELEM_INCOMPATIBLE (the paper's Q6 / H11, Sec. 2: one mode
+                           4 x_m (1 - x_m) per axis and component, condensed out of K_e0;
+                           G_e0 and the centroid stress keep the nodal interpolation) */
 } mlb_desc;
 
 /* Solver options (mlb_set_opts); zero fields keep their defaults. */

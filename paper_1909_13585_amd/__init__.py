@@ -12,10 +12,10 @@ import ctypes as C
 import numpy as np
 
 from . import _binding as B
-from ._binding import (MLB_FP64, MLB_MIXED, MLB_WARM_COARSE, MLB_WARM_NONE, MLB_WARM_STATIC, MlbError,
+from ._binding import (MLB_ELEM_CONFORMING, MLB_ELEM_INCOMPATIBLE, MLB_FP64, MLB_MIXED, MLB_WARM_COARSE, MLB_WARM_NONE, MLB_WARM_STATIC, MlbError,
                        MlbEigInfo, MlbSolveInfo)
 
-__all__ = ["Context", "MlbError", "MLB_FP64", "MLB_MIXED", "MLB_WARM_NONE", "MLB_WARM_COARSE",
+__all__ = ["Context", "MlbError", "MLB_FP64", "MLB_MIXED", "MLB_ELEM_CONFORMING", "MLB_ELEM_INCOMPATIBLE", "MLB_WARM_NONE", "MLB_WARM_COARSE",
            "MLB_WARM_STATIC", "load_library"]
 
 
@@ -44,7 +44,7 @@ class Context:
     """One analysis context (``mlb_ctx``) for a fixed grid and material."""
 
     def __init__(self, nel, E1=1.0, E0=1e-6, nu=0.3, penal=3.0, mg_levels=3, eig_level=2,
-                 precision=MLB_FP64, device=0):
+                 precision=MLB_FP64, device=0, element=0):
         self.lib = B.load()
         d = B.MlbDesc()
         d.dim = len(nel)
@@ -52,6 +52,7 @@ class Context:
             d.nel[i] = int(v)
         d.E1, d.E0, d.nu, d.penal = E1, E0, nu, penal
         d.mg_levels, d.eig_level, d.precision, d.device = mg_levels, eig_level, precision, device
+        d.element = element
         self.nel = tuple(int(v) for v in nel)
         self.dim = d.dim
         self.mg_levels, self.eig_level = mg_levels, eig_level

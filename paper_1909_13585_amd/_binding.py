@@ -20,6 +20,8 @@ MLB_ENOTCONV = -5
 MLB_ENOPOS = -6
 MLB_EBREAKDOWN = -7
 MLB_FP64 = 0
+MLB_ELEM_CONFORMING = 0
+MLB_ELEM_INCOMPATIBLE = 1
 MLB_MIXED = 1
 MLB_WARM_NONE = 0
 MLB_WARM_COARSE = 1
@@ -32,7 +34,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EDEVICE"
 class MlbDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("nel", C.c_int * 3), ("E1", C.c_double), ("E0", C.c_double),
                 ("nu", C.c_double), ("penal", C.c_double), ("mg_levels", C.c_int), ("eig_level", C.c_int),
-                ("precision", C.c_int), ("device", C.c_int)]
+                ("precision", C.c_int), ("device", C.c_int), ("element", C.c_int)]
 
 
 class MlbOpts(C.Structure):

@@ -537,7 +537,7 @@ int mlb_batch_create(const mlb_batch_desc* desc, mlb_batch** out) {
     if (hipSetDevice(desc->device) != hipSuccess) return fail(b, MLB_EDEVICE, "hipSetDevice failed");
     HIPC(hipStreamCreate(&b->own));
     b->st = b->own;
-    build_tables(2, desc->nu, &b->tab);
+    build_tables(2, desc->nu, 0, &b->tab);
     for (int k = 0; k < 64; ++k) {
         b->K0d.k[k] = b->tab.K0[k];
         b->K0f.k[k] = (float)b->tab.K0[k];

@@ -1460,6 +1460,8 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     if (desc->mg_levels < 1 || desc->mg_levels > 12) return bad("mg_levels must be in 1..12");
     if (desc->eig_level < 1 || desc->eig_level > desc->mg_levels) return bad("eig_level must be in 1..mg_levels");
     if (desc->precision != MLB_FP64 && desc->precision != MLB_MIXED) return bad("unknown precision");
+    if (desc->element != MLB_ELEM_CONFORMING && desc->element != MLB_ELEM_INCOMPATIBLE)
+        return bad("unknown element (MLB_ELEM_CONFORMING or MLB_ELEM_INCOMPATIBLE)");
     if (!(desc->E1 > 0) || !(desc->E0 >= 0) || !(desc->E0 < desc->E1)) return bad("need 0 <= E0 < E1");
     if (!(desc->nu > -1.0 && desc->nu < 0.5)) return bad("Poisson ratio must lie in (-1, 0.5)");
     if (!(desc->penal >= 1.0)) return bad("penalty p must be >= 1");
@@ -1481,7 +1483,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     *out = c;
     HIPC(hipStreamCreate(&c->own));
     c->st = c->own;
-    build_tables(dim, desc->nu, &c->tab);
+    build_tables(dim, desc->nu, desc->element, &c->tab);
     for (int i = 0; i < 9; ++i) c->whtf[i] = (float)c->tab.whs[i];
     // device tables
     CHK(dalloc(c, &c->dK0, 576));

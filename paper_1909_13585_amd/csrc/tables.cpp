@@ -5,7 +5,10 @@
 // (3D) unit square/cube; K_e0 = integral B^T D0 B with 2 Gauss points per
 // axis (exact for these elements); G_e0 uses one stress per element, at the
 // centroid: G_e0 = (sum_ij sigma_ij H^ij) kron I_dim, H^ij = integral of
-// dN/dx_i dN/dx_j^T.  Voigt order: 2D (xx, yy, xy), 3D (xx, yy, zz, xy, yz,
+// dN/dx_i dN/dx_j^T.  With element == 1 (the paper's incompatible Q6/H11,
+// Sec. 2) every displacement component gets one mode 4 x_m (1 - x_m) per
+// axis, condensed out of K_e0; their gradients vanish at the centroid, so
+// the centroid stress and G_e0 are those of the nodal interpolation.  Voigt order: 2D (xx, yy, xy), 3D (xx, yy, zz, xy, yz,
 // xz), engineering shear strains.
 //
 // Galerkin coarsening (Sec. 2.1 step 1): a coarse element of level j+1 holds
@@ -68,13 +71,36 @@ static void strain_disp(int dim, const double* xi, double* B /* nv x nde */) {
     }
 }
 
+// Strains of the incompatible modes at xi (nv x dim^2): column dim*c + m is
+// the field u_c = 4 x_m (1 - x_m), zero at the nodes, whose only nonzero
+// derivative is d u_c / d x_m = 4 - 8 x_m.
+static void bubble_strain(int dim, const double* xi, double* Bt) {
+    const int nv = dim == 2 ? 3 : 6, ni = dim * dim;
+    std::memset(Bt, 0, sizeof(double) * nv * ni);
+    static const int shear3[3][2] = {{0, 1}, {1, 2}, {0, 2}};   // Voigt rows 3, 4, 5
+    for (int c = 0; c < dim; ++c)
+        for (int m = 0; m < dim; ++m) {
+            const double g = 4.0 - 8.0 * xi[m];
+            const int col = dim * c + m;
+            if (m == c) Bt[c * ni + col] = g;                  // normal strain
+            if (dim == 2) {
+                if (m != c) Bt[2 * ni + col] = g;              // gamma_xy
+            } else {
+                for (int r = 0; r < 3; ++r) {
+                    const int i = shear3[r][0], j = shear3[r][1];
+                    if ((c == i && m == j) || (c == j && m == i)) Bt[(3 + r) * ni + col] = g;
+                }
+            }
+        }
+}
+
 static double interp_w1(int p, int A) {
     if (p == 1) return 0.5;
     if (p == 0) return A == 0 ? 1.0 : 0.0;
     return A == 1 ? 1.0 : 0.0;  // p == 2
 }
 
-void build_tables(int dim, double nu, Tables* t) {
+void build_tables(int dim, double nu, int element, Tables* t) {
     std::memset(t, 0, sizeof(Tables));
     t->dim = dim;
     const int nn = 1 << dim, nde = dim * nn, nv = dim == 2 ? 3 : 6;
@@ -102,6 +128,11 @@ void build_tables(int dim, double nu, Tables* t) {
     double B[6 * 24], DB[6 * 24];
     double Hij[3][3][64];
     std::memset(Hij, 0, sizeof(Hij));
+    // incompatible modes: couplings K_ci (nde x ni) and K_ii (ni x ni)
+    const int ni = dim * dim;
+    double Bt[6 * 9], Kci[24 * 9], Kii[9 * 9];
+    std::memset(Kci, 0, sizeof(Kci));
+    std::memset(Kii, 0, sizeof(Kii));
     for (int q = 0; q < ngp; ++q) {
         double xi[3];
         for (int k = 0; k < dim; ++k) xi[k] = gp[(q >> k) & 1];
@@ -118,6 +149,27 @@ void build_tables(int dim, double nu, Tables* t) {
                 for (int k = 0; k < nv; ++k) s += B[k * nde + i] * DB[k * nde + j];
                 t->K0[i * nde + j] += wgp * s;
             }
+        if (element == 1) {
+            bubble_strain(dim, xi, Bt);
+            for (int i = 0; i < ni; ++i) {
+                double DBt[6];
+                for (int k = 0; k < nv; ++k) {
+                    double s = 0;
+                    for (int l = 0; l < nv; ++l) s += t->D0[k * nv + l] * Bt[l * ni + i];
+                    DBt[k] = s;
+                }
+                for (int a = 0; a < nde; ++a) {
+                    double s = 0;
+                    for (int k = 0; k < nv; ++k) s += B[k * nde + a] * DBt[k];
+                    Kci[a * ni + i] += wgp * s;
+                }
+                for (int j = 0; j < ni; ++j) {
+                    double s = 0;
+                    for (int k = 0; k < nv; ++k) s += Bt[k * ni + j] * DBt[k];
+                    Kii[j * ni + i] += wgp * s;
+                }
+            }
+        }
         double g[8][3];
         for (int a = 0; a < nn; ++a)
             for (int i = 0; i < dim; ++i) g[a][i] = shape_grad(dim, a, i, xi);
@@ -125,6 +177,43 @@ void build_tables(int dim, double nu, Tables* t) {
             for (int j = 0; j < dim; ++j)
                 for (int a = 0; a < nn; ++a)
                     for (int b = 0; b < nn; ++b) Hij[i][j][a * nn + b] += wgp * g[a][i] * g[b][j];
+    }
+    // static condensation of the incompatible modes: K0 -= K_ci K_ii^-1 K_ci^T
+    // (K_ii is SPD: Cholesky, then one solve per nodal DOF)
+    if (element == 1) {
+        double L[81];
+        std::memcpy(L, Kii, sizeof(double) * ni * ni);
+        for (int j = 0; j < ni; ++j) {
+            double d = L[j * ni + j];
+            for (int k = 0; k < j; ++k) d -= L[j * ni + k] * L[j * ni + k];
+            L[j * ni + j] = std::sqrt(d);
+            for (int i = j + 1; i < ni; ++i) {
+                double s = L[i * ni + j];
+                for (int k = 0; k < j; ++k) s -= L[i * ni + k] * L[j * ni + k];
+                L[i * ni + j] = s / L[j * ni + j];
+            }
+        }
+        std::vector<double> Y((size_t)nde * ni);   // Y = K_ii^-1 K_ci^T, column per nodal DOF
+        for (int a = 0; a < nde; ++a) {
+            double y[9];
+            for (int i = 0; i < ni; ++i) {
+                double s = Kci[a * ni + i];
+                for (int k = 0; k < i; ++k) s -= L[i * ni + k] * y[k];
+                y[i] = s / L[i * ni + i];
+            }
+            for (int i = ni - 1; i >= 0; --i) {
+                double s = y[i];
+                for (int k = i + 1; k < ni; ++k) s -= L[k * ni + i] * y[k];
+                y[i] = s / L[i * ni + i];
+            }
+            for (int i = 0; i < ni; ++i) Y[(size_t)a * ni + i] = y[i];
+        }
+        for (int a = 0; a < nde; ++a)
+            for (int b = 0; b < nde; ++b) {
+                double s = 0;
+                for (int i = 0; i < ni; ++i) s += Kci[a * ni + i] * Y[(size_t)b * ni + i];
+                t->K0[a * nde + b] -= s;
+            }
     }
     // symmetrise K0 exactly
     for (int i = 0; i < nde; ++i)

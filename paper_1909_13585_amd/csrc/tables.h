@@ -18,6 +18,7 @@ struct Tables {
     bool wht_ok;            // K0 is exactly block diagonal in that basis, with that structure
 };
 
-void build_tables(int dim, double nu, Tables* t);
+// element: 0 bilinear/trilinear, 1 with condensed incompatible modes
+void build_tables(int dim, double nu, int element, Tables* t);
 
 }  // namespace mlb
