@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-instances", action="store_true",
                     help="skip the 32 independent 2D instances (batched vs one context at a time)")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-incompatible", action="store_true",
+                    help="skip the analysis with the incompatible-mode element (Q6/H11)")
     ap.add_argument("--no-pinvit", action="store_true",
                     help="skip the legs with preconditioned inverse iteration steps on the fine modes and with "
                          "the intermediate-level refinement")
@@ -98,13 +100,14 @@ def cpu_baseline(args):
     return t, n_sample
 
 
-def run_path(args, precision, p, x_dev, steps, warmup, label, net=None):
+def run_path(args, precision, p, x_dev, steps, warmup, label, net=None, element=0):
     """Times `steps` full analyses after `warmup` untimed ones.  With `net`,
     every timed analysis first predicts its warm starts from the density."""
     import torch
     import paper_1909_13585_amd as mlb
     nel = tuple(int(v) for v in args.nel.split(","))
-    ctx = mlb.Context(nel, mg_levels=args.levels, eig_level=args.eig_level, precision=precision)
+    ctx = mlb.Context(nel, mg_levels=args.levels, eig_level=args.eig_level, precision=precision,
+                      element=element)
     ctx.set_bc(p["fixed"])
     ctx.set_loads(p["F"])
     n, m = ctx.level_size(1)
@@ -364,6 +367,17 @@ def main():
                    "max_rel_lambda_diff_vs_cold": float(np.max(np.abs(np.asarray(outl[2]) / np.asarray(lam) - 1))),
                    "weights": os.path.relpath(args.learned, ROOT)}
 
+    incompatible = None
+    if not args.no_incompatible:
+        ctxi, seci, outi = run_path(args, prec, p, x_dev, 1, 1, "incompatible", element=mlb.MLB_ELEM_INCOMPATIBLE)
+        ctxi.close()
+        incompatible = {"s_per_analysis": seci, "static_iterations": outi[1]["iterations"],
+                        "coarse_iterations": outi[3]["coarse_iterations"],
+                        "fine_block_iterations": outi[3]["fine_iterations"],
+                        "adjoint_iterations": outi[4]["iterations"],
+                        "lambda": [float(v) for v in outi[2]],
+                        "lambda_ratio_to_conforming": [float(a / b) for a, b in zip(outi[2], lam)]}
+
     fp64 = None
     if args.precision == "mixed" and not args.no_fp64_reference:
         ctx64, sec64, out64 = run_path(args, mlb.MLB_FP64, p, x_dev, max(1, min(args.steps, 2)), 1, "fp64")
@@ -416,6 +430,7 @@ def main():
         "learned_warm_start": learned,
         "pinvit_refinement": pinv,
         "intermediate_refinement": refine,
+        "incompatible_element": incompatible,
         "batched_instances": inst,
         "roofline": {"bound": "hbm", "kernel": f"{FINE_KERNELS[var64]}<double> (fine H8 K apply, 1 column)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -422,12 +422,12 @@ template void launch_restrict_nb<float>(int, const Geo&, const Geo&, const uint8
 // X.  Rows are visited colour by colour, colour (i mod 3) + 3 (j mod 3) +
 // 9 (k mod 3) in increasing order: a row couples a node to its 3^d
 // neighbours only, so the rows of the nodes of one colour touch disjoint
-// columns and one thread per node applies its rows (components in increasing
-// order) without conflicts; the result equals the row-by-row sweep in that
+// columns and one thread per (node, column of X) applies the node's rows
+// (components in increasing order) without conflicts; the columns of X are
+// independent systems.  The result equals the row-by-row sweep in that
 // order.  Each free row r projects x onto a_r . x = 0; Dirichlet rows are
 // skipped.  K: full node-block stencil, G: block-diagonal stencil.
 constexpr int kKzThreads = 64;
-constexpr int kKzCols = 8;   // columns per pass (coefficients loaded once per pass)
 
 template <int DIM>
 __global__ __launch_bounds__(kKzThreads) void k_kaczmarz_color(Geo g, int cx, int cy, int cz,
@@ -438,14 +438,18 @@ __global__ __launch_bounds__(kKzThreads) void k_kaczmarz_color(Geo g, int cx, in
     constexpr int NB = DIM == 3 ? 27 : 9;
     const int mx = (g.nnx - cx + 2) / 3, my = (g.nny - cy + 2) / 3;
     const int mz = DIM == 3 ? (g.nnz - cz + 2) / 3 : 1;
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= (int64_t)mx * my * mz) return;
+    const int64_t nodes_c = (int64_t)mx * my * mz;
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (tid >= nodes_c * ncols) return;
+    const int q = (int)(tid / nodes_c);
+    const int64_t t = tid % nodes_c;
     const int i = cx + 3 * (int)(t % mx);
     const int j = cy + 3 * (int)((t / mx) % my);
     const int k = DIM == 3 ? cz + 3 * (int)(t / ((int64_t)mx * my)) : 0;
     const int64_t N = g.nodes, sy = g.nnx, sz = (int64_t)g.nnx * g.nny;
     const int64_t node = i + sy * j + sz * k;
     const unsigned m = nmask[node];
+    double* Xq = X + (int64_t)q * ld;
     auto nb_ok = [&](int nb) -> bool {
         const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = DIM == 3 ? nb / 9 - 1 : 0;
         return i + dx >= 0 && i + dx < g.nnx && j + dy >= 0 && j + dy < g.nny &&
@@ -461,49 +465,26 @@ __global__ __launch_bounds__(kKzThreads) void k_kaczmarz_color(Geo g, int cx, in
     };
     for (int c = 0; c < DIM; ++c) {
         if ((m >> c) & 1u) continue;
-        double nrm = 0.0;
+        double nrm = 0.0, res = 0.0;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             if (!nb_ok(nb)) continue;
+            const int64_t o = nb_node(nb) * DIM;
 #pragma unroll
             for (int c2 = 0; c2 < DIM; ++c2) {
                 const double a = coef(nb, c, c2);
                 nrm += a * a;
+                res += a * Xq[o + c2];
             }
         }
         if (!(nrm > 0.0)) continue;
-        for (int q0 = 0; q0 < ncols; q0 += kKzCols) {
-            const int nq = min(kKzCols, ncols - q0);
-            double* Xq = X + (int64_t)q0 * ld;
-            double res[kKzCols];
+        const double tq = res / nrm;
 #pragma unroll
-            for (int q = 0; q < kKzCols; ++q) res[q] = 0.0;
+        for (int nb = 0; nb < NB; ++nb) {
+            if (!nb_ok(nb)) continue;
+            const int64_t o = nb_node(nb) * DIM;
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                if (!nb_ok(nb)) continue;
-                const int64_t o = nb_node(nb) * DIM;
-#pragma unroll
-                for (int c2 = 0; c2 < DIM; ++c2) {
-                    const double a = coef(nb, c, c2);
-#pragma unroll
-                    for (int q = 0; q < kKzCols; ++q)
-                        if (q < nq) res[q] += a * Xq[q * ld + o + c2];
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < kKzCols; ++q) res[q] /= nrm;
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                if (!nb_ok(nb)) continue;
-                const int64_t o = nb_node(nb) * DIM;
-#pragma unroll
-                for (int c2 = 0; c2 < DIM; ++c2) {
-                    const double a = coef(nb, c, c2);
-#pragma unroll
-                    for (int q = 0; q < kKzCols; ++q)
-                        if (q < nq) Xq[q * ld + o + c2] -= res[q] * a;
-                }
-            }
+            for (int c2 = 0; c2 < DIM; ++c2) Xq[o + c2] -= tq * coef(nb, c, c2);
         }
     }
 }
@@ -515,7 +496,7 @@ void launch_kaczmarz_sweep(int dim, const Geo& g, const double* A, const double*
         const int cx = col % 3, cy = (col / 3) % 3, cz = col / 9;
         const int64_t mx = (g.nnx - cx + 2) / 3, my = (g.nny - cy + 2) / 3;
         const int64_t mz = dim == 3 ? (g.nnz - cz + 2) / 3 : 1;
-        const int64_t th = mx * my * mz;
+        const int64_t th = mx * my * mz * ncols;
         if (th <= 0) continue;
         const dim3 gr((unsigned)((th + kKzThreads - 1) / kKzThreads)), b(kKzThreads);
         if (dim == 3)
