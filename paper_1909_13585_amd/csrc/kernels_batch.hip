@@ -287,41 +287,51 @@ __global__ __launch_bounds__(kBT) void k_bq_coarsest(BQueue q, const BSeg* __res
 }
 
 // In-place Gauss-Jordan inversion of an SPD matrix (no pivoting), one block
-// per instance.  Every thread owns a fixed set of entries (t = tid mod
-// blocksize), so global memory is only ever touched by its owner; the pivot
-// row and column travel through LDS: while updating step k the owners of
-// row / column k+1 also write them to the next LDS buffer.
-constexpr int kGjThreads = 512;
+// per instance.  Thread (tx, ty) = (tid mod 64, tid / 64) owns the entries
+// (i, j) with i = ty mod 16 and j = tx mod 64, so global memory is only ever
+// touched by its owner and a wave updates 64 consecutive entries of a row;
+// the pivot row and column travel through LDS: while updating step k the
+// owners of row / column k+1 also write them to the next LDS buffer.  Each
+// step first divides the pivot row by the pivot once (n divisions) and then
+// updates every entry with one multiply-add.
+constexpr int kGjThreads = 1024;
+constexpr int kGjCols = 64;                       // threads along a row
+constexpr int kGjRows = kGjThreads / kGjCols;     // rows updated concurrently
 constexpr int kGjMax = 1024;
 
 __global__ __launch_bounds__(kGjThreads) void k_bq_gj(const int* __restrict__ cs, const BSeg* __restrict__ segs,
                                                       double* __restrict__ Ainv) {
-    __shared__ double rowb[2][kGjMax], colb[2][kGjMax];
+    __shared__ double rowb[2][kGjMax], colb[2][kGjMax], rs[kGjMax];
     const BSeg s = segs[cs[blockIdx.x]];
     const int n = 2 * s.nnx * s.nny;
     double* A = Ainv + s.coff;
+    const int tx = threadIdx.x % kGjCols, ty = threadIdx.x / kGjCols;
     for (int t = threadIdx.x; t < n; t += kGjThreads) {
         rowb[0][t] = A[t];
         colb[0][t] = A[(int64_t)t * n];
     }
     __syncthreads();
-    const int64_t nn = (int64_t)n * n;
     for (int k = 0; k < n; ++k) {
         const double* rowk = rowb[k & 1];
         const double* colk = colb[k & 1];
         double* rown = rowb[(k + 1) & 1];
         double* coln = colb[(k + 1) & 1];
         const double p = rowk[k];
-        for (int64_t t = threadIdx.x; t < nn; t += kGjThreads) {
-            const int i = (int)(t / n), j = (int)(t % n);
-            double v;
-            if (i == k && j == k) v = 1.0 / p;
-            else if (i == k) v = rowk[j] / p;
-            else if (j == k) v = -colk[i] / p;
-            else v = A[t] - colk[i] * (rowk[j] / p);
-            A[t] = v;
-            if (i == k + 1) rown[j] = v;
-            if (j == k + 1) coln[i] = v;
+        for (int j = threadIdx.x; j < n; j += kGjThreads) rs[j] = rowk[j] / p;
+        __syncthreads();
+        for (int i = ty; i < n; i += kGjRows) {
+            const double ci = colk[i];
+            double* Ai = A + (int64_t)i * n;
+            for (int j = tx; j < n; j += kGjCols) {
+                double v;
+                if (i == k && j == k) v = 1.0 / p;
+                else if (i == k) v = rs[j];
+                else if (j == k) v = -ci / p;
+                else v = Ai[j] - ci * rs[j];
+                Ai[j] = v;
+                if (i == k + 1) rown[j] = v;
+                if (j == k + 1) coln[i] = v;
+            }
         }
         __syncthreads();
     }
