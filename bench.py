@@ -298,8 +298,8 @@ def apply_roofline(ctx, n, m, reps, ncols=1):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the analysis is single-GPU by design "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the analysis is built for one GPU; "
+              "sharding it across GPUs is not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
