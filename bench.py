@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-instances", action="store_true",
                     help="skip the 32 independent 2D instances (batched vs one context at a time)")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-post", action="store_true",
+                    help="skip the post-processing measures (strain energy density, variation, correlation, dilation)")
     ap.add_argument("--no-incompatible", action="store_true",
                     help="skip the analysis with the incompatible-mode element (Q6/H11)")
     ap.add_argument("--no-pinvit", action="store_true",
@@ -273,6 +275,51 @@ def refine_leg(ctx, k, n, tol_eig, lam0):
     return out
 
 
+def post_leg(ctx, k, n, m, x_dev, tol_eig, reps=5):
+    """Post-processing measures of Sec. 5 on the fine modes of the same context
+    (after the timed analyses): strain energy density, gradient and total
+    variation on {x >= 0.5}, the k x k modal energy correlation, and the
+    dilation (r_th = 2, threshold 1e-2 of the maximum) around the two modes of
+    largest normalised variation.  Times are HIP events on the library's
+    stream, per call, including the read-back of the host results."""
+    import numpy as np
+    import torch
+    Phi = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    ctx.buckling_dev(k, Phi, tol_eig=tol_eig)
+    sed = torch.empty((k, m), dtype=torch.float64, device="cuda")
+    gradn = torch.empty_like(sed)
+    Wk = torch.empty_like(Phi)
+    xo = torch.empty_like(x_dev)
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            out = fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    ms_tv, tv = timed(lambda: ctx.sed_tv_dev(Phi, 0.5, sed, gradn))
+    ms_mac, C = timed(lambda: ctx.mac_dev(Phi, Phi, Wk))
+    sel = np.argsort(tv / tv[0])[-2:]
+    gsel = gradn[torch.from_numpy(sel).cuda()].contiguous()
+    ms_dil, _ = timed(lambda: ctx.dilate_dev(gsel, 1e-2, 2.0, x_dev, xo))
+    xs = x_dev.sum().item()
+    alg_tv = k * (8 * n + 32 * m) + 8 * m   # Phi, sed write + read, x, gradn write; E_kappa
+    return {"sed_tv_ms": ms_tv, "sed_tv_alg_bytes": alg_tv,
+            "sed_tv_gbs": alg_tv / (ms_tv * 1e-3) / 1e9,
+            "mac_ms": ms_mac, "dilate_ms": ms_dil,
+            "tv_normalised": [float(v) for v in tv / tv[0]],
+            "mac_offdiag_max": float(np.abs(C - np.diag(np.diag(C))).max()),
+            "mac_diag_min": float(np.diag(C).min()),
+            "dilated_modes": [int(v) for v in sel],
+            "volume_increase_pct": float((xo.sum().item() - xs) / xs * 100.0)}
+
+
 def apply_roofline(ctx, n, m, reps, ncols=1):
     """Fine-level H8 apply (public entry, FP64), HIP events on the stream the
     library launches on (the caller's current stream)."""
@@ -352,6 +399,7 @@ def main():
     achieved = alg_bytes / (apply_ms * 1e-3) / 1e9
     pinv = None if args.no_pinvit else pinvit_leg(ctx, k, n, args.tol_eig, lam)
     refine = None if args.no_pinvit else refine_leg(ctx, k, n, args.tol_eig, lam)
+    postp = None if args.no_post else post_leg(ctx, k, n, m, x_dev, args.tol_eig)
     ctx.close()
 
     learned = None
@@ -431,6 +479,7 @@ def main():
         "pinvit_refinement": pinv,
         "intermediate_refinement": refine,
         "incompatible_element": incompatible,
+        "post_processing": postp,
         "batched_instances": inst,
         "roofline": {"bound": "hbm", "kernel": f"{FINE_KERNELS[var64]}<double> (fine H8 K apply, 1 column)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

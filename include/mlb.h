@@ -311,6 +311,48 @@ int mlb_solve_block_dev(mlb_ctx* ctx, int ncols, const double* B, double* X, dou
 /* One multigrid V-cycle z = M^-1 r starting at `level` (ncols columns). */
 int mlb_vcycle_dev(mlb_ctx* ctx, int level, int ncols, const double* r, double* z, void* stream);
 
+/* ---- post-processing measures of local buckling (Sec. 5) -------------- */
+
+/* Energy-weighted modal correlation (eq. macCorrelationIndex):
+ *   C[j + qa r] = a_j^T K b_r,  j < qa, r < qb
+ * with K the fine stiffness of the current densities, identity rows/columns
+ * at fixed DOFs (the operator of mlb_apply_K_dev).  For modes normalised to
+ * a^T K a = b^T K b = 1 (as mlb_buckling returns them) |C| <= 1, 1 for equal
+ * modes, 0 for K-orthogonal ones; the sign follows the modes' signs.
+ * A (n x qa), B (n x qb): device, column-major, read only.  W: device
+ * workspace n x qb, caller-owned, overwritten with K B; it must not overlap
+ * B.  C_host: host, qa x qb column-major.  Synchronises the stream.
+ * MLB_EINVAL if qa + qb > 192 or qa qb > 96 x 192, MLB_ESTATE before the
+ * mask and the densities are set. */
+int mlb_mac_dev(mlb_ctx* ctx, int qa, const double* A, int qb, const double* B, double* W, double* C_host,
+                void* stream);
+
+/* Strain energy density, its gradient and total variation (eq. TVsed) of q
+ * modes Phi (n x q, device, column-major):
+ *   sed[i m + e]   = E_kappa(x_e) phi_{i|e}^T K_e0 phi_{i|e}
+ *   gradn[i m + e] = |grad sed_i| at element e on the solid set
+ *                    {x_e >= xbar}, 0 elsewhere
+ *   tv_host[i]     = sum of gradn[i m + e] over the solid set (unit cells)
+ * The gradient of the element-constant density uses differences between
+ * neighbouring solid elements only, per axis central when both neighbours
+ * are solid, one-sided when one is, none when neither is; so a density
+ * constant on the solid set has zero variation.  x is the density of the
+ * last mlb_set_density*, K_e0 the context's element.  sed, gradn: device
+ * q x m, caller-owned.  tv_host: host q doubles, or NULL (then nothing
+ * synchronises).  MLB_ESTATE before the densities are set. */
+int mlb_sed_tv_dev(mlb_ctx* ctx, int q, const double* Phi, double xbar, double* sed, double* gradn,
+                   double* tv_host, void* stream);
+
+/* Local dilation of densities (eq. postProcessingDilation):
+ *   xout_e = max(x_e, max { x_k : |c_k - c_e| <= r_th, k flagged })
+ * with c the element centroids (unit cells) and k flagged when, for some
+ * selected mode s < nsel, gradn[s m + k] >= rel_thr * max_e gradn[s m + e]
+ * (and that maximum is positive).  gradn: device nsel x m, non-negative
+ * (rows of mlb_sed_tv_dev's gradn); x, xout: device m, distinct; r_th in
+ * [0, 8], rel_thr >= 0.  Enqueue only. */
+int mlb_dilate_dev(mlb_ctx* ctx, int nsel, const double* gradn, double rel_thr, double r_th, const double* x,
+                   double* xout, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,19 +44,21 @@ def mac(K, A, B):
     return np.asarray(A).T @ (K @ np.asarray(B))
 
 
-def strain_energy_density(nel, x, Phi, mat):
-    """pi[j, e] = E_kappa(x_e) phi_{j|e}^T K_e0 phi_{j|e} for the columns of Phi (n x q)."""
+def strain_energy_density(nel, x, Phi, mat, elements=None):
+    """pi[j, e] = E_kappa(x_e) phi_{j|e}^T K_e0 phi_{j|e} for the columns of Phi (n x q)
+    (for the listed elements only, in that order, when ``elements`` is given)."""
     dim = len(nel)
     Ke0 = fem.material_stiffness(dim, mat)
     Ek, _ = fem.moduli(np.asarray(x, dtype=np.float64), mat)
     ed = fem.element_dofs(nel)
+    elems = np.arange(len(Ek)) if elements is None else np.asarray(elements)
     Phi = np.asarray(Phi)
     Phi = Phi[:, None] if Phi.ndim == 1 else Phi
-    out = np.empty((Phi.shape[1], len(Ek)))
+    out = np.empty((Phi.shape[1], len(elems)))
     for j in range(Phi.shape[1]):
-        for e in range(len(Ek)):
+        for t, e in enumerate(elems):
             pe = Phi[ed[e], j]
-            out[j, e] = Ek[e] * (pe @ Ke0 @ pe)
+            out[j, t] = Ek[e] * (pe @ Ke0 @ pe)
     return out
 
 

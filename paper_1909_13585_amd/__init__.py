@@ -249,6 +249,45 @@ class Context:
                                                  _stream()))
         return _info_dict(info)
 
+    def _block(self, t, rows, width, name):
+        import torch
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != rows * width:
+            raise ValueError(f"{name}: contiguous float64 CUDA tensor of {rows} x {width} expected")
+
+    def mac_dev(self, A, B, W):
+        """C[j, r] = a_j^T K b_r (Sec. 5, modal energy correlation) for the rows of
+        A (qa, n) and B (qb, n); W (qb, n) is overwritten with K B."""
+        qa, qb = A.shape[0], B.shape[0]
+        self._block(A, qa, self.n, "A")
+        self._block(B, qb, self.n, "B")
+        self._block(W, qb, self.n, "W")
+        out = np.zeros(qa * qb)
+        self._check(self.lib.mlb_mac_dev(self.h, qa, _dptr(A), qb, _dptr(B), _dptr(W),
+                                         out.ctypes.data_as(C.c_void_p), _stream()))
+        return out.reshape(qb, qa).T
+
+    def sed_tv_dev(self, Phi, xbar, sed, gradn):
+        """Strain energy density sed (q, m), its gradient magnitude on {x >= xbar}
+        gradn (q, m) for the modes Phi (q, n); returns the total variations (q,)."""
+        q = Phi.shape[0]
+        self._block(Phi, q, self.n, "Phi")
+        self._block(sed, q, self.m, "sed")
+        self._block(gradn, q, self.m, "gradn")
+        tv = np.zeros(q)
+        self._check(self.lib.mlb_sed_tv_dev(self.h, q, _dptr(Phi), xbar, _dptr(sed), _dptr(gradn),
+                                            tv.ctypes.data_as(C.c_void_p), _stream()))
+        return tv
+
+    def dilate_dev(self, gradn, rel_thr, r_th, x, xout):
+        """xout = local dilation of x (m,) within r_th around the elements where a
+        row of gradn (nsel, m) reaches rel_thr times its maximum."""
+        nsel = gradn.shape[0] if gradn.dim() > 1 else 1
+        self._block(gradn, nsel, self.m, "gradn")
+        self._block(x, 1, self.m, "x")
+        self._block(xout, 1, self.m, "xout")
+        self._check(self.lib.mlb_dilate_dev(self.h, nsel, _dptr(gradn), rel_thr, r_th, _dptr(x), _dptr(xout),
+                                            _stream()))
+
     def adjoints_dev(self, k, Z):
         """Copies the adjoint solutions of the last sensitivities call into Z (k, n)."""
         self._check(self.lib.mlb_adjoints_dev(self.h, k, _dptr(Z), _stream()))

@@ -1856,6 +1856,62 @@ int mlb_sensitivities_dev(mlb_ctx* c, double* dJ, double* dlam, mlb_solve_info* 
     return do_sens(c, dJ, dlam, info);
 }
 
+int mlb_mac_dev(mlb_ctx* c, int qa, const double* A, int qb, const double* B, double* W, double* C_host,
+                void* stream) {
+    if (!c || !A || !B || !W || !C_host || qa < 1 || qb < 1) return MLB_EINVAL;
+    if (qa + qb > 192 || (int64_t)qa * qb > 96 * 192)
+        return fail(c, MLB_EINVAL, "correlation blocks too wide (qa + qb <= 192, qa qb <= 96 x 192)");
+    if (W == B) return fail(c, MLB_EINVAL, "the workspace must not overlap B");
+    if (!c->has_density || !c->has_bc) return fail(c, MLB_ESTATE, "set the mask and the densities first");
+    c->st = pick(c, stream);
+    apply_K<double>(c, 1, qb, B, W, kModeY, nullptr, nullptr, false);
+    HIPC(hipGetLastError());
+    std::vector<double> C;
+    CHK(gram(c, c->n, qa, A, c->n, qb, W, c->n, C));
+    std::memcpy(C_host, C.data(), sizeof(double) * qa * qb);
+    return MLB_OK;
+}
+
+int mlb_sed_tv_dev(mlb_ctx* c, int q, const double* Phi, double xbar, double* sed, double* gradn,
+                   double* tv_host, void* stream) {
+    if (!c || !Phi || !sed || !gradn || q < 1 || q > 65535) return MLB_EINVAL;
+    if (!std::isfinite(xbar)) return fail(c, MLB_EINVAL, "xbar must be finite");
+    if (!c->has_density) return fail(c, MLB_ESTATE, "set the densities first");
+    c->st = pick(c, stream);
+    const Geo& g = c->lv[0].g;
+    const int np = grad_tv_parts(g);
+    CHK(ensure_part(c, (int64_t)np * q + q));
+    launch_sed(c->dim, g, c->Ek, q, c->n, Phi, c->dK0, sed, c->st);
+    launch_grad_tv(c->dim, g, c->x, xbar, q, sed, gradn, c->part, c->st);
+    HIPC(hipGetLastError());
+    if (tv_host) {
+        double* tv = c->part + (int64_t)np * q;
+        launch_sum_parts(q, np, c->part, tv, c->st);
+        HIPC(hipGetLastError());
+        for (int i0 = 0; i0 < q; i0 += 96 * 192)
+            CHK(read_scal(c, tv + i0, std::min(q - i0, 96 * 192), tv_host + i0));
+    }
+    return MLB_OK;
+}
+
+int mlb_dilate_dev(mlb_ctx* c, int nsel, const double* gradn, double rel_thr, double r_th, const double* x,
+                   double* xout, void* stream) {
+    if (!c || !gradn || !x || !xout || nsel < 1 || nsel > 65535) return MLB_EINVAL;
+    if (!(r_th >= 0.0 && r_th <= 8.0)) return fail(c, MLB_EINVAL, "r_th must be in [0, 8]");
+    if (!(rel_thr >= 0.0) || !std::isfinite(rel_thr)) return fail(c, MLB_EINVAL, "rel_thr must be >= 0 and finite");
+    const Geo& g = c->lv[0].g;
+    if (x < xout + g.m && xout < x + g.m) return fail(c, MLB_EINVAL, "x and xout must not overlap");
+    c->st = pick(c, stream);
+    const int np = grad_tv_parts(g);
+    CHK(ensure_part(c, (int64_t)np * nsel + nsel));
+    double* gmax = c->part + (int64_t)np * nsel;
+    launch_infnorm_part(g.m, nsel, g.m, gradn, np, c->part, c->st);
+    launch_max_parts(nsel, np, c->part, gmax, c->st);
+    launch_dilate(c->dim, g, nsel, gradn, gmax, rel_thr, r_th, x, xout, c->st);
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
 int mlb_coarse_modes_dev(mlb_ctx* c, int k, double* Psi, void* stream) {
     if (!c || !Psi || k < 1) return MLB_EINVAL;
     if (!c->has_buck || k > c->k) return fail(c, MLB_ESTATE, "no coarse modes: call mlb_buckling with at least k modes");

@@ -125,6 +125,18 @@ void launch_infnorm_part(int64_t n, int ncols, int64_t ld, const double* X, int 
 void launch_max_parts(int ncols, int nparts, const double* part, double* out, hipStream_t st);
 void launch_scale_cols(int64_t n, int ncols, int64_t ld, const double* s, double* X, hipStream_t st);
 
+// ---- post-processing measures (kernels_post.hip)
+// sed (q x m) = E_kappa phi^T K_e0 phi per element and mode
+void launch_sed(int dim, const Geo& g, const double* Ek, int q, int64_t ld, const double* Phi, const double* K0,
+                double* sed, hipStream_t st);
+// gradn (q x m) = |grad sed| on {x >= xbar}; part (q x grad_tv_parts) block sums of gradn there
+int grad_tv_parts(const Geo& g);
+void launch_grad_tv(int dim, const Geo& g, const double* x, double xbar, int q, const double* sed, double* gradn,
+                    double* part, hipStream_t st);
+// xout = dilation of x around elements flagged by gradn >= rel_thr * gmax (nsel rows)
+void launch_dilate(int dim, const Geo& g, int nsel, const double* gradn, const double* gmax, double rel_thr,
+                   double r_th, const double* x, double* xout, hipStream_t st);
+
 // ---- physics (kernels_sens.hip)
 void launch_stress(int dim, const Geo& g, const double* Es, const double* u, const double* D0Bc, double* S,
                    hipStream_t st);
