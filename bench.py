@@ -58,7 +58,8 @@ def parse():
                     help="skip the 32 independent 2D instances (batched vs one context at a time)")
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-post", action="store_true",
-                    help="skip the post-processing measures (strain energy density, variation, correlation, dilation)")
+                    help="skip the post-processing measures (strain energy density, variation, correlation, dilation) "
+                         "and the design chain (filter, projection, chain rule)")
     ap.add_argument("--no-incompatible", action="store_true",
                     help="skip the analysis with the incompatible-mode element (Q6/H11)")
     ap.add_argument("--no-pinvit", action="store_true",
@@ -320,6 +321,42 @@ def post_leg(ctx, k, n, m, x_dev, tol_eig, reps=5):
             "volume_increase_pct": float((xo.sum().item() - xs) / xs * 100.0)}
 
 
+def design_leg(ctx, m, x_dev, k, reps=5, rmin=8.0, eta=0.5, beta=6.0):
+    """Three-field design chain of Sec. 2 at the bench size: the density filter
+    (r_min = 8, the paper's radius) with the Heaviside projection (eta 0.5,
+    beta 6), and the chain rule of 1 + k sensitivity fields (compliance and k
+    buckling factors) back to the design variables.  HIP events on the
+    library's stream, per call."""
+    import numpy as np
+    import torch
+    xt = torch.empty_like(x_dev)
+    xp = torch.empty_like(x_dev)
+    df = torch.randn((1 + k, m), dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(7))
+    work = torch.empty_like(df)
+    out = torch.empty_like(df)
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_f = timed(lambda: ctx.filter_project_dev(x_dev, rmin, eta, beta, xt, xp))
+    ms_c = timed(lambda: ctx.filter_chain_dev(xt, rmin, eta, beta, df, work, out))
+    r = int(np.ceil(rmin))
+    o = np.indices((2 * r + 1,) * 3).reshape(3, -1) - r
+    nt = int((rmin - np.sqrt((o ** 2).sum(0)) > 0).sum())
+    return {"rmin": rmin, "eta": eta, "beta": beta, "weights_per_element": nt,
+            "filter_project_ms": ms_f, "chain_rule_columns": 1 + k, "chain_rule_ms": ms_c,
+            "filter_gweights_per_s": m * nt / (ms_f * 1e-3) / 1e9}
+
+
 def apply_roofline(ctx, n, m, reps, ncols=1):
     """Fine-level H8 apply (public entry, FP64), HIP events on the stream the
     library launches on (the caller's current stream)."""
@@ -400,6 +437,7 @@ def main():
     pinv = None if args.no_pinvit else pinvit_leg(ctx, k, n, args.tol_eig, lam)
     refine = None if args.no_pinvit else refine_leg(ctx, k, n, args.tol_eig, lam)
     postp = None if args.no_post else post_leg(ctx, k, n, m, x_dev, args.tol_eig)
+    designp = None if args.no_post else design_leg(ctx, m, x_dev, k)
     ctx.close()
 
     learned = None
@@ -480,6 +518,7 @@ def main():
         "intermediate_refinement": refine,
         "incompatible_element": incompatible,
         "post_processing": postp,
+        "design_chain": designp,
         "batched_instances": inst,
         "roofline": {"bound": "hbm", "kernel": f"{FINE_KERNELS[var64]}<double> (fine H8 K apply, 1 column)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

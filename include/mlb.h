@@ -353,6 +353,33 @@ int mlb_sed_tv_dev(mlb_ctx* ctx, int q, const double* Phi, double xbar, double* 
 int mlb_dilate_dev(mlb_ctx* ctx, int nsel, const double* gradn, double rel_thr, double r_th, const double* x,
                    double* xout, void* stream);
 
+/* ---- three-field design variables (Sec. 2) ------------------------------ */
+
+/* Density filter and relaxed Heaviside projection (eq. projectionOperator):
+ *   xtilde_e = sum_k w_ek xhat_k / sum_k w_ek,  w_ek = max(0, rmin - |c_e - c_k|)
+ *   x_e = (tanh(beta eta) + tanh(beta (xtilde_e - eta)))
+ *         / (tanh(beta eta) + tanh(beta (1 - eta)))
+ * with c the element centroids on the grid of unit cells and k over the
+ * elements inside the grid (rows renormalised at the boundary).  xhat,
+ * xtilde, x: device, m doubles each, distinct.  rmin in (0, 16], eta in
+ * [0, 1], beta > 0.  The first call with a new rmin uploads its weight
+ * table (synchronising the stream); later calls enqueue only.  The result
+ * does not depend on the launch: each sum runs in one fixed order. */
+int mlb_filter_project_dev(mlb_ctx* ctx, const double* xhat, double rmin, double eta, double beta,
+                           double* xtilde, double* x, void* stream);
+
+/* Chain rule from physical to design variables for ncols fields
+ * (Sec. 2, after eq. AdjointSystem):
+ *   dfdxhat[c m + k] = sum_e w_ek dfdx[c m + e] (dx/dxtilde)_e / W_e,
+ *   (dx/dxtilde)_e = beta (1 - tanh^2(beta (xtilde_e - eta)))
+ *                    / (tanh(beta eta) + tanh(beta (1 - eta))),
+ *   W_e = sum_j w_ej,
+ * with xtilde from mlb_filter_project_dev for the same rmin, eta, beta.
+ * dfdx, dfdxhat: device ncols x m (column c at c m); work: device
+ * workspace ncols x m, caller-owned, overwritten, distinct from both. */
+int mlb_filter_chain_dev(mlb_ctx* ctx, int ncols, const double* xtilde, double rmin, double eta, double beta,
+                         const double* dfdx, double* work, double* dfdxhat, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

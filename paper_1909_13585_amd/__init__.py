@@ -288,6 +288,24 @@ class Context:
         self._check(self.lib.mlb_dilate_dev(self.h, nsel, _dptr(gradn), rel_thr, r_th, _dptr(x), _dptr(xout),
                                             _stream()))
 
+    def filter_project_dev(self, xhat, rmin, eta, beta, xtilde, x):
+        """Density filter of radius rmin and Heaviside projection (eta, beta) of
+        the design variables xhat (m,) into xtilde and x (m,) (Sec. 2)."""
+        for t, name in ((xhat, "xhat"), (xtilde, "xtilde"), (x, "x")):
+            self._block(t, 1, self.m, name)
+        self._check(self.lib.mlb_filter_project_dev(self.h, _dptr(xhat), rmin, eta, beta, _dptr(xtilde), _dptr(x),
+                                                    _stream()))
+
+    def filter_chain_dev(self, xtilde, rmin, eta, beta, dfdx, work, dfdxhat):
+        """Sensitivities dfdx (ncols, m) w.r.t. the physical densities taken back
+        to the design variables into dfdxhat (ncols, m); work (ncols, m) scratch."""
+        nc = dfdx.shape[0] if dfdx.dim() > 1 else 1
+        self._block(xtilde, 1, self.m, "xtilde")
+        for t, name in ((dfdx, "dfdx"), (work, "work"), (dfdxhat, "dfdxhat")):
+            self._block(t, nc, self.m, name)
+        self._check(self.lib.mlb_filter_chain_dev(self.h, nc, _dptr(xtilde), rmin, eta, beta, _dptr(dfdx),
+                                                  _dptr(work), _dptr(dfdxhat), _stream()))
+
     def adjoints_dev(self, k, Z):
         """Copies the adjoint solutions of the last sensitivities call into Z (k, n)."""
         self._check(self.lib.mlb_adjoints_dev(self.h, k, _dptr(Z), _stream()))

@@ -122,6 +122,8 @@ _SIGS = {
     "mlb_mac_dev": (_I, [_P, _I, _P, _I, _P, _P, _P, _P]),
     "mlb_sed_tv_dev": (_I, [_P, _I, _P, _D, _P, _P, _P, _P]),
     "mlb_dilate_dev": (_I, [_P, _I, _P, _D, _D, _P, _P, _P]),
+    "mlb_filter_project_dev": (_I, [_P, _P, _D, _D, _D, _P, _P, _P]),
+    "mlb_filter_chain_dev": (_I, [_P, _I, _P, _D, _D, _D, _P, _P, _P, _P]),
     # warm-start network kernels (include/mlb_nn.h)
     "mlb_nn_conv3d": (_I, [_I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P]),
     "mlb_nn_conv3d_wgrad": (_I, [_I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),

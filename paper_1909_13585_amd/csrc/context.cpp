@@ -126,6 +126,11 @@ struct mlb_ctx {
     std::vector<double> warm_coarse;
     int warm_coarse_cols = 0;
     std::vector<double> warm_static;
+    // density filter weight table (di, dj, dk, w) for the radius fw_r
+    double* fw = nullptr;
+    int fw_n = 0;
+    double fw_r = -1.0;
+    std::vector<double> fw_host;
     std::string err;
 };
 
@@ -1575,6 +1580,7 @@ void mlb_destroy(mlb_ctx* c) {
     dfree(c->X1); dfree(c->X2); dfree(c->Phi); dfree(c->Zadj); dfree(c->dlam_l); dfree(c->eS); dfree(c->eK);
     dfree(c->eA); dfree(c->eT); dfree(c->eTK); dfree(c->eTA); dfree(c->eR); dfree(c->eP); dfree(c->ePK); dfree(c->ePA); dfree(c->part); dfree(c->pidx);
     dfree(c->scal); dfree(c->iscal); dfree(c->gbuf); dfree(c->cbuf); dfree(c->cbuf2);
+    dfree(c->fw);
     if (c->hpin) (void)hipHostFree(c->hpin);
     if (c->hup) (void)hipHostFree(c->hup);
     drop_graphs(c);
@@ -1908,6 +1914,58 @@ int mlb_dilate_dev(mlb_ctx* c, int nsel, const double* gradn, double rel_thr, do
     launch_infnorm_part(g.m, nsel, g.m, gradn, np, c->part, c->st);
     launch_max_parts(nsel, np, c->part, gmax, c->st);
     launch_dilate(c->dim, g, nsel, gradn, gmax, rel_thr, r_th, x, xout, c->st);
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+// Filter weights w = rmin - |o| > 0 for the integer offsets o, axis 0 outermost.
+static int filter_table(mlb_ctx* c, double rmin) {
+    if (rmin == c->fw_r && c->fw) return MLB_OK;
+    const int r = (int)std::ceil(rmin);
+    const int rz = c->dim == 3 ? r : 0;
+    std::vector<double> t;
+    for (int oi = -r; oi <= r; ++oi)
+        for (int oj = -r; oj <= r; ++oj)
+            for (int ok = -rz; ok <= rz; ++ok) {
+                const double w = rmin - std::sqrt((double)(oi * oi + oj * oj + ok * ok));
+                if (w > 0.0) t.insert(t.end(), {(double)oi, (double)oj, (double)ok, w});
+            }
+    CHK(sync(c));   // the previous table may still be read
+    c->fw_host = std::move(t);
+    c->fw_n = (int)(c->fw_host.size() / 4);
+    CHK(dalloc(c, &c->fw, c->fw_host.size()));
+    HIPC(hipMemcpy(c->fw, c->fw_host.data(), sizeof(double) * c->fw_host.size(), hipMemcpyHostToDevice));
+    c->fw_r = rmin;
+    return MLB_OK;
+}
+
+static int check_design_args(mlb_ctx* c, double rmin, double eta, double beta) {
+    if (!(rmin > 0.0 && rmin <= 16.0)) return fail(c, MLB_EINVAL, "rmin must be in (0, 16]");
+    if (!(eta >= 0.0 && eta <= 1.0)) return fail(c, MLB_EINVAL, "eta must be in [0, 1]");
+    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(c, MLB_EINVAL, "beta must be positive and finite");
+    return MLB_OK;
+}
+
+int mlb_filter_project_dev(mlb_ctx* c, const double* xhat, double rmin, double eta, double beta, double* xtilde,
+                           double* x, void* stream) {
+    if (!c || !xhat || !xtilde || !x) return MLB_EINVAL;
+    CHK(check_design_args(c, rmin, eta, beta));
+    if (xtilde == x || xhat == xtilde || xhat == x) return fail(c, MLB_EINVAL, "xhat, xtilde and x must be distinct");
+    c->st = pick(c, stream);
+    CHK(filter_table(c, rmin));
+    launch_filter_project(c->lv[0].g, c->fw_n, c->fw, eta, beta, xhat, xtilde, x, c->st);
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+int mlb_filter_chain_dev(mlb_ctx* c, int ncols, const double* xtilde, double rmin, double eta, double beta,
+                         const double* dfdx, double* work, double* dfdxhat, void* stream) {
+    if (!c || !xtilde || !dfdx || !work || !dfdxhat || ncols < 1 || ncols > 65535) return MLB_EINVAL;
+    CHK(check_design_args(c, rmin, eta, beta));
+    if (work == dfdxhat || work == dfdx) return fail(c, MLB_EINVAL, "the workspace must not overlap the fields");
+    c->st = pick(c, stream);
+    CHK(filter_table(c, rmin));
+    launch_filter_chain(c->lv[0].g, c->fw_n, c->fw, eta, beta, ncols, xtilde, dfdx, work, dfdxhat, c->st);
     HIPC(hipGetLastError());
     return MLB_OK;
 }

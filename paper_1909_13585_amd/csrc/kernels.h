@@ -137,6 +137,12 @@ void launch_grad_tv(int dim, const Geo& g, const double* x, double xbar, int q, 
 void launch_dilate(int dim, const Geo& g, int nsel, const double* gradn, const double* gmax, double rel_thr,
                    double r_th, const double* x, double* xout, hipStream_t st);
 
+// ---- design variables (kernels_design.hip); tab: nt entries (di, dj, dk, w)
+void launch_filter_project(const Geo& g, int nt, const double* tab, double eta, double beta, const double* xhat,
+                           double* xtilde, double* x, hipStream_t st);
+void launch_filter_chain(const Geo& g, int nt, const double* tab, double eta, double beta, int ncols,
+                         const double* xtilde, const double* dfdx, double* work, double* out, hipStream_t st);
+
 // ---- physics (kernels_sens.hip)
 void launch_stress(int dim, const Geo& g, const double* Es, const double* u, const double* D0Bc, double* S,
                    hipStream_t st);
