@@ -58,8 +58,10 @@ def _run(torch, c, xh, rmin, eta, beta, dfdx):
     return xt.cpu().numpy(), x.cpu().numpy(), out.cpu().numpy().T
 
 
+# the last case has a filter ball wider than the grid
 @pytest.mark.parametrize("nel,rmin,eta,beta", [((60, 20), 2.5, 0.5, 6.0), ((20, 12, 10), 2.2, 0.5, 6.0),
-                                               ((52, 20), 0.7, 0.3, 16.0), ((20, 12, 10), 1.5, 0.6, 1.0)])
+                                               ((52, 20), 0.7, 0.3, 16.0), ((20, 12, 10), 1.5, 0.6, 1.0),
+                                               ((6, 5, 4), 8.3, 0.5, 6.0)])
 def test_filter_projection_chain(torch_mod, nel, rmin, eta, beta):
     torch = torch_mod
     _step(f"design chain nel={nel} rmin={rmin} eta={eta} beta={beta}")
