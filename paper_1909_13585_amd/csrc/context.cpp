@@ -1406,6 +1406,15 @@ int autotune_t(mlb_ctx* c, int ncols, bool stencils, int mode, int* zout, int* v
             (v == 0 ? ms_reg : v == 1 ? ms_lds : v == 2 ? ms_nopf : ms_v3)[i] = ms;
             if (ms < best) best = ms, bz = zc[i], bv = v;
         }
+    // Variant 3 is much the fastest on single columns (the solvers' residual
+    // and line-search products), which a sweep over ncols columns does not
+    // see; it stays unless another variant wins the sweep by more than 3 %.
+    if (nvar == 4 && bv != 3) {
+        int i3 = 0;
+        for (int i = 1; i < 5; ++i)
+            if (ms_v3[i] < ms_v3[i3]) i3 = i;
+        if (ms_v3[i3] <= 1.03f * best) bz = zc[i3], bv = 3;
+    }
     c->wz[tix<T>()] = bz;
     c->wv[tix<T>()] = bv;
     *zout = bz;
