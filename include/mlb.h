@@ -175,6 +175,9 @@ typedef struct {
     int refine_levels;          /* intermediate levels refined (mlb_opts.refine_sweeps) */
     double refine_lambda1[8];   /* smallest Ritz value on each of them, level l-1 first */
     double seconds_refine;      /* wall time of the sweeps and Ritz steps */
+    int coarse_guard_fired;     /* 1 if the coarse eigensolver stopped above tol_eig because its
+                                   residual had stalled (accepted only below sqrt(tol_eig));
+                                   coarse_residual then holds the residual reached */
 } mlb_eig_info;
 
 /* ---- lifetime --------------------------------------------------------- */
@@ -221,7 +224,9 @@ int mlb_solve_static_dev(mlb_ctx* ctx, double tol, int max_it, double* U, double
  * (n x k, K-normalised, largest-magnitude entry positive) may be NULL.
  * With eig_level == 1 the eigensolve runs on the fine grid (exact pairs).
  * ESTATE without a converged static solve; ENOPOS if fewer than k
- * positive factors exist; ENOTCONV if the coarse eigensolver stalls. */
+ * positive factors exist; ENOTCONV if the coarse eigensolver stalls above
+ * sqrt(tol_eig) or reaches its iteration limit above tol_eig; EBREAKDOWN if a
+ * Gram matrix of the eigensolver is not finite or not positive. */
 int mlb_buckling(mlb_ctx* ctx, int ref_case, int k, double tol_eig, double* lambda,
                  double* Phi, mlb_eig_info* info);
 int mlb_buckling_dev(mlb_ctx* ctx, int ref_case, int k, double tol_eig, double* lambda_host,
@@ -230,6 +235,9 @@ int mlb_buckling_dev(mlb_ctx* ctx, int ref_case, int k, double tol_eig, double* 
 /* Residual norms ||(K + lambda_i G) phi_i||_inf of the last buckling call
  * (eq. eigResidual); res_inf has k entries (host). */
 int mlb_eig_residuals(mlb_ctx* ctx, double* res_inf);
+/* The same norms into device memory res_inf (k doubles), enqueued on `stream`
+ * (they stay valid until the next mlb_buckling*). */
+int mlb_eig_residuals_dev(mlb_ctx* ctx, double* res_inf, void* stream);
 
 /* Sensitivities w.r.t. the physical densities (no filter/projection):
  * dJ (m x ncases) = -p x^(p-1) (E1-E0) u_e^T K_e0 u_e; dlam (m x k) for the
@@ -275,6 +283,11 @@ int mlb_autotune(mlb_ctx* ctx, int ncols, mlb_tune_info* info, void* stream);
  * A warm start only changes iteration counts, never the tolerance the
  * solvers reach. */
 int mlb_set_warm_start(mlb_ctx* ctx, int kind, int ncols, const double* data);
+/* The same from device memory: `data` is copied on `stream` into the
+ * context's buffers (no host round trip), so a prediction computed on the
+ * device can start the solvers directly.  At most 64 coarse or 32 static
+ * columns. */
+int mlb_set_warm_start_dev(mlb_ctx* ctx, int kind, int ncols, const double* data, void* stream);
 
 /* ---- kernel-level entry points (device pointers, enqueue only) -------- */
 

@@ -147,6 +147,12 @@ class Context:
             D = D[:, None]
         self._check(self.lib.mlb_set_warm_start(self.h, kind, D.shape[1], C.c_void_p(D.ctypes.data)))
 
+    def set_warm_start_dev(self, kind, data):
+        """Warm start from a float64 device tensor (n x ncols, column-major:
+        pass the transpose of a contiguous (ncols, n) tensor, or one column)."""
+        ncols = 1 if data.dim() == 1 else data.shape[1]
+        self._check(self.lib.mlb_set_warm_start_dev(self.h, kind, ncols, _dptr(data), _stream()))
+
     # -- analysis (host outputs)
     def solve_static(self, tol=1e-8, max_it=1000):
         U = np.zeros((self.n, self.ncases), order="F")
@@ -169,6 +175,9 @@ class Context:
         r = np.zeros(self.k)
         self._check(self.lib.mlb_eig_residuals(self.h, _ptr(r)))
         return r
+
+    def eig_residuals_dev(self, out):
+        self._check(self.lib.mlb_eig_residuals_dev(self.h, _dptr(out), _stream()))
 
     def sensitivities(self, compliance=True, buckling=True):
         dJ = np.zeros((self.m, self.ncases), order="F") if compliance else None

@@ -54,7 +54,8 @@ class MlbEigInfo(C.Structure):
                 ("fine_iterations", C.c_int), ("fine_true_residual", C.c_double), ("seconds_coarse", C.c_double),
                 ("seconds_fine", C.c_double), ("seconds_ritz", C.c_double), ("coarse_warm_used", C.c_int),
                 ("pinvit_steps", C.c_int), ("lambda1_before_pinvit", C.c_double), ("seconds_pinvit", C.c_double),
-                ("refine_levels", C.c_int), ("refine_lambda1", C.c_double * 8), ("seconds_refine", C.c_double)]
+                ("refine_levels", C.c_int), ("refine_lambda1", C.c_double * 8), ("seconds_refine", C.c_double),
+                ("coarse_guard_fired", C.c_int)]
 
 
 class MlbTuneInfo(C.Structure):
@@ -102,9 +103,11 @@ _SIGS = {
     "mlb_buckling": (_I, [_P, _I, _I, _D, _P, _P, C.POINTER(MlbEigInfo)]),
     "mlb_buckling_dev": (_I, [_P, _I, _I, _D, _P, _P, C.POINTER(MlbEigInfo), _P]),
     "mlb_eig_residuals": (_I, [_P, _P]),
+    "mlb_eig_residuals_dev": (_I, [_P, _P, _P]),
     "mlb_sensitivities": (_I, [_P, _P, _P, C.POINTER(MlbSolveInfo)]),
     "mlb_sensitivities_dev": (_I, [_P, _P, _P, C.POINTER(MlbSolveInfo), _P]),
     "mlb_set_warm_start": (_I, [_P, _I, _I, _P]),
+    "mlb_set_warm_start_dev": (_I, [_P, _I, _I, _P, _P]),
     "mlb_apply_K_dev": (_I, [_P, _I, _I, _P, _P, _P]),
     "mlb_apply_G_dev": (_I, [_P, _I, _I, _P, _P, _P]),
     "mlb_set_state_dev": (_I, [_P, _P, _P, _P]),

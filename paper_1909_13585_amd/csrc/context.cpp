@@ -123,9 +123,10 @@ struct mlb_ctx {
     double* hup = nullptr;    // pinned staging of coefficient uploads (2 x 96 x 96)
     bool up_pending = false;  // an upload from hup may still be in flight
     // warm starts
-    std::vector<double> warm_coarse;
+    double* warm_coarse = nullptr;   // device, n_l x warm_coarse_cols
     int warm_coarse_cols = 0;
-    std::vector<double> warm_static;
+    double* warm_static = nullptr;   // device, n x warm_static_cols
+    int warm_static_cols = 0;
     // density filter weight table (di, dj, dk, w) for the radius fw_r
     double* fw = nullptr;
     int fw_n = 0;
@@ -746,17 +747,24 @@ bool rayleigh_ritz_gram(int ncol, int ld, const std::vector<double>& GK, const s
 
 // SVQB: given the Gram matrix G (r0 x r0, column-major) of a block V,
 // returns T (column-major r0 x r) with V T orthonormal in that inner product,
-// dropping directions whose Gram eigenvalue is below drop * largest.
+// dropping directions whose Gram eigenvalue is below drop * largest, and
+// r >= 1.  Returns 0 if the block is exactly zero (nothing left to add) and
+// -1 if G is not a Gram matrix of finite vectors: a non-finite entry, a
+// negative diagonal or largest eigenvalue, or an eigensolver failure.
 static int svqb(int r0, const std::vector<double>& G, double drop, std::vector<double>& T) {
     std::vector<double> d(r0), Gs((size_t)r0 * r0), w(r0), V((size_t)r0 * r0);
+    for (size_t i = 0; i < (size_t)r0 * r0; ++i)
+        if (!std::isfinite(G[i])) return -1;
     for (int i = 0; i < r0; ++i) {
         const double g = G[i + (size_t)r0 * i];
+        if (g < 0) return -1;
         d[i] = g > 0 ? 1.0 / std::sqrt(g) : 0.0;
     }
     for (int a = 0; a < r0; ++a)
         for (int q = 0; q < r0; ++q)
             Gs[(size_t)a * r0 + q] = d[a] * d[q] * 0.5 * (G[a + (size_t)r0 * q] + G[q + (size_t)r0 * a]);
-    if (!sym_eig(r0, Gs.data(), w.data(), V.data()) || !(w[0] > 0)) return 0;
+    if (!sym_eig(r0, Gs.data(), w.data(), V.data()) || w[0] < 0) return -1;
+    if (!(w[0] > 0)) return 0;
     int r = 0;
     while (r < r0 && w[r] > drop * w[0]) ++r;
     T.assign((size_t)r0 * r, 0.0);
@@ -826,6 +834,7 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
             CHK(gram(c, n, sp, P, n, sp, Q, n, G, nc, c->R, n));
             std::vector<double> PQ(G.begin(), G.begin() + (size_t)sp * sp);
             const int r = svqb(sp, PQ, 1e-13, Tm);
+            if (r < 0) return fail(c, MLB_EBREAKDOWN, "block CG: P^T K P is not a finite Gram matrix");
             if (r == 0) return fail(c, MLB_EBREAKDOWN, "block CG: search space collapsed");
             // alpha = T^T (P^T R): r x nc
             Al.assign((size_t)r * nc, 0.0);
@@ -884,7 +893,7 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
 // by the same recurrences drifts once the basis becomes ill-conditioned).
 // On exit eS[0..nb) holds X (K-orthonormal), mu the Ritz values (descending).
 int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double* gap, std::vector<double>& mu,
-                int* warm_used) {
+                int* warm_used, int* guard_fired) {
     const bool verbose = std::getenv("MLB_VERBOSE") != nullptr;
     const int j = c->ell;
     Level& l = c->lv[j - 1];
@@ -947,9 +956,8 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         launch_random_fill(n, nb, n, c->o.seed, l.nmask, c->dim, X, c->st);
         if (warm) {
             const int wc = std::min(c->warm_coarse_cols, nb);
-            HIPC(hipMemcpyAsync(X, c->warm_coarse.data(), sizeof(double) * n * wc, hipMemcpyHostToDevice, c->st));
+            HIPC(hipMemcpyAsync(X, c->warm_coarse, sizeof(double) * n * wc, hipMemcpyDeviceToDevice, c->st));
             launch_mask_fixed(n, wc, n, l.nmask, c->dim, X, c->st);
-            CHK(sync(c));
         }
         applyKA(nb, X, bufs[0].KS, bufs[0].AS);
         CHK(gram2(c, n, nb, bufs[0].S, nb, bufs[0].KS, bufs[0].AS, GK, GA));
@@ -966,7 +974,7 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         if (!ok) return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: start block is rank deficient");
         mu.assign(ev.begin(), ev.begin() + nb);
         *warm_used = 0;
-        if (c->warm_coarse_cols > 0 && (int64_t)c->warm_coarse.size() == n * c->warm_coarse_cols) {
+        if (c->warm_coarse_cols > 0 && c->warm_coarse) {
             double w_plain = 0.0, w_warm = 0.0;
             CHK(ritz_residual(mu, &w_plain));
             // keep the plain Ritz block in the P buffers while the warm one is built
@@ -1066,7 +1074,8 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         applyKA(nb, W, KW, AW);
         CHK(gram(c, n, nb, W, n, nb, KW, n, G));
         const int rw = svqb(nb, G, 1e-10, Tm);
-        if (rw == 0) {   // nothing new to add: converged to working precision
+        if (rw < 0) return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: W^T K W is not a finite Gram matrix");
+        if (rw == 0) {   // the preconditioned residual vanished: nothing new to add
             stalled = true;
             break;
         }
@@ -1117,7 +1126,10 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
     *iters = it;
     *worst = wres;
     *gap = mu[k - 1] > 0 ? (mu[k - 1] - mu[k]) / mu[k - 1] : 0.0;
-    if (wres > tol && !stalled)
+    *guard_fired = wres > tol ? 1 : 0;
+    // A stalled residual is accepted only below sqrt(tol); the caller
+    // reports it (mlb_eig_info.coarse_guard_fired, coarse_residual).
+    if (wres > tol && !(stalled && wres <= std::sqrt(tol)))
         return fail(c, MLB_ENOTCONV, "coarse eigensolver stalled at relative residual " + std::to_string(wres) +
                                          " after " + std::to_string(it) + " iterations");
     if (!(mu[k - 1] > 0.0)) return fail(c, MLB_ENOPOS, "fewer than k positive buckling factors at the coarse level");
@@ -1165,8 +1177,8 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
     int cit = 0;
     double cres = 0, gap = 0;
     std::vector<double> mu;
-    int warm_used = 0;
-    CHK(coarse_eigs(c, k, tol_eig, &cit, &cres, &gap, mu, &warm_used));
+    int warm_used = 0, guard = 0;
+    CHK(coarse_eigs(c, k, tol_eig, &cit, &cres, &gap, mu, &warm_used, &guard));
     const double t1 = now_s();
     // step 2: interpolate the coarse modes to the fine grid
     CHK(ensure_cg(c, std::max(k, c->ncases)));
@@ -1304,6 +1316,7 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         info->coarse_residual = cres;
         info->coarse_gap = gap;
         info->coarse_warm_used = warm_used;
+        info->coarse_guard_fired = guard;
         info->fine_iterations = si.iterations;
         info->fine_true_residual = si.true_rel_residual;
         info->seconds_coarse = t1 - t0;
@@ -1589,7 +1602,7 @@ void mlb_destroy(mlb_ctx* c) {
     dfree(c->X1); dfree(c->X2); dfree(c->Phi); dfree(c->Zadj); dfree(c->dlam_l); dfree(c->eS); dfree(c->eK);
     dfree(c->eA); dfree(c->eT); dfree(c->eTK); dfree(c->eTA); dfree(c->eR); dfree(c->eP); dfree(c->ePK); dfree(c->ePA); dfree(c->part); dfree(c->pidx);
     dfree(c->scal); dfree(c->iscal); dfree(c->gbuf); dfree(c->cbuf); dfree(c->cbuf2);
-    dfree(c->fw);
+    dfree(c->fw); dfree(c->warm_coarse); dfree(c->warm_static);
     if (c->hpin) (void)hipHostFree(c->hpin);
     if (c->hup) (void)hipHostFree(c->hup);
     drop_graphs(c);
@@ -1771,13 +1784,13 @@ static int solve_static_common(mlb_ctx* c, double tol, int max_it, mlb_solve_inf
     c->has_static = c->has_buck = false;
     c->has_adj = false;
     bool x0 = false;
-    if ((int64_t)c->warm_static.size() == c->n * c->ncases) {
+    if (c->warm_static && c->warm_static_cols == c->ncases) {
         // initial guess scaled per column to its energy-optimal multiple
         // alpha = f^T u0 / u0^T K u0 (the minimiser of the energy-norm error
         // along u0), so a guess of the right shape but any scale helps
         const int nc = c->ncases;
         CHK(ensure_cg(c, nc));
-        HIPC(hipMemcpyAsync(c->U, c->warm_static.data(), sizeof(double) * c->n * nc, hipMemcpyHostToDevice, c->st));
+        HIPC(hipMemcpyAsync(c->U, c->warm_static, sizeof(double) * c->n * nc, hipMemcpyDeviceToDevice, c->st));
         launch_mask_fixed(c->n, nc, c->n, c->lv[0].nmask, c->dim, c->U, c->st);
         apply_K<double>(c, 1, nc, c->U, c->R, kModeY, nullptr, nullptr);
         dots(c, c->n, nc, c->F, c->U, sc(c, 0));
@@ -1848,6 +1861,16 @@ int mlb_eig_residuals(mlb_ctx* c, double* res) {
     if (!c || !res) return MLB_EINVAL;
     if (!c->has_buck) return fail(c, MLB_ESTATE, "no buckling result");
     std::memcpy(res, c->eigres.data(), sizeof(double) * c->eigres.size());
+    return MLB_OK;
+}
+
+int mlb_eig_residuals_dev(mlb_ctx* c, double* res, void* stream) {
+    if (!c || !res) return MLB_EINVAL;
+    if (!c->has_buck) return fail(c, MLB_ESTATE, "no buckling result");
+    c->st = pick(c, stream);
+    // the norms were reduced on the device into scalar slot 14 by the last
+    // buckling call (one value per mode)
+    HIPC(hipMemcpyAsync(res, sc(c, 14), sizeof(double) * c->k, hipMemcpyDeviceToDevice, c->st));
     return MLB_OK;
 }
 
@@ -2084,26 +2107,52 @@ int mlb_adjoints_dev(mlb_ctx* c, int k, double* Z, void* stream) {
     return MLB_OK;
 }
 
-int mlb_set_warm_start(mlb_ctx* c, int kind, int ncols, const double* data) {
-    if (!c) return MLB_EINVAL;
+// Copies a warm start into the context's device buffers (host or device
+// source; `stream` only for a device source).
+static int set_warm_common(mlb_ctx* c, int kind, int ncols, const double* data, bool dev, void* stream) {
     if (kind == MLB_WARM_NONE) {
-        c->warm_coarse.clear();
-        c->warm_coarse_cols = 0;
-        c->warm_static.clear();
+        dfree(c->warm_coarse);
+        dfree(c->warm_static);
+        c->warm_coarse_cols = c->warm_static_cols = 0;
         return MLB_OK;
     }
     if (!data || ncols < 1) return fail(c, MLB_EINVAL, "warm start needs data and ncols >= 1");
+    double** dst = nullptr;
+    int64_t rows = 0;
     if (kind == MLB_WARM_COARSE) {
-        const int64_t nl = c->lv[c->ell - 1].n;
-        c->warm_coarse.assign(data, data + (size_t)nl * ncols);
-        c->warm_coarse_cols = ncols;
-        return MLB_OK;
+        if (ncols > 64) return fail(c, MLB_EINVAL, "at most 64 coarse warm-start columns");
+        dst = &c->warm_coarse;
+        rows = c->lv[c->ell - 1].n;
+        c->warm_coarse_cols = 0;
+    } else if (kind == MLB_WARM_STATIC) {
+        if (ncols > 32) return fail(c, MLB_EINVAL, "at most 32 static warm-start columns");
+        dst = &c->warm_static;
+        rows = c->n;
+        c->warm_static_cols = 0;
+    } else {
+        return fail(c, MLB_EINVAL, "unknown warm-start kind");
     }
-    if (kind == MLB_WARM_STATIC) {
-        c->warm_static.assign(data, data + (size_t)c->n * ncols);
-        return MLB_OK;
+    CHK(dalloc(c, dst, (size_t)rows * ncols));
+    const size_t bytes = sizeof(double) * (size_t)rows * ncols;
+    if (dev) {
+        c->st = pick(c, stream);
+        HIPC(hipMemcpyAsync(*dst, data, bytes, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        HIPC(hipMemcpy(*dst, data, bytes, hipMemcpyHostToDevice));
     }
-    return fail(c, MLB_EINVAL, "unknown warm-start kind");
+    if (kind == MLB_WARM_COARSE) c->warm_coarse_cols = ncols;
+    else c->warm_static_cols = ncols;
+    return MLB_OK;
+}
+
+int mlb_set_warm_start(mlb_ctx* c, int kind, int ncols, const double* data) {
+    if (!c) return MLB_EINVAL;
+    return set_warm_common(c, kind, ncols, data, false, nullptr);
+}
+
+int mlb_set_warm_start_dev(mlb_ctx* c, int kind, int ncols, const double* data, void* stream) {
+    if (!c) return MLB_EINVAL;
+    return set_warm_common(c, kind, ncols, data, true, stream);
 }
 
 // ---- kernel-level entry points

@@ -1,7 +1,8 @@
 // Small dense FP64 linear algebra on the host (Rayleigh-Ritz problems of
 // size <= ~100): Cholesky, symmetric eigendecomposition by Householder
-// tridiagonalisation followed by implicit-shift QL iterations (Golub & Van
-// Loan, Sec. 8.3), and the symmetric-definite generalized problem.
+// tridiagonalisation followed by the implicit symmetric QR algorithm with
+// Wilkinson shifts (Golub & Van Loan, Sec. 8.3), and the symmetric-definite
+// generalized problem.
 #include "dense.h"
 
 #include <algorithm>
@@ -80,60 +81,92 @@ static void tridiagonalize(int n, double* Q, double* d, double* e) {
     std::copy(q.begin(), q.end(), Q);
 }
 
-// Implicit-shift QL on the tridiagonal (d, e), accumulating rotations into
-// the columns of Q.  Returns false if an eigenvalue fails to converge.
-static bool tql(int n, double* d, double* e, double* Q) {
-    for (int i = 1; i < n; ++i) e[i - 1] = e[i];
-    if (n > 0) e[n - 1] = 0.0;
-    for (int l = 0; l < n; ++l) {
-        int iter = 0;
-        int m;
-        do {
-            for (m = l; m < n - 1; ++m) {
-                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-                if (std::fabs(e[m]) <= 1e-300 || std::fabs(e[m]) <= 2.2e-16 * dd) break;
+// Symmetric QR algorithm on the tridiagonal matrix T = tridiag(e, d, e)
+// (Golub & Van Loan, Matrix Computations, 4th ed., Alg. 8.3.2 "implicit
+// symmetric QR step with Wilkinson shift" inside the deflation loop of
+// Alg. 8.3.3).  d: diagonal (n); off: off[i] = T(i, i+1) (n - 1 used).
+// Every Givens rotation G_k of plane (k, k+1) is accumulated as Q <- Q G_k
+// (Q row-major n x n), so on exit T = diag(d) and the columns of Q are the
+// eigenvectors of the matrix whose tridiagonal form T was.  Returns false
+// if the active block has not split after 30 n sweeps.
+namespace {
+
+// c, s with [c s; -s c]^T [a; b] = [r; 0] (Golub & Van Loan, Alg. 5.1.3)
+void givens(double a, double b, double* c, double* s) {
+    if (b == 0.0) {
+        *c = 1.0;
+        *s = 0.0;
+        return;
+    }
+    const double r = std::hypot(a, b);
+    *c = a / r;
+    *s = -b / r;
+}
+
+// One implicit QR step with Wilkinson shift on the unreduced block [p, q].
+void qr_step(int n, int p, int q, double* d, double* off, double* Q) {
+    // shift: eigenvalue of the trailing 2 x 2 block closer to d[q]
+    const double half = 0.5 * (d[q - 1] - d[q]);
+    const double b2 = off[q - 1] * off[q - 1];
+    const double den = half + (half >= 0.0 ? 1.0 : -1.0) * std::hypot(half, off[q - 1]);
+    const double mu = den != 0.0 ? d[q] - b2 / den : d[q];
+    double x = d[p] - mu;   // first column of T - mu I ...
+    double z = off[p];      // ... and, after the first rotation, the bulge
+    for (int k = p; k < q; ++k) {
+        double c, s;
+        givens(x, z, &c, &s);
+        if (k > p) off[k - 1] = c * x - s * z;   // the bulge moves down
+        const double a = d[k], b = off[k], cc = d[k + 1];
+        d[k] = c * c * a - 2.0 * c * s * b + s * s * cc;
+        d[k + 1] = s * s * a + 2.0 * c * s * b + c * c * cc;
+        off[k] = c * s * (a - cc) + (c * c - s * s) * b;
+        if (k + 1 < q) {
+            z = -s * off[k + 1];
+            off[k + 1] *= c;
+        }
+        x = off[k];
+        for (int i = 0; i < n; ++i) {
+            double* row = Q + (size_t)i * n;
+            const double u = row[k], v = row[k + 1];
+            row[k] = c * u - s * v;
+            row[k + 1] = s * u + c * v;
+        }
+    }
+}
+
+bool tridiagonal_qr(int n, double* d, double* off, double* Q) {
+    const double eps = 2.220446049250313e-16;
+    int q = n - 1;
+    long sweeps = 0;
+    while (q > 0) {
+        // deflate converged eigenvalues at the bottom
+        if (std::fabs(off[q - 1]) <= eps * (std::fabs(d[q - 1]) + std::fabs(d[q])) ||
+            std::fabs(off[q - 1]) < 1e-300) {
+            off[q - 1] = 0.0;
+            --q;
+            continue;
+        }
+        // largest unreduced block ending at q
+        int p = q - 1;
+        while (p > 0) {
+            if (std::fabs(off[p - 1]) <= eps * (std::fabs(d[p - 1]) + std::fabs(d[p])) ||
+                std::fabs(off[p - 1]) < 1e-300) {
+                off[p - 1] = 0.0;
+                break;
             }
-            if (m != l) {
-                if (++iter > 60) return false;
-                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = std::hypot(g, 1.0);
-                g = d[m] - d[l] + e[l] / (g + (g >= 0 ? std::fabs(r) : -std::fabs(r)));
-                double s = 1.0, c = 1.0, p = 0.0;
-                int i;
-                for (i = m - 1; i >= l; --i) {
-                    double f = s * e[i];
-                    const double b = c * e[i];
-                    r = std::hypot(f, g);
-                    e[i + 1] = r;
-                    if (r == 0.0) {
-                        d[i + 1] -= p;
-                        e[m] = 0.0;
-                        break;
-                    }
-                    s = f / r;
-                    c = g / r;
-                    g = d[i + 1] - p;
-                    r = (d[i] - g) * s + 2.0 * c * b;
-                    p = s * r;
-                    d[i + 1] = g + p;
-                    g = c * r - b;
-                    for (int k = 0; k < n; ++k) {
-                        f = Q[(size_t)k * n + i + 1];
-                        Q[(size_t)k * n + i + 1] = s * Q[(size_t)k * n + i] + c * f;
-                        Q[(size_t)k * n + i] = c * Q[(size_t)k * n + i] - s * f;
-                    }
-                }
-                if (r == 0.0 && i >= l) continue;
-                d[l] -= p;
-                e[l] = g;
-                e[m] = 0.0;
-            }
-        } while (m != l);
+            --p;
+        }
+        if (++sweeps > 30L * n) return false;
+        qr_step(n, p, q, d, off, Q);
     }
     return true;
 }
 
+}  // namespace
+
 bool sym_eig(int n, const double* A, double* w, double* V) {
+    for (size_t i = 0; i < (size_t)n * n; ++i)
+        if (!std::isfinite(A[i])) return false;
     std::vector<double> Q(A, A + (size_t)n * n), d(n), e(n);
     // symmetrise input
     for (int i = 0; i < n; ++i)
@@ -147,7 +180,10 @@ bool sym_eig(int n, const double* A, double* w, double* V) {
         return true;
     }
     tridiagonalize(n, Q.data(), d.data(), e.data());
-    if (!tql(n, d.data(), e.data(), Q.data())) return false;
+    // e[i] = T(i, i-1) -> off[i] = T(i, i+1)
+    std::vector<double> off(n, 0.0);
+    for (int i = 0; i + 1 < n; ++i) off[i] = e[i + 1];
+    if (!tridiagonal_qr(n, d.data(), off.data(), Q.data())) return false;
     // sort descending, eigenvectors as columns (row-major V[i*n + j]: row i of column j)
     std::vector<int> idx(n);
     for (int i = 0; i < n; ++i) idx[i] = i;
