@@ -383,7 +383,7 @@ int precondition(mlb_ctx* c, int j, int nc, const double* r, double* z) {
             HIPC(hipGraphLaunch(g.exec, c->st));
             return MLB_OK;
         }
-    if (c->graphs.size() >= 32) drop_graphs(c);
+    if (c->graphs.size() >= 128) drop_graphs(c);
     if (!c->cap) HIPC(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     hipStream_t saved = c->st;
     c->st = c->cap;
@@ -1009,11 +1009,11 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
     const int max_it = c->o.eig_max_it > 0 ? c->o.eig_max_it : 400;
     double t_host = 0.0, t_pre = 0.0;
     const double t_start = now_s();
+    std::vector<double> cres(nb);
+    std::vector<int> act;
     for (it = 0; it <= max_it; ++it) {
         Buf& b = bufs[cur];
         double *X = b.S, *KX = b.KS, *AX = b.AS;
-        const int64_t oW = n * (nb + rp);
-        double *W = b.S + oW, *KW = b.KS + oW, *AW = b.AS + oW;
         std::memcpy(c->hpin, mu.data(), sizeof(double) * nb);
         HIPC(hipMemcpyAsync(sc(c, 11), c->hpin, sizeof(double) * nb, hipMemcpyHostToDevice, c->st));
         launch_residual_block(n, nb, n, AX, KX, sc(c, 11), c->eR, c->st);
@@ -1021,28 +1021,82 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         dots(c, n, nb, KX, KX, sc(c, 12) + nb);
         CHK(read_scal(c, sc(c, 12), 2 * nb, nrm.data()));
         wres = 0.0;
-        for (int i = 0; i < k; ++i) {
+        for (int i = 0; i < nb; ++i) {
             const double den = std::fabs(mu[i]) * std::sqrt(nrm[nb + i]);
-            wres = std::max(wres, den > 0 ? std::sqrt(nrm[i]) / den : 1e300);
+            cres[i] = den > 0 ? std::sqrt(nrm[i]) / den : 1e300;
+            if (!std::isfinite(cres[i])) cres[i] = 1e300;
+            if (i < k) wres = std::max(wres, cres[i]);
         }
-        if (!std::isfinite(wres)) return fail(c, MLB_EBREAKDOWN, "coarse eigensolver residual not finite");
-        if (verbose) std::fprintf(stderr, "[mlb] lobpcg it %d worst %.3e rp %d mu0 %.12g muk %.12g\n", it, wres, rp,
-                                  mu[0], mu[k - 1]);
+        if (!(wres < 1e300)) return fail(c, MLB_EBREAKDOWN, "coarse eigensolver residual not finite");
+        // Soft locking: a column whose residual is already below tol keeps its
+        // place in X (and in every Rayleigh-Ritz step) but adds no new
+        // direction.  Its residual is then dominated by rounding, and adding
+        // that noise, normalised, to the basis spoils the conditioning of the
+        // Gram matrices and with it the pairs that had converged.  The active
+        // set is recomputed every iteration, so a locked column whose residual
+        // grows again is unlocked.
+        act.clear();
+        for (int i = 0; i < nb; ++i)
+            if (cres[i] > tol) act.push_back(i);
+        const int na = (int)act.size();
+        if (verbose) std::fprintf(stderr, "[mlb] lobpcg it %d worst %.3e rp %d active %d mu0 %.12g muk %.12g\n", it,
+                                  wres, rp, na, mu[0], mu[k - 1]);
         if (wres <= tol || it == max_it) break;
         // Precision floor: the residual of the k-th pair cannot fall below
         // about eps * ||K^-1 G|| / mu_k.  Accept a residual that has stopped
-        // improving for 15 iterations once it is below sqrt(tol).
+        // improving for 15 iterations once it (and the best of those 15) is
+        // below sqrt(tol).
         hist.push_back(wres);
         if ((int)hist.size() > 15) {
             const double best_old = *std::min_element(hist.begin(), hist.end() - 15);
             const double best_new = *std::min_element(hist.end() - 15, hist.end());
-            if (best_new > 0.5 * best_old && best_new <= std::sqrt(tol)) {
+            if (best_new > 0.5 * best_old && wres <= std::sqrt(tol)) {
                 stalled = true;
                 break;
             }
         }
         if (it >= 30 && !(mu[k - 1] > 0.0))
             return fail(c, MLB_ENOPOS, "fewer than k positive buckling factors at the coarse level");
+        // compact the active residual columns (and, below, the active search
+        // directions) to the front of their blocks; every move is to a lower
+        // or equal column, in increasing order, so no source is overwritten
+        // before it is read
+        for (int a = 0; a < na; ++a)
+            if (act[a] != a) launch_copy_cols(n, 1, n, c->eR + n * act[a], n, c->eR + n * a, c->st);
+        if (rp > 0) {
+            for (int a = 0; a < na; ++a)
+                if (act[a] != a)
+                    for (double* base : {b.S, b.KS, b.AS})
+                        launch_copy_cols(n, 1, n, base + n * (nb + act[a]), n, base + n * (nb + a), c->st);
+            rp = na;
+            // K-orthonormalise the active directions against X (twice) and
+            // among themselves (SVQB), updating their images by the same
+            // combinations, so that [X P W] below is K-orthonormal block by
+            // block and its Rayleigh-Ritz problem well conditioned
+            double *P = b.S + n * nb, *KP = b.KS + n * nb, *AP = b.AS + n * nb;
+            for (int pass = 0; pass < 2; ++pass) {
+                CHK(gram(c, n, rp, P, n, nb, KX, n, G));
+                Co.assign((size_t)nb * rp, 0.0);   // Co[a, q] = -(X^T K P)[a, q]
+                for (int a = 0; a < nb; ++a)
+                    for (int q = 0; q < rp; ++q) Co[a + (size_t)nb * q] = -G[q + (size_t)rp * a];
+                CHK(upload_cm(c, c->cbuf2, Co));
+                launch_gemm_cat(n, nb, n, X, 0, n, nullptr, rp, c->cbuf2, 1.0, n, P, c->st);
+                launch_gemm_cat(n, nb, n, KX, 0, n, nullptr, rp, c->cbuf2, 1.0, n, KP, c->st);
+                launch_gemm_cat(n, nb, n, AX, 0, n, nullptr, rp, c->cbuf2, 1.0, n, AP, c->st);
+            }
+            CHK(gram(c, n, rp, P, n, rp, KP, n, G));
+            const int rq = svqb(rp, G, 1e-10, Tm);
+            if (rq < 0) return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: P^T K P is not a finite Gram matrix");
+            if (rq > 0) {
+                CHK(upload_cm(c, c->cbuf, Tm));
+                launch_xform_inplace(n, rp, rq, c->cbuf, n, P, c->st);
+                launch_xform_inplace(n, rp, rq, c->cbuf, n, KP, c->st);
+                launch_xform_inplace(n, rp, rq, c->cbuf, n, AP, c->st);
+            }
+            rp = rq;
+        }
+        const int64_t oW = n * (nb + rp);
+        double *W = b.S + oW, *KW = b.KS + oW, *AW = b.AS + oW;
         // W = T R
         if (verbose) {
             CHK(sync(c));
@@ -1050,11 +1104,11 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         }
         // (eig_sweeps stationary multigrid iterations from zero: a symmetric
         // preconditioner that approximates (K^l)^-1 better than one cycle)
-        CHK(precondition(c, j, nb, c->eR, W));
+        CHK(precondition(c, j, na, c->eR, W));
         for (int sw = 1; sw < c->o.eig_sweeps; ++sw) {   // W += B (R - K W)
-            apply_K<double>(c, j, nb, W, c->eP, kModeResidual, c->eR, nullptr);
-            CHK(precondition(c, j, nb, c->eP, c->ePK));
-            launch_axpby(n * nb, 1.0, c->ePK, 1.0, W, c->st);
+            apply_K<double>(c, j, na, W, c->eP, kModeResidual, c->eR, nullptr);
+            CHK(precondition(c, j, na, c->eP, c->ePK));
+            launch_axpby(n * na, 1.0, c->ePK, 1.0, W, c->st);
         }
         if (verbose) {
             CHK(sync(c));
@@ -1063,26 +1117,26 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         // W -= [X P] ([K X, K P]^T W), twice
         const int nx = nb + rp;
         for (int pass = 0; pass < 2; ++pass) {
-            CHK(gram(c, n, nb, W, n, nx, KX, n, G));
-            Co.assign((size_t)nx * nb, 0.0);   // Co[a, q] = G[q, a]
+            CHK(gram(c, n, na, W, n, nx, KX, n, G));
+            Co.assign((size_t)nx * na, 0.0);   // Co[a, q] = G[q, a]
             for (int a = 0; a < nx; ++a)
-                for (int q = 0; q < nb; ++q) Co[a + (size_t)nx * q] = G[q + (size_t)nb * a];
+                for (int q = 0; q < na; ++q) Co[a + (size_t)nx * q] = G[q + (size_t)na * a];
             CHK(upload_cm(c, c->cbuf2, Co));
-            launch_gemm_cat(n, nx, n, X, 0, n, nullptr, nb, c->cbuf2, 0.0, n, c->eR, c->st);
-            launch_axpby(n * nb, -1.0, c->eR, 1.0, W, c->st);
+            launch_gemm_cat(n, nx, n, X, 0, n, nullptr, na, c->cbuf2, 0.0, n, c->eR, c->st);
+            launch_axpby(n * na, -1.0, c->eR, 1.0, W, c->st);
         }
-        applyKA(nb, W, KW, AW);
-        CHK(gram(c, n, nb, W, n, nb, KW, n, G));
-        const int rw = svqb(nb, G, 1e-10, Tm);
+        applyKA(na, W, KW, AW);
+        CHK(gram(c, n, na, W, n, na, KW, n, G));
+        const int rw = svqb(na, G, 1e-10, Tm);
         if (rw < 0) return fail(c, MLB_EBREAKDOWN, "coarse eigensolver: W^T K W is not a finite Gram matrix");
         if (rw == 0) {   // the preconditioned residual vanished: nothing new to add
             stalled = true;
             break;
         }
         CHK(upload_cm(c, c->cbuf, Tm));
-        launch_xform_inplace(n, nb, rw, c->cbuf, n, W, c->st);
-        launch_xform_inplace(n, nb, rw, c->cbuf, n, KW, c->st);
-        launch_xform_inplace(n, nb, rw, c->cbuf, n, AW, c->st);
+        launch_xform_inplace(n, na, rw, c->cbuf, n, W, c->st);
+        launch_xform_inplace(n, na, rw, c->cbuf, n, KW, c->st);
+        launch_xform_inplace(n, na, rw, c->cbuf, n, AW, c->st);
         int ncol = nx + rw;
         int np_ = rp;   // P columns inside the Ritz basis
         CHK(gram2(c, n, ncol, b.S, ncol, b.KS, b.AS, GK, GA));
