@@ -64,8 +64,15 @@ def adjoint_rhs(nel, x, phi, fixed, mat):
     Gunit = _unit_stress_stiffness(dim, mat.nu)
     _, Es = fem.moduli(np.asarray(x, dtype=np.float64), mat)
     ed = fem.element_dofs(nel)
-    pe = np.asarray(phi)[ed]
-    loc = Es[:, None] * np.einsum("ei,aij,ej->ea", pe, Gunit, pe)
+    nde = Gunit.shape[0]
+    # loc[e, a] = phi_e^T G_e0[e_a] phi_e = sum_ij phi_ei phi_ej G_e0[e_a]_ij,
+    # evaluated as (phi_e outer phi_e) . G_e0[e_a] over blocks of elements
+    Gmat = Gunit.transpose(1, 2, 0).reshape(nde * nde, nde)
+    loc = np.empty((len(ed), nde))
+    for lo in range(0, len(ed), 65536):
+        pe = np.asarray(phi)[ed[lo:lo + 65536]]
+        loc[lo:lo + 65536] = (pe[:, :, None] * pe[:, None, :]).reshape(-1, nde * nde) @ Gmat
+    loc *= Es[:, None]
     b = np.bincount(ed.ravel(), weights=loc.ravel(), minlength=fem.n_dofs(nel))
     b[np.asarray(fixed) != 0] = 0.0
     return b

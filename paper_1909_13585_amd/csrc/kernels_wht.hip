@@ -149,6 +149,31 @@ constexpr int kXcd3 = 8;        // XCDs the blocks are dealt over
 #ifndef MLB_WHT3_WAVES
 #define MLB_WHT3_WAVES 2
 #endif
+
+// Work of one block of a 3D apply launched with `cgrid` column groups on the
+// grid (gridDim.x = cgrid x tile blocks, tile blocks a multiple of kXcd3).
+// Block b runs on XCD b mod kXcd3; the tile blocks of each XCD form one
+// contiguous range of the tile order, and the cgrid groups of a tile block
+// are consecutive there.  `slot` is the block's index in a launch with one
+// group (partial dot products go to part[col * nblk + slot], so every column
+// is reduced in the same order whatever cgrid is).
+struct WhtSlot {
+    int64_t bl, slot, nblk;
+    int c0, c1;
+};
+__device__ inline WhtSlot wht_slot(int cgrid, int ncols) {
+    WhtSlot s;
+    s.nblk = gridDim.x / cgrid;
+    const int64_t per_xcd = s.nblk / kXcd3;
+    const int64_t li = blockIdx.x / kXcd3;
+    const int grp = (int)(li % cgrid);
+    s.bl = (blockIdx.x % kXcd3) * per_xcd + li / cgrid;
+    s.slot = (s.bl % per_xcd) * kXcd3 + s.bl / per_xcd;
+    const int per = (ncols + cgrid - 1) / cgrid;
+    s.c0 = grp * per;
+    s.c1 = min(ncols, s.c0 + per);
+    return s;
+}
 // CLEAN: the caller guarantees x == 0 at every Dirichlet DOF (true for every
 // vector inside the solvers), so neighbour values need no masking; only the
 // owned node's mask is read (identity rows).
@@ -159,15 +184,18 @@ template <typename T, int MODE, bool DOT, bool CLEAN, bool PF>
 __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(PF || DOT ? MLB_WHT3_WAVES : 3, 8))) void k_apply_wht3(
     Geo g, int kz_chunk, int ntiles_x, int ntiles_y, const T* __restrict__ E, const uint8_t* __restrict__ nmask,
     WhtBlocks<T> B, int ncols, int64_t ld, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ r,
-    const T* __restrict__ dinv, T omega, double* __restrict__ part) {
+    const T* __restrict__ dinv, T omega, double* __restrict__ part, int cgrid) {
     __shared__ double sh[16];
     const int lane = threadIdx.x;              // 0..63
     const int tx = lane & 7, ty = lane >> 3;
     // Blocks are dealt round robin over the 8 XCDs; each XCD gets one
     // contiguous range of the (z-chunk major) tile order, so the node planes
     // and columns that neighbouring tiles share are re-read from its own L2.
-    const int64_t per_xcd = gridDim.x / kXcd3;   // grid is a multiple of kXcd3
-    const int64_t bl = (blockIdx.x % kXcd3) * per_xcd + blockIdx.x / kXcd3;
+    // With cgrid column groups on the grid, the groups of one tile block are
+    // consecutive on the same XCD (its modulus, masks and diagonal are read
+    // from HBM once and then from that L2).
+    const WhtSlot sl = wht_slot(cgrid, ncols);
+    const int64_t bl = sl.bl;
     const int64_t tile = bl * kW3 + threadIdx.y;
     const int64_t ntile_xy = (int64_t)ntiles_x * ntiles_y;
     const int tzc = (int)(tile / ntile_xy);
@@ -180,7 +208,7 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(PF || 
     const bool owner = tx >= 1 && ty >= 1 && ie >= 0 && je >= 0 && ie <= g.nx && je <= g.ny;
     const int64_t plane = (int64_t)g.nnx * g.nny;
     const int64_t eplane = (int64_t)g.nx * g.ny;
-    const int64_t nblk = gridDim.x;
+    const int64_t nblk = sl.nblk;
     // per-lane node columns (ie+ax, je+ay): in-plane index and validity
     int64_t base[4];
     bool qok[4];
@@ -191,7 +219,7 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(PF || 
         base[q] = qok[q] ? ii + (int64_t)g.nnx * jj : 0;
     }
     const int64_t ebase = col_ok ? ie + (int64_t)g.nx * je : 0;
-    for (int col = 0; col < ncols; ++col) {
+    for (int col = sl.c0; col < sl.c1; ++col) {
         const T* xc = x + col * ld;
         double dsum = 0.0;
         // values (and, unless CLEAN, masks) of the 4 nodes of node plane kk;
@@ -290,7 +318,7 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(PF || 
         }
         if (DOT) {
             const double bs = wht_block_sum(dsum, sh);
-            if (lane == 0 && threadIdx.y == 0) part[col * nblk + blockIdx.x] = bs;
+            if (lane == 0 && threadIdx.y == 0) part[col * nblk + sl.slot] = bs;
         }
     }
 }
@@ -396,18 +424,18 @@ __device__ inline void blocks3_scaled(const T (&s)[9], T (&u)[3][8]) {
 }
 
 template <typename T, int MODE, bool DOT, bool CLEAN>
-__global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(MLB_WHT3_WAVES, 8))) void k_apply_wht3r(
+__global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && CLEAN ? 4 : MLB_WHT3_WAVES, 8))) void k_apply_wht3r(
     Geo g, int kz_chunk, int ntiles_x, int ntiles_y, const T* __restrict__ E, const uint8_t* __restrict__ nmask,
     WhtBlocks<T> B, int ncols, int64_t ld, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ r,
-    const T* __restrict__ dinv, T omega, double* __restrict__ part) {
+    const T* __restrict__ dinv, T omega, double* __restrict__ part, int cgrid) {
     // no contraction: the loop is unrolled twice and both copies must round
     // alike, so that results do not depend on the pencil length
 #pragma clang fp contract(off)
     __shared__ double sh[16];
     const int lane = threadIdx.x;
     const int tx = lane & 7, ty = lane >> 3;
-    const int64_t per_xcd = gridDim.x / kXcd3;
-    const int64_t bl = (blockIdx.x % kXcd3) * per_xcd + blockIdx.x / kXcd3;
+    const WhtSlot sl = wht_slot(cgrid, ncols);
+    const int64_t bl = sl.bl;
     // the wave's index in its block, as a wave-uniform value: everything
     // derived from it (pencil, loop bounds, plane offsets) stays scalar
     const int wib = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
@@ -440,12 +468,12 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(MLB_WH
     const __amdgpu_buffer_rsrc_t rM = buf_rsrc(nmask, (uint32_t)g.nodes);
     const __amdgpu_buffer_rsrc_t rD = buf_rsrc(dinv, MODE == kModeJacobi ? xbytes : 0u);
     const T dd0 = B.v[0] - B.v[1], dd7 = B.v[2] - B.v[3];
-    const int64_t nblk = gridDim.x;
+    const int64_t nblk = sl.nblk;
     // byte offsets of node plane kk / element layer ke (out of range: zeros)
     auto poff = [&](int kk) -> uint32_t { return kk >= 0 && kk < g.nnz ? (uint32_t)kk * xplane : kOffPlane; };
     auto moff = [&](int kk) -> uint32_t { return kk >= 0 && kk < g.nnz ? (uint32_t)kk * plane : kOffPlane; };
     auto eoff = [&](int ke) -> uint32_t { return ke >= 0 && ke < g.nz ? (uint32_t)ke * eplane : kOffPlane; };
-    for (int col = 0; col < ncols; ++col) {
+    for (int col = sl.c0; col < sl.c1; ++col) {
         const __amdgpu_buffer_rsrc_t rX = buf_rsrc(x + col * ld, xbytes);
         const __amdgpu_buffer_rsrc_t rY = buf_rsrc(y + col * ld, xbytes);
         const __amdgpu_buffer_rsrc_t rR = buf_rsrc(r + col * ld, MODE == kModeY ? 0u : xbytes);
@@ -600,7 +628,7 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(MLB_WH
         if (kW3rSched >= 1) flush();
         if (DOT) {
             const double bs = wht_block_sum(dsum, sh);
-            if (lane == 0 && threadIdx.y == 0) part[col * nblk + blockIdx.x] = bs;
+            if (lane == 0 && threadIdx.y == 0) part[col * nblk + sl.slot] = bs;
         }
     }
 }
@@ -783,10 +811,16 @@ __global__ __launch_bounds__(kTX2* kTW2) void k_apply_wht2(Geo g, int ky_chunk, 
                                                            int ncols, int64_t ld, const T* __restrict__ x,
                                                            T* __restrict__ y, const T* __restrict__ r,
                                                            const T* __restrict__ dinv, T omega,
-                                                           double* __restrict__ part) {
+                                                           double* __restrict__ part, int cgrid) {
     __shared__ double sh[16];
     const int tx = threadIdx.x;
-    const int64_t tile = (int64_t)blockIdx.x * kTW2 + threadIdx.y;
+    // cgrid column groups on the grid, the groups of one tile block
+    // consecutive; partial dot products go to the block's one-group slot
+    const int64_t blk = blockIdx.x / cgrid;
+    const int64_t nblk = gridDim.x / cgrid;
+    const int per = (ncols + cgrid - 1) / cgrid;
+    const int c0 = (int)(blockIdx.x % cgrid) * per, c1 = min(ncols, c0 + per);
+    const int64_t tile = blk * kTW2 + threadIdx.y;
     const int tile_x = (int)(tile % ntiles_x);
     const int tile_y = (int)(tile / ntiles_x);
     const int ie = tile_x * (kTX2 - 1) - 1 + tx;
@@ -794,9 +828,7 @@ __global__ __launch_bounds__(kTX2* kTW2) void k_apply_wht2(Geo g, int ky_chunk, 
     const int kend = min(ky0 + ky_chunk, g.nny);
     const bool col_ok = ie >= 0 && ie < g.nx;
     const bool owner = tx >= 1 && ie >= 0 && ie <= g.nx;
-    const int64_t blk = blockIdx.x;
-    const int64_t nblk = gridDim.x;
-    for (int col = 0; col < ncols; ++col) {
+    for (int col = c0; col < c1; ++col) {
         const T* xc = x + col * ld;
         T cx[2][2], craw[2], cout[2][2];
         double dsum = 0.0;
@@ -942,17 +974,20 @@ void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, c
     if (dim == 3 && variant == 3 &&
         ((uint64_t)g.nodes * 3 * sizeof(T) > kMaxBufBytes || (uint64_t)g.m * sizeof(T) > kMaxBufBytes))
         variant = 0;
+    // one column per block group (the LDS variant walks its columns itself)
+    const int cgrid = (dim == 3 && variant == 1) ? 1 : std::max(1, ncols);
+    const dim3 grc(gr.x * cgrid, gr.y, gr.z);
 #define MLB_L3C(M, D, C)                                                                                          \
     do {                                                                                                          \
         if (variant == 3)                                                                                         \
-            hipLaunchKernelGGL((k_apply_wht3r<T, M, D, C>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B, ncols, ld, \
-                               x, y, r, dinv, omega, dot_part);                                                   \
+            hipLaunchKernelGGL((k_apply_wht3r<T, M, D, C>), grc, b, 0, st, g, ch, ntx, nty, E, nmask, B, ncols, ld, \
+                               x, y, r, dinv, omega, dot_part, cgrid);                                            \
         else if (variant == 2)                                                                                    \
-            hipLaunchKernelGGL((k_apply_wht3<T, M, D, C, false>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B,      \
-                               ncols, ld, x, y, r, dinv, omega, dot_part);                                        \
+            hipLaunchKernelGGL((k_apply_wht3<T, M, D, C, false>), grc, b, 0, st, g, ch, ntx, nty, E, nmask, B,     \
+                               ncols, ld, x, y, r, dinv, omega, dot_part, cgrid);                                 \
         else                                                                                                      \
-            hipLaunchKernelGGL((k_apply_wht3<T, M, D, C, true>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B,       \
-                               ncols, ld, x, y, r, dinv, omega, dot_part);                                        \
+            hipLaunchKernelGGL((k_apply_wht3<T, M, D, C, true>), grc, b, 0, st, g, ch, ntx, nty, E, nmask, B,      \
+                               ncols, ld, x, y, r, dinv, omega, dot_part, cgrid);                                 \
     } while (0)
 #define MLB_L3(M, D)                       \
     do {                                   \
@@ -960,8 +995,8 @@ void launch_apply_wht(int dim, const Geo& g, const T* E, const uint8_t* nmask, c
         else MLB_L3C(M, D, false);         \
     } while (0)
 #define MLB_L2(M, D)                                                                                              \
-    hipLaunchKernelGGL((k_apply_wht2<T, M, D>), gr, b, 0, st, g, ch, ntx, E, nmask, B, ncols, ld, x, y, r, dinv, omega, \
-                       dot_part)
+    hipLaunchKernelGGL((k_apply_wht2<T, M, D>), grc, b, 0, st, g, ch, ntx, E, nmask, B, ncols, ld, x, y, r, dinv,  \
+                       omega, dot_part, cgrid)
 #define MLB_LL(M, D)                                                                                              \
     hipLaunchKernelGGL((k_apply_wht3_lds<T, M, D>), gr, b, 0, st, g, ch, ntx, nty, E, nmask, B, ncols, ld, x, y, r,  \
                        dinv, omega, dot_part)
