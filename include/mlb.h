@@ -146,6 +146,8 @@ typedef struct {
                              are visited by colour (i mod 3) + 3 (j mod 3) + 9 (k mod 3), then by
                              component.  > 0 sets the count (at most 16), < 0 sets none (the
                              default: the main text's method), 0 keeps the current value */
+    int coarse_sweeps;    /* Jacobi sweeps before and after the coarse correction on levels >= 3,
+                             where sweeps are cheap (> 0 sets it, at most 64; default: smooth_steps) */
 } mlb_opts;
 
 /* Per-call solver report; for blocks, the worst column is reported. */

@@ -478,7 +478,8 @@ int build(mlb_batch* b) {
                                    b->Af + sc.soff, b->dinv + sc.voff, b->dinvf + sc.voff, st);
             else
                 launch_assemble_dense(2, geo_of(sc), b->Ke + b->keoff[si], b->nmask + sc.noff,
-                                      2 * (int64_t)sc.nnx * sc.nny, b->Ainv + sc.coff, st);
+                                      2 * (int64_t)sc.nnx * sc.nny, 2 * (int64_t)sc.nnx * sc.nny,
+                                      b->Ainv + sc.coff, st);
         }
     }
     launch_bq_gj((int)b->cs.size(), b->dcs, b->dseg, b->Ainv, st);

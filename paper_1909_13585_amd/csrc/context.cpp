@@ -96,9 +96,13 @@ struct mlb_ctx {
     double tol_solve = 1e-8;
     int max_it = 1000;
     double* S = nullptr;   // element stresses of the reference case (SoA nv x m)
-    // coarsest level dense inverse
+    // coarsest level: dense FP64 inverse (N x N, N = n_L rounded up to a
+    // multiple of 64, identity pad), its block Gauss-Jordan work buffers and
+    // the split-K partial products of the coarsest solve
     double* Ainv = nullptr;
-    double *gj_r0 = nullptr, *gj_c0 = nullptr, *gj_r1 = nullptr, *gj_c1 = nullptr;
+    int64_t nA = 0;
+    int nsplit = 1;
+    double *gjP = nullptr, *gjR = nullptr, *gjC = nullptr, *cpart = nullptr;
     // block work (fine level, cg_cap columns)
     int cg_cap = 0;
     double *R = nullptr, *Zb = nullptr, *Pb = nullptr, *Qb = nullptr, *Zo = nullptr, *X1 = nullptr, *X2 = nullptr;
@@ -138,6 +142,8 @@ struct mlb_ctx {
 namespace {
 
 constexpr int kScal = 256;
+// largest coarsest level (DOFs) inverted explicitly: 16384^2 doubles = 2 GiB
+constexpr int64_t kMaxCoarsest = 16384;
 
 int fail(mlb_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
@@ -319,10 +325,13 @@ void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z) {
     Level& l = c->lv[j - 1];
     if (j == c->L) {
         if (c->L == 1) launch_jacobi0<T>(l.n, nc, l.n, l.dinv ? dinv_of<T>(l) : nullptr, (T)1.0, r, z, c->st);
-        else launch_dense_matvec<T>(l.n, nc, l.n, c->Ainv, r, z, c->st);
+        else
+            for (int c0 = 0; c0 < nc; c0 += 32)   // the product takes up to 32 columns
+                launch_coarse_solve<T>(l.n, c->nA, std::min(32, nc - c0), l.n, c->Ainv, r + c0 * l.n, z + c0 * l.n,
+                                       c->nsplit, c->cpart, c->st);
         return;
     }
-    const int nu = std::max(1, c->o.smooth_steps);
+    const int nu = std::max(1, j >= 3 && c->o.coarse_sweeps > 0 ? c->o.coarse_sweeps : c->o.smooth_steps);
     T* a = lbuf<T>(l, 2);   // current iterate alternates between a and b
     T* b = z;
     T* t = lbuf<T>(l, 3);
@@ -605,15 +614,11 @@ int build_hierarchy(mlb_ctx* c) {
     } else {
         Level& lL = c->lv[c->L - 1];
         const int64_t nL = lL.n;
-        HIPC(hipMemsetAsync(c->Ainv, 0, sizeof(double) * nL * nL, c->st));
-        launch_assemble_dense(dim, lL.g, lL.Ke, lL.nmask, nL, c->Ainv, c->st);
-        double *r0 = c->gj_r0, *c0 = c->gj_c0, *r1 = c->gj_r1, *c1 = c->gj_c1;
-        launch_gj_init(nL, c->Ainv, r0, c0, c->st);
-        for (int64_t k = 0; k < nL; ++k) {
-            launch_gj_step(nL, k, c->Ainv, r0, c0, r1, c1, c->st);
-            std::swap(r0, r1);
-            std::swap(c0, c1);
-        }
+        const int64_t N = c->nA;
+        HIPC(hipMemsetAsync(c->Ainv, 0, sizeof(double) * N * N, c->st));
+        launch_assemble_dense(dim, lL.g, lL.Ke, lL.nmask, nL, N, c->Ainv, c->st);
+        launch_pad_identity(nL, N, c->Ainv, c->st);
+        launch_block_inverse(N, c->Ainv, c->gjP, c->gjR, c->gjC, c->st);
     }
     CHK(sync(c));
     return MLB_OK;
@@ -1610,15 +1615,18 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     c->m = c->lv[0].g.m;
     if (c->L > 1) {
         const int64_t nL = c->lv[c->L - 1].n;
-        if (nL > 8192) {
-            c->err = "coarsest level has " + std::to_string(nL) + " DOFs (> 8192): use more multigrid levels";
+        if (nL > kMaxCoarsest) {
+            c->err = "coarsest level has " + std::to_string(nL) + " DOFs (> " + std::to_string(kMaxCoarsest) +
+                     "): use more multigrid levels";
             return MLB_EINVAL;
         }
-        CHK(dalloc(c, &c->Ainv, (size_t)nL * nL));
-        CHK(dalloc(c, &c->gj_r0, (size_t)nL));
-        CHK(dalloc(c, &c->gj_c0, (size_t)nL));
-        CHK(dalloc(c, &c->gj_r1, (size_t)nL));
-        CHK(dalloc(c, &c->gj_c1, (size_t)nL));
+        c->nA = coarse_pad(nL);
+        c->nsplit = coarse_splits(c->nA);
+        CHK(dalloc(c, &c->Ainv, (size_t)c->nA * c->nA));
+        CHK(dalloc(c, &c->gjP, (size_t)64 * 64));
+        CHK(dalloc(c, &c->gjR, (size_t)64 * c->nA));
+        CHK(dalloc(c, &c->gjC, (size_t)64 * c->nA));
+        CHK(dalloc(c, &c->cpart, (size_t)c->nsplit * 32 * c->nA));
     }
     if (c->ell > 1) {
         Level& le = c->lv[c->ell - 1];
@@ -1651,8 +1659,8 @@ void mlb_destroy(mlb_ctx* c) {
     }
     dfree(c->dK0); dfree(c->fK0); dfree(c->dHk); dfree(c->dBc); dfree(c->dD0Bc); dfree(c->dD0); dfree(c->dT);
     dfree(c->dMc); dfree(c->dGHc); dfree(c->x); dfree(c->Ek); dfree(c->Ekf); dfree(c->Es); dfree(c->fixed);
-    dfree(c->F); dfree(c->U); dfree(c->S); dfree(c->Ainv); dfree(c->gj_r0); dfree(c->gj_c0);
-    dfree(c->gj_r1); dfree(c->gj_c1); dfree(c->R); dfree(c->Zb); dfree(c->Pb); dfree(c->Qb); dfree(c->Zo);
+    dfree(c->F); dfree(c->U); dfree(c->S); dfree(c->Ainv); dfree(c->gjP); dfree(c->gjR);
+    dfree(c->gjC); dfree(c->cpart); dfree(c->R); dfree(c->Zb); dfree(c->Pb); dfree(c->Qb); dfree(c->Zo);
     dfree(c->X1); dfree(c->X2); dfree(c->Phi); dfree(c->Zadj); dfree(c->dlam_l); dfree(c->eS); dfree(c->eK);
     dfree(c->eA); dfree(c->eT); dfree(c->eTK); dfree(c->eTA); dfree(c->eR); dfree(c->eP); dfree(c->ePK); dfree(c->ePA); dfree(c->part); dfree(c->pidx);
     dfree(c->scal); dfree(c->iscal); dfree(c->gbuf); dfree(c->cbuf); dfree(c->cbuf2);
@@ -1681,6 +1689,7 @@ int mlb_set_opts(mlb_ctx* c, const mlb_opts* o) {
     if (o->graphs > 0) c->o.graphs = o->graphs == 1 ? 1 : 2;
     if (o->pinvit_steps > 0) c->o.pinvit_steps = std::min(o->pinvit_steps, 64);
     else if (o->pinvit_steps < 0) c->o.pinvit_steps = 0;
+    if (o->coarse_sweeps > 0) c->o.coarse_sweeps = std::min(o->coarse_sweeps, 64);
     if (o->refine_sweeps > 0) c->o.refine_sweeps = std::min(o->refine_sweeps, 16);
     else if (o->refine_sweeps < 0) c->o.refine_sweeps = 0;
     drop_graphs(c);

@@ -61,13 +61,19 @@ void launch_galerkin_G_from_S(int dim, const Geo& gf, const Geo& gc, const doubl
 void launch_galerkin_dense(int dim, bool kron, const Geo& gf, const Geo& gc, const double* Kf,
                            const double* T, double* Kc, hipStream_t st);
 void launch_to_float(int64_t n, const double* a, float* b, hipStream_t st);
-void launch_assemble_dense(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, int64_t n,
+void launch_assemble_dense(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, int64_t n, int64_t ld,
                            double* A, hipStream_t st);
-void launch_gj_init(int64_t n, const double* A, double* rowk, double* colk, hipStream_t st);
-void launch_gj_step(int64_t n, int64_t k, double* A, const double* rowk, const double* colk,
-                    double* rowk1, double* colk1, hipStream_t st);
+void launch_pad_identity(int64_t n, int64_t N, double* A, hipStream_t st);
+// coarsest level on the matrix cores (kernels_dense.hip): N = n rounded up
+// to a multiple of 64; the inverse is N x N row-major with an identity pad
+int coarse_pad(int64_t n);
+int coarse_splits(int64_t N);
+void launch_gemm_f64(int M, int N, int K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     double beta, double* C, int64_t ldc, hipStream_t st);
+void launch_block_inverse(int64_t N, double* A, double* P, double* R, double* Cp, hipStream_t st);
 template <typename T>
-void launch_dense_matvec(int64_t n, int ncols, int64_t ld, const double* A, const T* x, T* y, hipStream_t st);
+void launch_coarse_solve(int64_t n, int64_t N, int nc, int64_t ld, const double* A, const T* x, T* z, int nsplit,
+                         double* part, hipStream_t st);
 
 // ---- vector kernels (kernels_blas.hip)
 template <typename T>

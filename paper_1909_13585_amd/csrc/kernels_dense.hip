@@ -1,0 +1,240 @@
+// Dense FP64 linear algebra of the coarsest multigrid level on the matrix
+// cores: the explicit inverse of the coarsest Galerkin matrix (blocked
+// Gauss-Jordan, whose rank-b updates are FP64 MFMA GEMMs) and the coarsest
+// solve z = A^-1 r as a split-K MFMA product that reads the inverse once
+// for up to 32 columns.
+//
+// Matrix-core instruction: v_mfma_f64_16x16x4f64, D(16x16) += A(16x4) B(4x16)
+// over a 64-lane wave.  Operand layout (lane l, 0..63):
+//   A: element (l % 16, l / 16)            one double per lane
+//   B: element (l / 16, l % 16)            one double per lane
+//   D: element (l / 16 + 4 r, l % 16)      r = 0..3, four doubles per lane
+#include "kernels.h"
+
+namespace mlb {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma16x16x4(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// C = alpha A B + beta C, all row-major FP64; M, N multiples of 64, K a
+// multiple of 16.  One 256-thread block per 64 x 64 tile of C (wave w owns
+// the 32 x 32 quarter (w / 2, w % 2), four 16 x 16 MFMA tiles); A and B
+// stream through LDS in 16-deep slices.  beta == 0 never reads C.
+constexpr int kGT = 64;   // tile edge
+constexpr int kGK = 16;   // K slice
+__global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                                  int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
+                                                  double* __restrict__ C, int64_t ldc) {
+    __shared__ double As[kGT * kGK];   // [row][k]
+    __shared__ double Bs[kGK * kGT];   // [k][col]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.y * kGT, c0 = (int64_t)blockIdx.x * kGT;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    v4d acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += kGK) {
+        // 1024 entries of each slice, 4 per thread, coalesced along rows
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;
+            const int ar = e / kGK, ak = e % kGK;          // A slice: 64 rows x 16
+            As[e] = A[(r0 + ar) * lda + k0 + ak];
+            const int bk = e / kGT, bc = e % kGT;          // B slice: 16 x 64 cols
+            Bs[e] = B[(int64_t)(k0 + bk) * ldb + c0 + bc];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kGK; ks += 4) {
+            const int kk = ks + (lane >> 4);
+            double av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = As[(wr + 16 * a + (lane & 15)) * kGK + kk];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[kk * kGT + wc + 16 * b + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x4(av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + wr + 16 * a + (lane >> 4) + 4 * r;
+                const int64_t col = c0 + wc + 16 * b + (lane & 15);
+                double* p = C + row * ldc + col;
+                *p = beta == 0.0 ? alpha * acc[a][b][r] : fma(alpha, acc[a][b][r], beta * *p);
+            }
+}
+
+// In-place inverse of the 64 x 64 diagonal block at (k0, k0) of A (row-major,
+// leading dimension ld) into P (64 x 64, row-major) by scalar Gauss-Jordan
+// in LDS; the block is SPD (a Schur complement of an SPD matrix), so no
+// pivoting.  One block of 256 threads.
+__global__ __launch_bounds__(256) void k_gj_diag(const double* __restrict__ A, int64_t ld, int64_t k0,
+                                                 double* __restrict__ P) {
+    __shared__ double s[kGT * kGT];
+    __shared__ double rowk[kGT], colk[kGT];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kGT * kGT; e += 256) s[e] = A[(k0 + e / kGT) * ld + k0 + e % kGT];
+    __syncthreads();
+    for (int k = 0; k < kGT; ++k) {
+        if (tid < kGT) {
+            rowk[tid] = s[k * kGT + tid];
+            colk[tid] = s[tid * kGT + k];
+        }
+        __syncthreads();
+        const double p = rowk[k];
+        for (int e = tid; e < kGT * kGT; e += 256) {
+            const int i = e / kGT, j = e % kGT;
+            double v;
+            if (i == k && j == k) v = 1.0 / p;
+            else if (i == k) v = rowk[j] / p;
+            else if (j == k) v = -colk[i] / p;
+            else v = s[e] - colk[i] * (rowk[j] / p);
+            s[e] = v;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < kGT * kGT; e += 256) P[e] = s[e];
+}
+
+// dst (rows x 64, leading dimension ldd) = src (leading dimension lds)
+__global__ void k_copy_panel(int64_t rows, const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                             int64_t ldd) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= rows * kGT) return;
+    const int64_t i = t / kGT, j = t % kGT;
+    dst[i * ldd + j] = src[i * lds + j];
+}
+
+// A = (A + A^T) / 2 for an N x N row-major matrix (each pair once)
+__global__ void k_symmetrize(int64_t N, double* __restrict__ A) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * N) return;
+    const int64_t i = t / N, j = t % N;
+    if (j <= i) return;
+    const double v = 0.5 * (A[i * N + j] + A[j * N + i]);
+    A[i * N + j] = v;
+    A[j * N + i] = v;
+}
+
+// Partial products of Z = A X with A symmetric N x N (row-major) and X the
+// n x nc level block (column-major, leading dimension ld, rows >= n read as
+// zero), computed as Z^T = X^T A: wave (tile, split) forms the 16 (or 32)
+// columns x 16 rows of Z^T for rows j0 .. j0 + 15 over its share of the
+// K range, so every row of A is read by one wave per tile, 4 full 128-byte
+// lines per load.  part[(split * 32 + c) * N + j].
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_part(int64_t n, int64_t N, int nc, int64_t ld,
+                                                     const double* __restrict__ A, const T* __restrict__ x,
+                                                     int nsplit, double* __restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t ntiles = N / 16;
+    if (wid >= ntiles * nsplit) return;
+    const int64_t tile = wid / nsplit;
+    const int split = (int)(wid % nsplit);
+    const int64_t kchunk = (N / 4 + nsplit - 1) / nsplit * 4;
+    const int64_t kb = split * kchunk, ke = min(N, kb + kchunk);
+    const int64_t j0 = tile * 16;
+    const int cl = lane & 15, kl = lane >> 4;
+    const bool two = nc > 16;
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = kb; k < ke; k += 4) {
+        const int64_t kr = k + kl;
+        const double b = A[kr * N + j0 + cl];
+        const double a0 = (cl < nc && kr < n) ? (double)x[cl * ld + kr] : 0.0;
+        acc0 = mfma16x16x4(a0, b, acc0);
+        if (two) {
+            const double a1 = (cl + 16 < nc && kr < n) ? (double)x[(cl + 16) * ld + kr] : 0.0;
+            acc1 = mfma16x16x4(a1, b, acc1);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int c = kl + 4 * r;
+        part[((int64_t)split * 32 + c) * N + j0 + cl] = acc0[r];
+        if (two) part[((int64_t)split * 32 + c + 16) * N + j0 + cl] = acc1[r];
+    }
+}
+
+// z[c * ld + j] = sum over splits of the partials (fixed order), j < n, c < nc
+template <typename T>
+__global__ void k_coarse_sum(int64_t n, int64_t N, int nc, int64_t ld, int nsplit, const double* __restrict__ part,
+                             T* __restrict__ z) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n * nc) return;
+    const int64_t c = t / n, j = t % n;
+    double s = 0.0;
+    for (int q = 0; q < nsplit; ++q) s += part[((int64_t)q * 32 + c) * N + j];
+    z[c * ld + j] = (T)s;
+}
+
+static inline unsigned nbk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+int coarse_pad(int64_t n) { return (int)((n + kGT - 1) / kGT * kGT); }
+
+int coarse_splits(int64_t N) {
+    // enough waves to cover the chip (>= ~2048) with >= 64 k-steps per wave
+    const int64_t tiles = N / 16;
+    int s = 1;
+    while (tiles * s < 2048 && N / (4 * (s * 2)) >= 64) s *= 2;
+    return s;
+}
+
+void launch_gemm_f64(int M, int N, int K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     double beta, double* C, int64_t ldc, hipStream_t st) {
+    hipLaunchKernelGGL(k_gemm_f64, dim3(N / kGT, M / kGT), dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
+                       ldc);
+}
+
+// In-place inverse of the N x N SPD matrix A (N a multiple of 64; pad with an
+// identity block) by 64-wide panels: P = A_KK^-1, R = P A_K:, C = A_:K,
+// A -= C R, A_:K = -C P, A_K: = R, A_KK = P; then A = (A + A^T) / 2.
+// Work: P (64 x 64), R (64 x N), C (N x 64), all device.
+void launch_block_inverse(int64_t N, double* A, double* P, double* R, double* Cp, hipStream_t st) {
+    const int n = (int)N;
+    for (int64_t k0 = 0; k0 < N; k0 += kGT) {
+        hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, st, A, N, k0, P);
+        launch_gemm_f64(kGT, n, kGT, 1.0, P, kGT, A + k0 * N, N, 0.0, R, N, st);
+        hipLaunchKernelGGL(k_copy_panel, dim3(nbk(N * kGT)), dim3(256), 0, st, N, A + k0, N, Cp, (int64_t)kGT);
+        launch_gemm_f64(n, n, kGT, -1.0, Cp, kGT, R, N, 1.0, A, N, st);
+        launch_gemm_f64(n, kGT, kGT, -1.0, Cp, kGT, P, kGT, 0.0, A + k0, N, st);
+        hipLaunchKernelGGL(k_copy_panel, dim3(nbk(kGT * (N / kGT) * kGT)), dim3(256), 0, st, (int64_t)kGT, R, N,
+                           A + k0 * N, N);
+        // the rest of row block K (columns outside K) from R, 64 columns at a time
+        for (int64_t c = 0; c < N; c += kGT)
+            if (c != k0)
+                hipLaunchKernelGGL(k_copy_panel, dim3(nbk(kGT * kGT)), dim3(256), 0, st, (int64_t)kGT, R + c, N,
+                                   A + k0 * N + c, N);
+        hipLaunchKernelGGL(k_copy_panel, dim3(nbk(kGT * kGT)), dim3(256), 0, st, (int64_t)kGT, P, (int64_t)kGT,
+                           A + k0 * N + k0, N);
+    }
+    hipLaunchKernelGGL(k_symmetrize, dim3(nbk(N * N)), dim3(256), 0, st, N, A);
+}
+
+template <typename T>
+void launch_coarse_solve(int64_t n, int64_t N, int nc, int64_t ld, const double* A, const T* x, T* z, int nsplit,
+                         double* part, hipStream_t st) {
+    const int64_t waves = N / 16 * nsplit;
+    hipLaunchKernelGGL(k_coarse_part<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, n, N, nc, ld, A, x,
+                       nsplit, part);
+    hipLaunchKernelGGL(k_coarse_sum<T>, dim3(nbk(n * nc)), dim3(256), 0, st, n, N, nc, ld, nsplit, part, z);
+}
+template void launch_coarse_solve<double>(int64_t, int64_t, int, int64_t, const double*, const double*, double*, int,
+                                          double*, hipStream_t);
+template void launch_coarse_solve<float>(int64_t, int64_t, int, int64_t, const double*, const float*, float*, int,
+                                         double*, hipStream_t);
+
+}  // namespace mlb

@@ -142,14 +142,14 @@ __global__ void k_to_float(int64_t n, const double* __restrict__ a, float* __res
 // One thread per row: each thread writes only its own row.
 template <int DIM>
 __global__ void k_assemble_dense(Geo g, const double* __restrict__ Ke, const uint8_t* __restrict__ nmask, int64_t n,
-                                 double* __restrict__ A) {
+                                 int64_t ld, double* __restrict__ A) {
     constexpr int NN = 1 << DIM, ND = DIM, NDE = DIM << DIM;
     const int64_t rowdof = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (rowdof >= n) return;
     const int64_t node = rowdof / ND;
     const int c = (int)(rowdof % ND);
     const int i = (int)(node % g.nnx), j = (int)((node / g.nnx) % g.nny), k = (int)(node / ((int64_t)g.nnx * g.nny));
-    double* Ar = A + rowdof * n;
+    double* Ar = A + rowdof * ld;
     if ((nmask[node] >> c) & 1) {
         Ar[rowdof] = 1.0;
         return;
@@ -172,66 +172,10 @@ __global__ void k_assemble_dense(Geo g, const double* __restrict__ Ke, const uin
     }
 }
 
-// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting needed),
-// one launch per pivot k.  rowk/colk hold row k and column k as they were
-// before step k (pivot = rowk[k]); each step also records row/column k+1
-// after its own update for the next launch.
-__global__ void k_gj_init(int64_t n, const double* __restrict__ A, double* __restrict__ rowk,
-                          double* __restrict__ colk) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    rowk[t] = A[t];          // row 0
-    colk[t] = A[t * n];      // column 0
-}
-
-__global__ void k_gj_step(int64_t n, int64_t k, double* __restrict__ A, const double* __restrict__ rowk,
-                          const double* __restrict__ colk, double* __restrict__ rowk1, double* __restrict__ colk1) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= n * n) return;
-    const int64_t i = t / n, j = t % n;
-    const double p = rowk[k];
-    double v;
-    if (i == k && j == k) v = 1.0 / p;
-    else if (i == k) v = rowk[j] / p;
-    else if (j == k) v = -colk[i] / p;
-    else v = A[t] - colk[i] * (rowk[j] / p);
-    A[t] = v;
-    if (k + 1 < n) {
-        if (i == k + 1) rowk1[j] = v;
-        if (j == k + 1) colk1[i] = v;
-    }
-}
-
-// y = A x for a dense symmetric FP64 matrix, one wavefront per row.
-// y = A x for a dense row-major A (coarsest inverse), one wave per row, up
-// to 8 columns per pass so each row is read once per 8 columns.
-template <typename T, int CB>
-__global__ void k_dense_matvec(int64_t n, int ncols, int64_t ld, const double* __restrict__ A,
-                               const T* __restrict__ x, T* __restrict__ y) {
-    const int lane = threadIdx.x & 63;
-    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    if (row >= n) return;
-    const double* Ar = A + row * n;
-    for (int c0 = 0; c0 < ncols; c0 += CB) {
-        const int nq = min(CB, ncols - c0);
-        double s[CB];
-#pragma unroll
-        for (int q = 0; q < CB; ++q) s[q] = 0.0;
-#pragma unroll 4
-        for (int64_t j = lane; j < n; j += 64) {
-            const double a = Ar[j];
-#pragma unroll
-            for (int q = 0; q < CB; ++q)
-                if (q < nq) s[q] += a * (double)x[(c0 + q) * ld + j];
-        }
-#pragma unroll
-        for (int q = 0; q < CB; ++q) {
-            double v = s[q];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-            if (lane == 0 && q < nq) y[(c0 + q) * ld + row] = (T)v;
-        }
-    }
+// A[i * N + i] = 1 for n <= i < N (identity padding of the coarsest matrix)
+__global__ void k_pad_identity(int64_t n, int64_t N, double* __restrict__ A) {
+    const int64_t i = n + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < N) A[i * N + i] = 1.0;
 }
 
 // ---- launchers
@@ -277,26 +221,13 @@ void launch_galerkin_dense(int dim, bool kron, const Geo& gf, const Geo& gc, con
 void launch_to_float(int64_t n, const double* a, float* b, hipStream_t st) {
     hipLaunchKernelGGL(k_to_float, dim3(nb1(n)), dim3(kBlock), 0, st, n, a, b);
 }
-void launch_assemble_dense(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, int64_t n, double* A,
-                           hipStream_t st) {
-    if (dim == 2) hipLaunchKernelGGL(k_assemble_dense<2>, dim3(nb1(n)), dim3(kBlock), 0, st, g, Ke, nmask, n, A);
-    else hipLaunchKernelGGL(k_assemble_dense<3>, dim3(nb1(n)), dim3(kBlock), 0, st, g, Ke, nmask, n, A);
+void launch_assemble_dense(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, int64_t n, int64_t ld,
+                           double* A, hipStream_t st) {
+    if (dim == 2) hipLaunchKernelGGL(k_assemble_dense<2>, dim3(nb1(n)), dim3(kBlock), 0, st, g, Ke, nmask, n, ld, A);
+    else hipLaunchKernelGGL(k_assemble_dense<3>, dim3(nb1(n)), dim3(kBlock), 0, st, g, Ke, nmask, n, ld, A);
 }
-void launch_gj_init(int64_t n, const double* A, double* rowk, double* colk, hipStream_t st) {
-    hipLaunchKernelGGL(k_gj_init, dim3(nb1(n)), dim3(kBlock), 0, st, n, A, rowk, colk);
+void launch_pad_identity(int64_t n, int64_t N, double* A, hipStream_t st) {
+    if (N > n) hipLaunchKernelGGL(k_pad_identity, dim3(nb1(N - n)), dim3(kBlock), 0, st, n, N, A);
 }
-void launch_gj_step(int64_t n, int64_t k, double* A, const double* rowk, const double* colk, double* rowk1,
-                    double* colk1, hipStream_t st) {
-    hipLaunchKernelGGL(k_gj_step, dim3(nb1(n * n)), dim3(kBlock), 0, st, n, k, A, rowk, colk, rowk1, colk1);
-}
-template <typename T>
-void launch_dense_matvec(int64_t n, int ncols, int64_t ld, const double* A, const T* x, T* y, hipStream_t st) {
-    if (ncols == 1)
-        hipLaunchKernelGGL((k_dense_matvec<T, 1>), dim3(nb1(n * 64)), dim3(kBlock), 0, st, n, ncols, ld, A, x, y);
-    else
-        hipLaunchKernelGGL((k_dense_matvec<T, 8>), dim3(nb1(n * 64)), dim3(kBlock), 0, st, n, ncols, ld, A, x, y);
-}
-template void launch_dense_matvec<double>(int64_t, int, int64_t, const double*, const double*, double*, hipStream_t);
-template void launch_dense_matvec<float>(int64_t, int, int64_t, const double*, const float*, float*, hipStream_t);
 
 }  // namespace mlb

@@ -125,3 +125,41 @@ def test_vcycle_symmetric_and_contracting(nel, L):
     e1 = e - from_dev(zd1)
     assert (e1 @ (K @ e1)) < 0.5 * (e @ (K @ e))
     c.close()
+
+
+# coarsest grids of 2,450 / 810 / 1,215 DOFs: not multiples of 64 (identity
+# pad), 13 to 39 panels of the block inverse, 2 to 8 K splits of the product,
+# 1 to 33 columns (two column tiles, and a second pass above 32)
+@pytest.mark.parametrize("nel,L,ncols", [((96, 48), 2, 1), ((96, 48), 2, 20), ((104, 56), 3, 33),
+                                         ((32, 16, 32), 3, 12)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_coarsest_solve_is_exact_inverse(nel, L, ncols, precision):
+    # The V-cycle entered at the coarsest level is the exact solve with the
+    # Galerkin coarsest matrix (blocked Gauss-Jordan inverse on the matrix
+    # cores, FP64 in both precisions; in mixed precision the block enters and
+    # leaves in FP32).
+    print(f"case coarsest nel={nel} L={L} ncols={ncols} precision={precision}", flush=True)
+    dim = len(nel)
+    x = W.random_small(dim, nel, 41)
+    fixed = W.clamp_mask(nel)
+    grids, masks, Ps, Ks = oracle_levels(nel, x, fixed, L)
+    c = _ctx(nel, L, x, fixed, precision=precision)
+    torch = __import__("torch")
+    KL = Ks[L - 1].toarray()
+    nL = KL.shape[0]
+    freeL = masks[L - 1] == 0
+    R = W.random_vectors(nL, ncols, 42) * freeL[:, None]
+    zd = torch.empty((ncols, nL), dtype=torch.float64, device="cuda")
+    c.vcycle_dev(L, to_dev(R), zd)
+    torch.cuda.synchronize()
+    Z = from_dev(zd)
+    Zo = np.linalg.solve(KL, R)
+    if precision == 0:
+        # the inverse is exact to ~eps cond(K_L)
+        assert rel_inf(Z, Zo) < 1e-9
+    else:
+        # FP32 in and out: every column to FP32 rounding of the inputs
+        for q in range(ncols):
+            assert rel_inf(Z[:, q], Zo[:, q]) < 1e-4, q
+    assert np.all(Z[~freeL] == 0)
+    c.close()
