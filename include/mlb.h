@@ -370,6 +370,18 @@ int mlb_sed_tv_dev(mlb_ctx* ctx, int q, const double* Phi, double xbar, double* 
 int mlb_dilate_dev(mlb_ctx* ctx, int nsel, const double* gradn, double rel_thr, double r_th, const double* x,
                    double* xout, void* stream);
 
+/* mlb_dilate_dev for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, bit for bit, with the partial maxima in
+ * a fixed per-GPU scratch array of the library (525 KiB, held until the
+ * process ends) instead of the context's growable buffers.  It calls no
+ * allocating routine.  nsel <= 64 (MLB_EINVAL above).  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (other streams,
+ * other contexts, other threads) race; calls ordered on one stream do not.
+ * Enqueue only. */
+int mlb_dilate_noalloc_dev(mlb_ctx* ctx, int nsel, const double* gradn, double rel_thr, double r_th,
+                           const double* x, double* xout, void* stream);
+
 /* ---- three-field design variables (Sec. 2) ------------------------------ */
 
 /* Density filter and relaxed Heaviside projection (eq. projectionOperator):

@@ -297,6 +297,16 @@ class Context:
         self._check(self.lib.mlb_dilate_dev(self.h, nsel, _dptr(gradn), rel_thr, r_th, _dptr(x), _dptr(xout),
                                             _stream()))
 
+    def dilate_noalloc_dev(self, gradn, rel_thr, r_th, x, xout):
+        """dilate_dev without any device allocation (fixed per-GPU scratch;
+        calls that overlap on one GPU race)."""
+        nsel = gradn.shape[0] if gradn.dim() > 1 else 1
+        self._block(gradn, nsel, self.m, "gradn")
+        self._block(x, 1, self.m, "x")
+        self._block(xout, 1, self.m, "xout")
+        self._check(self.lib.mlb_dilate_noalloc_dev(self.h, nsel, _dptr(gradn), rel_thr, r_th, _dptr(x),
+                                                    _dptr(xout), _stream()))
+
     def filter_project_dev(self, xhat, rmin, eta, beta, xtilde, x):
         """Density filter of radius rmin and Heaviside projection (eta, beta) of
         the design variables xhat (m,) into xtilde and x (m,) (Sec. 2)."""

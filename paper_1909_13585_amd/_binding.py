@@ -125,6 +125,7 @@ _SIGS = {
     "mlb_mac_dev": (_I, [_P, _I, _P, _I, _P, _P, _P, _P]),
     "mlb_sed_tv_dev": (_I, [_P, _I, _P, _D, _P, _P, _P, _P]),
     "mlb_dilate_dev": (_I, [_P, _I, _P, _D, _D, _P, _P, _P]),
+    "mlb_dilate_noalloc_dev": (_I, [_P, _I, _P, _D, _D, _P, _P, _P]),
     "mlb_filter_project_dev": (_I, [_P, _P, _D, _D, _D, _P, _P, _P]),
     "mlb_filter_chain_dev": (_I, [_P, _I, _P, _D, _D, _D, _P, _P, _P, _P]),
     # warm-start network kernels (include/mlb_nn.h)

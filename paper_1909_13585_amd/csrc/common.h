@@ -14,6 +14,10 @@ constexpr int nv_of(int dim) { return dim == 2 ? 3 : 6; }
 
 constexpr int kBlock = 256;          // threads per block for 1D kernels
 constexpr int kMaxPartials = 1024;   // blocks per reduction stage
+// fixed device scratch of the no-allocation entry points (scratch.hip):
+// per-block partial maxima and the maxima of up to kNoallocMaxSel rows
+constexpr int kNoallocMaxSel = 64;
+constexpr int64_t kScratchDoubles = (int64_t)kMaxPartials * kNoallocMaxSel + kNoallocMaxSel;
 
 // Geometry of one grid level (unit elements at level 1).
 struct Geo {

@@ -118,6 +118,7 @@ struct mlb_ctx {
     // reductions and scalars
     double* part = nullptr;
     int64_t part_cap = 0;
+    double* scratch = nullptr;   // the device's fixed scratch array (kScratchDoubles)
     int64_t* pidx = nullptr;
     double* scal = nullptr;   // 16 blocks of kScal doubles
     double* gbuf = nullptr;   // summed Gram matrices (up to 96 x 192)
@@ -1566,6 +1567,13 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
         *out = c;
         return MLB_EDEVICE;
     }
+    // the fixed scratch of the no-allocation entry points, looked up once per
+    // device with that device current
+    if (scratch_address(desc->device, &c->scratch) != hipSuccess) {
+        c->err = "no address for the device scratch array";
+        *out = c;
+        return MLB_EDEVICE;
+    }
     *out = c;
     HIPC(hipStreamCreate(&c->own));
     c->st = c->own;
@@ -2008,6 +2016,30 @@ int mlb_dilate_dev(mlb_ctx* c, int nsel, const double* gradn, double rel_thr, do
     double* gmax = c->part + (int64_t)np * nsel;
     launch_infnorm_part(g.m, nsel, g.m, gradn, np, c->part, c->st);
     launch_max_parts(nsel, np, c->part, gmax, c->st);
+    launch_dilate(c->dim, g, nsel, gradn, gmax, rel_thr, r_th, x, xout, c->st);
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+int mlb_dilate_noalloc_dev(mlb_ctx* c, int nsel, const double* gradn, double rel_thr, double r_th, const double* x,
+                           double* xout, void* stream) {
+    if (!c || !gradn || !x || !xout || nsel < 1) return MLB_EINVAL;
+    if (nsel > kNoallocMaxSel)
+        return fail(c, MLB_EINVAL, "mlb_dilate_noalloc_dev takes at most " + std::to_string(kNoallocMaxSel) +
+                                       " rows of gradn (the fixed scratch holds no more)");
+    if (!(r_th >= 0.0 && r_th <= 8.0)) return fail(c, MLB_EINVAL, "r_th must be in [0, 8]");
+    if (!(rel_thr >= 0.0) || !std::isfinite(rel_thr)) return fail(c, MLB_EINVAL, "rel_thr must be >= 0 and finite");
+    const Geo& g = c->lv[0].g;
+    if (x < xout + g.m && xout < x + g.m) return fail(c, MLB_EINVAL, "x and xout must not overlap");
+    const int np = grad_tv_parts(g);
+    if ((int64_t)np * nsel + nsel > kScratchDoubles) return fail(c, MLB_EINVAL, "scratch too small");
+    c->st = pick(c, stream);
+    // every slot the kernels read is written first in the same call (one
+    // partial per block and row, then one maximum per row): nothing is cleared
+    double* part = c->scratch;
+    double* gmax = c->scratch + (int64_t)np * nsel;
+    launch_infnorm_part(g.m, nsel, g.m, gradn, np, part, c->st);
+    launch_max_parts(nsel, np, part, gmax, c->st);
     launch_dilate(c->dim, g, nsel, gradn, gmax, rel_thr, r_th, x, xout, c->st);
     HIPC(hipGetLastError());
     return MLB_OK;

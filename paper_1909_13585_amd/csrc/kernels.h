@@ -140,6 +140,9 @@ int grad_tv_parts(const Geo& g);
 void launch_grad_tv(int dim, const Geo& g, const double* x, double xbar, int q, const double* sed, double* gradn,
                     double* part, hipStream_t st);
 // xout = dilation of x around elements flagged by gradn >= rel_thr * gmax (nsel rows)
+// device address of the fixed scratch array on `device` (which must be the
+// current device); looked up once per device (scratch.hip)
+hipError_t scratch_address(int device, double** out);
 void launch_dilate(int dim, const Geo& g, int nsel, const double* gradn, const double* gmax, double rel_thr,
                    double r_th, const double* x, double* xout, hipStream_t st);
 
