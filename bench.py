@@ -1,22 +1,29 @@
 """Benchmark: full linearized buckling analysis on the 2.4M-DOF H8 box.
 
 One step = one complete analysis with the densities already in HBM:
-SIMP moduli + multigrid hierarchy (Galerkin levels, coarsest inverse),
-static MG-PCG solve to 1e-8, element stresses, Galerkin K^l/G^l, 12 coarse
-modes (LOBPCG to 1e-8), interpolation, 12-column fine block solve
-K Phi = G Psi to 1e-8, Rayleigh-Ritz, compliance sensitivities, 12 adjoint
-solves (block, 1e-8) and buckling sensitivities.  The default precision is
-mixed (FP32 multigrid cycle inside FP64 Krylov solvers, the workload's
-configuration); the plain FP64 path is timed in the same run and reported
-beside it.  Prints ONE JSON line (rank 0, N = 1 only).
+SIMP moduli + multigrid hierarchy (Galerkin levels, coarsest FP64 inverse on
+the matrix cores), static MG-PCG solve to 1e-8, element stresses, Galerkin
+K^l/G^l, 12 coarse modes (LOBPCG to 1e-8), interpolation, 12-column fine
+block solve K Phi = G Psi to 1e-8, Rayleigh-Ritz, compliance sensitivities,
+12 adjoint solves (block, 1e-8) and buckling sensitivities.  The default is
+mixed precision (FP32 multigrid cycle inside FP64 Krylov solvers) on a
+4-level hierarchy (2 Jacobi sweeps on levels 1-2, 4 on level 3, omega =
+1.5 / (1.05 rho)), the fastest setting of the multigrid study; the 5-level
+hierarchy and the plain FP64 path are timed in the same run and reported
+beside it, with the achieved residuals of every solve.  Prints ONE JSON line
+(rank 0, N = 1 only).
 
-Also reported: MG-PCG throughput of the static solve (free DOFs x iterations
-/ solve time) and the roofline of the fine-level H8 stiffness apply, timed
-with HIP events on the stream the library launches on.
+Also reported: MG-PCG throughput of the static solve, the 960x320 column in
+FP64 (the oracle solves it directly), the 16-column block solve on the
+96x48x48 box, the roofline of the dominant kernel (the 12-column FP32
+Jacobi sweep of the fine level, timed with HIP events on the stream the
+library launches on), and the oracle timed on the host on a bounded sample
+of the same workload recipe, next to the GPU on that sample.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -24,15 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the fine FP64 1-column apply, per 3D variant (0
-# register tiles, 1 LDS tiles, 2 register tiles without prefetch, 3 register
-# tiles with per-plane transforms): rocprofv3 FETCH_SIZE x (copy factor,
-# 1.99977 and 1.99963 in the two runs) + WRITE_SIZE x 1.0 (factors from a
-# 256 MiB calibration copy), KiB per dispatch, from
-# profiles/fine_apply_h8_192x64x64_hbm_counters.md; None where the counters
-# were not taken for the current kernel.
-FINE_KERNELS = {0: "k_apply_wht3", 1: "k_apply_wht3_lds", 2: "k_apply_wht3 (no prefetch)", 3: "k_apply_wht3r"}
-TRAFFIC_BYTES = {0: (17363 * 1.99977 + 19153) * 1024, 1: None, 2: None, 3: (17031 * 1.99963 + 19169) * 1024}
+# HBM bytes per launch of the dominant kernel (12-column FP32 Jacobi sweep of
+# the fine level, variant and z chunk as tuned at 192x64x64): rocprofv3
+# FETCH_SIZE x copy factor + WRITE_SIZE x copy factor, KiB per dispatch, from
+# the counter summary under profiles/; None until counters were taken for
+# the current kernel.
+SWEEP_TRAFFIC_BYTES = None
 
 
 def parse():
@@ -48,15 +52,22 @@ def parse():
     ap.add_argument("--learned", default=os.path.join(ROOT, "paper_1909_13585_amd", "data", "warmstart_unet.npz"),
                     help="trained warm-start network; the learned leg is timed when the file exists")
     ap.add_argument("--nel", type=str, default="192,64,64")
-    ap.add_argument("--levels", type=int, default=5)
+    ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--smooth", type=int, default=2, help="Jacobi sweeps per half cycle on levels 1-2")
+    ap.add_argument("--coarse-sweeps", type=int, default=4, help="Jacobi sweeps per half cycle on levels >= 3")
+    ap.add_argument("--omega", type=float, default=1.5, help="Jacobi weight times 1.05 rho(D^-1 A)")
     ap.add_argument("--eig-level", type=int, default=3)
     ap.add_argument("--modes", type=int, default=12)
+    ap.add_argument("--no-five-level", action="store_true", help="skip the 5-level hierarchy leg")
+    ap.add_argument("--no-column", action="store_true", help="skip the 960x320 column leg")
+    ap.add_argument("--no-block16", action="store_true", help="skip the 16-column block leg on 96x48x48")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-reps", type=int, default=3, help="oracle runs of the CPU sample (median reported)")
     ap.add_argument("--instances-only", action="store_true",
                     help="run only the 32 independent 2D instances and print their JSON object")
     ap.add_argument("--no-instances", action="store_true",
                     help="skip the 32 independent 2D instances (batched vs one context at a time)")
-    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--sweep-reps", type=int, default=50)
     ap.add_argument("--no-post", action="store_true",
                     help="skip the post-processing measures (strain energy density, variation, correlation, dilation) "
                          "and the design chain (filter, projection, chain rule)")
@@ -65,52 +76,114 @@ def parse():
     ap.add_argument("--no-pinvit", action="store_true",
                     help="skip the legs with preconditioned inverse iteration steps on the fine modes and with "
                          "the intermediate-level refinement")
-    ap.add_argument("--wht-variant", type=int, default=-1,
-                    help="with --roofline-only: fine-apply variant to run (0 register tiles, 1 LDS tiles, "
-                         "2 register tiles without prefetch, 3 register tiles with per-plane transforms)")
-    ap.add_argument("--wht-zchunk", type=int, default=0,
-                    help="with --roofline-only: pencil length of the fine apply (0 keeps the default)")
     ap.add_argument("--roofline-only", action="store_true",
-                    help="only the dominant-kernel timing and a copy of known size (for counter runs)")
+                    help="only the dominant-kernel sweeps and a copy of known size (for counter runs)")
     return ap.parse_args()
 
 
-CPU_SAMPLE = (64, 12, 12)
+CPU_SAMPLE = (40, 16, 16)
 
 
 def cpu_baseline(args):
-    """The oracle (sparse direct + LAPACK/ARPACK) on a bounded sample of the
-    same workload recipe: 64x12x12 H8 box, eigen level 2, 12 modes."""
-    import numpy as np
-    try:
-        from threadpoolctl import threadpool_limits
-    except ImportError:  # pragma: no cover
-        threadpool_limits = None
+    """The oracle (SuperLU, LAPACK/ARPACK, numpy) on a bounded sample of the
+    same workload recipe, in a child process that imports only the oracle and
+    the input generators: per-phase times, median of `cpu_reps` runs, peak
+    RSS, BLAS threads, CPU model."""
+    code = r"""
+import json, resource, sys, time
+sys.path.insert(0, %r)
+import numpy as np
+from threadpoolctl import threadpool_info
+import workloads as W
+from oracle import fem, lba, sens
+nel = %r
+p = W.box_3d(nel=nel, seed=3)
+mat = fem.Material()
+runs = []
+for rep in range(%d):
+    ph = {}
+    t = time.perf_counter()
+    K = fem.constrain(fem.assemble_K(nel, p["x"], mat), p["fixed"], 1.0); ph["assembly"] = time.perf_counter() - t
+    t = time.perf_counter(); solver = lba.FreeSolver(K, p["fixed"]); ph["factorization"] = time.perf_counter() - t
+    t = time.perf_counter(); U, J, _ = lba.static_solve(K, p["F"], p["fixed"], solver); ph["static"] = time.perf_counter() - t
+    t = time.perf_counter()
+    u = U[:, 0]
+    s = fem.element_stresses(nel, p["x"], u, mat)
+    G = fem.constrain(fem.assemble_G(nel, s), p["fixed"], 0.0); ph["stress_G"] = time.perf_counter() - t
+    t = time.perf_counter()
+    b = lba.multilevel_buckling(nel, p["x"], u, p["fixed"], mat, 2, 12, K=K, G=G, solver=solver)
+    ph["multilevel_eigen"] = time.perf_counter() - t
+    t = time.perf_counter()
+    sens.compliance_sensitivity(nel, p["x"], U, mat)
+    sens.buckling_sensitivity(nel, p["x"], u, b.lam, b.phi, p["fixed"], mat, solver)
+    ph["sensitivities"] = time.perf_counter() - t
+    ph["total"] = sum(ph.values())
+    runs.append(ph)
+tot = sorted(r["total"] for r in runs)
+med = min(runs, key=lambda r: abs(r["total"] - tot[len(tot) // 2]))
+blas = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas")
+model = ""
+try:
+    for line in open("/proc/cpuinfo"):
+        if line.startswith("model name"):
+            model = line.split(":", 1)[1].strip(); break
+except OSError:
+    pass
+print(json.dumps({"median": med, "totals": tot, "dofs": int(fem.n_dofs(nel)), "lambda1": float(b.lam[0]),
+                  "rss_gb": resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / 1e6, "blas_threads": blas,
+                  "cpu_model": model, "logical_cpus": len(__import__("os").sched_getaffinity(0))}))
+""" % (ROOT, CPU_SAMPLE, args.cpu_reps)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=1200)
+    if r.returncode != 0:
+        raise RuntimeError("oracle sample failed: " + r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def gpu_on_cpu_sample(args, reps=3):
+    """The GPU analysis (same precision and settings) on the CPU sample box."""
+    import torch
+    import paper_1909_13585_amd as mlb
     import workloads as W
-    from oracle import fem, lba, sens
     nel = CPU_SAMPLE
-    p = W.box_3d(nel=nel, seed=3, sigma=1.0)
-    mat = fem.Material()
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
-    t0 = time.perf_counter()
-    r = lba.analysis(nel, p["x"], p["F"], p["fixed"], mat, ell=2, q=args.modes)
-    sens.compliance_sensitivity(nel, p["x"], r["U"], mat)
-    sens.buckling_sensitivity(nel, p["x"], r["u"], r["buck"].lam, r["buck"].phi, p["fixed"], mat, r["solver"])
-    t = time.perf_counter() - t0
-    if ctx is not None:
-        ctx.__exit__(None, None, None)
-    n_sample = W.n_dofs(nel)
-    return t, n_sample
+    p = W.box_3d(nel=nel, seed=3)
+    ctx = mlb.Context(nel, mg_levels=3, eig_level=2, precision=mlb.MLB_MIXED if args.precision == "mixed" else 0)
+    ctx.set_bc(p["fixed"])
+    ctx.set_loads(p["F"])
+    n, m = ctx.level_size(1)
+    xd = torch.from_numpy(p["x"]).cuda()
+    U = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    dJ = torch.empty((1, m), dtype=torch.float64, device="cuda")
+    dl = torch.empty((args.modes, m), dtype=torch.float64, device="cuda")
+    ts = []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.set_density_dev(xd)
+        ctx.solve_static_dev(U, tol=1e-8, max_it=2000)
+        lam, _ = ctx.buckling_dev(args.modes, None, tol_eig=args.tol_eig)
+        ctx.sensitivities_dev(dJ, dl)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ctx.close()
+    ts = sorted(ts[1:])
+    return ts[len(ts) // 2], float(lam[0])
 
 
-def run_path(args, precision, p, x_dev, steps, warmup, label, net=None, element=0):
+def set_solver_opts(ctx, args):
+    ctx.set_opts(smooth_steps=args.smooth, coarse_sweeps=args.coarse_sweeps, jacobi_omega=args.omega)
+
+
+def run_path(args, precision, p, x_dev, steps, warmup, label, net=None, element=0, levels=None, tuned=True):
     """Times `steps` full analyses after `warmup` untimed ones.  With `net`,
-    every timed analysis first predicts its warm starts from the density."""
+    every timed analysis first predicts its warm starts from the density.
+    `tuned`: the benchmark's multigrid settings (else the library defaults)."""
     import torch
     import paper_1909_13585_amd as mlb
     nel = tuple(int(v) for v in args.nel.split(","))
-    ctx = mlb.Context(nel, mg_levels=args.levels, eig_level=args.eig_level, precision=precision,
+    ctx = mlb.Context(nel, mg_levels=levels or args.levels, eig_level=args.eig_level, precision=precision,
                       element=element)
+    if tuned:
+        set_solver_opts(ctx, args)
     ctx.set_bc(p["fixed"])
     ctx.set_loads(p["F"])
     n, m = ctx.level_size(1)
@@ -357,26 +430,141 @@ def design_leg(ctx, m, x_dev, k, reps=5, rmin=8.0, eta=0.5, beta=6.0):
             "filter_gweights_per_s": m * nt / (ms_f * 1e-3) / 1e9}
 
 
-def apply_roofline(ctx, n, m, reps, ncols=1):
-    """Fine-level H8 apply (public entry, FP64), HIP events on the stream the
-    library launches on (the caller's current stream)."""
+def sweep_timing(ctx, level, ncols, reps):
+    """Mean time (ms) of one Jacobi sweep of the cycle (the smoother kernel as
+    a cycle launches it), HIP events on the stream the library launches on
+    (the caller's current stream)."""
     import torch
-    xa = torch.randn((ncols, n) if ncols > 1 else (n,), dtype=torch.float64, device="cuda")
-    ya = torch.empty_like(xa)
-    for _ in range(5):
-        ctx.apply_K_dev(1, xa, ya)
+    ctx.sweep_dev(level, ncols, 5)
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(st)
-    for _ in range(reps):
-        ctx.apply_K_dev(1, xa, ya)
+    ctx.sweep_dev(level, ncols, reps)
     e1.record(st)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    nodes = n // 3
-    alg = ncols * 16 * n + 8 * m + nodes   # x read + y write per column, E_kappa, node mask
-    return ms, alg
+    return e0.elapsed_time(e1) / reps
+
+
+def sweep_bytes(dim, nel, level, ncols, word):
+    """Algorithmic HBM bytes of one Jacobi sweep of `ncols` columns on `level`:
+    per column x and r read and y written (3 words per DOF); D^-1 read once;
+    level 1 (matrix-free): one modulus per element and one mask byte per
+    node; coarser levels: the node-block stencil, 3^dim neighbour blocks of
+    dim x dim words per node."""
+    f = 2 ** (level - 1)
+    ne = [v // f for v in nel]
+    nodes = 1
+    for v in ne:
+        nodes *= v + 1
+    m = 1
+    for v in ne:
+        m *= v
+    n = dim * nodes
+    b = ncols * 3 * word * n + word * n
+    b += word * m + nodes if level == 1 else nodes * (3 ** dim) * dim * dim * word
+    return b
+
+
+def column_leg(args, steps=3):
+    """The 960x320 Q4 column (616,962 DOFs) in plain FP64 on 4 and 5 multigrid
+    levels: static solve + 12 modes on the 240x80 eigen level + sensitivities."""
+    import numpy as np
+    import torch
+    import paper_1909_13585_amd as mlb
+    import workloads as W
+    nel = (960, 320)
+    p = W.column_2d_large()
+    xd = torch.from_numpy(p["x"]).cuda()
+    out = {}
+    for L in (4, 5):
+        ctx = mlb.Context(nel, mg_levels=L, eig_level=3, precision=mlb.MLB_FP64)
+        ctx.set_bc(p["fixed"])
+        ctx.set_loads(p["F"])
+        n, m = ctx.level_size(1)
+        U = torch.empty((1, n), dtype=torch.float64, device="cuda")
+        dJ = torch.empty((1, m), dtype=torch.float64, device="cuda")
+        dl = torch.empty((12, m), dtype=torch.float64, device="cuda")
+        ts = []
+        for _ in range(steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.set_density_dev(xd)
+            J, si = ctx.solve_static_dev(U, tol=1e-8, max_it=3000)
+            lam, ei = ctx.buckling_dev(12, None, tol_eig=1e-8)
+            ai = ctx.sensitivities_dev(dJ, dl)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ctx.close()
+        ts = sorted(ts[1:])
+        out[f"levels_{L}"] = {"s_per_analysis": ts[len(ts) // 2], "static_iterations": si["iterations"],
+                              "static_true_rel_res": si["true_rel_residual"],
+                              "coarse_iterations": ei["coarse_iterations"], "coarse_residual": ei["coarse_residual"],
+                              "coarse_guard_fired": ei["coarse_guard_fired"],
+                              "fine_block_iterations": ei["fine_iterations"],
+                              "fine_true_rel_res": ei["fine_true_residual"],
+                              "adjoint_iterations": ai["iterations"], "adjoint_true_rel_res": ai["true_rel_residual"],
+                              "lambda1": float(lam[0])}
+        print(f"# column levels {L}: {out[f'levels_{L}']}", file=sys.stderr, flush=True)
+    return {"workload": "Q4 column 960x320 (616962 DOFs), FP64, eigen level 3 (240x80), 12 modes, 1e-8", **out}
+
+
+def block16_leg(args, reps=3):
+    """16-column block CG on the 96x48x48 box (698,691 DOFs, mixed precision):
+    4 static load cases (axial, shear y, shear z, torsion) and the 12 adjoint
+    right-hand sides of a prior analysis of the same density, one block solve
+    to 1e-8 per column, against the same 16 columns solved one at a time."""
+    import torch
+    import paper_1909_13585_amd as mlb
+    import workloads as W
+    nel = (96, 48, 48)
+    p = W.box_3d_four_cases(nel=nel)
+    ctx = mlb.Context(nel, mg_levels=4, eig_level=3, precision=mlb.MLB_MIXED)
+    set_solver_opts(ctx, args)
+    ctx.set_bc(p["fixed"])
+    ctx.set_loads(p["F"])
+    n, m = ctx.level_size(1)
+    xd = torch.from_numpy(p["x"]).cuda()
+    ctx.set_density_dev(xd)
+    ctx.autotune(16)
+    U = torch.empty((4, n), dtype=torch.float64, device="cuda")
+    ctx.solve_static_dev(U, tol=1e-8, max_it=3000)
+    ctx.buckling_dev(12, None, tol_eig=args.tol_eig)
+    dl = torch.empty((12, m), dtype=torch.float64, device="cuda")
+    ctx.sensitivities_dev(None, dl)
+    Badj = torch.empty((12, n), dtype=torch.float64, device="cuda")
+    ctx.adjoint_rhs_dev(12, Badj)
+    B = torch.cat([torch.from_numpy(p["F"].T.copy()).cuda(), Badj]).contiguous()
+    X = torch.empty_like(B)
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts = sorted(ts[1:])
+        return ts[len(ts) // 2], r
+
+    t_blk, info = timed(lambda: ctx.solve_block_dev(B, X, tol=1e-8, max_it=3000))
+    Xc = torch.empty((1, n), dtype=torch.float64, device="cuda")
+
+    def one_by_one():
+        its = []
+        for j in range(16):
+            its.append(ctx.solve_block_dev(B[j:j + 1].contiguous(), Xc, tol=1e-8, max_it=3000)["iterations"])
+        return its
+
+    t_col, its = timed(one_by_one)
+    ctx.close()
+    free = int(n - p["fixed"].sum())
+    return {"workload": "H8 box 96x48x48 (698691 DOFs), mixed, 4 levels: 4 load cases + 12 adjoint RHS",
+            "columns": 16, "s_block": t_blk, "block_iterations": info["iterations"],
+            "worst_true_rel_res": info["true_rel_residual"], "s_one_column_at_a_time": t_col,
+            "column_iterations": its, "speedup": t_col / t_blk,
+            "gdof_col_iter_per_s": free * 16 * info["iterations"] / t_blk / 1e9}
 
 
 def main():
@@ -397,33 +585,34 @@ def main():
     nel = tuple(int(v) for v in args.nel.split(","))
     p = W.box_3d(nel=nel, seed=3)
     x_dev = torch.from_numpy(p["x"]).cuda()
+    prec = mlb.MLB_MIXED if args.precision == "mixed" else mlb.MLB_FP64
+    word = 4 if args.precision == "mixed" else 8
 
     if args.roofline_only:
-        # counter runs: the fine apply, then a calibration copy of a buffer far
+        # counter runs: the dominant kernel (12-column Jacobi sweeps of the
+        # fine level, tuned tiles), then a calibration copy of a buffer far
         # larger than the L2 caches, written by a fill and flushed before
-        ctx = mlb.Context(nel, mg_levels=args.levels, eig_level=args.eig_level)
+        ctx = mlb.Context(nel, mg_levels=args.levels, eig_level=args.eig_level, precision=prec)
+        set_solver_opts(ctx, args)
         ctx.set_bc(p["fixed"])
         ctx.set_loads(p["F"])
         ctx.set_density_dev(x_dev)
-        if args.wht_variant >= 0 or args.wht_zchunk > 0:
-            ctx.set_tiles(args.wht_zchunk, 0, args.wht_variant)
-        n, m = ctx.level_size(1)
-        xa = torch.randn(n, dtype=torch.float64, device="cuda")
-        ya = torch.empty_like(xa)
-        for _ in range(args.apply_reps):
-            ctx.apply_K_dev(1, xa, ya)
+        tune = ctx.autotune(args.modes)
+        torch.cuda.synchronize()
+        ctx.sweep_dev(1, args.modes, args.sweep_reps)
         cal = 1 << 25   # 32 Mi doubles = 256 MiB
         src = torch.empty(cal, dtype=torch.float64, device="cuda").fill_(1.0)
         flush = torch.empty(cal, dtype=torch.float64, device="cuda").fill_(2.0)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"roofline_only": True, "n": n, "m": m, "copy_bytes": 8 * cal,
+        print(json.dumps({"roofline_only": True, "tiles": {k: tune[k] for k in ("wht_zchunk", "wht_variant")},
+                          "sweeps": args.sweep_reps, "copy_bytes": 8 * cal,
+                          "alg_bytes": sweep_bytes(3, nel, 1, args.modes, word),
                           "flush_bytes": int(flush.numel() * 8)}), flush=True)
         ctx.close()
         return
 
-    prec = mlb.MLB_MIXED if args.precision == "mixed" else mlb.MLB_FP64
     ctx, sec, out = run_path(args, prec, p, x_dev, args.steps, args.warmup, args.precision)
     J, si, lam, ei, ai = out
     n, m = ctx.level_size(1)
@@ -431,14 +620,29 @@ def main():
     free = int(n - p["fixed"].sum())
     gdofs = free * si["iterations"] / si["seconds"] / 1e9
 
-    var64 = ctx.tune["wht64_variant"] if ctx.tune else 0
-    apply_ms, alg_bytes = apply_roofline(ctx, n, m, args.apply_reps, 1)
-    achieved = alg_bytes / (apply_ms * 1e-3) / 1e9
+    # dominant kernel: the 12-column Jacobi sweep of the fine level; the
+    # level-2 stencil sweep beside it
+    sw1 = sweep_timing(ctx, 1, k, args.sweep_reps)
+    b1 = sweep_bytes(3, nel, 1, k, word)
+    sw2 = sweep_timing(ctx, 2, k, args.sweep_reps)
+    b2 = sweep_bytes(3, nel, 2, k, word)
     pinv = None if args.no_pinvit else pinvit_leg(ctx, k, n, args.tol_eig, lam)
     refine = None if args.no_pinvit else refine_leg(ctx, k, n, args.tol_eig, lam)
     postp = None if args.no_post else post_leg(ctx, k, n, m, x_dev, args.tol_eig)
     designp = None if args.no_post else design_leg(ctx, m, x_dev, k)
+    tiles = {q: ctx.tune[q] for q in ("wht_zchunk", "wht_variant", "wht64_zchunk", "wht64_variant",
+                                      "stencil_cols")} if ctx.tune else None
     ctx.close()
+
+    five = None
+    if not args.no_five_level:
+        ctx5, sec5, out5 = run_path(args, prec, p, x_dev, max(1, min(args.steps, 3)), 1, "five-level", levels=5,
+                                    tuned=False)
+        ctx5.close()
+        five = {"s_per_analysis": sec5, "levels": 5, "settings": "library defaults (2 sweeps, omega 4/3)",
+                "static_iterations": out5[1]["iterations"], "coarse_iterations": out5[3]["coarse_iterations"],
+                "fine_block_iterations": out5[3]["fine_iterations"], "adjoint_iterations": out5[4]["iterations"],
+                "max_rel_lambda_diff": float(np.max(np.abs(np.asarray(out5[2]) / np.asarray(lam) - 1)))}
 
     learned = None
     if os.path.exists(args.learned):
@@ -447,7 +651,7 @@ def main():
         ctxl, secl, outl = run_path(args, prec, p, x_dev, args.steps, 1, "learned", net=net)
         ctxl.close()
         learned = {"s_per_analysis": secl, "static_iterations": outl[1]["iterations"],
-                   "coarse_iterations": outl[3]["coarse_iterations"],
+                   "coarse_iterations": outl[3]["coarse_iterations"], "coarse_warm_used": outl[3]["coarse_warm_used"],
                    "fine_block_iterations": outl[3]["fine_iterations"],
                    "adjoint_iterations": outl[4]["iterations"],
                    "max_rel_lambda_diff_vs_cold": float(np.max(np.abs(np.asarray(outl[2]) / np.asarray(lam) - 1))),
@@ -466,7 +670,7 @@ def main():
 
     fp64 = None
     if args.precision == "mixed" and not args.no_fp64_reference:
-        ctx64, sec64, out64 = run_path(args, mlb.MLB_FP64, p, x_dev, max(1, min(args.steps, 2)), 1, "fp64")
+        ctx64, sec64, out64 = run_path(args, mlb.MLB_FP64, p, x_dev, max(1, min(args.steps, 3)), 1, "fp64")
         ctx64.close()
         fp64 = {"s_per_analysis": sec64, "static_iterations": out64[1]["iterations"],
                 "coarse_iterations": out64[3]["coarse_iterations"],
@@ -474,17 +678,24 @@ def main():
                 "adjoint_iterations": out64[4]["iterations"],
                 "max_rel_lambda_diff_vs_mixed": float(np.max(np.abs(np.asarray(out64[2]) / np.asarray(lam) - 1)))}
 
+    column = None if args.no_column else column_leg(args)
+    block16 = None if args.no_block16 else block16_leg(args)
     inst = None if args.no_instances else batched_instances()
 
     cpu = None
     if not args.no_cpu_baseline:
-        t_cpu, n_sample = cpu_baseline(args)
-        cpu = {"value": t_cpu * n / n_sample, "unit": "s/analysis", "cores": 1, "kind": "oracle",
-               "sample": (f"oracle analysis (SuperLU static + adjoint solves, dense/ARPACK coarse eigen, Ritz, "
-                          f"sensitivities) on the {CPU_SAMPLE[0]}x{CPU_SAMPLE[1]}x{CPU_SAMPLE[2]} H8 box of the "
-                          f"same recipe ({n_sample} DOFs, eigen level 2, {k} modes, one thread): {t_cpu:.2f}s, "
-                          f"scaled linearly in DOFs to {n} DOFs (a lower bound: direct solvers scale "
-                          f"superlinearly)")}
+        o = cpu_baseline(args)
+        g_s, g_l1 = gpu_on_cpu_sample(args)
+        med = o["median"]
+        cpu = {"value": med["total"], "unit": "s/analysis", "cores": o["blas_threads"], "kind": "oracle",
+               "sample": (f"oracle analysis (SuperLU factorization and solves, dense LAPACK eigen level, "
+                          f"Rayleigh-Ritz, adjoints, sensitivities) of the {CPU_SAMPLE[0]}x{CPU_SAMPLE[1]}x"
+                          f"{CPU_SAMPLE[2]} H8 box of the same recipe ({o['dofs']} DOFs, eigen level 2, {k} modes), "
+                          f"median of {len(o['totals'])} runs on the host, not scaled; the SuperLU "
+                          f"factorization runs on one thread, LAPACK on {o['blas_threads']}"),
+               "phases_s": med, "totals_s": o["totals"], "peak_rss_gb": o["rss_gb"], "cpu_model": o["cpu_model"],
+               "logical_cpus": o["logical_cpus"], "gpu_s_same_sample": g_s,
+               "lambda1_oracle": o["lambda1"], "lambda1_gpu": g_l1}
 
     line = {
         "metric": "buckling-analysis wall time @2.4M DOF, FP64 vs mixed/learned; MG-PCG GDOF/s",
@@ -500,30 +711,43 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"H8 box {nel[0]}x{nel[1]}x{nel[2]} ({n} DOFs), clamped x=0, unit axial load, "
-                               f"Gaussian-filtered density vf 0.3 (seed 3), {args.levels}-level MG, eigen level "
-                               f"{args.eig_level}, {k} modes, solves to 1e-8, coarse eigen to {args.tol_eig:g}",
+                               f"Gaussian-filtered density vf 0.3 (seed 3), {args.levels}-level MG "
+                               f"({args.smooth}/{args.smooth}/{args.coarse_sweeps} Jacobi sweeps, omega "
+                               f"{args.omega:g}/(1.05 rho); the 5-level hierarchy is timed in five_level_mg), "
+                               f"eigen level {args.eig_level}, {k} modes, solves to 1e-8, coarse eigen to "
+                               f"{args.tol_eig:g}",
                    "precision": args.precision},
-        "tiles": {k: ctx.tune[k] for k in ("wht_zchunk", "wht_variant", "wht64_zchunk", "wht64_variant", "stencil_cols")} if ctx.tune else None,
+        "tiles": tiles,
         "mgpcg_gdof_per_s": gdofs,
         "static_iterations": si["iterations"],
         "coarse_iterations": ei["coarse_iterations"],
         "fine_block_iterations": ei["fine_iterations"],
         "adjoint_iterations": ai["iterations"],
+        "residuals": {"static_true_rel": si["true_rel_residual"], "fine_block_true_rel": ei["fine_true_residual"],
+                      "adjoint_true_rel": ai["true_rel_residual"], "coarse_eigen_rel": ei["coarse_residual"],
+                      "coarse_guard_fired": ei["coarse_guard_fired"]},
         "lambda": [float(v) for v in lam],
         "phase_s": {"coarse": ei["seconds_coarse"], "fine": ei["seconds_fine"], "ritz": ei["seconds_ritz"],
                     "static": si["seconds"], "adjoint": ai["seconds"]},
+        "five_level_mg": five,
         "fp64_reference": fp64,
         "learned_warm_start": learned,
+        "column_960x320_fp64": column,
+        "block16_96x48x48": block16,
         "pinvit_refinement": pinv,
         "intermediate_refinement": refine,
         "incompatible_element": incompatible,
         "post_processing": postp,
         "design_chain": designp,
         "batched_instances": inst,
-        "roofline": {"bound": "hbm", "kernel": f"{FINE_KERNELS[var64]}<double> (fine H8 K apply, 1 column)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES.get(var64), "apply_ms": apply_ms,
-                     "alg_bytes": alg_bytes, "launches_timed": args.apply_reps},
+        "roofline": {"bound": "hbm", "kernel": f"fine-level Jacobi sweep, {k} columns, "
+                                               f"{'FP32' if word == 4 else 'FP64'} (k_apply_wht3*)",
+                     "achieved": b1 / (sw1 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": b1 / (sw1 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": SWEEP_TRAFFIC_BYTES,
+                     "sweep_ms": sw1, "alg_bytes": b1, "launches_timed": args.sweep_reps,
+                     "level2_stencil_sweep": {"sweep_ms": sw2, "alg_bytes": b2,
+                                              "achieved": b2 / (sw2 * 1e-3) / 1e9,
+                                              "frac": b2 / (sw2 * 1e-3) / 1e9 / HBM_PEAK_GBS}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -325,6 +325,13 @@ int mlb_adjoint_rhs_dev(mlb_ctx* ctx, int k, double* B, void* stream);
 int mlb_solve_block_dev(mlb_ctx* ctx, int ncols, const double* B, double* X, double tol, int max_it,
                         mlb_solve_info* info, void* stream);
 
+/* `reps` damped-Jacobi sweeps x <- x + omega_j D^-1 (r - A x) of the multigrid
+ * cycle on level `level` (1 .. levels - 1) for ncols <= 32 columns, in the
+ * cycle's precision (FP32 in MLB_MIXED), on the level's own work blocks
+ * (zeroed on first use): the smoother kernel exactly as a cycle launches it,
+ * for timing it on `stream`.  Enqueue only. */
+int mlb_sweep_dev(mlb_ctx* ctx, int level, int ncols, int reps, void* stream);
+
 /* One multigrid V-cycle z = M^-1 r starting at `level` (ncols columns). */
 int mlb_vcycle_dev(mlb_ctx* ctx, int level, int ncols, const double* r, double* z, void* stream);
 

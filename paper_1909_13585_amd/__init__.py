@@ -329,6 +329,10 @@ class Context:
         """Copies the adjoint solutions of the last sensitivities call into Z (k, n)."""
         self._check(self.lib.mlb_adjoints_dev(self.h, k, _dptr(Z), _stream()))
 
+    def sweep_dev(self, level, ncols, reps=1):
+        """reps Jacobi sweeps of the cycle on its level work blocks (for timing)."""
+        self._check(self.lib.mlb_sweep_dev(self.h, level, ncols, reps, _stream()))
+
     def vcycle_dev(self, level, r, z):
         self._check(self.lib.mlb_vcycle_dev(self.h, level, r.shape[0] if r.dim() > 1 else 1,
                                             _dptr(r), _dptr(z), _stream()))

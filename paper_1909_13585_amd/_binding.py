@@ -113,6 +113,7 @@ _SIGS = {
     "mlb_set_state_dev": (_I, [_P, _P, _P, _P]),
     "mlb_prolong_dev": (_I, [_P, _I, _I, _P, _P, _P]),
     "mlb_restrict_dev": (_I, [_P, _I, _I, _P, _P, _P]),
+    "mlb_sweep_dev": (_I, [_P, _I, _I, _I, _P]),
     "mlb_vcycle_dev": (_I, [_P, _I, _I, _P, _P, _P]),
     "mlb_coarse_modes_dev": (_I, [_P, _I, _P, _P]),
     "mlb_adjoints_dev": (_I, [_P, _I, _P, _P]),

@@ -119,6 +119,7 @@ struct mlb_ctx {
     double* part = nullptr;
     int64_t part_cap = 0;
     double* scratch = nullptr;   // the device's fixed scratch array (kScratchDoubles)
+    bool sweep_ready = false;    // mlb_sweep_dev has given its work blocks defined contents
     int64_t* pidx = nullptr;
     double* scal = nullptr;   // 16 blocks of kScal doubles
     double* gbuf = nullptr;   // summed Gram matrices (up to 96 x 192)
@@ -209,6 +210,7 @@ void drop_graphs(mlb_ctx* c);
 int ensure_level_cols(mlb_ctx* c, int cols) {
     if (cols <= c->wcols) return MLB_OK;
     drop_graphs(c);   // captured cycles point at the old buffers
+    c->sweep_ready = false;
     for (auto& l : c->lv) {
         const size_t s = (size_t)l.n * cols;
         CHK(dalloc(c, &l.vr, s));
@@ -2309,6 +2311,34 @@ int mlb_restrict_dev(mlb_ctx* c, int level, int ncols, const double* xf, double*
     Level& lf = c->lv[level - 1];
     Level& lc = c->lv[level];
     launch_restrict_nb<double>(c->dim, lf.g, lc.g, lf.nmask, lc.nmask, ncols, lf.n, lc.n, xf, yc, c->st);
+    HIPC(hipGetLastError());
+    return MLB_OK;
+}
+
+int mlb_sweep_dev(mlb_ctx* c, int level, int ncols, int reps, void* stream) {
+    if (!c || ncols < 1 || ncols > 32 || reps < 1) return MLB_EINVAL;
+    if (level < 1 || level >= c->L) return fail(c, MLB_EINVAL, "level must be a smoothed level (1 .. levels - 1)");
+    if (!c->has_density || !c->has_bc) return fail(c, MLB_ESTATE, "set the mask and the densities first");
+    c->st = pick(c, stream);
+    CHK(ensure_level_cols(c, ncols));
+    Level& l = c->lv[level - 1];
+    const size_t cnt = (size_t)l.n * ncols;
+    if (c->d.precision == MLB_MIXED) {
+        if (!c->sweep_ready) {   // defined contents, once per buffer set
+            HIPC(hipMemsetAsync(l.fz2, 0, cnt * sizeof(float), c->st));
+            HIPC(hipMemsetAsync(l.fr, 0, cnt * sizeof(float), c->st));
+        }
+        for (int i = 0; i < reps; ++i)
+            apply_K<float>(c, level, ncols, i % 2 ? l.fz : l.fz2, i % 2 ? l.fz2 : l.fz, kModeJacobi, l.fr, nullptr);
+    } else {
+        if (!c->sweep_ready) {
+            HIPC(hipMemsetAsync(l.vz2, 0, cnt * sizeof(double), c->st));
+            HIPC(hipMemsetAsync(l.vr, 0, cnt * sizeof(double), c->st));
+        }
+        for (int i = 0; i < reps; ++i)
+            apply_K<double>(c, level, ncols, i % 2 ? l.vz : l.vz2, i % 2 ? l.vz2 : l.vz, kModeJacobi, l.vr, nullptr);
+    }
+    c->sweep_ready = true;
     HIPC(hipGetLastError());
     return MLB_OK;
 }
