@@ -1636,7 +1636,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
         CHK(dalloc(c, &c->gjP, (size_t)64 * 64));
         CHK(dalloc(c, &c->gjR, (size_t)64 * c->nA));
         CHK(dalloc(c, &c->gjC, (size_t)64 * c->nA));
-        CHK(dalloc(c, &c->cpart, (size_t)c->nsplit * 32 * c->nA));
+        CHK(dalloc(c, &c->cpart, (size_t)c->nsplit * 32 * c->nA + (size_t)coarse_stage_doubles(c->nA)));
     }
     if (c->ell > 1) {
         Level& le = c->lv[c->ell - 1];

@@ -68,6 +68,7 @@ void launch_pad_identity(int64_t n, int64_t N, double* A, hipStream_t st);
 // to a multiple of 64; the inverse is N x N row-major with an identity pad
 int coarse_pad(int64_t n);
 int coarse_splits(int64_t N);
+int64_t coarse_stage_doubles(int64_t N);
 void launch_gemm_f64(int M, int N, int K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                      double beta, double* C, int64_t ldc, hipStream_t st);
 void launch_block_inverse(int64_t N, double* A, double* P, double* R, double* Cp, hipStream_t st);

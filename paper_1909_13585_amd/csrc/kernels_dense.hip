@@ -94,14 +94,14 @@ __global__ __launch_bounds__(256) void k_gj_diag(const double* __restrict__ A, i
             colk[tid] = s[tid * kGT + k];
         }
         __syncthreads();
-        const double p = rowk[k];
+        const double pinv = 1.0 / rowk[k];
         for (int e = tid; e < kGT * kGT; e += 256) {
             const int i = e / kGT, j = e % kGT;
             double v;
-            if (i == k && j == k) v = 1.0 / p;
-            else if (i == k) v = rowk[j] / p;
-            else if (j == k) v = -colk[i] / p;
-            else v = s[e] - colk[i] * (rowk[j] / p);
+            if (i == k && j == k) v = pinv;
+            else if (i == k) v = rowk[j] * pinv;
+            else if (j == k) v = -colk[i] * pinv;
+            else v = s[e] - colk[i] * (rowk[j] * pinv);
             s[e] = v;
         }
         __syncthreads();
@@ -109,12 +109,12 @@ __global__ __launch_bounds__(256) void k_gj_diag(const double* __restrict__ A, i
     for (int e = tid; e < kGT * kGT; e += 256) P[e] = s[e];
 }
 
-// dst (rows x 64, leading dimension ldd) = src (leading dimension lds)
-__global__ void k_copy_panel(int64_t rows, const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
-                             int64_t ldd) {
+// dst (rows x cols, leading dimension ldd) = src (leading dimension lds)
+__global__ void k_copy_block(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
+                             double* __restrict__ dst, int64_t ldd) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= rows * kGT) return;
-    const int64_t i = t / kGT, j = t % kGT;
+    if (t >= rows * cols) return;
+    const int64_t i = t / cols, j = t % cols;
     dst[i * ldd + j] = src[i * lds + j];
 }
 
@@ -129,43 +129,61 @@ __global__ void k_symmetrize(int64_t N, double* __restrict__ A) {
     A[j * N + i] = v;
 }
 
-// Partial products of Z = A X with A symmetric N x N (row-major) and X the
-// n x nc level block (column-major, leading dimension ld, rows >= n read as
-// zero), computed as Z^T = X^T A: wave (tile, split) forms the 16 (or 32)
-// columns x 16 rows of Z^T for rows j0 .. j0 + 15 over its share of the
-// K range, so every row of A is read by one wave per tile, 4 full 128-byte
-// lines per load.  part[(split * 32 + c) * N + j].
+// Xt[k * 32 + c] = x[c * ld + k] as FP64 for k < n and c < nc, zero for
+// the padding rows n <= k < N and columns nc <= c < 32 (k-major, so that the
+// MFMA operand loads below read four full 128-byte lines)
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_part(int64_t n, int64_t N, int nc, int64_t ld,
-                                                     const double* __restrict__ A, const T* __restrict__ x,
-                                                     int nsplit, double* __restrict__ part) {
+__global__ void k_coarse_stage(int64_t n, int64_t N, int nc, int64_t ld, const T* __restrict__ x,
+                               double* __restrict__ Xt) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * 32) return;
+    const int64_t k = t >> 5;
+    const int c = (int)(t & 31);
+    Xt[t] = (k < n && c < nc) ? (double)x[c * ld + k] : 0.0;
+}
+
+// Partial products of Z = A X with A symmetric N x N (row-major) and X
+// staged k-major in Xt (N x 32), computed as Z^T = X^T A: wave (tile, split)
+// forms the 16 (or 32) columns x 16 rows of Z^T for rows j0 .. j0 + 15 over
+// its share of the K range, so every row of A is read by one wave per tile;
+// each operand load reads four full 128-byte lines, and the loop issues the
+// loads of four K steps before their products.  part[(split * 32 + c) * N + j].
+template <int NCT>
+__global__ __launch_bounds__(256) void k_coarse_part(int64_t N, const double* __restrict__ A,
+                                                     const double* __restrict__ Xt, int nsplit,
+                                                     double* __restrict__ part) {
     const int lane = threadIdx.x & 63;
     const int64_t wid = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t ntiles = N / 16;
     if (wid >= ntiles * nsplit) return;
     const int64_t tile = wid / nsplit;
     const int split = (int)(wid % nsplit);
-    const int64_t kchunk = (N / 4 + nsplit - 1) / nsplit * 4;
+    const int64_t kchunk = (N / 16 + nsplit - 1) / nsplit * 16;
     const int64_t kb = split * kchunk, ke = min(N, kb + kchunk);
     const int64_t j0 = tile * 16;
     const int cl = lane & 15, kl = lane >> 4;
-    const bool two = nc > 16;
-    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t k = kb; k < ke; k += 4) {
-        const int64_t kr = k + kl;
-        const double b = A[kr * N + j0 + cl];
-        const double a0 = (cl < nc && kr < n) ? (double)x[cl * ld + kr] : 0.0;
-        acc0 = mfma16x16x4(a0, b, acc0);
-        if (two) {
-            const double a1 = (cl + 16 < nc && kr < n) ? (double)x[(cl + 16) * ld + kr] : 0.0;
-            acc1 = mfma16x16x4(a1, b, acc1);
+    v4d acc[NCT];
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = kb; k < ke; k += 16) {   // N and kchunk are multiples of 16
+        double b[4], a[4][NCT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t kr = k + 4 * u + kl;
+            b[u] = A[kr * N + j0 + cl];
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) a[u][t] = Xt[kr * 32 + 16 * t + cl];
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) acc[t] = mfma16x16x4(a[u][t], b[u], acc[t]);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int c = kl + 4 * r;
-        part[((int64_t)split * 32 + c) * N + j0 + cl] = acc0[r];
-        if (two) part[((int64_t)split * 32 + c + 16) * N + j0 + cl] = acc1[r];
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) part[((int64_t)split * 32 + c + 16 * t) * N + j0 + cl] = acc[t][r];
     }
 }
 
@@ -186,12 +204,14 @@ static inline unsigned nbk(int64_t n) { return (unsigned)((n + 255) / 256); }
 int coarse_pad(int64_t n) { return (int)((n + kGT - 1) / kGT * kGT); }
 
 int coarse_splits(int64_t N) {
-    // enough waves to cover the chip (>= ~2048) with >= 64 k-steps per wave
+    // enough waves to cover the chip (>= ~2048) with >= 64 K steps of 4 per wave
     const int64_t tiles = N / 16;
     int s = 1;
     while (tiles * s < 2048 && N / (4 * (s * 2)) >= 64) s *= 2;
     return s;
 }
+
+int64_t coarse_stage_doubles(int64_t N) { return N * 32; }
 
 void launch_gemm_f64(int M, int N, int K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                      double beta, double* C, int64_t ldc, hipStream_t st) {
@@ -208,28 +228,30 @@ void launch_block_inverse(int64_t N, double* A, double* P, double* R, double* Cp
     for (int64_t k0 = 0; k0 < N; k0 += kGT) {
         hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, st, A, N, k0, P);
         launch_gemm_f64(kGT, n, kGT, 1.0, P, kGT, A + k0 * N, N, 0.0, R, N, st);
-        hipLaunchKernelGGL(k_copy_panel, dim3(nbk(N * kGT)), dim3(256), 0, st, N, A + k0, N, Cp, (int64_t)kGT);
+        hipLaunchKernelGGL(k_copy_block, dim3(nbk(N * kGT)), dim3(256), 0, st, N, (int64_t)kGT, A + k0, N, Cp,
+                           (int64_t)kGT);
         launch_gemm_f64(n, n, kGT, -1.0, Cp, kGT, R, N, 1.0, A, N, st);
         launch_gemm_f64(n, kGT, kGT, -1.0, Cp, kGT, P, kGT, 0.0, A + k0, N, st);
-        hipLaunchKernelGGL(k_copy_panel, dim3(nbk(kGT * (N / kGT) * kGT)), dim3(256), 0, st, (int64_t)kGT, R, N,
-                           A + k0 * N, N);
-        // the rest of row block K (columns outside K) from R, 64 columns at a time
-        for (int64_t c = 0; c < N; c += kGT)
-            if (c != k0)
-                hipLaunchKernelGGL(k_copy_panel, dim3(nbk(kGT * kGT)), dim3(256), 0, st, (int64_t)kGT, R + c, N,
-                                   A + k0 * N + c, N);
-        hipLaunchKernelGGL(k_copy_panel, dim3(nbk(kGT * kGT)), dim3(256), 0, st, (int64_t)kGT, P, (int64_t)kGT,
-                           A + k0 * N + k0, N);
+        hipLaunchKernelGGL(k_copy_block, dim3(nbk(kGT * N)), dim3(256), 0, st, (int64_t)kGT, N, R, N, A + k0 * N, N);
+        hipLaunchKernelGGL(k_copy_block, dim3(nbk(kGT * kGT)), dim3(256), 0, st, (int64_t)kGT, (int64_t)kGT, P,
+                           (int64_t)kGT, A + k0 * N + k0, N);
     }
     hipLaunchKernelGGL(k_symmetrize, dim3(nbk(N * N)), dim3(256), 0, st, N, A);
 }
 
+// part holds nsplit * 32 * N doubles followed by the N x 32 staging block
 template <typename T>
 void launch_coarse_solve(int64_t n, int64_t N, int nc, int64_t ld, const double* A, const T* x, T* z, int nsplit,
                          double* part, hipStream_t st) {
+    double* Xt = part + (int64_t)nsplit * 32 * N;
+    hipLaunchKernelGGL(k_coarse_stage<T>, dim3(nbk(N * 32)), dim3(256), 0, st, n, N, nc, ld, x, Xt);
     const int64_t waves = N / 16 * nsplit;
-    hipLaunchKernelGGL(k_coarse_part<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, n, N, nc, ld, A, x,
-                       nsplit, part);
+    if (nc > 16)
+        hipLaunchKernelGGL(k_coarse_part<2>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, N, A, Xt, nsplit,
+                           part);
+    else
+        hipLaunchKernelGGL(k_coarse_part<1>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, N, A, Xt, nsplit,
+                           part);
     hipLaunchKernelGGL(k_coarse_sum<T>, dim3(nbk(n * nc)), dim3(256), 0, st, n, N, nc, ld, nsplit, part, z);
 }
 template void launch_coarse_solve<double>(int64_t, int64_t, int, int64_t, const double*, const double*, double*, int,
