@@ -48,6 +48,11 @@ int mlb_nn_split(int N, int Ca, int Cb, int64_t V, const float* y, float* a, flo
    (D+1)(H+1)(W+1)); node2cell_grad is its adjoint. */
 int mlb_nn_cell2node(int64_t planes, int D, int H, int W, const float* cells, float* nodes, void* stream);
 int mlb_nn_node2cell_grad(int64_t planes, int D, int H, int W, const float* gnodes, float* gcells, void* stream);
+/* Node channels of one sample, (q + 1) vector fields of 3 components each
+   (channel 3 f + c, node index fastest), to the solver's DOF blocks:
+   blocks[f * 3 nodes + 3 node + c] = chan[(3 f + c) nodes + node] in FP64,
+   i.e. q start vectors and one displacement, column-major, interleaved. */
+int mlb_nn_nodes_to_dofs(int nfields, int64_t nodes, const float* chan, double* blocks, void* stream);
 /* loss = sum w (p - t)^2 (w may be NULL = 1), grad = 2 w (p - t) * scale;
    the loss (FP64) is written to loss_dev[0]; work needs mlb_nn_mse_work(n) doubles. */
 int64_t mlb_nn_mse_work(int64_t n);

@@ -139,6 +139,7 @@ _SIGS = {
     "mlb_nn_concat": (_I, [_I, _I, _I, C.c_int64, _P, _P, _P, _P]),
     "mlb_nn_split": (_I, [_I, _I, _I, C.c_int64, _P, _P, _P, _P]),
     "mlb_nn_cell2node": (_I, [C.c_int64, _I, _I, _I, _P, _P, _P]),
+    "mlb_nn_nodes_to_dofs": (_I, [_I, C.c_int64, _P, _P, _P]),
     "mlb_nn_node2cell_grad": (_I, [C.c_int64, _I, _I, _I, _P, _P, _P]),
     "mlb_nn_mse_work": (C.c_int64, [C.c_int64]),
     "mlb_nn_mse": (_I, [C.c_int64, _P, _P, _P, C.c_float, _P, _P, _P, _P]),

@@ -178,6 +178,7 @@ void launch_nn_unpool2(int64_t planes, int D, int H, int W, float scale, const f
 void launch_nn_concat(int N, int Ca, int Cb, int64_t V, const float* a, const float* b, float* y, hipStream_t st);
 void launch_nn_split(int N, int Ca, int Cb, int64_t V, const float* y, float* a, float* b, hipStream_t st);
 void launch_nn_cell2node(int64_t planes, int D, int H, int W, const float* c, float* nd, hipStream_t st);
+void launch_nn_nodes_to_dofs(int nfields, int64_t nodes, const float* ch, double* b, hipStream_t st);
 void launch_nn_node2cell_grad(int64_t planes, int D, int H, int W, const float* gn, float* gc, hipStream_t st);
 int nn_mse_parts(int64_t n);
 void launch_nn_mse(int64_t n, const float* pred, const float* target, const float* weight, float scale, float* grad,

@@ -236,6 +236,15 @@ __global__ void k_cell2node(int64_t planes, int D, int H, int W, const float* __
     nd[i] = s / (float)cnt;
 }
 
+__global__ void k_nodes_to_dofs(int nfields, int64_t nodes, const float* __restrict__ ch, double* __restrict__ b) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nfields * 3 * nodes) return;
+    const int64_t f = i / (3 * nodes), r = i % (3 * nodes);
+    const int64_t node = r / 3;
+    const int c = (int)(r % 3);
+    b[i] = (double)ch[(3 * f + c) * nodes + node];
+}
+
 __global__ void k_node2cell_grad(int64_t planes, int D, int H, int W, const float* __restrict__ gn,
                                  float* __restrict__ gc) {
     const int64_t NV = (int64_t)(D + 1) * (H + 1) * (W + 1), CV = (int64_t)D * H * W;
@@ -348,6 +357,9 @@ void launch_nn_split(int N, int Ca, int Cb, int64_t V, const float* y, float* a,
 void launch_nn_cell2node(int64_t planes, int D, int H, int W, const float* c, float* nd, hipStream_t st) {
     hipLaunchKernelGGL(k_cell2node, dim3(nbk(planes * (D + 1) * (H + 1) * (W + 1))), dim3(kNnThreads), 0, st, planes,
                        D, H, W, c, nd);
+}
+void launch_nn_nodes_to_dofs(int nfields, int64_t nodes, const float* ch, double* b, hipStream_t st) {
+    hipLaunchKernelGGL(k_nodes_to_dofs, dim3(nbk(nfields * 3 * nodes)), dim3(kNnThreads), 0, st, nfields, nodes, ch, b);
 }
 void launch_nn_node2cell_grad(int64_t planes, int D, int H, int W, const float* gn, float* gc, hipStream_t st) {
     hipLaunchKernelGGL(k_node2cell_grad, dim3(nbk(planes * D * H * W)), dim3(kNnThreads), 0, st, planes, D, H, W, gn,

@@ -77,6 +77,12 @@ int mlb_nn_node2cell_grad(int64_t planes, int D, int H, int W, const float* gnod
     return last();
 }
 
+int mlb_nn_nodes_to_dofs(int nfields, int64_t nodes, const float* chan, double* blocks, void* stream) {
+    if (nfields < 1 || nodes < 1 || !chan || !blocks) return MLB_EINVAL;
+    launch_nn_nodes_to_dofs(nfields, nodes, chan, blocks, S(stream));
+    return last();
+}
+
 int64_t mlb_nn_mse_work(int64_t n) { return n < 1 ? 0 : nn_mse_parts(n); }
 
 int mlb_nn_mse(int64_t n, const float* pred, const float* target, const float* weight, float scale, float* grad,

@@ -1,13 +1,19 @@
 """Trains the warm-start U-Net on data the plain method generates.
 
-    python -m paper_1909_13585_amd.train_warmstart --samples 600 --epochs 40 --out weights.npz
+    python -m paper_1909_13585_amd.train_warmstart --samples 2000 --epochs 40 --out weights.npz
 
 Each sample is a seeded Gaussian-filtered density on a 96x32x32 H8 grid
 (the 192x64x64 workload recipe at half resolution: volume fraction 0.3,
 filter width 2 elements, solid end layers), analysed by the library
 (mixed precision, 4 multigrid levels, eigen level 2, i.e. the same
 48x16x16-element eigen-level grid as the 192x64x64 workload at level 3).
-Targets: the 12 coarse modes (sign-fixed, max-abs 1) and the static
+
+Targets are invariant to the rotations inside the 12-mode subspace: the
+K-orthogonal projections Y = Psi (Psi^T K^l Q) of 12 fixed probe vectors Q
+(the coarse modes of the recipe's mean density field) onto the span of the
+sample's coarse modes Psi, each column scaled to max-abs 1.  Y spans the
+same subspace as Psi and varies smoothly with the density, while single
+modes swap order and sign where their factors cross.  Plus the static
 displacement injected onto the eigen-level nodes (max-abs 1).  Inputs: the
 density averaged onto the eigen-level cells plus coordinate channels.
 Training: Adam, mean squared error, all in the library's kernels.
@@ -25,12 +31,22 @@ def generate(n_samples, seed0, nel=(96, 32, 32), ell=2, levels=4, log=print):
     import workloads as W
     from paper_1909_13585_amd import warmstart as ws
     ctx = mlb.Context(nel, mg_levels=levels, eig_level=ell, precision=mlb.MLB_MIXED)
+    ctx.set_opts(smooth_steps=2, coarse_sweeps=4, jacobi_omega=1.5)
     p0 = W.box_3d(nel=nel, seed=seed0, sigma=2.0)
     ctx.set_bc(p0["fixed"])
     ctx.set_loads(p0["F"])
     n_l, _ = ctx.level_size(ell)
     Psi = torch.empty((12, n_l), dtype=torch.float64, device="cuda")
     U = torch.empty((1, ctx.n), dtype=torch.float64, device="cuda")
+    # probes: the coarse modes of the recipe's mean density (volume fraction
+    # everywhere, the solid end layers kept)
+    xm = np.where(p0["x"] >= 1.0, 1.0, 0.3)
+    ctx.set_density_dev(torch.from_numpy(xm).cuda())
+    ctx.solve_static_dev(U, tol=1e-8, max_it=3000)
+    ctx.buckling_dev(12, None, tol_eig=1e-8)
+    Q = torch.empty((12, n_l), dtype=torch.float64, device="cuda")
+    ctx.coarse_modes_dev(12, Q)
+    KQ = torch.empty_like(Q)
     Dn, Hn, Wn = nel[2] // 2 ** (ell - 1) + 1, nel[1] // 2 ** (ell - 1) + 1, nel[0] // 2 ** (ell - 1) + 1
     X, Y = [], []
     t0 = time.perf_counter()
@@ -41,7 +57,11 @@ def generate(n_samples, seed0, nel=(96, 32, 32), ell=2, levels=4, log=print):
         ctx.solve_static_dev(U, tol=1e-8, max_it=3000)
         ctx.buckling_dev(12, None, tol_eig=1e-6)
         ctx.coarse_modes_dev(12, Psi)
-        modes = ws.normalize_modes(Psi.cpu().numpy().T)
+        ctx.apply_K_dev(ell, Q, KQ)            # K^l of this density on the probes
+        P = Psi.cpu().numpy()                  # (12, n_l), K^l-orthonormal rows
+        Yp = (P @ KQ.cpu().numpy().T).T @ P    # rows: projections of the probes
+        Yp /= np.maximum(np.abs(Yp).max(axis=1, keepdims=True), 1e-300)
+        modes = np.asfortranarray(Yp.T)
         ul = ws.coarse_nodes_of_fine(U[0].cpu().numpy(), nel, ell)
         ul = ul / max(np.abs(ul).max(), 1e-300)
         X.append(ws.coarse_inputs(p["x"], nel, ell))

@@ -309,20 +309,37 @@ def predict(net, x_fine, nel, ell):
     return node_channels_to_blocks(out)
 
 
+def predict_dev(net, x_fine, nel, ell):
+    """Network prediction as device blocks: (q + 1) x n_l FP64 (q start
+    vectors, then the displacement), interleaved DOF order, converted from the
+    node channels by the library's kernel (no host round trip)."""
+    import torch
+    inp = coarse_inputs(x_fine, nel, ell)
+    out = net.forward(inp)
+    nfields = out.shape[1] // 3
+    nodes = out.shape[2] * out.shape[3] * out.shape[4]
+    blocks = torch.empty((nfields, 3 * nodes), dtype=torch.float64, device="cuda")
+    st = net.lib.mlb_nn_nodes_to_dofs(nfields, nodes, _p(out), _p(blocks), _st())
+    if st != B.MLB_OK:
+        raise B.MlbError(st, "nodes_to_dofs")
+    return blocks
+
+
 def set_learned_warm_start(ctx, net, x_fine, nel, ell):
     """Predicts the coarse start block and the static guess for this density
-    and hands them to the context (coarse modes as MLB_WARM_COARSE; the
-    displacement prolonged level by level to the fine grid in the library's
-    transfer kernel, then MLB_WARM_STATIC)."""
+    and hands them to the context from device memory: the q start vectors as
+    MLB_WARM_COARSE, the displacement prolonged level by level to the fine
+    grid in the library's transfer kernel as MLB_WARM_STATIC."""
     import torch
     from . import MLB_WARM_COARSE, MLB_WARM_STATIC
-    modes, ul = predict(net, x_fine, nel, ell)
-    ctx.set_warm_start(MLB_WARM_COARSE, modes)
-    cur = torch.from_numpy(ul).cuda()
+    blocks = predict_dev(net, x_fine, nel, ell)
+    q = blocks.shape[0] - 1
+    ctx.set_warm_start_dev(MLB_WARM_COARSE, blocks[:q].T)
+    cur = blocks[q]
     for j in range(ell - 1, 0, -1):
         nj, _ = ctx.level_size(j)
         nxt = torch.empty(nj, dtype=torch.float64, device="cuda")
         ctx.prolong_dev(j, cur, nxt)
         cur = nxt
-    ctx.set_warm_start(MLB_WARM_STATIC, cur.cpu().numpy())
-    return modes, ul
+    ctx.set_warm_start_dev(MLB_WARM_STATIC, cur)
+    return blocks

@@ -152,3 +152,28 @@ def test_unet_forward_backward_match_reference(env):
     for name in net.w:
         assert _rel(net.gw[name].cpu().numpy(), G[name][0]) < 1e-4, name
         assert _rel(net.gb[name].cpu().numpy(), G[name][1]) < 1e-4, name
+
+
+def test_nodes_to_dofs_matches_host_permutation():
+    # device-resident prediction path: the kernel's channel -> DOF blocks
+    # against the host permutation used for training targets (bit for bit)
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import ctypes as C
+    from paper_1909_13585_amd import _binding as B
+    from paper_1909_13585_amd import warmstart as ws
+    lib = B.load()
+    q, dims = 12, (5, 7, 9)
+    nodes = dims[0] * dims[1] * dims[2]
+    rng = np.random.default_rng(3)
+    out = torch.from_numpy(rng.standard_normal((1, 3 * q + 3) + dims).astype(np.float32)).cuda()
+    blocks = torch.empty((q + 1, 3 * nodes), dtype=torch.float64, device="cuda")
+    st = lib.mlb_nn_nodes_to_dofs(q + 1, nodes, C.c_void_p(out.data_ptr()), C.c_void_p(blocks.data_ptr()),
+                                  C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    torch.cuda.synchronize()
+    modes, u = ws.node_channels_to_blocks(out, q)
+    b = blocks.cpu().numpy()
+    assert np.array_equal(b[:q].T, modes)
+    assert np.array_equal(b[q], u)
