@@ -253,6 +253,24 @@ int mlb_sensitivities(mlb_ctx* ctx, double* dJ, double* dlam, mlb_solve_info* in
 int mlb_sensitivities_dev(mlb_ctx* ctx, double* dJ, double* dlam, mlb_solve_info* info,
                           void* stream);
 
+/* Consistent sensitivities of the multilevel factors (appendix on numerical
+ * procedures, eq. consistentSensitivity, with the residual y_i = (K +
+ * lam~_i G) phi~_i of eq. eigResidual).  Printed literally, that formula's
+ * adjoint -2 (K + lam~ G)^-1 y equals -2 phi~ and the formula reduces to the
+ * plain one; here it is the derivative of what the method computes:
+ * lam~_i(x) = i-th Ritz value of span(K^-1 G[x, u(x)] Psi) with the
+ * interpolated coarse modes Psi held fixed:
+ *   dlam_i/dx_e = lam [phi^T K'_e phi + lam (phi^T G'_e phi - zt^T K'_e u)]
+ *                 + 2 lam (w^T G'_e psi - w^T K'_e phi),
+ *   w = K^-1 y_i,  K zt = grad_u(phi^T G phi) + (2 / lam) grad_u(w^T G psi),
+ * psi = the combination of Psi with K phi = G psi.  Two block solves of k
+ * columns (tolerance of mlb_solve_static).  dlam: m x k (host / device).
+ * ESTATE before mlb_buckling or after one with inverse-iteration steps
+ * (mlb_opts.pinvit_steps), whose modes are not of that form.  Afterwards
+ * mlb_adjoints_dev returns zt. */
+int mlb_sensitivities_consistent(mlb_ctx* ctx, double* dlam, mlb_solve_info* info);
+int mlb_sensitivities_consistent_dev(mlb_ctx* ctx, double* dlam, mlb_solve_info* info, void* stream);
+
 /* Tile parameters of the fine apply (pencil length in node planes, 1..64;
    3D variant 0..3 as in mlb_tune_info, -1 keeps it) and of the stencil
    applies (columns per thread, 1..12); 0 keeps a value; both precisions are

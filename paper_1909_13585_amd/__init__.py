@@ -211,6 +211,19 @@ class Context:
         self._check(self.lib.mlb_sensitivities_dev(self.h, _dptr(dJ), _dptr(dlam), C.byref(info), _stream()))
         return _info_dict(info)
 
+    def sensitivities_consistent(self):
+        """Consistent buckling sensitivities (m, k) of the last buckling call (host)."""
+        dl = np.zeros((self.m, self.k), order="F")
+        info = MlbSolveInfo()
+        self._check(self.lib.mlb_sensitivities_consistent(self.h, dl.ctypes.data_as(C.c_void_p), C.byref(info)))
+        return dl, _info_dict(info)
+
+    def sensitivities_consistent_dev(self, dlam):
+        """Consistent buckling sensitivities into dlam (k, m) on the device."""
+        info = MlbSolveInfo()
+        self._check(self.lib.mlb_sensitivities_consistent_dev(self.h, _dptr(dlam), C.byref(info), _stream()))
+        return _info_dict(info)
+
     def apply_K_dev(self, level, x, y):
         self._check(self.lib.mlb_apply_K_dev(self.h, level, x.shape[0] if x.dim() > 1 else 1,
                                              _dptr(x), _dptr(y), _stream()))

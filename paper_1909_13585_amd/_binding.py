@@ -106,6 +106,8 @@ _SIGS = {
     "mlb_eig_residuals_dev": (_I, [_P, _P, _P]),
     "mlb_sensitivities": (_I, [_P, _P, _P, C.POINTER(MlbSolveInfo)]),
     "mlb_sensitivities_dev": (_I, [_P, _P, _P, C.POINTER(MlbSolveInfo), _P]),
+    "mlb_sensitivities_consistent": (_I, [_P, _P, C.POINTER(MlbSolveInfo)]),
+    "mlb_sensitivities_consistent_dev": (_I, [_P, _P, C.POINTER(MlbSolveInfo), _P]),
     "mlb_set_warm_start": (_I, [_P, _I, _I, _P]),
     "mlb_set_warm_start_dev": (_I, [_P, _I, _I, _P, _P]),
     "mlb_apply_K_dev": (_I, [_P, _I, _I, _P, _P, _P]),

@@ -110,6 +110,13 @@ struct mlb_ctx {
     // eigen
     int k = 0;
     double *Phi = nullptr, *Zadj = nullptr, *dlam_l = nullptr;
+    // for the consistent sensitivities: the interpolated coarse modes on the
+    // fine grid (right-hand side basis of K Phi~ = G Psi), the Rayleigh-Ritz
+    // coefficients of the returned modes (signs included), the residual
+    // adjoints w = K^-1 (K + lam G) phi
+    double *Psif = nullptr, *cW = nullptr;
+    std::vector<double> rrC;
+    bool psi_ok = false;
     std::vector<double> lam, eigres;
     // coarse eigensolver work
     int eig_cap = 0;
@@ -1248,8 +1255,11 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         CHK(dalloc(c, &c->Phi, (size_t)n * k));
         CHK(dalloc(c, &c->Zadj, (size_t)n * k));
         CHK(dalloc(c, &c->dlam_l, (size_t)k));
+        CHK(dalloc(c, &c->Psif, (size_t)n * k));
+        dfree(c->cW);
         c->k = k;
     }
+    c->psi_ok = false;
     // Optionally (Alg. 2, intermediate levels): on every level ell-1 .. 2
     // smooth the prolonged modes by Kaczmarz sweeps on (K^j + sigma G^j) psi
     // = 0, sigma the smallest Ritz value of the coarser level, and replace
@@ -1300,6 +1310,7 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         }
     }
     if (c->ell == 1) launch_copy_cols(n, k, n, c->eS, n, c->X1, c->st);
+    launch_copy_cols(n, k, n, c->X1, n, c->Psif, c->st);
     // step 3: K Phi~ = G Psi
     apply_G(c, 1, k, c->X1, c->X2);
     mlb_solve_info si{};
@@ -1346,6 +1357,7 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         std::vector<double> C(k * k);
         for (int a = 0; a < k; ++a)
             for (int q = 0; q < k; ++q) C[a + k * q] = Y[a * k + q];
+        c->rrC = C;
         CHK(upload_cm(c, c->cbuf, C));
         launch_gemm_small(n, k, n, c->Phi, k, c->cbuf, n, c->Zo, c->st);
         launch_gemm_small(n, k, n, c->X1, k, c->cbuf, n, c->R, c->st);
@@ -1367,6 +1379,11 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
     std::vector<double> sv(k);
     CHK(read_scal(c, sc(c, 15), k, sv.data()));
     for (int i = 0; i < k; ++i) sv[i] = sv[i] < 0 ? -1.0 : 1.0;
+    // returned mode i = sv_i Phi~ C_i, so K phi_i = G (sv_i Psi C_i) when no
+    // inverse-iteration step followed the Rayleigh-Ritz step
+    for (int i = 0; i < k; ++i)
+        for (int a = 0; a < k; ++a) c->rrC[a + (size_t)k * i] *= sv[i];
+    c->psi_ok = steps == 0;
     std::memcpy(c->hpin, sv.data(), sizeof(double) * k);
     HIPC(hipMemcpyAsync(sc(c, 15), c->hpin, sizeof(double) * k, hipMemcpyHostToDevice, c->st));
     launch_scale_cols(n, k, n, sc(c, 15), c->Phi, c->st);
@@ -1419,6 +1436,52 @@ int do_sens(mlb_ctx* c, double* dJ_dev, double* dlam_dev, mlb_solve_info* info) 
     }
     CHK(sync(c));
     if (info) info->seconds = now_s() - t0;
+    return MLB_OK;
+}
+
+// Consistent buckling sensitivities (appendix, eq. consistentSensitivity,
+// read through the fine solve K Phi~ = G Psi with Psi fixed): residual
+// adjoints w = K^-1 (K + lam G) phi, then K zt = b + (2 / lam) grad_u(w^T G psi)
+// as one block each, then the element formula with the residual terms.
+int do_sens_consistent(mlb_ctx* c, double* dlam_dev, mlb_solve_info* info) {
+    const double t0 = now_s();
+    if (!c->has_buck) return fail(c, MLB_ESTATE, "buckling sensitivities need mlb_buckling first");
+    if (!c->psi_ok)
+        return fail(c, MLB_ESTATE, "the consistent sensitivity is defined for modes from the fine solve and one "
+                                   "Rayleigh-Ritz step (no inverse-iteration steps)");
+    const Geo& g = c->lv[0].g;
+    const int k = c->k;
+    const int64_t n = c->n;
+    if (!c->cW) CHK(dalloc(c, &c->cW, (size_t)n * k));
+    // psi = Psi C (signs included) into X1
+    CHK(upload_cm(c, c->cbuf, c->rrC));
+    launch_gemm_small(n, k, n, c->Psif, k, c->cbuf, n, c->X1, c->st);
+    // y = K phi + lam G phi into Zo (dlam_l holds the factors of the last call)
+    apply_K<double>(c, 1, k, c->Phi, c->Zo, kModeY, nullptr, nullptr);
+    apply_G(c, 1, k, c->Phi, c->X2);
+    launch_axpy_cols(n, k, n, c->dlam_l, 1.0, c->X2, c->Zo, c->st);
+    mlb_solve_info s1{}, s2{};
+    if (c->o.block_cg) CHK(bpcg(c, c->Zo, c->cW, k, c->tol_solve, c->max_it, false, &s1));
+    else CHK(pcg(c, c->Zo, c->cW, k, c->tol_solve, c->max_it, false, &s1));
+    double* V = nullptr;
+    CHK(dalloc(c, &V, (size_t)g.m * c->nv * k));
+    launch_adj_elem(c->dim, g, c->Es, k, n, c->Phi, c->dHk, c->dD0, V, c->st, c->cW, c->X1, c->dlam_l);
+    launch_adj_gather(c->dim, g, k, V, c->dBc, c->lv[0].nmask, n, c->X2, c->st);
+    CHK(sync(c));
+    dfree(V);
+    if (c->o.block_cg) CHK(bpcg(c, c->X2, c->Zadj, k, c->tol_solve, c->max_it, false, &s2));
+    else CHK(pcg(c, c->X2, c->Zadj, k, c->tol_solve, c->max_it, false, &s2));
+    launch_dlam(c->dim, g, c->x, c->d.penal, c->d.E1, c->d.E0, c->U + (int64_t)c->ref_case_used * n, k, n, c->Phi,
+                c->Zadj, c->dlam_l, c->dK0, c->dHk, c->dD0Bc, dlam_dev, c->st, c->cW, c->X1);
+    c->has_adj = true;
+    CHK(sync(c));
+    if (info) {
+        info->iterations = s1.iterations + s2.iterations;
+        info->converged = s1.converged && s2.converged;
+        info->rel_residual = std::max(s1.rel_residual, s2.rel_residual);
+        info->true_rel_residual = std::max(s1.true_rel_residual, s2.true_rel_residual);
+        info->seconds = now_s() - t0;
+    }
     return MLB_OK;
 }
 
@@ -1674,7 +1737,7 @@ void mlb_destroy(mlb_ctx* c) {
     dfree(c->X1); dfree(c->X2); dfree(c->Phi); dfree(c->Zadj); dfree(c->dlam_l); dfree(c->eS); dfree(c->eK);
     dfree(c->eA); dfree(c->eT); dfree(c->eTK); dfree(c->eTA); dfree(c->eR); dfree(c->eP); dfree(c->ePK); dfree(c->ePA); dfree(c->part); dfree(c->pidx);
     dfree(c->scal); dfree(c->iscal); dfree(c->gbuf); dfree(c->cbuf); dfree(c->cbuf2);
-    dfree(c->fw); dfree(c->warm_coarse); dfree(c->warm_static);
+    dfree(c->fw); dfree(c->warm_coarse); dfree(c->warm_static); dfree(c->Psif); dfree(c->cW);
     if (c->hpin) (void)hipHostFree(c->hpin);
     if (c->hup) (void)hipHostFree(c->hup);
     drop_graphs(c);
@@ -1959,6 +2022,24 @@ int mlb_sensitivities(mlb_ctx* c, double* dJ, double* dlam, mlb_solve_info* info
     dfree(dJd);
     dfree(dld);
     return r;
+}
+
+int mlb_sensitivities_consistent(mlb_ctx* c, double* dlam, mlb_solve_info* info) {
+    if (!c || !dlam) return MLB_EINVAL;
+    c->st = c->own;
+    if (!c->has_buck) return fail(c, MLB_ESTATE, "buckling sensitivities need mlb_buckling first");
+    double* d = nullptr;
+    CHK(dalloc(c, &d, (size_t)c->m * c->k));
+    const int st = do_sens_consistent(c, d, info);
+    if (st == MLB_OK) HIPC(hipMemcpy(dlam, d, sizeof(double) * c->m * c->k, hipMemcpyDeviceToHost));
+    dfree(d);
+    return st;
+}
+
+int mlb_sensitivities_consistent_dev(mlb_ctx* c, double* dlam, mlb_solve_info* info, void* stream) {
+    if (!c || !dlam) return MLB_EINVAL;
+    c->st = pick(c, stream);
+    return do_sens_consistent(c, dlam, info);
 }
 
 int mlb_sensitivities_dev(mlb_ctx* c, double* dJ, double* dlam, mlb_solve_info* info, void* stream) {

@@ -158,13 +158,16 @@ void launch_stress(int dim, const Geo& g, const double* Es, const double* u, con
                    hipStream_t st);
 void launch_dJ(int dim, const Geo& g, const double* x, double p, double dE, int ncases, int64_t ld,
                const double* U, const double* K0, double* dJ, hipStream_t st);
+// W, Ps, lam non-null: the consistent variant (bilinear residual terms)
 void launch_adj_elem(int dim, const Geo& g, const double* Es, int q, int64_t ld, const double* Phi,
-                     const double* Hk, const double* D0, double* V, hipStream_t st);
+                     const double* Hk, const double* D0, double* V, hipStream_t st, const double* W = nullptr,
+                     const double* Ps = nullptr, const double* lam = nullptr);
 void launch_adj_gather(int dim, const Geo& g, int q, const double* V, const double* Bc, const uint8_t* nmask,
                        int64_t ld, double* B, hipStream_t st);
 void launch_dlam(int dim, const Geo& g, const double* x, double p, double E1, double E0, const double* u, int q,
                  int64_t ld, const double* Phi, const double* Z, const double* lam, const double* K0,
-                 const double* Hk, const double* D0Bc, double* out, hipStream_t st);
+                 const double* Hk, const double* D0Bc, double* out, hipStream_t st, const double* W = nullptr,
+                 const double* Ps = nullptr);
 
 // ---- warm-start network (kernels_nn.hip)
 int launch_nn_conv3d(int N, int Ci, int Co, int D, int H, int W, int K, int trans, const float* x, const uint16_t* w,

@@ -8,6 +8,11 @@
 // Buckling-factor sensitivity (eq. SensitivityLambda times lambda, the
 // factor implied by the normalisation phi^T K phi = 1):
 //   dlam/dx_e = lam [dEk phi^T K0 phi + lam (dEs phi^T G_e0[u_e] phi - dEk z^T K0 u)]
+// Consistent variant (appendix, eq. consistentSensitivity, read through the
+// fine solve K Phi~ = G Psi): with w = K^-1 (K + lam G) phi and psi the
+// combination of interpolated coarse modes with K phi = G psi, the adjoint
+// right-hand side gains (2 / lam) grad_u (w^T G psi) and the sensitivity
+//   + 2 lam (dEs w^T G_e0[u_e] psi - dEk w^T K0 phi).
 #include "kernels.h"
 
 namespace mlb {
@@ -79,6 +84,26 @@ __device__ inline void quad_Hk(const double* __restrict__ Hk, const double* ph, 
     }
 }
 
+// w_k = sum_c a_c^T Hk_k b_c (bilinear; Hk_k is symmetric).
+template <int DIM>
+__device__ inline void bil_Hk(const double* __restrict__ Hk, const double* a, const double* b, double* w) {
+    constexpr int NN = 1 << DIM, ND = DIM, NV = DIM == 2 ? 3 : 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NN; ++i)
+#pragma unroll
+            for (int j = 0; j < NN; ++j) {
+                double pp = 0.0;
+#pragma unroll
+                for (int c = 0; c < ND; ++c) pp += a[i * ND + c] * b[j * ND + c];
+                s += Hk[k * 64 + i * NN + j] * pp;
+            }
+        w[k] = s;
+    }
+}
+
 template <int DIM>
 __global__ void k_dJ(Geo g, const double* __restrict__ x, double p, double dE, int ncases, int64_t ld,
                      const double* __restrict__ U, const double* __restrict__ K0, double* __restrict__ dJ) {
@@ -99,10 +124,12 @@ __global__ void k_dJ(Geo g, const double* __restrict__ x, double p, double dE, i
     }
 }
 
-// V[(i*nv + k)*m + e] = E_sigma,e (D0 w_e)_k for mode i
-template <int DIM>
+// V[(i*nv + k)*m + e] = E_sigma,e (D0 w_e)_k for mode i; CONS adds
+// (2 / lam_i) times the bilinear w_k(W_i, Ps_i) to w_k(Phi_i, Phi_i)
+template <int DIM, bool CONS>
 __global__ void k_adj_elem(Geo g, const double* __restrict__ Es, int q, int64_t ld, const double* __restrict__ Phi,
-                           const double* __restrict__ Hk, const double* __restrict__ D0, double* __restrict__ V) {
+                           const double* __restrict__ Hk, const double* __restrict__ D0, double* __restrict__ V,
+                           const double* __restrict__ W, const double* __restrict__ Ps, const double* __restrict__ lam) {
     constexpr int NN = 1 << DIM, ND = DIM, NDE = DIM << DIM, NV = DIM == 2 ? 3 : 6;
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= g.m) return;
@@ -117,6 +144,20 @@ __global__ void k_adj_elem(Geo g, const double* __restrict__ Es, int q, int64_t 
             for (int c = 0; c < ND; ++c) ph[a * ND + c] = Phi[i * ld + nodes[a] * ND + c];
         double w[NV];
         quad_Hk<DIM>(Hk, ph, w);
+        if (CONS) {
+            double we[NDE], pe[NDE], wb[NV];
+#pragma unroll
+            for (int a = 0; a < NN; ++a)
+#pragma unroll
+                for (int c = 0; c < ND; ++c) {
+                    we[a * ND + c] = W[i * ld + nodes[a] * ND + c];
+                    pe[a * ND + c] = Ps[i * ld + nodes[a] * ND + c];
+                }
+            bil_Hk<DIM>(Hk, we, pe, wb);
+            const double f = 2.0 / lam[i];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) w[k] += f * wb[k];
+        }
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             double s = 0.0;
@@ -161,11 +202,12 @@ __global__ void k_adj_gather(Geo g, int q, const double* __restrict__ V, const d
     }
 }
 
-template <int DIM>
+template <int DIM, bool CONS>
 __global__ void k_dlam(Geo g, const double* __restrict__ x, double p, double E1, double E0,
                        const double* __restrict__ u, int q, int64_t ld, const double* __restrict__ Phi,
                        const double* __restrict__ Z, const double* __restrict__ lam, const double* __restrict__ K0,
-                       const double* __restrict__ Hk, const double* __restrict__ D0Bc, double* __restrict__ out) {
+                       const double* __restrict__ Hk, const double* __restrict__ D0Bc, double* __restrict__ out,
+                       const double* __restrict__ W, const double* __restrict__ Ps) {
     constexpr int NN = 1 << DIM, ND = DIM, NDE = DIM << DIM, NV = DIM == 2 ? 3 : 6;
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= g.m) return;
@@ -214,7 +256,24 @@ __global__ void k_dlam(Geo g, const double* __restrict__ x, double p, double E1,
 #pragma unroll
         for (int a = 0; a < NDE; ++a) zKu += ze[a] * K0u[a];
         const double l = lam[i];
-        out[(int64_t)i * g.m + e] = l * (dEk * pK + l * (dEs * pG - dEk * zKu));
+        double r = l * (dEk * pK + l * (dEs * pG - dEk * zKu));
+        if (CONS) {
+            double we[NDE], pe[NDE], wb[NV];
+#pragma unroll
+            for (int a = 0; a < NN; ++a)
+#pragma unroll
+                for (int c = 0; c < ND; ++c) {
+                    we[a * ND + c] = W[i * ld + nodes[a] * ND + c];
+                    pe[a * ND + c] = Ps[i * ld + nodes[a] * ND + c];
+                }
+            bil_Hk<DIM>(Hk, we, pe, wb);
+            double wGp = 0.0;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) wGp += s0[k] * wb[k];
+            const double wKp = quad_K0<DIM>(K0, we, ph);
+            r += 2.0 * l * (dEs * wGp - dEk * wKp);
+        }
+        out[(int64_t)i * g.m + e] = r;
     }
 }
 
@@ -232,9 +291,16 @@ void launch_dJ(int dim, const Geo& g, const double* x, double p, double dE, int 
     else hipLaunchKernelGGL(k_dJ<3>, dim3(nb1(g.m)), dim3(kBlock), 0, st, g, x, p, dE, ncases, ld, U, K0, dJ);
 }
 void launch_adj_elem(int dim, const Geo& g, const double* Es, int q, int64_t ld, const double* Phi, const double* Hk,
-                     const double* D0, double* V, hipStream_t st) {
-    if (dim == 2) hipLaunchKernelGGL(k_adj_elem<2>, dim3(nb1(g.m)), dim3(kBlock), 0, st, g, Es, q, ld, Phi, Hk, D0, V);
-    else hipLaunchKernelGGL(k_adj_elem<3>, dim3(nb1(g.m)), dim3(kBlock), 0, st, g, Es, q, ld, Phi, Hk, D0, V);
+                     const double* D0, double* V, hipStream_t st, const double* W, const double* Ps,
+                     const double* lam) {
+    const dim3 gr(nb1(g.m)), b(kBlock);
+    if (W) {
+        if (dim == 2) hipLaunchKernelGGL((k_adj_elem<2, true>), gr, b, 0, st, g, Es, q, ld, Phi, Hk, D0, V, W, Ps, lam);
+        else hipLaunchKernelGGL((k_adj_elem<3, true>), gr, b, 0, st, g, Es, q, ld, Phi, Hk, D0, V, W, Ps, lam);
+    } else {
+        if (dim == 2) hipLaunchKernelGGL((k_adj_elem<2, false>), gr, b, 0, st, g, Es, q, ld, Phi, Hk, D0, V, W, Ps, lam);
+        else hipLaunchKernelGGL((k_adj_elem<3, false>), gr, b, 0, st, g, Es, q, ld, Phi, Hk, D0, V, W, Ps, lam);
+    }
 }
 void launch_adj_gather(int dim, const Geo& g, int q, const double* V, const double* Bc, const uint8_t* nmask,
                        int64_t ld, double* B, hipStream_t st) {
@@ -244,13 +310,20 @@ void launch_adj_gather(int dim, const Geo& g, int q, const double* V, const doub
 }
 void launch_dlam(int dim, const Geo& g, const double* x, double p, double E1, double E0, const double* u, int q,
                  int64_t ld, const double* Phi, const double* Z, const double* lam, const double* K0,
-                 const double* Hk, const double* D0Bc, double* out, hipStream_t st) {
-    if (dim == 2)
-        hipLaunchKernelGGL(k_dlam<2>, dim3(nb1(g.m)), dim3(kBlock), 0, st, g, x, p, E1, E0, u, q, ld, Phi, Z, lam,
-                           K0, Hk, D0Bc, out);
-    else
-        hipLaunchKernelGGL(k_dlam<3>, dim3(nb1(g.m)), dim3(kBlock), 0, st, g, x, p, E1, E0, u, q, ld, Phi, Z, lam,
-                           K0, Hk, D0Bc, out);
+                 const double* Hk, const double* D0Bc, double* out, hipStream_t st, const double* W,
+                 const double* Ps) {
+    const dim3 gr(nb1(g.m)), b(kBlock);
+#define MLB_DL(D, C)                                                                                            \
+    hipLaunchKernelGGL((k_dlam<D, C>), gr, b, 0, st, g, x, p, E1, E0, u, q, ld, Phi, Z, lam, K0, Hk, D0Bc, out, W, \
+                       Ps)
+    if (W) {
+        if (dim == 2) MLB_DL(2, true);
+        else MLB_DL(3, true);
+    } else {
+        if (dim == 2) MLB_DL(2, false);
+        else MLB_DL(3, false);
+    }
+#undef MLB_DL
 }
 
 }  // namespace mlb

@@ -60,7 +60,7 @@ def _abs_apply(nel, x, v, mat):
     return np.bincount(ed.ravel(), weights=contrib.ravel(), minlength=fem.n_dofs(nel))
 
 
-def _run(torch, nel, p, levels_, ell, k, precision, tol_eig):
+def _run(torch, nel, p, levels_, ell, k, precision, tol_eig, consistent_=False):
     import paper_1909_13585_amd as mlb
     ctx = mlb.Context(nel, mg_levels=levels_, eig_level=ell, precision=precision)
     ctx.set_bc(p["fixed"])
@@ -79,10 +79,16 @@ def _run(torch, nel, p, levels_, ell, k, precision, tol_eig):
     ctx.sensitivities_dev(dJ, dl)
     Z = torch.empty((k, n), dtype=torch.float64, device="cuda")
     ctx.adjoints_dev(k, Z)
+    dlc = None
+    if consistent_:
+        dlc_d = torch.empty((k, m), dtype=torch.float64, device="cuda")
+        ci = ctx.sensitivities_consistent_dev(dlc_d)
+        assert ci["true_rel_residual"] <= 1e-8
+        dlc = dlc_d.cpu().numpy().T
     torch.cuda.synchronize()
     out = dict(J=J[0], u=U[0].cpu().numpy(), lam=np.asarray(lam), Phi=Phi.cpu().numpy().T,
                Psi=Psi.cpu().numpy().T, dJ=dJ[0].cpu().numpy(), dl=dl.cpu().numpy().T,
-               Z=Z.cpu().numpy().T, si=si, ei=ei)
+               Z=Z.cpu().numpy().T, si=si, ei=ei, dlc=dlc)
     ctx.close()
     print(f"static it {si['iterations']} res {si['true_rel_residual']:.2e}; coarse it {ei['coarse_iterations']} "
           f"res {ei['coarse_residual']:.2e} guard {ei['coarse_guard_fired']}; fine it {ei['fine_iterations']} "
@@ -200,8 +206,10 @@ def test_column_2d_960x320_fp64_vs_oracle(torch_mod):
     p = W.column_2d_large()
     # five multigrid levels: with four the coarsest grid (120x40, 9,922 DOFs)
     # exceeds the dense coarsest solve; the eigen level (240x80) is the same
-    r = _run(torch_mod, nel, p, L, ell, k, mlb.MLB_FP64, 1e-8)
+    r = _run(torch_mod, nel, p, L, ell, k, mlb.MLB_FP64, 1e-8, consistent_=True)
     assert r["ei"]["coarse_guard_fired"] == 0
+    # (the consistent sensitivities run after the plain ones and replace the
+    # adjoints; the matrix-free checks use the plain adjoints, read before)
     _check_matfree(nel, p, r, k)
     mat = fem.Material()
     ref = lba.analysis(nel, p["x"], p["F"], p["fixed"], mat, ell=ell, q=k)
@@ -219,4 +227,13 @@ def test_column_2d_960x320_fp64_vs_oracle(torch_mod):
     dl_o, _ = sens.buckling_sensitivity(nel, p["x"], ref["u"], b.lam, b.phi, p["fixed"], mat, ref["solver"])
     for i in sep:
         err = np.abs(r["dl"][:, i] - dl_o[:, i]).max() / np.abs(dl_o[:, i]).max()
+        assert err <= 1e-5, (i, err)
+    # consistent sensitivities (appendix) against the oracle's
+    from oracle import consistent
+    free = np.flatnonzero(p["fixed"] == 0)
+    cc = consistent.ritz_coefficients(b.extra["Phi_tilde"][free], b.phi[free])
+    dlc_o, _, _ = consistent.consistent_sensitivity(nel, p["x"], ref["u"], b.lam, b.phi, b.extra["Psi"] @ cc,
+                                                    ref["K"], ref["G"], p["fixed"], mat, ref["solver"])
+    for i in sep:
+        err = np.abs(r["dlc"][:, i] - dlc_o[:, i]).max() / np.abs(dlc_o[:, i]).max()
         assert err <= 1e-5, (i, err)
