@@ -32,11 +32,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel (12-column FP32 Jacobi sweep of
-# the fine level, variant and z chunk as tuned at 192x64x64): rocprofv3
-# FETCH_SIZE x copy factor + WRITE_SIZE x copy factor, KiB per dispatch, from
-# the counter summary under profiles/; None until counters were taken for
-# the current kernel.
-SWEEP_TRAFFIC_BYTES = None
+# the fine level) by tuned (variant, z chunk): rocprofv3 FETCH_SIZE x 1.99973
+# + WRITE_SIZE x 1.0 (factors from a 256 MiB calibration copy), KiB per
+# dispatch, from profiles/jacobi_sweep_h8_192x64x64_12col_fp32_hbm_counters.md;
+# reported only when the run tuned the same tile.
+SWEEP_TRAFFIC_BYTES = {(0, 12): (160331.19 * 1.99973 + 118492.34) * 1024}
 
 
 def parse():
@@ -743,7 +743,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": f"fine-level Jacobi sweep, {k} columns, "
                                                f"{'FP32' if word == 4 else 'FP64'} (k_apply_wht3*)",
                      "achieved": b1 / (sw1 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": b1 / (sw1 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": SWEEP_TRAFFIC_BYTES,
+                     "frac": b1 / (sw1 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": SWEEP_TRAFFIC_BYTES.get((tiles["wht_variant"], tiles["wht_zchunk"])) if tiles and word == 4 else None,
                      "sweep_ms": sw1, "alg_bytes": b1, "launches_timed": args.sweep_reps,
                      "level2_stencil_sweep": {"sweep_ms": sw2, "alg_bytes": b2,
                                               "achieved": b2 / (sw2 * 1e-3) / 1e9,
