@@ -375,6 +375,46 @@ __device__ inline void buf_store(__amdgpu_buffer_rsrc_t rs, uint32_t off, float 
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, v), rs, (int)off, 0, 0);
 }
 
+// The three components of one node (12 or 24 contiguous bytes) in one
+// access (FP32: 96 bits) or two (FP64: 128 + 64 bits).  Out-of-range offsets
+// read zeros and drop stores, like the single-word accesses.
+typedef int mlb_v2i __attribute__((ext_vector_type(2)));
+__device__ inline void buf_load3(__amdgpu_buffer_rsrc_t rs, uint32_t off, float& a, float& b, float& c) {
+    // Components are taken out with shuffles: subscripting the 96-bit result
+    // type lowers to a one-word load whose value fills all three.
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, (int)off, 0, 0);
+    a = __builtin_bit_cast(float, __builtin_shufflevector(v, v, 0)[0]);
+    b = __builtin_bit_cast(float, __builtin_shufflevector(v, v, 1)[0]);
+    c = __builtin_bit_cast(float, __builtin_shufflevector(v, v, 2)[0]);
+}
+__device__ inline void buf_load3(__amdgpu_buffer_rsrc_t rs, uint32_t off, double& a, double& b, double& c) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+    const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(off + 16u), 0, 0);
+    a = __builtin_bit_cast(double, mlb_v2i{(int)__builtin_shufflevector(v, v, 0)[0], (int)__builtin_shufflevector(v, v, 1)[0]});
+    b = __builtin_bit_cast(double, mlb_v2i{(int)__builtin_shufflevector(v, v, 2)[0], (int)__builtin_shufflevector(v, v, 3)[0]});
+    c = __builtin_bit_cast(double, w);
+}
+__device__ inline void buf_store3(__amdgpu_buffer_rsrc_t rs, uint32_t off, float a, float b, float c) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b96(rs, 0, 0, 0));
+    V v;
+    v[0] = __builtin_bit_cast(int, a);
+    v[1] = __builtin_bit_cast(int, b);
+    v[2] = __builtin_bit_cast(int, c);
+    __builtin_amdgcn_raw_buffer_store_b96(v, rs, (int)off, 0, 0);
+}
+__device__ inline void buf_store3(__amdgpu_buffer_rsrc_t rs, uint32_t off, double a, double b, double c) {
+    using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0));
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0));
+    const mlb_v2i ia = __builtin_bit_cast(mlb_v2i, a), ib = __builtin_bit_cast(mlb_v2i, b);
+    V4 v;
+    v[0] = ia[0];
+    v[1] = ia[1];
+    v[2] = ib[0];
+    v[3] = ib[1];
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, c), rs, (int)(off + 16u), 0, 0);
+}
+
 __device__ inline double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ inline float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -482,8 +522,7 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(sizeof
             const uint32_t po = poff(kk), pm = moff(kk);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) buf_load(rX, vo[q] + po + c * (uint32_t)sizeof(T), v[c][q]);
+                buf_load3(rX, vo[q] + po, v[0][q], v[1][q], v[2][q]);
                 if (!CLEAN || q == 0) mk[q] = __builtin_amdgcn_raw_buffer_load_b8(rM, (int)(mo[q] + pm), 0, 0);
             }
         };
@@ -538,10 +577,7 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(sizeof
         // its loads, the stores complete during the element arithmetic.
         T py[3] = {T(0), T(0), T(0)};
         uint32_t pod = kOffLane;
-        auto flush = [&]() {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) buf_store(rY, pod + c * (uint32_t)sizeof(T), py[c]);
-        };
+        auto flush = [&]() { buf_store3(rY, pod, py[0], py[1], py[2]); };
         auto step = [&](int ke, T (&hl)[3][4], const T (&hh)[3][4], T (&olo)[3], uint8_t& mlo, const T& Ecur,
                         T& Enext) {
             T s[9];
@@ -563,14 +599,9 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(sizeof
             buf_load(rE, eo + eoff(ke + 1), Enext);
             const bool out = ke >= kz0;   // wave-uniform
             const uint32_t od = owner && out ? vo[0] + poff(ke) : kOffLane;
-            T rr[3], di[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                rr[c] = T(0);
-                di[c] = T(0);
-                if (MODE != kModeY) buf_load(rR, od + c * (uint32_t)sizeof(T), rr[c]);
-                if (MODE == kModeJacobi) buf_load(rD, od + c * (uint32_t)sizeof(T), di[c]);
-            }
+            T rr[3] = {T(0), T(0), T(0)}, di[3] = {T(0), T(0), T(0)};
+            if (MODE != kModeY) buf_load3(rR, od, rr[0], rr[1], rr[2]);
+            if (MODE == kModeJacobi) buf_load3(rD, od, di[0], di[1], di[2]);
             // all of the step's loads are issued before its arithmetic
             if (kW3rSched >= 2) __builtin_amdgcn_sched_barrier(0);
             T u[3][8];
