@@ -253,6 +253,19 @@ def p1_functions(J, dJ, lam, dlam, x, J0, lam_bar, vol_frac, alpha=0.99):
     return J / J0, np.asarray(dJ, dtype=np.float64) / J0, fval, dfdx
 
 
+
+def p2_functions(J, dJ, lam, dlam, x, J_max, lam_bar, alpha=0.99):
+    """Problem P2 (Sec. 6) in MMA form, with respect to the physical
+    densities x: objective V / |Omega| (the volume fraction); constraints
+    J / J_max - 1 (J_max = 6 times the fully solid design's compliance in the
+    paper) and the bound formulation of reading (b).
+    Returns (f0, df0, fval, dfdx)."""
+    m = x.size
+    g_b, dg_b = bound_constraints(lam, dlam.T, lam_bar, alpha)
+    fval = np.concatenate(([J / J_max - 1.0], g_b))
+    dfdx = np.vstack([np.asarray(dJ, dtype=np.float64)[None, :] / J_max, dg_b])
+    return volume(x), np.full(m, 1.0 / m), fval, dfdx
+
 def p1_step(nel, xhat, F, fixed, mat, ell, q, nb, rmin, eta, beta, J0, lam_bar, vol_frac, mma, alpha=0.99):
     """One design step of problem P1 (Sec. 3) on the design variables xhat:
     density filter and projection (Sec. 2), the analysis of Sec. 2.1 with q

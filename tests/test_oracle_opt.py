@@ -252,3 +252,17 @@ def test_p1_loop_reaches_feasibility_on_a_small_column():
     assert hist[-1][1][1:].max() < 0.0
     assert -0.02 < hist[-1][1][0] <= 1e-3
     assert hist[-1][0] < hist[-4][0]
+
+
+def test_p2_functions_values_and_gradients():
+    rng = np.random.default_rng(8)
+    m, nb = 20, 3
+    x = rng.uniform(0.1, 0.9, m)
+    lam = np.sort(rng.uniform(1.0, 2.0, nb))
+    dlam = rng.normal(size=(m, nb))
+    dJ = rng.normal(size=m)
+    f0, df0, fval, dfdx = opt.p2_functions(3.0, dJ, lam, dlam, x, 2.0, 1.2)
+    assert np.isclose(f0, x.mean()) and np.allclose(df0, 1.0 / m)
+    assert np.isclose(fval[0], 0.5) and np.allclose(dfdx[0], dJ / 2.0)
+    assert np.allclose(fval[1:], 1.0 - 0.99 ** np.arange(1, nb + 1) * lam / 1.2)
+    assert np.allclose(dfdx[1:], -(0.99 ** np.arange(1, nb + 1) / 1.2)[:, None] * dlam.T)
