@@ -407,6 +407,12 @@ int mlb_dilate_dev(mlb_ctx* ctx, int nsel, const double* gradn, double rel_thr, 
 int mlb_dilate_noalloc_dev(mlb_ctx* ctx, int nsel, const double* gradn, double rel_thr, double r_th,
                            const double* x, double* xout, void* stream);
 
+/* SIMP exponent p of eq. interpolationSIMP2-SIMP for the following
+ * mlb_set_density* calls (continuation of p, Secs. 3 and 6).  The moduli of
+ * the current densities are stale afterwards, so every later solve returns
+ * MLB_ESTATE until the densities are set again.  MLB_EINVAL unless p >= 1. */
+int mlb_set_penal(mlb_ctx* ctx, double penal);
+
 /* ---- three-field design variables (Sec. 2) ------------------------------ */
 
 /* Density filter and relaxed Heaviside projection (eq. projectionOperator):

@@ -320,6 +320,10 @@ class Context:
         self._check(self.lib.mlb_dilate_noalloc_dev(self.h, nsel, _dptr(gradn), rel_thr, r_th, _dptr(x),
                                                     _dptr(xout), _stream()))
 
+    def set_penal(self, penal):
+        """SIMP exponent for the following set_density* calls (continuation)."""
+        self._check(self.lib.mlb_set_penal(self.h, float(penal)))
+
     def filter_project_dev(self, xhat, rmin, eta, beta, xtilde, x):
         """Density filter of radius rmin and Heaviside projection (eta, beta) of
         the design variables xhat (m,) into xtilde and x (m,) (Sec. 2)."""

@@ -83,6 +83,17 @@ class MlbBatchInfo(C.Structure):
                 ("solve_s", C.c_double)]
 
 
+
+class MlbMmaOpts(C.Structure):
+    _fields_ = [("xmin", C.c_double), ("xmax", C.c_double), ("move", C.c_double), ("asyinit", C.c_double),
+                ("asyincr", C.c_double), ("asydecr", C.c_double), ("c", C.c_double), ("d", C.c_double)]
+
+
+class MlbMmaInfo(C.Structure):
+    _fields_ = [("dual_iterations", C.c_int), ("dual_evaluations", C.c_int), ("proj_grad", C.c_double),
+                ("dual_value", C.c_double), ("lam", C.c_double * 32), ("y", C.c_double * 32),
+                ("seconds", C.c_double)]
+
 _P = C.c_void_p
 _I = C.c_int
 _D = C.c_double
@@ -131,6 +142,15 @@ _SIGS = {
     "mlb_dilate_noalloc_dev": (_I, [_P, _I, _P, _D, _D, _P, _P, _P]),
     "mlb_filter_project_dev": (_I, [_P, _P, _D, _D, _D, _P, _P, _P]),
     "mlb_filter_chain_dev": (_I, [_P, _I, _P, _D, _D, _D, _P, _P, _P, _P]),
+    "mlb_set_penal": (_I, [_P, _D]),
+    # optimisation layer (include/mlb_opt.h)
+    "mlb_continuation": (_I, [_I, _D, _D, _I, _D, _D, _I, _D, C.POINTER(_D), C.POINTER(_D)]),
+    "mlb_p1_functions_dev": (_I, [C.c_int64, _I, _P, _D, _P, _P, _P, C.c_int64, _D, _D, _D, _D, _P, _P, _P, _P]),
+    "mlb_p2_functions_dev": (_I, [C.c_int64, _I, _P, _D, _P, _P, _P, C.c_int64, _D, _D, _D, _P, _P, _P, _P]),
+    "mlb_mma_create": (_I, [C.c_int64, _I, C.POINTER(MlbMmaOpts), _I, C.POINTER(_P)]),
+    "mlb_mma_destroy": (None, [_P]),
+    "mlb_mma_last_error": (C.c_char_p, [_P]),
+    "mlb_mma_update_dev": (_I, [_P, _P, _D, _P, _P, _P, C.c_int64, C.POINTER(MlbMmaInfo), _P]),
     # warm-start network kernels (include/mlb_nn.h)
     "mlb_nn_conv3d": (_I, [_I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P]),
     "mlb_nn_conv3d_wgrad": (_I, [_I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),

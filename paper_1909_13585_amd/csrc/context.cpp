@@ -1894,6 +1894,16 @@ static int set_density_common(mlb_ctx* c) {
     return build_hierarchy(c);
 }
 
+int mlb_set_penal(mlb_ctx* c, double penal) {
+    if (!c) return MLB_EINVAL;
+    if (!(penal >= 1.0) || !std::isfinite(penal)) return fail(c, MLB_EINVAL, "penalty p must be finite and >= 1");
+    c->d.penal = penal;
+    // the moduli were interpolated with the old exponent
+    c->has_density = false;
+    c->has_static = c->has_buck = c->has_stress = c->has_adj = false;
+    return MLB_OK;
+}
+
 int mlb_set_density(mlb_ctx* c, const double* x) {
     if (!c || !x) return MLB_EINVAL;
     c->st = c->own;

@@ -190,4 +190,23 @@ void launch_nn_adam(int64_t n, float lr, float b1, float b2, float eps, int step
                     const float* g, float* m, float* v, hipStream_t st);
 void launch_nn_to_bf16(int64_t n, const float* a, uint16_t* b, hipStream_t st);
 
+// method of moving asymptotes and design-problem columns (kernels_mma.hip)
+constexpr int kMmaMaxCon = 32;
+struct MmaLam {
+    double v[kMmaMaxCon];
+};
+struct MmaParams {
+    double xmin, xmax, move, asyinit, asyincr, asydecr;
+};
+int mma_parts(int64_t n);
+void launch_mma_prep(int64_t n, int m, int it, const MmaParams& pr, const double* x, double* xold1, double* xold2,
+                     double* low, double* upp, double* alo, double* bhi, const double* df0, const double* dfdx,
+                     int64_t ldg, int nparts, double* part, hipStream_t st);
+void launch_mma_dual(int64_t n, int m, const MmaLam& lam, const MmaParams& pr, const double* xk, const double* low,
+                     const double* upp, const double* alo, const double* bhi, const double* df0, const double* dfdx,
+                     int64_t ldg, int nparts, double* part, double* B, double* xout, hipStream_t st);
+void launch_opt_cols(int64_t m, int kind, int nb, const double* x, const double* dJ, double sJ, double vcol,
+                     const double* dlam, int64_t ld, const MmaLam& w, double* grad, int nparts, double* part,
+                     hipStream_t st);
+
 }  // namespace mlb

@@ -106,7 +106,8 @@ def test_struct_fields_match_header():
     structs = _declared_structs()
     pairs = {"mlb_desc": B.MlbDesc, "mlb_opts": B.MlbOpts, "mlb_solve_info": B.MlbSolveInfo,
              "mlb_eig_info": B.MlbEigInfo, "mlb_tune_info": B.MlbTuneInfo, "mlb_batch_desc": B.MlbBatchDesc,
-             "mlb_batch_opts": B.MlbBatchOpts, "mlb_batch_info": B.MlbBatchInfo}
+             "mlb_batch_opts": B.MlbBatchOpts, "mlb_batch_info": B.MlbBatchInfo, "mlb_mma_opts": B.MlbMmaOpts,
+             "mlb_mma_info": B.MlbMmaInfo}
     assert set(pairs) <= set(structs)
     for cname, py in pairs.items():
         assert [f for f, _ in py._fields_] == structs[cname], cname
@@ -117,7 +118,8 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     B = _binding()
     pairs = {"mlb_desc": B.MlbDesc, "mlb_opts": B.MlbOpts, "mlb_solve_info": B.MlbSolveInfo,
              "mlb_eig_info": B.MlbEigInfo, "mlb_tune_info": B.MlbTuneInfo, "mlb_batch_desc": B.MlbBatchDesc,
-             "mlb_batch_opts": B.MlbBatchOpts, "mlb_batch_info": B.MlbBatchInfo}
+             "mlb_batch_opts": B.MlbBatchOpts, "mlb_batch_info": B.MlbBatchInfo, "mlb_mma_opts": B.MlbMmaOpts,
+             "mlb_mma_info": B.MlbMmaInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>'] + [f'#include "{h}"' for h in HEADERS] + ["int main(void) {"]
     for cname, py in pairs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
