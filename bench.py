@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-five-level", action="store_true", help="skip the 5-level hierarchy leg")
     ap.add_argument("--no-column", action="store_true", help="skip the 960x320 column leg")
     ap.add_argument("--no-block16", action="store_true", help="skip the 16-column block leg on 96x48x48")
+    ap.add_argument("--no-opt", action="store_true", help="skip the design-step (P2, Sec. 6) leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3, help="oracle runs of the CPU sample (median reported)")
     ap.add_argument("--instances-only", action="store_true",
@@ -466,6 +467,67 @@ def sweep_bytes(dim, nel, level, ncols, word):
     return b
 
 
+def optimisation_leg(args, steps=3):
+    """Design steps of problem P2 (Sec. 6) on the bench box: minimum volume
+    with the lowest 12 of 24 buckling factors bounded (bound formulation,
+    alpha 0.99) and the compliance at most 6 times the solid design's; filter
+    radius 4 sqrt(3), eta 0.5, p = 3 and beta = 1 (the start of Sec. 6's
+    continuation).  As in Sec. 6 the start is the solid design, feasible
+    for lambda_bar = 0.4 lambda_1(solid) (the section's bounds are at most
+    0.42 of its solid factor).  Each step: filter and projection, analysis,
+    sensitivities, problem functions, chain rule, MMA update.  One untimed
+    step, then the median of ``steps``."""
+    import numpy as np
+    import torch
+    import paper_1909_13585_amd as mlb
+    import workloads as W
+    from paper_1909_13585_amd.optimize import P2Step
+    nel = tuple(int(v) for v in args.nel.split(","))
+    p = W.box_3d(nel=nel, seed=3)
+    ctx = mlb.Context(nel, mg_levels=args.levels, eig_level=args.eig_level, precision=mlb.MLB_MIXED)
+    set_solver_opts(ctx, args)
+    ctx.set_bc(p["fixed"])
+    ctx.set_loads(p["F"])
+    n, m = ctx.level_size(1)
+    U = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    ctx.set_density_dev(torch.ones(m, dtype=torch.float64, device="cuda"))
+    J_solid, _ = ctx.solve_static_dev(U, tol=1e-8, max_it=3000)
+    xhat = torch.ones(m, dtype=torch.float64, device="cuda")
+    rmin, q, nb = 4.0 * np.sqrt(3.0), 24, 12
+    lam_solid, _ = ctx.buckling_dev(q, None, tol_eig=args.tol_eig)
+    lam_bar = 0.4 * lam_solid[0]
+    stepper = P2Step(ctx, q, nb, rmin, 0.5, 1.0, 6.0 * J_solid[0], lam_bar, tol_eig=args.tol_eig)
+    rows = []
+    for s in range(steps + 1):
+        tm = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = stepper.step(xhat, penal=3.0, beta=1.0, timings=tm)
+        torch.cuda.synchronize()
+        tm["step_s"] = time.perf_counter() - t0
+        tm.update(volume=info["f0"], max_constraint=float(np.max(info["fval"])),
+                  dual_evaluations=info["dual_evaluations"], dual_iterations=info["dual_iterations"])
+        rows.append(tm)
+        print(f"# P2 step {s}: {tm}", file=sys.stderr, flush=True)
+    ctx.close()
+    timed = rows[1:]
+    med = lambda key: float(np.median([r[key] for r in timed]))
+    mcon = 1 + nb
+    ev = float(np.median([r["dual_evaluations"] for r in timed]))
+    # algorithmic bytes of one MMA update: the preparation pass, the dual
+    # passes (gradient rows, 5 per-variable arrays, B written and read by the
+    # Gram product) and the final pass
+    mma_bytes = 8 * m * ((mcon + 12) + ev * (3 * mcon + 6) + (mcon + 7))
+    return {"workload": f"P2 (Sec. 6) design steps on the H8 box {nel[0]}x{nel[1]}x{nel[2]}: {q} modes, lowest "
+                        f"{nb} bounded, rmin 4 sqrt(3), p 3, beta 1, mixed precision, {args.levels} levels",
+            "s_per_design_step": med("step_s"), "analysis_s": med("analysis_s"),
+            "functions_chain_s": med("functions_chain_s"), "mma_s": med("mma_s"),
+            "mma_dual_evaluations": ev, "mma_alg_bytes": mma_bytes,
+            "mma_gbs": mma_bytes / med("mma_s") / 1e9,
+            "volume_after": [r["volume"] for r in rows], "max_constraint_after": [r["max_constraint"] for r in rows],
+            "lambda_bar": float(lam_bar), "lambda1_solid": float(lam_solid[0]), "J_max": float(6.0 * J_solid[0])}
+
+
 def column_leg(args, steps=3):
     """The 960x320 Q4 column (616,962 DOFs) in plain FP64 on 4 and 5 multigrid
     levels: static solve + 12 modes on the 240x80 eigen level + sensitivities."""
@@ -680,6 +742,7 @@ def main():
 
     column = None if args.no_column else column_leg(args)
     block16 = None if args.no_block16 else block16_leg(args)
+    optim = None if args.no_opt else optimisation_leg(args)
     inst = None if args.no_instances else batched_instances()
 
     cpu = None
@@ -734,6 +797,7 @@ def main():
         "learned_warm_start": learned,
         "column_960x320_fp64": column,
         "block16_96x48x48": block16,
+        "optimisation_p2": optim,
         "pinvit_refinement": pinv,
         "intermediate_refinement": refine,
         "incompatible_element": incompatible,

@@ -288,3 +288,24 @@ def p1_step(nel, xhat, F, fixed, mat, ell, q, nb, rmin, eta, beta, J0, lam_bar, 
     xnew, info = mma.update(xhat, f0, dhat[:, 0], fval, dhat[:, 1:].T)
     info.update(J=J, lam=buck.lam.copy(), x=x, xtilde=xt, f0=f0, fval=fval, grad_hat=dhat, grad_x=cols)
     return xnew, info
+
+
+def p2_step(nel, xhat, F, fixed, mat, ell, q, nb, rmin, eta, beta, J_max, lam_bar, mma, alpha=0.99):
+    """One design step of problem P2 (Sec. 6): as ``p1_step`` with the volume
+    fraction as objective and the compliance bound J <= J_max as the first
+    constraint.  Returns (xhat_new, diagnostics)."""
+    from . import design, lba, sens
+    xt = design.filter_density(nel, xhat, rmin)
+    x = design.project(xt, eta, beta)
+    an = lba.analysis(nel, x, F, fixed, mat, ell, q)
+    J = float(an["J"][0])
+    buck = an["buck"]
+    lam = buck.lam[:nb]
+    dJ = sens.compliance_sensitivity(nel, x, an["U"][:, :1], mat)[:, 0]
+    dlam, _ = sens.buckling_sensitivity(nel, x, an["u"], lam, buck.phi[:, :nb], fixed, mat, an["solver"])
+    f0, df0, fval, dfdx = p2_functions(J, dJ, lam, dlam, x, J_max, lam_bar, alpha)
+    cols = np.vstack([df0[None, :], dfdx]).T
+    dhat = design.chain_rule(nel, xt, rmin, eta, beta, cols)
+    xnew, info = mma.update(xhat, f0, dhat[:, 0], fval, dhat[:, 1:].T)
+    info.update(J=J, lam=buck.lam.copy(), x=x, xtilde=xt, f0=f0, fval=fval, grad_hat=dhat, grad_x=cols)
+    return xnew, info

@@ -454,9 +454,14 @@ int gram(mlb_ctx* c, int64_t n, int k1, const double* A, int64_t lda, int k2, co
     return MLB_OK;
 }
 
-// G1 = A^T B1, G2 = A^T B2 (each k1 x k2) in one pass over A.
+// G1 = A^T B1, G2 = A^T B2 (each k1 x k2) in one pass over A, or in two when
+// the three operands together are wider than the Gram kernel's 192 columns.
 int gram2(mlb_ctx* c, int64_t n, int k1, const double* A, int k2, const double* B1, const double* B2,
           std::vector<double>& G1, std::vector<double>& G2) {
+    if (k1 + 2 * k2 > 192) {
+        CHK(gram(c, n, k1, A, n, k2, B1, n, G1));
+        return gram(c, n, k1, A, n, k2, B2, n, G2);
+    }
     std::vector<double> G;
     CHK(gram(c, n, k1, A, n, k2, B1, n, G, k2, B2, n));
     const size_t h = (size_t)k1 * k2;
@@ -914,8 +919,8 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
     Level& l = c->lv[j - 1];
     const int64_t n = l.n;
     int guard = c->o.eig_guard > 0 ? c->o.eig_guard : std::max(4, k / 2);
-    const int nb = std::min(k + guard, 24);
-    if (nb <= k) return fail(c, MLB_EINVAL, "k must be at most 23");
+    const int nb = std::min(k + guard, 32);
+    if (nb <= k) return fail(c, MLB_EINVAL, "k must be at most 31");
     if (nb > n / 2) return fail(c, MLB_EINVAL, "eigen level too small for the requested modes");
     CHK(ensure_level_cols(c, nb));
     if (nb > c->eig_cap) {

@@ -128,17 +128,24 @@ class MMA:
                     y=np.array(info.y[:self.m]), seconds=info.seconds)
 
 
-class P1Step:
-    """Device buffers and settings of one P1 design-step sequence (Sec. 3) on
-    a context whose Dirichlet mask and loads are set.  ``step(xhat)`` runs
-    one design step in place on the device design variables xhat (m,)."""
+class DesignStep:
+    """Device buffers and settings of one design-step sequence on a context
+    whose Dirichlet mask and loads are set: problem 1 = P1 (Sec. 3, minimum
+    compliance; ``scale`` = J0 normalises the objective, ``f_bar`` the
+    volume bound), problem 2 = P2 (Sec. 6, minimum volume; ``scale`` = J_max
+    bounds the compliance).  ``step(xhat)`` runs one design step in place on
+    the device design variables xhat (m,): filter and projection, analysis
+    with q modes, sensitivities, problem functions with nb bounded factors,
+    chain rule, MMA update."""
 
-    def __init__(self, ctx, q, nb, rmin, eta, beta, J0, lam_bar, f_bar, alpha=0.99, tol=1e-8, tol_eig=1e-8,
-                 max_it=3000, mma=None):
+    def __init__(self, ctx, problem, q, nb, rmin, eta, beta, scale, lam_bar, f_bar=1.0, alpha=0.99, tol=1e-8,
+                 tol_eig=1e-8, max_it=3000, mma=None, **mma_opts):
         import torch
-        self.ctx, self.q, self.nb = ctx, q, nb
+        if problem not in (1, 2):
+            raise ValueError("problem must be 1 (P1) or 2 (P2)")
+        self.ctx, self.problem, self.q, self.nb = ctx, problem, q, nb
         self.rmin, self.eta, self.beta = rmin, eta, beta
-        self.J0, self.lam_bar, self.f_bar, self.alpha = J0, lam_bar, f_bar, alpha
+        self.scale, self.lam_bar, self.f_bar, self.alpha = scale, lam_bar, f_bar, alpha
         self.tol, self.tol_eig, self.max_it = tol, tol_eig, max_it
         m, n = ctx.m, ctx.n
         dev = dict(dtype=torch.float64, device="cuda")
@@ -150,19 +157,57 @@ class P1Step:
         self.gx = torch.empty((2 + nb, m), **dev)
         self.work = torch.empty((2 + nb, m), **dev)
         self.gh = torch.empty((2 + nb, m), **dev)
-        self.mma = mma or MMA(m, 1 + nb)
+        self.mma = mma or MMA(m, 1 + nb, **mma_opts)
 
-    def step(self, xhat):
+    def step(self, xhat, penal=None, beta=None, timings=None):
+        """One design step; ``penal`` / ``beta`` (optional) first move the SIMP
+        exponent and the projection sharpness (continuation).  With a dict
+        ``timings``, wall times of the analysis, the functions + chain rule
+        and the MMA update are stored in it (the stream is synchronised
+        between the parts)."""
+        import time
+        import torch
         c = self.ctx
+        if penal is not None:
+            c.set_penal(penal)
+        if beta is not None:
+            self.beta = float(beta)
+        t0 = time.perf_counter()
         c.filter_project_dev(xhat, self.rmin, self.eta, self.beta, self.xt, self.x)
         c.set_density_dev(self.x)
         J, si = c.solve_static_dev(self.U, tol=self.tol, max_it=self.max_it)
         lam, ei = c.buckling_dev(self.q, None, tol_eig=self.tol_eig)
         c.sensitivities_dev(self.dJ, self.dlam)
-        f0, fval = p1_functions_dev(self.x, J[0], self.dJ, lam[:self.nb], self.dlam, self.J0, self.lam_bar,
-                                    self.f_bar, self.gx, self.alpha)
+        if timings is not None:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        if self.problem == 1:
+            f0, fval = p1_functions_dev(self.x, J[0], self.dJ, lam[:self.nb], self.dlam, self.scale, self.lam_bar,
+                                        self.f_bar, self.gx, self.alpha)
+        else:
+            f0, fval = p2_functions_dev(self.x, J[0], self.dJ, lam[:self.nb], self.dlam, self.scale, self.lam_bar,
+                                        self.gx, self.alpha)
         c.filter_chain_dev(self.xt, self.rmin, self.eta, self.beta, self.gx, self.work, self.gh)
+        if timings is not None:
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
         info = self.mma.update_dev(xhat, f0, self.gh[0], fval, self.gh[1:])
+        if timings is not None:
+            timings.update(analysis_s=t1 - t0, functions_chain_s=t2 - t1, mma_s=time.perf_counter() - t2)
         info.update(J=float(J[0]), lam=lam, f0=f0, fval=fval, static_iterations=si["iterations"],
                     coarse_iterations=ei["coarse_iterations"])
         return info
+
+
+class P1Step(DesignStep):
+    """Design steps of P1 (Sec. 3): objective J / J0, volume fraction <= f_bar."""
+
+    def __init__(self, ctx, q, nb, rmin, eta, beta, J0, lam_bar, f_bar, **kw):
+        super().__init__(ctx, 1, q, nb, rmin, eta, beta, J0, lam_bar, f_bar, **kw)
+
+
+class P2Step(DesignStep):
+    """Design steps of P2 (Sec. 6): objective volume fraction, J <= J_max."""
+
+    def __init__(self, ctx, q, nb, rmin, eta, beta, J_max, lam_bar, **kw):
+        super().__init__(ctx, 2, q, nb, rmin, eta, beta, J_max, lam_bar, **kw)

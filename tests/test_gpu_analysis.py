@@ -153,3 +153,15 @@ def test_error_paths():
     c.close()
     with pytest.raises(mlb.MlbError):
         mlb.Context((15, 8), mg_levels=2, eig_level=1)
+
+
+def test_24_modes_2d():
+    """24 modes (the count Secs. 3 and 6 compute): the coarse eigensolver's
+    block is 32 columns wide, so its Gram products take two passes.  Factors,
+    modes and sensitivities against the oracle."""
+    p = W.column_2d_small()
+    nel, k, L, ell = p["nel"], 24, 3, 2
+    print(f"case column_2d_small k={k} ell={ell}", flush=True)
+    g = _run(nel, p["x"], p["F"], p["fixed"], L, ell, k)
+    ref = _oracle(nel, p["x"], p["F"], p["fixed"], ell, k, L)
+    _check(g, ref, p["fixed"], p["F"], k)

@@ -104,7 +104,8 @@ def test_p1_p2_functions_match_oracle(torch):
 
 def test_p1_design_steps_match_oracle(torch):
     """Three P1 steps on a 48x16 Q4 column (eigen level 2, 6 modes, 4
-    constrained, filter radius 2.5, beta 6) from the same start: the GPU's
+    constrained, filter radius 2.5, beta 6; p and beta moved on the third
+    step) from the same start: the GPU's
     design variables, compliance and factors against the oracle's
     (direct solves), each side on its own trajectory."""
     import paper_1909_13585_amd as mlb
@@ -127,9 +128,12 @@ def test_p1_design_steps_match_oracle(torch):
     xo = x0.copy()
     orc = O.MMA(m, 5)
     bars = [1e-8, 1e-8, 1e-8]
+    # the third step moves p and beta (continuation) on both sides
+    sched = [(3.0, 6.0), (3.0, 6.0), (3.25, 8.0)]
     for k in range(3):
-        gi = stepper.step(xg)
-        xo, oi = O.p1_step(nel, xo, F, fixed, mat, 2, 6, 4, 2.5, 0.5, 6.0, J0, lam_bar, 0.4, orc)
+        p, beta = sched[k]
+        gi = stepper.step(xg, penal=p, beta=beta)
+        xo, oi = O.p1_step(nel, xo, F, fixed, fem.Material(p=p), 2, 6, 4, 2.5, 0.5, beta, J0, lam_bar, 0.4, orc)
         err = np.max(np.abs(xg.cpu().numpy() - xo))
         print(f"step {k}: J {gi['J']:.10e} vs {oi['J']:.10e}, lam1 {gi['lam'][0]:.10f} vs {oi['lam'][0]:.10f}, "
               f"max|dxhat| {err:.2e}, dual its {gi['dual_iterations']}")
@@ -137,4 +141,43 @@ def test_p1_design_steps_match_oracle(torch):
         assert np.max(np.abs(gi["lam"][:4] / oi["lam"][:4] - 1)) < 1e-7
         assert np.allclose(gi["fval"], oi["fval"], rtol=0, atol=1e-7)
         assert err < bars[k], k
+    ctx.close()
+
+
+def test_p2_design_steps_match_oracle(torch):
+    """Two P2 steps (Sec. 6: minimum volume, compliance at most J_max) on a
+    16x12x8 H8 box from a random start (eigen level 2, 6 modes, 4
+    constrained), continuation of p on the second step, against the
+    oracle's steps.  The section and the start are chosen so that the
+    bounded factors are simple (gaps of 14 % or more): a repeated factor's
+    individual sensitivities depend on the basis of its eigenspace, which
+    two correct solvers need not share."""
+    import paper_1909_13585_amd as mlb
+    import workloads as W
+    from oracle import fem, lba
+    from paper_1909_13585_amd.optimize import P2Step
+    nel = (16, 12, 8)
+    fixed = W.clamp_mask(nel)
+    F = W.axial_load(nel)[:, None]
+    m = 16 * 12 * 8
+    x0 = W.random_small(3, nel, 21, 0.35, 0.65)
+    an = lba.analysis(nel, x0, F, fixed, fem.Material(p=3.0), 2, 6)
+    J_max, lam_bar = 1.5 * float(an["J"][0]), 1.1 * an["buck"].lam[0]
+    ctx = mlb.Context(nel, mg_levels=3, eig_level=2)
+    ctx.set_bc(fixed)
+    ctx.set_loads(F)
+    stepper = P2Step(ctx, 6, 4, 1.8, 0.5, 2.0, J_max, lam_bar, tol=1e-11, tol_eig=1e-11)
+    xg = _dev(torch, x0)
+    xo = x0.copy()
+    orc = O.MMA(m, 5)
+    for k, p in enumerate((3.0, 3.25)):
+        gi = stepper.step(xg, penal=p)
+        xo, oi = O.p2_step(nel, xo, F, fixed, fem.Material(p=p), 2, 6, 4, 1.8, 0.5, 2.0, J_max, lam_bar, orc)
+        err = np.max(np.abs(xg.cpu().numpy() - xo))
+        print(f"P2 step {k}: volume {gi['f0']:.8f} vs {oi['f0']:.8f}, fval {np.round(gi['fval'], 5)}, "
+              f"max|dxhat| {err:.2e}")
+        assert abs(gi["f0"] - oi["f0"]) < 1e-12
+        assert abs(gi["J"] / oi["J"] - 1) < 1e-8
+        assert np.allclose(gi["fval"], oi["fval"], rtol=0, atol=1e-7)
+        assert err < 1e-8, k
     ctx.close()
