@@ -207,3 +207,31 @@ def test_adjoint_rhs_directional_derivative():
         G = fem.assemble_G(nel, fem.element_stresses(nel, x, uu, MAT))
         return phi @ (G @ phi)
     assert abs((q(u + 0.7 * v) - q(u)) / 0.7 - b @ v) < 1e-12 * max(1.0, abs(b @ v))
+
+
+@pytest.mark.parametrize("nel,q", [((40, 12), 6), ((12, 4, 4), 12)])
+def test_arpack_branch_matches_dense_eigh(nel, q):
+    """The two branches of generalized_lowest_positive (dense LAPACK eigh
+    below the size limit, ARPACK shift-invert above it) on the same free-DOF
+    matrices: factors to 1e-11, K-normalised modes equal up to sign
+    (|psi_a^T K psi_d| = 1 to 1e-9) for separated factors, same next gap."""
+    import workloads as W
+    from oracle import fem, lba
+    x = W.random_small(len(nel), nel, 9, 0.2, 1.0)
+    fixed = W.clamp_mask(nel)
+    F = W.axial_load(nel)[:, None]
+    mat = fem.Material()
+    an = lba.analysis(nel, x, F, fixed, mat, 1, 1)
+    free = np.flatnonzero(fixed == 0)
+    Kff = an["K"][free][:, free]
+    Gff = an["G"][free][:, free]
+    assert Kff.shape[0] < 6000
+    lam_d, V_d, mu_d = lba.generalized_lowest_positive(Kff, Gff, q, dense_limit=10 ** 9)
+    lam_a, V_a, mu_a = lba.generalized_lowest_positive(Kff, Gff, q, dense_limit=0)
+    assert np.max(np.abs(lam_a / lam_d - 1)) < 1e-11
+    assert abs(mu_a / mu_d - 1) < 1e-9
+    KV = Kff @ V_d
+    for i in range(q):
+        gaps = [abs(lam_d[i] - lam_d[j]) / lam_d[i] for j in range(q) if j != i]
+        if min(gaps) > 1e-6:
+            assert abs(abs(V_a[:, i] @ KV[:, i]) - 1) < 1e-9, i
