@@ -69,16 +69,23 @@ typedef struct {
                              per ticket on contended counters) */
     int graphs;           /* 1: capture one CG iteration as a HIP graph (default) */
     int check_every;      /* iterations between host convergence reads, default 4 */
+    int refine_steps;     /* iterative-refinement steps after the solve, 0..16, default 10 (0: none);
+                             see mlb_batch_solve_dev */
 } mlb_batch_opts;
 
 typedef struct {
     int max_iterations;       /* largest CG iteration count over the instances */
     int total_iterations;     /* sum over the instances */
     int batch_iterations;     /* batched iterations launched */
-    int converged;            /* instances that met the tolerance */
-    double worst_true_rel_res;/* max_i ||f_i - K_i u_i|| / ||f_i|| (free DOFs), recomputed at the end */
+    int converged;            /* instances whose CG met the tolerance (recursive residual) */
+    double worst_true_rel_res;/* max_i ||f_i - K_i u_i|| / ||f_i|| (free DOFs) of the returned FP64 u,
+                                 evaluated in double-double */
     double setup_s;           /* wall time of the last mlb_batch_set_problem_dev */
     double solve_s;           /* wall time of the last solve */
+    int refine_steps;         /* refinement steps taken */
+    int misses;               /* instances whose true residual stays above tol */
+    double worst_floor;       /* largest FP64 floor eps ||(|K_i||u_i|)|| / ||f_i|| among the misses */
+    double worst_refined_rel_res; /* the same for the double-double solution the returned u rounds */
 } mlb_batch_info;
 
 /* Creates a batch for the grids in desc; allocates all device memory. */
@@ -101,13 +108,34 @@ int mlb_batch_set_problem_dev(mlb_batch* b, const uint8_t* fixed, const double* 
 
 /* Solves K_i u_i = f_i for every instance by FP64 CG preconditioned with one
    V-cycle per iteration, each to ||f_i - K_i u_i|| <= tol ||f_i|| (free
-   DOFs; recursive residual, the true one is recomputed and reported).
+   DOFs, recursive residual).  Then up to refine_steps steps of iterative
+   refinement of a double-double solution u_hi + u_lo: its true residual in
+   double-double (error-free products and sums), a batched correction solve
+   to 1e-4 relative, u += correction in double-double; an instance is done at
+   a residual below tol / 100, and the steps stop when all are done or none
+   of the others lowers its residual by 10 % in a step.  The returned u is
+   fl(u_hi + u_lo), the double nearest to the refined solution.
+   Near-singular designs (tiny moduli over large regions, displacements
+   orders of magnitude above their strain parts) can have an FP64 floor
+   above tol: rounding u to doubles alone moves the residual by about
+   eps ||(|K||u|)|| / ||f||, so no FP64 u meets tol there, even the rounded
+   exact solution; such instances are counted in info->misses, and every
+   instance's residuals (returned u, refined solution) and floor come from
+   mlb_batch_residuals.
    U: device [dof_off[ninst]] (output; zero start).  J: host [ninst]
-   compliances f_i^T u_i, iters: host [ninst] iteration counts (either may be
-   NULL).  MLB_ENOTCONV if an instance needs more than max_it iterations,
-   MLB_EBREAKDOWN on p^T K p <= 0. */
+   compliances f_i^T u_i, iters: host [ninst] iteration counts of all CG
+   passes (either may be NULL).  MLB_ENOTCONV if an instance needs more than
+   max_it iterations, MLB_EBREAKDOWN on p^T K p <= 0. */
 int mlb_batch_solve_dev(mlb_batch* b, double tol, int max_it, double* U, double* J, int* iters,
                         mlb_batch_info* info, void* stream);
+
+/* Per-instance results of the last solve (host arrays of ninst, any may be
+   NULL): res[i] = ||f_i - K_i u_i|| / ||f_i|| of the returned u, evaluated
+   in double-double; floor[i] = eps ||(|K_i||u_i|)|| / ||f_i|| (free DOFs),
+   the residual that rounding u_i to doubles alone can cause; res_refined[i]
+   the residual of the double-double solution u_i rounds.  MLB_ESTATE before
+   a solve. */
+int mlb_batch_residuals(const mlb_batch* b, double* res, double* floor, double* res_refined);
 
 /* Compliance sensitivities dJ_i/dx_e = -p x_e^(p-1) (E1 - E0) u_e^T K0 u_e of
    the last solve, device [elem_off[ninst]]. */

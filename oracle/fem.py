@@ -303,6 +303,34 @@ def apply_K_matfree(nel, x, v, mat):
     return np.bincount(ed.ravel(), weights=contrib.ravel(), minlength=n_dofs(nel))
 
 
+def residual_extended(nel, x, u, f, fixed, mat):
+    """r = f - K[x] u on the free DOFs (zero at fixed ones), evaluated in the
+    platform's extended precision (numpy longdouble: a 64-bit significand on
+    x86-64) by an element loop, then rounded to float64; u may be float64 or
+    longdouble.  On x86-64 it is
+    about 2000 times closer to the exact residual of the stored u than an
+    FP64 evaluation, whose own rounding (eps |K||u|) hides the residual of
+    nearly singular designs.  Also returns |K||u| (free DOFs, float64)."""
+    ld = np.longdouble
+    dim = len(nel)
+    Ke0 = material_stiffness(dim, mat).astype(ld)
+    Ek, _ = moduli(np.asarray(x, dtype=np.float64), mat)
+    ed = element_dofs(nel)
+    uu = np.asarray(u)
+    ue = (uu if uu.dtype == ld else uu.astype(np.float64))[ed].astype(ld)
+    contrib = Ek.astype(ld)[:, None] * (ue @ Ke0.T)
+    Ku = np.zeros(n_dofs(nel), dtype=ld)
+    np.add.at(Ku, ed.ravel(), contrib.ravel())
+    # |K||u| entrywise: sum over the row's terms of |E_e K0_ab u_b|
+    acontrib = Ek[:, None] * (np.abs(uu.astype(np.float64)[ed]) @ np.abs(material_stiffness(dim, mat)).T)
+    absK = np.bincount(ed.ravel(), weights=acontrib.ravel(), minlength=n_dofs(nel))
+    free = np.asarray(fixed) == 0
+    r = (np.asarray(f, dtype=np.float64).astype(ld) - Ku).astype(np.float64)
+    r[~free] = 0.0
+    absK[~free] = 0.0
+    return r, absK
+
+
 def apply_G_matfree(nel, s, v):
     """y = G v by an element loop from per-element stresses ``s``."""
     dim = len(nel)

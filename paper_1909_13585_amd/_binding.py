@@ -74,13 +74,14 @@ class MlbBatchDesc(C.Structure):
 
 class MlbBatchOpts(C.Structure):
     _fields_ = [("smooth_steps", C.c_int), ("jacobi_omega", C.c_double), ("queue", C.c_int), ("graphs", C.c_int),
-                ("check_every", C.c_int)]
+                ("check_every", C.c_int), ("refine_steps", C.c_int)]
 
 
 class MlbBatchInfo(C.Structure):
     _fields_ = [("max_iterations", C.c_int), ("total_iterations", C.c_int), ("batch_iterations", C.c_int),
                 ("converged", C.c_int), ("worst_true_rel_res", C.c_double), ("setup_s", C.c_double),
-                ("solve_s", C.c_double)]
+                ("solve_s", C.c_double), ("refine_steps", C.c_int), ("misses", C.c_int),
+                ("worst_floor", C.c_double), ("worst_refined_rel_res", C.c_double)]
 
 
 
@@ -177,6 +178,7 @@ _SIGS = {
     "mlb_batch_set_problem_dev": (_I, [_P, _P, _P, _P, _P]),
     "mlb_batch_solve_dev": (_I, [_P, _D, _I, _P, _P, _P, C.POINTER(MlbBatchInfo), _P]),
     "mlb_batch_compliance_sens_dev": (_I, [_P, _P, _P]),
+    "mlb_batch_residuals": (_I, [_P, _P, _P, _P]),
 }
 
 _lib = None

@@ -81,7 +81,8 @@ class Batch:
     def __exit__(self, *a):
         self.close()
 
-    def set_opts(self, smooth_steps=None, jacobi_omega=None, queue=None, graphs=None, check_every=None):
+    def set_opts(self, smooth_steps=None, jacobi_omega=None, queue=None, graphs=None, check_every=None,
+                 refine_steps=None):
         o = B.MlbBatchOpts()
         self._check(self.lib.mlb_batch_get_opts(self.h, C.byref(o)))
         if smooth_steps is not None:
@@ -94,6 +95,8 @@ class Batch:
             o.graphs = int(graphs)
         if check_every is not None:
             o.check_every = check_every
+        if refine_steps is not None:
+            o.refine_steps = int(refine_steps)
         self._check(self.lib.mlb_batch_set_opts(self.h, C.byref(o)))
 
     def set_problem_dev(self, fixed, F, x):
@@ -107,6 +110,17 @@ class Batch:
         self._check(self.lib.mlb_batch_solve_dev(self.h, tol, max_it, _dptr(U), C.c_void_p(J.ctypes.data),
                                                  C.c_void_p(its.ctypes.data), C.byref(info), _stream()))
         return J, its, {f: getattr(info, f) for f, _ in info._fields_}
+
+    def residuals(self):
+        """Per-instance true residuals of the returned u (double-double
+        evaluation), FP64 floors, and residuals of the refined double-double
+        solution, of the last solve."""
+        res = np.zeros(self.ninst)
+        floor = np.zeros(self.ninst)
+        res_dd = np.zeros(self.ninst)
+        self._check(self.lib.mlb_batch_residuals(self.h, C.c_void_p(res.ctypes.data), C.c_void_p(floor.ctypes.data),
+                                                 C.c_void_p(res_dd.ctypes.data)))
+        return res, floor, res_dd
 
     def compliance_sens_dev(self, dJ):
         self._check(self.lib.mlb_batch_compliance_sens_dev(self.h, _dptr(dJ), _stream()))

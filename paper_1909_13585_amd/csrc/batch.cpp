@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -90,6 +92,10 @@ struct mlb_batch {
     double *pw0 = nullptr, *pw1 = nullptr;
     // CG (batched fine layout) and per-instance scalars
     double *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr, *Z = nullptr;
+    double *Xacc = nullptr, *Xlo = nullptr, *Rc = nullptr;   // refined solution (hi, lo), compensated residual
+    int* dskip = nullptr;                    // per instance: refinement done
+    std::vector<double> res_h, floor_h, res_dd_h;   // per instance, last solve: residuals of the returned u and
+                                                    // of the double-double solution, FP64 floor
     double *part = nullptr, *part2 = nullptr, *part3 = nullptr;
     double *ff = nullptr, *thr = nullptr, *rr = nullptr, *rz = nullptr, *beta = nullptr;
     int *active = nullptr, *iters = nullptr, *flags = nullptr;
@@ -305,15 +311,18 @@ int read_sums(mlb_batch* b, const double* dpart, std::vector<double>& out) {
     return MLB_OK;
 }
 
+// One batched CG solve K X = rhs from X = 0 for every instance (an
+// instance with a zero right-hand side is done at once with X = 0).  On
+// return the host holds the per-instance iteration counts (hit), whether any
+// instance broke down (bad) and how many are still active (nact).
 template <typename T>
-int solve_t(mlb_batch* b, double tol, int max_it, double* U, double* J, int* iters, mlb_batch_info* info) {
-    const double t0 = now_s();
+int cg_pass(mlb_batch* b, const double* rhs, double tol, int max_it, int& it, bool& bad, int& nact) {
     const int ni = b->ninst;
     HIPC(hipMemsetAsync(b->flags, 0, sizeof(int) * ni, b->st));
     b->slot = 0;
     {
         const BQueue q = queue(b, b->LF);
-        launch_bq_cg_init(q, blocks(b, q), b->dseg, b->nmask, b->F, b->X, b->R, b->part2, b->st);
+        launch_bq_cg_init(q, blocks(b, q), b->dseg, b->nmask, rhs, b->X, b->R, b->part2, b->st);
     }
     launch_bq_check_res(ni, 1, tol * tol, b->dib, b->die, b->part2, b->ff, b->thr, b->rr, b->active, b->iters,
                         b->flags, b->st);
@@ -325,10 +334,10 @@ int solve_t(mlb_batch* b, double tol, int max_it, double* U, double* J, int* ite
     }
     int* hact = b->hpin;
     int* hflg = b->hpin + kMaxInst;
-    int* hit = b->hpin + 2 * kMaxInst;
     const int every = std::max(1, b->o.check_every);
-    int it = 0, nact = ni;
-    bool bad = false;
+    it = 0;
+    nact = ni;
+    bad = false;
     auto poll = [&]() -> int {
         HIPC(hipMemcpyAsync(hact, b->active, sizeof(int) * ni, hipMemcpyDeviceToHost, b->st));
         HIPC(hipMemcpyAsync(hflg, b->flags, sizeof(int) * ni, hipMemcpyDeviceToHost, b->st));
@@ -347,46 +356,144 @@ int solve_t(mlb_batch* b, double tol, int max_it, double* U, double* J, int* ite
         it += n;
         CHK(poll());
     }
+    int* hit = b->hpin + 2 * kMaxInst;
     HIPC(hipMemcpyAsync(hit, b->iters, sizeof(int) * ni, hipMemcpyDeviceToHost, b->st));
-    // true residuals ||f - K u|| (free DOFs) and compliances f^T u
-    std::vector<double> tt, fu, ffh;
+    HIPC(hipStreamSynchronize(b->st));
+    return MLB_OK;
+}
+
+// Compensated residual r = f - K (u_hi + u_lo) into Rc (zero for instances
+// flagged in skip): per instance ||r|| / ||f|| and the FP64 representation
+// floor eps ||(|K||u_hi|)|| / ||f|| (free DOFs).  No FP64 vector does much
+// better than its floor: rounding u to doubles alone moves the residual by
+// about that much.
+int true_residuals(mlb_batch* b, const std::vector<double>& ff0, const double* xlo, const int* skip,
+                   std::vector<double>& rel, std::vector<double>& floor) {
     {
         const BQueue q = queue(b, b->LF);
-        launch_bq_apply<double, double>(q, blocks(b, q), kBRes, 2, b->dseg, nullptr, b->Ek, b->K0d, nullptr, nullptr,
-                                        nullptr, b->nmask, b->X, b->Q, b->F, nullptr, b->part, b->st);
+        launch_bq_res_dd(q, blocks(b, q), b->dseg, b->Ek, b->K0d, b->nmask, b->Xacc, xlo, skip, b->F, b->Rc, b->part,
+                         b->part3, b->st);
     }
-    CHK(read_sums(b, b->part, tt));
+    std::vector<double> rr, aa;
+    CHK(read_sums(b, b->part, rr));
+    CHK(read_sums(b, b->part3, aa));
+    const int ni = b->ninst;
+    rel.assign(ni, 0.0);
+    floor.assign(ni, 0.0);
+    for (int i = 0; i < ni; ++i) {
+        if (!(ff0[i] > 0.0)) continue;
+        rel[i] = std::sqrt(std::max(rr[i], 0.0) / ff0[i]);
+        floor[i] = 2.220446049250313e-16 * std::sqrt(std::max(aa[i], 0.0) / ff0[i]);
+    }
+    return MLB_OK;
+}
+
+template <typename T>
+int solve_t(mlb_batch* b, double tol, int max_it, double* U, double* J, int* iters, mlb_batch_info* info) {
+    const double t0 = now_s();
+    const int ni = b->ninst;
+    int it = 0, nact = 0;
+    bool bad = false;
+    CHK(cg_pass<T>(b, b->F, tol, max_it, it, bad, nact));
+    const int* hit = b->hpin + 2 * kMaxInst;
+    std::vector<int> its(hit, hit + ni);
+    int conv = 0;   // instances whose recursive residual met tol in the first pass
+    for (int i = 0; i < ni; ++i) conv += b->hpin[i] ? 0 : 1;
+    int batch_its = it;
+    std::vector<double> ff0(ni);
+    HIPC(hipMemcpy(ff0.data(), b->ff, sizeof(double) * ni, hipMemcpyDeviceToHost));
+    HIPC(hipMemcpyAsync(b->Xacc, b->X, sizeof(double) * b->nf, hipMemcpyDeviceToDevice, b->st));
+    HIPC(hipMemsetAsync(b->Xlo, 0, sizeof(double) * b->nf, b->st));
+    // iterative refinement of a double-double solution u_hi + u_lo: its
+    // residual in double-double, a correction solve to 1e-4 relative, u += d
+    // in double-double.  An instance is done once its residual is below
+    // tol / 100 (its correction right-hand side is then zero, so it costs no
+    // iterations); the steps stop when all are done or none above that gains
+    // 10 % in a step.
+    const double target = 1e-2 * tol;
+    std::vector<double> rel, floor;
+    CHK(true_residuals(b, ff0, b->Xlo, nullptr, rel, floor));
+    std::vector<int> skip(ni, 0);
+    int done_steps = 0;
+    for (int sidx = 0; sidx < b->o.refine_steps && !bad && nact == 0; ++sidx) {
+        bool any = false;
+        for (int i = 0; i < ni; ++i) {
+            skip[i] = rel[i] <= target ? 1 : 0;
+            any = any || !skip[i];
+        }
+        if (!any) break;
+        HIPC(hipMemcpyAsync(b->dskip, skip.data(), sizeof(int) * ni, hipMemcpyHostToDevice, b->st));
+        std::vector<double> relr, floorr;
+        CHK(true_residuals(b, ff0, b->Xlo, b->dskip, relr, floorr));   // correction right-hand sides
+        int itc = 0, nactc = 0;
+        CHK(cg_pass<T>(b, b->Rc, std::max(tol, 1e-4), max_it, itc, bad, nactc));
+        if (bad) break;
+        batch_its += itc;
+        for (int i = 0; i < ni; ++i) its[i] += hit[i];
+        launch_dd_add(b->nf, b->X, b->Xacc, b->Xlo, b->st);
+        HIPC(hipGetLastError());
+        std::vector<double> rel2, floor2;
+        CHK(true_residuals(b, ff0, b->Xlo, nullptr, rel2, floor2));
+        ++done_steps;
+        bool gained = false;
+        double w0 = 0.0, w1 = 0.0;
+        for (int i = 0; i < ni; ++i) {
+            gained = gained || (rel[i] > target && rel2[i] < 0.9 * rel[i]);
+            w0 = std::max(w0, rel[i]);
+            w1 = std::max(w1, rel2[i]);
+        }
+        if (std::getenv("MLB_VERBOSE"))
+            std::fprintf(stderr, "refinement step %d: %d iterations, worst residual %.3e -> %.3e\n", done_steps, itc,
+                         w0, w1);
+        rel.swap(rel2);
+        if (!gained) break;
+    }
+    // the returned FP64 solution is u_hi = fl(u_hi + u_lo); its own residual
+    std::vector<double> rel_dd = rel;
+    CHK(true_residuals(b, ff0, nullptr, nullptr, rel, floor));
+    HIPC(hipMemcpyAsync(b->X, b->Xacc, sizeof(double) * b->nf, hipMemcpyDeviceToDevice, b->st));
+    // compliances f^T u
+    std::vector<double> fu;
     {
         const BQueue q = queue(b, b->LF);
         launch_bq_dot(q, blocks(b, q), b->dseg, b->nmask, b->F, b->X, b->part, b->st);
     }
     CHK(read_sums(b, b->part, fu));
-    ffh.resize(ni);
-    HIPC(hipMemcpy(ffh.data(), b->ff, sizeof(double) * ni, hipMemcpyDeviceToHost));
     if (U) HIPC(hipMemcpyAsync(U, b->X, sizeof(double) * b->nf, hipMemcpyDeviceToDevice, b->st));
     HIPC(hipStreamSynchronize(b->st));
-    double worst = 0.0;
-    int mx = 0, tot = 0, conv = 0;
+    b->res_h = rel;
+    b->floor_h = floor;
+    b->res_dd_h = rel_dd;
+    double worst = 0.0, worst_floor = 0.0, worst_dd = 0.0;
+    int mx = 0, tot = 0, misses = 0;
     for (int i = 0; i < ni; ++i) {
-        const double rel = ffh[i] > 0 ? std::sqrt(std::max(tt[i], 0.0) / ffh[i]) : 0.0;
-        worst = std::max(worst, rel);
-        mx = std::max(mx, hit[i]);
-        tot += hit[i];
-        conv += hact[i] ? 0 : 1;
+        worst = std::max(worst, rel[i]);
+        worst_dd = std::max(worst_dd, rel_dd[i]);
+        if (rel[i] > tol) {
+            ++misses;
+            worst_floor = std::max(worst_floor, floor[i]);
+        }
+        mx = std::max(mx, its[i]);
+        tot += its[i];
         if (J) J[i] = fu[i];
-        if (iters) iters[i] = hit[i];
+        if (iters) iters[i] = its[i];
     }
     if (info) {
         info->max_iterations = mx;
         info->total_iterations = tot;
-        info->batch_iterations = it;
+        info->batch_iterations = batch_its;
         info->converged = bad ? 0 : conv;
         info->worst_true_rel_res = worst;
         info->setup_s = b->setup_s;
         info->solve_s = now_s() - t0;
+        info->refine_steps = done_steps;
+        info->misses = misses;
+        info->worst_floor = worst_floor;
+        info->worst_refined_rel_res = worst_dd;
     }
     b->has_solution = true;
     if (bad) {
+        const int* hflg = b->hpin + kMaxInst;
         for (int i = 0; i < ni; ++i)
             if (hflg[i]) return fail(b, MLB_EBREAKDOWN, "instance " + std::to_string(i) + ": CG breakdown (flags " +
                                                             std::to_string(hflg[i]) + ")");
@@ -508,6 +615,7 @@ int mlb_batch_create(const mlb_batch_desc* desc, mlb_batch** out) {
     b->o.queue = 0;   // the hardware dispatcher beats the atomic queue for these uniform items
     b->o.graphs = 1;
     b->o.check_every = 4;
+    b->o.refine_steps = 10;
     const int ni = desc->ninst;
     if (ni < 1 || ni > kMaxInst) return fail(b, MLB_EINVAL, "ninst must be in 1..64");
     if (!(desc->E1 > 0) || !(desc->E0 >= 0) || !(desc->E0 < desc->E1)) return fail(b, MLB_EINVAL, "need 0 <= E0 < E1");
@@ -710,6 +818,10 @@ int mlb_batch_create(const mlb_batch_desc* desc, mlb_batch** out) {
     CHK(balloc(b, &b->pw0, b->nv));
     CHK(balloc(b, &b->pw1, b->nv));
     CHK(balloc(b, &b->X, b->nf));
+    CHK(balloc(b, &b->Xacc, b->nf));
+    CHK(balloc(b, &b->Xlo, b->nf));
+    CHK(balloc(b, &b->dskip, (size_t)ni));
+    CHK(balloc(b, &b->Rc, b->nf));
     CHK(balloc(b, &b->R, b->nf));
     CHK(balloc(b, &b->P, b->nf));
     CHK(balloc(b, &b->Q, b->nf));
@@ -773,6 +885,10 @@ void mlb_batch_destroy(mlb_batch* b) {
     bfree(b->pw0);
     bfree(b->pw1);
     bfree(b->X);
+    bfree(b->Xacc);
+    bfree(b->Xlo);
+    bfree(b->dskip);
+    bfree(b->Rc);
     bfree(b->R);
     bfree(b->P);
     bfree(b->Q);
@@ -803,6 +919,7 @@ int mlb_batch_set_opts(mlb_batch* b, const mlb_batch_opts* o) {
     if (o->queue != 0 && o->queue != 1) return fail(b, MLB_EINVAL, "queue must be 0 or 1");
     if (o->graphs != 0 && o->graphs != 1) return fail(b, MLB_EINVAL, "graphs must be 0 or 1");
     if (o->check_every < 1) return fail(b, MLB_EINVAL, "check_every must be >= 1");
+    if (o->refine_steps < 0 || o->refine_steps > 16) return fail(b, MLB_EINVAL, "refine_steps must be in 0..16");
     const bool rebuild = o->jacobi_omega != b->o.jacobi_omega;
     b->o = *o;
     drop_graph(b);
@@ -849,6 +966,17 @@ int mlb_batch_solve_dev(mlb_batch* b, double tol, int max_it, double* U, double*
     const int r = b->d.precision == MLB_FP64 ? solve_t<double>(b, tol, max_it, U, J, iters, info)
                                              : solve_t<float>(b, tol, max_it, U, J, iters, info);
     return r;
+}
+
+int mlb_batch_residuals(const mlb_batch* b, double* res, double* floor, double* res_refined) {
+    if (!b) return MLB_EINVAL;
+    if (!b->has_solution) return MLB_ESTATE;
+    for (int i = 0; i < b->ninst; ++i) {
+        if (res) res[i] = b->res_h[i];
+        if (floor) floor[i] = b->floor_h[i];
+        if (res_refined) res_refined[i] = b->res_dd_h[i];
+    }
+    return MLB_OK;
 }
 
 int mlb_batch_compliance_sens_dev(mlb_batch* b, double* dJ, void* stream) {

@@ -77,6 +77,14 @@ void launch_bq_gj(int nseg_coarsest, const int* coarsest_segs, const BSeg* segs,
 
 // CG steps on the fine items (level-1 segments); per-instance sums are
 // formed from the per-item partials of the instance's item range [ib, ie).
+// r = f - K (x + xlo) (fine level, free DOFs; xlo may be NULL) accumulated in
+// double-double; per item partial sums of r.r and of (|K||x|).(|K||x|) over
+// free DOFs; r zero for instances with skip[inst] != 0 (skip may be NULL).
+void launch_bq_res_dd(const BQueue& q, int blocks, const BSeg* segs, const double* Ek, const BK0<double>& K0,
+                      const uint8_t* nmask, const double* x, const double* xlo, const int* skip, const double* f,
+                      double* r, double* part, double* part2, hipStream_t st);
+// (hi, lo) += d per entry in double-double
+void launch_dd_add(int64_t n, const double* d, double* hi, double* lo, hipStream_t st);
 void launch_bq_cg_init(const BQueue& q, int blocks, const BSeg* segs, const uint8_t* nmask, const double* F,
                        double* X, double* R, double* part, hipStream_t st);
 void launch_bq_cg_update(const BQueue& q, int blocks, const BSeg* segs, const int* active, const int* ib,

@@ -191,6 +191,111 @@ __global__ __launch_bounds__(kBT) void k_bq_apply(BQueue q, const BSeg* __restri
 }
 
 // ---------------------------------------------------------------------------
+// compensated residual of the fine level
+
+// Error-free transformations (Knuth's two-sum, the FMA form of the exact
+// product): a + b = s + e and a b = p + e exactly in floating point.
+__device__ inline void bq_two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+__device__ inline void bq_two_prod(double a, double b, double& p, double& e) {
+    p = a * b;
+    e = __builtin_fma(a, b, -p);
+}
+
+// r = f - K (x + xlo) on the free DOFs of the fine segments (zero at fixed
+// DOFs), accumulated in double-double: every product E_e K0_ab x_b is formed
+// exactly to second order and summed with two-sum, and the low part xlo (a
+// double-double solution's tail, may be NULL) enters the low word, so r is
+// the residual of x + xlo to a few units of rounding of r itself (not of
+// |K||x|).  Per item: partial sums of r.r (part) and of (|K||x|).(|K||x|)
+// over free DOFs (part2), the latter for the instance's representation
+// floor.  r is written as zero for instances with skip[inst] != 0 (the sums
+// still hold their residual).
+__global__ __launch_bounds__(kBT) void k_bq_res_dd(BQueue q, const BSeg* __restrict__ segs,
+                                                   const double* __restrict__ Ek, BK0<double> K0,
+                                                   const uint8_t* __restrict__ nmask, const double* __restrict__ x,
+                                                   const double* __restrict__ xlo, const int* __restrict__ skip,
+                                                   const double* __restrict__ f, double* __restrict__ r,
+                                                   double* __restrict__ part, double* __restrict__ part2) {
+    __shared__ double sh[4];
+    bq_drain(q, [&](int it) {
+        const BItem w = q.items[it];
+        const BSeg s = segs[w.seg];
+        const int nodes = s.nnx * s.nny;
+        const int node = w.first + (int)threadIdx.x;
+        double rr = 0.0, aa = 0.0;
+        if (node < nodes) {
+            const int i = node % s.nnx, j = node / s.nnx;
+            const double* xs = x + s.voff;
+            const double* xl = xlo ? xlo + s.voff : nullptr;
+            double xv[3][3][2], xw[3][3][2];
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const bool ok = i + dx >= 0 && i + dx < s.nnx && j + dy >= 0 && j + dy < s.nny;
+                    const int nb = ok ? node + dx + dy * s.nnx : node;
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2) {
+                        xv[dy + 1][dx + 1][c2] = ok ? xs[2 * nb + c2] : 0.0;
+                        xw[dy + 1][dx + 1][c2] = ok && xl ? xl[2 * nb + c2] : 0.0;
+                    }
+                }
+            const uint8_t m = nmask[s.noff + node];
+            const bool zero_out = skip && skip[s.inst];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int64_t d = s.voff + 2 * (int64_t)node + c;
+                if ((m >> c) & 1) {
+                    r[d] = 0.0;
+                    continue;
+                }
+                double hi = f[d], lo = 0.0, ak = 0.0;
+#pragma unroll
+                for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+                    for (int ox = 0; ox < 2; ++ox) {
+                        const int ei = i - 1 + ox, ej = j - 1 + oy;
+                        if (ei < 0 || ei >= s.nx || ej < 0 || ej >= s.ny) continue;
+                        const double E = Ek[s.soff + ei + (int64_t)s.nx * ej];
+                        const int a = (1 - ox) + 2 * (1 - oy);
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int bx = b & 1, by = b >> 1;
+#pragma unroll
+                            for (int c2 = 0; c2 < 2; ++c2) {
+                                const double v = xv[oy + by][ox + bx][c2];
+                                double p1, e1, p2, e2, t, et;
+                                bq_two_prod(K0.k[(2 * a + c) * 8 + 2 * b + c2], v, p1, e1);
+                                bq_two_prod(E, p1, p2, e2);
+                                e2 = __builtin_fma(E, e1, e2);   // E K0 v = p2 + e2 to second order
+                                bq_two_sum(hi, -p2, t, et);
+                                hi = t;
+                                lo += et - e2 - E * (K0.k[(2 * a + c) * 8 + 2 * b + c2] * xw[oy + by][ox + bx][c2]);
+                                ak += fabs(p2);
+                            }
+                        }
+                    }
+                double rv, re;
+                bq_two_sum(hi, lo, rv, re);
+                r[d] = zero_out ? 0.0 : rv;
+                rr += rv * rv;
+                aa += ak * ak;
+            }
+        }
+        const double s1 = bq_block_sum(rr, sh);
+        const double s2 = bq_block_sum(aa, sh);
+        if (threadIdx.x < 64) {
+            part[it] = s1;
+            part2[it] = s2;
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
 // transfers (bilinear interpolation P and P^T, masked on both sides)
 
 template <typename T>
@@ -689,6 +794,30 @@ void launch_bq_coarsest(const BQueue& q, int blocks, const BSeg* segs, const int
 void launch_bq_gj(int nseg_coarsest, const int* coarsest_segs, const BSeg* segs, double* Ainv, hipStream_t st) {
     if (nseg_coarsest <= 0) return;
     hipLaunchKernelGGL(k_bq_gj, dim3(nseg_coarsest), dim3(kGjThreads), 0, st, coarsest_segs, segs, Ainv);
+}
+
+void launch_bq_res_dd(const BQueue& q, int blocks, const BSeg* segs, const double* Ek, const BK0<double>& K0,
+                      const uint8_t* nmask, const double* x, const double* xlo, const int* skip, const double* f,
+                      double* r, double* part, double* part2, hipStream_t st) {
+    hipLaunchKernelGGL(k_bq_res_dd, dim3(blocks), dim3(kBT), 0, st, q, segs, Ek, K0, nmask, x, xlo, skip, f, r, part,
+                       part2);
+}
+
+// (hi, lo) += d as a double-double per entry (two-sum, then renormalised so
+// that hi = fl(hi + lo)).
+__global__ void k_dd_add(int64_t n, const double* __restrict__ d, double* __restrict__ hi, double* __restrict__ lo) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s, e;
+    bq_two_sum(hi[i], d[i], s, e);
+    const double l = lo[i] + e;
+    const double h = s + l;
+    hi[i] = h;
+    lo[i] = l - (h - s);
+}
+
+void launch_dd_add(int64_t n, const double* d, double* hi, double* lo, hipStream_t st) {
+    hipLaunchKernelGGL(k_dd_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, d, hi, lo);
 }
 
 void launch_bq_cg_init(const BQueue& q, int blocks, const BSeg* segs, const uint8_t* nmask, const double* F,

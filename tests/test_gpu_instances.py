@@ -58,46 +58,54 @@ def _run(torch, mlb_batch, insts, precision, tol=1e-10, max_it=2000, **opts):
     b.compliance_sens_dev(dJ)
     torch.cuda.synchronize()
     _step("done")
+    res, floor, res_dd = b.residuals()
     out = dict(U=b.split_dofs(U.cpu().numpy()), dJ=b.split_elems(dJ.cpu().numpy()), J=J, its=its, info=info,
-               levels=b.levels.copy())
+               levels=b.levels.copy(), res=res, floor=floor, res_dd=res_dd)
     b.close()
     return out
 
 
 def _check_against_oracle(insts, r, tol, e_tol, verbose=False):
-    """Per instance, against the oracle's own direct solve of that instance:
-    true residual within tol or the instance's FP64 floor; relative error in
-    the energy norm (well posed even for nearly singular designs, where the
-    max-norm error of u reflects the conditioning, not the solver); the
-    compliance; the gradient against the closed form with the batch's u
-    (per-element rounding bound) and with the oracle's u (1e-5 of the largest
-    entry)."""
+    """Per instance, against the oracle's own solve of that instance (direct
+    solve refined with an extended-precision residual, which brings nearly
+    singular designs to the accuracy a double-precision u can have):
+      * the true residual of the batch's u, evaluated in extended precision,
+        within tol, or within the instance's FP64 floor eps ||(|K||u|)||/||f||
+        where that floor lies above tol (rounding u to doubles alone moves the
+        residual by about that much, so no FP64 u does better); such
+        instances are reported as misses with their floors;
+      * the library's own double-double residual and floor equal the
+        oracle's evaluation, and the refined (double-double) solution that
+        the returned u rounds meets tol;
+      * relative error in the energy norm; the compliance;
+      * the gradient against the closed form with the batch's u (per-element
+        rounding bound) and against the oracle's u within 1e-5 of the largest
+        entry for every instance whose refined solution met tol.
+    Instances whose refined solution stays above tol are printed by name
+    with their residuals, floors and gradient errors; they must have a floor
+    above 10 tol and are held to 1e-4."""
     mat = fem.Material()
     Ka = np.abs(fem.element_stiffness(2, mat.nu))
-    rows, failures = [], []
+    rows, failures, misses = [], [], []
     for i, p in enumerate(insts):
         nel, x, f = p["nel"], p["x"], p["F"][:, 0]
         free = p["fixed"] == 0
+        fz = f * free
         u = r["U"][i]
-        K = fem.assemble_K(nel, x, mat)
-        Uo, Jo, _ = lba.static_solve(K, f, p["fixed"])
-        uo = Uo[:, 0]
-        res = f * free - fem.apply_K_matfree(nel, x, u, mat)
-        res[~free] = 0.0
-        rel = np.linalg.norm(res) / np.linalg.norm(f[free])
-        Ek, _ = fem.moduli(x, mat)
-        ed = fem.element_dofs(nel)
-        aK = np.bincount(ed.ravel(), weights=(Ek[:, None] * (np.abs(u)[ed] @ Ka.T)).ravel(), minlength=u.size)
-        floor = 4 * EPS * np.linalg.norm(aK[free]) / np.linalg.norm(f[free])
+        uo, Jo, hist = lba.static_solve_refined(nel, x, p["F"], p["fixed"], mat)
+        res, absK = fem.residual_extended(nel, x, u, fz, p["fixed"], mat)
+        rel = np.linalg.norm(res) / np.linalg.norm(fz)
+        floor = EPS * np.linalg.norm(absK) / np.linalg.norm(fz)
         d = u - uo
         Kd = fem.apply_K_matfree(nel, x, d, mat)
-        e_rel = np.sqrt(max(float(d[free] @ Kd[free]), 0.0) / Jo[0])
-        j_rel = abs(r["J"][i] / Jo[0] - 1)
+        e_rel = np.sqrt(max(float(d[free] @ Kd[free]), 0.0) / Jo)
+        j_rel = abs(r["J"][i] / Jo - 1)
         g_own = sens.compliance_sensitivity(nel, x, u, mat)[:, 0]
         # two summation orders of u_e^T K0 u_e differ by at most
         # 2 gamma_16 |u_e|^T |K0| |u_e| per element (Higham, Sec. 3.1); nearly
         # rigid element motions of large amplitude make that far exceed eps of
         # the value itself
+        ed = fem.element_dofs(nel)
         ue = np.abs(u)[ed]
         dEa = mat.p * np.power(x, mat.p - 1.0) * (mat.E1 - mat.E0)
         bound = 2 * 16 * EPS * dEa * np.einsum("ei,ij,ej->e", ue, Ka, ue) + 1e-300
@@ -105,10 +113,26 @@ def _check_against_oracle(insts, r, tol, e_tol, verbose=False):
         s_rel = np.abs(r["dJ"][i] - g_orc).max() / np.abs(g_orc).max()
         rows.append((i, nel, int(r["its"][i]), rel, floor, e_rel, j_rel, s_rel))
         if verbose:
-            print(f"instance {i} {nel}: {r['its'][i]} it, true res {rel:.2e} (floor {floor:.2e}), energy err "
-                  f"{e_rel:.2e}, J err {j_rel:.2e}, dJ err {s_rel:.2e}, |u|max {np.abs(uo).max():.2e}")
+            print(f"instance {i} {nel}: {r['its'][i]} it, true res {rel:.2e} (library {r['res'][i]:.2e}, refined "
+                  f"{r['res_dd'][i]:.2e}, floor "
+                  f"{floor:.2e}, oracle refined {hist[-1]:.2e}), energy err {e_rel:.2e}, J err {j_rel:.2e}, "
+                  f"dJ err {s_rel:.2e}, |u|max {np.abs(uo).max():.2e}")
+        refined_ok = r["res_dd"][i] <= tol
+        if rel > tol or not refined_ok:
+            misses.append((i, nel, rel, r["res_dd"][i], floor, s_rel))
+        # the refined (double-double) solution meets tol, except where the
+        # FP64 floor lies far above it: there the correction solves (FP64 CG)
+        # stall at about a tenth of the floor
+        if not (refined_ok or (floor > 10 * tol and r["res_dd"][i] <= 0.2 * floor)):
+            failures.append((i, "refined residual", r["res_dd"][i], floor))
         if not rel <= max(tol, floor):
             failures.append((i, "residual", rel, floor))
+        # the oracle's extended evaluation errs by about 2^-12 of the FP64
+        # floor (times a few terms); the library's double-double one less
+        if not abs(r["res"][i] - rel) <= 0.02 * rel + 0.05 * floor:
+            failures.append((i, "library residual", r["res"][i], rel))
+        if not abs(r["floor"][i] / floor - 1) <= 1e-12:
+            failures.append((i, "library floor", r["floor"][i], floor))
         if not np.all(u[~free] == 0.0):
             failures.append((i, "fixed DOFs not zero"))
         if not e_rel <= e_tol:
@@ -117,10 +141,15 @@ def _check_against_oracle(insts, r, tol, e_tol, verbose=False):
             failures.append((i, "compliance", j_rel, floor))
         if not np.all(np.abs(r["dJ"][i] - g_own) <= bound):
             failures.append((i, "dJ formula", float(np.max(np.abs(r["dJ"][i] - g_own) / bound))))
-        # where the instance's FP64 floor exceeds the solve tolerance (nearly
-        # singular designs), no solution agrees better than a multiple of it
-        if not s_rel <= max(1e-5, 10 * floor):
+        # sensitivities: 1e-5 of the largest entry wherever the refined
+        # solution met tol; the named misses (refined residual above tol,
+        # floor above 10 tol) are held to 1e-4
+        if not s_rel <= (1e-5 if refined_ok else 1e-4):
             failures.append((i, "dJ vs oracle", s_rel, floor))
+    if misses:
+        print("instances above tol:", ", ".join(
+            f"{i} {nel}: returned {rel:.1e}, refined {rd:.1e} (floor {fl:.1e}), dJ err {se:.1e}"
+            for i, nel, rel, rd, fl, se in misses))
     assert not failures, failures
     return rows
 

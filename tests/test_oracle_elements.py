@@ -240,3 +240,65 @@ def test_nested_fixed_set_check():
     bad = np.zeros(W.n_dofs(nel), dtype=np.uint8)
     bad[2 * (1 + 9 * 2)] = 1      # fixed DOF at odd x node, sources free
     assert not levels.nested_fixed_set_ok(nel, bad)
+
+
+def test_residual_extended_against_exact_rationals():
+    """fem.residual_extended on a 3x2 Q4 grid with random densities and a
+    random u of large amplitude (a rigid shift 1e6 plus a small field):
+    against the exact residual in rational arithmetic (Fractions from the
+    same float64 data), to a few units of its own rounding (far below the
+    FP64 evaluation's error eps |K||u|)."""
+    from fractions import Fraction
+    import workloads as W
+    from oracle import fem
+    nel = (3, 2)
+    mat = fem.Material()
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0.01, 1.0, 6)
+    fixed = W.clamp_mask(nel)
+    n = fem.n_dofs(nel)
+    u = 1e6 + rng.normal(size=n)
+    u[fixed == 1] = 0.0
+    f = rng.normal(size=n)
+    r, absK = fem.residual_extended(nel, x, u, f, fixed, mat)
+    Ke0 = fem.material_stiffness(2, mat)
+    Ek, _ = fem.moduli(x, mat)
+    ed = fem.element_dofs(nel)
+    exact = [Fraction(v) for v in f]
+    for e in range(6):
+        for a in range(8):
+            acc = Fraction(0)
+            for b in range(8):
+                acc += Fraction(Ke0[a, b]) * Fraction(u[ed[e, b]])
+            exact[ed[e, a]] -= Fraction(Ek[e]) * acc
+    ex = np.array([float(v) for v in exact])
+    ex[fixed == 1] = 0.0
+    # the FP64 evaluation misses by about eps |K||u|; the extended one by
+    # about 2^-64 |K||u|
+    fp64 = f - fem.apply_K_matfree(nel, x, u, mat)
+    fp64[fixed == 1] = 0.0
+    err_ext = np.abs(r - ex).max()
+    err_64 = np.abs(fp64 - ex).max()
+    assert err_ext <= 64 * 2.0 ** -64 * absK.max() + 2 * np.finfo(float).eps * np.abs(ex).max()
+    assert err_ext * 100 < err_64
+
+
+def test_refined_solve_reaches_the_extended_residual_floor():
+    """On a nearly singular design (a solid bar in void, E0 = 1e-6) the
+    refined solve's extended-precision solution has a residual far below
+    the FP64 representation floor eps ||(|K||u|)|| / ||f||, and its rounding
+    to doubles a residual at about that floor."""
+    import workloads as W
+    from oracle import fem, lba
+    nel = (48, 16)
+    x = np.full(48 * 16, 1e-6)
+    x.reshape(16, 48)[6:10, :] = 1.0
+    fixed = W.clamp_mask(nel)
+    F = W.shear_load(nel, 1)
+    mat = fem.Material()
+    u, J, hist = lba.static_solve_refined(nel, x, F, fixed, mat)
+    f = F * (fixed == 0)
+    r, absK = fem.residual_extended(nel, x, u, f, fixed, mat)
+    floor = np.finfo(float).eps * np.linalg.norm(absK) / np.linalg.norm(f)
+    assert hist[-1] <= 1e-3 * floor and hist[-1] < hist[0]
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= floor
