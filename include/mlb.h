@@ -127,7 +127,8 @@ typedef struct {
     double jacobi_omega;  /* damping factor times rho(D^-1 A); default 4/3 (omega = 4/(3 rho)) */
     int eig_guard;        /* extra vectors in the coarse eigensolver block (default max(4, k/2)) */
     int eig_max_it;       /* coarse eigensolver iteration limit (default 400) */
-    int check_every;      /* CG iterations between host convergence checks (default 1) */
+    int check_every;      /* CG iterations between host reads of the device convergence flags (default 8;
+                             results do not depend on it) */
     uint64_t seed;        /* seed of the coarse eigensolver start block (default 1) */
     int cycle;            /* coarse-grid visits per level: 1 = V-cycle, 2 = W-cycle (default 1) */
     int block_cg;         /* multi-column solves: 1 = block CG (default), 2 = column-wise CG */

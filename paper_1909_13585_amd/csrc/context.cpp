@@ -131,7 +131,7 @@ struct mlb_ctx {
     double* scal = nullptr;   // 16 blocks of kScal doubles
     double* gbuf = nullptr;   // summed Gram matrices (up to 96 x 192)
     double *cbuf = nullptr, *cbuf2 = nullptr;   // small coefficient matrices
-    int* iscal = nullptr;     // active / flags
+    int* iscal = nullptr;     // active / flags / iteration counts
     double* hpin = nullptr;   // pinned host staging (96 x 192 doubles)
     double* hup = nullptr;    // pinned staging of coefficient uploads (2 x 96 x 96)
     bool up_pending = false;  // an upload from hup may still be in flight
@@ -488,6 +488,8 @@ int pcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, 
     double* rzn = sc(c, 6);
     int* active = c->iscal;
     int* flags = c->iscal + kScal;
+    int* dits = c->iscal + 2 * kScal;
+    double* thr = sc(c, 7);
     const bool flex = c->d.precision == MLB_MIXED;
 
     dots(c, n, nc, B, B, bb);
@@ -502,15 +504,23 @@ int pcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, 
     CHK(read_scal(c, bb, nc, hb.data()));
     CHK(read_scal(c, rr, nc, hr.data()));
     std::vector<int> act(nc);
+    std::vector<double> hthr(nc);
     int nact = 0;
     for (int i = 0; i < nc; ++i) {
         if (!std::isfinite(hb[i]) || !std::isfinite(hr[i]))
             return fail(c, MLB_EINVAL, "non-finite right-hand side or initial guess");
         act[i] = hr[i] > tol * tol * hb[i] ? 1 : 0;
+        hthr[i] = tol * tol * hb[i];
         nact += act[i];
     }
+    // the convergence test runs on the device after every iteration; the
+    // host reads the flags every check_every iterations (iterations past a
+    // column's convergence leave it unchanged: alpha = 0)
     HIPC(hipMemcpyAsync(active, act.data(), sizeof(int) * nc, hipMemcpyHostToDevice, c->st));
+    HIPC(hipMemcpyAsync(thr, hthr.data(), sizeof(double) * nc, hipMemcpyHostToDevice, c->st));
     HIPC(hipMemsetAsync(flags, 0, sizeof(int) * nc, c->st));
+    HIPC(hipMemsetAsync(dits, 0, sizeof(int) * nc, c->st));
+    CHK(sync(c));   // act and hthr are host locals
     int it = 0;
     int status = MLB_OK;
     if (nact > 0) {
@@ -524,25 +534,30 @@ int pcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, 
             launch_cg_alpha(nc, rz, pq, active, alpha, flags, c->st);
             launch_cg_update_xr(n, nc, n, alpha, c->Pb, c->Qb, X, c->R, np, c->part, c->st);
             launch_sum_parts(nc, np, c->part, rr, c->st);
+            launch_cg_check(nc, rr, thr, active, dits, flags, c->st);
             if (it % every == 0 || it == max_it) {
                 CHK(read_scal(c, rr, nc, hr.data()));
-                int fl[kScal];
-                HIPC(hipMemcpyAsync(fl, flags, sizeof(int) * nc, hipMemcpyDeviceToHost, c->st));
+                int fl[3 * kScal];
+                HIPC(hipMemcpyAsync(fl, c->iscal, sizeof(int) * 3 * kScal, hipMemcpyDeviceToHost, c->st));
                 CHK(sync(c));
                 nact = 0;
                 for (int i = 0; i < nc; ++i) {
-                    if (fl[i]) return fail(c, MLB_EBREAKDOWN, "CG breakdown: p^T K p <= 0 or non-finite");
-                    if (!std::isfinite(hr[i])) return fail(c, MLB_EBREAKDOWN, "CG residual not finite");
-                    act[i] = act[i] && hr[i] > tol * tol * hb[i] ? 1 : 0;
-                    nact += act[i];
+                    if (fl[kScal + i] & 1) return fail(c, MLB_EBREAKDOWN, "CG breakdown: p^T K p <= 0 or non-finite");
+                    if (fl[kScal + i] & 2) return fail(c, MLB_EBREAKDOWN, "CG residual not finite");
+                    nact += fl[i] ? 1 : 0;
                 }
-                HIPC(hipMemcpyAsync(active, act.data(), sizeof(int) * nc, hipMemcpyHostToDevice, c->st));
                 if (std::getenv("MLB_VERBOSE") && (it % 10 == 0 || nact == 0)) {
                     double w = 0.0;
                     for (int i = 0; i < nc; ++i) w = std::max(w, hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0);
                     std::fprintf(stderr, "[mlb] pcg it %d worst rel %.3e active %d\n", it, w, nact);
                 }
-                if (nact == 0) break;
+                if (nact == 0) {
+                    // the iteration count: the largest over the columns
+                    int mx = 0;
+                    for (int i = 0; i < nc; ++i) mx = std::max(mx, fl[2 * kScal + i]);
+                    it = mx;
+                    break;
+                }
             }
             if (flex) dots(c, n, nc, c->R, c->Zb, sc(c, 8));   // r_{k+1} . z_k for the flexible beta
             CHK(precondition(c, 1, nc, c->R, c->Zb));
@@ -1600,7 +1615,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     c->o.jacobi_omega = 4.0 / 3.0;
     c->o.eig_guard = 0;
     c->o.eig_max_it = 400;
-    c->o.check_every = 1;
+    c->o.check_every = 8;
     c->o.seed = 1;
     c->o.cycle = 1;
     c->o.block_cg = 1;
@@ -1717,7 +1732,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     CHK(dalloc(c, &c->S, (size_t)c->m * c->nv));
     CHK(dalloc(c, &c->fixed, (size_t)c->n));
     CHK(dalloc(c, &c->scal, (size_t)16 * kScal));
-    CHK(dalloc(c, &c->iscal, (size_t)2 * kScal));
+    CHK(dalloc(c, &c->iscal, (size_t)3 * kScal));
     CHK(dalloc(c, &c->gbuf, (size_t)96 * 192));
     CHK(dalloc(c, &c->cbuf, (size_t)2 * 96 * 96));
     CHK(dalloc(c, &c->cbuf2, (size_t)96 * 96));

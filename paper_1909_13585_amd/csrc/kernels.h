@@ -85,6 +85,9 @@ int reduction_parts(int64_t n);
 void launch_dot_part(int64_t n, int ncols, int64_t lda, const double* a, int64_t ldb, const double* b,
                      int nparts, double* part, hipStream_t st);
 void launch_sum_parts(int ncols, int64_t nparts, const double* part, double* out, hipStream_t st);
+// device convergence test after a CG update (counts iterations of active columns)
+void launch_cg_check(int ncols, const double* rr, const double* thr, int* active, int* iters, int* flags,
+                     hipStream_t st);
 void launch_cg_alpha(int ncols, const double* rz, const double* pq, const int* active, double* alpha,
                      int* flags, hipStream_t st);
 void launch_cg_beta(int ncols, const double* rz_new, double* rz, const int* active, double* beta,

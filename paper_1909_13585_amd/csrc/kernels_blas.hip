@@ -98,6 +98,24 @@ __global__ void k_sum_parts(int64_t nparts, const double* __restrict__ part, dou
     if (threadIdx.x == 0) out[col] = s;
 }
 
+// Convergence test on the device after a CG update: an active column counts
+// the iteration, and stops at rr <= thr (or with flags |= 2 when rr is not
+// finite).  Inactive columns get alpha = 0 afterwards, so iterations run
+// past convergence leave their x and r bitwise unchanged.
+__global__ void k_cg_check(int ncols, const double* __restrict__ rr, const double* __restrict__ thr,
+                           int* __restrict__ active, int* __restrict__ iters, int* __restrict__ flags) {
+    const int c = threadIdx.x;
+    if (c >= ncols || !active[c]) return;
+    iters[c] += 1;
+    const double v = rr[c];
+    if (!(v == v) || v >= __builtin_huge_val()) {
+        flags[c] |= 2;
+        active[c] = 0;
+    } else if (v <= thr[c]) {
+        active[c] = 0;
+    }
+}
+
 // alpha = rz / pq per active column; flags[col] = 1 on breakdown (pq <= 0 / non-finite)
 __global__ void k_cg_alpha(int ncols, const double* __restrict__ rz, const double* __restrict__ pq,
                            const int* __restrict__ active, double* __restrict__ alpha, int* __restrict__ flags) {
@@ -640,6 +658,11 @@ void launch_sum_parts(int ncols, int64_t nparts, const double* part, double* out
 void launch_cg_alpha(int ncols, const double* rz, const double* pq, const int* active, double* alpha, int* flags,
                      hipStream_t st) {
     hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64 * ((ncols + 63) / 64)), 0, st, ncols, rz, pq, active, alpha, flags);
+}
+void launch_cg_check(int ncols, const double* rr, const double* thr, int* active, int* iters, int* flags,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64 * ((ncols + 63) / 64)), 0, st, ncols, rr, thr, active, iters,
+                       flags);
 }
 void launch_cg_beta(int ncols, const double* rz_new, double* rz, const int* active, double* beta, hipStream_t st) {
     hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64 * ((ncols + 63) / 64)), 0, st, ncols, rz_new, rz, active, beta);
