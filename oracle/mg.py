@@ -98,15 +98,20 @@ class VCycle:
         return z[:, 0] if vec else z
 
 
-def pinvit(Kff, Gff, Phi, lam, apply_P, steps):
+def pinvit(Kff, Gff, Phi, lam, apply_P, steps, shift="own"):
     """``steps`` preconditioned inverse iteration steps on the Ritz block Phi
     (free DOFs, columns paired with the Ritz values lam), each followed by
-    Rayleigh-Ritz.  Returns the final Ritz values and vectors and the Ritz
-    values before and after every step."""
+    Rayleigh-Ritz.  ``shift``: "own" shifts each vector by its Ritz value (the
+    gradient step of its Rayleigh quotient, the reading taken), "first" by
+    lambda~_1 for every vector (the step as printed).  Returns the final Ritz
+    values and vectors and the Ritz values before and after every step."""
+    if shift not in ("own", "first"):
+        raise ValueError("shift must be 'own' or 'first'")
     hist = [np.array(lam, dtype=np.float64)]
     q = Phi.shape[1]
     for _ in range(steps):
-        R = Kff @ Phi + (Gff @ Phi) * np.asarray(lam)[None, :]
+        sh = np.asarray(lam) if shift == "own" else np.full(q, lam[0])
+        R = Kff @ Phi + (Gff @ Phi) * sh[None, :]
         Phi = Phi - apply_P(R)
         lam, Phi = rayleigh_ritz(Kff, Gff, Phi)
         if len(lam) < q:

@@ -95,3 +95,30 @@ def test_vcycle_pinvit_is_monotone_and_bounded(case, request):
     assert np.all(h >= exact[None, :] * (1 - 1e-12)), (h, exact)
     assert np.all(lam >= exact * (1 - 1e-12)), (lam, exact)
     assert np.all(h[-1] - exact < 0.5 * (h[0] - exact)), (h, exact)
+
+
+@pytest.mark.parametrize("case", ["col2d", "box3d"])
+def test_printed_shift_variant(case, request):
+    """The printed step (every vector shifted by lambda~_1): the fundamental
+    Ritz value still never grows and stays above the exact one, every Ritz
+    value stays above its exact counterpart (Courant-Fischer), and on the
+    first step the two variants give the same fundamental value update only
+    if q = 1; with q > 1 the higher Ritz values move differently."""
+    p = request.getfixturevalue(case)
+    Kff, Gff = p["Kff"], p["Gff"]
+    b = p["r"]["buck"]
+    q = len(b.lam)
+    exact = lba.generalized_lowest_positive(Kff, Gff, q)[0]
+    V = mg.VCycle(p["As"], p["Ps"], p["omegas"], nu=2)
+    lam_f, _, hist_f = mg.pinvit(Kff, Gff, b.phi[p["free"]], b.lam, V, 3, shift="first")
+    lam_o, _, hist_o = mg.pinvit(Kff, Gff, b.phi[p["free"]], b.lam, V, 3, shift="own")
+    h = np.asarray(hist_f)
+    assert np.all(np.diff(h[:, 0]) <= 1e-12 * h[0, 0])
+    assert np.all(h >= exact[None, :] * (1 - 1e-12))
+    assert not np.allclose(lam_f[1:], lam_o[1:], rtol=1e-6)
+    # a single vector: both shifts are its own Ritz value
+    l1f, _, _ = mg.pinvit(Kff, Gff, b.phi[p["free"]][:, :1], b.lam[:1], V, 2, shift="first")
+    l1o, _, _ = mg.pinvit(Kff, Gff, b.phi[p["free"]][:, :1], b.lam[:1], V, 2, shift="own")
+    assert np.array_equal(l1f, l1o)
+    with pytest.raises(ValueError):
+        mg.pinvit(Kff, Gff, b.phi[p["free"]], b.lam, V, 1, shift="mean")
