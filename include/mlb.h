@@ -149,6 +149,9 @@ typedef struct {
                              default: the main text's method), 0 keeps the current value */
     int coarse_sweeps;    /* Jacobi sweeps before and after the coarse correction on levels >= 3,
                              where sweeps are cheap (> 0 sets it, at most 64; default: smooth_steps) */
+    int pinvit_shift;     /* shift of the inverse iteration steps: 1 = each Ritz vector's own Ritz value
+                             (the default: the gradient step of its Rayleigh quotient), 2 = lam~_1 for
+                             every vector (the step as printed in App. A); 0 keeps the current value */
 } mlb_opts;
 
 /* Per-call solver report; for blocks, the worst column is reported. */

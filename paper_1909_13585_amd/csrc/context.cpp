@@ -1342,7 +1342,8 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
     // PInvIt-GeneralInteration), each followed by Rayleigh-Ritz again:
     // phi_i <- phi_i - M^-1 (K + lam~_i G) phi_i, M^-1 one multigrid cycle,
     // each vector shifted by its own Ritz value (the gradient step of its
-    // Rayleigh quotient).  After each Ritz step Zo holds the Ritz vectors,
+    // Rayleigh quotient), or, with pinvit_shift = 2, every vector by lam~_1
+    // as the step is printed.  After each Ritz step Zo holds the Ritz vectors,
     // R = K Zo, Qb = G Zo.
     const int steps = c->o.pinvit_steps;
     double lam1_before = 0.0, t_pinvit = 0.0;
@@ -1350,7 +1351,7 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         if (s > 0) {
             const double ts = now_s();
             if (s == 1) lam1_before = c->lam[0];
-            for (int i = 0; i < k; ++i) c->hpin[i] = c->lam[i];
+            for (int i = 0; i < k; ++i) c->hpin[i] = c->o.pinvit_shift == 2 ? c->lam[0] : c->lam[i];
             HIPC(hipMemcpyAsync(c->dlam_l, c->hpin, sizeof(double) * k, hipMemcpyHostToDevice, c->st));
             launch_axpy_cols(n, k, n, c->dlam_l, 1.0, c->Qb, c->R, c->st);   // (K + lam~_i G) phi_i
             CHK(precondition(c, 1, k, c->R, c->Zb));
@@ -1616,6 +1617,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     c->o.eig_guard = 0;
     c->o.eig_max_it = 400;
     c->o.check_every = 8;
+    c->o.pinvit_shift = 1;
     c->o.seed = 1;
     c->o.cycle = 1;
     c->o.block_cg = 1;
@@ -1783,6 +1785,7 @@ int mlb_set_opts(mlb_ctx* c, const mlb_opts* o) {
     if (o->pinvit_steps > 0) c->o.pinvit_steps = std::min(o->pinvit_steps, 64);
     else if (o->pinvit_steps < 0) c->o.pinvit_steps = 0;
     if (o->coarse_sweeps > 0) c->o.coarse_sweeps = std::min(o->coarse_sweeps, 64);
+    if (o->pinvit_shift > 0) c->o.pinvit_shift = o->pinvit_shift == 2 ? 2 : 1;
     if (o->refine_sweeps > 0) c->o.refine_sweeps = std::min(o->refine_sweeps, 16);
     else if (o->refine_sweeps < 0) c->o.refine_sweeps = 0;
     drop_graphs(c);
