@@ -195,11 +195,14 @@ def kaczmarz_sweep_rowwise(A, X, nel, fixed):
     return X
 
 
-def multilevel_buckling_refined(nel, K, G, fixed, ell, q, sweeps, dense_limit=6000):
+def multilevel_buckling_refined(nel, K, G, fixed, ell, q, sweeps, dense_limit=6000, fine_step=False):
     """Sec. 2.1 steps 1-4 with the intermediate-level smoothing and Ritz steps
     of Alg. 2 (``sweeps`` Kaczmarz sweeps per level).  K, G: constrained fine
-    operators.  Returns the fine Ritz values and vectors and, per refined
-    level (l-1 first), its Ritz values."""
+    operators.  With ``fine_step`` the loop also visits the fine grid (the
+    printed loop runs down to it): the prolonged modes take the same sweeps
+    on (K + sigma G) psi = 0 and a fine Ritz step before the block solve.
+    Returns the fine Ritz values and vectors and, per refined level (l-1
+    first, the fine grid last when ``fine_step``), its Ritz values."""
     grids, masks, Ps = lv.hierarchy(nel, fixed, ell)
     Ks, Gs = [K], [G]
     for j in range(ell - 1):
@@ -226,6 +229,16 @@ def multilevel_buckling_refined(nel, K, G, fixed, ell, q, sweeps, dense_limit=60
         per_level.append(lam_j)
     Psi = Ps[0] @ Psi if ell > 1 else Psi
     f0 = _free(fixed)
+    if fine_step and ell > 1:
+        A = (K + sigma * G).tocsr()
+        for _ in range(sweeps):
+            Psi = kaczmarz_sweep(A, Psi, nel, fixed)
+        lam_1, V1 = rayleigh_ritz(K[f0][:, f0], G[f0][:, f0], Psi[f0])
+        if len(lam_1) < q:
+            raise ValueError("fewer than q positive Ritz values on the fine grid")
+        Psi = np.zeros((K.shape[0], q))
+        Psi[f0] = V1
+        per_level.append(lam_1)
     Kff = K[f0][:, f0].tocsc()
     import scipy.sparse.linalg as spla
     Phi_t = spla.splu(Kff).solve(np.ascontiguousarray((G @ Psi)[f0]))

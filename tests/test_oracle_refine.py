@@ -78,3 +78,25 @@ def test_refinement_without_sweeps_is_the_plain_method_and_bounds_hold(nel, ell,
         assert np.all(lam >= exact * (1 - 1e-12))
         for lj in per:
             assert np.all(lj >= exact * (1 - 1e-12))
+
+
+@pytest.mark.parametrize("nel,ell,seed", [((32, 8), 3, 43), ((16, 8, 8), 3, 44)])
+def test_fine_level_step_bounds(nel, ell, seed):
+    """The loop run down to the fine grid: the fine-grid Ritz values of the
+    smoothed modes and the final Ritz values stay above the exact ones
+    (Courant-Fischer), the fine-grid Ritz step is reported last, and with no
+    sweeps the fine Ritz step leaves the final values unchanged (the block
+    solve's span is that of G Psi, whatever basis of span Psi is used)."""
+    K, G, fixed = _problem(nel, seed)
+    q = 4
+    free = np.flatnonzero(fixed == 0)
+    exact = lba.generalized_lowest_positive(K[free][:, free], G[free][:, free], q)[0]
+    lam_plain, _, _, per_plain = mg.multilevel_buckling_refined(nel, K, G, fixed, ell, q, 0)
+    lam0, _, _, per0 = mg.multilevel_buckling_refined(nel, K, G, fixed, ell, q, 0, fine_step=True)
+    assert len(per0) == len(per_plain) + 1
+    assert np.allclose(lam0, lam_plain, rtol=1e-10, atol=0)
+    for sweeps in (1, 3):
+        lam, _, _, per = mg.multilevel_buckling_refined(nel, K, G, fixed, ell, q, sweeps, fine_step=True)
+        assert len(per) == ell - 1
+        assert np.all(per[-1] >= exact * (1 - 1e-12))
+        assert np.all(lam >= exact * (1 - 1e-12))
