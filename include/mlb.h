@@ -152,6 +152,11 @@ typedef struct {
     int pinvit_shift;     /* shift of the inverse iteration steps: 1 = each Ritz vector's own Ritz value
                              (the default: the gradient step of its Rayleigh quotient), 2 = lam~_1 for
                              every vector (the step as printed in App. A); 0 keeps the current value */
+    int refine_fine;      /* with refine_sweeps: 1 = the refinement loop also visits the fine grid (Alg. 2's
+                             loop is printed down to it): the prolonged modes take the sweeps on
+                             (K + sigma G) psi = 0 with assembled fine stencils of K and G (about
+                             (dim 3^dim)^2 + 3^dim doubles per node, allocated on first use) and a fine
+                             Ritz step before the block solve; < 0 = not (the default); 0 keeps */
 } mlb_opts;
 
 /* Per-call solver report; for blocks, the worst column is reported. */

@@ -102,12 +102,13 @@ class Context:
 
     def set_opts(self, smooth_steps=0, jacobi_omega=0.0, eig_guard=0, eig_max_it=0, check_every=0, seed=0,
                  cycle=0, block_cg=0, eig_sweeps=0, graphs=0, pinvit_steps=0, refine_sweeps=0, coarse_sweeps=0,
-                 pinvit_shift=0):
+                 pinvit_shift=0, refine_fine=0):
         """Zero (the default of every argument) keeps the current value;
         pinvit_steps < 0 and refine_sweeps < 0 turn those steps off;
-        pinvit_shift 1 = own Ritz values, 2 = the printed lam~_1."""
+        pinvit_shift 1 = own Ritz values, 2 = the printed lam~_1;
+        refine_fine 1 = the refinement also visits the fine grid, < 0 = not."""
         o = B.MlbOpts(smooth_steps, jacobi_omega, eig_guard, eig_max_it, check_every, seed, cycle, block_cg,
-                      eig_sweeps, graphs, pinvit_steps, refine_sweeps, coarse_sweeps, pinvit_shift)
+                      eig_sweeps, graphs, pinvit_steps, refine_sweeps, coarse_sweeps, pinvit_shift, refine_fine)
         self._check(self.lib.mlb_set_opts(self.h, C.byref(o)))
 
     def set_omegas(self, omegas):

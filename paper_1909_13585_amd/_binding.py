@@ -41,7 +41,8 @@ class MlbOpts(C.Structure):
     _fields_ = [("smooth_steps", C.c_int), ("jacobi_omega", C.c_double), ("eig_guard", C.c_int),
                 ("eig_max_it", C.c_int), ("check_every", C.c_int), ("seed", C.c_uint64), ("cycle", C.c_int),
                 ("block_cg", C.c_int), ("eig_sweeps", C.c_int), ("graphs", C.c_int), ("pinvit_steps", C.c_int),
-                ("refine_sweeps", C.c_int), ("coarse_sweeps", C.c_int), ("pinvit_shift", C.c_int)]
+                ("refine_sweeps", C.c_int), ("coarse_sweeps", C.c_int), ("pinvit_shift", C.c_int),
+                ("refine_fine", C.c_int)]
 
 
 class MlbSolveInfo(C.Structure):

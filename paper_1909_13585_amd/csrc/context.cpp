@@ -115,6 +115,10 @@ struct mlb_ctx {
     // coefficients of the returned modes (signs included), the residual
     // adjoints w = K^-1 (K + lam G) phi
     double *Psif = nullptr, *cW = nullptr;
+    // fine-grid stencils of K and G, built only when the refinement of Alg. 2
+    // also visits the fine grid (mlb_opts.refine_fine)
+    double *fineA = nullptr, *fineGs = nullptr, *fineDinv = nullptr;
+    float *fineAf = nullptr, *fineDinvf = nullptr;
     std::vector<double> rrC;
     bool psi_ok = false;
     std::vector<double> lam, eigres;
@@ -1329,6 +1333,62 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
             t_refine += now_s() - ts;
         }
     }
+    // Optionally the loop also visits the fine grid (it is printed down to
+    // it): the same sweeps on (K + sigma G) psi = 0 with assembled fine
+    // stencils, then a fine Ritz step, before the block solve.
+    if (sweeps > 0 && c->o.refine_fine && c->ell > 1) {
+        const double ts = now_s();
+        Level& l1 = c->lv[0];
+        const int dim = c->dim;
+        const int nn = 1 << dim, nde = dim << dim;
+        if (!c->fineA) {
+            CHK(dalloc(c, &c->fineA, (size_t)stencil_entries(dim, l1.g, false)));
+            CHK(dalloc(c, &c->fineAf, (size_t)stencil_entries(dim, l1.g, false)));
+            CHK(dalloc(c, &c->fineGs, (size_t)stencil_entries(dim, l1.g, true)));
+            CHK(dalloc(c, &c->fineDinv, (size_t)n));
+            CHK(dalloc(c, &c->fineDinvf, (size_t)n));
+        }
+        double *Ke = nullptr, *Ge = nullptr;
+        CHK(dalloc(c, &Ke, (size_t)l1.g.m * nde * nde));
+        const int rge = dalloc(c, &Ge, (size_t)l1.g.m * nn * nn);
+        if (rge != MLB_OK) {
+            dfree(Ke);
+            return rge;
+        }
+        launch_fine_elem_mats(dim, l1.g, c->Ek, c->dK0, c->S, c->dHk, Ke, Ge, c->st);
+        launch_assemble_nb(dim, l1.g, Ke, l1.nmask, c->fineA, c->fineAf, c->fineDinv, c->fineDinvf, c->st);
+        launch_assemble_nb_diag(dim, l1.g, Ge, l1.nmask, c->fineGs, c->st);
+        const hipError_t es = hipStreamSynchronize(c->st);
+        dfree(Ke);
+        dfree(Ge);
+        HIPC(es);
+        for (int sw = 0; sw < sweeps; ++sw)
+            launch_kaczmarz_sweep(dim, l1.g, c->fineA, c->fineGs, sigma, l1.nmask, k, n, c->X1, c->st);
+        apply_K<double>(c, 1, k, c->X1, c->Phi, kModeY, nullptr, nullptr);
+        apply_G(c, 1, k, c->X1, c->X2);
+        std::vector<double> A, B;
+        CHK(gram2(c, n, k, c->X1, k, c->Phi, c->X2, A, B));
+        std::vector<double> A2(k * k), B2(k * k), ev(k), Y(k * k);
+        for (int a = 0; a < k; ++a)
+            for (int q = 0; q < k; ++q) {
+                A2[a * k + q] = 0.5 * (A[a + k * q] + A[q + k * a]);
+                B2[a * k + q] = -0.5 * (B[a + k * q] + B[q + k * a]);
+            }
+        if (!gen_eig(k, A2.data(), B2.data(), ev.data(), Y.data()))
+            return fail(c, MLB_EBREAKDOWN, "fine Rayleigh-Ritz: Psi^T K Psi not positive definite");
+        if (!(ev[k - 1] > 0.0)) return fail(c, MLB_ENOPOS, "fewer than k positive Ritz values on the fine grid");
+        std::vector<double> C(k * k);
+        for (int a = 0; a < k; ++a)
+            for (int q = 0; q < k; ++q) C[a + k * q] = Y[a * k + q];
+        CHK(upload_cm(c, c->cbuf, C));
+        launch_gemm_small(n, k, n, c->X1, k, c->cbuf, n, c->Zb, c->st);
+        launch_copy_cols(n, k, n, c->Zb, n, c->X1, c->st);
+        sigma = 1.0 / ev[0];
+        if (nref < 8) lam1_ref[nref] = sigma;
+        ++nref;
+        CHK(sync(c));
+        t_refine += now_s() - ts;
+    }
     if (c->ell == 1) launch_copy_cols(n, k, n, c->eS, n, c->X1, c->st);
     launch_copy_cols(n, k, n, c->X1, n, c->Psif, c->st);
     // step 3: K Phi~ = G Psi
@@ -1618,6 +1678,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
     c->o.eig_max_it = 400;
     c->o.check_every = 8;
     c->o.pinvit_shift = 1;
+    c->o.refine_fine = 0;
     c->o.seed = 1;
     c->o.cycle = 1;
     c->o.block_cg = 1;
@@ -1760,6 +1821,7 @@ void mlb_destroy(mlb_ctx* c) {
     dfree(c->eA); dfree(c->eT); dfree(c->eTK); dfree(c->eTA); dfree(c->eR); dfree(c->eP); dfree(c->ePK); dfree(c->ePA); dfree(c->part); dfree(c->pidx);
     dfree(c->scal); dfree(c->iscal); dfree(c->gbuf); dfree(c->cbuf); dfree(c->cbuf2);
     dfree(c->fw); dfree(c->warm_coarse); dfree(c->warm_static); dfree(c->Psif); dfree(c->cW);
+    dfree(c->fineA); dfree(c->fineGs); dfree(c->fineDinv); dfree(c->fineAf); dfree(c->fineDinvf);
     if (c->hpin) (void)hipHostFree(c->hpin);
     if (c->hup) (void)hipHostFree(c->hup);
     drop_graphs(c);
@@ -1786,6 +1848,8 @@ int mlb_set_opts(mlb_ctx* c, const mlb_opts* o) {
     else if (o->pinvit_steps < 0) c->o.pinvit_steps = 0;
     if (o->coarse_sweeps > 0) c->o.coarse_sweeps = std::min(o->coarse_sweeps, 64);
     if (o->pinvit_shift > 0) c->o.pinvit_shift = o->pinvit_shift == 2 ? 2 : 1;
+    if (o->refine_fine > 0) c->o.refine_fine = 1;
+    else if (o->refine_fine < 0) c->o.refine_fine = 0;
     if (o->refine_sweeps > 0) c->o.refine_sweeps = std::min(o->refine_sweeps, 16);
     else if (o->refine_sweeps < 0) c->o.refine_sweeps = 0;
     drop_graphs(c);

@@ -25,6 +25,9 @@ void launch_assemble_nb(int dim, const Geo& g, const double* Ke, const uint8_t* 
 // in colour order (i mod 3) + 3 (j mod 3) + 9 (k mod 3); Dirichlet rows skipped.
 void launch_kaczmarz_sweep(int dim, const Geo& g, const double* A, const double* Gd, double sigma,
                            const uint8_t* nmask, int ncols, int64_t ld, double* X, hipStream_t st);
+// fine-grid element matrices E_e K0 and sum_q S_qe H_q ([entry m + e])
+void launch_fine_elem_mats(int dim, const Geo& g, const double* E, const double* K0, const double* S,
+                           const double* Hk, double* Ke, double* Ge, hipStream_t st);
 void launch_assemble_nb_diag(int dim, const Geo& g, const double* Ge, const uint8_t* nmask, double* A,
                              hipStream_t st);
 template <typename T>

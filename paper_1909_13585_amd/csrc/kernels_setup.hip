@@ -198,6 +198,38 @@ void launch_galerkin_from_E(int dim, const Geo& gf, const Geo& gc, const double*
     if (dim == 2) hipLaunchKernelGGL(k_galerkin_from_E<2>, dim3(nb1(tot)), dim3(kBlock), 0, st, gf, gc, E, Mc, Kc);
     else hipLaunchKernelGGL(k_galerkin_from_E<3>, dim3(nb1(tot)), dim3(kBlock), 0, st, gf, gc, E, Mc, Kc);
 }
+// Fine-grid element matrices in the layout the stencil assembly reads
+// ([entry m + e]): K_e = E_e K0 (nde x nde) and the scalar stress matrix
+// g_e = sum_q S_qe H_q (nn x nn).  Used only when the refinement of Alg. 2
+// also visits the fine grid.
+__global__ void k_fine_Ke(int64_t m, int nde2, const double* __restrict__ E, const double* __restrict__ K0,
+                          double* __restrict__ Ke) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= m * nde2) return;
+    const int64_t e = t % m;
+    const int entry = (int)(t / m);
+    Ke[t] = E[e] * K0[entry];
+}
+
+__global__ void k_fine_Ge(int64_t m, int nn, int nv, const double* __restrict__ S, const double* __restrict__ Hk,
+                          double* __restrict__ Ge) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= m * nn * nn) return;
+    const int64_t e = t % m;
+    const int entry = (int)(t / m);
+    double s = 0.0;
+    for (int q = 0; q < nv; ++q) s += S[q * m + e] * Hk[q * 64 + entry];
+    Ge[t] = s;
+}
+
+void launch_fine_elem_mats(int dim, const Geo& g, const double* E, const double* K0, const double* S,
+                           const double* Hk, double* Ke, double* Ge, hipStream_t st) {
+    const int nn = 1 << dim, nde = dim << dim, nv = dim == 2 ? 3 : 6;
+    const int64_t t1 = g.m * nde * nde, t2 = g.m * nn * nn;
+    hipLaunchKernelGGL(k_fine_Ke, dim3(nb1(t1)), dim3(kBlock), 0, st, g.m, nde * nde, E, K0, Ke);
+    hipLaunchKernelGGL(k_fine_Ge, dim3(nb1(t2)), dim3(kBlock), 0, st, g.m, nn, nv, S, Hk, Ge);
+}
+
 void launch_galerkin_G_from_S(int dim, const Geo& gf, const Geo& gc, const double* S, const double* GHc,
                               double* gout, hipStream_t st) {
     const int nn = 1 << dim;

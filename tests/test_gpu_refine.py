@@ -48,28 +48,30 @@ def _problem(c):
     return x, fixed, F, K, G
 
 
-@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("case,fine", [(k, False) for k in CASES] + [("column_2d_l3", True), ("box_3d_l3", True)])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_refinement_matches_oracle(torch_mod, case, precision):
+def test_refinement_matches_oracle(torch_mod, case, fine, precision):
+    """fine: the loop also visits the fine grid (mlb_opts.refine_fine)."""
     torch = torch_mod
     import paper_1909_13585_amd as mlb
     c = CASES[case]
     x, fixed, F, K, G = _problem(c)
     tol = 1e-9 if precision == mlb.MLB_FP64 else 1e-6
     for sweeps in (1, 3):
-        lam_o, _, _, per = mg.multilevel_buckling_refined(c["nel"], K, G, fixed, c["ell"], c["q"], sweeps)
+        lam_o, _, _, per = mg.multilevel_buckling_refined(c["nel"], K, G, fixed, c["ell"], c["q"], sweeps,
+                                                          fine_step=fine)
         plain = lba.multilevel_buckling(c["nel"], x, None, fixed, MAT, c["ell"], c["q"], K=K, G=G)
-        _step(f"{case} precision {precision}: {sweeps} sweep(s)")
+        _step(f"{case} fine {fine} precision {precision}: {sweeps} sweep(s)")
         ctx = mlb.Context(c["nel"], mg_levels=c["levels"], eig_level=c["ell"], precision=precision)
         ctx.set_bc(fixed)
         ctx.set_loads(F)
         ctx.set_density_dev(torch.from_numpy(x).cuda())
-        ctx.set_opts(refine_sweeps=sweeps)
+        ctx.set_opts(refine_sweeps=sweeps, refine_fine=1 if fine else -1)
         U = torch.empty((1, ctx.n), dtype=torch.float64, device="cuda")
         ctx.solve_static_dev(U, tol=1e-10, max_it=3000)
         lam, _, info = ctx.buckling(c["q"], tol_eig=1e-12, want_modes=False)
         ctx.close()
-        nref = c["ell"] - 2
+        nref = c["ell"] - 2 + (1 if fine else 0)
         got1 = np.asarray(info["refine_lambda1"][:nref])
         ref1 = np.asarray([p[0] for p in per])
         err = np.abs(lam / lam_o - 1).max()
