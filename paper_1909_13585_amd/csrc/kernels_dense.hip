@@ -77,36 +77,50 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double al
             }
 }
 
-// In-place inverse of the 64 x 64 diagonal block at (k0, k0) of A (row-major,
-// leading dimension ld) into P (64 x 64, row-major) by scalar Gauss-Jordan
-// in LDS; the block is SPD (a Schur complement of an SPD matrix), so no
-// pivoting.  One block of 256 threads.
+// Inverse of the 64 x 64 diagonal block at (k0, k0) of A (row-major,
+// leading dimension ld) into P (64 x 64, row-major) by scalar Gauss-Jordan;
+// the block is SPD (a Schur complement of an SPD matrix), so no pivoting.
+// One block of 256 threads; thread t keeps column j = t % 64 of rows
+// t / 64 + 4 r (r = 0..15) in registers.  Step k: the owners publish row k
+// and column k to LDS (double-buffered by the parity of k, so one barrier
+// per step), then every thread updates its 16 entries; within a wave the
+// rows, hence the column-k entries read, are the same (LDS broadcasts).
 __global__ __launch_bounds__(256) void k_gj_diag(const double* __restrict__ A, int64_t ld, int64_t k0,
                                                  double* __restrict__ P) {
-    __shared__ double s[kGT * kGT];
-    __shared__ double rowk[kGT], colk[kGT];
+    __shared__ double rowk[2][kGT], colk[2][kGT];
     const int tid = threadIdx.x;
-    for (int e = tid; e < kGT * kGT; e += 256) s[e] = A[(k0 + e / kGT) * ld + k0 + e % kGT];
-    __syncthreads();
+    const int j = tid & (kGT - 1), i0 = tid >> 6;   // rows i0 + 4 r
+    double v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = A[(k0 + i0 + 4 * r) * ld + k0 + j];
     for (int k = 0; k < kGT; ++k) {
-        if (tid < kGT) {
-            rowk[tid] = s[k * kGT + tid];
-            colk[tid] = s[tid * kGT + k];
+        const int b = k & 1;
+        // row k lives in the threads with i0 == k % 4 (r = k / 4), column k
+        // in the threads with j == k
+        if (i0 == (k & 3)) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (r == (k >> 2)) rowk[b][j] = v[r];
+        }
+        if (j == k) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) colk[b][i0 + 4 * r] = v[r];
         }
         __syncthreads();
-        const double pinv = 1.0 / rowk[k];
-        for (int e = tid; e < kGT * kGT; e += 256) {
-            const int i = e / kGT, j = e % kGT;
-            double v;
-            if (i == k && j == k) v = pinv;
-            else if (i == k) v = rowk[j] * pinv;
-            else if (j == k) v = -colk[i] * pinv;
-            else v = s[e] - colk[i] * (rowk[j] * pinv);
-            s[e] = v;
+        const double pinv = 1.0 / rowk[b][k];
+        const double rj = rowk[b][j] * pinv;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = i0 + 4 * r;
+            const double ci = colk[b][i];
+            double w;
+            if (i == k) w = j == k ? pinv : rj;
+            else w = j == k ? -ci * pinv : v[r] - ci * rj;
+            v[r] = w;
         }
-        __syncthreads();
     }
-    for (int e = tid; e < kGT * kGT; e += 256) P[e] = s[e];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) P[(i0 + 4 * r) * kGT + j] = v[r];
 }
 
 // dst (rows x cols, leading dimension ldd) = src (leading dimension lds)

@@ -232,22 +232,25 @@ __global__ __launch_bounds__(kNbThreads) void k_apply_nb(Geo g, int64_t nblk_nod
 
 // ---------------------------------------------------------------------------
 // transfers: nodal (bi/tri)linear interpolation P and its transpose, masked
-// on both sides.  Thread per (node, component, column).
+// on both sides.  Thread per (DOF, column): consecutive threads take
+// consecutive DOFs of one column, so the fine-side (prolongation) and
+// coarse-side (restriction) vectors are read and written contiguously.
 
 template <int DIM, typename T, bool ADD>
-__global__ __launch_bounds__(kNbThreads) void k_prolong_nb(Geo gf, Geo gc, int64_t nblk_nodes, int ncols,
+__global__ __launch_bounds__(kNbThreads) void k_prolong_nb(Geo gf, Geo gc, int64_t nblk_dofs, int ncols,
                                                            const uint8_t* __restrict__ mf,
                                                            const uint8_t* __restrict__ mc, int64_t ldf, int64_t ldc,
                                                            const T* __restrict__ xc, T* __restrict__ yf) {
     int64_t nbk;
-    int grp;
-    if (!xcd_decode(nblk_nodes, DIM * ncols, nbk, grp)) return;
-    const int64_t node = nbk * kNbThreads + threadIdx.x;
-    if (node >= gf.nodes) return;
-    const int c = grp % DIM, col = grp / DIM;
+    int col;
+    if (!xcd_decode(nblk_dofs, ncols, nbk, col)) return;
+    const int64_t dof = nbk * kNbThreads + threadIdx.x;
+    if (dof >= gf.nodes * DIM) return;
+    const int64_t node = dof / DIM;
+    const int c = (int)(dof - node * DIM);
     int i, j, k;
     node_ijk(gf, node, i, j, k);
-    const int64_t d = (int64_t)col * ldf + node * DIM + c;
+    const int64_t d = (int64_t)col * ldf + dof;
     if ((mf[node] >> c) & 1) {
         if (!ADD) yf[d] = T(0);
         return;
@@ -268,19 +271,20 @@ __global__ __launch_bounds__(kNbThreads) void k_prolong_nb(Geo gf, Geo gc, int64
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(kNbThreads) void k_restrict_nb(Geo gf, Geo gc, int64_t nblk_nodes, int ncols,
+__global__ __launch_bounds__(kNbThreads) void k_restrict_nb(Geo gf, Geo gc, int64_t nblk_dofs, int ncols,
                                                             const uint8_t* __restrict__ mf,
                                                             const uint8_t* __restrict__ mc, int64_t ldf, int64_t ldc,
                                                             const T* __restrict__ xf, T* __restrict__ yc) {
     int64_t nbk;
-    int grp;
-    if (!xcd_decode(nblk_nodes, DIM * ncols, nbk, grp)) return;
-    const int64_t cnode = nbk * kNbThreads + threadIdx.x;
-    if (cnode >= gc.nodes) return;
-    const int c = grp % DIM, col = grp / DIM;
+    int col;
+    if (!xcd_decode(nblk_dofs, ncols, nbk, col)) return;
+    const int64_t cdof = nbk * kNbThreads + threadIdx.x;
+    if (cdof >= gc.nodes * DIM) return;
+    const int64_t cnode = cdof / DIM;
+    const int c = (int)(cdof - cnode * DIM);
     int I, J, K;
     node_ijk(gc, cnode, I, J, K);
-    const int64_t o = (int64_t)col * ldc + cnode * DIM + c;
+    const int64_t o = (int64_t)col * ldc + cdof;
     if ((mc[cnode] >> c) & 1) {
         yc[o] = T(0);
         return;
@@ -377,8 +381,8 @@ void launch_apply_nb(int dim, const Geo& g, const T* A, bool diag, int ncols, in
 template <typename T>
 void launch_prolong_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
                        int64_t ldf, int64_t ldc, const T* xc, T* yf, bool add, hipStream_t st) {
-    const int64_t nbn = (gf.nodes + kNbThreads - 1) / kNbThreads;
-    const dim3 gr = xcd_grid(gf.nodes, dim * ncols);
+    const int64_t nbn = (gf.nodes * dim + kNbThreads - 1) / kNbThreads;
+    const dim3 gr = xcd_grid(gf.nodes * dim, ncols);
     const dim3 b(kNbThreads);
 #define MLB_P(D, AD) \
     hipLaunchKernelGGL((k_prolong_nb<D, T, AD>), gr, b, 0, st, gf, gc, nbn, ncols, mf, mc, ldf, ldc, xc, yf)
@@ -395,8 +399,8 @@ void launch_prolong_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf,
 template <typename T>
 void launch_restrict_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
                         int64_t ldf, int64_t ldc, const T* xf, T* yc, hipStream_t st) {
-    const int64_t nbn = (gc.nodes + kNbThreads - 1) / kNbThreads;
-    const dim3 gr = xcd_grid(gc.nodes, dim * ncols);
+    const int64_t nbn = (gc.nodes * dim + kNbThreads - 1) / kNbThreads;
+    const dim3 gr = xcd_grid(gc.nodes * dim, ncols);
     const dim3 b(kNbThreads);
     if (dim == 2)
         hipLaunchKernelGGL((k_restrict_nb<2, T>), gr, b, 0, st, gf, gc, nbn, ncols, mf, mc, ldf, ldc, xf, yc);
