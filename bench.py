@@ -535,6 +535,41 @@ def optimisation_leg(args, steps=3):
             "lambda_bar": float(lam_bar), "lambda1_solid": float(lam_solid[0]), "J_max": float(6.0 * J_solid[0])}
 
 
+def nn_forward_leg(net, nel, ell, reps=20):
+    """The warm-start network's forward pass on its input for the bench box
+    (eigen-level cells), with the 3x3x3 convolutions on the VALU kernels
+    (FP32 activations) and on the matrix cores (BF16 activations, FP32
+    accumulation); HIP events on the current stream, mean over ``reps``.
+    The flop count is that of the 3x3x3 convolutions (2 flops per
+    multiply-add)."""
+    import torch
+    from paper_1909_13585_amd import warmstart as ws
+    shp = [v // 2 ** (ell - 1) for v in nel]
+    x = torch.randn((1, net.cin) + tuple(reversed(shp)), dtype=torch.float32, device="cuda",
+                    generator=torch.Generator("cuda").manual_seed(3))
+    V = [int(np.prod(shp)), int(np.prod(shp)) // 8, int(np.prod(shp)) // 64]
+    lev = {"e1a": 0, "e1b": 0, "e2a": 1, "e2b": 1, "b1": 2, "b2": 2, "d2a": 1, "d2b": 1, "d1a": 0, "d1b": 0}
+    flops = sum(2.0 * V[lev[name]] * ci * co * 27 for name, ci, co, k, _ in net.layers if k == 3)
+    st = torch.cuda.current_stream()
+    out = {}
+    for mode in (False, True):
+        net.mfma = mode
+        net.forward(x)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            net.forward(x)
+        e1.record(st)
+        torch.cuda.synchronize()
+        out["mfma_ms" if mode else "valu_ms"] = e0.elapsed_time(e1) / reps
+    net.mfma = False
+    out.update(input=[1, net.cin] + list(reversed(shp)), conv_gflop=flops / 1e9,
+               mfma_tflops=flops / (out["mfma_ms"] * 1e-3) / 1e12,
+               note="whole forward pass (convolutions, pooling, concatenation, head) per call")
+    return out
+
+
 def column_leg(args, steps=3):
     """The 960x320 Q4 column (616,962 DOFs) in plain FP64 on 4 and 5 multigrid
     levels: static solve + 12 modes on the 240x80 eigen level + sensitivities."""
@@ -724,7 +759,8 @@ def main():
                    "fine_block_iterations": outl[3]["fine_iterations"],
                    "adjoint_iterations": outl[4]["iterations"],
                    "max_rel_lambda_diff_vs_cold": float(np.max(np.abs(np.asarray(outl[2]) / np.asarray(lam) - 1))),
-                   "weights": os.path.relpath(args.learned, ROOT)}
+                   "weights": os.path.relpath(args.learned, ROOT),
+                   "network_forward": nn_forward_leg(net, nel, args.eig_level)}
 
     incompatible = None
     if not args.no_incompatible:

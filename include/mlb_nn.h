@@ -28,6 +28,13 @@ extern "C" {
    w ([Ci_fwd=Co][Co_fwd=Ci]); bias must then be NULL.  relu: 1 applies max(.,0). */
 int mlb_nn_conv3d(int N, int Ci, int Co, int D, int H, int W, int k, int trans, const float* x,
                   const uint16_t* w, const float* bias, float* y, int relu, void* stream);
+/* The forward 3x3x3 convolution of mlb_nn_conv3d (k = 3, trans = 0) on the
+   matrix cores: both operands BF16 (the activations x rounded to nearest
+   even as they are read, the weights w as stored), products accumulated in
+   FP32 (v_mfma_f32_16x16x32_bf16 on gfx950), i.e. the same convolution of
+   bf16(x).  Same layouts and arguments; bias may be NULL. */
+int mlb_nn_conv3d_mfma(int N, int Ci, int Co, int D, int H, int W, const float* x, const uint16_t* w,
+                       const float* bias, float* y, int relu, void* stream);
 /* dw[Co][Ci][k^3] = sum over samples and voxels of dy * shifted x; db[Co] = sum dy (db may be NULL). */
 int mlb_nn_conv3d_wgrad(int N, int Ci, int Co, int D, int H, int W, int k, const float* x, const float* dy,
                         float* dw, float* db, void* stream);

@@ -145,13 +145,16 @@ def unet_layers(cin, cout, c=16):
             ("head", c, cout, 1, False)]
 
 
-def unet_forward(params, x, c=16):
-    """params: name -> (w (BF16-rounded float64), b).  Returns node outputs and the cache."""
+def unet_forward(params, x, c=16, act_bf16=False):
+    """params: name -> (w (BF16-rounded float64), b).  Returns node outputs and
+    the cache.  act_bf16: the inputs of the 3x3x3 convolutions are rounded to
+    BF16 first (the matrix-core forward pass)."""
     A = {}
 
     def conv(name, inp, relu):
         w, b = params[name]
-        out = conv3d(inp, w, b, relu)
+        src = bf16_round(inp) if act_bf16 and w.shape[-1] == 3 else inp
+        out = conv3d(src, w, b, relu)
         A[name] = (inp, out)
         return out
 

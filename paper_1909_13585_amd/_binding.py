@@ -156,6 +156,7 @@ _SIGS = {
     # warm-start network kernels (include/mlb_nn.h)
     "mlb_nn_conv3d": (_I, [_I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P]),
     "mlb_nn_conv3d_wgrad": (_I, [_I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),
+    "mlb_nn_conv3d_mfma": (_I, [_I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P]),
     "mlb_nn_relu_mask": (_I, [C.c_int64, _P, _P, _P]),
     "mlb_nn_pool2": (_I, [C.c_int64, _I, _I, _I, C.c_float, _P, _P, _P]),
     "mlb_nn_axpy": (_I, [C.c_int64, C.c_float, _P, _P, _P]),

@@ -178,6 +178,8 @@ void launch_dlam(int dim, const Geo& g, const double* x, double p, double E1, do
 // ---- warm-start network (kernels_nn.hip)
 int launch_nn_conv3d(int N, int Ci, int Co, int D, int H, int W, int K, int trans, const float* x, const uint16_t* w,
                      const float* bias, float* y, int relu, hipStream_t st);
+int launch_nn_conv3d_mfma(int N, int Ci, int Co, int D, int H, int W, const float* x, const uint16_t* w,
+                          const float* bias, float* y, int relu, hipStream_t st);
 int launch_nn_conv3d_wgrad(int N, int Ci, int Co, int D, int H, int W, int K, const float* x, const float* dy,
                            float* dw, float* db, hipStream_t st);
 void launch_nn_relu_mask(int64_t n, const float* y, float* g, hipStream_t st);

@@ -85,6 +85,80 @@ __global__ __launch_bounds__(kNnThreads) void k_conv3d(int Ci, int Co, int D, in
     }
 }
 
+// Forward 3x3x3 convolution on the matrix cores (implicit GEMM): per sample,
+// Y (Co x V) = W (Co x Ci 27) X^ (Ci 27 x V) with X^ the zero-padded taps
+// of x, both operands in BF16 (activations rounded to nearest even on load,
+// the weights already BF16), products accumulated in FP32 by
+// v_mfma_f32_16x16x32_bf16.  Its operands: lane l holds row / column l % 16
+// and the 8 consecutive k = 8 (l / 16) + e; its result: column l % 16, rows
+// 4 (l / 16) + r.  A wave computes MT 16-channel tiles (channel group
+// blockIdx.z) for 16 consecutive voxels, gathering each tap once for all
+// of them; the k index runs over (input channel, tap) in the weights' order
+// and is padded with zeros to a multiple of 32.
+typedef __bf16 mlb_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float mlb_f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline __bf16 mlb_bits_bf16(uint16_t h) { return __builtin_bit_cast(__bf16, h); }
+
+template <int MT>
+__global__ __launch_bounds__(kNnThreads) void k_conv3d_mfma(int Ci, int Co, int D, int H, int W,
+                                                            const float* __restrict__ x,
+                                                            const uint16_t* __restrict__ w,
+                                                            const float* __restrict__ bias, float* __restrict__ y,
+                                                            int relu) {
+    const int64_t V = (int64_t)D * H * W;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kg = lane >> 4;
+    const int n = blockIdx.y;
+    const int obase = blockIdx.z * MT * 16;
+    const int64_t p = ((int64_t)blockIdx.x * (kNnThreads / 64) + wv) * 16 + col;
+    const bool live = p < V;
+    const int64_t pc = live ? p : 0;
+    const int wx = (int)(pc % W), hy = (int)((pc / W) % H), dz = (int)(pc / ((int64_t)W * H));
+    const float* xn = x + (int64_t)n * Ci * V;
+    const int KT = Ci * 27;
+    mlb_f32x4 acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = mlb_f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < KT; k0 += 32) {
+        mlb_bf16x8 b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int kk = k0 + 8 * kg + e;
+            float v = 0.f;
+            if (live && kk < KT) {
+                const int i = kk / 27, t = kk - 27 * i;
+                const int zz = dz + t / 9 - 1, yy = hy + (t / 3) % 3 - 1, xx = wx + t % 3 - 1;
+                if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    v = xn[(int64_t)i * V + ((int64_t)zz * H + yy) * W + xx];
+            }
+            b[e] = mlb_bits_bf16(f32_to_bf16(v));
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int o = obase + mt * 16 + col;
+            mlb_bf16x8 a;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int kk = k0 + 8 * kg + e;
+                a[e] = mlb_bits_bf16((o < Co && kk < KT) ? w[(int64_t)o * KT + kk] : (uint16_t)0);
+            }
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mt], 0, 0, 0);
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = obase + mt * 16 + 4 * kg + r;
+            if (o >= Co) continue;
+            float v = acc[mt][r] + (bias ? bias[o] : 0.f);
+            if (relu) v = v > 0.f ? v : 0.f;
+            y[((int64_t)n * Co + o) * V + p] = v;
+        }
+}
+
 // dw[o, i, t] = sum_{n,p} dy[n, o, p] x[n, i, p + off(t)]  (one block per (o, i))
 template <int K>
 __global__ __launch_bounds__(kNnThreads) void k_conv3d_wgrad(int N, int Ci, int Co, int D, int H, int W,
@@ -321,6 +395,27 @@ int launch_nn_conv3d(int N, int Ci, int Co, int D, int H, int W, int K, int tran
     else if (K == 1 && !trans) hipLaunchKernelGGL((k_conv3d<1, false>), gr, dim3(kNnThreads), 0, st, Ci, Co, D, H, W, x, w, bias, y, relu);
     else if (K == 1 && trans) hipLaunchKernelGGL((k_conv3d<1, true>), gr, dim3(kNnThreads), 0, st, Ci, Co, D, H, W, x, w, bias, y, relu);
     else return -1;
+    return 0;
+}
+
+int launch_nn_conv3d_mfma(int N, int Ci, int Co, int D, int H, int W, const float* x, const uint16_t* w,
+                          const float* bias, float* y, int relu, hipStream_t st) {
+    const int64_t V = (int64_t)D * H * W;
+    const int64_t wavesv = (V + 15) / 16;
+    const unsigned gx = (unsigned)((wavesv + kNnThreads / 64 - 1) / (kNnThreads / 64));
+    const int ntile = (Co + 15) / 16;
+    if (ntile <= 4) {
+        const dim3 gr(gx, (unsigned)N, 1);
+#define MLB_CM(MT) hipLaunchKernelGGL(k_conv3d_mfma<MT>, gr, dim3(kNnThreads), 0, st, Ci, Co, D, H, W, x, w, bias, y, relu)
+        if (ntile == 1) MLB_CM(1);
+        else if (ntile == 2) MLB_CM(2);
+        else if (ntile == 3) MLB_CM(3);
+        else MLB_CM(4);
+#undef MLB_CM
+    } else {
+        const dim3 gr(gx, (unsigned)N, (unsigned)((ntile + 3) / 4));
+        hipLaunchKernelGGL(k_conv3d_mfma<4>, gr, dim3(kNnThreads), 0, st, Ci, Co, D, H, W, x, w, bias, y, relu);
+    }
     return 0;
 }
 

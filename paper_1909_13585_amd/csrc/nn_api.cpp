@@ -22,6 +22,14 @@ int mlb_nn_conv3d(int N, int Ci, int Co, int D, int H, int W, int k, int trans, 
     return last();
 }
 
+int mlb_nn_conv3d_mfma(int N, int Ci, int Co, int D, int H, int W, const float* x, const uint16_t* w,
+                       const float* bias, float* y, int relu, void* stream) {
+    if (!dims_ok(N, Ci, Co) || !dims_ok(D, H, W) || !x || !w || !y) return MLB_EINVAL;
+    if ((int64_t)Ci * 27 > (1 << 30)) return MLB_EINVAL;
+    launch_nn_conv3d_mfma(N, Ci, Co, D, H, W, x, w, bias, y, relu, S(stream));
+    return last();
+}
+
 int mlb_nn_conv3d_wgrad(int N, int Ci, int Co, int D, int H, int W, int k, const float* x, const float* dy, float* dw,
                         float* db, void* stream) {
     if (!dims_ok(N, Ci, Co) || !dims_ok(D, H, W) || !x || !dy || !dw) return MLB_EINVAL;

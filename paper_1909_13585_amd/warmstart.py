@@ -66,6 +66,9 @@ class UNet3D:
             for d in (self.m, self.v):
                 d[name] = (torch.zeros_like(w), torch.zeros_like(self.b[name]))
         self.step_no = 0
+        # forward 3x3x3 convolutions on the matrix cores (BF16 activations);
+        # training keeps the FP32-activation kernels
+        self.mfma = False
         self.refresh_bf16()
 
     # -- plumbing
@@ -83,9 +86,17 @@ class UNet3D:
         _, ci, co, k, _ = next(L for L in self.layers if L[0] == name)
         N, _, D, H, W = x.shape
         y = torch.empty((N, co, D, H, W), dtype=torch.float32, device="cuda")
+        if self.mfma and k == 3 and self._cache_off():
+            self._check(self.lib.mlb_nn_conv3d_mfma(N, ci, co, D, H, W, _p(x), _p(self.wb[name]), _p(self.b[name]),
+                                                    _p(y), 1 if relu else 0, _st()), "conv3d_mfma " + name)
+            return y
         self._check(self.lib.mlb_nn_conv3d(N, ci, co, D, H, W, k, 0, _p(x), _p(self.wb[name]), _p(self.b[name]),
                                            _p(y), 1 if relu else 0, _st()), "conv3d " + name)
         return y
+
+    def _cache_off(self):
+        # the matrix-core path serves inference only (no backward cache)
+        return not getattr(self, "_keeping", False)
 
     def _pool(self, x, scale=1.0):
         import torch
@@ -131,6 +142,7 @@ class UNet3D:
             return out
 
         x = x.contiguous()
+        self._keeping = keep
         e1 = conv("e1b", conv("e1a", x))
         e2 = conv("e2b", conv("e2a", self._pool(e1)))
         bt = conv("b2", conv("b1", self._pool(e2)))

@@ -177,3 +177,57 @@ def test_nodes_to_dofs_matches_host_permutation():
     b = blocks.cpu().numpy()
     assert np.array_equal(b[:q].T, modes)
     assert np.array_equal(b[q], u)
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 5, 6, 7), (1, 16, 8, 4, 12), (1, 37, 4, 4, 4), (2, 1, 3, 9, 5)])
+@pytest.mark.parametrize("co", [1, 11, 16, 40, 70])
+def test_conv3d_mfma_matches_reference(env, shape, co):
+    """The matrix-core forward convolution: the oracle's convolution of the
+    BF16-rounded activations with the BF16 weights (products exact in FP32,
+    sums in FP32 on the GPU): normwise 1e-5, maximum 1e-5 of the largest
+    entry.  Shapes with voxel counts that are not multiples of 16, channel
+    counts that are not multiples of 16, k ranges not a multiple of 32 and
+    more than 64 output channels (two channel groups)."""
+    torch, lib = env
+    N, ci, D, H, W = shape
+    rng = np.random.default_rng(ci * 13 + co)
+    x = rng.standard_normal((N, ci, D, H, W)).astype(np.float32)
+    w = rng.standard_normal((co, ci, 3, 3, 3)) / np.sqrt(ci * 27)
+    b = rng.standard_normal(co).astype(np.float32)
+    wbits, wr = _bf16_bits(torch, w)
+    xd, bd = _t(torch, x), _t(torch, b)
+    y = torch.empty((N, co, D, H, W), dtype=torch.float32, device="cuda")
+    xr = nn.bf16_round(x.astype(np.float64))
+    for relu in (0, 1):
+        for bias in (bd, None):
+            assert lib.mlb_nn_conv3d_mfma(N, ci, co, D, H, W, _p(xd), _p(wbits), _p(bias), _p(y), relu, None) == 0
+            ref = nn.conv3d(xr, wr.astype(np.float64), b.astype(np.float64) if bias is not None else None,
+                            relu=bool(relu))
+            got = y.cpu().numpy()
+            assert _rel(got, ref) < 1e-5
+            assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_unet_forward_on_the_matrix_cores(env):
+    """The U-Net forward pass with its 3x3x3 convolutions on the matrix cores
+    equals the oracle's forward pass with every such convolution's input
+    rounded to BF16 (1e-4 normwise), and stays within BF16 rounding of the
+    FP32-activation pass (2e-2 normwise)."""
+    torch, lib = env
+    from paper_1909_13585_amd.warmstart import UNet3D
+    net = UNet3D(cin=4, cout=3, c=8, seed=5)
+    rng = np.random.default_rng(9)
+    for name in net.w:
+        net.b[name].copy_(torch.from_numpy(rng.standard_normal(net.b[name].numel()).astype(np.float32) * 0.1))
+    x = rng.standard_normal((1, 4, 8, 8, 16)).astype(np.float32)
+    xd = _t(torch, x)
+    y_valu = net.forward(xd).cpu().numpy()
+    net.mfma = True
+    y_mfma = net.forward(xd).cpu().numpy()
+    params = {name: (nn.bf16_round(net.w[name].cpu().numpy()), net.b[name].cpu().numpy().astype(np.float64))
+              for name in net.w}
+    ref, _ = nn.unet_forward(params, x.astype(np.float64), c=8, act_bf16=True)
+    print(f"U-Net forward: MFMA vs BF16-activation oracle {_rel(y_mfma, ref):.2e}, "
+          f"vs FP32-activation pass {_rel(y_mfma, y_valu):.2e}")
+    assert _rel(y_mfma, ref) < 1e-4
+    assert _rel(y_mfma, y_valu) < 2e-2

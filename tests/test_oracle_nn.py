@@ -115,3 +115,25 @@ def test_unet_backward_matches_finite_differences():
         bm[j] -= h
         fd = (loss({**params, name: (w, bp)}) - loss({**params, name: (w, bm)})) / (2 * h)
         assert abs(fd - G[name][1][j]) <= 1e-6 * max(1.0, abs(fd)), (name, fd, G[name][1][j])
+
+
+def test_unet_forward_with_bf16_activations():
+    """act_bf16 rounds exactly the inputs of the 3x3x3 convolutions: the first
+    layer's output equals conv3d of the rounded input, the head (1x1x1)
+    reads its FP64 input, and the whole pass stays within BF16 rounding of
+    the plain one."""
+    rng = np.random.default_rng(3)
+    cin, cout, c = 2, 3, 4
+    params = {}
+    for name, ci, co, k, _ in nn.unet_layers(cin, cout, c):
+        params[name] = (nn.bf16_round(rng.standard_normal((co, ci, k, k, k)) / np.sqrt(ci * k ** 3)),
+                        rng.standard_normal(co) * 0.1)
+    x = rng.standard_normal((1, cin, 4, 4, 8))
+    y0, A0 = nn.unet_forward(params, x, c)
+    y1, A1 = nn.unet_forward(params, x, c, act_bf16=True)
+    w, b = params["e1a"]
+    assert np.array_equal(A1["e1a"][1], nn.conv3d(nn.bf16_round(x), w, b, relu=True))
+    wh, bh = params["head"]
+    assert np.array_equal(A1["head"][1], nn.conv3d(A1["head"][0], wh, bh))
+    rel = np.linalg.norm(y1 - y0) / np.linalg.norm(y0)
+    assert 0 < rel < 2e-2
