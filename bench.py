@@ -32,11 +32,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel (12-column FP32 Jacobi sweep of
-# the fine level) by tuned (variant, z chunk): rocprofv3 FETCH_SIZE x 1.99973
+# the fine level) by tuned (variant, z chunk): rocprofv3 FETCH_SIZE x ~2.0
 # + WRITE_SIZE x 1.0 (factors from a 256 MiB calibration copy), KiB per
 # dispatch, from profiles/jacobi_sweep_h8_192x64x64_12col_fp32_hbm_counters.md;
 # reported only when the run tuned the same tile.
-SWEEP_TRAFFIC_BYTES = {(0, 12): (160331.19 * 1.99973 + 118492.34) * 1024}
+SWEEP_TRAFFIC_BYTES = {(3, 6): (168196.71 * 1.99965 + 120368.36) * 1024,
+                       (0, 6): (169269.43 * 1.99976 + 118064.79) * 1024}
 
 
 def parse():
@@ -69,6 +70,8 @@ def parse():
     ap.add_argument("--no-instances", action="store_true",
                     help="skip the 32 independent 2D instances (batched vs one context at a time)")
     ap.add_argument("--sweep-reps", type=int, default=50)
+    ap.add_argument("--force-wht", type=str, default="",
+                    help="with --roofline-only: variant,zchunk of the fine sweep instead of the autotuned ones")
     ap.add_argument("--no-post", action="store_true",
                     help="skip the post-processing measures (strain energy density, variation, correlation, dilation) "
                          "and the design chain (filter, projection, chain rule)")
@@ -267,6 +270,11 @@ def batched_instances(reps=3):
                           "batch_iterations": t[3]["batch_iterations"]}
         print(f"# instances {name}: {t[0]:.4f} s (setup {t[3]['setup_s']:.4f}, solve {t[3]['solve_s']:.4f}, "
               f"{t[3]['batch_iterations']} batched iterations)", file=sys.stderr, flush=True)
+    # the same solve without the refinement steps: the work the separate
+    # contexts below do (one CG solve to 1e-8 each)
+    batched(dict(queue=0, graphs=1, refine_steps=0))
+    t_norefine = min(batched(dict(queue=0, graphs=1, refine_steps=0))[0] for _ in range(reps))
+    b.set_opts(refine_steps=10)
     _, J, its, info = batched(dict(queue=1, graphs=1))
     res, floor, res_dd = b.residuals()
     levels = [int(v) for v in b.levels]
@@ -300,6 +308,7 @@ def batched_instances(reps=3):
     return {"instances": len(insts), "dofs": int(sum(int(np.prod([v + 1 for v in q["nel"]])) * 2 for q in insts)),
             "levels": levels, "precision": "mixed", "tol": 1e-8,
             "s_batched": best, "batched_variant": best_name, "variants": variants, "s_one_context_at_a_time": tseq, "speedup": tseq / best,
+            "s_batched_without_refinement": t_norefine, "speedup_same_work": tseq / t_norefine,
             "max_iterations": int(info["max_iterations"]), "total_iterations": int(info["total_iterations"]),
             "worst_true_rel_res": info["worst_true_rel_res"], "refine_steps": int(info["refine_steps"]),
             "worst_refined_rel_res": info["worst_refined_rel_res"],
@@ -542,8 +551,8 @@ def nn_forward_leg(net, nel, ell, reps=20):
     accumulation); HIP events on the current stream, mean over ``reps``.
     The flop count is that of the 3x3x3 convolutions (2 flops per
     multiply-add)."""
+    import numpy as np
     import torch
-    from paper_1909_13585_amd import warmstart as ws
     shp = [v // 2 ** (ell - 1) for v in nel]
     x = torch.randn((1, net.cin) + tuple(reversed(shp)), dtype=torch.float32, device="cuda",
                     generator=torch.Generator("cuda").manual_seed(3))
@@ -702,6 +711,10 @@ def main():
         ctx.set_loads(p["F"])
         ctx.set_density_dev(x_dev)
         tune = ctx.autotune(args.modes)
+        if args.force_wht:
+            fv, fz = (int(v) for v in args.force_wht.split(","))
+            ctx.set_tiles(wht_zchunk=fz, wht_variant=fv)
+            tune = dict(tune, wht_variant=fv, wht_zchunk=fz)
         torch.cuda.synchronize()
         ctx.sweep_dev(1, args.modes, args.sweep_reps)
         cal = 1 << 25   # 32 Mi doubles = 256 MiB
