@@ -1645,7 +1645,7 @@ int autotune_t(mlb_ctx* c, int ncols, bool stencils, int mode, int* zout, int* v
         T* r2 = lbuf<T>(l2, 0);
         launch_restrict_nb<T>(c->dim, l1.g, l2.g, l1.nmask, l2.nmask, ncols, l1.n, l2.n, x, x2, c->st);
         launch_restrict_nb<T>(c->dim, l1.g, l2.g, l1.nmask, l2.nmask, ncols, l1.n, l2.n, r, r2, c->st);
-        const int cb[] = {2, 3, 4, 6, 8};
+        const int cb[] = {2, 3, 4, 6, 12};
         best = 1e30f;
         int bc = c->nb_cbmax;
         for (int i = 0; i < 5; ++i) {
