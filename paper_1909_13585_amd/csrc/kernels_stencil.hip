@@ -166,73 +166,64 @@ __device__ inline T nb_epilogue(T ax, T xown, T rr, T di, T omega) {
     return xown + omega * di * (rr - ax);
 }
 
-template <int DIM, typename T, int MODE, int CB, bool DIAG>
+template <int DIM, typename T, int MODE, int CB, bool DIAG, bool SPLITC>
 __global__ __launch_bounds__(kNbThreads) void k_apply_nb(Geo g, int64_t nblk_nodes, int nchunks,
                                                          const T* __restrict__ A, int ncols, int64_t ld,
                                                          const T* __restrict__ x, T* __restrict__ y,
                                                          const T* __restrict__ r, const T* __restrict__ dinv,
                                                          T omega) {
-    // Thread per (node, column chunk): all DIM components of the node, so
-    // each neighbour value is gathered once for the node's rows (the
-    // per-output sums run in the same order as one thread per component).
+    // SPLITC: thread per (node, component, column chunk), for few columns
+    // (enough threads).  Otherwise thread per (node, column chunk) over all
+    // DIM components of the node, so each neighbour value and stencil block
+    // is loaded once for the node's rows and all columns.  Every output sums
+    // the same terms in the same order either way.
     using S = Sten<DIM>;
     int64_t nbk;
     int grp;
-    if (!xcd_decode(nblk_nodes, nchunks, nbk, grp)) return;
+    if (!xcd_decode(nblk_nodes, SPLITC ? DIM * nchunks : nchunks, nbk, grp)) return;
     const int64_t node = nbk * kNbThreads + threadIdx.x;
     if (node >= g.nodes) return;
-    const int c0 = grp * CB;
-    const int nq = min(CB, ncols - c0);
     int i, j, k;
     node_ijk(g, node, i, j, k);
     const int64_t N = g.nodes;
     const int64_t sy = g.nnx, sz = (int64_t)g.nnx * g.nny;
-    const T* xb = x + (int64_t)c0 * ld;
-    T acc[DIM][CB];
+    if constexpr (SPLITC) {
+        const int c = grp % DIM;
+        const int c0 = (grp / DIM) * CB;
+        const int nq = min(CB, ncols - c0);
+        const T* xb = x + (int64_t)c0 * ld;
+        T acc[CB];
 #pragma unroll
-    for (int c = 0; c < DIM; ++c)
+        for (int q = 0; q < CB; ++q) acc[q] = T(0);
 #pragma unroll
-        for (int q = 0; q < CB; ++q) acc[c][q] = T(0);
+        for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+            const bool okz = k + dz >= 0 && k + dz < g.nnz;
 #pragma unroll
-    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
-        const bool okz = k + dz >= 0 && k + dz < g.nnz;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const bool oky = okz && j + dy >= 0 && j + dy < g.nny;
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-            const bool oky = okz && j + dy >= 0 && j + dy < g.nny;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const bool ok = oky && i + dx >= 0 && i + dx < g.nnx;
+                    const int nb = (dx + 1) + 3 * (dy + 1) + (DIM == 3 ? 9 * (dz + 1) : 0);
+                    const int64_t nbn = ok ? node + dx + sy * dy + sz * dz : node;
+                    if (DIAG) {
+                        const T a = A[(int64_t)(nb * DIM + c) * N + node];
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                const bool ok = oky && i + dx >= 0 && i + dx < g.nnx;
-                const int nb = (dx + 1) + 3 * (dy + 1) + (DIM == 3 ? 9 * (dz + 1) : 0);
-                const int64_t nbn = ok ? node + dx + sy * dy + sz * dz : node;
-                // the neighbour's block of the stencil, once for all columns
-                T a[DIM][DIM];
+                        for (int q = 0; q < CB; ++q)
+                            if (q < nq) acc[q] += a * xb[q * ld + nbn * DIM + c];
+                    } else {
+                        T a[DIM];
 #pragma unroll
-                for (int c = 0; c < DIM; ++c)
+                        for (int c2 = 0; c2 < DIM; ++c2) a[c2] = A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node];
 #pragma unroll
-                    for (int c2 = 0; c2 < DIM; ++c2)
-                        a[c][c2] = DIAG ? (c2 == c ? A[(int64_t)(nb * DIM + c) * N + node] : T(0))
-                                        : A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node];
+                        for (int q = 0; q < CB; ++q)
+                            if (q < nq)
 #pragma unroll
-                for (int q = 0; q < CB; ++q) {
-                    if (q >= nq) break;
-                    T xv[DIM];
-#pragma unroll
-                    for (int c2 = 0; c2 < DIM; ++c2) xv[c2] = xb[q * ld + nbn * DIM + c2];
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) {
-                        if (DIAG) {
-                            acc[c][q] += a[c][c] * xv[c];
-                        } else {
-#pragma unroll
-                            for (int c2 = 0; c2 < DIM; ++c2) acc[c][q] += a[c][c2] * xv[c2];
-                        }
+                                for (int c2 = 0; c2 < DIM; ++c2) acc[q] += a[c2] * xb[q * ld + nbn * DIM + c2];
                     }
                 }
             }
         }
-    }
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
         const int64_t d = node * DIM + c;
         const T di = MODE == kModeJacobi ? dinv[d] : T(0);
 #pragma unroll
@@ -241,7 +232,67 @@ __global__ __launch_bounds__(kNbThreads) void k_apply_nb(Geo g, int64_t nblk_nod
             const int64_t o = (int64_t)(c0 + q) * ld + d;
             const T xown = MODE == kModeJacobi ? x[o] : T(0);
             const T rr = MODE == kModeY ? T(0) : r[o];
-            y[o] = nb_epilogue<T, MODE>(acc[c][q], xown, rr, di, omega);
+            y[o] = nb_epilogue<T, MODE>(acc[q], xown, rr, di, omega);
+        }
+    } else {
+        const int c0 = grp * CB;
+        const int nq = min(CB, ncols - c0);
+        const T* xb = x + (int64_t)c0 * ld;
+        T acc[DIM][CB];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int q = 0; q < CB; ++q) acc[c][q] = T(0);
+#pragma unroll
+        for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+            const bool okz = k + dz >= 0 && k + dz < g.nnz;
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const bool oky = okz && j + dy >= 0 && j + dy < g.nny;
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const bool ok = oky && i + dx >= 0 && i + dx < g.nnx;
+                    const int nb = (dx + 1) + 3 * (dy + 1) + (DIM == 3 ? 9 * (dz + 1) : 0);
+                    const int64_t nbn = ok ? node + dx + sy * dy + sz * dz : node;
+                    // the neighbour's block of the stencil, once for all columns
+                    T a[DIM][DIM];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                        for (int c2 = 0; c2 < DIM; ++c2)
+                            a[c][c2] = DIAG ? (c2 == c ? A[(int64_t)(nb * DIM + c) * N + node] : T(0))
+                                            : A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node];
+#pragma unroll
+                    for (int q = 0; q < CB; ++q) {
+                        if (q >= nq) break;
+                        T xv[DIM];
+#pragma unroll
+                        for (int c2 = 0; c2 < DIM; ++c2) xv[c2] = xb[q * ld + nbn * DIM + c2];
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) {
+                            if (DIAG) {
+                                acc[c][q] += a[c][c] * xv[c];
+                            } else {
+#pragma unroll
+                                for (int c2 = 0; c2 < DIM; ++c2) acc[c][q] += a[c][c2] * xv[c2];
+                            }
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const int64_t d = node * DIM + c;
+            const T di = MODE == kModeJacobi ? dinv[d] : T(0);
+#pragma unroll
+            for (int q = 0; q < CB; ++q) {
+                if (q >= nq) break;
+                const int64_t o = (int64_t)(c0 + q) * ld + d;
+                const T xown = MODE == kModeJacobi ? x[o] : T(0);
+                const T rr = MODE == kModeY ? T(0) : r[o];
+                y[o] = nb_epilogue<T, MODE>(acc[c][q], xown, rr, di, omega);
+            }
         }
     }
 }
@@ -365,11 +416,19 @@ void launch_apply_nb(int dim, const Geo& g, const T* A, bool diag, int ncols, in
     const int want = (ncols + per - 1) / per;
     const int cb = want <= 1 ? 1 : want <= 2 ? 2 : want <= 3 ? 3 : want <= 4 ? 4 : want <= 6 ? 6 : want <= 8 ? 8 : 12;
     const int nchunks = (ncols + cb - 1) / cb;
-    const dim3 gr = xcd_grid(g.nodes, nchunks);
+    // one-column calls (and DIAG) keep a thread per component: enough threads
+    const bool split = ncols == 1 || diag;
+    const dim3 gr = xcd_grid(g.nodes, split ? dim * nchunks : nchunks);
     const dim3 b(kNbThreads);
-#define MLB_NB(D, M, C, DG)                                                                                      \
-    hipLaunchKernelGGL((k_apply_nb<D, T, M, C, DG>), gr, b, 0, st, g, nbn, nchunks, A, ncols, ld, x, y, r, dinv, \
-                       omega)
+#define MLB_NB(D, M, C, DG)                                                                                         \
+    do {                                                                                                            \
+        if (split)                                                                                                  \
+            hipLaunchKernelGGL((k_apply_nb<D, T, M, C, DG, true>), gr, b, 0, st, g, nbn, nchunks, A, ncols, ld, x, \
+                               y, r, dinv, omega);                                                                  \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_apply_nb<D, T, M, C, DG, false>), gr, b, 0, st, g, nbn, nchunks, A, ncols, ld, x, \
+                               y, r, dinv, omega);                                                                  \
+    } while (0)
 #define MLB_NB_M(D, C)                                             \
     do {                                                           \
         if (diag) MLB_NB(D, kModeY, C, true);                      \
