@@ -458,6 +458,19 @@ int gram(mlb_ctx* c, int64_t n, int k1, const double* A, int64_t lda, int k2, co
     return MLB_OK;
 }
 
+// out = sign (A^T B)^T (k2 x k1, column-major) in device memory, enqueued
+// only (no host read): the coefficients of an orthogonalisation step.
+int gram_coeffs_dev(mlb_ctx* c, int64_t n, int k1, const double* A, int64_t lda, int k2, const double* B,
+                    int64_t ldb, double sign, double* out) {
+    if ((int64_t)k1 * k2 > 96 * 192) return fail(c, MLB_EINVAL, "Gram matrix larger than 96 x 192");
+    const int np = gram_parts(n, k1, k2);
+    CHK(ensure_part(c, (int64_t)np * k1 * k2));
+    if (launch_gram(n, k1, lda, A, k2, ldb, B, 0, 0, nullptr, np, c->part, c->gbuf, c->st) != 0)
+        return fail(c, MLB_EINVAL, "Gram operands wider than 192 columns");
+    launch_gram_transpose(k1, k2, sign, c->gbuf, out, c->st);
+    return MLB_OK;
+}
+
 // G1 = A^T B1, G2 = A^T B2 (each k1 x k2) in one pass over A, or in two when
 // the three operands together are wider than the Gram kernel's 192 columns.
 int gram2(mlb_ctx* c, int64_t n, int k1, const double* A, int k2, const double* B1, const double* B2,
@@ -1114,11 +1127,8 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
             // block and its Rayleigh-Ritz problem well conditioned
             double *P = b.S + n * nb, *KP = b.KS + n * nb, *AP = b.AS + n * nb;
             for (int pass = 0; pass < 2; ++pass) {
-                CHK(gram(c, n, rp, P, n, nb, KX, n, G));
-                Co.assign((size_t)nb * rp, 0.0);   // Co[a, q] = -(X^T K P)[a, q]
-                for (int a = 0; a < nb; ++a)
-                    for (int q = 0; q < rp; ++q) Co[a + (size_t)nb * q] = -G[q + (size_t)rp * a];
-                CHK(upload_cm(c, c->cbuf2, Co));
+                // cbuf2[a, q] = -(X^T K P)[a, q], formed on the device
+                CHK(gram_coeffs_dev(c, n, rp, P, n, nb, KX, n, -1.0, c->cbuf2));
                 launch_gemm_cat(n, nb, n, X, 0, n, nullptr, rp, c->cbuf2, 1.0, n, P, c->st);
                 launch_gemm_cat(n, nb, n, KX, 0, n, nullptr, rp, c->cbuf2, 1.0, n, KP, c->st);
                 launch_gemm_cat(n, nb, n, AX, 0, n, nullptr, rp, c->cbuf2, 1.0, n, AP, c->st);
@@ -1156,11 +1166,8 @@ int coarse_eigs(mlb_ctx* c, int k, double tol, int* iters, double* worst, double
         // W -= [X P] ([K X, K P]^T W), twice
         const int nx = nb + rp;
         for (int pass = 0; pass < 2; ++pass) {
-            CHK(gram(c, n, na, W, n, nx, KX, n, G));
-            Co.assign((size_t)nx * na, 0.0);   // Co[a, q] = G[q, a]
-            for (int a = 0; a < nx; ++a)
-                for (int q = 0; q < na; ++q) Co[a + (size_t)nx * q] = G[q + (size_t)na * a];
-            CHK(upload_cm(c, c->cbuf2, Co));
+            // cbuf2[a, q] = ([K X, K P]^T W)[a, q], formed on the device
+            CHK(gram_coeffs_dev(c, n, na, W, n, nx, KX, n, 1.0, c->cbuf2));
             launch_gemm_cat(n, nx, n, X, 0, n, nullptr, na, c->cbuf2, 0.0, n, c->eR, c->st);
             launch_axpby(n * na, -1.0, c->eR, 1.0, W, c->st);
         }

@@ -112,6 +112,8 @@ void launch_axpy_cols(int64_t n, int ncols, int64_t ld, const double* coef, doub
 int gram_parts(int64_t n, int k1, int k2);
 int launch_gram(int64_t n, int k1, int64_t lda, const double* A, int k2a, int64_t ldb1, const double* B1, int k2b,
                 int64_t ldb2, const double* B2, int nparts, double* part, double* out, hipStream_t st);
+// out (k2 x k1, column-major) = sign G^T for G (k1 x k2, column-major)
+void launch_gram_transpose(int k1, int k2, double sign, const double* G, double* out, hipStream_t st);
 // block CG row updates (sp, r, nc <= 32)
 int bcg_step_parts(int64_t n);
 void launch_bcg_step(int64_t n, int sp, int r, int nc, const double* T, const double* alpha, double* P, double* Q,

@@ -664,6 +664,18 @@ void launch_cg_check(int ncols, const double* rr, const double* thr, int* active
     hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64 * ((ncols + 63) / 64)), 0, st, ncols, rr, thr, active, iters,
                        flags);
 }
+// out[a + k2 q] = sign G[q + k1 a] (a < k2, q < k1): the transposed Gram
+// block, scaled, as a column-major coefficient matrix for k_gemm_cat.
+__global__ void k_gram_transpose(int k1, int k2, double sign, const double* __restrict__ G,
+                                 double* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= k1 * k2) return;
+    const int a = t % k2, q = t / k2;
+    out[a + k2 * q] = sign * G[q + k1 * a];
+}
+void launch_gram_transpose(int k1, int k2, double sign, const double* G, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_gram_transpose, dim3((k1 * k2 + 255) / 256), dim3(256), 0, st, k1, k2, sign, G, out);
+}
 void launch_cg_beta(int ncols, const double* rz_new, double* rz, const int* active, double* beta, hipStream_t st) {
     hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64 * ((ncols + 63) / 64)), 0, st, ncols, rz_new, rz, active, beta);
 }
