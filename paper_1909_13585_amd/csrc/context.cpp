@@ -144,6 +144,7 @@ struct mlb_ctx {
     int warm_coarse_cols = 0;
     double* warm_static = nullptr;   // device, n x warm_static_cols
     int warm_static_cols = 0;
+    size_t warm_coarse_cap = 0, warm_static_cap = 0;   // allocated doubles
     // density filter weight table (di, dj, dk, w) for the radius fw_r
     double* fw = nullptr;
     int fw_n = 0;
@@ -2396,25 +2397,34 @@ static int set_warm_common(mlb_ctx* c, int kind, int ncols, const double* data, 
         dfree(c->warm_coarse);
         dfree(c->warm_static);
         c->warm_coarse_cols = c->warm_static_cols = 0;
+        c->warm_coarse_cap = c->warm_static_cap = 0;
         return MLB_OK;
     }
     if (!data || ncols < 1) return fail(c, MLB_EINVAL, "warm start needs data and ncols >= 1");
     double** dst = nullptr;
+    size_t* cap = nullptr;
     int64_t rows = 0;
     if (kind == MLB_WARM_COARSE) {
         if (ncols > 64) return fail(c, MLB_EINVAL, "at most 64 coarse warm-start columns");
         dst = &c->warm_coarse;
+        cap = &c->warm_coarse_cap;
         rows = c->lv[c->ell - 1].n;
         c->warm_coarse_cols = 0;
     } else if (kind == MLB_WARM_STATIC) {
         if (ncols > 32) return fail(c, MLB_EINVAL, "at most 32 static warm-start columns");
         dst = &c->warm_static;
+        cap = &c->warm_static_cap;
         rows = c->n;
         c->warm_static_cols = 0;
     } else {
         return fail(c, MLB_EINVAL, "unknown warm-start kind");
     }
-    CHK(dalloc(c, dst, (size_t)rows * ncols));
+    // the buffer is kept between calls (a design loop sets one every step)
+    if (!*dst || *cap < (size_t)rows * ncols) {
+        *cap = 0;
+        CHK(dalloc(c, dst, (size_t)rows * ncols));
+        *cap = (size_t)rows * ncols;
+    }
     const size_t bytes = sizeof(double) * (size_t)rows * ncols;
     if (dev) {
         c->st = pick(c, stream);

@@ -181,3 +181,45 @@ def test_p2_design_steps_match_oracle(torch):
         assert np.allclose(gi["fval"], oi["fval"], rtol=0, atol=1e-7)
         assert err < 1e-8, k
     ctx.close()
+
+
+def test_design_steps_recycling(torch):
+    """Three P2 steps that recycle the previous analysis (its coarse modes
+    start the coarse eigensolve, its displacement the static CG) against the
+    same steps started cold, with a move limit of 0.02 (the small steps of a
+    settling design): the designs agree to the solver tolerances, and from
+    the second step on the recycled block is kept and the coarse eigensolve
+    needs fewer iterations."""
+    import paper_1909_13585_amd as mlb
+    import workloads as W
+    from oracle import fem, lba
+    from paper_1909_13585_amd.optimize import P2Step
+    nel = (16, 12, 8)
+    fixed = W.clamp_mask(nel)
+    F = W.axial_load(nel)[:, None]
+    x0 = W.random_small(3, nel, 21, 0.35, 0.65)
+    an = lba.analysis(nel, x0, F, fixed, fem.Material(p=3.0), 2, 6)
+    J_max, lam_bar = 1.5 * float(an["J"][0]), 1.1 * an["buck"].lam[0]
+    runs = {}
+    for rec in (False, True):
+        ctx = mlb.Context(nel, mg_levels=3, eig_level=2)
+        ctx.set_bc(fixed)
+        ctx.set_loads(F)
+        stepper = P2Step(ctx, 6, 4, 1.8, 0.5, 2.0, J_max, lam_bar, tol=1e-11, tol_eig=1e-11, recycle=rec,
+                         move=0.02)
+        xg = _dev(torch, x0)
+        infos = [stepper.step(xg, penal=3.0) for _ in range(3)]
+        runs[rec] = (xg.cpu().numpy(), infos)
+        ctx.close()
+    (xc, ic), (xr, ir) = runs[False], runs[True]
+    for k in range(3):
+        print(f"step {k}: coarse its cold {ic[k]['coarse_iterations']} recycled {ir[k]['coarse_iterations']} "
+              f"(kept {ir[k]['coarse_warm_used']}), static its {ic[k]['static_iterations']} / "
+              f"{ir[k]['static_iterations']}, f0 {ic[k]['f0']:.12f} / {ir[k]['f0']:.12f}")
+    assert np.max(np.abs(xc - xr)) < 1e-8
+    assert ir[0]["coarse_warm_used"] == 0 and ir[0]["coarse_iterations"] == ic[0]["coarse_iterations"]
+    for k in (1, 2):
+        assert ir[k]["coarse_warm_used"] == 1
+        assert ir[k]["coarse_iterations"] < ic[k]["coarse_iterations"]
+        assert abs(ir[k]["f0"] - ic[k]["f0"]) < 1e-12
+        assert np.allclose(ir[k]["fval"], ic[k]["fval"], rtol=0, atol=1e-8)
