@@ -310,7 +310,10 @@ int mlb_autotune(mlb_ctx* ctx, int ncols, mlb_tune_info* info, void* stream);
  * fine initial guess per load case (n x ncases, host), scaled per column
  * by alpha = f^T u0 / u0^T K u0 before the solve.  MLB_WARM_NONE clears both.
  * A warm start only changes iteration counts, never the tolerance the
- * solvers reach. */
+ * solvers reach.  A coarse block is used only if the worst initial Ritz
+ * residual of the wanted pairs is no larger than that of the random start
+ * block.  The context keeps its warm-start buffers between calls and
+ * reallocates only to grow them (MLB_WARM_NONE frees them). */
 int mlb_set_warm_start(mlb_ctx* ctx, int kind, int ncols, const double* data);
 /* The same from device memory: `data` is copied on `stream` into the
  * context's buffers (no host round trip), so a prediction computed on the
