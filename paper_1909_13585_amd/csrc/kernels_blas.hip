@@ -204,14 +204,13 @@ __global__ void k_axpy_cols(int64_t n, int ncols, int64_t ld, const double* __re
     for (int c = 0; c < ncols; ++c) y[c * ld + i] += sign * coef[c] * x[c * ld + i];
 }
 
-// ---- Gram products A^T B (n x k1, n x k2): partial per block of rows
-// Rows are staged through LDS in chunks of 32; each thread owns outputs.
-// ---------------------------------------------------------------------------
+// ---- Gram products
 // Gram matrices G = A^T [B1 B2] (A: n x k1, B1: n x k2a, B2: n x k2b, all
 // column-major).  Bandwidth-bound: every block streams slabs of `rows`
 // consecutive rows of all operands into LDS (coalesced, one wave per column),
 // then each thread accumulates a TS x TS tile of G over a strided subset of
-// the slab rows in registers.  Tiles x row-groups fill the 256 threads; the
+// the slab rows in registers.  Where the slab fits 12 values per thread, the
+// next slab is loaded into registers while the current one is multiplied.  Tiles x row-groups fill the 256 threads; the
 // row groups are summed through LDS in a fixed order at the end and every
 // block writes one partial G, reduced by k_gram_reduce in block order, so
 // the result is deterministic.
@@ -247,22 +246,53 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(int64_t n, int rows, int 
 #pragma unroll
         for (int v = 0; v < TS; ++v) acc[u][v] = 0.0;
     const int64_t nslab = (n + rows - 1) / rows;
+    // the next slab's share of this thread is loaded into registers while
+    // the current one is multiplied (when (k1 + k2) rows <= PF x 256)
+    constexpr int PF = TS == 4 ? 12 : 1;
+    const int tot = (k1 + k2) * rows;
+    const bool pf_ok = tot <= PF * kGramThreads;
+    double pv[PF];
+    // rows divides the block size: a thread keeps its row r = t % rows and
+    // takes columns c0, c0 + cstep, ...
+    const int prow = t % rows, pc0 = t / rows, pcs = kGramThreads / rows;
+    auto fetch = [&](int64_t sl) {
+        const int64_t row = sl * rows + prow;
+        const bool rok = sl < nslab && row < n;
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int cc = pc0 + q * pcs;
+            const double* src = cc < k1 ? A + cc * lda
+                                        : (cc - k1 < k2a ? B1 + (cc - k1) * ldb1 : B2 + (cc - k1 - k2a) * ldb2);
+            pv[q] = rok && cc < k1 + k2 ? src[row] : 0.0;
+        }
+    };
+    if (pf_ok) fetch(blockIdx.x);
     for (int64_t sl = blockIdx.x; sl < nslab; sl += gridDim.x) {
         const int64_t r0 = sl * rows;
         __syncthreads();
-        for (int e = t; e < k1 * rows; e += kGramThreads) {
-            const int r = e % rows, cc = e / rows;
-            const int64_t row = r0 + r;
-            sa[cc * stride + r] = row < n ? A[cc * lda + row] : 0.0;
+        if (pf_ok) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int cc = pc0 + q * pcs;
+                if (cc < k1 + k2) sa[cc * stride + prow] = pv[q];   // sb follows sa
+            }
+            __syncthreads();
+            fetch(sl + gridDim.x);
+        } else {
+            for (int e = t; e < k1 * rows; e += kGramThreads) {
+                const int r = e % rows, cc = e / rows;
+                const int64_t row = r0 + r;
+                sa[cc * stride + r] = row < n ? A[cc * lda + row] : 0.0;
+            }
+            for (int e = t; e < k2 * rows; e += kGramThreads) {
+                const int r = e % rows, cc = e / rows;
+                const int64_t row = r0 + r;
+                double v = 0.0;
+                if (row < n) v = cc < k2a ? B1[cc * ldb1 + row] : B2[(cc - k2a) * ldb2 + row];
+                sb[cc * stride + r] = v;
+            }
+            __syncthreads();
         }
-        for (int e = t; e < k2 * rows; e += kGramThreads) {
-            const int r = e % rows, cc = e / rows;
-            const int64_t row = r0 + r;
-            double v = 0.0;
-            if (row < n) v = cc < k2a ? B1[cc * ldb1 + row] : B2[(cc - k2a) * ldb2 + row];
-            sb[cc * stride + r] = v;
-        }
-        __syncthreads();
         if (active) {
             for (int r = rg; r < rows; r += rg_n) {
                 double av[TS], bv[TS];
