@@ -467,8 +467,10 @@ def sweep_bytes(dim, nel, level, ncols, word):
     """Algorithmic HBM bytes of one Jacobi sweep of `ncols` columns on `level`:
     per column x and r read and y written (3 words per DOF); D^-1 read once;
     level 1 (matrix-free): one modulus per element and one mask byte per
-    node; coarser levels: the node-block stencil, 3^dim neighbour blocks of
-    dim x dim words per node."""
+    node; coarser levels: the node-block stencil, dim x dim words for each of
+    the 3^dim neighbour blocks per node in FP64, for the (3^dim + 1) / 2
+    stored ones in FP32 (the FP32 stencil is kept by half, its other blocks
+    being the neighbours' transposes)."""
     f = 2 ** (level - 1)
     ne = [v // f for v in nel]
     nodes = 1
@@ -479,7 +481,8 @@ def sweep_bytes(dim, nel, level, ncols, word):
         m *= v
     n = dim * nodes
     b = ncols * 3 * word * n + word * n
-    b += word * m + nodes if level == 1 else nodes * (3 ** dim) * dim * dim * word
+    nblk = 3 ** dim if word == 8 else (3 ** dim + 1) // 2
+    b += word * m + nodes if level == 1 else nodes * nblk * dim * dim * word
     return b
 
 

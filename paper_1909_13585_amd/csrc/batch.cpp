@@ -582,7 +582,7 @@ int build(mlb_batch* b) {
                                        b->Ke + b->keoff[si], st);
             if (j < b->L[i])
                 launch_assemble_nb(2, geo_of(sc), b->Ke + b->keoff[si], b->nmask + sc.noff, b->A + sc.soff,
-                                   b->Af + sc.soff, b->dinv + sc.voff, b->dinvf + sc.voff, st);
+                                   b->Af + sc.soff, b->dinv + sc.voff, b->dinvf + sc.voff, false, st);
             else
                 launch_assemble_dense(2, geo_of(sc), b->Ke + b->keoff[si], b->nmask + sc.noff,
                                       2 * (int64_t)sc.nnx * sc.nny, 2 * (int64_t)sc.nnx * sc.nny,

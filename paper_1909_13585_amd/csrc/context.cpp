@@ -654,7 +654,7 @@ int build_hierarchy(mlb_ctx* c) {
         Level& lc = c->lv[j - 1];
         if (j == 2) launch_galerkin_from_E(dim, lf.g, lc.g, c->Ek, c->dMc, lc.Ke, c->st);
         else launch_galerkin_dense(dim, false, lf.g, lc.g, lf.Ke, c->dT, lc.Ke, c->st);
-        launch_assemble_nb(dim, lc.g, lc.Ke, lc.nmask, lc.A, lc.Af, lc.dinv, lc.dinvf, c->st);
+        launch_assemble_nb(dim, lc.g, lc.Ke, lc.nmask, lc.A, lc.Af, lc.dinv, lc.dinvf, true, c->st);
     }
     for (int j = 1; j < c->L; ++j) CHK(estimate_omega(c, j));
     if (c->L == 1) {
@@ -1351,7 +1351,7 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
         const int nn = 1 << dim, nde = dim << dim;
         if (!c->fineA) {
             CHK(dalloc(c, &c->fineA, (size_t)stencil_entries(dim, l1.g, false)));
-            CHK(dalloc(c, &c->fineAf, (size_t)stencil_entries(dim, l1.g, false)));
+            CHK(dalloc(c, &c->fineAf, (size_t)stencil_entries(dim, l1.g, false, true)));
             CHK(dalloc(c, &c->fineGs, (size_t)stencil_entries(dim, l1.g, true)));
             CHK(dalloc(c, &c->fineDinv, (size_t)n));
             CHK(dalloc(c, &c->fineDinvf, (size_t)n));
@@ -1364,7 +1364,7 @@ int do_buckling(mlb_ctx* c, int ref_case, int k, double tol_eig, mlb_eig_info* i
             return rge;
         }
         launch_fine_elem_mats(dim, l1.g, c->Ek, c->dK0, c->S, c->dHk, Ke, Ge, c->st);
-        launch_assemble_nb(dim, l1.g, Ke, l1.nmask, c->fineA, c->fineAf, c->fineDinv, c->fineDinvf, c->st);
+        launch_assemble_nb(dim, l1.g, Ke, l1.nmask, c->fineA, c->fineAf, c->fineDinv, c->fineDinvf, true, c->st);
         launch_assemble_nb_diag(dim, l1.g, Ge, l1.nmask, c->fineGs, c->st);
         const hipError_t es = hipStreamSynchronize(c->st);
         dfree(Ke);
@@ -1771,7 +1771,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
         if (j > 0) {
             CHK(dalloc(c, &l.Ke, (size_t)l.g.m * c->nde * c->nde));
             CHK(dalloc(c, &l.A, (size_t)stencil_entries(dim, l.g, false)));
-            CHK(dalloc(c, &l.Af, (size_t)stencil_entries(dim, l.g, false)));
+            CHK(dalloc(c, &l.Af, (size_t)stencil_entries(dim, l.g, false, true)));
         }
         if (j > 0 && j < c->ell) CHK(dalloc(c, &l.Ge, (size_t)l.g.m * c->nn * c->nn));
     }

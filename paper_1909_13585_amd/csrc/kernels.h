@@ -17,9 +17,12 @@ void launch_dinv_fine(int dim, const Geo& g, const double* E, const uint8_t* nma
                       double* dinv, float* dinvf, hipStream_t st);
 
 // ---- assembled node-block stencils and transfers (kernels_stencil.hip)
-int64_t stencil_entries(int dim, const Geo& g, bool diag);
+// entries of a node-block stencil (half: the FP32 copy of K's, blocks nb <= NB/2)
+int64_t stencil_entries(int dim, const Geo& g, bool diag, bool half = false);
+// af_half: the FP32 copy Af keeps only the blocks nb <= NB/2 (what
+// launch_apply_nb<float> reads); otherwise Af is the full stencil
 void launch_assemble_nb(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, double* A, float* Af,
-                        double* dinv, float* dinvf, hipStream_t st);
+                        double* dinv, float* dinvf, bool af_half, hipStream_t st);
 // One Kaczmarz sweep for (K + sigma G) x = 0 on every column of X (a
 // Galerkin level: K full node-block stencil, Gd block-diagonal stencil), rows
 // in colour order (i mod 3) + 3 (j mod 3) + 9 (k mod 3); Dirichlet rows skipped.

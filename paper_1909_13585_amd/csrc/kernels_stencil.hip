@@ -13,10 +13,17 @@
 // grid are zero, so the apply clamps their addresses and reads no masks.
 // The stored level-2 stencil of K is half the size of the element matrices
 // it is summed from (3^3 x 9 vs 2^3 x 72 doubles per node).
+// The FP32 copy of K's stencil that the mixed-precision cycle reads
+// (assembled with af_half) keeps only the blocks nb <= NB/2 (the centre and the neighbours that come first
+// in the node order): the operator is symmetric, so block nb > NB/2 of a node
+// is the transpose of block NB-1-nb of that neighbour, and the apply reads
+// it there.  That stores and streams 14 of 27 blocks (3D) per node.
 //
-// Apply mapping: one thread per (node, component, column chunk); lanes run
-// over consecutive nodes (coalesced stencil loads, stride-dim vector loads
-// that hit the same cache lines).  Each XCD (blocks are dealt round robin
+// Apply mapping: one thread per (node, column chunk) over all components
+// (each stencil block and neighbour value loaded once for the node's rows),
+// or per (node, component, column chunk) for one-column and block-diagonal
+// calls, which need the threads; lanes run over consecutive nodes (coalesced
+// stencil loads, stride-dim vector loads that hit the same cache lines).  Each XCD (blocks are dealt round robin
 // over the 8 XCDs) works on one contiguous range of nodes with every
 // component and column chunk, so the x values they share come from one L2.
 #include "kernels.h"
@@ -71,7 +78,7 @@ template <int DIM>
 __global__ __launch_bounds__(kNbThreads) void k_assemble_nb(Geo g, const double* __restrict__ Ke,
                                                             const uint8_t* __restrict__ nmask, double* __restrict__ A,
                                                             float* __restrict__ Af, double* __restrict__ dinv,
-                                                            float* __restrict__ dinvf) {
+                                                            float* __restrict__ dinvf, bool af_half) {
     using S = Sten<DIM>;
     const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
@@ -109,7 +116,7 @@ __global__ __launch_bounds__(kNbThreads) void k_assemble_nb(Geo g, const double*
         for (int c2 = 0; c2 < DIM; ++c2) {
             const int64_t at = (int64_t)((nb * DIM + c) * DIM + c2) * N + node;
             A[at] = s[c2];
-            Af[at] = (float)s[c2];
+            if (!af_half || nb <= S::NB / 2) Af[at] = (float)s[c2];
         }
     }
     const double v = own_fixed ? 1.0 : (diag > 0.0 ? 1.0 / diag : 0.0);
@@ -178,6 +185,8 @@ __global__ __launch_bounds__(kNbThreads) void k_apply_nb(Geo g, int64_t nblk_nod
     // is loaded once for the node's rows and all columns.  Every output sums
     // the same terms in the same order either way.
     using S = Sten<DIM>;
+    // FP32 operator stencils are stored by half (see the top of this file)
+    constexpr bool HALF = sizeof(T) == 4 && !DIAG;
     int64_t nbk;
     int grp;
     if (!xcd_decode(nblk_nodes, SPLITC ? DIM * nchunks : nchunks, nbk, grp)) return;
@@ -214,7 +223,10 @@ __global__ __launch_bounds__(kNbThreads) void k_apply_nb(Geo g, int64_t nblk_nod
                     } else {
                         T a[DIM];
 #pragma unroll
-                        for (int c2 = 0; c2 < DIM; ++c2) a[c2] = A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node];
+                        for (int c2 = 0; c2 < DIM; ++c2)
+                            a[c2] = !HALF || nb <= S::NB / 2
+                                        ? A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node]
+                                        : (ok ? A[(int64_t)(((S::NB - 1 - nb) * DIM + c2) * DIM + c) * N + nbn] : T(0));
 #pragma unroll
                         for (int q = 0; q < CB; ++q)
                             if (q < nq)
@@ -261,7 +273,10 @@ __global__ __launch_bounds__(kNbThreads) void k_apply_nb(Geo g, int64_t nblk_nod
 #pragma unroll
                         for (int c2 = 0; c2 < DIM; ++c2)
                             a[c][c2] = DIAG ? (c2 == c ? A[(int64_t)(nb * DIM + c) * N + node] : T(0))
-                                            : A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node];
+                                       : !HALF || nb <= S::NB / 2
+                                           ? A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node]
+                                           : (ok ? A[(int64_t)(((S::NB - 1 - nb) * DIM + c2) * DIM + c) * N + nbn]
+                                                 : T(0));
 #pragma unroll
                     for (int q = 0; q < CB; ++q) {
                         if (q >= nq) break;
@@ -299,65 +314,76 @@ __global__ __launch_bounds__(kNbThreads) void k_apply_nb(Geo g, int64_t nblk_nod
 
 // ---------------------------------------------------------------------------
 // transfers: nodal (bi/tri)linear interpolation P and its transpose, masked
-// on both sides.  Thread per (DOF, column): consecutive threads take
-// consecutive DOFs of one column, so the fine-side (prolongation) and
-// coarse-side (restriction) vectors are read and written contiguously.
-
+// on both sides.  Thread per (node, column) over all DIM components: each
+// neighbour's mask and its DIM contiguous vector values are loaded once for
+// the node; consecutive threads take consecutive nodes of one column, so the
+// fine-side (prolongation) and coarse-side (restriction) vectors are read
+// and written contiguously.
 template <int DIM, typename T, bool ADD>
-__global__ __launch_bounds__(kNbThreads) void k_prolong_nb(Geo gf, Geo gc, int64_t nblk_dofs, int ncols,
+__global__ __launch_bounds__(kNbThreads) void k_prolong_nb(Geo gf, Geo gc, int64_t nblk_nodes, int ncols,
                                                            const uint8_t* __restrict__ mf,
-                                                           const uint8_t* __restrict__ mc, int64_t ldf, int64_t ldc,
-                                                           const T* __restrict__ xc, T* __restrict__ yf) {
+                                                           const uint8_t* __restrict__ mc, int64_t ldf,
+                                                           int64_t ldc, const T* __restrict__ xc,
+                                                           T* __restrict__ yf) {
     int64_t nbk;
     int col;
-    if (!xcd_decode(nblk_dofs, ncols, nbk, col)) return;
-    const int64_t dof = nbk * kNbThreads + threadIdx.x;
-    if (dof >= gf.nodes * DIM) return;
-    const int64_t node = dof / DIM;
-    const int c = (int)(dof - node * DIM);
+    if (!xcd_decode(nblk_nodes, ncols, nbk, col)) return;
+    const int64_t node = nbk * kNbThreads + threadIdx.x;
+    if (node >= gf.nodes) return;
     int i, j, k;
     node_ijk(gf, node, i, j, k);
-    const int64_t d = (int64_t)col * ldf + dof;
-    if ((mf[node] >> c) & 1) {
-        if (!ADD) yf[d] = T(0);
-        return;
-    }
+    const uint8_t fm = mf[node];
     const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
     const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
     const T* xcol = xc + (int64_t)col * ldc;
-    T acc = T(0);
-    for (int dk = 0; dk < nk; ++dk)
-        for (int dj = 0; dj < nj; ++dj)
-            for (int di = 0; di < ni; ++di) {
+    T acc[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) acc[c] = T(0);
+#pragma unroll
+    for (int dk = 0; dk < (DIM == 3 ? 2 : 1); ++dk)
+#pragma unroll
+        for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+            for (int di = 0; di < 2; ++di) {
+                if (di >= ni || dj >= nj || dk >= nk) continue;
                 const int64_t cn = (i0 + di) + (int64_t)gc.nnx * ((j0 + dj) + (int64_t)gc.nny * (k0 + dk));
-                const T v = xcol[cn * DIM + c];
-                acc += ((mc[cn] >> c) & 1) ? T(0) : v;
+                const uint8_t cm = mc[cn];
+                T v[DIM];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) v[c] = xcol[cn * DIM + c];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) acc[c] += ((cm >> c) & 1) ? T(0) : v[c];
             }
     const T w = T(1) / T(ni * nj * nk);
-    yf[d] = ADD ? yf[d] + w * acc : w * acc;
+    T* ycol = yf + (int64_t)col * ldf + node * DIM;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        if ((fm >> c) & 1) {
+            if (!ADD) ycol[c] = T(0);
+        } else {
+            ycol[c] = ADD ? ycol[c] + w * acc[c] : w * acc[c];
+        }
+    }
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(kNbThreads) void k_restrict_nb(Geo gf, Geo gc, int64_t nblk_dofs, int ncols,
+__global__ __launch_bounds__(kNbThreads) void k_restrict_nb(Geo gf, Geo gc, int64_t nblk_nodes, int ncols,
                                                             const uint8_t* __restrict__ mf,
-                                                            const uint8_t* __restrict__ mc, int64_t ldf, int64_t ldc,
-                                                            const T* __restrict__ xf, T* __restrict__ yc) {
+                                                            const uint8_t* __restrict__ mc, int64_t ldf,
+                                                            int64_t ldc, const T* __restrict__ xf,
+                                                            T* __restrict__ yc) {
     int64_t nbk;
     int col;
-    if (!xcd_decode(nblk_dofs, ncols, nbk, col)) return;
-    const int64_t cdof = nbk * kNbThreads + threadIdx.x;
-    if (cdof >= gc.nodes * DIM) return;
-    const int64_t cnode = cdof / DIM;
-    const int c = (int)(cdof - cnode * DIM);
+    if (!xcd_decode(nblk_nodes, ncols, nbk, col)) return;
+    const int64_t cnode = nbk * kNbThreads + threadIdx.x;
+    if (cnode >= gc.nodes) return;
     int I, J, K;
     node_ijk(gc, cnode, I, J, K);
-    const int64_t o = (int64_t)col * ldc + cdof;
-    if ((mc[cnode] >> c) & 1) {
-        yc[o] = T(0);
-        return;
-    }
+    const uint8_t cm = mc[cnode];
     const T* xcol = xf + (int64_t)col * ldf;
-    T acc = T(0);
+    T acc[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) acc[c] = T(0);
 #pragma unroll
     for (int dk = (DIM == 3 ? -1 : 0); dk <= (DIM == 3 ? 1 : 0); ++dk) {
         const int kk = 2 * K + dk;
@@ -374,23 +400,33 @@ __global__ __launch_bounds__(kNbThreads) void k_restrict_nb(Geo gf, Geo gc, int6
                 const bool ok = okj && ii >= 0 && ii < gf.nnx;
                 const T w = di == 0 ? wj : wj * T(0.5);
                 const int64_t fn = ok ? ii + (int64_t)gf.nnx * (jj + (int64_t)gf.nny * kk) : 0;
-                const T v = xcol[fn * DIM + c];
-                const bool use = ok && !((mf[fn] >> c) & 1);
-                acc += use ? w * v : T(0);
+                const uint8_t fmk = mf[fn];
+                T v[DIM];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) v[c] = xcol[fn * DIM + c];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    const bool use = ok && !((fmk >> c) & 1);
+                    acc[c] += use ? w * v[c] : T(0);
+                }
             }
         }
     }
-    yc[o] = acc;
+    T* ycol = yc + (int64_t)col * ldc + cnode * DIM;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) ycol[c] = ((cm >> c) & 1) ? T(0) : acc[c];
 }
 
 // ---------------------------------------------------------------------------
 // host launchers
 
 void launch_assemble_nb(int dim, const Geo& g, const double* Ke, const uint8_t* nmask, double* A, float* Af,
-                        double* dinv, float* dinvf, hipStream_t st) {
+                        double* dinv, float* dinvf, bool af_half, hipStream_t st) {
     const dim3 gr((unsigned)((g.nodes + kNbThreads - 1) / kNbThreads), dim, 1);
-    if (dim == 2) hipLaunchKernelGGL(k_assemble_nb<2>, gr, dim3(kNbThreads), 0, st, g, Ke, nmask, A, Af, dinv, dinvf);
-    else hipLaunchKernelGGL(k_assemble_nb<3>, gr, dim3(kNbThreads), 0, st, g, Ke, nmask, A, Af, dinv, dinvf);
+    if (dim == 2)
+        hipLaunchKernelGGL(k_assemble_nb<2>, gr, dim3(kNbThreads), 0, st, g, Ke, nmask, A, Af, dinv, dinvf, af_half);
+    else
+        hipLaunchKernelGGL(k_assemble_nb<3>, gr, dim3(kNbThreads), 0, st, g, Ke, nmask, A, Af, dinv, dinvf, af_half);
 }
 
 void launch_assemble_nb_diag(int dim, const Geo& g, const double* Ge, const uint8_t* nmask, double* A,
@@ -400,8 +436,8 @@ void launch_assemble_nb_diag(int dim, const Geo& g, const double* Ge, const uint
     else hipLaunchKernelGGL(k_assemble_nb_diag<3>, gr, dim3(kNbThreads), 0, st, g, Ge, nmask, A);
 }
 
-int64_t stencil_entries(int dim, const Geo& g, bool diag) {
-    const int nb = dim == 2 ? 9 : 27;
+int64_t stencil_entries(int dim, const Geo& g, bool diag, bool half) {
+    const int nb = dim == 2 ? (half ? 5 : 9) : (half ? 14 : 27);
     return (int64_t)nb * dim * (diag ? 1 : dim) * g.nodes;
 }
 
@@ -456,8 +492,8 @@ void launch_apply_nb(int dim, const Geo& g, const T* A, bool diag, int ncols, in
 template <typename T>
 void launch_prolong_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
                        int64_t ldf, int64_t ldc, const T* xc, T* yf, bool add, hipStream_t st) {
-    const int64_t nbn = (gf.nodes * dim + kNbThreads - 1) / kNbThreads;
-    const dim3 gr = xcd_grid(gf.nodes * dim, ncols);
+    const int64_t nbn = (gf.nodes + kNbThreads - 1) / kNbThreads;
+    const dim3 gr = xcd_grid(gf.nodes, ncols);
     const dim3 b(kNbThreads);
 #define MLB_P(D, AD) \
     hipLaunchKernelGGL((k_prolong_nb<D, T, AD>), gr, b, 0, st, gf, gc, nbn, ncols, mf, mc, ldf, ldc, xc, yf)
@@ -474,8 +510,8 @@ void launch_prolong_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf,
 template <typename T>
 void launch_restrict_nb(int dim, const Geo& gf, const Geo& gc, const uint8_t* mf, const uint8_t* mc, int ncols,
                         int64_t ldf, int64_t ldc, const T* xf, T* yc, hipStream_t st) {
-    const int64_t nbn = (gc.nodes * dim + kNbThreads - 1) / kNbThreads;
-    const dim3 gr = xcd_grid(gc.nodes * dim, ncols);
+    const int64_t nbn = (gc.nodes + kNbThreads - 1) / kNbThreads;
+    const dim3 gr = xcd_grid(gc.nodes, ncols);
     const dim3 b(kNbThreads);
     if (dim == 2)
         hipLaunchKernelGGL((k_restrict_nb<2, T>), gr, b, 0, st, gf, gc, nbn, ncols, mf, mc, ldf, ldc, xf, yc);
