@@ -37,7 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # dispatch, from profiles/jacobi_sweep_h8_192x64x64_12col_fp32_hbm_counters.md;
 # reported only when the run tuned the same tile.
 SWEEP_TRAFFIC_BYTES = {(3, 6): (168196.71 * 1.99965 + 120368.36) * 1024,
-                       (0, 6): (169269.43 * 1.99976 + 118064.79) * 1024}
+                       (0, 6): (169269.43 * 1.99976 + 118064.79) * 1024,
+                       (0, 12): (160371.06 * 1.99964 + 118585.46) * 1024}
 
 
 def parse():
