@@ -100,6 +100,7 @@ struct mlb_ctx {
     // multiple of 64, identity pad), its block Gauss-Jordan work buffers and
     // the split-K partial products of the coarsest solve
     double* Ainv = nullptr;
+    double* Apk = nullptr;   // lower triangle of Ainv in packed 16 x 16 tiles
     int64_t nA = 0;
     int nsplit = 1;
     double *gjP = nullptr, *gjR = nullptr, *gjC = nullptr, *cpart = nullptr;
@@ -342,7 +343,7 @@ void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z) {
         if (c->L == 1) launch_jacobi0<T>(l.n, nc, l.n, l.dinv ? dinv_of<T>(l) : nullptr, (T)1.0, r, z, c->st);
         else
             for (int c0 = 0; c0 < nc; c0 += 32)   // the product takes up to 32 columns
-                launch_coarse_solve<T>(l.n, c->nA, std::min(32, nc - c0), l.n, c->Ainv, r + c0 * l.n, z + c0 * l.n,
+                launch_coarse_solve<T>(l.n, c->nA, std::min(32, nc - c0), l.n, c->Apk, r + c0 * l.n, z + c0 * l.n,
                                        c->nsplit, c->cpart, c->st);
         return;
     }
@@ -667,6 +668,7 @@ int build_hierarchy(mlb_ctx* c) {
         launch_assemble_dense(dim, lL.g, lL.Ke, lL.nmask, nL, N, c->Ainv, c->st);
         launch_pad_identity(nL, N, c->Ainv, c->st);
         launch_block_inverse(N, c->Ainv, c->gjP, c->gjR, c->gjC, c->st);
+        launch_pack_lower(N, c->Ainv, c->Apk, c->st);
     }
     CHK(sync(c));
     return MLB_OK;
@@ -826,14 +828,28 @@ static int svqb(int r0, const std::vector<double>& G, double drop, std::vector<d
     return r;
 }
 
+// out (sp x nc) = sign T C for T (sp x r) and C (r x nc), column-major.
+void fold_t(int sp, int r, int nc, const std::vector<double>& T, const std::vector<double>& Cr, double sign,
+            std::vector<double>& out) {
+    out.assign((size_t)sp * nc, 0.0);
+    for (int q = 0; q < nc; ++q)
+        for (int i = 0; i < sp; ++i) {
+            double a = 0.0;
+            for (int j = 0; j < r; ++j) a += T[i + (size_t)sp * j] * Cr[j + (size_t)r * q];
+            out[i + (size_t)sp * q] = sign * a;
+        }
+}
+
 // ---- Block PCG (O'Leary's block conjugate gradients, in the breakdown-free
 // form of Ji & Li: the search block is A-orthonormalised by SVQB every
 // iteration, so converged or linearly dependent directions drop out).
 // Per iteration, with Q = A P:
 //   [P^T Q, P^T R]     one Gram pass over P, Q, R
 //   T = svqb(P^T Q),  alpha = T^T P^T R                      (host, tiny)
-//   P <- P T, Q <- Q T, X += P alpha, R -= Q alpha, |R|^2   one fused pass
-//   Z = M R,  beta = -Q^T Z,  P <- Z + P beta,  Q = A P
+//   X += P (T alpha), R -= Q (T alpha), |R|^2                one fused pass
+//   Z = M R,  beta = -T^T Q^T Z,  P <- Z + P (T beta),  Q = A P
+// (the orthonormal block P T and its image Q T are never formed: T is
+// folded into the coefficients, so P and Q are only read by the updates)
 // All columns share one block Krylov space, which deflates the outlying
 // eigenvalues of M A for every right-hand side at once.
 int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it, bool use_x0, mlb_solve_info* info) {
@@ -889,7 +905,9 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
             const int r = svqb(sp, PQ, 1e-13, Tm);
             if (r < 0) return fail(c, MLB_EBREAKDOWN, "block CG: P^T K P is not a finite Gram matrix");
             if (r == 0) return fail(c, MLB_EBREAKDOWN, "block CG: search space collapsed");
-            // alpha = T^T (P^T R): r x nc
+            // The K-orthonormal search block is P T (r columns); it is never
+            // formed: its coefficients are folded into the small matrices.
+            // alpha = T^T (P^T R) (r x nc); X += P (T alpha), R -= Q (T alpha)
             Al.assign((size_t)r * nc, 0.0);
             for (int j = 0; j < r; ++j)
                 for (int q = 0; q < nc; ++q) {
@@ -897,17 +915,24 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
                     for (int i = 0; i < sp; ++i) a += Tm[i + (size_t)sp * j] * G[(size_t)sp * sp + i + (size_t)sp * q];
                     Al[j + (size_t)r * q] = a;
                 }
-            CHK(upload_cm2(c, c->cbuf, Tm, Al));
+            fold_t(sp, r, nc, Tm, Al, 1.0, Cm);
+            CHK(upload_cm(c, c->cbuf, Cm));
             const int nps = bcg_step_parts(n);
-            launch_bcg_step(n, sp, r, nc, c->cbuf, c->cbuf + Tm.size(), P, Q, X, c->R, c->part, c->st);
+            launch_bcg_step(n, sp, nc, c->cbuf, P, Q, X, c->R, c->part, c->st);
             launch_sum_parts(nc, nps, c->part, rr, c->st);
-            sp = r;
             CHK(check(&done));
             if (done) break;
-            // Z = M R; beta = -Q^T Z; P <- Z + P beta; Q = A P
+            // Z = M R; beta = -(Q T)^T Z (r x nc); P <- Z + P (T beta); Q = A P
             CHK(precondition(c, 1, nc, c->R, Z));
-            CHK(gram(c, n, sp, Q, n, nc, Z, n, Cm));
-            for (auto& v : Cm) v = -v;
+            CHK(gram(c, n, sp, Q, n, nc, Z, n, G));
+            Al.assign((size_t)r * nc, 0.0);
+            for (int j = 0; j < r; ++j)
+                for (int q = 0; q < nc; ++q) {
+                    double a = 0.0;
+                    for (int i = 0; i < sp; ++i) a += Tm[i + (size_t)sp * j] * G[i + (size_t)sp * q];
+                    Al[j + (size_t)r * q] = a;
+                }
+            fold_t(sp, r, nc, Tm, Al, -1.0, Cm);
             CHK(upload_cm(c, c->cbuf, Cm));
             launch_bcg_dir(n, sp, nc, c->cbuf, Z, P, c->st);
             sp = nc;
@@ -1787,6 +1812,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
         c->nA = coarse_pad(nL);
         c->nsplit = coarse_splits(c->nA);
         CHK(dalloc(c, &c->Ainv, (size_t)c->nA * c->nA));
+        CHK(dalloc(c, &c->Apk, (size_t)packed_lower_doubles(c->nA)));
         CHK(dalloc(c, &c->gjP, (size_t)64 * 64));
         CHK(dalloc(c, &c->gjR, (size_t)64 * c->nA));
         CHK(dalloc(c, &c->gjC, (size_t)64 * c->nA));
@@ -1823,7 +1849,7 @@ void mlb_destroy(mlb_ctx* c) {
     }
     dfree(c->dK0); dfree(c->fK0); dfree(c->dHk); dfree(c->dBc); dfree(c->dD0Bc); dfree(c->dD0); dfree(c->dT);
     dfree(c->dMc); dfree(c->dGHc); dfree(c->x); dfree(c->Ek); dfree(c->Ekf); dfree(c->Es); dfree(c->fixed);
-    dfree(c->F); dfree(c->U); dfree(c->S); dfree(c->Ainv); dfree(c->gjP); dfree(c->gjR);
+    dfree(c->F); dfree(c->U); dfree(c->S); dfree(c->Ainv); dfree(c->Apk); dfree(c->gjP); dfree(c->gjR);
     dfree(c->gjC); dfree(c->cpart); dfree(c->R); dfree(c->Zb); dfree(c->Pb); dfree(c->Qb); dfree(c->Zo);
     dfree(c->X1); dfree(c->X2); dfree(c->Phi); dfree(c->Zadj); dfree(c->dlam_l); dfree(c->eS); dfree(c->eK);
     dfree(c->eA); dfree(c->eT); dfree(c->eTK); dfree(c->eTA); dfree(c->eR); dfree(c->eP); dfree(c->ePK); dfree(c->ePA); dfree(c->part); dfree(c->pidx);

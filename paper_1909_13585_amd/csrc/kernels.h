@@ -78,8 +78,13 @@ int64_t coarse_stage_doubles(int64_t N);
 void launch_gemm_f64(int M, int N, int K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                      double beta, double* C, int64_t ldc, hipStream_t st);
 void launch_block_inverse(int64_t N, double* A, double* P, double* R, double* Cp, hipStream_t st);
+// the lower triangle of a symmetric N x N row-major matrix as packed 16 x 16
+// tiles (tile (R, C), R >= C, row-major at (R (R + 1) / 2 + C) 256)
+int64_t packed_lower_doubles(int64_t N);
+void launch_pack_lower(int64_t N, const double* A, double* Apk, hipStream_t st);
+// z = A x for the packed symmetric A (up to 32 columns)
 template <typename T>
-void launch_coarse_solve(int64_t n, int64_t N, int nc, int64_t ld, const double* A, const T* x, T* z, int nsplit,
+void launch_coarse_solve(int64_t n, int64_t N, int nc, int64_t ld, const double* Apk, const T* x, T* z, int nsplit,
                          double* part, hipStream_t st);
 
 // ---- vector kernels (kernels_blas.hip)
@@ -117,10 +122,10 @@ int launch_gram(int64_t n, int k1, int64_t lda, const double* A, int k2a, int64_
                 int64_t ldb2, const double* B2, int nparts, double* part, double* out, hipStream_t st);
 // out (k2 x k1, column-major) = sign G^T for G (k1 x k2, column-major)
 void launch_gram_transpose(int k1, int k2, double sign, const double* G, double* out, hipStream_t st);
-// block CG row updates (sp, r, nc <= 32)
+// block CG row updates (sp, nc <= 32)
 int bcg_step_parts(int64_t n);
-void launch_bcg_step(int64_t n, int sp, int r, int nc, const double* T, const double* alpha, double* P, double* Q,
-                     double* X, double* R, double* rr_part, hipStream_t st);
+void launch_bcg_step(int64_t n, int sp, int nc, const double* alpha, const double* P, const double* Q, double* X,
+                     double* R, double* rr_part, hipStream_t st);
 void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const double* Z, double* P, hipStream_t st);
 // Y = alpha Y + [A1 A2] C (k1a + k1b <= 96, k2 <= 32; Y disjoint from A1, A2)
 void launch_gemm_cat(int64_t n, int k1a, int64_t lda1, const double* A1, int k1b, int64_t lda2, const double* A2,

@@ -358,73 +358,45 @@ __global__ __launch_bounds__(1024) void k_gram_reduce(int nout, int nparts, cons
 // matrices staged in LDS; rows are independent, so updates are in place).
 constexpr int kBcgMax = 32;
 
-// P <- P T, Q <- Q T (first r columns), X += P alpha, R -= Q alpha, and the
-// block partials of the column norms |R_q|^2.  MC bounds sp, r and nc.
+// X += P alpha, R -= Q alpha (P, Q: n x sp; alpha: sp x nc), and the block
+// partials of the column norms |R_q|^2.  MC bounds sp and nc.  The search
+// block's orthonormalising transform is folded into alpha by the caller, so
+// P and Q are only read.
 template <int MC>
-__global__ __launch_bounds__(256) void k_bcg_step(int64_t n, int sp, int r, int nc, const double* __restrict__ Tm,
-                                                  const double* __restrict__ alpha, double* __restrict__ P,
-                                                  double* __restrict__ Q, double* __restrict__ X,
-                                                  double* __restrict__ R, double* __restrict__ rr_part) {
-    __shared__ double sT[MC * MC];
+__global__ __launch_bounds__(256) void k_bcg_step(int64_t n, int sp, int nc, const double* __restrict__ alpha,
+                                                  const double* __restrict__ P, const double* __restrict__ Q,
+                                                  double* __restrict__ X, double* __restrict__ R,
+                                                  double* __restrict__ rr_part) {
     __shared__ double sA[MC * MC];
     __shared__ double sred[4][MC];
-    for (int e = threadIdx.x; e < sp * r; e += blockDim.x) sT[e] = Tm[e];
-    for (int e = threadIdx.x; e < r * nc; e += blockDim.x) sA[e] = alpha[e];
+    for (int e = threadIdx.x; e < sp * nc; e += blockDim.x) sA[e] = alpha[e];
     __syncthreads();
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool ok = i < n;
     const int64_t ii = ok ? i : 0;
-    double v[MC], w[MC];
+    double v[MC];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // P
 #pragma unroll
     for (int a = 0; a < MC; ++a) v[a] = a < sp ? P[a * n + ii] : 0.0;
-#pragma unroll
-    for (int j = 0; j < MC; ++j) {
-        double s = 0.0;
-        if (j < r)
-#pragma unroll
-            for (int a = 0; a < MC; ++a)
-                if (a < sp) s += v[a] * sT[a + sp * j];
-        w[j] = s;
-    }
-    if (ok)
-#pragma unroll
-        for (int j = 0; j < MC; ++j)
-            if (j < r) P[j * n + i] = w[j];
 #pragma unroll
     for (int q = 0; q < MC; ++q) {
         if (q >= nc) break;
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < MC; ++j)
-            if (j < r) s += w[j] * sA[j + r * q];
+        for (int a = 0; a < MC; ++a)
+            if (a < sp) s += v[a] * sA[a + sp * q];
         if (ok) X[q * n + i] += s;
     }
-    // Q
 #pragma unroll
     for (int a = 0; a < MC; ++a) v[a] = a < sp ? Q[a * n + ii] : 0.0;
-#pragma unroll
-    for (int j = 0; j < MC; ++j) {
-        double s = 0.0;
-        if (j < r)
-#pragma unroll
-            for (int a = 0; a < MC; ++a)
-                if (a < sp) s += v[a] * sT[a + sp * j];
-        w[j] = s;
-    }
-    if (ok)
-#pragma unroll
-        for (int j = 0; j < MC; ++j)
-            if (j < r) Q[j * n + i] = w[j];
     // R -= Q alpha with the wave sums of |R_q|^2 (fixed-order trees)
 #pragma unroll
     for (int q = 0; q < MC; ++q) {
         if (q >= nc) break;
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < MC; ++j)
-            if (j < r) s += w[j] * sA[j + r * q];
+        for (int a = 0; a < MC; ++a)
+            if (a < sp) s += v[a] * sA[a + sp * q];
         double e = 0.0;
         if (ok) {
             const double nr = R[q * n + i] - s;
@@ -759,10 +731,10 @@ int launch_gram(int64_t n, int k1, int64_t lda, const double* A, int k2a, int64_
     return 0;
 }
 
-void launch_bcg_step(int64_t n, int sp, int r, int nc, const double* T, const double* alpha, double* P, double* Q,
-                     double* X, double* R, double* rr_part, hipStream_t st) {
+void launch_bcg_step(int64_t n, int sp, int nc, const double* alpha, const double* P, const double* Q, double* X,
+                     double* R, double* rr_part, hipStream_t st) {
     const int mc = std::max(sp, nc);
-#define MLB_BS(M) hipLaunchKernelGGL(k_bcg_step<M>, dim3(nb1(n)), dim3(256), 0, st, n, sp, r, nc, T, alpha, P, Q, X, R, rr_part)
+#define MLB_BS(M) hipLaunchKernelGGL(k_bcg_step<M>, dim3(nb1(n)), dim3(256), 0, st, n, sp, nc, alpha, P, Q, X, R, rr_part)
     if (mc <= 4) MLB_BS(4);
     else if (mc <= 8) MLB_BS(8);
     else if (mc <= 12) MLB_BS(12);

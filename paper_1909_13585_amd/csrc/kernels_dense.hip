@@ -156,11 +156,32 @@ __global__ void k_coarse_stage(int64_t n, int64_t N, int nc, int64_t ld, const T
     Xt[t] = (k < n && c < nc) ? (double)x[c * ld + k] : 0.0;
 }
 
-// Partial products of Z = A X with A symmetric N x N (row-major) and X
-// staged k-major in Xt (N x 32), computed as Z^T = X^T A: wave (tile, split)
-// forms the 16 (or 32) columns x 16 rows of Z^T for rows j0 .. j0 + 15 over
-// its share of the K range, so every row of A is read by one wave per tile;
-// each operand load reads four full 128-byte lines, and the loop issues the
+// The symmetric inverse is read from its lower triangle only, stored as
+// 16 x 16 tiles: tile (R, C), R >= C, is row-major at (R (R + 1) / 2 + C) 256.
+// Half the bytes of the full matrix per coarsest solve; the operator applied
+// is exactly symmetric (the upper triangle of the computed inverse, equal to
+// the lower one up to rounding, is not used).
+__global__ void k_pack_lower(int64_t N, const double* __restrict__ A, double* __restrict__ Apk) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * N) return;
+    const int64_t row = t / N, col = t % N;
+    const int64_t R = row >> 4, C = col >> 4;
+    if (R < C) return;
+    Apk[(R * (R + 1) / 2 + C) * 256 + (row & 15) * 16 + (col & 15)] = A[t];
+}
+
+int64_t packed_lower_doubles(int64_t N) {
+    const int64_t T = N / 16;
+    return T * (T + 1) / 2 * 256;
+}
+
+// Partial products of Z = A X with A symmetric N x N (packed lower tiles)
+// and X staged k-major in Xt (N x 32), computed as Z^T = X^T A: wave (tile,
+// split) forms the 16 (or 32) columns x 16 rows of Z^T for rows
+// j0 .. j0 + 15 over its share of the K range.  A K-tile at or below the
+// diagonal is read as stored (each operand load: 512 contiguous bytes), one
+// above it as the transpose of the stored tile (J, K) (16 runs of 32 bytes,
+// the four loads of a K step covering the tile's 2 KB); the loop issues the
 // loads of four K steps before their products.  part[(split * 32 + c) * N + j].
 template <int NCT>
 __global__ __launch_bounds__(256) void k_coarse_part(int64_t N, const double* __restrict__ A,
@@ -179,12 +200,17 @@ __global__ __launch_bounds__(256) void k_coarse_part(int64_t N, const double* __
     v4d acc[NCT];
 #pragma unroll
     for (int t = 0; t < NCT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int64_t J = tile;
     for (int64_t k = kb; k < ke; k += 16) {   // N and kchunk are multiples of 16
+        const int64_t K = k >> 4;
+        const bool below = K >= J;   // wave-uniform
+        const double* At = A + (below ? K * (K + 1) / 2 + J : J * (J + 1) / 2 + K) * 256;
+        const int rs = below ? 16 : 1, cs = below ? 1 : 16;
         double b[4], a[4][NCT];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t kr = k + 4 * u + kl;
-            b[u] = A[kr * N + j0 + cl];
+            b[u] = At[(4 * u + kl) * rs + cl * cs];
 #pragma unroll
             for (int t = 0; t < NCT; ++t) a[u][t] = Xt[kr * 32 + 16 * t + cl];
         }
@@ -254,6 +280,10 @@ void launch_block_inverse(int64_t N, double* A, double* P, double* R, double* Cp
 }
 
 // part holds nsplit * 32 * N doubles followed by the N x 32 staging block
+void launch_pack_lower(int64_t N, const double* A, double* Apk, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_lower, dim3(nbk(N * N)), dim3(256), 0, st, N, A, Apk);
+}
+
 template <typename T>
 void launch_coarse_solve(int64_t n, int64_t N, int nc, int64_t ld, const double* A, const T* x, T* z, int nsplit,
                          double* part, hipStream_t st) {
