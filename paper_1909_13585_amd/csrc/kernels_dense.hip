@@ -157,17 +157,18 @@ __global__ void k_coarse_stage(int64_t n, int64_t N, int nc, int64_t ld, const T
 }
 
 // The symmetric inverse is read from its lower triangle only, stored as
-// 16 x 16 tiles: tile (R, C), R >= C, is row-major at (R (R + 1) / 2 + C) 256.
-// Half the bytes of the full matrix per coarsest solve; the operator applied
-// is exactly symmetric (the upper triangle of the computed inverse, equal to
-// the lower one up to rounding, is not used).
+// 16 x 16 tiles: tile (R, C), R >= C, at (R (R + 1) / 2 + C) 256, each tile
+// as four slabs of four columns (element (r, c) at (c / 4) 64 + 4 r + c % 4),
+// so that a K step reads a tile below the diagonal as four 128-byte runs and
+// one above it (the transpose of the stored tile) as one 512-byte run.  Half
+// the bytes of the full matrix per coarsest solve.
 __global__ void k_pack_lower(int64_t N, const double* __restrict__ A, double* __restrict__ Apk) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= N * N) return;
     const int64_t row = t / N, col = t % N;
     const int64_t R = row >> 4, C = col >> 4;
     if (R < C) return;
-    Apk[(R * (R + 1) / 2 + C) * 256 + (row & 15) * 16 + (col & 15)] = A[t];
+    Apk[(R * (R + 1) / 2 + C) * 256 + ((col & 15) >> 2) * 64 + (row & 15) * 4 + (col & 3)] = A[t];
 }
 
 int64_t packed_lower_doubles(int64_t N) {
@@ -179,10 +180,9 @@ int64_t packed_lower_doubles(int64_t N) {
 // and X staged k-major in Xt (N x 32), computed as Z^T = X^T A: wave (tile,
 // split) forms the 16 (or 32) columns x 16 rows of Z^T for rows
 // j0 .. j0 + 15 over its share of the K range.  A K-tile at or below the
-// diagonal is read as stored (each operand load: 512 contiguous bytes), one
-// above it as the transpose of the stored tile (J, K) (16 runs of 32 bytes,
-// the four loads of a K step covering the tile's 2 KB); the loop issues the
-// loads of four K steps before their products.  part[(split * 32 + c) * N + j].
+// diagonal is read as stored, one above it as the transpose of the stored
+// tile (J, K); the loop issues the loads of four K steps before their
+// products.  part[(split * 32 + c) * N + j].
 template <int NCT>
 __global__ __launch_bounds__(256) void k_coarse_part(int64_t N, const double* __restrict__ A,
                                                      const double* __restrict__ Xt, int nsplit,
@@ -205,12 +205,12 @@ __global__ __launch_bounds__(256) void k_coarse_part(int64_t N, const double* __
         const int64_t K = k >> 4;
         const bool below = K >= J;   // wave-uniform
         const double* At = A + (below ? K * (K + 1) / 2 + J : J * (J + 1) / 2 + K) * 256;
-        const int rs = below ? 16 : 1, cs = below ? 1 : 16;
         double b[4], a[4][NCT];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t kr = k + 4 * u + kl;
-            b[u] = At[(4 * u + kl) * rs + cl * cs];
+            // element (kr, j0 + cl): stored (4 u + kl, cl) below, (cl, 4 u + kl) above
+            b[u] = At[below ? (cl >> 2) * 64 + (4 * u + kl) * 4 + (cl & 3) : u * 64 + cl * 4 + kl];
 #pragma unroll
             for (int t = 0; t < NCT; ++t) a[u][t] = Xt[kr * 32 + 16 * t + cl];
         }
