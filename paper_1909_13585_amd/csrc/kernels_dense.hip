@@ -38,6 +38,18 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double al
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    // C is read before the products, so its loads overlap them (the rank-64
+    // updates of the inverse are bound by streaming C in and out)
+    v4d cv[2][2];
+    if (beta != 0.0) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    cv[a][b][r] = C[(r0 + wr + 16 * a + (lane >> 4) + 4 * r) * ldc + c0 + wc + 16 * b + (lane & 15)];
+    }
     for (int k0 = 0; k0 < K; k0 += kGK) {
         // 1024 entries of each slice, 4 per thread, coalesced along rows
 #pragma unroll
@@ -72,8 +84,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double al
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = r0 + wr + 16 * a + (lane >> 4) + 4 * r;
                 const int64_t col = c0 + wc + 16 * b + (lane & 15);
-                double* p = C + row * ldc + col;
-                *p = beta == 0.0 ? alpha * acc[a][b][r] : fma(alpha, acc[a][b][r], beta * *p);
+                C[row * ldc + col] = beta == 0.0 ? alpha * acc[a][b][r] : fma(alpha, acc[a][b][r], beta * cv[a][b][r]);
             }
 }
 
