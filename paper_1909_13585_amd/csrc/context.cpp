@@ -61,6 +61,8 @@ struct mlb_ctx {
     int dim = 0, nn = 0, nde = 0, nv = 0, L = 1, ell = 1;
     hipStream_t own = nullptr, st = nullptr;
     hipStream_t cap = nullptr;   // capture stream for the preconditioner graphs
+    hipStream_t aux = nullptr;   // second stream of the coarsest-level inversion
+    hipEvent_t aux_ev[2] = {nullptr, nullptr};
     struct Graph {
         int j, nc;
         const void* r;
@@ -667,7 +669,12 @@ int build_hierarchy(mlb_ctx* c) {
         HIPC(hipMemsetAsync(c->Ainv, 0, sizeof(double) * N * N, c->st));
         launch_assemble_dense(dim, lL.g, lL.Ke, lL.nmask, nL, N, c->Ainv, c->st);
         launch_pad_identity(nL, N, c->Ainv, c->st);
-        launch_block_inverse(N, c->Ainv, c->gjP, c->gjR, c->gjC, c->st);
+        if (!c->aux) {
+            HIPC(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+            HIPC(hipEventCreateWithFlags(&c->aux_ev[0], hipEventDisableTiming));
+            HIPC(hipEventCreateWithFlags(&c->aux_ev[1], hipEventDisableTiming));
+        }
+        launch_block_inverse(N, c->Ainv, c->gjP, c->gjR, c->gjC, c->st, c->aux, c->aux_ev[0], c->aux_ev[1]);
         launch_pack_lower(N, c->Ainv, c->Apk, c->st);
     }
     CHK(sync(c));
@@ -1813,7 +1820,7 @@ int mlb_create(const mlb_desc* desc, mlb_ctx** out) {
         c->nsplit = coarse_splits(c->nA);
         CHK(dalloc(c, &c->Ainv, (size_t)c->nA * c->nA));
         CHK(dalloc(c, &c->Apk, (size_t)packed_lower_doubles(c->nA)));
-        CHK(dalloc(c, &c->gjP, (size_t)64 * 64));
+        CHK(dalloc(c, &c->gjP, (size_t)2 * 64 * 64));
         CHK(dalloc(c, &c->gjR, (size_t)64 * c->nA));
         CHK(dalloc(c, &c->gjC, (size_t)64 * c->nA));
         CHK(dalloc(c, &c->cpart, (size_t)c->nsplit * 32 * c->nA + (size_t)coarse_stage_doubles(c->nA)));
@@ -1860,6 +1867,9 @@ void mlb_destroy(mlb_ctx* c) {
     if (c->hup) (void)hipHostFree(c->hup);
     drop_graphs(c);
     if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
+    for (hipEvent_t e : c->aux_ev)
+        if (e) (void)hipEventDestroy(e);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
 }

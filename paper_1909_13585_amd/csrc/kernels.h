@@ -76,8 +76,11 @@ int coarse_pad(int64_t n);
 int coarse_splits(int64_t N);
 int64_t coarse_stage_doubles(int64_t N);
 void launch_gemm_f64(int M, int N, int K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
-                     double beta, double* C, int64_t ldc, hipStream_t st);
-void launch_block_inverse(int64_t N, double* A, double* P, double* R, double* Cp, hipStream_t st);
+                     double beta, double* C, int64_t ldc, hipStream_t st, int skip_r = -1, int skip_c = -1);
+// P: 2 x 64 x 64 doubles; st2 (with its two events) overlaps each diagonal
+// block inversion with the previous panel's update, or null for one stream
+void launch_block_inverse(int64_t N, double* A, double* P, double* R, double* Cp, hipStream_t st,
+                          hipStream_t st2 = nullptr, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr);
 // the lower triangle of a symmetric N x N row-major matrix as packed 16 x 16
 // tiles (tile (R, C), R >= C, row-major at (R (R + 1) / 2 + C) 256)
 int64_t packed_lower_doubles(int64_t N);

@@ -25,11 +25,13 @@ __device__ inline v4d mfma16x16x4(double a, double b, v4d c) {
 // stream through LDS in 16-deep slices.  beta == 0 never reads C.
 constexpr int kGT = 64;   // tile edge
 constexpr int kGK = 16;   // K slice
+// Tile (skip_r, skip_c) of C, if any, is left untouched.
 __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double alpha, const double* __restrict__ A,
                                                   int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
-                                                  double* __restrict__ C, int64_t ldc) {
+                                                  double* __restrict__ C, int64_t ldc, int skip_r, int skip_c) {
     __shared__ double As[kGT * kGK];   // [row][k]
     __shared__ double Bs[kGK * kGT];   // [k][col]
+    if ((int)blockIdx.y == skip_r && (int)blockIdx.x == skip_c) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t r0 = (int64_t)blockIdx.y * kGT, c0 = (int64_t)blockIdx.x * kGT;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
@@ -265,27 +267,53 @@ int coarse_splits(int64_t N) {
 int64_t coarse_stage_doubles(int64_t N) { return N * 32; }
 
 void launch_gemm_f64(int M, int N, int K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
-                     double beta, double* C, int64_t ldc, hipStream_t st) {
+                     double beta, double* C, int64_t ldc, hipStream_t st, int skip_r, int skip_c) {
     hipLaunchKernelGGL(k_gemm_f64, dim3(N / kGT, M / kGT), dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                       ldc);
+                       ldc, skip_r, skip_c);
 }
 
 // In-place inverse of the N x N SPD matrix A (N a multiple of 64; pad with an
 // identity block) by 64-wide panels: P = A_KK^-1, R = P A_K:, C = A_:K,
 // A -= C R, A_:K = -C P, A_K: = R, A_KK = P; then A = (A + A^T) / 2.
 // Work: P (64 x 64), R (64 x N), C (N x 64), all device.
-void launch_block_inverse(int64_t N, double* A, double* P, double* R, double* Cp, hipStream_t st) {
+// Panel k: P_k = inverse of the diagonal block (k, k); R = P_k A[k rows];
+// A -= A[:, k cols] R; A[:, k cols] = -A[:, k cols] P_k; A[k rows] = R;
+// block (k, k) = P_k.  With a second stream the next diagonal block is
+// updated first and inverted there while the rest of the rank-64 update runs
+// (P double-buffered: 2 x 64 x 64); the results are the same either way.
+void launch_block_inverse(int64_t N, double* A, double* P, double* R, double* Cp, hipStream_t st, hipStream_t st2,
+                          hipEvent_t ev_a, hipEvent_t ev_b) {
     const int n = (int)N;
-    for (int64_t k0 = 0; k0 < N; k0 += kGT) {
-        hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, st, A, N, k0, P);
-        launch_gemm_f64(kGT, n, kGT, 1.0, P, kGT, A + k0 * N, N, 0.0, R, N, st);
+    const int64_t nk = N / kGT;
+    auto pbuf = [&](int64_t kb) { return P + (kb & 1) * kGT * kGT; };
+    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, st, A, N, (int64_t)0, pbuf(0));
+    for (int64_t kb = 0; kb < nk; ++kb) {
+        const int64_t k0 = kb * kGT, k1 = k0 + kGT;
+        double* Pk = pbuf(kb);
+        const bool more = kb + 1 < nk, ahead = more && st2;
+        launch_gemm_f64(kGT, n, kGT, 1.0, Pk, kGT, A + k0 * N, N, 0.0, R, N, st);
         hipLaunchKernelGGL(k_copy_block, dim3(nbk(N * kGT)), dim3(256), 0, st, N, (int64_t)kGT, A + k0, N, Cp,
                            (int64_t)kGT);
-        launch_gemm_f64(n, n, kGT, -1.0, Cp, kGT, R, N, 1.0, A, N, st);
-        launch_gemm_f64(n, kGT, kGT, -1.0, Cp, kGT, P, kGT, 0.0, A + k0, N, st);
+        if (ahead) {
+            // block (k + 1, k + 1) gets its update now (the same tile
+            // product as in the full update) and is inverted on st2
+            launch_gemm_f64(kGT, kGT, kGT, -1.0, Cp + k1 * kGT, kGT, R + k1, N, 1.0, A + k1 * N + k1, N, st);
+            (void)hipEventRecord(ev_a, st);
+            (void)hipStreamWaitEvent(st2, ev_a, 0);
+            hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, st2, A, N, k1, pbuf(kb + 1));
+            (void)hipEventRecord(ev_b, st2);
+            launch_gemm_f64(n, n, kGT, -1.0, Cp, kGT, R, N, 1.0, A, N, st, (int)(kb + 1), (int)(kb + 1));
+        } else {
+            launch_gemm_f64(n, n, kGT, -1.0, Cp, kGT, R, N, 1.0, A, N, st);
+        }
+        launch_gemm_f64(n, kGT, kGT, -1.0, Cp, kGT, Pk, kGT, 0.0, A + k0, N, st);
         hipLaunchKernelGGL(k_copy_block, dim3(nbk(kGT * N)), dim3(256), 0, st, (int64_t)kGT, N, R, N, A + k0 * N, N);
-        hipLaunchKernelGGL(k_copy_block, dim3(nbk(kGT * kGT)), dim3(256), 0, st, (int64_t)kGT, (int64_t)kGT, P,
+        hipLaunchKernelGGL(k_copy_block, dim3(nbk(kGT * kGT)), dim3(256), 0, st, (int64_t)kGT, (int64_t)kGT, Pk,
                            (int64_t)kGT, A + k0 * N + k0, N);
+        if (ahead)
+            (void)hipStreamWaitEvent(st, ev_b, 0);
+        else if (more)
+            hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, st, A, N, k1, pbuf(kb + 1));
     }
     hipLaunchKernelGGL(k_symmetrize, dim3(nbk(N * N)), dim3(256), 0, st, N, A);
 }
