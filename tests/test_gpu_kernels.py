@@ -163,3 +163,35 @@ def test_coarsest_solve_is_exact_inverse(nel, L, ncols, precision):
             assert rel_inf(Z[:, q], Zo[:, q]) < 1e-4, q
     assert np.all(Z[~freeL] == 0)
     c.close()
+
+
+@pytest.mark.parametrize("nel,L", [((52, 20), 3), ((20, 12, 8), 3), ((24, 16, 16), 4)])
+def test_mixed_vcycle_matches_fp64_vcycle(nel, L):
+    # The mixed-precision cycle runs the same smoother, transfers and coarsest
+    # solve as the FP64 one, in FP32 on the Galerkin levels from the half-stored
+    # FP32 stencils (a node's trailing neighbour blocks read as the transposes
+    # of the neighbours' leading ones).  With the same Jacobi weights the two
+    # cycles agree to FP32 rounding; a wrong or misplaced block would not.
+    print(f"case mixed vcycle nel={nel} L={L}", flush=True)
+    dim = len(nel)
+    x = W.random_small(dim, nel, 43)
+    fixed = W.clamp_mask(nel)
+    c64 = _ctx(nel, L, x, fixed, precision=0)
+    c32 = _ctx(nel, L, x, fixed, precision=1)
+    c32.set_omegas(c64.get_omegas(L - 1))   # the smoothed levels 1 .. L-1
+    torch = __import__("torch")
+    n = c64.level_size(1)[0]
+    free = (fixed == 0)
+    R = W.random_vectors(n, 3, 44) * free[:, None]
+    out = []
+    for c in (c64, c32):
+        zd = torch.empty((3, n), dtype=torch.float64, device="cuda")
+        c.vcycle_dev(1, to_dev(R), zd)
+        torch.cuda.synchronize()
+        out.append(from_dev(zd))
+    for q in range(3):
+        err = rel_inf(out[1][:, q], out[0][:, q])
+        print(f"column {q}: mixed vs FP64 cycle {err:.2e}")
+        assert err < 1e-5, q
+    c64.close()
+    c32.close()
