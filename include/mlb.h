@@ -76,7 +76,7 @@ typedef struct mlb_ctx mlb_ctx;
 
 /* Result of mlb_autotune: the chosen tile parameters and the mean time (ms)
    of a Jacobi sweep for each candidate (z chunk 4, 6, 8, 10, 12; stencil
-   columns per thread 2, 3, 4, 6, 8; 3D fine-apply variant 0 = register tiles
+   columns per thread 2, 3, 4, 6, 12; 3D fine-apply variant 0 = register tiles
    of 8 x 8 element columns per wave prefetching the next node plane, 1 =
    16 x 16 tiles staged in LDS, 2 = register tiles without prefetch, 3 = the
    register tiles of variant 0 with each node plane transformed once, plane
@@ -101,6 +101,11 @@ typedef struct {
     float wht64_nopf_ms[5];
     float wht_v3_ms[5];
     float wht64_v3_ms[5];
+    /* score of candidate (variant v, z chunk i) at [5 v + i]: one
+       ncols-column plus one single-column sweep (ms); the chosen tile has
+       the smallest (3D: 4 variants; 2D: variant 0 only) */
+    float wht_score_ms[20];
+    float wht64_score_ms[20];
 } mlb_tune_info;
 
 /* Problem description (copied by mlb_create). */
@@ -300,9 +305,10 @@ int mlb_set_tiles(mlb_ctx* ctx, int wht_zchunk, int stencil_cols, int wht_varian
 int mlb_set_omegas(mlb_ctx* ctx, int nlevels, const double* omega);
 int mlb_get_omegas(const mlb_ctx* ctx, int nlevels, double* omega);
 /* Times Jacobi sweeps of ncols (<= 32) columns on the current hierarchy for
-   each candidate tile and keeps the fastest (needs mask and densities); the
-   3D fine apply keeps variant 3 unless another variant is more than 3 %
-   faster, since variant 3 is also the fastest on single columns. */
+   each candidate tile and keeps the fastest (needs mask and densities); a
+   fine-apply candidate is scored by one ncols-column sweep plus one
+   single-column sweep (the solvers run both about equally often), and the
+   times reported are the ncols-column ones. */
 int mlb_autotune(mlb_ctx* ctx, int ncols, mlb_tune_info* info, void* stream);
 
 /* Warm starts.  kind MLB_WARM_COARSE: `data` holds ncols start vectors of

@@ -64,7 +64,8 @@ class MlbTuneInfo(C.Structure):
                 ("stencil_ms", C.c_float * 5), ("wht_variant", C.c_int), ("wht_lds_ms", C.c_float * 5),
                 ("wht_nopf_ms", C.c_float * 5), ("wht64_zchunk", C.c_int), ("wht64_variant", C.c_int),
                 ("wht64_ms", C.c_float * 5), ("wht64_lds_ms", C.c_float * 5), ("wht64_nopf_ms", C.c_float * 5),
-                ("wht_v3_ms", C.c_float * 5), ("wht64_v3_ms", C.c_float * 5)]
+                ("wht_v3_ms", C.c_float * 5), ("wht64_v3_ms", C.c_float * 5), ("wht_score_ms", C.c_float * 20),
+                ("wht64_score_ms", C.c_float * 20)]
 
 
 class MlbBatchDesc(C.Structure):

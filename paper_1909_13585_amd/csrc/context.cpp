@@ -1640,7 +1640,7 @@ template <typename T>
 // operator of the outer solvers in mixed precision), and keeps the fastest;
 // with `stencils`, also the stencil applies of level 2.
 int autotune_t(mlb_ctx* c, int ncols, bool stencils, int mode, int* zout, int* vout, float* ms_reg, float* ms_lds,
-               float* ms_nopf, float* ms_v3) {
+               float* ms_nopf, float* ms_v3, float* score) {
     Level& l1 = c->lv[0];
     T* x = lbuf<T>(l1, 1);
     T* y = lbuf<T>(l1, 2);
@@ -1656,24 +1656,20 @@ int autotune_t(mlb_ctx* c, int ncols, bool stencils, int mode, int* zout, int* v
     float best = 1e30f;
     int bz = c->wz[tix<T>()], bv = c->wv[tix<T>()];
     const int nvar = c->dim == 3 ? 4 : 1;
+    // The solvers run the fine apply on single columns (static CG) about as
+    // often as on the ncols-column blocks (block solves), so each candidate
+    // is scored by one sweep of each; the reported times are the block's.
     for (int v = 0; v < nvar; ++v)
         for (int i = 0; i < 5; ++i) {
             c->wz[tix<T>()] = zc[i];
             c->wv[tix<T>()] = v;
-            float ms = 0.f;
+            float ms = 0.f, ms1 = 0.f;
             CHK(time_ms(c, 5, [&] { apply_K<T>(c, 1, ncols, x, y, mode, r, nullptr); }, &ms));
+            if (ncols > 1) CHK(time_ms(c, 5, [&] { apply_K<T>(c, 1, 1, x, y, mode, r, nullptr); }, &ms1));
             (v == 0 ? ms_reg : v == 1 ? ms_lds : v == 2 ? ms_nopf : ms_v3)[i] = ms;
-            if (ms < best) best = ms, bz = zc[i], bv = v;
+            score[5 * v + i] = ms + ms1;
+            if (ms + ms1 < best) best = ms + ms1, bz = zc[i], bv = v;
         }
-    // Variant 3 is much the fastest on single columns (the solvers' residual
-    // and line-search products), which a sweep over ncols columns does not
-    // see; it stays unless another variant wins the sweep by more than 3 %.
-    if (nvar == 4 && bv != 3) {
-        int i3 = 0;
-        for (int i = 1; i < 5; ++i)
-            if (ms_v3[i] < ms_v3[i3]) i3 = i;
-        if (ms_v3[i3] <= 1.03f * best) bz = zc[i3], bv = 3;
-    }
     c->wz[tix<T>()] = bz;
     c->wv[tix<T>()] = bv;
     *zout = bz;
@@ -2369,12 +2365,12 @@ int mlb_autotune(mlb_ctx* c, int ncols, mlb_tune_info* info, void* stream) {
     mlb_tune_info t{};
     if (c->d.precision == MLB_MIXED) {
         CHK(autotune_t<float>(c, ncols, true, kModeJacobi, &t.wht_zchunk, &t.wht_variant, t.wht_ms, t.wht_lds_ms,
-                              t.wht_nopf_ms, t.wht_v3_ms));
+                              t.wht_nopf_ms, t.wht_v3_ms, t.wht_score_ms));
         CHK(autotune_t<double>(c, ncols, false, kModeY, &t.wht64_zchunk, &t.wht64_variant, t.wht64_ms, t.wht64_lds_ms,
-                               t.wht64_nopf_ms, t.wht64_v3_ms));
+                               t.wht64_nopf_ms, t.wht64_v3_ms, t.wht64_score_ms));
     } else {
         CHK(autotune_t<double>(c, ncols, true, kModeJacobi, &t.wht_zchunk, &t.wht_variant, t.wht_ms, t.wht_lds_ms,
-                               t.wht_nopf_ms, t.wht_v3_ms));
+                               t.wht_nopf_ms, t.wht_v3_ms, t.wht_score_ms));
         t.wht64_zchunk = t.wht_zchunk;
         t.wht64_variant = t.wht_variant;
         for (int i = 0; i < 5; ++i) {
@@ -2383,6 +2379,7 @@ int mlb_autotune(mlb_ctx* c, int ncols, mlb_tune_info* info, void* stream) {
             t.wht64_nopf_ms[i] = t.wht_nopf_ms[i];
             t.wht64_v3_ms[i] = t.wht_v3_ms[i];
         }
+        for (int i = 0; i < 20; ++i) t.wht64_score_ms[i] = t.wht_score_ms[i];
     }
     t.stencil_cols = c->nb_cbmax;
     for (int i = 0; i < 5; ++i) t.stencil_ms[i] = c->tune_stencil_ms[i];
