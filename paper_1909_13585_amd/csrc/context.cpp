@@ -378,13 +378,15 @@ void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z) {
     // a now holds the result; by construction a == z
 }
 
-// z = M^-1 r at level j in FP64 or mixed precision (FP32 inside).
+// z = M^-1 r at level j in FP64 or mixed precision (FP32 inside).  In mixed
+// precision z == nullptr leaves the result in FP32 in the level's block fz
+// (for callers that read it directly).
 void precondition_eager(mlb_ctx* c, int j, int nc, const double* r, double* z) {
     Level& l = c->lv[j - 1];
     if (c->d.precision == MLB_MIXED) {
         launch_d2f(l.n, nc, l.n, r, l.fr, c->st);
         vcycle<float>(c, j, nc, l.fr, l.fz);
-        launch_f2d(l.n, nc, l.n, l.fz, z, c->st);
+        if (z) launch_f2d(l.n, nc, l.n, l.fz, z, c->st);
     } else {
         vcycle<double>(c, j, nc, r, z);
     }
@@ -459,6 +461,20 @@ int gram(mlb_ctx* c, int64_t n, int k1, const double* A, int64_t lda, int k2, co
     HIPC(hipMemcpyAsync(c->hpin, c->gbuf, sizeof(double) * k1 * kt, hipMemcpyDeviceToHost, c->st));
     CHK(sync(c));
     std::memcpy(G.data(), c->hpin, sizeof(double) * k1 * kt);
+    return MLB_OK;
+}
+
+// G = A^T B (k1 x k2) -> host, B in FP32 (n x k2, leading dimension n)
+int gram_f32b(mlb_ctx* c, int64_t n, int k1, const double* A, int k2, const float* B, std::vector<double>& G) {
+    if ((int64_t)k1 * k2 > 96 * 192) return fail(c, MLB_EINVAL, "Gram matrix larger than 96 x 192");
+    const int np = gram_parts(n, k1, k2);
+    CHK(ensure_part(c, (int64_t)np * k1 * k2));
+    if (launch_gram_f32b(n, k1, n, A, k2, n, B, np, c->part, c->gbuf, c->st) != 0)
+        return fail(c, MLB_EINVAL, "Gram operands wider than 192 columns");
+    G.resize((size_t)k1 * k2);
+    HIPC(hipMemcpyAsync(c->hpin, c->gbuf, sizeof(double) * k1 * k2, hipMemcpyDeviceToHost, c->st));
+    CHK(sync(c));
+    std::memcpy(G.data(), c->hpin, sizeof(double) * k1 * k2);
     return MLB_OK;
 }
 
@@ -929,9 +945,18 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
             launch_sum_parts(nc, nps, c->part, rr, c->st);
             CHK(check(&done));
             if (done) break;
-            // Z = M R; beta = -(Q T)^T Z (r x nc); P <- Z + P (T beta); Q = A P
-            CHK(precondition(c, 1, nc, c->R, Z));
-            CHK(gram(c, n, sp, Q, n, nc, Z, n, G));
+            // Z = M R; beta = -(Q T)^T Z (r x nc); P <- Z + P (T beta); Q = A P.
+            // In mixed precision Z stays in the cycle's FP32 block (read as
+            // doubles, exactly: no conversion pass).
+            const float* Zf = nullptr;
+            if (c->d.precision == MLB_MIXED) {
+                CHK(precondition(c, 1, nc, c->R, nullptr));
+                Zf = c->lv[0].fz;
+                CHK(gram_f32b(c, n, sp, Q, nc, Zf, G));
+            } else {
+                CHK(precondition(c, 1, nc, c->R, Z));
+                CHK(gram(c, n, sp, Q, n, nc, Z, n, G));
+            }
             Al.assign((size_t)r * nc, 0.0);
             for (int j = 0; j < r; ++j)
                 for (int q = 0; q < nc; ++q) {
@@ -941,7 +966,8 @@ int bpcg(mlb_ctx* c, const double* B, double* X, int nc, double tol, int max_it,
                 }
             fold_t(sp, r, nc, Tm, Al, -1.0, Cm);
             CHK(upload_cm(c, c->cbuf, Cm));
-            launch_bcg_dir(n, sp, nc, c->cbuf, Z, P, c->st);
+            if (Zf) launch_bcg_dir(n, sp, nc, c->cbuf, Zf, P, c->st);
+            else launch_bcg_dir(n, sp, nc, c->cbuf, Z, P, c->st);
             sp = nc;
             apply_K<double>(c, 1, nc, P, Q, kModeY, nullptr, nullptr);
         }

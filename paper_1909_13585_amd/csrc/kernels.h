@@ -123,6 +123,9 @@ void launch_axpy_cols(int64_t n, int ncols, int64_t ld, const double* coef, doub
 int gram_parts(int64_t n, int k1, int k2);
 int launch_gram(int64_t n, int k1, int64_t lda, const double* A, int k2a, int64_t ldb1, const double* B1, int k2b,
                 int64_t ldb2, const double* B2, int nparts, double* part, double* out, hipStream_t st);
+// the same with B in FP32 (one operand block, read as doubles)
+int launch_gram_f32b(int64_t n, int k1, int64_t lda, const double* A, int k2, int64_t ldb, const float* B, int nparts,
+                     double* part, double* out, hipStream_t st);
 // out (k2 x k1, column-major) = sign G^T for G (k1 x k2, column-major)
 void launch_gram_transpose(int k1, int k2, double sign, const double* G, double* out, hipStream_t st);
 // block CG row updates (sp, nc <= 32)
@@ -130,6 +133,7 @@ int bcg_step_parts(int64_t n);
 void launch_bcg_step(int64_t n, int sp, int nc, const double* alpha, const double* P, const double* Q, double* X,
                      double* R, double* rr_part, hipStream_t st);
 void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const double* Z, double* P, hipStream_t st);
+void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const float* Z, double* P, hipStream_t st);
 // Y = alpha Y + [A1 A2] C (k1a + k1b <= 96, k2 <= 32; Y disjoint from A1, A2)
 void launch_gemm_cat(int64_t n, int k1a, int64_t lda1, const double* A1, int k1b, int64_t lda2, const double* A2,
                      int k2, const double* C, double alpha, int64_t ldy, double* Y, hipStream_t st);

@@ -217,11 +217,11 @@ __global__ void k_axpy_cols(int64_t n, int ncols, int64_t ld, const double* __re
 constexpr int kGramThreads = 256;
 constexpr int kGramMaxCols = 192;   // k1 + k2a + k2b
 
-template <int TS>
+template <int TS, typename TB>
 __global__ __launch_bounds__(kGramThreads) void k_gram(int64_t n, int rows, int k1, int64_t lda,
                                                        const double* __restrict__ A, int k2a, int64_t ldb1,
-                                                       const double* __restrict__ B1, int k2b, int64_t ldb2,
-                                                       const double* __restrict__ B2, double* __restrict__ part) {
+                                                       const TB* __restrict__ B1, int k2b, int64_t ldb2,
+                                                       const TB* __restrict__ B2, double* __restrict__ part) {
     extern __shared__ double sm[];
     const int k2 = k2a + k2b;
     const int stride = rows + 1;            // padded column stride (bank spread)
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(int64_t n, int rows, int 
     // the current one is multiplied (when (k1 + k2) rows <= PF x 256)
     constexpr int PF = TS == 4 ? 12 : 1;
     const int tot = (k1 + k2) * rows;
-    const bool pf_ok = tot <= PF * kGramThreads;
+    const bool pf_ok = sizeof(TB) == 8 && tot <= PF * kGramThreads;
     double pv[PF];
     // rows divides the block size: a thread keeps its row r = t % rows and
     // takes columns c0, c0 + cstep, ...
@@ -261,9 +261,16 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(int64_t n, int rows, int 
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int cc = pc0 + q * pcs;
-            const double* src = cc < k1 ? A + cc * lda
-                                        : (cc - k1 < k2a ? B1 + (cc - k1) * ldb1 : B2 + (cc - k1 - k2a) * ldb2);
-            pv[q] = rok && cc < k1 + k2 ? src[row] : 0.0;
+            double v = 0.0;
+            if (rok && cc < k1 + k2) {
+                if (cc < k1) {
+                    v = A[cc * lda + row];
+                } else {
+                    const TB* src = cc - k1 < k2a ? B1 + (cc - k1) * ldb1 : B2 + (cc - k1 - k2a) * ldb2;
+                    v = (double)src[row];
+                }
+            }
+            pv[q] = v;
         }
     };
     if (pf_ok) fetch(blockIdx.x);
@@ -288,7 +295,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(int64_t n, int rows, int 
                 const int r = e % rows, cc = e / rows;
                 const int64_t row = r0 + r;
                 double v = 0.0;
-                if (row < n) v = cc < k2a ? B1[cc * ldb1 + row] : B2[(cc - k2a) * ldb2 + row];
+                if (row < n) v = cc < k2a ? (double)B1[cc * ldb1 + row] : (double)B2[(cc - k2a) * ldb2 + row];
                 sb[cc * stride + r] = v;
             }
             __syncthreads();
@@ -415,9 +422,9 @@ __global__ __launch_bounds__(256) void k_bcg_step(int64_t n, int sp, int nc, con
 }
 
 // P <- Z + P beta  (P: n x sp in, n x nc out; beta sp x nc).
-template <int MC>
+template <int MC, typename TZ>
 __global__ __launch_bounds__(256) void k_bcg_dir(int64_t n, int sp, int nc, const double* __restrict__ beta,
-                                                 const double* __restrict__ Z, double* __restrict__ P) {
+                                                 const TZ* __restrict__ Z, double* __restrict__ P) {
     __shared__ double sB[MC * MC];
     for (int e = threadIdx.x; e < sp * nc; e += blockDim.x) sB[e] = beta[e];
     __syncthreads();
@@ -429,7 +436,7 @@ __global__ __launch_bounds__(256) void k_bcg_dir(int64_t n, int sp, int nc, cons
 #pragma unroll
     for (int q = 0; q < MC; ++q) {
         if (q >= nc) break;
-        double s = Z[q * n + i];
+        double s = (double)Z[q * n + i];
 #pragma unroll
         for (int a = 0; a < MC; ++a)
             if (a < sp) s += v[a] * sB[a + sp * q];
@@ -713,22 +720,31 @@ int gram_parts(int64_t n, int k1, int k2) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(nslab, 1024));
 }
 
-int launch_gram(int64_t n, int k1, int64_t lda, const double* A, int k2a, int64_t ldb1, const double* B1, int k2b,
-                int64_t ldb2, const double* B2, int nparts, double* part, double* out, hipStream_t st) {
+template <typename TB>
+static int launch_gram_t(int64_t n, int k1, int64_t lda, const double* A, int k2a, int64_t ldb1, const TB* B1, int k2b,
+                         int64_t ldb2, const TB* B2, int nparts, double* part, double* out, hipStream_t st) {
     const int k2 = k2a + k2b;
     if (k1 < 1 || k2 < 1 || k1 + k2 > kGramMaxCols) return -1;
     const int rows = k1 + k2 > 120 ? 32 : 64;
     const size_t lds = std::max<size_t>((size_t)(k1 + k2) * (rows + 1), kGramThreads) * sizeof(double);
     const int t4 = ((k1 + 3) / 4) * ((k2 + 3) / 4);
     if (t4 <= kGramThreads)
-        hipLaunchKernelGGL(k_gram<4>, dim3(nparts), dim3(kGramThreads), lds, st, n, rows, k1, lda, A, k2a, ldb1, B1,
-                           k2b, ldb2, B2, part);
+        hipLaunchKernelGGL((k_gram<4, TB>), dim3(nparts), dim3(kGramThreads), lds, st, n, rows, k1, lda, A, k2a, ldb1,
+                           B1, k2b, ldb2, B2, part);
     else
-        hipLaunchKernelGGL(k_gram<6>, dim3(nparts), dim3(kGramThreads), lds, st, n, rows, k1, lda, A, k2a, ldb1, B1,
-                           k2b, ldb2, B2, part);
+        hipLaunchKernelGGL((k_gram<6, TB>), dim3(nparts), dim3(kGramThreads), lds, st, n, rows, k1, lda, A, k2a, ldb1,
+                           B1, k2b, ldb2, B2, part);
     const int nout = k1 * k2;
     hipLaunchKernelGGL(k_gram_reduce, dim3((nout + 63) / 64), dim3(1024), 0, st, nout, nparts, part, out);
     return 0;
+}
+int launch_gram(int64_t n, int k1, int64_t lda, const double* A, int k2a, int64_t ldb1, const double* B1, int k2b,
+                int64_t ldb2, const double* B2, int nparts, double* part, double* out, hipStream_t st) {
+    return launch_gram_t<double>(n, k1, lda, A, k2a, ldb1, B1, k2b, ldb2, B2, nparts, part, out, st);
+}
+int launch_gram_f32b(int64_t n, int k1, int64_t lda, const double* A, int k2, int64_t ldb, const float* B, int nparts,
+                     double* part, double* out, hipStream_t st) {
+    return launch_gram_t<float>(n, k1, lda, A, k2, ldb, B, 0, 0, (const float*)nullptr, nparts, part, out, st);
 }
 
 void launch_bcg_step(int64_t n, int sp, int nc, const double* alpha, const double* P, const double* Q, double* X,
@@ -746,9 +762,10 @@ void launch_bcg_step(int64_t n, int sp, int nc, const double* alpha, const doubl
 
 int bcg_step_parts(int64_t n) { return nb1(n); }
 
-void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const double* Z, double* P, hipStream_t st) {
+template <typename TZ>
+static void launch_bcg_dir_t(int64_t n, int sp, int nc, const double* beta, const TZ* Z, double* P, hipStream_t st) {
     const int mc = std::max(sp, nc);
-#define MLB_BD(M) hipLaunchKernelGGL(k_bcg_dir<M>, dim3(nb1(n)), dim3(256), 0, st, n, sp, nc, beta, Z, P)
+#define MLB_BD(M) hipLaunchKernelGGL((k_bcg_dir<M, TZ>), dim3(nb1(n)), dim3(256), 0, st, n, sp, nc, beta, Z, P)
     if (mc <= 4) MLB_BD(4);
     else if (mc <= 8) MLB_BD(8);
     else if (mc <= 12) MLB_BD(12);
@@ -756,6 +773,12 @@ void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const double*
     else if (mc <= 24) MLB_BD(24);
     else MLB_BD(32);
 #undef MLB_BD
+}
+void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const double* Z, double* P, hipStream_t st) {
+    launch_bcg_dir_t<double>(n, sp, nc, beta, Z, P, st);
+}
+void launch_bcg_dir(int64_t n, int sp, int nc, const double* beta, const float* Z, double* P, hipStream_t st) {
+    launch_bcg_dir_t<float>(n, sp, nc, beta, Z, P, st);
 }
 
 void launch_gemm_small(int64_t n, int k1, int64_t lds, const double* S, int k2, const double* C, int64_t ldy,
