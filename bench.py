@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # reported only when the run tuned the same tile.
 SWEEP_TRAFFIC_BYTES = {(3, 6): (168196.71 * 1.99965 + 120368.36) * 1024,
                        (0, 6): (169269.43 * 1.99976 + 118064.79) * 1024,
-                       (0, 12): (160371.06 * 1.99964 + 118585.46) * 1024}
+                       (0, 12): (160371.06 * 1.99964 + 118585.46) * 1024,
+                       (3, 12): (163089.49 * 1.99963 + 125806.16) * 1024}
 
 
 def parse():
