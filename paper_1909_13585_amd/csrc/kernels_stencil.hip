@@ -17,7 +17,9 @@
 // (assembled with af_half) keeps only the blocks nb <= NB/2 (the centre and the neighbours that come first
 // in the node order): the operator is symmetric, so block nb > NB/2 of a node
 // is the transpose of block NB-1-nb of that neighbour, and the apply reads
-// it there.  That stores and streams 14 of 27 blocks (3D) per node.
+// it there.  That stores and streams 14 of 27 blocks (3D) per node.  Its
+// blocks are node-major, Af[(nb * nodes + node) * dim^2 + c * dim + c2], so a
+// thread reads a block with a few wide loads.
 //
 // Apply mapping: one thread per (node, column chunk) over all components
 // (each stencil block and neighbour value loaded once for the node's rows),
@@ -116,7 +118,8 @@ __global__ __launch_bounds__(kNbThreads) void k_assemble_nb(Geo g, const double*
         for (int c2 = 0; c2 < DIM; ++c2) {
             const int64_t at = (int64_t)((nb * DIM + c) * DIM + c2) * N + node;
             A[at] = s[c2];
-            if (!af_half || nb <= S::NB / 2) Af[at] = (float)s[c2];
+            if (!af_half) Af[at] = (float)s[c2];
+            else if (nb <= S::NB / 2) Af[((int64_t)nb * N + node) * (DIM * DIM) + c * DIM + c2] = (float)s[c2];
         }
     }
     const double v = own_fixed ? 1.0 : (diag > 0.0 ? 1.0 / diag : 0.0);
@@ -185,20 +188,25 @@ __global__ __launch_bounds__(kNbThreads) void k_apply_nb(Geo g, int64_t nblk_nod
     // is loaded once for the node's rows and all columns.  Every output sums
     // the same terms in the same order either way.
     using S = Sten<DIM>;
-    // FP32 operator stencils are stored by half (see the top of this file)
+    // FP32 operator stencils are stored by half, node-major (see the top of
+    // this file); their one-component threads run DOF-major (lanes over the
+    // components of consecutive nodes, so a lane's stencil row is the next
+    // lane's neighbour in memory); nblk_nodes then counts blocks of DOFs
     constexpr bool HALF = sizeof(T) == 4 && !DIAG;
+    constexpr bool DOFS = SPLITC && HALF;
     int64_t nbk;
     int grp;
-    if (!xcd_decode(nblk_nodes, SPLITC ? DIM * nchunks : nchunks, nbk, grp)) return;
-    const int64_t node = nbk * kNbThreads + threadIdx.x;
+    if (!xcd_decode(nblk_nodes, SPLITC && !DOFS ? DIM * nchunks : nchunks, nbk, grp)) return;
+    const int64_t tix = nbk * kNbThreads + threadIdx.x;
+    const int64_t node = DOFS ? tix / DIM : tix;
     if (node >= g.nodes) return;
     int i, j, k;
     node_ijk(g, node, i, j, k);
     const int64_t N = g.nodes;
     const int64_t sy = g.nnx, sz = (int64_t)g.nnx * g.nny;
     if constexpr (SPLITC) {
-        const int c = grp % DIM;
-        const int c0 = (grp / DIM) * CB;
+        const int c = DOFS ? (int)(tix - node * DIM) : grp % DIM;
+        const int c0 = (DOFS ? grp : grp / DIM) * CB;
         const int nq = min(CB, ncols - c0);
         const T* xb = x + (int64_t)c0 * ld;
         T acc[CB];
@@ -224,9 +232,11 @@ __global__ __launch_bounds__(kNbThreads) void k_apply_nb(Geo g, int64_t nblk_nod
                         T a[DIM];
 #pragma unroll
                         for (int c2 = 0; c2 < DIM; ++c2)
-                            a[c2] = !HALF || nb <= S::NB / 2
-                                        ? A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node]
-                                        : (ok ? A[(int64_t)(((S::NB - 1 - nb) * DIM + c2) * DIM + c) * N + nbn] : T(0));
+                            a[c2] = !HALF ? A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node]
+                                    : nb <= S::NB / 2
+                                        ? A[((int64_t)nb * N + node) * (DIM * DIM) + c * DIM + c2]
+                                        : (ok ? A[((int64_t)(S::NB - 1 - nb) * N + nbn) * (DIM * DIM) + c2 * DIM + c]
+                                              : T(0));
 #pragma unroll
                         for (int q = 0; q < CB; ++q)
                             if (q < nq)
@@ -273,10 +283,17 @@ __global__ __launch_bounds__(kNbThreads) void k_apply_nb(Geo g, int64_t nblk_nod
 #pragma unroll
                         for (int c2 = 0; c2 < DIM; ++c2)
                             a[c][c2] = DIAG ? (c2 == c ? A[(int64_t)(nb * DIM + c) * N + node] : T(0))
-                                       : !HALF || nb <= S::NB / 2
-                                           ? A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node]
-                                           : (ok ? A[(int64_t)(((S::NB - 1 - nb) * DIM + c2) * DIM + c) * N + nbn]
-                                                 : T(0));
+                                       : !HALF ? A[(int64_t)((nb * DIM + c) * DIM + c2) * N + node]
+                                       : nb <= S::NB / 2
+                                           ? A[((int64_t)nb * N + node) * (DIM * DIM) + c * DIM + c2]
+                                           // unconditional (nbn is the node itself off the grid),
+                                           // so the block's loads merge; zero selected after
+                                           : A[((int64_t)(S::NB - 1 - nb) * N + nbn) * (DIM * DIM) + c2 * DIM + c];
+                    if (HALF && nb > S::NB / 2 && !ok)
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                            for (int c2 = 0; c2 < DIM; ++c2) a[c][c2] = T(0);
 #pragma unroll
                     for (int q = 0; q < CB; ++q) {
                         if (q >= nq) break;
@@ -453,14 +470,17 @@ void launch_apply_nb(int dim, const Geo& g, const T* A, bool diag, int ncols, in
     const int cb = want <= 1 ? 1 : want <= 2 ? 2 : want <= 3 ? 3 : want <= 4 ? 4 : want <= 6 ? 6 : want <= 8 ? 8 : 12;
     const int nchunks = (ncols + cb - 1) / cb;
     // one-column calls (and DIAG) keep a thread per component: enough threads
+    // (FP32 operator stencils: DOF-major threads, nbn counting DOF blocks)
     const bool split = ncols == 1 || diag;
-    const dim3 gr = xcd_grid(g.nodes, split ? dim * nchunks : nchunks);
+    const bool dofs = split && sizeof(T) == 4 && !diag;
+    const int64_t nbn_s = dofs ? (g.nodes * dim + kNbThreads - 1) / kNbThreads : nbn;
+    const dim3 gr = dofs ? xcd_grid(g.nodes * dim, nchunks) : xcd_grid(g.nodes, split ? dim * nchunks : nchunks);
     const dim3 b(kNbThreads);
 #define MLB_NB(D, M, C, DG)                                                                                         \
     do {                                                                                                            \
         if (split)                                                                                                  \
-            hipLaunchKernelGGL((k_apply_nb<D, T, M, C, DG, true>), gr, b, 0, st, g, nbn, nchunks, A, ncols, ld, x, \
-                               y, r, dinv, omega);                                                                  \
+            hipLaunchKernelGGL((k_apply_nb<D, T, M, C, DG, true>), gr, b, 0, st, g, nbn_s, nchunks, A, ncols, ld,  \
+                               x, y, r, dinv, omega);                                                               \
         else                                                                                                        \
             hipLaunchKernelGGL((k_apply_nb<D, T, M, C, DG, false>), gr, b, 0, st, g, nbn, nchunks, A, ncols, ld, x, \
                                y, r, dinv, omega);                                                                  \
