@@ -338,8 +338,10 @@ float* lbuf<float>(Level& l, int w) { return w == 0 ? l.fr : w == 1 ? l.fz : w =
 // One V(nu,nu)-cycle with damped Jacobi, symmetric (same sweeps before and
 // after, restriction = interpolation^T), so it is an SPD preconditioner.
 // r, z: level-j blocks with leading dimension n_j; z is overwritten.
+// first_done: the first sweep from zero (a = omega D^-1 r in the level's
+// block z2) was fused into the caller's conversion of r.
 template <typename T>
-void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z) {
+void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z, bool first_done = false) {
     Level& l = c->lv[j - 1];
     if (j == c->L) {
         if (c->L == 1) launch_jacobi0<T>(l.n, nc, l.n, l.dinv ? dinv_of<T>(l) : nullptr, (T)1.0, r, z, c->st);
@@ -354,7 +356,7 @@ void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z) {
     T* b = z;
     T* t = lbuf<T>(l, 3);
     // 2*nu - 1 Jacobi sweeps after the first: start in z2 so the result ends in z
-    launch_jacobi0<T>(l.n, nc, l.n, dinv_of<T>(l), (T)l.omega, r, a, c->st);
+    if (!first_done) launch_jacobi0<T>(l.n, nc, l.n, dinv_of<T>(l), (T)l.omega, r, a, c->st);
     for (int s = 1; s < nu; ++s) {
         apply_K<T>(c, j, nc, a, b, kModeJacobi, r, nullptr);
         std::swap(a, b);
@@ -384,8 +386,13 @@ void vcycle(mlb_ctx* c, int j, int nc, const T* r, T* z) {
 void precondition_eager(mlb_ctx* c, int j, int nc, const double* r, double* z) {
     Level& l = c->lv[j - 1];
     if (c->d.precision == MLB_MIXED) {
-        launch_d2f(l.n, nc, l.n, r, l.fr, c->st);
-        vcycle<float>(c, j, nc, l.fr, l.fz);
+        if (j < c->L) {   // the conversion and the first sweep from zero in one pass
+            launch_d2f_jacobi0(l.n, nc, l.n, r, l.dinvf, (float)l.omega, l.fr, lbuf<float>(l, 2), c->st);
+            vcycle<float>(c, j, nc, l.fr, l.fz, true);
+        } else {
+            launch_d2f(l.n, nc, l.n, r, l.fr, c->st);
+            vcycle<float>(c, j, nc, l.fr, l.fz);
+        }
         if (z) launch_f2d(l.n, nc, l.n, l.fz, z, c->st);
     } else {
         vcycle<double>(c, j, nc, r, z);

@@ -94,6 +94,8 @@ void launch_coarse_solve(int64_t n, int64_t N, int nc, int64_t ld, const double*
 template <typename T>
 void launch_jacobi0(int64_t n, int ncols, int64_t ld, const T* dinv, T omega, const T* r, T* z, hipStream_t st);
 void launch_d2f(int64_t n, int ncols, int64_t ld, const double* a, float* b, hipStream_t st);
+void launch_d2f_jacobi0(int64_t n, int ncols, int64_t ld, const double* a, const float* dinv, float omega, float* b,
+                        float* z, hipStream_t st);
 void launch_f2d(int64_t n, int ncols, int64_t ld, const float* a, double* b, hipStream_t st);
 int reduction_parts(int64_t n);
 void launch_dot_part(int64_t n, int ncols, int64_t lda, const double* a, int64_t ldb, const double* b,

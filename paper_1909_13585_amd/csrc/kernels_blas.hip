@@ -61,6 +61,22 @@ __global__ void k_jacobi0(int64_t n, int ncols, int64_t ld, const T* __restrict_
     for (int c = 0; c < ncols; ++c) z[c * ld + i] = d * r[c * ld + i];
 }
 
+// b = (float) a and z = (omega D^-1) b in one pass: the right-hand side of a
+// mixed-precision cycle and its first Jacobi sweep from zero (the same
+// products as k_d2f followed by k_jacobi0<float>)
+__global__ void k_d2f_jacobi0(int64_t n, int ncols, int64_t ld, const double* __restrict__ a,
+                              const float* __restrict__ dinv, float omega, float* __restrict__ b,
+                              float* __restrict__ z) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float d = omega * dinv[i];
+    for (int c = 0; c < ncols; ++c) {
+        const float v = (float)a[c * ld + i];
+        b[c * ld + i] = v;
+        z[c * ld + i] = d * v;
+    }
+}
+
 __global__ void k_d2f(int64_t n, int ncols, int64_t ld, const double* __restrict__ a, float* __restrict__ b) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -651,6 +667,10 @@ void launch_jacobi0(int64_t n, int ncols, int64_t ld, const T* dinv, T omega, co
 template void launch_jacobi0<double>(int64_t, int, int64_t, const double*, double, const double*, double*, hipStream_t);
 template void launch_jacobi0<float>(int64_t, int, int64_t, const float*, float, const float*, float*, hipStream_t);
 
+void launch_d2f_jacobi0(int64_t n, int ncols, int64_t ld, const double* a, const float* dinv, float omega, float* b,
+                        float* z, hipStream_t st) {
+    hipLaunchKernelGGL(k_d2f_jacobi0, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, a, dinv, omega, b, z);
+}
 void launch_d2f(int64_t n, int ncols, int64_t ld, const double* a, float* b, hipStream_t st) {
     hipLaunchKernelGGL(k_d2f, dim3(nb1(n)), dim3(kBlock), 0, st, n, ncols, ld, a, b);
 }
