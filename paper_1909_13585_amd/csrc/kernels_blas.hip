@@ -225,8 +225,9 @@ __global__ void k_axpy_cols(int64_t n, int ncols, int64_t ld, const double* __re
 // column-major).  Bandwidth-bound: every block streams slabs of `rows`
 // consecutive rows of all operands into LDS (coalesced, one wave per column),
 // then each thread accumulates a TS x TS tile of G over a strided subset of
-// the slab rows in registers.  Where the slab fits 12 values per thread, the
-// next slab is loaded into registers while the current one is multiplied.  Tiles x row-groups fill the 256 threads; the
+// the slab rows in registers.  Where the slab fits 12 values per thread (FP64
+// operands), the next slab is loaded into registers while the current one is
+// multiplied.  B may be FP32 (converted on load; exact).  Tiles x row-groups fill the 256 threads; the
 // row groups are summed through LDS in a fixed order at the end and every
 // block writes one partial G, reduced by k_gram_reduce in block order, so
 // the result is deterministic.
