@@ -40,6 +40,12 @@ SWEEP_TRAFFIC_BYTES = {(3, 6): (168196.71 * 1.99965 + 120368.36) * 1024,
                        (0, 6): (169269.43 * 1.99976 + 118064.79) * 1024,
                        (0, 12): (160371.06 * 1.99964 + 118585.46) * 1024,
                        (3, 12): (163089.49 * 1.99963 + 125806.16) * 1024}
+# wave-level VALU instructions per launch of the same sweep (rocprofv3
+# SQ_INSTS_VALU, profiles/jacobi_sweep_h8_192x64x64_12col_fp32_sq_counters.md):
+# at 4 cycles per FP32 wave instruction on 1,024 SIMDs at 2.4 GHz they set
+# the kernel's VALU ceiling, reported beside the HBM roofline.
+SWEEP_VALU_INSTS = {(3, 6): 56317728}
+VALU_CYCLES_PER_INST, SIMDS, CLOCK_HZ = 4, 1024, 2.4e9
 
 
 def parse():
@@ -463,6 +469,17 @@ def sweep_timing(ctx, level, ncols, reps):
     e1.record(st)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def valu_ceiling(tiles, word, sweep_ms):
+    """The fine sweep's VALU ceiling (ms) from its counted instructions, and
+    the fraction of it the timed sweep reaches (tuned tile with counters
+    only, else None)."""
+    insts = SWEEP_VALU_INSTS.get((tiles["wht_variant"], tiles["wht_zchunk"])) if tiles and word == 4 else None
+    if insts is None:
+        return None
+    ms = insts * VALU_CYCLES_PER_INST / (SIMDS * CLOCK_HZ) * 1e3
+    return {"valu_insts": insts, "ceiling_ms": ms, "frac": ms / sweep_ms}
 
 
 def sweep_bytes(dim, nel, level, ncols, word):
@@ -890,6 +907,7 @@ def main():
                      "achieved": b1 / (sw1 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": b1 / (sw1 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": SWEEP_TRAFFIC_BYTES.get((tiles["wht_variant"], tiles["wht_zchunk"])) if tiles and word == 4 else None,
                      "sweep_ms": sw1, "alg_bytes": b1, "launches_timed": args.sweep_reps,
+                     "valu_ceiling": valu_ceiling(tiles, word, sw1),
                      "level2_stencil_sweep": {"sweep_ms": sw2, "alg_bytes": b2,
                                               "achieved": b2 / (sw2 * 1e-3) / 1e9,
                                               "frac": b2 / (sw2 * 1e-3) / 1e9 / HBM_PEAK_GBS}},
