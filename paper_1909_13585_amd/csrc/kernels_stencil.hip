@@ -34,6 +34,7 @@ namespace mlb {
 
 constexpr int kXcd = 8;
 constexpr int kNbThreads = 256;
+constexpr int64_t kNbSplitBelow = 131072;   // (node, chunk) threads below which levels split components
 
 template <int DIM>
 struct Sten {
@@ -469,9 +470,10 @@ void launch_apply_nb(int dim, const Geo& g, const T* A, bool diag, int ncols, in
     const int want = (ncols + per - 1) / per;
     const int cb = want <= 1 ? 1 : want <= 2 ? 2 : want <= 3 ? 3 : want <= 4 ? 4 : want <= 6 ? 6 : want <= 8 ? 8 : 12;
     const int nchunks = (ncols + cb - 1) / cb;
-    // one-column calls (and DIAG) keep a thread per component: enough threads
+    // one-column calls, DIAG and small levels (whose node threads alone would
+    // leave most SIMDs idle) keep a thread per component: enough threads
     // (FP32 operator stencils: DOF-major threads, nbn counting DOF blocks)
-    const bool split = ncols == 1 || diag;
+    const bool split = ncols == 1 || diag || g.nodes * nchunks < kNbSplitBelow;
     const bool dofs = split && sizeof(T) == 4 && !diag;
     const int64_t nbn_s = dofs ? (g.nodes * dim + kNbThreads - 1) / kNbThreads : nbn;
     const dim3 gr = dofs ? xcd_grid(g.nodes * dim, nchunks) : xcd_grid(g.nodes, split ? dim * nchunks : nchunks);
