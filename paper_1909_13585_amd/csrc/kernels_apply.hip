@@ -256,7 +256,10 @@ __global__ __launch_bounds__(256) void k_apply_G_fine(Geo g, const double* __res
 }
 
 // ---------------------------------------------------------------------------
-// Inverse diagonals (Jacobi), FP64 and FP32 copies; 1 at fixed DOFs.
+// Inverse diagonals (Jacobi), FP64 and FP32 copies.  The FP64 copy is 1 at
+// fixed DOFs (identity rows); the FP32 copy, read only by the mixed-precision
+// smoother, whose blocks are 0 at fixed DOFs, is 0 there, so that its sweeps
+// leave those DOFs at 0 without reading the mask.
 
 template <int DIM>
 __global__ void k_dinv_fine(Geo g, const double* __restrict__ E, const uint8_t* __restrict__ nmask,
@@ -278,9 +281,10 @@ __global__ void k_dinv_fine(Geo g, const double* __restrict__ E, const uint8_t* 
             const int a = (N::NN - 1) ^ s;
             if (ok) d += E[e] * K0[(a * N::ND + c) * N::NDE + a * N::ND + c];
         }
-        const double v = (own >> c) & 1 ? 1.0 : (d > 0.0 ? 1.0 / d : 0.0);
+        const bool fixed = (own >> c) & 1;
+        const double v = fixed ? 1.0 : (d > 0.0 ? 1.0 / d : 0.0);
         dinv[node * N::ND + c] = v;
-        dinvf[node * N::ND + c] = (float)v;
+        dinvf[node * N::ND + c] = fixed ? 0.0f : (float)v;
     }
 }
 

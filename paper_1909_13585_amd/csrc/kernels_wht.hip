@@ -471,6 +471,10 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(sizeof
     // no contraction: the loop is unrolled twice and both copies must round
     // alike, so that results do not depend on the pencil length
 #pragma clang fp contract(off)
+    // FP32 Jacobi sweeps of clean blocks need no identity rows: their D^-1
+    // copy is 0 at fixed DOFs, where x and r are 0, so y = x + 0 = 0 there
+    // (the value the identity row gives) and the owned node's mask is not read
+    constexpr bool NOMASK = sizeof(T) == 4 && CLEAN && MODE == kModeJacobi;
     __shared__ double sh[16];
     const int lane = threadIdx.x;
     const int tx = lane & 7, ty = lane >> 3;
@@ -523,7 +527,8 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 buf_load3(rX, vo[q] + po, v[0][q], v[1][q], v[2][q]);
-                if (!CLEAN || q == 0) mk[q] = __builtin_amdgcn_raw_buffer_load_b8(rM, (int)(mo[q] + pm), 0, 0);
+                if (!CLEAN || (q == 0 && !NOMASK)) mk[q] = __builtin_amdgcn_raw_buffer_load_b8(rM, (int)(mo[q] + pm), 0, 0);
+                else if (q == 0) mk[q] = 0;
             }
         };
         // Walsh-Hadamard transform of a plane over the 4 column corners
@@ -638,7 +643,7 @@ __global__ __launch_bounds__(64 * kW3) __attribute__((amdgpu_waves_per_eu(sizeof
                     const T q1 = a[c][2] + shfl_up_w(a[c][3], 1, kWT);
                     const T acc = q0 + shfl_up_w(q1, kWT, 64);
                     const T xown = olo[c];
-                    const T ax = (mlo >> c) & 1 ? xown : acc;
+                    const T ax = !NOMASK && ((mlo >> c) & 1) ? xown : acc;
                     py[c] = wht_epilogue_fixed<T, MODE>(ax, xown, rr[c], di[c], omega);
                     if (DOT && owner && out) dsum += (double)xown * (double)ax;
                 }
