@@ -36,15 +36,15 @@ HBM_PEAK_GBS = 8000.0
 # + WRITE_SIZE x 1.0 (factors from a 256 MiB calibration copy), KiB per
 # dispatch, from profiles/jacobi_sweep_h8_192x64x64_12col_fp32_hbm_counters.md;
 # reported only when the run tuned the same tile.
-SWEEP_TRAFFIC_BYTES = {(3, 6): (168196.71 * 1.99965 + 120368.36) * 1024,
+SWEEP_TRAFFIC_BYTES = {(3, 6): (167796.60 * 1.99964 + 120207.33) * 1024,
                        (0, 6): (169269.43 * 1.99976 + 118064.79) * 1024,
                        (0, 12): (160371.06 * 1.99964 + 118585.46) * 1024,
-                       (3, 12): (163089.49 * 1.99963 + 125806.16) * 1024}
+                       (3, 12): (162433.38 * 1.99978 + 125531.06) * 1024}
 # wave-level VALU instructions per launch of the same sweep (rocprofv3
 # SQ_INSTS_VALU, profiles/jacobi_sweep_h8_192x64x64_12col_fp32_sq_counters.md):
 # at 4 cycles per FP32 wave instruction on 1,024 SIMDs at 2.4 GHz they set
 # the kernel's VALU ceiling, reported beside the HBM roofline.
-SWEEP_VALU_INSTS = {(3, 6): 56317728}
+SWEEP_VALU_INSTS = {(3, 6): 53621856}
 VALU_CYCLES_PER_INST, SIMDS, CLOCK_HZ = 4, 1024, 2.4e9
 
 
